@@ -1,0 +1,201 @@
+"""Oracle entropy-stable dissipation (test infrastructure only).
+
+Section 4 (eq. ESFlux_HO): at the face (i, k, +1/2)
+    F^_{i+1/2} = F~^{2p}_{i+1/2} - 1/2 D Y <<V~>>^{WENO},   D = lambda^ T^{-1} R(T U),
+with
+  * T = diag{1, T_0, 1} (RHD) or diag{1, T_0, 1, T_0} (RMHD), T_0 the rotation
+    whose first row is the unit metric normal (read with atan2 semantics and no
+    trigonometry);
+  * lambda^ = max_m |J dxi_k/dt + L_k lambda_m(T U)|, L_k = |J grad xi_k|;
+  * R scaled eigenvectors: dU/dV = R R^T, dF_1/dU = R Lambda R^{-1} (for RMHD the
+    Godunov-Powell modified Jacobian dF_1/dU + Phi'(V)^T dB_1/dU);
+  * WENO-(2p-1) (Jiang-Shu) of V~ = R^T T V along the line, <<V~>> = V~^+ - V~^-;
+  * Y_ll = 1 iff <<V~_l>> and [V~_l] = V~_{i+1} - V~_i have the same sign
+    (strictly positive product).
+The face state, face metrics and the choice of basis inside the degenerate
+eigenvalue cluster are readings listed in the design doc.
+
+The eigen-structure is computed generically and numerically, so that it shares
+nothing with any closed form: the primitive-variable Jacobians dU/dP, dF_1/dP,
+dV/dP are taken by complex-step differentiation of the physics functions, the
+eigenpairs of A_P = (dU/dP)^{-1} dF_1/dP come from LAPACK, and each eigenvector
+dP_m maps to dU_m = (dU/dP) dP_m and dV_m = (dV/dP) dP_m.  Scaling r_m = dU_m /
+sqrt(dU_m . dV_m) gives R^T A0^{-1} R = I, i.e. R R^T = A0.  In the cluster
+lambda = v_n the columns are the canonical A0^{-1}-orthonormal basis obtained
+from the cluster projector P_c applied to fixed seed vectors.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import physics as ph
+
+H_CS = 1e-30
+
+
+def rotation(n):
+    """T_0 (3x3 per face) with first row n (unit), second row (-n2, n1, 0)/rho_perp,
+    third row (-n3 n1/rho_perp, -n3 n2/rho_perp, rho_perp), rho_perp = sqrt(n1^2+n2^2);
+    rows (0,1,0), (-n3,0,0) when rho_perp = 0."""
+    n1, n2, n3 = n
+    rp = np.sqrt(n1 * n1 + n2 * n2)
+    safe = rp > 0
+    rps = np.where(safe, rp, 1.0)
+    T = np.zeros(n1.shape + (3, 3))
+    T[..., 0, 0], T[..., 0, 1], T[..., 0, 2] = n1, n2, n3
+    T[..., 1, 0] = np.where(safe, -n2 / rps, 0.0)
+    T[..., 1, 1] = np.where(safe, n1 / rps, 1.0)
+    T[..., 2, 0] = np.where(safe, -n3 * n1 / rps, -n3)
+    T[..., 2, 1] = np.where(safe, -n3 * n2 / rps, 0.0)
+    T[..., 2, 2] = np.where(safe, rp, 0.0)
+    return T
+
+
+def rotate_full(X, T0, slots):
+    """Apply T_0 to the 3-vector slots of a full 8-vector field X (8, N)."""
+    out = X.copy()
+    for s in slots:
+        vec = X[s:s + 3]
+        out[s:s + 3] = np.einsum("nab,bn->an", T0, vec)
+    return out
+
+
+def unrotate_full(X, T0, slots):
+    out = X.copy()
+    for s in slots:
+        vec = X[s:s + 3]
+        out[s:s + 3] = np.einsum("nba,bn->an", T0, vec)
+    return out
+
+
+def _jac(fun, P, sel, G):
+    """Complex-step Jacobian d fun_sel / d P_sel, shape (N, m, m)."""
+    m = len(sel)
+    N = P.shape[1]
+    J = np.zeros((N, m, m))
+    for b, sb in enumerate(sel):
+        Pc = P.astype(complex)
+        Pc[sb] = Pc[sb] + 1j * H_CS
+        val = fun(Pc)
+        J[:, :, b] = (val[sel].imag / H_CS).T
+    return J
+
+
+def cluster_size(phys, dim):
+    if phys == ph.RMHD:
+        return 2
+    return 2 if dim == 2 else 3
+
+
+def cluster_seeds(phys, dim):
+    """Seed slots (selected-system indices) for the canonical cluster basis:
+    e_D then the transverse momenta (RHD), e_D then e_{B_n} (RMHD)."""
+    if phys == ph.RMHD:
+        return [0, 5]
+    return [0, 2] if dim == 2 else [0, 2, 3]
+
+
+def eigensystem(Pr, G, phys, dim):
+    """Numeric scaled eigen-structure at rotated face states Pr (8, N):
+    returns (lam (N, m), R (N, m, m)) with R R^T = dU/dV and (dF_1/dU) R = R diag(lam)."""
+    sel = ph.comps(phys, dim)
+    m = len(sel)
+    JU = _jac(lambda P: ph.cons(P, G), Pr, sel, G)
+    JF = _jac(lambda P: ph.flux(P, G, 0), Pr, sel, G)
+    JV = _jac(lambda P: ph.entropy_vars(P, G), Pr, sel, G)
+    if phys == ph.RMHD:
+        # Godunov-Powell modification: + Phi'(V) (dB_1/dP), B_1 is primitive slot 5
+        Phip = ph.phi_prime(Pr, G)[sel].T          # (N, m)
+        JF = JF.copy()
+        JF[:, :, 5] += Phip
+    AP = np.linalg.solve(JU, JF)
+    w, vec = np.linalg.eig(AP)
+    lam = w.real
+    dP = vec.real
+    vn = Pr[1] / np.sqrt(1.0 + Pr[1] ** 2 + Pr[2] ** 2 + Pr[3] ** 2)
+    c = cluster_size(phys, dim)
+    order = np.argsort(np.abs(lam - vn[:, None]), axis=1)
+    # The cluster lambda = v_n is semi-simple: its invariant subspace is taken from
+    # the null space of A_P - v_n I (SVD), which stays well conditioned where the
+    # individual eigenvectors of a repeated eigenvalue are not.
+    _, _, vh = np.linalg.svd(AP - vn[:, None, None] * np.eye(m)[None])
+    null = np.transpose(vh[:, m - c:, :], (0, 2, 1))                   # (N, m, c)
+    idx_cl = order[:, :c]
+    for q in range(c):
+        np.put_along_axis(dP, idx_cl[:, q][:, None, None].repeat(m, axis=1),
+                          null[:, :, q][:, :, None], axis=2)
+    dU = np.einsum("nab,nbm->nam", JU, dP)
+    dV = np.einsum("nab,nbm->nam", JV, dP)
+    # non-degenerate columns
+    norm = np.sqrt(np.einsum("nam,nam->nm", dU, dV))
+    R = dU / norm[:, None, :]
+    # cluster: canonical A0^{-1}-orthonormal basis from the projector
+    A0inv = np.einsum("nab,nbc->nac", JV, np.linalg.inv(JU))
+    A0inv = 0.5 * (A0inv + np.transpose(A0inv, (0, 2, 1)))
+    K = np.take_along_axis(dU, idx_cl[:, None, :].repeat(m, axis=1), axis=2)   # (N, m, c)
+    Gm = np.einsum("nac,nab,nbd->ncd", K, A0inv, K)
+    Pc = np.einsum("nac,ncd,nbd,nbe->nae", K, np.linalg.inv(Gm), K, A0inv)
+    cols = []
+    for s in cluster_seeds(phys, dim):
+        w_ = Pc[:, :, s].copy()
+        for r in cols:
+            w_ = w_ - np.einsum("na,nab,nb->n", r, A0inv, w_)[:, None] * r
+        w_ = w_ / np.sqrt(np.einsum("na,nab,nb->n", w_, A0inv, w_))[:, None]
+        cols.append(w_)
+    for q in range(c):
+        np.put_along_axis(R, idx_cl[:, q][:, None, None].repeat(m, axis=1),
+                          cols[q][:, :, None], axis=2)
+        np.put_along_axis(lam, idx_cl[:, q][:, None], vn[:, None], axis=1)
+    return lam, R
+
+
+def weno5_minus(a, b, c, d, e, eps):
+    """WENO5-JS value at i+1/2 from v_{i-2..i+2} = (a, b, c, d, e) (Jiang-Shu 1996)."""
+    q0 = (2 * a - 7 * b + 11 * c) / 6.0
+    q1 = (-b + 5 * c + 2 * d) / 6.0
+    q2 = (2 * c + 5 * d - e) / 6.0
+    b0 = 13.0 / 12.0 * (a - 2 * b + c) ** 2 + 0.25 * (a - 4 * b + 3 * c) ** 2
+    b1 = 13.0 / 12.0 * (b - 2 * c + d) ** 2 + 0.25 * (b - d) ** 2
+    b2 = 13.0 / 12.0 * (c - 2 * d + e) ** 2 + 0.25 * (3 * c - 4 * d + e) ** 2
+    a0 = 0.1 / (eps + b0) ** 2
+    a1 = 0.6 / (eps + b1) ** 2
+    a2 = 0.3 / (eps + b2) ** 2
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2)
+
+
+def face_dissipation(Pst, ast, G, phys, dim, eps, details=False):
+    """ES dissipation vector d = D Y <<V~>> at faces.
+    Pst: (6, 8, N) full primitive states of the stencil nodes i-2..i+3 of each face;
+    ast: (2, d+1, N) metric vectors of nodes i and i+1.
+    Returns the full 8-slot d (8, N) (zeros in unused slots)."""
+    sel = ph.comps(phys, dim)
+    m = len(sel)
+    abar = 0.5 * (ast[0] + ast[1])
+    ax = np.zeros((3,) + abar.shape[1:])
+    ax[:dim] = abar[1:1 + dim]
+    L = np.sqrt(np.sum(ax * ax, axis=0))
+    n = ax / L
+    T0 = rotation(n)
+    slots = [1, 5] if phys == ph.RMHD else [1]
+    Pbar = 0.5 * (Pst[2] + Pst[3])
+    Pr = rotate_full(Pbar, T0, slots)
+    lam, R = eigensystem(Pr, G, phys, dim)
+    lhat = np.max(np.abs(abar[0][:, None] + L[:, None] * lam), axis=1)
+    Vt = []
+    for j in range(6):
+        Vj = rotate_full(ph.entropy_vars(Pst[j], G), T0, slots)[sel]   # (m, N)
+        Vt.append(np.einsum("nab,an->bn", R, Vj))                       # R^T T V
+    vm = weno5_minus(Vt[0], Vt[1], Vt[2], Vt[3], Vt[4], eps)
+    vp = weno5_minus(Vt[5], Vt[4], Vt[3], Vt[2], Vt[1], eps)
+    jump_weno = vp - vm
+    jump = Vt[3] - Vt[2]
+    Y = (jump_weno * jump > 0).astype(np.float64)
+    coef = Y * jump_weno                                                 # (m, N)
+    dsel = lhat[None, :] * np.einsum("nab,bn->an", R, coef)              # R (Y <<V~>>)
+    dfull = np.zeros((8,) + dsel.shape[1:])
+    dfull[sel] = dsel
+    dfull = unrotate_full(dfull, T0, slots)                              # T^{-1}
+    if details:
+        return dfull, dict(lam=lam, R=R, lhat=lhat, jump=jump, jump_weno=jump_weno, Y=Y,
+                           T0=T0, Pr=Pr, L=L)
+    return dfull

@@ -1,0 +1,359 @@
+"""Seeded synthetic workloads: grids, initial primitive states and scheme parameters.
+
+This module only describes inputs.  It holds none of the scheme's arithmetic (no
+conservative variables, fluxes, metrics or mesh equations): both the CPU oracle
+and the HIP path start from the same primitive fields and uniform mesh produced
+here and convert them with their own code.
+
+Conventions shared by every consumer
+------------------------------------
+* Node arrays are C-ordered ``[z][y][x]`` (x fastest); a 2D array is ``[y][x]``.
+* Axis k of the computational index space (xi_1, xi_2, xi_3) maps to array axis
+  ``-1 - k``.
+* Periodic axes use nodes x_i = a + i*L/N (no duplicated end point) and
+  dxi = 1/N; bounded (outflow) axes use x_i = a + i*L/(N-1) and dxi = 1/(N-1).
+  The computational coordinate is xi in [0, 1], so J is about the physical
+  cell volume ratio (L/1)^d.
+* Primitive fields: rho, u = W v (spatial part of the four-velocity, 3 comps),
+  p, B (3 comps).  The velocity spec of a workload (v) is turned into u here
+  because u is the field the interface carries.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+PERIODIC = 0
+OUTFLOW = 1
+
+RHD = 0
+RMHD = 1
+
+SIGMA_RHO = 0
+SIGMA_LNRHO = 1
+MON_PAPER = 0     # omega = sqrt(1 + alpha |grad sigma| / max |grad sigma|)
+MON_SQGRAD = 1    # omega = sqrt(1 + alpha |grad sigma|^2)
+
+
+@dataclasses.dataclass
+class Grid:
+    dim: int
+    n: Tuple[int, int, int]          # interior nodes along xi_1, xi_2, xi_3 (n[2] = 1 in 2D)
+    bc: Tuple[int, int, int]         # PERIODIC / OUTFLOW per axis
+    dxi: Tuple[float, float, float]
+    period: Tuple[float, float, float]  # physical period (mesh shift) for periodic axes
+    lo: Tuple[float, float, float]
+    length: Tuple[float, float, float]
+
+    @property
+    def shape(self) -> Tuple[int, ...]:
+        """Array shape of an interior node field (C order, x fastest)."""
+        if self.dim == 2:
+            return (self.n[1], self.n[0])
+        return (self.n[2], self.n[1], self.n[0])
+
+    @property
+    def nnodes(self) -> int:
+        return int(np.prod(self.shape))
+
+
+@dataclasses.dataclass
+class Scheme:
+    phys: int = RHD
+    gamma: float = 5.0 / 3.0
+    order_p: int = 3            # 2p-th order EC flux, WENO-(2p-1) dissipation
+    dissipation: int = 1        # 0 = entropy conservative, 1 = entropy stable
+    weno_eps: float = 1e-6
+    cfl: float = 0.4
+    mixed: int = 0              # 1 = FP32 flux/WENO arithmetic with FP64 accumulation
+
+
+@dataclasses.dataclass
+class Monitor:
+    enabled: int = 0
+    sigma: int = SIGMA_RHO
+    form: int = MON_PAPER
+    alpha: float = 0.0
+    filter_passes: int = 3
+    sweeps: int = 10
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    grid: Grid
+    scheme: Scheme
+    monitor: Monitor
+    prim: Dict[str, np.ndarray]      # rho (shape), u (3, *shape), p (shape), B (3, *shape)
+    x: np.ndarray                    # (dim, *shape) uniform initial mesh
+    steps: int
+    t_end: Optional[float] = None
+
+
+def make_grid(dim: int, n: Sequence[int], bc: Sequence[int],
+              lo: Sequence[float] = (0.0, 0.0, 0.0),
+              length: Sequence[float] = (1.0, 1.0, 1.0)) -> Grid:
+    n3 = [int(n[0]), int(n[1]), int(n[2]) if dim == 3 else 1]
+    bc3 = [int(bc[0]), int(bc[1]), int(bc[2]) if dim == 3 else PERIODIC]
+    dxi, period = [], []
+    for k in range(3):
+        if k >= dim:
+            dxi.append(1.0)
+            period.append(0.0)
+        elif bc3[k] == PERIODIC:
+            dxi.append(1.0 / n3[k])
+            period.append(float(length[k]))
+        else:
+            dxi.append(1.0 / (n3[k] - 1))
+            period.append(0.0)
+    return Grid(dim, tuple(n3), tuple(bc3), tuple(dxi), tuple(period),
+                tuple(float(a) for a in lo), tuple(float(a) for a in length))
+
+
+def uniform_mesh(grid: Grid) -> np.ndarray:
+    """Uniform initial mesh x(xi): (dim, *shape)."""
+    axes = []
+    for k in range(grid.dim):
+        nk = grid.n[k]
+        if grid.bc[k] == PERIODIC:
+            axes.append(grid.lo[k] + grid.length[k] * np.arange(nk) / nk)
+        else:
+            axes.append(grid.lo[k] + grid.length[k] * np.arange(nk) / (nk - 1))
+    if grid.dim == 2:
+        Y, X = np.meshgrid(axes[1], axes[0], indexing="ij")
+        return np.stack([X, Y]).astype(np.float64)
+    Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return np.stack([X, Y, Z]).astype(np.float64)
+
+
+def _four_velocity(v: np.ndarray) -> np.ndarray:
+    v2 = np.sum(v * v, axis=0)
+    return v / np.sqrt(1.0 - v2)
+
+
+def _prim(rho, v, p, B) -> Dict[str, np.ndarray]:
+    return {"rho": np.ascontiguousarray(rho, dtype=np.float64),
+            "u": np.ascontiguousarray(_four_velocity(v), dtype=np.float64),
+            "p": np.ascontiguousarray(p, dtype=np.float64),
+            "B": np.ascontiguousarray(B, dtype=np.float64)}
+
+
+# ---------------------------------------------------------------------------
+# The five workload families.  Sizes are parameters so tests can run small
+# instances with the same structure as the full-size ones.
+# ---------------------------------------------------------------------------
+
+def advected_sine(n: int = 64) -> Workload:
+    """2D RHD, periodic [0,1)^2, rho = 1 + 0.2 sin 2pi(x+y), v = (0.2, 0.2), p = 1,
+    adaptive mesh with omega = sqrt(1 + 10 |grad_xi rho|^2), 10 Jacobi sweeps; run to t = 0.2.
+    The density is advected exactly: rho(x, y, t) = 1 + 0.2 sin 2pi(x + y - 0.4 t)."""
+    g = make_grid(2, (n, n, 1), (PERIODIC, PERIODIC, PERIODIC))
+    x = uniform_mesh(g)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * (x[0] + x[1]))
+    v = np.zeros((3,) + g.shape)
+    v[0] = 0.2
+    v[1] = 0.2
+    p = np.ones(g.shape)
+    B = np.zeros((3,) + g.shape)
+    return Workload("rhd2d_advected_sine_%d" % n, g,
+                    Scheme(phys=RHD, cfl=0.4),
+                    Monitor(enabled=1, sigma=SIGMA_RHO, form=MON_SQGRAD, alpha=10.0,
+                            filter_passes=3, sweeps=10),
+                    _prim(rho, v, p, B), x, steps=0, t_end=0.2)
+
+
+def quadrant_riemann(n: int = 400, seed: int = 0, steps: int = 300) -> Workload:
+    """2D RHD quadrant Riemann problem on [0,1]^2 with outflow boundaries.  Four
+    constant states drawn from ``seed`` in the order NE, NW, SW, SE; per quadrant
+    rho ~ U[0.01,1], p ~ U[0.01,1], |v| ~ U[0,0.99), angle ~ U[0,2pi), v_3 = 0.
+    Adaptive mesh: paper monitor with alpha = 1200 on sigma = ln rho, 10 sweeps."""
+    g = make_grid(2, (n, n, 1), (OUTFLOW, OUTFLOW, PERIODIC))
+    x = uniform_mesh(g)
+    rng = np.random.default_rng(seed)
+    states = []
+    for _ in range(4):
+        r = rng.uniform(0.01, 1.0)
+        pr = rng.uniform(0.01, 1.0)
+        vm = rng.uniform(0.0, 0.99)
+        ang = rng.uniform(0.0, 2.0 * np.pi)
+        states.append((r, pr, vm * math.cos(ang), vm * math.sin(ang)))
+    east = x[0] > 0.5
+    north = x[1] > 0.5
+    quads = [east & north, (~east) & north, (~east) & (~north), east & (~north)]
+    rho = np.zeros(g.shape)
+    p = np.zeros(g.shape)
+    v = np.zeros((3,) + g.shape)
+    for q, (r, pr, vx, vy) in zip(quads, states):
+        rho[q] = r
+        p[q] = pr
+        v[0][q] = vx
+        v[1][q] = vy
+    B = np.zeros((3,) + g.shape)
+    return Workload("rhd2d_quadrant_riemann_%d_seed%d" % (n, seed), g,
+                    Scheme(phys=RHD, cfl=0.4),
+                    Monitor(enabled=1, sigma=SIGMA_LNRHO, form=MON_PAPER, alpha=1200.0,
+                            filter_passes=3, sweeps=10),
+                    _prim(rho, v, p, B), x, steps=steps)
+
+
+def rmhd_rotor(n: int = 512, steps: int = 200) -> Workload:
+    """2D RMHD rotor on [0,1]^2, outflow, static mesh: disk r < 0.1 about (0.5, 0.5)
+    with rho = 10 rotating rigidly at |v| = 0.99 r / 0.1; rho = 1 outside; p = 1;
+    B = (1, 0, 0)."""
+    g = make_grid(2, (n, n, 1), (OUTFLOW, OUTFLOW, PERIODIC))
+    x = uniform_mesh(g)
+    dx = x[0] - 0.5
+    dy = x[1] - 0.5
+    r = np.sqrt(dx * dx + dy * dy)
+    inside = r < 0.1
+    rho = np.where(inside, 10.0, 1.0)
+    v = np.zeros((3,) + g.shape)
+    v[0] = np.where(inside, -0.99 * dy / 0.1, 0.0)
+    v[1] = np.where(inside, 0.99 * dx / 0.1, 0.0)
+    p = np.ones(g.shape)
+    B = np.zeros((3,) + g.shape)
+    B[0] = 1.0
+    return Workload("rmhd2d_rotor_%d" % n, g, Scheme(phys=RMHD, cfl=0.4),
+                    Monitor(enabled=0), _prim(rho, v, p, B), x, steps=steps)
+
+
+def blast3d(n: int = 128, seed: int = 0, steps: int = 100) -> Workload:
+    """3D RHD blast wave on [0,1]^3, outflow, adaptive mesh (paper monitor on
+    sigma = rho, alpha = 800, 5 sweeps), CFL 0.3: sphere r < 0.1 about the centre
+    with p = 1000, p = 1 outside, rho = 1 + U[-0.01, 0.01] iid noise."""
+    g = make_grid(3, (n, n, n), (OUTFLOW, OUTFLOW, OUTFLOW))
+    x = uniform_mesh(g)
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + rng.uniform(-0.01, 0.01, size=g.shape)
+    r = np.sqrt((x[0] - 0.5) ** 2 + (x[1] - 0.5) ** 2 + (x[2] - 0.5) ** 2)
+    p = np.where(r < 0.1, 1000.0, 1.0)
+    v = np.zeros((3,) + g.shape)
+    B = np.zeros((3,) + g.shape)
+    return Workload("rhd3d_blast_%d" % n, g, Scheme(phys=RHD, cfl=0.3),
+                    Monitor(enabled=1, sigma=SIGMA_RHO, form=MON_PAPER, alpha=800.0,
+                            filter_passes=3, sweeps=5),
+                    _prim(rho, v, p, B), x, steps=steps)
+
+
+def fourier_modes(seed: int = 0, nmodes: int = 8):
+    """The 8 Fourier modes of the adjoint workload: (k_m, l_m) from {-4..4}^2 \\ {0}
+    without replacement, then theta_m ~ U[0, 2pi), then c_m ~ U[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    pairs = [(a, b) for a in range(-4, 5) for b in range(-4, 5) if (a, b) != (0, 0)]
+    idx = rng.choice(len(pairs), size=nmodes, replace=False)
+    kl = np.array([pairs[i] for i in idx], dtype=np.float64)
+    theta = rng.uniform(0.0, 2.0 * np.pi, size=nmodes)
+    c = rng.uniform(-1.0, 1.0, size=nmodes)
+    return kl, theta, c
+
+
+def rmhd_fourier(n: int = 256, seed: int = 0, steps: int = 100, eps: float = 0.05,
+                 coeffs: Optional[np.ndarray] = None) -> Workload:
+    """2D RMHD, periodic [0,1)^2, static mesh: rho = 1 + eps f(x, y) with
+    f = (1/8) sum_m c_m cos(2 pi (k_m x + l_m y) + theta_m), p = 1, v = (0.3, 0.2),
+    B = (0.5, 0.5, 0)."""
+    g = make_grid(2, (n, n, 1), (PERIODIC, PERIODIC, PERIODIC))
+    x = uniform_mesh(g)
+    kl, theta, c = fourier_modes(seed)
+    if coeffs is not None:
+        c = np.asarray(coeffs, dtype=np.float64)
+    f = np.zeros(g.shape)
+    for m in range(len(c)):
+        f += c[m] * np.cos(2 * np.pi * (kl[m, 0] * x[0] + kl[m, 1] * x[1]) + theta[m])
+    f /= len(c)
+    rho = 1.0 + eps * f
+    v = np.zeros((3,) + g.shape)
+    v[0] = 0.3
+    v[1] = 0.2
+    p = np.ones(g.shape)
+    B = np.zeros((3,) + g.shape)
+    B[0] = 0.5
+    B[1] = 0.5
+    return Workload("rmhd2d_fourier_%d" % n, g, Scheme(phys=RMHD, cfl=0.4),
+                    Monitor(enabled=0), _prim(rho, v, p, B), x, steps=steps)
+
+
+# ---------------------------------------------------------------------------
+# Random test inputs (parity and invariant tests).
+# ---------------------------------------------------------------------------
+
+def random_prim(shape, rng: np.random.Generator, phys: int = RHD, dim: int = 2,
+                vmax: float = 0.9, rho_rng=(0.1, 1.0), p_rng=(0.1, 1.0),
+                bmax: float = 1.0) -> Dict[str, np.ndarray]:
+    """Admissible random primitive state per node (non-smooth)."""
+    rho = rng.uniform(*rho_rng, size=shape)
+    p = rng.uniform(*p_rng, size=shape)
+    ncomp = 3 if (dim == 3 or phys == RMHD) else 2
+    dirs = rng.normal(size=(3,) + tuple(shape))
+    dirs[ncomp:] = 0.0
+    dirs /= np.sqrt(np.sum(dirs * dirs, axis=0))
+    vm = rng.uniform(0.0, vmax, size=shape)
+    v = dirs * vm
+    B = np.zeros((3,) + tuple(shape))
+    if phys == RMHD:
+        B = rng.uniform(-bmax, bmax, size=(3,) + tuple(shape))
+    return _prim(rho, v, p, B)
+
+
+def smooth_prim(x: np.ndarray, rng: np.random.Generator, phys: int = RHD,
+                amp: float = 0.2, period=(1.0, 1.0, 1.0)) -> Dict[str, np.ndarray]:
+    """Smooth periodic primitive state on physical points x (dim, *shape)."""
+    dim = x.shape[0]
+    shape = x.shape[1:]
+
+    def field(scale, off):
+        kx = rng.integers(1, 3, size=dim)
+        ph = rng.uniform(0, 2 * np.pi)
+        arg = sum(2 * np.pi * kx[k] * x[k] / period[k] for k in range(dim))
+        return off + scale * np.sin(arg + ph)
+
+    rho = field(amp, 1.0)
+    p = field(amp, 1.0)
+    ncomp = 3 if (dim == 3 or phys == RMHD) else 2
+    v = np.zeros((3,) + shape)
+    for c in range(ncomp):
+        v[c] = field(0.2, 0.1 * (c + 1))
+    B = np.zeros((3,) + shape)
+    if phys == RMHD:
+        for c in range(3):
+            B[c] = field(0.3, 0.4 - 0.2 * c)
+    return _prim(rho, v, p, B)
+
+
+def perturbed_mesh(grid: Grid, rng: np.random.Generator, amp: float = 0.02,
+                   t: float = 0.0) -> np.ndarray:
+    """Smooth sinusoidal deformation of the uniform mesh that keeps periodicity
+    and the bounded-edge normal coordinates (used as a curvilinear test mesh)."""
+    x = uniform_mesh(grid)
+    xi = []
+    for k in range(grid.dim):
+        nk = grid.n[k]
+        if grid.bc[k] == PERIODIC:
+            a = np.arange(nk) / nk
+        else:
+            a = np.arange(nk) / (nk - 1)
+        xi.append(a)
+    if grid.dim == 2:
+        E2, E1 = np.meshgrid(xi[1], xi[0], indexing="ij")
+        E = [E1, E2]
+    else:
+        E3, E2, E1 = np.meshgrid(xi[2], xi[1], xi[0], indexing="ij")
+        E = [E1, E2, E3]
+    ph = rng.uniform(0, 2 * np.pi, size=(grid.dim, grid.dim))
+    c = np.cos(np.pi * t / 4.0)
+    for k in range(grid.dim):
+        disp = np.ones(grid.shape)
+        for j in range(grid.dim):
+            if j == k:
+                continue
+            disp = disp * np.sin(2 * np.pi * E[j] + ph[k, j])
+        # vanish on bounded faces normal to k so the domain stays fixed
+        if grid.bc[k] != PERIODIC:
+            disp = disp * np.sin(np.pi * E[k])
+        else:
+            disp = disp * (1.0 + 0.5 * np.sin(2 * np.pi * E[k] + ph[k, k]))
+        x[k] = x[k] + amp * c * grid.length[k] * disp
+    return x

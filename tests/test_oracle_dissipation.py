@@ -1,0 +1,146 @@
+"""Pins for the ES dissipation ingredients (Section 4): rotation, scaled
+eigenvectors, WENO and the sign switch."""
+import numpy as np
+import pytest
+
+from oracle import physics as ph, dissipation as ds
+from oracle_util import rand_P, prim_from_V
+
+G = 5.0 / 3.0
+CASES = [(ph.RHD, 2), (ph.RHD, 3), (ph.RMHD, 2)]
+
+
+def test_rotation_orthogonal_first_row_normal():
+    rng = np.random.default_rng(0)
+    n = rng.normal(size=(3, 500))
+    n[:, :3] = np.array([[0, 0, 1], [0, 0, -1], [1, 0, 0]]).T
+    n /= np.linalg.norm(n, axis=0)
+    T = ds.rotation(n)
+    I = np.einsum("nab,ncb->nac", T, T)
+    np.testing.assert_allclose(I, np.broadcast_to(np.eye(3), I.shape), atol=1e-14)
+    np.testing.assert_allclose(T[:, 0, :], n.T, atol=0)
+    # determinant +1 (a rotation, as the paper's T_0)
+    np.testing.assert_allclose(np.linalg.det(T), 1.0, atol=1e-14)
+
+
+def _A0_and_S(Pr, phys, dim):
+    """A0 = dU/dV and S = dF_1/dV (+ Godunov-Powell term) by complex step through the
+    explicit inverse V -> P, an independent route from the oracle's primitive one."""
+    sel = ph.comps(phys, dim)
+    V = ph.entropy_vars(Pr, G)
+    N = Pr.shape[1]
+    m = len(sel)
+    A0 = np.zeros((N, m, m))
+    S = np.zeros((N, m, m))
+    h = 1e-30
+    Phip = ph.phi_prime(Pr, G)
+    for b, sb in enumerate(sel):
+        Vc = V.astype(complex)
+        Vc[sb] += 1j * h
+        Pc = prim_from_V(Vc, G, phys, dim)
+        A0[:, :, b] = (ph.cons(Pc, G)[sel].imag / h).T
+        S[:, :, b] = (ph.flux(Pc, G, 0)[sel].imag / h).T
+    if phys == ph.RMHD:
+        # S + Phi' (dB_1/dV): dB_1/dV is row B_1 of A0
+        S = S + np.einsum("an,nb->nab", Phip[sel], A0[:, 5, :])
+    return A0, S
+
+
+@pytest.mark.parametrize("phys,dim", CASES)
+def test_scaled_eigenvectors_definition(phys, dim):
+    # dU/dV = R R^T and dF_1/dU R = R Lambda
+    rng = np.random.default_rng(1 + phys + dim)
+    Pr = rand_P(400, rng, phys, dim, vmax=0.95, lo=0.05)
+    lam, R = ds.eigensystem(Pr, G, phys, dim)
+    A0, S = _A0_and_S(Pr, phys, dim)
+    RRt = np.einsum("nab,ncb->nac", R, R)
+    rel = np.max(np.abs(RRt - A0), axis=(1, 2)) / np.max(np.abs(A0), axis=(1, 2))
+    assert np.max(rel) < 1e-10
+    A = np.einsum("nab,nbc->nac", S, np.linalg.inv(A0))
+    AR = np.einsum("nab,nbc->nac", A, R)
+    RL = R * lam[:, None, :]
+    rel = np.max(np.abs(AR - RL), axis=(1, 2)) / np.max(np.abs(R), axis=(1, 2))
+    assert np.max(rel) < 1e-8
+
+
+@pytest.mark.parametrize("phys,dim", CASES)
+def test_cluster_basis_is_canonical(phys, dim):
+    # seeds in order; each later cluster column carries no component of an earlier seed:
+    # r_q^T A0^{-1} e_{s_j} = 0 for j < q (so the basis does not depend on how the
+    # eigenspace was computed), and the cluster columns have eigenvalue v_n.
+    rng = np.random.default_rng(7 + phys + dim)
+    Pr = rand_P(300, rng, phys, dim, vmax=0.9, lo=0.05)
+    lam, R = ds.eigensystem(Pr, G, phys, dim)
+    A0, _ = _A0_and_S(Pr, phys, dim)
+    A0i = np.linalg.inv(A0)
+    vn = Pr[1] / np.sqrt(1 + Pr[1] ** 2 + Pr[2] ** 2 + Pr[3] ** 2)
+    seeds = ds.cluster_seeds(phys, dim)
+    for n in range(Pr.shape[1]):
+        cl = np.argsort(np.abs(lam[n] - vn[n]))[:len(seeds)]
+        np.testing.assert_allclose(lam[n][cl], vn[n], atol=1e-14)
+        # M[q, j] = r_q^T A0^{-1} e_{s_j}: r_q is built from seed s_q, so M[q, j] = 0 for j < q
+        M = (R[n][:, cl].T @ A0i[n])[:, seeds]
+        M = np.abs(M) / np.max(np.abs(M))
+        order = np.argsort(-np.sum(M > 1e-7, axis=1), kind="stable")
+        assert np.all(np.tril(M[order], -1) < 1e-9), M
+
+
+def test_weno5_linear_weights_exact_for_quartics():
+    # With eps -> infinity the JS weights become the linear ones.  Read as cell averages
+    # of H, point data of a quartic H' reconstruct H' at x_{i+1/2} exactly from both sides,
+    # so <<v>> = v^+ - v^- vanishes for point samples of any quartic and not of a quintic.
+    rng = np.random.default_rng(2)
+    x = np.arange(-2, 4) * 1.0
+    for deg in range(6):
+        c = rng.normal(size=deg + 1)
+        Hc = np.polyint(c)
+        v = np.polyval(Hc, x + 0.5) - np.polyval(Hc, x - 0.5)      # cell averages of c
+        vm = ds.weno5_minus(v[0], v[1], v[2], v[3], v[4], 1e30)
+        vp = ds.weno5_minus(v[5], v[4], v[3], v[2], v[1], 1e30)
+        exact = np.polyval(c, 0.5)
+        if deg <= 4:
+            assert abs(vm - exact) < 1e-12 * (1 + abs(exact))
+            assert abs(vp - exact) < 1e-12 * (1 + abs(exact))
+        w = np.polyval(c, x)                                         # point samples
+        jm = ds.weno5_minus(w[0], w[1], w[2], w[3], w[4], 1e30)
+        jp = ds.weno5_minus(w[5], w[4], w[3], w[2], w[1], 1e30)
+        if deg <= 4:
+            assert abs(jp - jm) < 1e-12 * (1 + np.max(np.abs(w)))
+        else:
+            assert abs(jp - jm) > 1e-6
+
+
+def test_weno5_jump_fifth_order_on_smooth_data():
+    errs = []
+    for n in (20, 40, 80, 160):
+        h = 1.0 / n
+        x = (np.arange(-2, 4) * h)[:, None] + np.linspace(0, 1, 50)[None, :]
+        v = np.sin(2 * np.pi * x) + 0.3 * np.cos(6 * np.pi * x)
+        vm = ds.weno5_minus(v[0], v[1], v[2], v[3], v[4], 1e-6)
+        vp = ds.weno5_minus(v[5], v[4], v[3], v[2], v[1], 1e-6)
+        errs.append(np.max(np.abs(vp - vm)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] > 4.5, (errs, rates)
+
+
+def test_weno5_odd_symmetry():
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=(5, 1000))
+    a = ds.weno5_minus(*v, 1e-6)
+    b = ds.weno5_minus(*(-v), 1e-6)
+    np.testing.assert_allclose(a, -b, rtol=1e-15, atol=1e-15)
+
+
+@pytest.mark.parametrize("phys,dim", CASES)
+def test_sign_property_and_constant_state(phys, dim):
+    rng = np.random.default_rng(4 + phys + dim)
+    N = 500
+    Pst = np.stack([rand_P(N, rng, phys, dim, vmax=0.9, lo=0.05) for _ in range(6)])
+    ast = rng.normal(size=(2, dim + 1, N))
+    d, info = ds.face_dissipation(Pst, ast, G, phys, dim, 1e-6, details=True)
+    prod = info["jump"] * info["Y"] * info["jump_weno"]
+    assert np.all(prod >= 0)       # [V~]^T Y <<V~>> >= 0 per component (Theorem 5.1)
+    # constant state: no dissipation (Remark after Theorem 5.1)
+    Pc = np.repeat(Pst[:1], 6, axis=0)
+    dc = ds.face_dissipation(Pc, ast, G, phys, dim, 1e-6)
+    assert np.max(np.abs(dc)) == 0.0

@@ -1,0 +1,145 @@
+"""Pins for the semi-discrete scheme (Section 3.2, Theorem 4.1, Proposition 4.2,
+Theorem 5.1) on random curvilinear moving meshes."""
+import numpy as np
+import pytest
+
+from oracle import physics as ph, metrics as mt, residual as rs, stepper as st, ecflux as ec
+from paper_2107_12027_amd import workloads as wl
+
+G = 5.0 / 3.0
+CASES = [(ph.RHD, 2, (12, 10, 1)), (ph.RHD, 3, (7, 6, 8)), (ph.RMHD, 2, (10, 12, 1))]
+
+
+def setup(phys, dim, n, bc=(0, 0, 0), seed=0, smooth=False):
+    rng = np.random.default_rng(seed)
+    g = wl.make_grid(dim, n, bc)
+    x = wl.perturbed_mesh(g, rng, amp=0.03)
+    xdot = wl.perturbed_mesh(g, rng, amp=0.05) - wl.uniform_mesh(g)
+    met = mt.metrics(g, x, xdot)
+    if smooth:
+        pr = wl.smooth_prim(x, rng, phys)
+    else:
+        pr = wl.random_prim(g.shape, rng, phys=phys, dim=dim, vmax=0.9)
+    P = ph.full_prim(pr["rho"], pr["u"], pr["p"], pr["B"])
+    return g, x, xdot, met, P
+
+
+@pytest.mark.parametrize("phys,dim,n", CASES)
+def test_ec_scheme_conserves_entropy(phys, dim, n):
+    # Theorem 4.1: sum_i (V_i . dU_i/dt - phi_i dJ_i/dt) = 0 on a periodic mesh
+    g, x, xdot, met, P = setup(phys, dim, n)
+    sc = wl.Scheme(phys=phys, dissipation=0)
+    dU, dJ = rs.residual(g, sc, st.pad_solution(g, P), met)
+    sel = ph.comps(phys, dim)
+    V = ph.entropy_vars(P, G)[sel]
+    phi, _, _ = ph.potentials(P, G)
+    ep = rs.entropy_production(g, sc, P, dU, dJ)
+    scale = np.sum(np.abs(V * dU)) + np.sum(np.abs(phi * dJ))
+    assert abs(ep) < 1e-14 * scale
+
+
+@pytest.mark.parametrize("phys,dim,n", CASES)
+def test_es_scheme_produces_entropy_with_right_sign(phys, dim, n):
+    # Theorem 5.1: the ES scheme can only decrease the total entropy
+    for seed in range(3):
+        g, x, xdot, met, P = setup(phys, dim, n, seed=seed)
+        sc = wl.Scheme(phys=phys, dissipation=1)
+        dU, dJ = rs.residual(g, sc, st.pad_solution(g, P), met)
+        assert rs.entropy_production(g, sc, P, dU, dJ) < 0
+
+
+@pytest.mark.parametrize("phys,dim,n", CASES)
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1)])
+def test_free_stream_preservation(phys, dim, n, bc):
+    # Proposition 4.2 / remark after Theorem 5.1: for a constant state dU/dt = U_0 dJ/dt
+    g, x, xdot, met, P = setup(phys, dim, n, bc=bc)
+    Pc = np.broadcast_to(P.reshape(8, -1)[:, :1].reshape((8,) + (1,) * dim), P.shape).copy()
+    U0 = ph.cons(Pc, G)[ph.comps(phys, dim)]
+    for diss in (0, 1):
+        sc = wl.Scheme(phys=phys, dissipation=diss)
+        dU, dJ = rs.residual(g, sc, st.pad_solution(g, Pc), met)
+        assert np.max(np.abs(dU - U0 * dJ)) < 1e-13 * np.max(np.abs(U0)) * np.max(np.abs(met)) / min(g.dxi[:dim])
+
+
+@pytest.mark.parametrize("phys,dim,n", CASES)
+def test_conservation_on_periodic_mesh(phys, dim, n):
+    # telescoping form: sum_i dD_i/dt = 0, sum_i dJ_i/dt = 0 and, for RHD, every component
+    g, x, xdot, met, P = setup(phys, dim, n)
+    sc = wl.Scheme(phys=phys, dissipation=1)
+    dU, dJ = rs.residual(g, sc, st.pad_solution(g, P), met)
+    comps = range(dU.shape[0]) if phys == ph.RHD else [0]
+    for c in comps:
+        assert abs(np.sum(dU[c])) < 1e-13 * np.sum(np.abs(dU[c]))
+    assert abs(np.sum(dJ)) < 1e-12 * (np.sum(np.abs(dJ)) + 1)
+
+
+@pytest.mark.parametrize("phys,dim,n", CASES)
+def test_literal_fluxes_equal_telescoped_pairs(phys, dim, n):
+    # eq. ECFlux_O2p summed over s telescopes to sum_n alpha_n [F~(i,i+n) - F~(i-n,i)]:
+    # an independent assembly of the EC part from the pair flux alone
+    g, x, xdot, met, P = setup(phys, dim, n, seed=4)
+    sc = wl.Scheme(phys=phys, dissipation=0)
+    dU, dJ = rs.residual(g, sc, st.pad_solution(g, P), met)
+    Ppad = st.pad_solution(g, P)
+    al = mt.alpha(3)
+    want = np.zeros((8,) + g.shape)
+    wantJ = np.zeros(g.shape)
+    src = np.zeros(g.shape)
+    for k in range(dim):
+        ax = dim - 1 - k
+        Pk = rs._line_view(Ppad, g, k, 1)
+        ak = rs._line_view(met[k * (dim + 1):(k + 1) * (dim + 1)], g, k, 1)
+        i = np.arange(3, 3 + g.n[k])
+        for m in range(1, 4):
+            T = lambda a, idx: np.take(a, idx, axis=1 + ax)
+            fp = ec.curvilinear_pair(T(Pk, i), T(Pk, i + m), T(ak, i), T(ak, i + m), G, phys, dim)
+            fm = ec.curvilinear_pair(T(Pk, i - m), T(Pk, i), T(ak, i - m), T(ak, i), G, phys, dim)
+            want -= al[m - 1] * (fp - fm) / g.dxi[k]
+            wantJ -= al[m - 1] * 0.5 * (T(ak, i + m)[0] - T(ak, i - m)[0]) / g.dxi[k]
+            if phys == ph.RMHD:
+                src += al[m - 1] * (ec.curvilinear_pair_B(T(Pk, i), T(Pk, i + m), T(ak, i), T(ak, i + m), dim)
+                                    - ec.curvilinear_pair_B(T(Pk, i - m), T(Pk, i), T(ak, i - m), T(ak, i), dim)) / g.dxi[k]
+    if phys == ph.RMHD:
+        want -= ph.phi_prime(P, G) * src
+    sel = ph.comps(phys, dim)
+    np.testing.assert_allclose(dU, want[sel], rtol=1e-11, atol=1e-11 * np.max(np.abs(dU)))
+    np.testing.assert_allclose(dJ, wantJ, rtol=1e-11, atol=1e-12 * (1 + np.max(np.abs(dJ))))
+
+
+def _order_errors(diss, moving, Ns):
+    errs = []
+    for n in Ns:
+        g = wl.make_grid(2, (n, n, 1), (0, 0, 0))
+        x = wl.perturbed_mesh(g, np.random.default_rng(5), amp=0.02)
+        xdot = (wl.perturbed_mesh(g, np.random.default_rng(9), amp=0.05) - wl.uniform_mesh(g)) if moving else np.zeros_like(x)
+        s = x[0] + x[1]
+        rho = 1 + 0.2 * np.sin(2 * np.pi * s)
+        drho = 0.4 * np.pi * np.cos(2 * np.pi * s)
+        vx = vy = 0.2
+        W = 1 / np.sqrt(1 - vx * vx - vy * vy)
+        u = np.zeros((3,) + g.shape)
+        u[0], u[1] = W * vx, W * vy
+        P = ph.full_prim(rho, u, np.ones(g.shape), np.zeros((3,) + g.shape))
+        met = mt.metrics(g, x, xdot)
+        J = mt.jacobian(g, x)
+        dU, dJ = rs.residual(g, wl.Scheme(dissipation=diss), st.pad_solution(g, P), met)
+        U = ph.cons(P, G)[[0, 1, 2, 4]]
+        # exact rate of change following a mesh node of the advected-density solution
+        dUdrho = np.array([W, W * W * vx, W * W * vy, W * W])[:, None, None]
+        exact = dUdrho * ((xdot[0] + xdot[1]) - (vx + vy)) * drho
+        errs.append(np.mean(np.abs((dU - U * dJ) / J - exact)))     # discrete L1 norm
+    return np.array(errs)
+
+
+@pytest.mark.parametrize("moving", [0, 1])
+def test_ec_residual_sixth_order(moving):
+    e = _order_errors(0, moving, (16, 32, 64))
+    rates = np.log2(e[:-1] / e[1:])
+    assert rates[-1] > 5.7, (e, rates)
+
+
+@pytest.mark.parametrize("moving", [0, 1])
+def test_es_residual_fifth_order(moving):
+    e = _order_errors(1, moving, (32, 64, 128))
+    rates = np.log2(e[:-1] / e[1:])
+    assert rates[-1] > 4.8, (e, rates)
