@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Benchmark: cell-updates/s of one SSP-RK3 step of the entropy-stable adaptive
+moving-mesh scheme (2D RHD quadrant Riemann problem, 400 x 400 nodes, adaptive
+mesh with 10 Jacobi sweeps, FP64) on one MI355X.
+
+One step = the whole hot path: con2prim, CFL step, mesh redistribution
+(monitor, filter, Jacobi sweeps, Delta_tau, new mesh and mesh velocity) and
+three Runge-Kutta stages of metrics + con2prim + residual + combination.
+Inputs are resident in HBM before the timed region; the time step stays on the
+device (no host synchronisation inside the timed steps).
+
+Prints one JSON line (see the repository contract).  ``--gpus N`` with N > 1
+exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per RK3 step, FP64 vs FP32-mixed at stated L1 err; adjoint/fwd"
+PEAK_FP64_VECTOR = 78.6e12       # FLOP/s, MI355X FP64 vector (FMA = 2 flops)
+PEAK_HBM = 8.0e12                # B/s
+
+# Algorithmic FP64 operations of one es_residual call per interior node (both
+# directions of the 2D RHD ES scheme, p = 3): counted by executing the device
+# arithmetic of the two-point flux and of the face dissipation with an
+# op-counting scalar (paper_2107_12027_amd/csrc/opcount.cpp); each of + - * /,
+# fma (2), sqrt, log, fabs/fmax/fmin comparisons counts as written there.
+RESIDUAL_FLOPS_PER_NODE_2D_RHD = None   # filled from opcount output when known
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=400)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--residual-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def cpu_baseline(n, seed):
+    """The oracle as it stands, timed on the host for one RK3 step of the same workload."""
+    import numpy as np
+    from oracle import physics as ph, stepper as st
+    from paper_2107_12027_amd import workloads as wl
+    w = wl.quadrant_riemann(n=n, seed=seed)
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    U, J = st.initial_state(w.grid, w.scheme, P, w.x)
+    t0 = time.perf_counter()
+    out = st.rk3_step(w.grid, w.scheme, w.monitor, U, J, w.x)
+    t = time.perf_counter() - t0
+    if not out["ok"].all():
+        return None
+    return {"value": w.grid.nnodes / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "one SSP-RK3 step of the full %dx%d workload from its initial state "
+                      "(numpy oracle, %.1f s)" % (n, n, t)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2107_12027_amd import es, workloads as wl
+
+    torch.cuda.set_device(0)
+    w = wl.quadrant_riemann(n=args.n, seed=args.seed)
+    g = w.grid
+    ctx = es.Context(g, w.scheme, w.monitor)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    sel = [0, 1, 2, 4]
+    P = np.concatenate([w.prim["rho"][None], w.prim["u"], w.prim["p"][None], w.prim["B"]])
+    met = torch.empty((ctx.nmet,) + ctx.padded_shape(), dtype=torch.float64, device="cuda")
+    prim = torch.empty((ctx.nprim,) + ctx.padded_shape(), dtype=torch.float64, device="cuda")
+    J = torch.empty(ctx.shape(), dtype=torch.float64, device="cuda")
+    x = dev(w.x)
+    ctx.metrics(x, None, met, J)
+    U = torch.empty((ctx.m,) + ctx.shape(), dtype=torch.float64, device="cuda")
+    ctx.prim2con(dev(P[sel]), J, U)
+    xdot = torch.empty_like(x)
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    for _ in range(args.warmup):
+        ctx.rk3_step(U, J, x, xdot, dt)
+    torch.cuda.synchronize()
+    st0 = ctx.status()[0]
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.rk3_step(U, J, x, xdot, dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_ms = e0.elapsed_time(e1)
+    status, nfail, first = ctx.status()
+    if st0 != es.ES_OK or status != es.ES_OK:
+        print("bench.py: con2prim failure during the run (status %d, %d nodes, first %d)"
+              % (status, nfail, first), file=sys.stderr)
+        sys.exit(3)
+
+    # dominant kernel: the residual (two directional sweeps) on the final state
+    dU = torch.empty_like(U)
+    dJ = torch.empty_like(J)
+    ctx.con2prim(U, J, prim)
+    ctx.metrics(x, xdot, met)
+    ctx.residual(prim, met, dU, dJ)
+    torch.cuda.synchronize()
+    r0 = torch.cuda.Event(enable_timing=True)
+    r1 = torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    for _ in range(args.residual_reps):
+        ctx.residual(prim, met, dU, dJ)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    res_ms = r0.elapsed_time(r1) / args.residual_reps
+
+    nodes = g.nnodes
+    value = nodes * args.steps / (t_ms * 1e-3)
+    flops = RESIDUAL_FLOPS_PER_NODE_2D_RHD
+    roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
+            "frac": None, "traffic": None, "kernel": "es_residual (k_residual_rhd x- and y-sweep)",
+            "avg_launch_ms": res_ms}
+    if flops is not None:
+        ach = flops * nodes / (res_ms * 1e-3)
+        roof["achieved"] = ach / 1e12
+        roof["frac"] = ach / PEAK_FP64_VECTOR
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.n, args.seed)
+    line = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "system": "2D RHD, Gamma 5/3", "grid": [args.n, args.n],
+                   "nodes": nodes, "scheme": "ES: 6th-order EC flux + WENO5 dissipation, SSP-RK3, CFL 0.4",
+                   "mesh": "adaptive, monitor alpha 1200 on ln rho, 3 filter passes, 10 Jacobi sweeps",
+                   "boundary": "outflow", "precision": "FP64"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

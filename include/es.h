@@ -1,0 +1,184 @@
+/*
+ * es.h -- C ABI of libes.so: the entropy-stable adaptive moving-mesh finite
+ * difference residual of Duan & Tang, "High-order accurate entropy stable
+ * adaptive moving mesh finite difference schemes for special relativistic
+ * (magneto)hydrodynamics" (arXiv 2107.12027), on one MI355X (gfx950) GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.  Every array argument is a DEVICE pointer owned by the caller; the
+ *   library never frees it and keeps no reference after the call returns.
+ *   Scalars that feed back into the computation (time step, mesh-move limiter)
+ *   stay in device memory ("*_dev" arguments) so a whole step runs without a
+ *   host synchronisation.  Only es_ctx_status() synchronises.
+ * Streams.  Work is enqueued on the given hipStream_t; calls on one stream
+ *   are ordered.  Calls that share an es_ctx use its workspace and must not
+ *   run concurrently on different streams.
+ * Layout.  All fields are float64, component-major structure-of-arrays:
+ *   a[c * nodes + node].  Interior node fields ("interior", nodes = n0*n1*n2)
+ *   index node = (k*n1 + j)*n0 + i with i fastest along xi_1.  Padded fields
+ *   ("padded") cover the box grown by NG = 3 ghost layers on each side of every
+ *   active axis: P0 = n0+6, P1 = n1+6, P2 = n2+6 (3D) or 1 (2D), node =
+ *   ((k+g)*P1 + (j+3))*P0 + (i+3) with g = 3 in 3D and 0 in 2D.
+ * Variables.  m = es_nvars(): 2D RHD (D, m1, m2, E); 3D RHD (D, m1, m2, m3, E);
+ *   RMHD (D, m1, m2, m3, E, B1, B2, B3) (eq. RMHDdiv2).  Ucurv = J U (eq. RMHDCurv).
+ *   Primitive interior input (es_prim2con): (rho, u_1..u_nu, p[, B1, B2, B3])
+ *   with u = W v (nu = dim for RHD, 3 for RMHD) -- the same slots as U.
+ *   Padded primitive output of es_con2prim has es_nprim() = m + 2 components:
+ *   the m primitive slots, then ln(rho) and ln(beta), beta = rho/p.
+ *   Metrics (es_nmet() = d(d+1) padded components): comp k*(d+1) is
+ *   J dxi_k/dt, comp k*(d+1)+1+j is J dxi_k/dx_j (Section 3.3).
+ * Errors.  Every entry point returns es_status; no C++ exception crosses the
+ *   ABI.  Invalid arguments give ES_EINVAL before anything is enqueued.  A HIP
+ *   launch error gives ES_EHIP.  Conservative-to-primitive failures are
+ *   recorded on the device (count and first failing interior node, the
+ *   primitive output is NaN there) and reported by es_ctx_status().
+ */
+#ifndef ES_H
+#define ES_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ES_OK = 0,
+    ES_EINVAL = 1,        /* bad argument (sizes, null pointer, unsupported option) */
+    ES_EADMISSIBLE = 2,   /* a state outside the admissible set reached con2prim */
+    ES_ENOCONV = 3,       /* con2prim iteration did not converge */
+    ES_EMESH = 4,         /* non-positive Jacobian */
+    ES_EHIP = 5,          /* HIP runtime error */
+    ES_EUNSUPPORTED = 6   /* valid option not built into this library */
+} es_status;
+
+enum { ES_RHD = 0, ES_RMHD = 1 };
+enum { ES_BC_PERIODIC = 0, ES_BC_OUTFLOW = 1 };
+enum { ES_SIGMA_RHO = 0, ES_SIGMA_LNRHO = 1 };
+enum { ES_MON_PAPER = 0, ES_MON_SQGRAD = 1 };
+
+/* Computational grid: a fixed orthogonal index box with constant spacing
+ * (Section 3.2).  Periodic axes wrap the solution and shift the mesh
+ * coordinate of that axis by period[k]; outflow axes copy the solution
+ * (zero gradient) and extend the mesh by odd reflection. */
+typedef struct {
+    int dim;            /* 2 or 3 */
+    int n[3];           /* interior nodes per axis, n[2] = 1 in 2D; >= 7 on outflow axes */
+    int bc[3];          /* ES_BC_PERIODIC / ES_BC_OUTFLOW */
+    double dxi[3];      /* computational spacing Delta xi_k */
+    double period[3];   /* physical period of periodic axes */
+} es_grid;
+
+/* Scheme parameters (Sections 3-4, eq. cfl). */
+typedef struct {
+    int phys;           /* ES_RHD / ES_RMHD */
+    double gamma;       /* adiabatic index of the ideal EOS (eq. EOS) */
+    int order_p;        /* p of the 2p-th order EC flux; this build supports p = 3 */
+    int dissipation;    /* 0: entropy conservative, 1: entropy stable (WENO-(2p-1)) */
+    int mixed;          /* 0: FP64 throughout; 1: FP32 pair/WENO arithmetic, FP64 elsewhere */
+    double weno_eps;    /* WENO-JS epsilon */
+    double cfl;         /* CFL number of eq. cfl */
+} es_scheme;
+
+/* Adaptive mesh redistribution (Section 5). */
+typedef struct {
+    int enabled;        /* 0: static mesh (xdot = 0) */
+    int sigma;          /* ES_SIGMA_RHO / ES_SIGMA_LNRHO: monitored variable */
+    int form;           /* ES_MON_PAPER: sqrt(1 + alpha |grad s| / max |grad s|) (eq. monitor);
+                           ES_MON_SQGRAD: sqrt(1 + alpha |grad s|^2) */
+    double alpha;
+    int filter_passes;  /* low-pass filter passes */
+    int sweeps;         /* Jacobi sweeps mu */
+} es_monitor;
+
+typedef struct es_ctx es_ctx;
+
+/* Validate the options and allocate the context workspace (device memory
+ * sized for one grid).  *out receives the context; free with es_destroy. */
+es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monitor* monitor,
+                    es_ctx** out);
+es_status es_destroy(es_ctx* ctx);
+
+size_t es_nvars(const es_ctx* ctx);          /* m */
+size_t es_nprim(const es_ctx* ctx);          /* m + 2 */
+size_t es_nmet(const es_ctx* ctx);           /* d (d + 1) */
+size_t es_nodes(const es_ctx* ctx);          /* interior nodes */
+size_t es_padded_nodes(const es_ctx* ctx);   /* padded nodes */
+
+/* Ucurv = J U(prim) on the interior (eq. RMHDdiv2, eq. RMHDCurv).
+ * prim: interior, m comps (rho, u, p[, B]); J: interior; Ucurv: interior, m comps. */
+es_status es_prim2con(es_ctx* ctx, const double* prim, const double* J, double* Ucurv,
+                      hipStream_t stream);
+
+/* Discrete metrics (Section 3.3, eq. SCLCoeff, eq. VCLCoeff; Appendix B in 2D)
+ * with the 2p-th order central difference delta_k, evaluated on the padded box
+ * from the mesh x (interior, d comps) extended by the boundary rule.
+ * xdot: interior mesh velocity (d comps) or NULL for zero temporal metrics.
+ * met: padded, d(d+1) comps.  J0: NULL, or interior output of the initial
+ * Jacobian (2D: (delta_xi[x] delta_eta[y] - delta_eta[x] delta_xi[y])/(dxi deta);
+ * 3D: sum_k (J dxi_k/dx_1) delta_k[x_1]/dxi_k). */
+es_status es_metrics(es_ctx* ctx, const double* x, const double* xdot, double* met, double* J0,
+                     hipStream_t stream);
+
+/* Conservative-to-primitive recovery (Section 1: the nonlinear algebraic
+ * equation; solver of this build: safeguarded Newton on p for RHD) at every
+ * padded node, ghosts filled by the boundary rule.  Ucurv, J: interior.
+ * prim: padded, m + 2 comps. */
+es_status es_con2prim(es_ctx* ctx, const double* Ucurv, const double* J, double* prim,
+                      hipStream_t stream);
+
+/* Semi-discrete right-hand side (eq. RMHDSemiU_O2p_ES, eq. RMHDSemiJ_O2p_ES):
+ * 2p-th order EC flux differences built from two-point EC fluxes (Proposition
+ * 4.1), ES dissipation (eq. ESFlux_HO) when scheme.dissipation = 1, the
+ * Godunov-Powell source for RMHD and the VCL.  prim, met: padded (from
+ * es_con2prim / es_metrics).  dUcurv: interior m comps; dJ: interior. */
+es_status es_residual(es_ctx* ctx, const double* prim, const double* met, double* dUcurv,
+                      double* dJ, hipStream_t stream);
+
+/* CFL time step (eq. cfl): dt = CFL / sum_k max_i rho_{k,i}/dxi_k with
+ * rho_{k,i} = L_k max_m |lambda_m| / J_i (fluid speeds on the current mesh).
+ * prim, met: padded; J: interior; dt_dev: one device double (output). */
+es_status es_cfl(es_ctx* ctx, const double* prim, const double* met, const double* J,
+                 double* dt_dev, hipStream_t stream);
+
+/* Mesh redistribution (Section 5): monitor, low-pass filter, Jacobi sweeps,
+ * move limiter Delta_tau, x_new = x + Delta_tau (x^[mu] - x),
+ * xdot = Delta_tau (x^[mu] - x) / dt.  prim: padded; x: interior (d comps);
+ * dt_dev: device double; x_new, xdot: interior outputs (d comps);
+ * dtau_dev: NULL or device double output.  x_new must not alias x. */
+es_status es_mesh_redistribute(es_ctx* ctx, const double* prim, const double* x,
+                               const double* dt_dev, double* x_new, double* xdot,
+                               double* dtau_dev, hipStream_t stream);
+
+/* One third-order SSP Runge-Kutta step of the whole scheme (con2prim, CFL,
+ * mesh redistribution when enabled, three stages with metrics recomputed on
+ * the stage meshes x + c dt xdot, c = 0, 1, 1/2), in place on Ucurv, J, x
+ * (interior).  xdot: interior output (d comps).  dt_dev: device double output.
+ * If fixed_dt_dev is not NULL the step uses that device value instead of the
+ * CFL step. */
+es_status es_rk3_step(es_ctx* ctx, double* Ucurv, double* J, double* x, double* xdot,
+                      double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
+
+/* FP64 diagnostics on the interior (Theorem 4.1 / 5.1, Section 6 total entropy):
+ * out_dev[0] = sum_i (V_i . dUcurv_i - phi_i dJ_i)   (entropy production rate)
+ * out_dev[1] = sum_i J_i eta_i                         (total entropy)
+ * out_dev[2] = sum_i J_i
+ * out_dev[3 .. 3+m) = sum_i Ucurv_i                    (conserved totals)
+ * prim: padded; the other arrays interior; out_dev: device, 3 + m doubles. */
+es_status es_diagnostics(es_ctx* ctx, const double* prim, const double* Ucurv, const double* J,
+                         const double* dUcurv, const double* dJ, double* out_dev,
+                         hipStream_t stream);
+
+/* Synchronise the stream and report recorded con2prim failures since the last
+ * call (then clear them): ES_OK, ES_EADMISSIBLE or ES_ENOCONV.  n_fail and
+ * first_fail (interior node index) may be NULL. */
+es_status es_ctx_status(es_ctx* ctx, hipStream_t stream, long long* n_fail, long long* first_fail);
+
+const char* es_status_string(es_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ES_H */

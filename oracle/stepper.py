@@ -95,6 +95,9 @@ def rk3_step(grid, scheme, mon, Ucurv, J, x, dt=None, details=False, xdot=None):
         if s > 0:
             P, oks = prim_from_cons(grid, scheme, Us, Js)
             ok = ok & oks
+        if not ok.all():
+            # an inadmissible state reached con2prim: stop and report (no clipping)
+            return dict(U=Ucurv, J=J, x=x, xdot=xdot, dt=dt, ok=ok, dtau=dtau, failed_stage=s)
         xs = x + coef[s] * dt * xdot
         met = mt.metrics(grid, xs, xdot, scheme.order_p)
         L, LJ = rs.residual(grid, scheme, pad_solution(grid, P), met)

@@ -1,0 +1,58 @@
+"""Build libes.so (HIP, gfx950) in-tree with hipcc.
+
+    python -m paper_2107_12027_amd.build            # compile
+    python -m paper_2107_12027_amd.build --verbose
+
+The library is written next to this file so that it travels with the source
+tree; tests, smoke() and bench.py load it from there and never compile.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libes.so")
+ARCH = "gfx950"
+
+SOURCES = ["es_api.hip", "es_kernels.hip"]
+HEADERS = ["es_common.h", "es_internal.h", "es_rhd.h"]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found (ROCm is required to build libes.so)")
+
+
+def command(out: str = LIB):
+    return [hipcc(), "-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-shared",
+            # packed FP32 instructions are kept out of all device code
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+            "-I" + INCLUDE, "-I" + CSRC, "-o", out] + [os.path.join(CSRC, s) for s in SOURCES]
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    cmd = command(tmp)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building libes.so")
+    if verbose and res.stderr.strip():
+        sys.stderr.write(res.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="--verbose" in sys.argv))

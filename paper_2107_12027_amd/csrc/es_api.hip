@@ -1,0 +1,236 @@
+// C ABI of libes.so: context, argument validation and the SSP-RK3 step.
+#include <limits.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "es_internal.h"
+
+using es::GridDev;
+
+namespace {
+
+es_status hip_status(hipError_t e) { return e == hipSuccess ? ES_OK : ES_EHIP; }
+
+#define ES_TRY(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return ES_EHIP;          \
+    } while (0)
+
+bool valid_grid(const es_grid* g) {
+    if (g == nullptr || (g->dim != 2 && g->dim != 3)) return false;
+    for (int k = 0; k < 3; ++k) {
+        if (k >= g->dim) {
+            if (g->n[k] != 1) return false;
+            continue;
+        }
+        if (g->bc[k] != ES_BC_PERIODIC && g->bc[k] != ES_BC_OUTFLOW) return false;
+        if (!(g->dxi[k] > 0.0)) return false;
+        // the mesh extension by reflection reaches 2*NG = 6 nodes past an edge
+        if (g->bc[k] == ES_BC_OUTFLOW && g->n[k] < 7) return false;
+        if (g->bc[k] == ES_BC_PERIODIC && (g->n[k] < 1 || !(g->period[k] > 0.0))) return false;
+        if (g->n[k] > (1 << 24)) return false;
+    }
+    return true;
+}
+
+template <typename T>
+hipError_t alloc(T** p, size_t n) {
+    return hipMalloc((void**)p, (n > 0 ? n : 1) * sizeof(T));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* es_status_string(es_status s) {
+    switch (s) {
+        case ES_OK: return "ok";
+        case ES_EINVAL: return "invalid argument";
+        case ES_EADMISSIBLE: return "inadmissible state in con2prim";
+        case ES_ENOCONV: return "con2prim did not converge";
+        case ES_EMESH: return "non-positive Jacobian";
+        case ES_EHIP: return "HIP runtime error";
+        case ES_EUNSUPPORTED: return "option not supported by this build";
+    }
+    return "unknown status";
+}
+
+es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monitor* monitor,
+                    es_ctx** out) {
+    if (out == nullptr) return ES_EINVAL;
+    *out = nullptr;
+    if (!valid_grid(grid) || scheme == nullptr || monitor == nullptr) return ES_EINVAL;
+    if (scheme->phys != ES_RHD && scheme->phys != ES_RMHD) return ES_EINVAL;
+    if (!(scheme->gamma > 1.0 && scheme->gamma <= 2.0)) return ES_EINVAL;
+    if (!(scheme->weno_eps > 0.0) || !(scheme->cfl > 0.0)) return ES_EINVAL;
+    if (scheme->dissipation != 0 && scheme->dissipation != 1) return ES_EINVAL;
+    if (scheme->mixed != 0 && scheme->mixed != 1) return ES_EINVAL;
+    if (monitor->enabled) {
+        if (monitor->sigma != ES_SIGMA_RHO && monitor->sigma != ES_SIGMA_LNRHO) return ES_EINVAL;
+        if (monitor->form != ES_MON_PAPER && monitor->form != ES_MON_SQGRAD) return ES_EINVAL;
+        if (monitor->filter_passes < 0 || monitor->sweeps < 0 || !(monitor->alpha >= 0.0)) return ES_EINVAL;
+    }
+    // kernels of this build: RHD, p = 3, FP64, 2D
+    if (scheme->phys != ES_RHD || scheme->order_p != 3 || scheme->mixed != 0 || grid->dim != 2)
+        return ES_EUNSUPPORTED;
+
+    es_ctx* c = new (std::nothrow) es_ctx();
+    if (c == nullptr) return ES_EHIP;
+    memset(c, 0, sizeof(*c));
+    c->grid = *grid;
+    c->scheme = *scheme;
+    c->monitor = *monitor;
+    GridDev& g = c->g;
+    g.dim = grid->dim;
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = grid->n[k];
+        g.bc[k] = grid->bc[k];
+        g.dxi[k] = grid->dxi[k];
+        g.period[k] = grid->period[k];
+        g.P[k] = (k < grid->dim) ? grid->n[k] + 2 * es::NG : 1;
+    }
+    g.g2 = grid->dim == 3 ? es::NG : 0;
+    g.nodes = (long long)g.n[0] * g.n[1] * g.n[2];
+    g.pnodes = (long long)g.P[0] * g.P[1] * g.P[2];
+    c->m = scheme->phys == ES_RMHD ? 8 : grid->dim + 2;
+    c->nprim = c->m + 2;
+    c->nmet = grid->dim * (grid->dim + 1);
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return ES_EHIP; }
+    long long nb = (g.nodes + 255) / 256;
+    c->red_blocks = (int)(nb < es::MAX_RED_BLOCKS ? (nb < 1 ? 1 : nb) : es::MAX_RED_BLOCKS);
+    const size_t N = (size_t)g.nodes, P = (size_t)g.pnodes, d = (size_t)grid->dim;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = alloc(&c->prim, P * c->nprim);
+    if (e == hipSuccess) e = alloc(&c->met, P * c->nmet);
+    if (e == hipSuccess) e = alloc(&c->L, N * c->m);
+    if (e == hipSuccess) e = alloc(&c->LJ, N);
+    if (e == hipSuccess) e = alloc(&c->Us, N * c->m);
+    if (e == hipSuccess) e = alloc(&c->Js, N);
+    if (e == hipSuccess) e = alloc(&c->xnew, N * d);
+    if (e == hipSuccess) e = alloc(&c->xa, N * d);
+    if (e == hipSuccess) e = alloc(&c->xb, N * d);
+    if (e == hipSuccess) e = alloc(&c->wa, N);
+    if (e == hipSuccess) e = alloc(&c->wb, N);
+    if (e == hipSuccess) e = alloc(&c->red, (size_t)es::MAX_RED_BLOCKS * (3 + 8));
+    if (e == hipSuccess) e = alloc(&c->scal, (size_t)es::NSCAL);
+    if (e == hipSuccess) e = alloc(&c->fail, (size_t)4);
+    if (e == hipSuccess) {
+        (void)es::launch_fill_u64(c->fail, 0ull, 2, nullptr);
+        e = es::launch_fill_u64(c->fail + 2, ULLONG_MAX, 1, nullptr);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        es_destroy(c);
+        return ES_EHIP;
+    }
+    *out = c;
+    return ES_OK;
+}
+
+es_status es_destroy(es_ctx* c) {
+    if (c == nullptr) return ES_EINVAL;
+    void* bufs[] = {c->prim, c->met, c->L, c->LJ, c->Us, c->Js, c->xnew, c->xa, c->xb,
+                    c->wa, c->wb, c->red, c->scal, c->fail};
+    for (void* b : bufs)
+        if (b != nullptr) (void)hipFree(b);
+    delete c;
+    return ES_OK;
+}
+
+size_t es_nvars(const es_ctx* c) { return c ? (size_t)c->m : 0; }
+size_t es_nprim(const es_ctx* c) { return c ? (size_t)c->nprim : 0; }
+size_t es_nmet(const es_ctx* c) { return c ? (size_t)c->nmet : 0; }
+size_t es_nodes(const es_ctx* c) { return c ? (size_t)c->g.nodes : 0; }
+size_t es_padded_nodes(const es_ctx* c) { return c ? (size_t)c->g.pnodes : 0; }
+
+es_status es_prim2con(es_ctx* c, const double* prim, const double* J, double* U, hipStream_t s) {
+    if (c == nullptr || prim == nullptr || J == nullptr || U == nullptr) return ES_EINVAL;
+    return hip_status(es::launch_prim2con(c, prim, J, U, s));
+}
+
+es_status es_metrics(es_ctx* c, const double* x, const double* xdot, double* met, double* J0,
+                     hipStream_t s) {
+    if (c == nullptr || x == nullptr || met == nullptr) return ES_EINVAL;
+    return hip_status(es::launch_metrics(c, x, xdot, nullptr, 0.0, met, J0, s));
+}
+
+es_status es_con2prim(es_ctx* c, const double* U, const double* J, double* prim, hipStream_t s) {
+    if (c == nullptr || U == nullptr || J == nullptr || prim == nullptr) return ES_EINVAL;
+    return hip_status(es::launch_con2prim(c, U, J, prim, s));
+}
+
+es_status es_residual(es_ctx* c, const double* prim, const double* met, double* dU, double* dJ,
+                      hipStream_t s) {
+    if (c == nullptr || prim == nullptr || met == nullptr || dU == nullptr || dJ == nullptr)
+        return ES_EINVAL;
+    return hip_status(es::launch_residual(c, prim, met, dU, dJ, s));
+}
+
+es_status es_cfl(es_ctx* c, const double* prim, const double* met, const double* J, double* dt_dev,
+                 hipStream_t s) {
+    if (c == nullptr || prim == nullptr || met == nullptr || J == nullptr || dt_dev == nullptr)
+        return ES_EINVAL;
+    return hip_status(es::launch_cfl(c, prim, met, J, dt_dev, nullptr, s));
+}
+
+es_status es_mesh_redistribute(es_ctx* c, const double* prim, const double* x, const double* dt_dev,
+                               double* x_new, double* xdot, double* dtau_dev, hipStream_t s) {
+    if (c == nullptr || prim == nullptr || x == nullptr || dt_dev == nullptr || x_new == nullptr ||
+        xdot == nullptr || x_new == x)
+        return ES_EINVAL;
+    if (!c->monitor.enabled) return hip_status(es::launch_zero_mesh_velocity(c, x, x_new, xdot, s));
+    return hip_status(es::launch_mesh(c, prim, x, dt_dev, x_new, xdot, dtau_dev, s));
+}
+
+es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, double* dt_dev,
+                      const double* fixed_dt_dev, hipStream_t s) {
+    if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
+        dt_dev == nullptr)
+        return ES_EINVAL;
+    // con2prim, metrics on x^n (spatial part), CFL step
+    ES_TRY(es::launch_con2prim(c, U, J, c->prim, s));
+    ES_TRY(es::launch_metrics(c, x, nullptr, nullptr, 0.0, c->met, nullptr, s));
+    ES_TRY(es::launch_cfl(c, c->prim, c->met, J, dt_dev, fixed_dt_dev, s));
+    // mesh redistribution: x^{n+1} into c->xnew, mesh velocity into xdot
+    if (c->monitor.enabled)
+        ES_TRY(es::launch_mesh(c, c->prim, x, dt_dev, c->xnew, xdot, nullptr, s));
+    else
+        ES_TRY(es::launch_zero_mesh_velocity(c, x, c->xnew, xdot, s));
+    static const double coef[3] = {0.0, 1.0, 0.5};
+    for (int st = 0; st < 3; ++st) {
+        if (st > 0) ES_TRY(es::launch_con2prim(c, c->Us, c->Js, c->prim, s));
+        ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s));
+        ES_TRY(es::launch_residual(c, c->prim, c->met, c->L, c->LJ, s));
+        ES_TRY(es::launch_rk_combine(c, st, U, J, c->Us, c->Js, c->L, c->LJ, dt_dev, s));
+    }
+    ES_TRY(es::launch_copy(x, c->xnew, c->g.nodes * c->g.dim, s));
+    return ES_OK;
+}
+
+es_status es_diagnostics(es_ctx* c, const double* prim, const double* U, const double* J,
+                         const double* dU, const double* dJ, double* out, hipStream_t s) {
+    if (c == nullptr || prim == nullptr || U == nullptr || J == nullptr || dU == nullptr ||
+        dJ == nullptr || out == nullptr)
+        return ES_EINVAL;
+    return hip_status(es::launch_diagnostics(c, prim, U, J, dU, dJ, out, s));
+}
+
+es_status es_ctx_status(es_ctx* c, hipStream_t s, long long* n_fail, long long* first_fail) {
+    if (c == nullptr) return ES_EINVAL;
+    if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
+    unsigned long long h[3];
+    if (hipMemcpy(h, c->fail, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return ES_EHIP;
+    if (n_fail) *n_fail = (long long)(h[0] + h[1]);
+    if (first_fail) *first_fail = h[2] == ULLONG_MAX ? -1 : (long long)h[2];
+    (void)es::launch_fill_u64(c->fail, 0ull, 2, s);
+    (void)es::launch_fill_u64(c->fail + 2, ULLONG_MAX, 1, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
+    if (h[0] > 0) return ES_EADMISSIBLE;
+    if (h[1] > 0) return ES_ENOCONV;
+    return ES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Host-side context and kernel launchers of libes.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "es.h"
+#include "es_common.h"
+
+struct es_ctx {
+    es_grid grid;
+    es_scheme scheme;
+    es_monitor monitor;
+    es::GridDev g;
+    int m;          // conserved variables
+    int nprim;      // padded primitive comps (m + 2)
+    int nmet;       // metric comps d(d+1)
+    int device;
+    // workspace (device)
+    double* prim;   // padded, nprim comps
+    double* met;    // padded, nmet comps
+    double* L;      // interior, m comps (stage residual)
+    double* LJ;     // interior
+    double* Us;     // interior, m comps (stage state)
+    double* Js;     // interior
+    double* xnew;   // interior, d comps
+    double* xa;     // interior, d comps (Jacobi ping)
+    double* xb;     // interior, d comps (Jacobi pong)
+    double* wa;     // interior (monitor ping)
+    double* wb;     // interior (monitor pong)
+    double* red;    // reduction partials
+    double* scal;   // device scalars: [0] dt, [1] gmax, [2] dtau, [3..] spare
+    unsigned long long* fail;   // [0] count inadmissible, [1] count no-convergence, [2] first index
+    int red_blocks;
+};
+
+namespace es {
+
+constexpr int SCAL_DT = 0;
+constexpr int SCAL_GMAX = 1;
+constexpr int SCAL_DTAU = 2;
+constexpr int NSCAL = 8;
+constexpr int MAX_RED_BLOCKS = 1024;
+
+hipError_t launch_prim2con(const es_ctx* c, const double* prim, const double* J, double* U,
+                           hipStream_t s);
+hipError_t launch_con2prim(const es_ctx* c, const double* U, const double* J, double* prim,
+                           hipStream_t s);
+hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
+                          const double* dt_dev, double coef, double* met, double* J0,
+                          hipStream_t s);
+hipError_t launch_residual(const es_ctx* c, const double* prim, const double* met, double* dU,
+                           double* dJ, hipStream_t s);
+hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, const double* J,
+                      double* dt_dev, const double* fixed_dt_dev, hipStream_t s);
+hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, const double* dt_dev,
+                       double* x_new, double* xdot, double* dtau_dev, hipStream_t s);
+hipError_t launch_zero_mesh_velocity(const es_ctx* c, const double* x, double* x_new, double* xdot,
+                                     hipStream_t s);
+hipError_t launch_rk_combine(const es_ctx* c, int stage, const double* U0, const double* J0,
+                             double* Us, double* Js, const double* L, const double* LJ,
+                             const double* dt_dev, hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, long long n, hipStream_t s);
+hipError_t launch_diagnostics(const es_ctx* c, const double* prim, const double* U,
+                              const double* J, const double* dU, const double* dJ, double* out,
+                              hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t s);
+
+}  // namespace es

@@ -1,0 +1,833 @@
+// HIP kernels of libes.so (gfx950) and their launchers.
+//
+// Node-parallel kernels map one thread to one node; the residual maps one
+// 64-lane wavefront to a 61-node segment of a grid line plus its 3-node halo,
+// stages the line in LDS and exchanges two-point fluxes and face dissipation
+// between lanes through LDS.  All scalars that feed back into the step (dt,
+// monitor maximum, Delta_tau) are produced by two-pass block reductions that
+// end in a one-block kernel: max/min are exact in any order, sums are only
+// used for diagnostics.
+#include <float.h>
+#include <math.h>
+
+#include "es_internal.h"
+#include "es_rhd.h"
+
+namespace es {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned grid_for(long long n, int tpb = TPB) {
+    return (unsigned)((n + tpb - 1) / tpb);
+}
+
+__device__ __forceinline__ long long gtid() {
+    return (long long)blockIdx.x * blockDim.x + threadIdx.x;
+}
+
+__device__ __forceinline__ void interior_coords(const GridDev& g, long long t, int& i, int& j, int& k) {
+    i = (int)(t % g.n[0]);
+    long long r = t / g.n[0];
+    j = (int)(r % g.n[1]);
+    k = (int)(r / g.n[1]);
+}
+
+__device__ __forceinline__ void padded_coords(const GridDev& g, long long t, int& i, int& j, int& k) {
+    i = (int)(t % g.P[0]) - NG;
+    long long r = t / g.P[0];
+    j = (int)(r % g.P[1]) - NG;
+    k = (int)(r / g.P[1]) - g.g2;
+}
+
+// Block reductions of one double (256 threads = 4 wavefronts).
+template <int OP>   // 0 max, 1 min, 2 sum
+__device__ __forceinline__ double block_reduce(double v, double* sh) {
+    v = OP == 0 ? wave_max(v) : (OP == 1 ? wave_min(v) : wave_sum(v));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = sh[0];
+    const int nw = blockDim.x >> 6;
+    for (int q = 1; q < nw; ++q) r = OP == 0 ? fmax(r, sh[q]) : (OP == 1 ? fmin(r, sh[q]) : r + sh[q]);
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, long long n) {
+    const long long t = gtid();
+    if (t < n) dst[t] = src[t];
+}
+
+// ---------------------------------------------------------------------------
+// primitive -> conservative (eq. RMHDdiv2 with B = 0), times J
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void k_prim2con_rhd(GridDev g, double G, const double* __restrict__ prim,
+                               const double* __restrict__ J, double* __restrict__ U) {
+    constexpr int M = DIM + 2;
+    const long long t = gtid();
+    if (t >= g.nodes) return;
+    const long long N = g.nodes;
+    const double rho = prim[t];
+    const double p = prim[(M - 1) * N + t];
+    double u[DIM], uu = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) { u[k] = prim[(1 + k) * N + t]; uu += u[k] * u[k]; }
+    const double W = sqrt(1.0 + uu);
+    const double h = 1.0 + G / (G - 1.0) * p / rho;
+    const double Jv = J[t];
+    U[t] = Jv * (rho * W);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) U[(1 + k) * N + t] = Jv * (rho * h * W * u[k]);
+    U[(M - 1) * N + t] = Jv * (rho * h * W * W - p);
+}
+
+// ---------------------------------------------------------------------------
+// conservative -> primitive on the padded box (ghosts by the solution rule)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void k_con2prim_rhd(GridDev g, double G, const double* __restrict__ U,
+                               const double* __restrict__ J, double* __restrict__ prim,
+                               unsigned long long* __restrict__ fail) {
+    constexpr int M = DIM + 2;
+    const long long t = gtid();
+    if (t >= g.pnodes) return;
+    int i, j, k;
+    padded_coords(g, t, i, j, k);
+    const int si = map_sol(i, g.n[0], g.bc[0]);
+    const int sj = map_sol(j, g.n[1], g.bc[1]);
+    const int sk = DIM == 3 ? map_sol(k, g.n[2], g.bc[2]) : 0;
+    const long long src = iidx(g, si, sj, sk);
+    const long long N = g.nodes;
+    const double Jv = J[src];
+    const double D = U[src] / Jv;
+    double m[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) m[c] = U[(1 + c) * N + src] / Jv;
+    const double E = U[(M - 1) * N + src] / Jv;
+    double rho, p, u[DIM];
+    const int st = c2p_rhd<DIM>(G, D, m, E, rho, u, p);
+    const long long P = g.pnodes;
+    if (st != 0) {
+        rho = p = __builtin_nan("");
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) u[c] = __builtin_nan("");
+        if (si == i && sj == j && sk == k) {
+            atomicAdd(&fail[st == 1 ? 0 : 1], 1ull);
+            atomicMin(&fail[2], (unsigned long long)src);
+        }
+    }
+    prim[t] = rho;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) prim[(1 + c) * P + t] = u[c];
+    prim[(M - 1) * P + t] = p;
+    prim[M * P + t] = log(rho);
+    prim[(M + 1) * P + t] = log(rho / p);
+}
+
+// ---------------------------------------------------------------------------
+// metrics (Section 3.3; 2D explicit form of Appendix B with 1/Delta xi)
+// ---------------------------------------------------------------------------
+__global__ void k_metrics2d(GridDev g, const double* __restrict__ x, const double* __restrict__ xd,
+                            const double* __restrict__ dt_dev, double coef,
+                            double* __restrict__ met, double* __restrict__ J0) {
+    const long long t = gtid();
+    if (t >= g.pnodes) return;
+    int i, j, k;
+    padded_coords(g, t, i, j, k);
+    const double cdt = dt_dev != nullptr ? coef * dt_dev[0] : 0.0;
+    const double* xs = dt_dev != nullptr ? xd : nullptr;
+    double dxi[2], deta[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        double s = 0.0, r = 0.0;
+#pragma unroll
+        for (int n = 1; n <= 3; ++n) {
+            const double a = 0.5 * alpha3(n);
+            s += a * (mesh_value(g, x, xs, cdt, c, i + n, j, 0, true) -
+                      mesh_value(g, x, xs, cdt, c, i - n, j, 0, true));
+            r += a * (mesh_value(g, x, xs, cdt, c, i, j + n, 0, true) -
+                      mesh_value(g, x, xs, cdt, c, i, j - n, 0, true));
+        }
+        dxi[c] = s;
+        deta[c] = r;
+    }
+    const long long P = g.pnodes;
+    const double xix = deta[1] / g.dxi[1];
+    const double xiy = -deta[0] / g.dxi[1];
+    const double etx = -dxi[1] / g.dxi[0];
+    const double ety = dxi[0] / g.dxi[0];
+    double at0 = 0.0, at1 = 0.0;
+    if (xd != nullptr) {
+        const double vx = mesh_value(g, xd, nullptr, 0.0, 0, i, j, 0, false);
+        const double vy = mesh_value(g, xd, nullptr, 0.0, 1, i, j, 0, false);
+        at0 = -(vx * xix + vy * xiy);
+        at1 = -(vx * etx + vy * ety);
+    }
+    met[0 * P + t] = at0;
+    met[1 * P + t] = xix;
+    met[2 * P + t] = xiy;
+    met[3 * P + t] = at1;
+    met[4 * P + t] = etx;
+    met[5 * P + t] = ety;
+    if (J0 != nullptr && i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1])
+        J0[iidx(g, i, j, 0)] = (dxi[0] * deta[1] - deta[0] * dxi[1]) / (g.dxi[0] * g.dxi[1]);
+}
+
+// ---------------------------------------------------------------------------
+// residual: one direction sweep
+// ---------------------------------------------------------------------------
+constexpr int SEG = 61;            // interior nodes per line segment
+constexpr int NLOAD = SEG + 6;     // loaded slots (3-node halo each side)
+constexpr int LINES = 4;           // line segments (wavefronts) per block
+
+template <int DIM, int DIR, bool ES, bool ACC>
+__global__ void __launch_bounds__(256) k_residual_rhd(GridDev g, double G, double eps,
+                                                      const double* __restrict__ prim,
+                                                      const double* __restrict__ met,
+                                                      double* __restrict__ dU,
+                                                      double* __restrict__ dJ, int nseg,
+                                                      long long nlines) {
+    constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1;
+    constexpr int F_RHO = 0, F_P = 1, F_BETA = 2, F_W = 3, F_LR = 4, F_LB = 5, F_U = 6,
+                  F_A = 6 + NU, NF = 6 + NU + NA;
+    __shared__ double sd[LINES][NF][NLOAD + 1];
+    __shared__ double sp[LINES][3][M + 1][64];
+
+    const int lane = threadIdx.x & 63;
+    const int line = threadIdx.x >> 6;
+    const int seg = blockIdx.x % nseg;
+    const long long lid = (long long)(blockIdx.x / nseg) * LINES + line;
+    const bool active = lid < nlines;
+    const int nAlong = g.n[DIR];
+    const int s0 = seg * SEG;
+    const int s_end = min(s0 + SEG, nAlong);
+
+    // transverse coordinates of this line and strides along it
+    int ci = 0, cj = 0, ck = 0;
+    if (active) {
+        if (DIR == 0) { cj = (int)(lid % g.n[1]); ck = (int)(lid / g.n[1]); }
+        else if (DIR == 1) { ci = (int)(lid % g.n[0]); ck = (int)(lid / g.n[0]); }
+        else { ci = (int)(lid % g.n[0]); cj = (int)(lid / g.n[0]); }
+    }
+    const long long pstride = DIR == 0 ? 1 : (DIR == 1 ? (long long)g.P[0] : (long long)g.P[0] * g.P[1]);
+    const long long istride = DIR == 0 ? 1 : (DIR == 1 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1]);
+    const long long pbase = pidx(g, ci, cj, ck);        // padded index of along-coordinate 0
+    const long long ibase = iidx(g, ci, cj, ck);
+    const long long P = g.pnodes;
+    const long long N = g.nodes;
+
+    // ---- load the line segment with its halo into LDS
+    for (int q = lane; q < NLOAD; q += 64) {
+        const int s = s0 - NG + q;
+        double rho = 1.0, p = 1.0, lr = 0.0, lb = 0.0, u[NU], a[NA];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) u[c] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NA; ++c) a[c] = c == 1 ? 1.0 : 0.0;
+        if (active && s < s_end + NG) {
+            const long long idx = pbase + (long long)s * pstride;
+            rho = prim[idx];
+#pragma unroll
+            for (int c = 0; c < NU; ++c) u[c] = prim[(1 + c) * P + idx];
+            p = prim[(M - 1) * P + idx];
+            lr = prim[M * P + idx];
+            lb = prim[(M + 1) * P + idx];
+#pragma unroll
+            for (int c = 0; c < NA; ++c) a[c] = met[(DIR * NA + c) * P + idx];
+        }
+        double uu = 0.0;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) uu += u[c] * u[c];
+        sd[line][F_RHO][q] = rho;
+        sd[line][F_P][q] = p;
+        sd[line][F_BETA][q] = rho / p;
+        sd[line][F_W][q] = sqrt(1.0 + uu);
+        sd[line][F_LR][q] = lr;
+        sd[line][F_LB][q] = lb;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) sd[line][F_U + c][q] = u[c];
+#pragma unroll
+        for (int c = 0; c < NA; ++c) sd[line][F_A + c][q] = a[c];
+    }
+    __syncthreads();
+
+    auto node_at = [&](int q) {
+        NodeRHD<NU> nd;
+        nd.rho = sd[line][F_RHO][q];
+        nd.p = sd[line][F_P][q];
+        nd.beta = sd[line][F_BETA][q];
+        nd.W = sd[line][F_W][q];
+        nd.lr = sd[line][F_LR][q];
+        nd.lb = sd[line][F_LB][q];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) nd.u[c] = sd[line][F_U + c][q];
+        return nd;
+    };
+
+    // ---- two-point fluxes (s, s+n), n = 1..3, owned by the lane of node s
+    const int s_own = s0 - NG + lane;
+    {
+        const bool valid = active && s_own < s_end;
+        if (valid) {
+            const NodeRHD<NU> l = node_at(lane);
+            double al[NA];
+#pragma unroll
+            for (int c = 0; c < NA; ++c) al[c] = sd[line][F_A + c][lane];
+#pragma unroll
+            for (int n = 1; n <= 3; ++n) {
+                const NodeRHD<NU> r = node_at(lane + n);
+                double ar[NA];
+#pragma unroll
+                for (int c = 0; c < NA; ++c) ar[c] = sd[line][F_A + c][lane + n];
+                double F[M], Jt;
+                pair_flux_rhd<NU>(G, l, r, al, ar, F, Jt);
+#pragma unroll
+                for (int c = 0; c < M; ++c) sp[line][n - 1][c][lane] = F[c];
+                sp[line][n - 1][M][lane] = Jt;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- flux differences: R_s = -(1/dxi) sum_n alpha_n [F(s,s+n) - F(s-n,s)]
+    const bool owner = active && lane >= NG && s_own < s_end;
+    const double idxi = 1.0 / g.dxi[DIR];
+    double R[M + 1];
+#pragma unroll
+    for (int c = 0; c <= M; ++c) R[c] = 0.0;
+    if (owner) {
+#pragma unroll
+        for (int c = 0; c <= M; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int n = 1; n <= 3; ++n) s += alpha3(n) * (sp[line][n - 1][c][lane] - sp[line][n - 1][c][lane - n]);
+            R[c] = -s * idxi;
+        }
+    }
+
+    if (ES) {
+        __syncthreads();
+        // ---- face dissipation at s+1/2 for faces s in [s0-1, s_end)
+        if (active && lane >= 2 && s_own < s_end) {
+            NodeRHD<NU> st[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) st[q] = node_at(lane - 2 + q);
+            double al[NA], ar[NA];
+#pragma unroll
+            for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane]; ar[c] = sd[line][F_A + c][lane + 1]; }
+            double d[M];
+            face_diss_rhd<DIM>(G, eps, st, al, ar, d);
+#pragma unroll
+            for (int c = 0; c < M; ++c) sp[line][0][c][lane] = d[c];
+        }
+        __syncthreads();
+        if (owner) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) R[c] += 0.5 * (sp[line][0][c][lane] - sp[line][0][c][lane - 1]) * idxi;
+        }
+    }
+
+    if (owner) {
+        const long long o = ibase + (long long)s_own * istride;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            if (ACC) dU[c * N + o] += R[c]; else dU[c * N + o] = R[c];
+        }
+        if (ACC) dJ[o] += R[M]; else dJ[o] = R[M];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CFL (eq. cfl): per-direction maxima of rho_k = L_k max|lambda| / J
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_cfl_partial(GridDev g, double G, const double* __restrict__ prim,
+                                                     const double* __restrict__ met,
+                                                     const double* __restrict__ J,
+                                                     double* __restrict__ partial) {
+    constexpr int M = DIM + 2, NA = DIM + 1;
+    __shared__ double sh[8];
+    double mx[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) mx[k] = 0.0;
+    const long long P = g.pnodes;
+    for (long long t = gtid(); t < g.nodes; t += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        interior_coords(g, t, i, j, k);
+        const long long pi = pidx(g, i, j, k);
+        const double rho = prim[pi], p = prim[(M - 1) * P + pi];
+        double u[DIM], uu = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) { u[c] = prim[(1 + c) * P + pi]; uu += u[c] * u[c]; }
+        const double W = sqrt(1.0 + uu);
+        const double v2 = uu / (W * W);
+        const double h = 1.0 + G / (G - 1.0) * p / rho;
+        const double cs2 = G * p / (rho * h);
+        const double cs = sqrt(cs2);
+        const double iJ = 1.0 / J[t];
+#pragma unroll
+        for (int kd = 0; kd < DIM; ++kd) {
+            double ax[DIM], L2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) { ax[c] = met[(kd * NA + 1 + c) * P + pi]; L2 += ax[c] * ax[c]; }
+            const double L = sqrt(L2);
+            double vn = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) vn += ax[c] * u[c];
+            vn = vn / (L * W);
+            const double disc = sqrt((1.0 - v2) * (1.0 - v2 * cs2 - vn * vn * (1.0 - cs2)));
+            const double iden = 1.0 / (1.0 - v2 * cs2);
+            const double lm = (vn * (1.0 - cs2) - cs * disc) * iden;
+            const double lp = (vn * (1.0 - cs2) + cs * disc) * iden;
+            const double r = L * fmax(fabs(lm), fabs(lp)) * iJ;
+            mx[kd] = fmax(mx[kd], r);
+        }
+    }
+#pragma unroll
+    for (int kd = 0; kd < DIM; ++kd) {
+        const double r = block_reduce<0>(mx[kd], sh);
+        if (threadIdx.x == 0) partial[kd * gridDim.x + blockIdx.x] = r;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cfl_final(int dim, int nb, double cfl, double dx0, double dx1,
+                                                   double dx2, const double* __restrict__ partial,
+                                                   const double* __restrict__ fixed_dt,
+                                                   double* __restrict__ dt_out) {
+    __shared__ double sh[8];
+    double tot = 0.0;
+    for (int kd = 0; kd < dim; ++kd) {
+        double m = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) m = fmax(m, partial[kd * nb + b]);
+        m = block_reduce<0>(m, sh);
+        tot += m / (kd == 0 ? dx0 : (kd == 1 ? dx1 : dx2));
+    }
+    if (threadIdx.x == 0) dt_out[0] = fixed_dt != nullptr ? fixed_dt[0] : cfl / tot;
+}
+
+// ---------------------------------------------------------------------------
+// mesh redistribution (Section 5)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_monitor_grad(GridDev g, int M, int sigma_ln, int sqgrad,
+                                                      double alpha, const double* __restrict__ prim,
+                                                      double* __restrict__ w, double* __restrict__ partial) {
+    __shared__ double sh[8];
+    const long long P = g.pnodes;
+    double mx = 0.0;
+    for (long long t = gtid(); t < g.nodes; t += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        interior_coords(g, t, i, j, k);
+        int c[3] = {i, j, k};
+        double g2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            auto sig = [&](int off) {
+                int cc[3] = {c[0], c[1], c[2]};
+                cc[a] = map_sol(c[a] + off, g.n[a], g.bc[a]);
+                const long long pi = pidx(g, cc[0], cc[1], cc[2]);
+                return sigma_ln ? prim[M * P + pi] : prim[pi];
+            };
+            double d;
+            if (g.bc[a] == ES_BC_PERIODIC || (c[a] > 0 && c[a] < g.n[a] - 1)) {
+                d = (sig(1) - sig(-1)) / (2.0 * g.dxi[a]);
+            } else if (c[a] == 0) {
+                d = (sig(1) - sig(0)) / g.dxi[a];
+            } else {
+                d = (sig(0) - sig(-1)) / g.dxi[a];
+            }
+            g2 += d * d;
+        }
+        if (sqgrad) {
+            w[t] = sqrt(1.0 + alpha * g2);
+        } else {
+            const double gn = sqrt(g2);
+            w[t] = gn;
+            mx = fmax(mx, gn);
+        }
+    }
+    const double r = block_reduce<0>(mx, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// one-block reduction of partial maxima (op 0) or minima capped at 1 (op 1)
+__global__ void __launch_bounds__(256) k_reduce_final(int op, int nb, const double* __restrict__ partial,
+                                                      double* __restrict__ out) {
+    __shared__ double sh[8];
+    double v = op == 0 ? 0.0 : 1.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v = op == 0 ? fmax(v, partial[b]) : fmin(v, partial[b]);
+    v = op == 0 ? block_reduce<0>(v, sh) : block_reduce<1>(v, sh);
+    if (threadIdx.x == 0) out[0] = v;
+}
+
+__global__ void k_monitor_apply(long long n, double alpha, const double* __restrict__ gmax,
+                                double* __restrict__ w) {
+    const long long t = gtid();
+    if (t >= n) return;
+    const double m = gmax[0];
+    w[t] = m == 0.0 ? 1.0 : sqrt(1.0 + alpha * w[t] / m);
+}
+
+template <int DIM>
+__global__ void k_filter(GridDev g, const double* __restrict__ win, double* __restrict__ wout) {
+    const long long t = gtid();
+    if (t >= g.nodes) return;
+    int i, j, k;
+    interior_coords(g, t, i, j, k);
+    double s = 0.0;
+    if (DIM == 2) {
+        for (int o0 = -1; o0 <= 1; ++o0)
+            for (int o1 = -1; o1 <= 1; ++o1) {
+                const int ii = map_sol(i + o0, g.n[0], g.bc[0]);
+                const int jj = map_sol(j + o1, g.n[1], g.bc[1]);
+                const int e = abs(o0) + abs(o1) + 2;
+                s += ldexp(1.0, -e) * win[iidx(g, ii, jj, 0)];
+            }
+    } else {
+        for (int o0 = -1; o0 <= 1; ++o0)
+            for (int o1 = -1; o1 <= 1; ++o1)
+                for (int o2 = -1; o2 <= 1; ++o2) {
+                    const int ii = map_sol(i + o0, g.n[0], g.bc[0]);
+                    const int jj = map_sol(j + o1, g.n[1], g.bc[1]);
+                    const int kk = map_sol(k + o2, g.n[2], g.bc[2]);
+                    const int e = abs(o0) + abs(o1) + abs(o2) + 3;
+                    s += ldexp(1.0, -e) * win[iidx(g, ii, jj, kk)];
+                }
+    }
+    wout[t] = s;
+}
+
+// One Jacobi sweep of the mesh equations over the axes along which a node is free.
+template <int DIM>
+__global__ void k_jacobi(GridDev g, const double* __restrict__ w, const double* __restrict__ xin,
+                         double* __restrict__ xout) {
+    const long long t = gtid();
+    if (t >= g.nodes) return;
+    int i, j, k;
+    interior_coords(g, t, i, j, k);
+    int c[3] = {i, j, k};
+    bool fr[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) fr[a] = g.bc[a] == ES_BC_PERIODIC || (c[a] > 0 && c[a] < g.n[a] - 1);
+    const double wc = w[t];
+    double den = 0.0, num[DIM];
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) num[q] = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        if (!fr[a]) continue;
+        int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+        cp[a] = c[a] + 1;
+        cm[a] = c[a] - 1;
+        int sp_[3] = {cp[0], cp[1], cp[2]}, sm_[3] = {cm[0], cm[1], cm[2]};
+        sp_[a] = map_sol(cp[a], g.n[a], g.bc[a]);
+        sm_[a] = map_sol(cm[a], g.n[a], g.bc[a]);
+        const double wp = w[iidx(g, sp_[0], sp_[1], sp_[2])];
+        const double wm = w[iidx(g, sm_[0], sm_[1], sm_[2])];
+        den += 2.0 * wc + wp + wm;
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+            const double xp = mesh_value(g, xin, nullptr, 0.0, q, cp[0], cp[1], cp[2], true);
+            const double xm = mesh_value(g, xin, nullptr, 0.0, q, cm[0], cm[1], cm[2], true);
+            num[q] += (wc + wp) * xp + (wc + wm) * xm;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+        const long long o = (long long)q * g.nodes + t;
+        xout[o] = (fr[q] && den > 0.0) ? num[q] / den : xin[o];
+    }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_dtau_partial(GridDev g, const double* __restrict__ x,
+                                                      const double* __restrict__ xm,
+                                                      double* __restrict__ partial) {
+    __shared__ double sh[8];
+    double best = 1.0;
+    for (long long t = gtid(); t < g.nodes; t += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        interior_coords(g, t, i, j, k);
+        int c[3] = {i, j, k};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const long long o = (long long)a * g.nodes + t;
+            const double dk = xm[o] - x[o];
+            if (dk == 0.0) continue;
+            int cc[3] = {c[0], c[1], c[2]};
+            cc[a] += dk > 0.0 ? 1 : -1;
+            const double nb = mesh_value(g, x, nullptr, 0.0, a, cc[0], cc[1], cc[2], true);
+            const double b = dk < 0.0 ? -(x[o] - nb) / (2.0 * dk) : (nb - x[o]) / (2.0 * dk);
+            best = fmin(best, b);
+        }
+    }
+    const double r = block_reduce<1>(best, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ void k_mesh_update(long long n, const double* __restrict__ x, const double* __restrict__ xm,
+                              const double* __restrict__ dtau, const double* __restrict__ dt,
+                              double* __restrict__ xnew, double* __restrict__ xdot) {
+    const long long t = gtid();
+    if (t >= n) return;
+    const double dx = xm[t] - x[t];
+    const double a = dtau[0];
+    xnew[t] = x[t] + a * dx;
+    xdot[t] = a * dx / dt[0];
+}
+
+__global__ void k_zero_mesh_velocity(long long n, const double* __restrict__ x, double* __restrict__ xnew,
+                                     double* __restrict__ xdot) {
+    const long long t = gtid();
+    if (t >= n) return;
+    xnew[t] = x[t];
+    xdot[t] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// SSP-RK3 stage combinations (Shu-Osher form)
+// ---------------------------------------------------------------------------
+// out may alias U0 (last stage writes the new state in place), so no __restrict__.
+__global__ void k_rk_combine(long long n, int stage, const double* U0, const double* Us,
+                             const double* __restrict__ L, const double* __restrict__ dt_dev,
+                             double* out) {
+    const long long t = gtid();
+    if (t >= n) return;
+    const double dt = dt_dev[0];
+    if (stage == 0) out[t] = U0[t] + dt * L[t];
+    else if (stage == 1) out[t] = 0.75 * U0[t] + 0.25 * (Us[t] + dt * L[t]);
+    else out[t] = U0[t] / 3.0 + 2.0 / 3.0 * (Us[t] + dt * L[t]);
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics (FP64 sums)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_diag_partial(GridDev g, double G, const double* __restrict__ prim,
+                                                      const double* __restrict__ U,
+                                                      const double* __restrict__ J,
+                                                      const double* __restrict__ dU,
+                                                      const double* __restrict__ dJ,
+                                                      double* __restrict__ partial) {
+    constexpr int M = DIM + 2;
+    constexpr int NQ = 3 + M;
+    __shared__ double sh[8];
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    const long long P = g.pnodes, N = g.nodes;
+    for (long long t = gtid(); t < N; t += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        interior_coords(g, t, i, j, k);
+        const long long pi = pidx(g, i, j, k);
+        const double rho = prim[pi], p = prim[(M - 1) * P + pi];
+        const double lr = prim[M * P + pi], lb = prim[(M + 1) * P + pi];
+        double u[DIM], uu = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) { u[c] = prim[(1 + c) * P + pi]; uu += u[c] * u[c]; }
+        const double W = sqrt(1.0 + uu);
+        const double beta = rho / p;
+        double V[M];
+        V[0] = G / (G - 1.0) + lr + lb / (G - 1.0) + beta;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) V[1 + c] = beta * u[c];
+        V[M - 1] = -beta * W;
+        const double phi = rho * W;
+        double ep = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) ep += V[c] * dU[c * N + t];
+        ep -= phi * dJ[t];
+        const double s = log(p) - G * lr;
+        const double eta = -rho * W * s / (G - 1.0);
+        acc[0] += ep;
+        acc[1] += J[t] * eta;
+        acc[2] += J[t];
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[3 + c] += U[c * N + t];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double r = block_reduce<2>(acc[q], sh);
+        if (threadIdx.x == 0) partial[q * gridDim.x + blockIdx.x] = r;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(int nq, int nb, const double* __restrict__ partial,
+                                                    double* __restrict__ out) {
+    __shared__ double sh[8];
+    for (int q = 0; q < nq; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[q * nb + b];
+        s = block_reduce<2>(s, sh);
+        if (threadIdx.x == 0) out[q] = s;
+    }
+}
+
+inline int red_blocks(const es_ctx* c) { return c->red_blocks; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t s) {
+    k_fill_u64<<<grid_for(n), TPB, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(double* dst, const double* src, long long n, hipStream_t s) {
+    k_copy<<<grid_for(n), TPB, 0, s>>>(dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_prim2con(const es_ctx* c, const double* prim, const double* J, double* U,
+                           hipStream_t s) {
+    const double G = c->scheme.gamma;
+    if (c->g.dim == 2) k_prim2con_rhd<2><<<grid_for(c->g.nodes), TPB, 0, s>>>(c->g, G, prim, J, U);
+    else k_prim2con_rhd<3><<<grid_for(c->g.nodes), TPB, 0, s>>>(c->g, G, prim, J, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_con2prim(const es_ctx* c, const double* U, const double* J, double* prim,
+                           hipStream_t s) {
+    const double G = c->scheme.gamma;
+    if (c->g.dim == 2) k_con2prim_rhd<2><<<grid_for(c->g.pnodes), TPB, 0, s>>>(c->g, G, U, J, prim, c->fail);
+    else k_con2prim_rhd<3><<<grid_for(c->g.pnodes), TPB, 0, s>>>(c->g, G, U, J, prim, c->fail);
+    return hipGetLastError();
+}
+
+hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
+                          const double* dt_dev, double coef, double* met, double* J0,
+                          hipStream_t s) {
+    if (c->g.dim != 2) return hipErrorNotSupported;
+    k_metrics2d<<<grid_for(c->g.pnodes), TPB, 0, s>>>(c->g, x, xdot, dt_dev, coef, met, J0);
+    return hipGetLastError();
+}
+
+template <int DIM, int DIR>
+static void residual_dir(const es_ctx* c, const double* prim, const double* met, double* dU,
+                         double* dJ, bool acc, hipStream_t s) {
+    const GridDev& g = c->g;
+    const int nAlong = g.n[DIR];
+    const int nseg = (nAlong + SEG - 1) / SEG;
+    long long nlines = 1;
+    for (int a = 0; a < DIM; ++a)
+        if (a != DIR) nlines *= g.n[a];
+    const long long ngroups = (nlines + LINES - 1) / LINES;
+    const unsigned nb = (unsigned)(ngroups * nseg);
+    const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
+    const bool es_ = c->scheme.dissipation != 0;
+    if (es_) {
+        if (acc) k_residual_rhd<DIM, DIR, true, true><<<nb, 256, 0, s>>>(g, G, eps, prim, met, dU, dJ, nseg, nlines);
+        else k_residual_rhd<DIM, DIR, true, false><<<nb, 256, 0, s>>>(g, G, eps, prim, met, dU, dJ, nseg, nlines);
+    } else {
+        if (acc) k_residual_rhd<DIM, DIR, false, true><<<nb, 256, 0, s>>>(g, G, eps, prim, met, dU, dJ, nseg, nlines);
+        else k_residual_rhd<DIM, DIR, false, false><<<nb, 256, 0, s>>>(g, G, eps, prim, met, dU, dJ, nseg, nlines);
+    }
+}
+
+hipError_t launch_residual(const es_ctx* c, const double* prim, const double* met, double* dU,
+                           double* dJ, hipStream_t s) {
+    if (c->g.dim == 2) {
+        residual_dir<2, 0>(c, prim, met, dU, dJ, false, s);
+        residual_dir<2, 1>(c, prim, met, dU, dJ, true, s);
+    } else {
+        residual_dir<3, 0>(c, prim, met, dU, dJ, false, s);
+        residual_dir<3, 1>(c, prim, met, dU, dJ, true, s);
+        residual_dir<3, 2>(c, prim, met, dU, dJ, true, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, const double* J,
+                      double* dt_dev, const double* fixed_dt_dev, hipStream_t s) {
+    const int nb = red_blocks(c);
+    const double G = c->scheme.gamma;
+    if (c->g.dim == 2) k_cfl_partial<2><<<nb, 256, 0, s>>>(c->g, G, prim, met, J, c->red);
+    else k_cfl_partial<3><<<nb, 256, 0, s>>>(c->g, G, prim, met, J, c->red);
+    k_cfl_final<<<1, 256, 0, s>>>(c->g.dim, nb, c->scheme.cfl, c->g.dxi[0], c->g.dxi[1], c->g.dxi[2],
+                                  c->red, fixed_dt_dev, dt_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_mesh_velocity(const es_ctx* c, const double* x, double* x_new, double* xdot,
+                                     hipStream_t s) {
+    const long long n = c->g.nodes * c->g.dim;
+    k_zero_mesh_velocity<<<grid_for(n), TPB, 0, s>>>(n, x, x_new, xdot);
+    return hipGetLastError();
+}
+
+hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, const double* dt_dev,
+                       double* x_new, double* xdot, double* dtau_dev, hipStream_t s) {
+    const GridDev& g = c->g;
+    const es_monitor& mo = c->monitor;
+    const int nb = red_blocks(c);
+    const int sig_ln = mo.sigma == ES_SIGMA_LNRHO;
+    const int sq = mo.form == ES_MON_SQGRAD;
+    double* w = c->wa;
+    double* w2 = c->wb;
+    if (g.dim == 2) k_monitor_grad<2><<<nb, 256, 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
+    else k_monitor_grad<3><<<nb, 256, 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
+    if (!sq) {
+        k_reduce_final<<<1, 256, 0, s>>>(0, nb, c->red, c->scal + SCAL_GMAX);
+        k_monitor_apply<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, c->scal + SCAL_GMAX, w);
+    }
+    for (int f = 0; f < mo.filter_passes; ++f) {
+        if (g.dim == 2) k_filter<2><<<grid_for(g.nodes), TPB, 0, s>>>(g, w, w2);
+        else k_filter<3><<<grid_for(g.nodes), TPB, 0, s>>>(g, w, w2);
+        double* tmp = w; w = w2; w2 = tmp;
+    }
+    const double* xin = x;
+    double* xo = c->xa;
+    double* xalt = c->xb;
+    for (int it = 0; it < mo.sweeps; ++it) {
+        if (g.dim == 2) k_jacobi<2><<<grid_for(g.nodes), TPB, 0, s>>>(g, w, xin, xo);
+        else k_jacobi<3><<<grid_for(g.nodes), TPB, 0, s>>>(g, w, xin, xo);
+        xin = xo;
+        double* tmp = xo; xo = xalt; xalt = tmp;
+    }
+    if (g.dim == 2) k_dtau_partial<2><<<nb, 256, 0, s>>>(g, x, xin, c->red);
+    else k_dtau_partial<3><<<nb, 256, 0, s>>>(g, x, xin, c->red);
+    double* dtau = dtau_dev != nullptr ? dtau_dev : c->scal + SCAL_DTAU;
+    k_reduce_final<<<1, 256, 0, s>>>(1, nb, c->red, dtau);
+    const long long n = g.nodes * g.dim;
+    k_mesh_update<<<grid_for(n), TPB, 0, s>>>(n, x, xin, dtau, dt_dev, x_new, xdot);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk_combine(const es_ctx* c, int stage, const double* U0, const double* J0,
+                             double* Us, double* Js, const double* L, const double* LJ,
+                             const double* dt_dev, hipStream_t s) {
+    const long long nU = c->g.nodes * c->m;
+    const long long nJ = c->g.nodes;
+    // stage 2 writes the new state over U0/J0 (the caller passes them as outputs)
+    double* outU = stage == 2 ? const_cast<double*>(U0) : Us;
+    double* outJ = stage == 2 ? const_cast<double*>(J0) : Js;
+    k_rk_combine<<<grid_for(nU), TPB, 0, s>>>(nU, stage, U0, Us, L, dt_dev, outU);
+    k_rk_combine<<<grid_for(nJ), TPB, 0, s>>>(nJ, stage, J0, Js, LJ, dt_dev, outJ);
+    return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(const es_ctx* c, const double* prim, const double* U,
+                              const double* J, const double* dU, const double* dJ, double* out,
+                              hipStream_t s) {
+    const int nb = red_blocks(c);
+    const double G = c->scheme.gamma;
+    if (c->g.dim == 2) k_diag_partial<2><<<nb, 256, 0, s>>>(c->g, G, prim, U, J, dU, dJ, c->red);
+    else k_diag_partial<3><<<nb, 256, 0, s>>>(c->g, G, prim, U, J, dU, dJ, c->red);
+    k_diag_final<<<1, 256, 0, s>>>(3 + c->m, nb, c->red, out);
+    return hipGetLastError();
+}
+
+}  // namespace es

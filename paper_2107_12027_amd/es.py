@@ -1,0 +1,195 @@
+"""ctypes binding of libes.so (include/es.h).
+
+Argument marshalling only: every computation runs in the HIP kernels of the
+library.  Arrays are torch tensors on the GPU (float64, contiguous); the binding
+passes their data pointers and the current HIP stream.  If the library is not
+built, or is loaded on a machine without a GPU, the calls fail loudly: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libes.so")
+
+ES_OK, ES_EINVAL, ES_EADMISSIBLE, ES_ENOCONV, ES_EMESH, ES_EHIP, ES_EUNSUPPORTED = range(7)
+SYMBOLS = ("es_create", "es_destroy", "es_nvars", "es_nprim", "es_nmet", "es_nodes",
+           "es_padded_nodes", "es_prim2con", "es_metrics", "es_con2prim", "es_residual",
+           "es_cfl", "es_mesh_redistribute", "es_rk3_step", "es_diagnostics", "es_ctx_status",
+           "es_status_string")
+
+
+class EsError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__("%s failed: %s (status %d)" % (where, msg, status))
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("bc", ctypes.c_int * 3),
+                ("dxi", ctypes.c_double * 3), ("period", ctypes.c_double * 3)]
+
+
+class Scheme(ctypes.Structure):
+    _fields_ = [("phys", ctypes.c_int), ("gamma", ctypes.c_double), ("order_p", ctypes.c_int),
+                ("dissipation", ctypes.c_int), ("mixed", ctypes.c_int),
+                ("weno_eps", ctypes.c_double), ("cfl", ctypes.c_double)]
+
+
+class Monitor(ctypes.Structure):
+    _fields_ = [("enabled", ctypes.c_int), ("sigma", ctypes.c_int), ("form", ctypes.c_int),
+                ("alpha", ctypes.c_double), ("filter_passes", ctypes.c_int),
+                ("sweeps", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libes.so (built by paper_2107_12027_amd.build); raises if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libes.so is not built: run `python -m paper_2107_12027_amd.build` "
+                           "(no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    st = ctypes.c_int
+    lib.es_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Scheme), ctypes.POINTER(Monitor),
+                              ctypes.POINTER(vp)]
+    lib.es_create.restype = st
+    lib.es_destroy.argtypes = [vp]
+    lib.es_destroy.restype = st
+    for name in ("es_nvars", "es_nprim", "es_nmet", "es_nodes", "es_padded_nodes"):
+        getattr(lib, name).argtypes = [vp]
+        getattr(lib, name).restype = ctypes.c_size_t
+    lib.es_prim2con.argtypes = [vp, vp, vp, vp, vp]
+    lib.es_metrics.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.es_con2prim.argtypes = [vp, vp, vp, vp, vp]
+    lib.es_residual.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.es_cfl.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.es_mesh_redistribute.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.es_rk3_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.es_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.es_ctx_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_longlong),
+                                  ctypes.POINTER(ctypes.c_longlong)]
+    for name in ("es_prim2con", "es_metrics", "es_con2prim", "es_residual", "es_cfl",
+                 "es_mesh_redistribute", "es_rk3_step", "es_diagnostics", "es_ctx_status"):
+        getattr(lib, name).restype = st
+    lib.es_status_string.argtypes = [st]
+    lib.es_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != ES_OK:
+        msg = _lib.es_status_string(status).decode()
+        raise EsError(status, where, msg)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 GPU tensor")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Context:
+    """An es_ctx: grid, scheme, monitor and the device workspace of the library."""
+
+    def __init__(self, grid, scheme, monitor):
+        lib = load()
+        self.grid_c = Grid(grid.dim, (ctypes.c_int * 3)(*grid.n), (ctypes.c_int * 3)(*grid.bc),
+                           (ctypes.c_double * 3)(*grid.dxi), (ctypes.c_double * 3)(*grid.period))
+        self.scheme_c = Scheme(scheme.phys, scheme.gamma, scheme.order_p, scheme.dissipation,
+                               scheme.mixed, scheme.weno_eps, scheme.cfl)
+        self.monitor_c = Monitor(monitor.enabled, monitor.sigma, monitor.form, monitor.alpha,
+                                 monitor.filter_passes, monitor.sweeps)
+        h = ctypes.c_void_p()
+        _check(lib.es_create(ctypes.byref(self.grid_c), ctypes.byref(self.scheme_c),
+                             ctypes.byref(self.monitor_c), ctypes.byref(h)), "es_create")
+        self.h = h
+        self.grid = grid
+        self.m = lib.es_nvars(h)
+        self.nprim = lib.es_nprim(h)
+        self.nmet = lib.es_nmet(h)
+        self.nodes = lib.es_nodes(h)
+        self.pnodes = lib.es_padded_nodes(h)
+        self.dim = grid.dim
+
+    def close(self):
+        if self.h:
+            _lib.es_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes -------------------------------------------------------------
+    def shape(self):
+        return tuple(self.grid.shape)
+
+    def padded_shape(self):
+        return tuple(s + 6 for s in self.grid.shape)
+
+    # entry points ---------------------------------------------------------
+    def prim2con(self, prim, J, U, stream=None):
+        _check(_lib.es_prim2con(self.h, _ptr(prim), _ptr(J), _ptr(U), _stream(stream)), "es_prim2con")
+
+    def metrics(self, x, xdot, met, J0=None, stream=None):
+        _check(_lib.es_metrics(self.h, _ptr(x), _ptr(xdot), _ptr(met), _ptr(J0), _stream(stream)),
+               "es_metrics")
+
+    def con2prim(self, U, J, prim, stream=None):
+        _check(_lib.es_con2prim(self.h, _ptr(U), _ptr(J), _ptr(prim), _stream(stream)), "es_con2prim")
+
+    def residual(self, prim, met, dU, dJ, stream=None):
+        _check(_lib.es_residual(self.h, _ptr(prim), _ptr(met), _ptr(dU), _ptr(dJ), _stream(stream)),
+               "es_residual")
+
+    def cfl(self, prim, met, J, dt, stream=None):
+        _check(_lib.es_cfl(self.h, _ptr(prim), _ptr(met), _ptr(J), _ptr(dt), _stream(stream)), "es_cfl")
+
+    def mesh_redistribute(self, prim, x, dt, x_new, xdot, dtau=None, stream=None):
+        _check(_lib.es_mesh_redistribute(self.h, _ptr(prim), _ptr(x), _ptr(dt), _ptr(x_new), _ptr(xdot),
+                                         _ptr(dtau), _stream(stream)), "es_mesh_redistribute")
+
+    def rk3_step(self, U, J, x, xdot, dt, fixed_dt=None, stream=None):
+        _check(_lib.es_rk3_step(self.h, _ptr(U), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt), _ptr(fixed_dt),
+                                _stream(stream)), "es_rk3_step")
+
+    def diagnostics(self, prim, U, J, dU, dJ, out, stream=None):
+        _check(_lib.es_diagnostics(self.h, _ptr(prim), _ptr(U), _ptr(J), _ptr(dU), _ptr(dJ), _ptr(out),
+                                   _stream(stream)), "es_diagnostics")
+
+    def status(self, stream=None):
+        """Synchronise and return (status, n_fail, first_fail) of recorded con2prim failures."""
+        nf = ctypes.c_longlong()
+        ff = ctypes.c_longlong()
+        st = _lib.es_ctx_status(self.h, _stream(stream), ctypes.byref(nf), ctypes.byref(ff))
+        if st not in (ES_OK, ES_EADMISSIBLE, ES_ENOCONV):
+            _check(st, "es_ctx_status")
+        return st, nf.value, ff.value
+
+
+def exported_symbols(path: str = LIB_PATH):
+    """Names of the C-ABI entry points exported by libes.so (ctypes lookup only,
+    nothing is executed)."""
+    lib = ctypes.CDLL(path)
+    return [s for s in SYMBOLS if hasattr(lib, s)]

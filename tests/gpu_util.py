@@ -1,0 +1,77 @@
+"""Helpers for the GPU parity tests: build seeded inputs, move them to the GPU,
+call the C ABI through the binding, and compare with the oracle."""
+import numpy as np
+import torch
+
+from oracle import physics as ph, metrics as mt, stepper as st
+from paper_2107_12027_amd import es, workloads as wl
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def empty(*shape):
+    return torch.empty(shape, dtype=torch.float64, device="cuda")
+
+
+def rel_inf(a, b):
+    """max |a - b| / max |b| per leading component."""
+    a = np.asarray(a).reshape(a.shape[0], -1)
+    b = np.asarray(b).reshape(b.shape[0], -1)
+    out = []
+    for c in range(a.shape[0]):
+        sc = np.max(np.abs(b[c]))
+        out.append(np.max(np.abs(a[c] - b[c])) / (sc if sc > 0 else 1.0))
+    return np.array(out)
+
+
+def full_P(prim):
+    return ph.full_prim(prim["rho"], prim["u"], prim["p"], prim["B"])
+
+
+def prim_interior(P, phys, dim):
+    return P[ph.comps(phys, dim)]
+
+
+class Case:
+    """A grid with a curvilinear (optionally moving) mesh and a primitive state."""
+
+    def __init__(self, dim, n, bc, phys=ph.RHD, seed=0, smooth=False, amp=0.03, vmax=0.9,
+                 moving=True, dissipation=1, monitor=None, rho_rng=(0.1, 1.0), p_rng=(0.1, 1.0)):
+        rng = np.random.default_rng(seed)
+        self.grid = wl.make_grid(dim, n, bc)
+        self.x = wl.perturbed_mesh(self.grid, rng, amp=amp)
+        self.xdot = (wl.perturbed_mesh(self.grid, rng, amp=0.05) - wl.uniform_mesh(self.grid)) if moving \
+            else np.zeros_like(self.x)
+        if smooth:
+            pr = wl.smooth_prim(self.x, rng, phys)
+        else:
+            pr = wl.random_prim(self.grid.shape, rng, phys=phys, dim=dim, vmax=vmax,
+                                rho_rng=rho_rng, p_rng=p_rng)
+        self.P = full_P(pr)
+        self.scheme = wl.Scheme(phys=phys, dissipation=dissipation)
+        self.monitor = monitor if monitor is not None else wl.Monitor(enabled=0)
+        self.ctx = es.Context(self.grid, self.scheme, self.monitor)
+        self.dim, self.phys = dim, phys
+        self.m = self.ctx.m
+
+    def oracle_state(self):
+        J = mt.jacobian(self.grid, self.x)
+        U = st.cons_from_prim(self.grid, self.scheme, self.P, J)
+        return U, J
+
+    def gpu_state(self):
+        """J^0 by es_metrics and Ucurv by es_prim2con from the same primitive input."""
+        c = self.ctx
+        met = empty(c.nmet, *c.padded_shape())
+        J = empty(*c.shape())
+        c.metrics(dev(self.x), None, met, J)
+        U = empty(c.m, *c.shape())
+        c.prim2con(dev(prim_interior(self.P, self.phys, self.dim)), J, U)
+        return U, J

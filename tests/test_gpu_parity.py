@@ -1,0 +1,221 @@
+"""GPU parity: every C-ABI entry point of libes.so against the CPU oracle on
+identical seeded inputs (FP64, tolerance 1e-12 relative to the component's
+max-norm unless stated), at sizes that span several 61-node line segments with
+a ragged tail, on periodic, outflow and mixed boundaries."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import physics as ph, metrics as mt, residual as rs, stepper as st, mesh as msh  # noqa: E402
+from paper_2107_12027_amd import es, workloads as wl  # noqa: E402
+from gpu_util import Case, dev, host, empty, rel_inf, prim_interior  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+GRIDS_2D = [((130, 70, 1), (0, 0, 0)), ((64, 123, 1), (1, 1, 0)), ((75, 66, 1), (0, 1, 0)),
+            ((8, 9, 1), (1, 0, 0))]
+
+
+@pytest.mark.parametrize("n,bc", GRIDS_2D)
+def test_metrics_and_jacobian(n, bc):
+    case = Case(2, n, bc, seed=1)
+    c = case.ctx
+    met = empty(c.nmet, *c.padded_shape())
+    J0 = empty(*c.shape())
+    c.metrics(dev(case.x), dev(case.xdot), met, J0)
+    want = mt.metrics(case.grid, case.x, case.xdot)
+    got = host(met)
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(got - want)) <= 1e-13 * scale
+    Jw = mt.jacobian(case.grid, case.x)
+    assert np.max(np.abs(host(J0) - Jw)) <= 1e-13 * np.max(np.abs(Jw))
+
+
+@pytest.mark.parametrize("n,bc", GRIDS_2D)
+def test_prim2con_and_con2prim(n, bc):
+    case = Case(2, n, bc, seed=2, vmax=0.99, rho_rng=(0.01, 1.0), p_rng=(0.01, 1.0))
+    c = case.ctx
+    U, J = case.gpu_state()
+    Uo, Jo = case.oracle_state()
+    assert np.all(rel_inf(host(U), Uo) <= 1e-13)
+    prim = empty(c.nprim, *c.padded_shape())
+    c.con2prim(U, J, prim)
+    Po, ok = st.prim_from_cons(case.grid, case.scheme, Uo, Jo)
+    assert ok.all()
+    Ppad = st.pad_solution(case.grid, Po)
+    want = np.concatenate([Ppad[ph.comps(ph.RHD, 2)], np.log(Ppad[0])[None],
+                           np.log(Ppad[0] / Ppad[4])[None]])
+    got = host(prim)
+    assert np.all(rel_inf(got, want) <= 1e-12), rel_inf(got, want)
+    assert c.status()[0] == es.ES_OK
+
+
+def test_con2prim_reports_inadmissible_node():
+    case = Case(2, (40, 30, 1), (1, 1, 0), seed=3)
+    c = case.ctx
+    U, J = case.gpu_state()
+    Uh = host(U)
+    bad = (7, 11)                       # (j, i)
+    Uh[3][bad] = 0.5 * np.sqrt(Uh[0][bad] ** 2 + Uh[1][bad] ** 2)   # E < sqrt(D^2 + |m|^2)
+    U = dev(Uh)
+    prim = empty(c.nprim, *c.padded_shape())
+    c.con2prim(U, J, prim)
+    status, nfail, first = c.status()
+    assert status == es.ES_EADMISSIBLE
+    assert nfail == 1 and first == bad[0] * 40 + bad[1]
+    assert np.isnan(host(prim)[0][bad[0] + 3, bad[1] + 3])
+    assert c.status()[0] == es.ES_OK       # cleared after reporting
+
+
+@pytest.mark.parametrize("n,bc", GRIDS_2D)
+@pytest.mark.parametrize("diss", [0, 1])
+def test_residual(n, bc, diss):
+    case = Case(2, n, bc, seed=4 + diss, dissipation=diss)
+    c = case.ctx
+    U, J = case.gpu_state()
+    prim = empty(c.nprim, *c.padded_shape())
+    met = empty(c.nmet, *c.padded_shape())
+    c.con2prim(U, J, prim)
+    c.metrics(dev(case.x), dev(case.xdot), met)
+    dU = empty(c.m, *c.shape())
+    dJ = empty(*c.shape())
+    c.residual(prim, met, dU, dJ)
+    Uo, Jo = case.oracle_state()
+    Po, _ = st.prim_from_cons(case.grid, case.scheme, Uo, Jo)
+    meto = mt.metrics(case.grid, case.x, case.xdot)
+    dUo, dJo = rs.residual(case.grid, case.scheme, st.pad_solution(case.grid, Po), meto)
+    r = rel_inf(host(dU), dUo)
+    assert np.all(r <= TOL), r
+    assert rel_inf(host(dJ)[None], dJo[None])[0] <= TOL
+
+
+@pytest.mark.parametrize("n,bc", GRIDS_2D[:3])
+def test_cfl_time_step(n, bc):
+    case = Case(2, n, bc, seed=6, vmax=0.99)
+    c = case.ctx
+    U, J = case.gpu_state()
+    prim = empty(c.nprim, *c.padded_shape())
+    met = empty(c.nmet, *c.padded_shape())
+    c.con2prim(U, J, prim)
+    c.metrics(dev(case.x), None, met)
+    dt = empty(1)
+    c.cfl(prim, met, J, dt)
+    Uo, Jo = case.oracle_state()
+    Po, _ = st.prim_from_cons(case.grid, case.scheme, Uo, Jo)
+    want = st.cfl_dt(case.grid, case.scheme, Po, mt.metrics(case.grid, case.x, None), Jo)
+    assert abs(host(dt)[0] - want) <= 1e-13 * want
+
+
+@pytest.mark.parametrize("n,bc,form,sigma", [((130, 70, 1), (0, 0, 0), 1, 0),
+                                             ((64, 123, 1), (1, 1, 0), 0, 1),
+                                             ((75, 66, 1), (0, 1, 0), 0, 0)])
+def test_mesh_redistribution(n, bc, form, sigma):
+    mon = wl.Monitor(enabled=1, sigma=sigma, form=form, alpha=10.0 if form else 1200.0,
+                     filter_passes=3, sweeps=10)
+    case = Case(2, n, bc, seed=7, smooth=True, monitor=mon)
+    c = case.ctx
+    U, J = case.gpu_state()
+    prim = empty(c.nprim, *c.padded_shape())
+    c.con2prim(U, J, prim)
+    dt = dev(np.array([1e-3]))
+    xn = empty(2, *c.shape())
+    xd = empty(2, *c.shape())
+    dtau = empty(1)
+    c.mesh_redistribute(prim, dev(case.x), dt, xn, xd, dtau)
+    Uo, Jo = case.oracle_state()
+    Po, _ = st.prim_from_cons(case.grid, case.scheme, Uo, Jo)
+    xo, xdo, w, dto = msh.redistribute(case.grid, mon, Po, case.x, 1e-3)
+    assert abs(host(dtau)[0] - dto) <= 1e-12
+    assert np.max(np.abs(host(xn) - xo)) <= 1e-13
+    assert np.max(np.abs(host(xd) - xdo)) <= 1e-12 * max(1.0, np.max(np.abs(xdo)))
+
+
+def _run_steps(w, nsteps, x0=None):
+    """Run nsteps of es_rk3_step and of the oracle from the same workload."""
+    g = w.grid
+    ctx = es.Context(g, w.scheme, w.monitor)
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    x = w.x if x0 is None else x0
+    met = empty(ctx.nmet, *ctx.padded_shape())
+    J = empty(*ctx.shape())
+    xg = dev(x)
+    ctx.metrics(xg, None, met, J)
+    U = empty(ctx.m, *ctx.shape())
+    ctx.prim2con(dev(P[ph.comps(w.scheme.phys, g.dim)]), J, U)
+    xdot = empty(g.dim, *ctx.shape())
+    dt = empty(1)
+    Uo, Jo = st.initial_state(g, w.scheme, P, x)
+    xo = x.copy()
+    for _ in range(nsteps):
+        ctx.rk3_step(U, J, xg, xdot, dt)
+        out = st.rk3_step(g, w.scheme, w.monitor, Uo, Jo, xo)
+        Uo, Jo, xo = out["U"], out["J"], out["x"]
+        assert abs(host(dt)[0] - out["dt"]) <= 1e-12 * out["dt"]
+    assert ctx.status()[0] == es.ES_OK
+    return (host(U), host(J), host(xg), host(xdot)), (Uo, Jo, xo, out["xdot"])
+
+
+def test_rk3_step_advected_sine_adaptive():
+    w = wl.advected_sine(n=72)
+    (U, J, x, xd), (Uo, Jo, xo, xdo) = _run_steps(w, 2)
+    assert np.all(rel_inf(U, Uo) <= TOL), rel_inf(U, Uo)
+    assert rel_inf(J[None], Jo[None])[0] <= TOL
+    assert np.max(np.abs(x - xo)) <= 1e-13
+
+
+def test_rk3_step_quadrant_riemann_adaptive():
+    w = wl.quadrant_riemann(n=70, seed=2)
+    (U, J, x, xd), (Uo, Jo, xo, xdo) = _run_steps(w, 2)
+    assert np.all(rel_inf(U, Uo) <= TOL), rel_inf(U, Uo)
+    assert rel_inf(J[None], Jo[None])[0] <= TOL
+    assert np.max(np.abs(x - xo)) <= 1e-13
+
+
+def test_quadrant_seed0_inadmissible_on_both_paths():
+    # the ES scheme has no positivity limiter: the seed-0 states leave the admissible
+    # set in the first step; both paths must report it rather than continue silently
+    w = wl.quadrant_riemann(n=70, seed=0)
+    g = w.grid
+    ctx = es.Context(g, w.scheme, w.monitor)
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    met = empty(ctx.nmet, *ctx.padded_shape())
+    J = empty(*ctx.shape())
+    xg = dev(w.x)
+    ctx.metrics(xg, None, met, J)
+    U = empty(ctx.m, *ctx.shape())
+    ctx.prim2con(dev(P[ph.comps(w.scheme.phys, g.dim)]), J, U)
+    xdot = empty(g.dim, *ctx.shape())
+    dt = empty(1)
+    ctx.rk3_step(U, J, xg, xdot, dt)
+    status, nfail, first = ctx.status()
+    assert status == es.ES_EADMISSIBLE and nfail > 0 and first >= 0
+    Uo, Jo = st.initial_state(g, w.scheme, P, w.x)
+    out = st.rk3_step(g, w.scheme, w.monitor, Uo, Jo, w.x)
+    assert not out["ok"].all()
+
+
+def test_diagnostics_entropy_production():
+    case = Case(2, (130, 70, 1), (0, 0, 0), seed=9, dissipation=0)
+    c = case.ctx
+    U, J = case.gpu_state()
+    prim = empty(c.nprim, *c.padded_shape())
+    met = empty(c.nmet, *c.padded_shape())
+    c.con2prim(U, J, prim)
+    c.metrics(dev(case.x), dev(case.xdot), met)
+    dU = empty(c.m, *c.shape())
+    dJ = empty(*c.shape())
+    c.residual(prim, met, dU, dJ)
+    out = empty(3 + c.m)
+    c.diagnostics(prim, U, J, dU, dJ, out)
+    o = host(out)
+    Uo, Jo = case.oracle_state()
+    Po, _ = st.prim_from_cons(case.grid, case.scheme, Uo, Jo)
+    V = ph.entropy_vars(Po, case.scheme.gamma)[ph.comps(ph.RHD, 2)]
+    scale = np.sum(np.abs(V * host(dU)))
+    assert abs(o[0]) <= 1e-13 * scale                  # EC on a periodic moving mesh
+    eta = ph.entropy(Po, case.scheme.gamma)
+    assert abs(o[1] - np.sum(Jo * eta)) <= 1e-12 * np.sum(np.abs(Jo * eta))
+    assert abs(o[2] - np.sum(Jo)) <= 1e-12 * np.sum(Jo)
+    np.testing.assert_allclose(o[3:], Uo.reshape(c.m, -1).sum(axis=1), rtol=1e-12)
