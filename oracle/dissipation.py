@@ -11,7 +11,8 @@ with
     Godunov-Powell modified Jacobian dF_1/dU + Phi'(V)^T dB_1/dU);
   * WENO-(2p-1) (Jiang-Shu) of V~ = R^T T V along the line, <<V~>> = V~^+ - V~^-;
   * Y_ll = 1 iff <<V~_l>> and [V~_l] = V~_{i+1} - V~_i have the same sign
-    (strictly positive product).
+    (strictly positive product), a jump below Y_TOL times the size of the terms
+    of its projections counting as zero.
 The face state, face metrics and the choice of basis inside the degenerate
 eigenvalue cluster are readings listed in the design doc.
 
@@ -31,6 +32,7 @@ import numpy as np
 from . import physics as ph
 
 H_CS = 1e-30
+Y_TOL = 1e-10
 
 
 def rotation(n):
@@ -189,7 +191,12 @@ def face_dissipation(Pst, ast, G, phys, dim, eps, details=False):
     vp = weno5_minus(Vt[5], Vt[4], Vt[3], Vt[2], Vt[1], eps)
     jump_weno = vp - vm
     jump = Vt[3] - Vt[2]
-    Y = (jump_weno * jump > 0).astype(np.float64)
+    # sign(0) reading: a jump [V~_l] within rounding of zero (below Y_TOL times the
+    # magnitude of the terms of its two projections) counts as zero, so Y_l = 0
+    Vi = rotate_full(ph.entropy_vars(Pst[2], G), T0, slots)[sel]
+    Vj = rotate_full(ph.entropy_vars(Pst[3], G), T0, slots)[sel]
+    scale = np.einsum("nab,an->bn", np.abs(R), np.abs(Vi) + np.abs(Vj))
+    Y = ((jump_weno * jump > 0) & (np.abs(jump) > Y_TOL * scale)).astype(np.float64)
     coef = Y * jump_weno                                                 # (m, N)
     dsel = lhat[None, :] * np.einsum("nab,bn->an", R, coef)              # R (Y <<V~>>)
     dfull = np.zeros((8,) + dsel.shape[1:])

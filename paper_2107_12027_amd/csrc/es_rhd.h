@@ -7,6 +7,8 @@
 
 namespace es {
 
+constexpr double Y_TOL = 1e-10;
+
 // Logarithmic mean [a]/[ln a] (cited in Section 3.1 to Ismail & Roe) from the
 // values and their precomputed logarithms.  With f = (al - ar)/(al + ar) and
 // u = f^2: for u < 1e-2 the ratio ln(al/ar)/(2f) is replaced by its series
@@ -211,7 +213,9 @@ __device__ __forceinline__ void rotation(const double* n, double T[3][3]) {
 //    from the cluster projector applied to the seeds e_D, e_{m_t1}(, e_{m_t2}),
 //    computed in the coefficient space of the cluster basis with the Gram
 //    matrix G_ab = dU_a . dV_b;
-//  * WENO5-JS of V~ = R^T T V on both sides, Y_l = [<<V~_l>> [V~_l] > 0].
+//  * WENO5-JS of V~ = R^T T V on both sides, Y_l = [<<V~_l>> [V~_l] > 0], with a
+//    jump [V~_l] below Y_TOL times the size of the terms of its projections
+//    counted as zero (sign(0) at rounding level).
 template <int DIM>
 __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRHD<DIM>* nd,
                                               const double* al, const double* ar, double* d) {
@@ -293,7 +297,11 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
         const double vp = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps);
         const double jw = vp - vm;
         const double jp = vt[3] - vt[2];
-        if (jw * jp > 0.0) {
+        // a jump within rounding of zero counts as zero (Y = 0)
+        double sc = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) sc += fabs(r[c]) * (fabs(TV[2][c]) + fabs(TV[3][c]));
+        if (jw * jp > 0.0 && fabs(jp) > Y_TOL * sc) {
 #pragma unroll
             for (int c = 0; c < M; ++c) dd[c] += jw * r[c];
         }
