@@ -31,9 +31,12 @@ PEAK_HBM = 8.0e12                # B/s
 # Algorithmic FP64 operations of one es_residual call per interior node (both
 # directions of the 2D RHD ES scheme, p = 3): counted by executing the device
 # arithmetic of the two-point flux and of the face dissipation with an
-# op-counting scalar (paper_2107_12027_amd/csrc/opcount.cpp); each of + - * /,
-# fma (2), sqrt, log, fabs/fmax/fmin comparisons counts as written there.
-RESIDUAL_FLOPS_PER_NODE_2D_RHD = None   # filled from opcount output when known
+# op-counting scalar (paper_2107_12027_amd/csrc/opcount.cpp, run by
+# `python -m paper_2107_12027_amd.build --opcount`): + - * / sqrt log fabs
+# fmax count 1, fma counts 2.  Per node and direction: 3 two-point fluxes
+# (92.4 each), 1 face dissipation (1553.2), state preparation (6) and the
+# flux-difference accumulation (66): 1902.3; two directions: 3804.6.
+RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3804.6
 
 
 def parse():

@@ -161,6 +161,13 @@ es_status es_mesh_redistribute(es_ctx* ctx, const double* prim, const double* x,
 es_status es_rk3_step(es_ctx* ctx, double* Ucurv, double* J, double* x, double* xdot,
                       double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
 
+/* Replay es_rk3_step as a HIP graph (default 1) or launch its kernels one by
+ * one (0).  In graph mode the step is captured on the context's own stream the
+ * first time it is called with a given set of array pointers and replayed
+ * afterwards, ordered after and before the caller's stream with events; the
+ * results are those of the eager launch sequence. */
+es_status es_set_graph(es_ctx* ctx, int enable);
+
 /* FP64 diagnostics on the interior (Theorem 4.1 / 5.1, Section 6 total entropy):
  * out_dev[0] = sum_i (V_i . dUcurv_i - phi_i dJ_i)   (entropy production rate)
  * out_dev[1] = sum_i J_i eta_i                         (total entropy)

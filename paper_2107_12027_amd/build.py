@@ -54,5 +54,22 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def opcount() -> str:
+    """Build and run the host op-counting program (csrc/opcount.cpp) that gives the
+    algorithmic FP64 work per node of the residual; returns its report."""
+    exe = os.path.join(ROOT, "_build", "opcount")
+    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    cmd = [hipcc(), "-O1", "-std=c++17", "-I" + INCLUDE, "-I" + CSRC, "-o", exe,
+           os.path.join(CSRC, "opcount.cpp")]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("building opcount failed")
+    return subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+
+
 if __name__ == "__main__":
-    print(build(verbose="--verbose" in sys.argv))
+    if "--opcount" in sys.argv:
+        print(opcount(), end="")
+    else:
+        print(build(verbose="--verbose" in sys.argv))

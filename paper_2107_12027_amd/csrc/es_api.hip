@@ -93,14 +93,16 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
         g.P[k] = (k < grid->dim) ? grid->n[k] + 2 * es::NG : 1;
     }
     g.g2 = grid->dim == 3 ? es::NG : 0;
+    for (int k = 0; k < 3; ++k) g.E[k] = (k < grid->dim) ? grid->n[k] + 4 * es::NG : 1;
+    g.g6 = grid->dim == 3 ? 2 * es::NG : 0;
     g.nodes = (long long)g.n[0] * g.n[1] * g.n[2];
     g.pnodes = (long long)g.P[0] * g.P[1] * g.P[2];
+    g.enodes = (long long)g.E[0] * g.E[1] * g.E[2];
     c->m = scheme->phys == ES_RMHD ? 8 : grid->dim + 2;
     c->nprim = c->m + 2;
     c->nmet = grid->dim * (grid->dim + 1);
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return ES_EHIP; }
-    long long nb = (g.nodes + 255) / 256;
-    c->red_blocks = (int)(nb < es::MAX_RED_BLOCKS ? (nb < 1 ? 1 : nb) : es::MAX_RED_BLOCKS);
+    c->red_blocks = es::reduction_blocks(g);
     const size_t N = (size_t)g.nodes, P = (size_t)g.pnodes, d = (size_t)grid->dim;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = alloc(&c->prim, P * c->nprim);
@@ -114,13 +116,22 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     if (e == hipSuccess) e = alloc(&c->xb, N * d);
     if (e == hipSuccess) e = alloc(&c->wa, N);
     if (e == hipSuccess) e = alloc(&c->wb, N);
-    if (e == hipSuccess) e = alloc(&c->red, (size_t)es::MAX_RED_BLOCKS * (3 + 8));
+    if (e == hipSuccess) e = alloc(&c->xe, (size_t)g.enodes * d);
+    if (e == hipSuccess) e = alloc(&c->ve, (size_t)g.enodes * d);
+    if (e == hipSuccess) e = alloc(&c->red, (size_t)c->red_blocks * (3 + 8));
     if (e == hipSuccess) e = alloc(&c->scal, (size_t)es::NSCAL);
     if (e == hipSuccess) e = alloc(&c->fail, (size_t)4);
     if (e == hipSuccess) {
         (void)es::launch_fill_u64(c->fail, 0ull, 2, nullptr);
         e = es::launch_fill_u64(c->fail + 2, ULLONG_MAX, 1, nullptr);
     }
+    // the primitive workspace seeds the pressure iteration of the next step: start
+    // from zeros (an invalid seed, so the first step uses the bracket midpoint)
+    if (e == hipSuccess) e = es::launch_zero(c->prim, (long long)(P * c->nprim), nullptr);
+    c->use_graph = 1;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         es_destroy(c);
@@ -133,7 +144,11 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
 es_status es_destroy(es_ctx* c) {
     if (c == nullptr) return ES_EINVAL;
     void* bufs[] = {c->prim, c->met, c->L, c->LJ, c->Us, c->Js, c->xnew, c->xa, c->xb,
-                    c->wa, c->wb, c->red, c->scal, c->fail};
+                    c->wa, c->wb, c->xe, c->ve, c->red, c->scal, c->fail};
+    if (c->gexec != nullptr) (void)hipGraphExecDestroy(c->gexec);
+    if (c->ev_in != nullptr) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out != nullptr) (void)hipEventDestroy(c->ev_out);
+    if (c->cap != nullptr) (void)hipStreamDestroy(c->cap);
     for (void* b : bufs)
         if (b != nullptr) (void)hipFree(b);
     delete c;
@@ -159,7 +174,7 @@ es_status es_metrics(es_ctx* c, const double* x, const double* xdot, double* met
 
 es_status es_con2prim(es_ctx* c, const double* U, const double* J, double* prim, hipStream_t s) {
     if (c == nullptr || U == nullptr || J == nullptr || prim == nullptr) return ES_EINVAL;
-    return hip_status(es::launch_con2prim(c, U, J, prim, s));
+    return hip_status(es::launch_con2prim(c, U, J, prim, 0, s));
 }
 
 es_status es_residual(es_ctx* c, const double* prim, const double* met, double* dU, double* dJ,
@@ -185,13 +200,11 @@ es_status es_mesh_redistribute(es_ctx* c, const double* prim, const double* x, c
     return hip_status(es::launch_mesh(c, prim, x, dt_dev, x_new, xdot, dtau_dev, s));
 }
 
-es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, double* dt_dev,
-                      const double* fixed_dt_dev, hipStream_t s) {
-    if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
-        dt_dev == nullptr)
-        return ES_EINVAL;
-    // con2prim, metrics on x^n (spatial part), CFL step
-    ES_TRY(es::launch_con2prim(c, U, J, c->prim, s));
+static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double* xdot,
+                              double* dt_dev, const double* fixed_dt_dev, hipStream_t s) {
+    // con2prim (the primitive workspace holds the previous stage and seeds the
+    // pressure iteration), metrics on x^n (spatial part), CFL step
+    ES_TRY(es::launch_con2prim(c, U, J, c->prim, 1, s));
     ES_TRY(es::launch_metrics(c, x, nullptr, nullptr, 0.0, c->met, nullptr, s));
     ES_TRY(es::launch_cfl(c, c->prim, c->met, J, dt_dev, fixed_dt_dev, s));
     // mesh redistribution: x^{n+1} into c->xnew, mesh velocity into xdot
@@ -201,12 +214,57 @@ es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, 
         ES_TRY(es::launch_zero_mesh_velocity(c, x, c->xnew, xdot, s));
     static const double coef[3] = {0.0, 1.0, 0.5};
     for (int st = 0; st < 3; ++st) {
-        if (st > 0) ES_TRY(es::launch_con2prim(c, c->Us, c->Js, c->prim, s));
+        if (st > 0) ES_TRY(es::launch_con2prim(c, c->Us, c->Js, c->prim, 1, s));
         ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s));
         ES_TRY(es::launch_residual(c, c->prim, c->met, c->L, c->LJ, s));
         ES_TRY(es::launch_rk_combine(c, st, U, J, c->Us, c->Js, c->L, c->LJ, dt_dev, s));
     }
     ES_TRY(es::launch_copy(x, c->xnew, c->g.nodes * c->g.dim, s));
+    return ES_OK;
+}
+
+es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, double* dt_dev,
+                      const double* fixed_dt_dev, hipStream_t s) {
+    if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
+        dt_dev == nullptr)
+        return ES_EINVAL;
+    if (!c->use_graph) return enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, s);
+    const void* key[6] = {U, J, x, xdot, dt_dev, fixed_dt_dev};
+    if (c->gexec == nullptr || memcmp(key, c->gkey, sizeof(key)) != 0) {
+        if (c->gexec != nullptr) {
+            ES_TRY(hipGraphExecDestroy(c->gexec));
+            c->gexec = nullptr;
+        }
+        // the capture stream must not depend on earlier work while capturing
+        ES_TRY(hipStreamSynchronize(c->cap));
+        ES_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        const es_status st = enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, c->cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap, &graph);
+        if (st != ES_OK || e != hipSuccess || graph == nullptr) {
+            if (graph != nullptr) (void)hipGraphDestroy(graph);
+            return st != ES_OK ? st : ES_EHIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            c->gexec = nullptr;
+            return ES_EHIP;
+        }
+        memcpy(c->gkey, key, sizeof(key));
+    }
+    // order the replay after the caller's stream and the caller's stream after it
+    ES_TRY(hipEventRecord(c->ev_in, s));
+    ES_TRY(hipStreamWaitEvent(c->cap, c->ev_in, 0));
+    ES_TRY(hipGraphLaunch(c->gexec, c->cap));
+    ES_TRY(hipEventRecord(c->ev_out, c->cap));
+    ES_TRY(hipStreamWaitEvent(s, c->ev_out, 0));
+    return ES_OK;
+}
+
+es_status es_set_graph(es_ctx* c, int enable) {
+    if (c == nullptr || (enable != 0 && enable != 1)) return ES_EINVAL;
+    c->use_graph = enable;
     return ES_OK;
 }
 

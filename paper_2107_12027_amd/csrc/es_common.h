@@ -25,8 +25,11 @@ struct GridDev {
     double period[3];
     int P[3];               // padded extents (n+6, or 1 for the unused 3rd axis in 2D)
     int g2;                 // ghost offset of the third axis (3 in 3D, 0 in 2D)
+    int E[3];               // mesh-extension box extents (n+12, or 1)
+    int g6;                 // extension offset of the third axis (6 in 3D, 0 in 2D)
     long long nodes;        // interior nodes
     long long pnodes;       // padded nodes
+    long long enodes;       // mesh-extension box nodes
 };
 
 __device__ __forceinline__ long long pidx(const GridDev& g, int i, int j, int k) {
@@ -82,6 +85,12 @@ __device__ __forceinline__ AxisTerms axis_terms(int i, int n, int bc) {
 __device__ __forceinline__ double mesh_value(const GridDev& g, const double* __restrict__ x,
                                              const double* __restrict__ xd, double cdt, int c,
                                              int i, int j, int k, bool shift) {
+    if (i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] && (g.dim == 2 || (k >= 0 && k < g.n[2]))) {
+        const long long nd = (long long)c * g.nodes + iidx(g, i, j, g.dim == 2 ? 0 : k);
+        double xv = x[nd];
+        if (xd != nullptr) xv += cdt * xd[nd];
+        return xv;
+    }
     AxisTerms a = axis_terms(i, g.n[0], g.bc[0]);
     AxisTerms b = axis_terms(j, g.n[1], g.bc[1]);
     AxisTerms e;
@@ -92,15 +101,25 @@ __device__ __forceinline__ double mesh_value(const GridDev& g, const double* __r
     }
     const long long off = (long long)c * g.nodes;
     double v = 0.0;
-    for (int te = 0; te < e.nt; ++te)
-        for (int tb = 0; tb < b.nt; ++tb)
-            for (int ta = 0; ta < a.nt; ++ta) {
+    // fully unrolled over the (at most) two terms per axis so the term arrays
+    // stay in registers
+#pragma unroll
+    for (int te = 0; te < 2; ++te) {
+        if (te >= e.nt) break;
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb) {
+            if (tb >= b.nt) break;
+#pragma unroll
+            for (int ta = 0; ta < 2; ++ta) {
+                if (ta >= a.nt) break;
                 const double w = a.w[ta] * b.w[tb] * e.w[te];
                 const long long nd = off + iidx(g, a.idx[ta], b.idx[tb], e.idx[te]);
                 double xv = x[nd];
                 if (xd != nullptr) xv += cdt * xd[nd];
                 v += w * xv;
             }
+        }
+    }
     if (shift) {
         const int wr = (c == 0) ? a.wraps : (c == 1 ? b.wraps : e.wraps);
         v += wr * g.period[c];

@@ -27,10 +27,18 @@ struct es_ctx {
     double* xb;     // interior, d comps (Jacobi pong)
     double* wa;     // interior (monitor ping)
     double* wb;     // interior (monitor pong)
+    double* xe;     // stage mesh on the extension box (d comps)
+    double* ve;     // mesh velocity on the extension box (d comps)
     double* red;    // reduction partials
     double* scal;   // device scalars: [0] dt, [1] gmax, [2] dtau, [3..] spare
     unsigned long long* fail;   // [0] count inadmissible, [1] count no-convergence, [2] first index
     int red_blocks;
+    // HIP graph of one es_rk3_step (replayed while the argument pointers stay the same)
+    int use_graph;
+    hipStream_t cap;            // capture / replay stream (default priority)
+    hipEvent_t ev_in, ev_out;
+    hipGraphExec_t gexec;
+    const void* gkey[6];
 };
 
 namespace es {
@@ -39,12 +47,12 @@ constexpr int SCAL_DT = 0;
 constexpr int SCAL_GMAX = 1;
 constexpr int SCAL_DTAU = 2;
 constexpr int NSCAL = 8;
-constexpr int MAX_RED_BLOCKS = 1024;
 
 hipError_t launch_prim2con(const es_ctx* c, const double* prim, const double* J, double* U,
                            hipStream_t s);
 hipError_t launch_con2prim(const es_ctx* c, const double* U, const double* J, double* prim,
-                           hipStream_t s);
+                           int use_guess, hipStream_t s);
+int reduction_blocks(const GridDev& g);
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
                           hipStream_t s);
@@ -64,5 +72,6 @@ hipError_t launch_diagnostics(const es_ctx* c, const double* prim, const double*
                               const double* J, const double* dU, const double* dJ, double* out,
                               hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t s);
+hipError_t launch_zero(double* p, long long n, hipStream_t s);
 
 }  // namespace es

@@ -1,12 +1,12 @@
 // HIP kernels of libes.so (gfx950) and their launchers.
 //
-// Node-parallel kernels map one thread to one node; the residual maps one
-// 64-lane wavefront to a 61-node segment of a grid line plus its 3-node halo,
-// stages the line in LDS and exchanges two-point fluxes and face dissipation
-// between lanes through LDS.  All scalars that feed back into the step (dt,
-// monitor maximum, Delta_tau) are produced by two-pass block reductions that
-// end in a one-block kernel: max/min are exact in any order, sums are only
-// used for diagnostics.
+// Node kernels use 64 x 4 thread blocks over an index box (no integer
+// division in the index map).  The residual maps one 64-lane wavefront to a
+// 61-node segment of a grid line plus its 3-node halo, stages the line in LDS
+// and exchanges two-point fluxes and face dissipation between lanes through
+// LDS.  All scalars that feed back into the step (dt, monitor maximum,
+// Delta_tau) come from two-pass block reductions ending in a one-block kernel:
+// max/min are exact in any order, sums are only used for diagnostics.
 #include <float.h>
 #include <math.h>
 
@@ -18,38 +18,52 @@ namespace es {
 namespace {
 
 constexpr int TPB = 256;
+constexpr int BX = 64, BY = 4;
 
 inline unsigned grid_for(long long n, int tpb = TPB) {
     return (unsigned)((n + tpb - 1) / tpb);
 }
 
+inline dim3 box_grid(int e0, int e1, int e2) {
+    return dim3((unsigned)((e0 + BX - 1) / BX), (unsigned)((e1 + BY - 1) / BY), (unsigned)e2);
+}
+
+inline dim3 box_block() { return dim3(BX, BY, 1); }
+
 __device__ __forceinline__ long long gtid() {
     return (long long)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
-__device__ __forceinline__ void interior_coords(const GridDev& g, long long t, int& i, int& j, int& k) {
-    i = (int)(t % g.n[0]);
-    long long r = t / g.n[0];
-    j = (int)(r % g.n[1]);
-    k = (int)(r / g.n[1]);
+// (i, j, k) of this thread in the box [lo, lo + e); false outside
+__device__ __forceinline__ bool box_ijk(int lo0, int lo1, int lo2, int e0, int e1, int& i, int& j,
+                                        int& k) {
+    i = lo0 + (int)(blockIdx.x * BX + threadIdx.x);
+    j = lo1 + (int)(blockIdx.y * BY + threadIdx.y);
+    k = lo2 + (int)blockIdx.z;
+    return i < lo0 + e0 && j < lo1 + e1;
 }
 
-__device__ __forceinline__ void padded_coords(const GridDev& g, long long t, int& i, int& j, int& k) {
-    i = (int)(t % g.P[0]) - NG;
-    long long r = t / g.P[0];
-    j = (int)(r % g.P[1]) - NG;
-    k = (int)(r / g.P[1]) - g.g2;
+__device__ __forceinline__ int flat_block() {
+    return (int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
 }
 
-// Block reductions of one double (256 threads = 4 wavefronts).
+__device__ __forceinline__ int flat_tid() { return (int)(threadIdx.y * blockDim.x + threadIdx.x); }
+
+// index in the mesh-extension box (6 layers beyond the interior on active axes)
+__device__ __forceinline__ long long eidx(const GridDev& g, int i, int j, int k) {
+    return ((long long)(k + g.g6) * g.E[1] + (j + 2 * NG)) * g.E[0] + (i + 2 * NG);
+}
+
+// Block reductions of one double over the whole block (wavefronts of 64).
 template <int OP>   // 0 max, 1 min, 2 sum
 __device__ __forceinline__ double block_reduce(double v, double* sh) {
     v = OP == 0 ? wave_max(v) : (OP == 1 ? wave_min(v) : wave_sum(v));
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    const int tid = flat_tid();
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) sh[w] = v;
     __syncthreads();
     double r = sh[0];
-    const int nw = blockDim.x >> 6;
+    const int nw = (int)(blockDim.x * blockDim.y) >> 6;
     for (int q = 1; q < nw; ++q) r = OP == 0 ? fmax(r, sh[q]) : (OP == 1 ? fmin(r, sh[q]) : r + sh[q]);
     __syncthreads();
     return r;
@@ -61,6 +75,11 @@ __device__ __forceinline__ double block_reduce(double v, double* sh) {
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) p[t] = v;
+}
+
+__global__ void k_zero(double* __restrict__ p, long long n) {
+    const long long t = gtid();
+    if (t < n) p[t] = 0.0;
 }
 
 __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, long long n) {
@@ -93,22 +112,24 @@ __global__ void k_prim2con_rhd(GridDev g, double G, const double* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// conservative -> primitive on the padded box (ghosts by the solution rule)
+// conservative -> primitive on the padded box (ghosts by the solution rule).
+// With use_guess the pressure already stored at the node (previous stage) seeds
+// the Newton iteration when it lies inside the bracket.
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ void k_con2prim_rhd(GridDev g, double G, const double* __restrict__ U,
-                               const double* __restrict__ J, double* __restrict__ prim,
+                               const double* __restrict__ J, double* prim, int use_guess,
                                unsigned long long* __restrict__ fail) {
     constexpr int M = DIM + 2;
-    const long long t = gtid();
-    if (t >= g.pnodes) return;
     int i, j, k;
-    padded_coords(g, t, i, j, k);
+    if (!box_ijk(-NG, -NG, -g.g2, g.P[0], g.P[1], i, j, k)) return;
+    const long long t = pidx(g, i, j, k);
     const int si = map_sol(i, g.n[0], g.bc[0]);
     const int sj = map_sol(j, g.n[1], g.bc[1]);
     const int sk = DIM == 3 ? map_sol(k, g.n[2], g.bc[2]) : 0;
     const long long src = iidx(g, si, sj, sk);
     const long long N = g.nodes;
+    const long long P = g.pnodes;
     const double Jv = J[src];
     const double D = U[src] / Jv;
     double m[DIM];
@@ -116,8 +137,8 @@ __global__ void k_con2prim_rhd(GridDev g, double G, const double* __restrict__ U
     for (int c = 0; c < DIM; ++c) m[c] = U[(1 + c) * N + src] / Jv;
     const double E = U[(M - 1) * N + src] / Jv;
     double rho, p, u[DIM];
-    const int st = c2p_rhd<DIM>(G, D, m, E, rho, u, p);
-    const long long P = g.pnodes;
+    const double guess = use_guess ? prim[(M - 1) * P + t] : -1.0;
+    const int st = c2p_rhd<DIM>(G, D, m, E, guess, rho, u, p);
     if (st != 0) {
         rho = p = __builtin_nan("");
 #pragma unroll
@@ -138,26 +159,42 @@ __global__ void k_con2prim_rhd(GridDev g, double G, const double* __restrict__ U
 // ---------------------------------------------------------------------------
 // metrics (Section 3.3; 2D explicit form of Appendix B with 1/Delta xi)
 // ---------------------------------------------------------------------------
-__global__ void k_metrics2d(GridDev g, const double* __restrict__ x, const double* __restrict__ xd,
-                            const double* __restrict__ dt_dev, double coef,
-                            double* __restrict__ met, double* __restrict__ J0) {
-    const long long t = gtid();
-    if (t >= g.pnodes) return;
+// Stage mesh x + cdt xdot and mesh velocity on the extension box (6 layers):
+// periodic copies with the coordinate shift, odd reflection on outflow axes.
+template <int DIM>
+__global__ void k_mesh_extend(GridDev g, const double* __restrict__ x, const double* __restrict__ xd,
+                              const double* __restrict__ dt_dev, double coef, double* __restrict__ xe,
+                              double* __restrict__ ve) {
     int i, j, k;
-    padded_coords(g, t, i, j, k);
+    if (!box_ijk(-2 * NG, -2 * NG, -g.g6, g.E[0], g.E[1], i, j, k)) return;
+    const long long t = eidx(g, i, j, k);
     const double cdt = dt_dev != nullptr ? coef * dt_dev[0] : 0.0;
     const double* xs = dt_dev != nullptr ? xd : nullptr;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        xe[c * g.enodes + t] = mesh_value(g, x, xs, cdt, c, i, j, k, true);
+        if (ve != nullptr) ve[c * g.enodes + t] = xd != nullptr ? mesh_value(g, xd, nullptr, 0.0, c, i, j, k, false) : 0.0;
+    }
+}
+
+__global__ void k_metrics2d(GridDev g, const double* __restrict__ xe, const double* __restrict__ ve,
+                            double* __restrict__ met, double* __restrict__ J0) {
+    int i, j, k;
+    if (!box_ijk(-NG, -NG, 0, g.P[0], g.P[1], i, j, k)) return;
+    const long long t = pidx(g, i, j, 0);
+    const long long e = eidx(g, i, j, 0);
+    const long long E0 = g.E[0];
+    const long long EN = g.enodes;
     double dxi[2], deta[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
+        const double* xc = xe + c * EN + e;
         double s = 0.0, r = 0.0;
 #pragma unroll
         for (int n = 1; n <= 3; ++n) {
             const double a = 0.5 * alpha3(n);
-            s += a * (mesh_value(g, x, xs, cdt, c, i + n, j, 0, true) -
-                      mesh_value(g, x, xs, cdt, c, i - n, j, 0, true));
-            r += a * (mesh_value(g, x, xs, cdt, c, i, j + n, 0, true) -
-                      mesh_value(g, x, xs, cdt, c, i, j - n, 0, true));
+            s += a * (xc[n] - xc[-n]);
+            r += a * (xc[n * E0] - xc[-n * E0]);
         }
         dxi[c] = s;
         deta[c] = r;
@@ -168,9 +205,8 @@ __global__ void k_metrics2d(GridDev g, const double* __restrict__ x, const doubl
     const double etx = -dxi[1] / g.dxi[0];
     const double ety = dxi[0] / g.dxi[0];
     double at0 = 0.0, at1 = 0.0;
-    if (xd != nullptr) {
-        const double vx = mesh_value(g, xd, nullptr, 0.0, 0, i, j, 0, false);
-        const double vy = mesh_value(g, xd, nullptr, 0.0, 1, i, j, 0, false);
+    if (ve != nullptr) {
+        const double vx = ve[e], vy = ve[EN + e];
         at0 = -(vx * xix + vy * xiy);
         at1 = -(vx * etx + vy * ety);
     }
@@ -362,9 +398,8 @@ __global__ void __launch_bounds__(256) k_cfl_partial(GridDev g, double G, const 
 #pragma unroll
     for (int k = 0; k < DIM; ++k) mx[k] = 0.0;
     const long long P = g.pnodes;
-    for (long long t = gtid(); t < g.nodes; t += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        interior_coords(g, t, i, j, k);
+    int i, j, k;
+    if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
         const long long pi = pidx(g, i, j, k);
         const double rho = prim[pi], p = prim[(M - 1) * P + pi];
         double u[DIM], uu = 0.0;
@@ -375,7 +410,7 @@ __global__ void __launch_bounds__(256) k_cfl_partial(GridDev g, double G, const 
         const double h = 1.0 + G / (G - 1.0) * p / rho;
         const double cs2 = G * p / (rho * h);
         const double cs = sqrt(cs2);
-        const double iJ = 1.0 / J[t];
+        const double iJ = 1.0 / J[iidx(g, i, j, k)];
 #pragma unroll
         for (int kd = 0; kd < DIM; ++kd) {
             double ax[DIM], L2 = 0.0;
@@ -390,14 +425,14 @@ __global__ void __launch_bounds__(256) k_cfl_partial(GridDev g, double G, const 
             const double iden = 1.0 / (1.0 - v2 * cs2);
             const double lm = (vn * (1.0 - cs2) - cs * disc) * iden;
             const double lp = (vn * (1.0 - cs2) + cs * disc) * iden;
-            const double r = L * fmax(fabs(lm), fabs(lp)) * iJ;
-            mx[kd] = fmax(mx[kd], r);
+            mx[kd] = L * fmax(fabs(lm), fabs(lp)) * iJ;
         }
     }
+    const int nb = (int)(gridDim.x * gridDim.y * gridDim.z);
 #pragma unroll
     for (int kd = 0; kd < DIM; ++kd) {
         const double r = block_reduce<0>(mx[kd], sh);
-        if (threadIdx.x == 0) partial[kd * gridDim.x + blockIdx.x] = r;
+        if (flat_tid() == 0) partial[kd * nb + flat_block()] = r;
     }
 }
 
@@ -426,39 +461,37 @@ __global__ void __launch_bounds__(256) k_monitor_grad(GridDev g, int M, int sigm
     __shared__ double sh[8];
     const long long P = g.pnodes;
     double mx = 0.0;
-    for (long long t = gtid(); t < g.nodes; t += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        interior_coords(g, t, i, j, k);
-        int c[3] = {i, j, k};
+    int i, j, k;
+    if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
+        const int c[3] = {i, j, k};
+        const long long pc = pidx(g, i, j, k);
+        const long long off = sigma_ln ? M * P : 0;
+        const long long strides[3] = {1, (long long)g.P[0], (long long)g.P[0] * g.P[1]};
         double g2 = 0.0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            auto sig = [&](int off) {
-                int cc[3] = {c[0], c[1], c[2]};
-                cc[a] = map_sol(c[a] + off, g.n[a], g.bc[a]);
-                const long long pi = pidx(g, cc[0], cc[1], cc[2]);
-                return sigma_ln ? prim[M * P + pi] : prim[pi];
-            };
+            // neighbours through the solution rule: ghosts of the padded box hold
+            // the periodic copies, so only outflow edges need the one-sided form
+            const double sp = prim[off + pc + strides[a]];
+            const double sm = prim[off + pc - strides[a]];
+            const double s0 = prim[off + pc];
             double d;
-            if (g.bc[a] == ES_BC_PERIODIC || (c[a] > 0 && c[a] < g.n[a] - 1)) {
-                d = (sig(1) - sig(-1)) / (2.0 * g.dxi[a]);
-            } else if (c[a] == 0) {
-                d = (sig(1) - sig(0)) / g.dxi[a];
-            } else {
-                d = (sig(0) - sig(-1)) / g.dxi[a];
-            }
+            if (g.bc[a] == ES_BC_PERIODIC || (c[a] > 0 && c[a] < g.n[a] - 1)) d = (sp - sm) / (2.0 * g.dxi[a]);
+            else if (c[a] == 0) d = (sp - s0) / g.dxi[a];
+            else d = (s0 - sm) / g.dxi[a];
             g2 += d * d;
         }
+        const long long t = iidx(g, i, j, k);
         if (sqgrad) {
             w[t] = sqrt(1.0 + alpha * g2);
         } else {
             const double gn = sqrt(g2);
             w[t] = gn;
-            mx = fmax(mx, gn);
+            mx = gn;
         }
     }
     const double r = block_reduce<0>(mx, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+    if (flat_tid() == 0) partial[flat_block()] = r;
 }
 
 // one-block reduction of partial maxima (op 0) or minima capped at 1 (op 1)
@@ -481,42 +514,56 @@ __global__ void k_monitor_apply(long long n, double alpha, const double* __restr
 
 template <int DIM>
 __global__ void k_filter(GridDev g, const double* __restrict__ win, double* __restrict__ wout) {
-    const long long t = gtid();
-    if (t >= g.nodes) return;
     int i, j, k;
-    interior_coords(g, t, i, j, k);
+    if (!box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) return;
     double s = 0.0;
     if (DIM == 2) {
-        for (int o0 = -1; o0 <= 1; ++o0)
+        for (int o0 = -1; o0 <= 1; ++o0) {
+            const int ii = map_sol(i + o0, g.n[0], g.bc[0]);
             for (int o1 = -1; o1 <= 1; ++o1) {
-                const int ii = map_sol(i + o0, g.n[0], g.bc[0]);
                 const int jj = map_sol(j + o1, g.n[1], g.bc[1]);
                 const int e = abs(o0) + abs(o1) + 2;
                 s += ldexp(1.0, -e) * win[iidx(g, ii, jj, 0)];
             }
+        }
     } else {
-        for (int o0 = -1; o0 <= 1; ++o0)
-            for (int o1 = -1; o1 <= 1; ++o1)
+        for (int o0 = -1; o0 <= 1; ++o0) {
+            const int ii = map_sol(i + o0, g.n[0], g.bc[0]);
+            for (int o1 = -1; o1 <= 1; ++o1) {
+                const int jj = map_sol(j + o1, g.n[1], g.bc[1]);
                 for (int o2 = -1; o2 <= 1; ++o2) {
-                    const int ii = map_sol(i + o0, g.n[0], g.bc[0]);
-                    const int jj = map_sol(j + o1, g.n[1], g.bc[1]);
                     const int kk = map_sol(k + o2, g.n[2], g.bc[2]);
                     const int e = abs(o0) + abs(o1) + abs(o2) + 3;
                     s += ldexp(1.0, -e) * win[iidx(g, ii, jj, kk)];
                 }
+            }
+        }
     }
-    wout[t] = s;
+    wout[iidx(g, i, j, k)] = s;
+}
+
+// Value of mesh component q at the neighbour c + s e_a of interior node c: a
+// direct load inside the box, the periodic copy with its shift across a
+// periodic edge (the Jacobi and limiter rules never look across an outflow edge).
+template <int DIM>
+__device__ __forceinline__ double mesh_nb(const GridDev& g, const double* __restrict__ x, int q,
+                                          const int* c, int a, int s) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[a] += s;
+    double shift = 0.0;
+    if (cc[a] < 0) { cc[a] += g.n[a]; if (q == a) shift = -g.period[a]; }
+    else if (cc[a] >= g.n[a]) { cc[a] -= g.n[a]; if (q == a) shift = g.period[a]; }
+    return x[(long long)q * g.nodes + iidx(g, cc[0], cc[1], cc[2])] + shift;
 }
 
 // One Jacobi sweep of the mesh equations over the axes along which a node is free.
 template <int DIM>
 __global__ void k_jacobi(GridDev g, const double* __restrict__ w, const double* __restrict__ xin,
                          double* __restrict__ xout) {
-    const long long t = gtid();
-    if (t >= g.nodes) return;
     int i, j, k;
-    interior_coords(g, t, i, j, k);
-    int c[3] = {i, j, k};
+    if (!box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) return;
+    const int c[3] = {i, j, k};
+    const long long t = iidx(g, i, j, k);
     bool fr[3];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) fr[a] = g.bc[a] == ES_BC_PERIODIC || (c[a] > 0 && c[a] < g.n[a] - 1);
@@ -528,18 +575,15 @@ __global__ void k_jacobi(GridDev g, const double* __restrict__ w, const double* 
     for (int a = 0; a < DIM; ++a) {
         if (!fr[a]) continue;
         int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
-        cp[a] = c[a] + 1;
-        cm[a] = c[a] - 1;
-        int sp_[3] = {cp[0], cp[1], cp[2]}, sm_[3] = {cm[0], cm[1], cm[2]};
-        sp_[a] = map_sol(cp[a], g.n[a], g.bc[a]);
-        sm_[a] = map_sol(cm[a], g.n[a], g.bc[a]);
-        const double wp = w[iidx(g, sp_[0], sp_[1], sp_[2])];
-        const double wm = w[iidx(g, sm_[0], sm_[1], sm_[2])];
+        cp[a] = map_sol(c[a] + 1, g.n[a], g.bc[a]);
+        cm[a] = map_sol(c[a] - 1, g.n[a], g.bc[a]);
+        const double wp = w[iidx(g, cp[0], cp[1], cp[2])];
+        const double wm = w[iidx(g, cm[0], cm[1], cm[2])];
         den += 2.0 * wc + wp + wm;
 #pragma unroll
         for (int q = 0; q < DIM; ++q) {
-            const double xp = mesh_value(g, xin, nullptr, 0.0, q, cp[0], cp[1], cp[2], true);
-            const double xm = mesh_value(g, xin, nullptr, 0.0, q, cm[0], cm[1], cm[2], true);
+            const double xp = mesh_nb<DIM>(g, xin, q, c, a, +1);
+            const double xm = mesh_nb<DIM>(g, xin, q, c, a, -1);
             num[q] += (wc + wp) * xp + (wc + wm) * xm;
         }
     }
@@ -556,24 +600,22 @@ __global__ void __launch_bounds__(256) k_dtau_partial(GridDev g, const double* _
                                                       double* __restrict__ partial) {
     __shared__ double sh[8];
     double best = 1.0;
-    for (long long t = gtid(); t < g.nodes; t += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        interior_coords(g, t, i, j, k);
-        int c[3] = {i, j, k};
+    int i, j, k;
+    if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
+        const int c[3] = {i, j, k};
+        const long long t = iidx(g, i, j, k);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             const long long o = (long long)a * g.nodes + t;
             const double dk = xm[o] - x[o];
-            if (dk == 0.0) continue;
-            int cc[3] = {c[0], c[1], c[2]};
-            cc[a] += dk > 0.0 ? 1 : -1;
-            const double nb = mesh_value(g, x, nullptr, 0.0, a, cc[0], cc[1], cc[2], true);
+            if (dk == 0.0) continue;       // fixed coordinates (outflow edges) never move
+            const double nb = mesh_nb<DIM>(g, x, a, c, a, dk > 0.0 ? 1 : -1);
             const double b = dk < 0.0 ? -(x[o] - nb) / (2.0 * dk) : (nb - x[o]) / (2.0 * dk);
             best = fmin(best, b);
         }
     }
     const double r = block_reduce<1>(best, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+    if (flat_tid() == 0) partial[flat_block()] = r;
 }
 
 __global__ void k_mesh_update(long long n, const double* __restrict__ x, const double* __restrict__ xm,
@@ -599,15 +641,22 @@ __global__ void k_zero_mesh_velocity(long long n, const double* __restrict__ x, 
 // SSP-RK3 stage combinations (Shu-Osher form)
 // ---------------------------------------------------------------------------
 // out may alias U0 (last stage writes the new state in place), so no __restrict__.
-__global__ void k_rk_combine(long long n, int stage, const double* U0, const double* Us,
-                             const double* __restrict__ L, const double* __restrict__ dt_dev,
-                             double* out) {
-    const long long t = gtid();
-    if (t >= n) return;
+// Threads [0, nU) combine Ucurv, threads [nU, nU + nJ) combine J.
+__global__ void k_rk_combine(long long nU, long long nJ, int stage, const double* U0, const double* Us,
+                             const double* __restrict__ L, const double* J0, const double* Js,
+                             const double* __restrict__ LJ, const double* __restrict__ dt_dev,
+                             double* outU, double* outJ) {
+    long long t = gtid();
+    if (t >= nU + nJ) return;
+    const double* a = U0;
+    const double* b = Us;
+    const double* l = L;
+    double* o = outU;
+    if (t >= nU) { t -= nU; a = J0; b = Js; l = LJ; o = outJ; }
     const double dt = dt_dev[0];
-    if (stage == 0) out[t] = U0[t] + dt * L[t];
-    else if (stage == 1) out[t] = 0.75 * U0[t] + 0.25 * (Us[t] + dt * L[t]);
-    else out[t] = U0[t] / 3.0 + 2.0 / 3.0 * (Us[t] + dt * L[t]);
+    if (stage == 0) o[t] = a[t] + dt * l[t];
+    else if (stage == 1) o[t] = 0.75 * a[t] + 0.25 * (b[t] + dt * l[t]);
+    else o[t] = a[t] / 3.0 + 2.0 / 3.0 * (b[t] + dt * l[t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -627,9 +676,9 @@ __global__ void __launch_bounds__(256) k_diag_partial(GridDev g, double G, const
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     const long long P = g.pnodes, N = g.nodes;
-    for (long long t = gtid(); t < N; t += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        interior_coords(g, t, i, j, k);
+    int i, j, k;
+    if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
+        const long long t = iidx(g, i, j, k);
         const long long pi = pidx(g, i, j, k);
         const double rho = prim[pi], p = prim[(M - 1) * P + pi];
         const double lr = prim[M * P + pi], lb = prim[(M + 1) * P + pi];
@@ -650,16 +699,17 @@ __global__ void __launch_bounds__(256) k_diag_partial(GridDev g, double G, const
         ep -= phi * dJ[t];
         const double s = log(p) - G * lr;
         const double eta = -rho * W * s / (G - 1.0);
-        acc[0] += ep;
-        acc[1] += J[t] * eta;
-        acc[2] += J[t];
+        acc[0] = ep;
+        acc[1] = J[t] * eta;
+        acc[2] = J[t];
 #pragma unroll
-        for (int c = 0; c < M; ++c) acc[3 + c] += U[c * N + t];
+        for (int c = 0; c < M; ++c) acc[3 + c] = U[c * N + t];
     }
+    const int nb = (int)(gridDim.x * gridDim.y * gridDim.z);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const double r = block_reduce<2>(acc[q], sh);
-        if (threadIdx.x == 0) partial[q * gridDim.x + blockIdx.x] = r;
+        if (flat_tid() == 0) partial[q * nb + flat_block()] = r;
     }
 }
 
@@ -674,15 +724,26 @@ __global__ void __launch_bounds__(256) k_diag_final(int nq, int nb, const double
     }
 }
 
-inline int red_blocks(const es_ctx* c) { return c->red_blocks; }
+inline dim3 interior_grid(const GridDev& g) { return box_grid(g.n[0], g.n[1], g.n[2]); }
+inline int interior_blocks(const GridDev& g) {
+    const dim3 b = interior_grid(g);
+    return (int)(b.x * b.y * b.z);
+}
 
 }  // namespace
+
+int reduction_blocks(const GridDev& g) { return interior_blocks(g); }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t s) {
     k_fill_u64<<<grid_for(n), TPB, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, long long n, hipStream_t s) {
+    k_zero<<<grid_for(n), TPB, 0, s>>>(p, n);
     return hipGetLastError();
 }
 
@@ -700,18 +761,24 @@ hipError_t launch_prim2con(const es_ctx* c, const double* prim, const double* J,
 }
 
 hipError_t launch_con2prim(const es_ctx* c, const double* U, const double* J, double* prim,
-                           hipStream_t s) {
+                           int use_guess, hipStream_t s) {
     const double G = c->scheme.gamma;
-    if (c->g.dim == 2) k_con2prim_rhd<2><<<grid_for(c->g.pnodes), TPB, 0, s>>>(c->g, G, U, J, prim, c->fail);
-    else k_con2prim_rhd<3><<<grid_for(c->g.pnodes), TPB, 0, s>>>(c->g, G, U, J, prim, c->fail);
+    const GridDev& g = c->g;
+    const dim3 gr = box_grid(g.P[0], g.P[1], g.P[2]);
+    if (g.dim == 2) k_con2prim_rhd<2><<<gr, box_block(), 0, s>>>(g, G, U, J, prim, use_guess, c->fail);
+    else k_con2prim_rhd<3><<<gr, box_block(), 0, s>>>(g, G, U, J, prim, use_guess, c->fail);
     return hipGetLastError();
 }
 
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
                           hipStream_t s) {
-    if (c->g.dim != 2) return hipErrorNotSupported;
-    k_metrics2d<<<grid_for(c->g.pnodes), TPB, 0, s>>>(c->g, x, xdot, dt_dev, coef, met, J0);
+    const GridDev& g = c->g;
+    if (g.dim != 2) return hipErrorNotSupported;
+    const dim3 ge = box_grid(g.E[0], g.E[1], g.E[2]);
+    double* ve = xdot != nullptr ? c->ve : nullptr;
+    k_mesh_extend<2><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve);
+    k_metrics2d<<<box_grid(g.P[0], g.P[1], 1), box_block(), 0, s>>>(g, c->xe, ve, met, J0);
     return hipGetLastError();
 }
 
@@ -752,11 +819,12 @@ hipError_t launch_residual(const es_ctx* c, const double* prim, const double* me
 
 hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, const double* J,
                       double* dt_dev, const double* fixed_dt_dev, hipStream_t s) {
-    const int nb = red_blocks(c);
+    const GridDev& g = c->g;
+    const int nb = interior_blocks(g);
     const double G = c->scheme.gamma;
-    if (c->g.dim == 2) k_cfl_partial<2><<<nb, 256, 0, s>>>(c->g, G, prim, met, J, c->red);
-    else k_cfl_partial<3><<<nb, 256, 0, s>>>(c->g, G, prim, met, J, c->red);
-    k_cfl_final<<<1, 256, 0, s>>>(c->g.dim, nb, c->scheme.cfl, c->g.dxi[0], c->g.dxi[1], c->g.dxi[2],
+    if (g.dim == 2) k_cfl_partial<2><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, c->red);
+    else k_cfl_partial<3><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, c->red);
+    k_cfl_final<<<1, 256, 0, s>>>(g.dim, nb, c->scheme.cfl, g.dxi[0], g.dxi[1], g.dxi[2],
                                   c->red, fixed_dt_dev, dt_dev);
     return hipGetLastError();
 }
@@ -772,33 +840,34 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
                        double* x_new, double* xdot, double* dtau_dev, hipStream_t s) {
     const GridDev& g = c->g;
     const es_monitor& mo = c->monitor;
-    const int nb = red_blocks(c);
+    const int nb = interior_blocks(g);
+    const dim3 gr = interior_grid(g);
     const int sig_ln = mo.sigma == ES_SIGMA_LNRHO;
     const int sq = mo.form == ES_MON_SQGRAD;
     double* w = c->wa;
     double* w2 = c->wb;
-    if (g.dim == 2) k_monitor_grad<2><<<nb, 256, 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
-    else k_monitor_grad<3><<<nb, 256, 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
+    if (g.dim == 2) k_monitor_grad<2><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
+    else k_monitor_grad<3><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
     if (!sq) {
         k_reduce_final<<<1, 256, 0, s>>>(0, nb, c->red, c->scal + SCAL_GMAX);
         k_monitor_apply<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, c->scal + SCAL_GMAX, w);
     }
     for (int f = 0; f < mo.filter_passes; ++f) {
-        if (g.dim == 2) k_filter<2><<<grid_for(g.nodes), TPB, 0, s>>>(g, w, w2);
-        else k_filter<3><<<grid_for(g.nodes), TPB, 0, s>>>(g, w, w2);
+        if (g.dim == 2) k_filter<2><<<gr, box_block(), 0, s>>>(g, w, w2);
+        else k_filter<3><<<gr, box_block(), 0, s>>>(g, w, w2);
         double* tmp = w; w = w2; w2 = tmp;
     }
     const double* xin = x;
     double* xo = c->xa;
     double* xalt = c->xb;
     for (int it = 0; it < mo.sweeps; ++it) {
-        if (g.dim == 2) k_jacobi<2><<<grid_for(g.nodes), TPB, 0, s>>>(g, w, xin, xo);
-        else k_jacobi<3><<<grid_for(g.nodes), TPB, 0, s>>>(g, w, xin, xo);
+        if (g.dim == 2) k_jacobi<2><<<gr, box_block(), 0, s>>>(g, w, xin, xo);
+        else k_jacobi<3><<<gr, box_block(), 0, s>>>(g, w, xin, xo);
         xin = xo;
         double* tmp = xo; xo = xalt; xalt = tmp;
     }
-    if (g.dim == 2) k_dtau_partial<2><<<nb, 256, 0, s>>>(g, x, xin, c->red);
-    else k_dtau_partial<3><<<nb, 256, 0, s>>>(g, x, xin, c->red);
+    if (g.dim == 2) k_dtau_partial<2><<<gr, box_block(), 0, s>>>(g, x, xin, c->red);
+    else k_dtau_partial<3><<<gr, box_block(), 0, s>>>(g, x, xin, c->red);
     double* dtau = dtau_dev != nullptr ? dtau_dev : c->scal + SCAL_DTAU;
     k_reduce_final<<<1, 256, 0, s>>>(1, nb, c->red, dtau);
     const long long n = g.nodes * g.dim;
@@ -814,18 +883,18 @@ hipError_t launch_rk_combine(const es_ctx* c, int stage, const double* U0, const
     // stage 2 writes the new state over U0/J0 (the caller passes them as outputs)
     double* outU = stage == 2 ? const_cast<double*>(U0) : Us;
     double* outJ = stage == 2 ? const_cast<double*>(J0) : Js;
-    k_rk_combine<<<grid_for(nU), TPB, 0, s>>>(nU, stage, U0, Us, L, dt_dev, outU);
-    k_rk_combine<<<grid_for(nJ), TPB, 0, s>>>(nJ, stage, J0, Js, LJ, dt_dev, outJ);
+    k_rk_combine<<<grid_for(nU + nJ), TPB, 0, s>>>(nU, nJ, stage, U0, Us, L, J0, Js, LJ, dt_dev, outU, outJ);
     return hipGetLastError();
 }
 
 hipError_t launch_diagnostics(const es_ctx* c, const double* prim, const double* U,
                               const double* J, const double* dU, const double* dJ, double* out,
                               hipStream_t s) {
-    const int nb = red_blocks(c);
+    const GridDev& g = c->g;
+    const int nb = interior_blocks(g);
     const double G = c->scheme.gamma;
-    if (c->g.dim == 2) k_diag_partial<2><<<nb, 256, 0, s>>>(c->g, G, prim, U, J, dU, dJ, c->red);
-    else k_diag_partial<3><<<nb, 256, 0, s>>>(c->g, G, prim, U, J, dU, dJ, c->red);
+    if (g.dim == 2) k_diag_partial<2><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, U, J, dU, dJ, c->red);
+    else k_diag_partial<3><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, U, J, dU, dJ, c->red);
     k_diag_final<<<1, 256, 0, s>>>(3 + c->m, nb, c->red, out);
     return hipGetLastError();
 }

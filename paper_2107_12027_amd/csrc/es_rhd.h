@@ -83,29 +83,35 @@ __device__ __forceinline__ void pair_flux_rhd(double G, const NodeRHD<NU>& l, co
 // Safeguarded Newton on g(p) = (G-1)[(E+p)(1-v^2) - p - D sqrt(1-v^2)] - p,
 // v = |m|/(E+p), g'(p) = (G-1) v^2 (1 - D W/(E+p)) - 1 < 0; the root lies in
 // (0, (G-1)E] for admissible states D > 0, E > sqrt(D^2 + |m|^2).
-// Returns 0 on success, 1 for an inadmissible state, 2 without convergence.
+// The iteration starts from ``guess`` when it lies inside the bracket, else
+// from the bracket midpoint.  Returns 0 on success, 1 for an inadmissible state,
+// 2 without convergence.
 template <int NU>
-__device__ __forceinline__ int c2p_rhd(double G, double D, const double* m, double E, double& rho,
-                                       double* u, double& p) {
+__device__ __forceinline__ int c2p_rhd(double G, double D, const double* m, double E, double guess,
+                                       double& rho, double* u, double& p) {
     double mm2 = 0.0;
 #pragma unroll
     for (int k = 0; k < NU; ++k) mm2 += m[k] * m[k];
     if (!(D > 0.0) || !(E > sqrt(D * D + mm2))) return 1;
     double lo = 0.0, hi = (G - 1.0) * E;
-    double pk = 0.5 * (lo + hi);
+    double pk = (guess > lo && guess < hi) ? guess : 0.5 * (lo + hi);
     int conv = 0;
     for (int it = 0; it < 200; ++it) {
         const double Ep = E + pk;
         const double v2 = mm2 / (Ep * Ep);
         const double sq = sqrt(1.0 - v2);
         const double gv = (G - 1.0) * (Ep * (1.0 - v2) - pk - D * sq) - pk;
+        if (gv == 0.0) { conv = 1; break; }
         if (gv > 0.0) lo = pk; else hi = pk;
         const double dg = (G - 1.0) * v2 * (1.0 - D / (sq * Ep)) - 1.0;
         double pn = pk - gv / dg;
-        if (!(pn > lo && pn < hi)) pn = 0.5 * (lo + hi);
+        // Newton step while it stays in the bracket (end points included), else bisection
+        if (!(pn >= lo && pn <= hi)) pn = 0.5 * (lo + hi);
         const double dp = fabs(pn - pk);
         pk = pn;
-        if (dp <= 1e-15 * pn || hi - lo <= 1e-15 * hi) { conv = 1; break; }
+        // g is evaluated from terms of size ~(E + p): the root is fixed only to
+        // ~eps (E + p), so the steps are measured against that scale
+        if (dp <= 1e-15 * (E + pn) || hi - lo <= 1e-15 * (E + hi)) { conv = 1; break; }
     }
     // one more Newton correction from the converged iterate
     {

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(HERE, "libes.so")
 ES_OK, ES_EINVAL, ES_EADMISSIBLE, ES_ENOCONV, ES_EMESH, ES_EHIP, ES_EUNSUPPORTED = range(7)
 SYMBOLS = ("es_create", "es_destroy", "es_nvars", "es_nprim", "es_nmet", "es_nodes",
            "es_padded_nodes", "es_prim2con", "es_metrics", "es_con2prim", "es_residual",
-           "es_cfl", "es_mesh_redistribute", "es_rk3_step", "es_diagnostics", "es_ctx_status",
-           "es_status_string")
+           "es_cfl", "es_mesh_redistribute", "es_rk3_step", "es_set_graph", "es_diagnostics",
+           "es_ctx_status", "es_status_string")
 
 
 class EsError(RuntimeError):
@@ -75,10 +75,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.es_mesh_redistribute.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.es_rk3_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.es_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.es_set_graph.argtypes = [vp, ctypes.c_int]
     lib.es_ctx_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(ctypes.c_longlong)]
     for name in ("es_prim2con", "es_metrics", "es_con2prim", "es_residual", "es_cfl",
-                 "es_mesh_redistribute", "es_rk3_step", "es_diagnostics", "es_ctx_status"):
+                 "es_mesh_redistribute", "es_rk3_step", "es_set_graph", "es_diagnostics",
+                 "es_ctx_status"):
         getattr(lib, name).restype = st
     lib.es_status_string.argtypes = [st]
     lib.es_status_string.restype = ctypes.c_char_p
@@ -173,6 +175,9 @@ class Context:
     def rk3_step(self, U, J, x, xdot, dt, fixed_dt=None, stream=None):
         _check(_lib.es_rk3_step(self.h, _ptr(U), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt), _ptr(fixed_dt),
                                 _stream(stream)), "es_rk3_step")
+
+    def set_graph(self, enable: bool):
+        _check(_lib.es_set_graph(self.h, int(bool(enable))), "es_set_graph")
 
     def diagnostics(self, prim, U, J, dU, dJ, out, stream=None):
         _check(_lib.es_diagnostics(self.h, _ptr(prim), _ptr(U), _ptr(J), _ptr(dU), _ptr(dJ), _ptr(out),

@@ -230,3 +230,35 @@ def test_diagnostics_entropy_production():
     assert abs(o[1] - np.sum(Jo * eta)) <= 1e-12 * np.sum(np.abs(Jo * eta))
     assert abs(o[2] - np.sum(Jo)) <= 1e-12 * np.sum(Jo)
     np.testing.assert_allclose(o[3:], Uo.reshape(c.m, -1).sum(axis=1), rtol=1e-12)
+
+
+def test_graph_replay_matches_eager_launches():
+    # es_rk3_step replays a captured HIP graph; every replay, with unrelated eager
+    # work and synchronisations in between, must equal the eager launch sequence
+    w = wl.quadrant_riemann(n=70, seed=2)
+    g = w.grid
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    runs = []
+    for graph in (True, False):
+        ctx = es.Context(g, w.scheme, w.monitor)
+        ctx.set_graph(graph)
+        met = empty(ctx.nmet, *ctx.padded_shape())
+        J = empty(*ctx.shape())
+        xg = dev(w.x)
+        ctx.metrics(xg, None, met, J)
+        U = empty(ctx.m, *ctx.shape())
+        ctx.prim2con(dev(P[ph.comps(w.scheme.phys, g.dim)]), J, U)
+        xdot = empty(g.dim, *ctx.shape())
+        dt = empty(1)
+        hist = []
+        for it in range(5):
+            ctx.rk3_step(U, J, xg, xdot, dt)
+            junk = torch.randn(1000, device="cuda").sum()      # unrelated eager work
+            torch.cuda.synchronize()
+            hist.append((host(U).copy(), host(J).copy(), host(xg).copy(), host(dt).copy()))
+            del junk
+        assert ctx.status()[0] == es.ES_OK
+        runs.append(hist)
+    for a, b in zip(*runs):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
