@@ -34,9 +34,9 @@ PEAK_HBM = 8.0e12                # B/s
 # op-counting scalar (paper_2107_12027_amd/csrc/opcount.cpp, run by
 # `python -m paper_2107_12027_amd.build --opcount`): + - * / sqrt log fabs
 # fmax count 1, fma counts 2.  Per node and direction: 3 two-point fluxes
-# (92.4 each), 1 face dissipation (1553.2), state preparation (6) and the
-# flux-difference accumulation (66): 1902.3; two directions: 3804.6.
-RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3804.6
+# (92.4 each), 1 face dissipation (1559.2), state preparation (6) and the
+# flux-difference accumulation (66): 1908.3; two directions: 3816.7.
+RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3816.7
 
 
 def parse():

@@ -11,7 +11,7 @@ which hold none of the scheme's arithmetic).
 
 Plain numpy in float64, vectorised over nodes and faces only; every function
 follows a passage of the paper (cited by section and equation label) or a
-reading of it listed in the design doc.
+stated reading of it where the paper is silent or garbled.
 
 Modules
   physics      equation of state, U/F/V, entropy pair, potentials, con2prim

@@ -5,16 +5,18 @@ Section 4 (eq. ESFlux_HO): at the face (i, k, +1/2)
 with
   * T = diag{1, T_0, 1} (RHD) or diag{1, T_0, 1, T_0} (RMHD), T_0 the rotation
     whose first row is the unit metric normal (read with atan2 semantics and no
-    trigonometry, see DESIGN.md);
+    trigonometry);
   * lambda^ = max_m |J dxi_k/dt + L_k lambda_m(T U)|, L_k = |J grad xi_k|;
   * R scaled eigenvectors: dU/dV = R R^T, dF_1/dU = R Lambda R^{-1} (for RMHD the
     Godunov-Powell modified Jacobian dF_1/dU + Phi'(V)^T dB_1/dU);
   * WENO-(2p-1) (Jiang-Shu) of V~ = R^T T V along the line, <<V~>> = V~^+ - V~^-;
   * Y_ll = 1 iff <<V~_l>> and [V~_l] = V~_{i+1} - V~_i have the same sign
-    (strictly positive product), a jump below Y_TOL times the size of the terms
-    of its projections counting as zero.
-The face state, face metrics and the choice of basis inside the degenerate
-eigenvalue cluster are readings listed in the design doc.
+    (strictly positive product), a jump below Y_TOL |r_l|_1 (|T V_i|_max +
+    |T V_i+1|_max) counting as zero.
+The face state (the state whose entropy variables are the mean of the two
+nodes', so that R R^T [V] = A0(V_mid)[V] is the midpoint rule for
+[U] = int A0 dV along the straight path in V), the face metrics and the choice of
+basis inside the degenerate eigenvalue cluster are readings of the paper.
 
 The eigen-structure is computed generically and numerically, so that it shares
 nothing with any closed form: the primitive-variable Jacobians dU/dP, dF_1/dP,
@@ -111,12 +113,20 @@ def eigensystem(Pr, G, phys, dim):
         JF = JF.copy()
         JF[:, :, 5] += Phip
     AP = np.linalg.solve(JU, JF)
-    w, vec = np.linalg.eig(AP)
-    lam = w.real
-    dP = vec.real
+    lam = np.linalg.eigvals(AP).real
     vn = Pr[1] / np.sqrt(1.0 + Pr[1] ** 2 + Pr[2] ** 2 + Pr[3] ** 2)
     c = cluster_size(phys, dim)
     order = np.argsort(np.abs(lam - vn[:, None]), axis=1)
+    # Eigenvectors of the simple eigenvalues: the null vector of A_P - lambda I from
+    # an SVD.  (LAPACK's general eigenvector routine balances the matrix first; with
+    # entries of order 1e-50 next to entries of order one, as at a state at rest up
+    # to rounding, the balanced back-transformation returned vectors with residuals
+    # of order one.)
+    eye = np.eye(m)[None]
+    dP = np.empty_like(AP)
+    for k in range(m):
+        _, _, vk = np.linalg.svd(AP - lam[:, k, None, None] * eye)
+        dP[:, :, k] = vk[:, m - 1, :]
     # The cluster lambda = v_n is semi-simple: its invariant subspace is taken from
     # the null space of A_P - v_n I (SVD), which stays well conditioned where the
     # individual eigenvectors of a repeated eigenvalue are not.
@@ -179,7 +189,11 @@ def face_dissipation(Pst, ast, G, phys, dim, eps, details=False):
     n = ax / L
     T0 = rotation(n)
     slots = [1, 5] if phys == ph.RMHD else [1]
-    Pbar = 0.5 * (Pst[2] + Pst[3])
+    # face state: the state whose entropy variables are the mean of the two nodes'
+    Vbar = 0.5 * (ph.entropy_vars(Pst[2], G) + ph.entropy_vars(Pst[3], G))
+    Pbar = ph.prim_from_entropy_vars(Vbar, G)
+    if phys == ph.RHD:
+        Pbar[5:8] = 0.0
     Pr = rotate_full(Pbar, T0, slots)
     lam, R = eigensystem(Pr, G, phys, dim)
     lhat = np.max(np.abs(abar[0][:, None] + L[:, None] * lam), axis=1)
@@ -191,11 +205,13 @@ def face_dissipation(Pst, ast, G, phys, dim, eps, details=False):
     vp = weno5_minus(Vt[5], Vt[4], Vt[3], Vt[2], Vt[1], eps)
     jump_weno = vp - vm
     jump = Vt[3] - Vt[2]
-    # sign(0) reading: a jump [V~_l] within rounding of zero (below Y_TOL times the
-    # magnitude of the terms of its two projections) counts as zero, so Y_l = 0
+    # sign(0) reading: a jump [V~_l] within rounding of zero counts as zero, so Y_l = 0.
+    # Rounding level: Y_TOL times |r_l|_1 (|T V_i|_max + |T V_i+1|_max), a scale that
+    # does not shrink with the components a column happens to touch (the transverse
+    # momentum entries of a state at rest are themselves rounding residue).
     Vi = rotate_full(ph.entropy_vars(Pst[2], G), T0, slots)[sel]
     Vj = rotate_full(ph.entropy_vars(Pst[3], G), T0, slots)[sel]
-    scale = np.einsum("nab,an->bn", np.abs(R), np.abs(Vi) + np.abs(Vj))
+    scale = np.sum(np.abs(R), axis=1).T * (np.max(np.abs(Vi), axis=0) + np.max(np.abs(Vj), axis=0))[None, :]
     Y = ((jump_weno * jump > 0) & (np.abs(jump) > Y_TOL * scale)).astype(np.float64)
     coef = Y * jump_weno                                                 # (m, N)
     dsel = lhat[None, :] * np.einsum("nab,bn->an", R, coef)              # R (Y <<V~>>)

@@ -6,8 +6,8 @@ eq. UFcircle)
     F~_k(l, r) = 1/2 (a_t,l + a_t,r) U~ + sum_j 1/2 (a_j,l + a_j,r) F~_j,
 with a_t = J d(xi_k)/dt, a_j = J d(xi_k)/dx_j and U~, F~_j satisfying
     [V].U~ = [phi],     [V].F~_j = [psi_j] - {B_j} [Phi].
-The paper prints U~ for RMHD (with a garbled R_1, read here as stated in
-the design doc) and defers F~_j (RMHD) and the RHD pair to other papers; the forms
+The paper prints U~ for RMHD (with a garbled R_1, read here so that the
+potential condition holds) and defers F~_j (RMHD) and the RHD pair to other papers; the forms
 below were derived from the two conditions above with the exact two-factor jump
 identities [ab] = {a}[b] + {b}[a], [W] = sum_k {u_k}[u_k]/{W}.  They are pinned
 by tests of the EC condition itself, consistency and symmetry.

@@ -5,7 +5,7 @@ Section 5 of the paper: Winslow's choice G_k = omega I in the mesh functional
 filter, the Jacobi iteration of the central-difference mesh equations, the move
 limiter Delta_tau and the mesh velocity xdot = Delta_tau delta_tau x / Delta t.
 Boundary treatment, the gradient discretisation, the squared-gradient monitor
-form and the limiter typo are readings listed in the design doc.
+form and the limiter typo are readings of the paper, not its printed text.
 """
 from __future__ import annotations
 

@@ -6,7 +6,7 @@ Section 3.3 (Discrete GCLs): spatial metrics by the conservative metric method
 temporal metrics J d(xi_k)/dt = -sum_j xdot_j (J d(xi_k)/dx_j) (eq. VCLCoeff);
 the 2D explicit form of Appendix B with the 1/Delta xi factors of eq. SCLCoeff.
 
-Ghost handling (readings in the design doc): the mesh is extended beyond the index
+Ghost handling (a reading; the paper does not fix it): the mesh is extended beyond the index
 box by a periodic copy plus the period shift, or by odd reflection
 x_{-a} = 2 x_0 - x_a on bounded axes; the metrics on the 3-wide ghost strips
 are evaluated from that extended mesh with the same formula as inside.

@@ -101,6 +101,22 @@ def entropy_vars(P, G):
     return np.concatenate([V1[None], beta * s["u"], (-beta * s["W"])[None], beta * s["b"]], axis=0)
 
 
+def prim_from_entropy_vars(V, G):
+    """Explicit inverse of the entropy-variable map: with beta^2 = V_5^2 - |V_2..4|^2
+    (since W^2 - |u|^2 = 1), u = V_2..4/beta, W = -V_5/beta,
+    ln rho = V_1 - Gamma/(Gamma-1) - ln(beta)/(Gamma-1) - beta, p = rho/beta, b = V_6..8/beta,
+    b^0 = u.b/W (from b = (B + b^0 u)/W and b^0 = u.B) and B = W b - b^0 u."""
+    beta = np.sqrt(V[4] ** 2 - _dot(V[1:4], V[1:4]))
+    u = V[1:4] / beta
+    W = -V[4] / beta
+    rho = np.exp(V[0] - G / (G - 1.0) - np.log(beta) / (G - 1.0) - beta)
+    p = rho / beta
+    b = V[5:8] / beta
+    b0 = _dot(u, b) / W
+    B = W * b - b0 * u
+    return np.concatenate([rho[None], u, p[None], B], axis=0)
+
+
 def entropy(P, G):
     """eta = -rho W s/(Gamma-1), s = ln(p/rho^Gamma) (eq. EntropyPair)."""
     s = state(P, G)

@@ -2,7 +2,7 @@
 
 * CFL time step (eq. cfl): Delta t = CFL / sum_k max_i rho_{k,i} / Delta xi_k, with
   rho_{k,i} the spectral radius of d(F_k)/dU + Phi'(V) dB_k/dU in curvilinear form,
-  i.e. L_k max_m |lambda_m(n_k)| / J (mesh-velocity term excluded).
+  i.e. L_k max_m |lambda_m(n_k)| / J (mesh-velocity term excluded, as eq. cfl prints it).
 * Third-order SSP Runge-Kutta (Proposition 4.2 and the conclusion) in Shu-Osher
   form applied to (U, J), with the stage meshes x^n + c Delta t xdot, c = 0, 1, 1/2,
   and metrics recomputed on each stage mesh.
@@ -78,6 +78,9 @@ def rk3_step(grid, scheme, mon, Ucurv, J, x, dt=None, details=False, xdot=None):
     the mesh velocity instead of the adaptive redistribution (the prescribed-motion
     tests of Section 6).  Returns dict(U, J, x, xdot, dt, ok)."""
     P0, ok = prim_from_cons(grid, scheme, Ucurv, J)
+    if not ok.all():
+        return dict(U=Ucurv, J=J, x=x, xdot=np.zeros_like(x), dt=np.nan, ok=ok, dtau=0.0,
+                    failed_stage=0)
     met0 = mt.metrics(grid, x, None, scheme.order_p)
     if dt is None:
         dt = cfl_dt(grid, scheme, P0, met0, J)

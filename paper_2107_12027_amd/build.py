@@ -59,7 +59,7 @@ def opcount() -> str:
     algorithmic FP64 work per node of the residual; returns its report."""
     exe = os.path.join(ROOT, "_build", "opcount")
     os.makedirs(os.path.dirname(exe), exist_ok=True)
-    cmd = [hipcc(), "-O1", "-std=c++17", "-I" + INCLUDE, "-I" + CSRC, "-o", exe,
+    cmd = [hipcc(), "-O1", "-std=c++17", "--offload-arch=" + ARCH, "-I" + INCLUDE, "-I" + CSRC, "-o", exe,
            os.path.join(CSRC, "opcount.cpp")]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

@@ -73,8 +73,8 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
         if (monitor->form != ES_MON_PAPER && monitor->form != ES_MON_SQGRAD) return ES_EINVAL;
         if (monitor->filter_passes < 0 || monitor->sweeps < 0 || !(monitor->alpha >= 0.0)) return ES_EINVAL;
     }
-    // kernels of this build: RHD, p = 3, FP64, 2D
-    if (scheme->phys != ES_RHD || scheme->order_p != 3 || scheme->mixed != 0 || grid->dim != 2)
+    // kernels of this build: RHD, p = 3, FP64
+    if (scheme->phys != ES_RHD || scheme->order_p != 3 || scheme->mixed != 0)
         return ES_EUNSUPPORTED;
 
     es_ctx* c = new (std::nothrow) es_ctx();
@@ -118,6 +118,7 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     if (e == hipSuccess) e = alloc(&c->wb, N);
     if (e == hipSuccess) e = alloc(&c->xe, (size_t)g.enodes * d);
     if (e == hipSuccess) e = alloc(&c->ve, (size_t)g.enodes * d);
+    if (e == hipSuccess && grid->dim == 3) e = alloc(&c->pi, (size_t)g.enodes * 9);
     if (e == hipSuccess) e = alloc(&c->red, (size_t)c->red_blocks * (3 + 8));
     if (e == hipSuccess) e = alloc(&c->scal, (size_t)es::NSCAL);
     if (e == hipSuccess) e = alloc(&c->fail, (size_t)4);
@@ -144,7 +145,7 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
 es_status es_destroy(es_ctx* c) {
     if (c == nullptr) return ES_EINVAL;
     void* bufs[] = {c->prim, c->met, c->L, c->LJ, c->Us, c->Js, c->xnew, c->xa, c->xb,
-                    c->wa, c->wb, c->xe, c->ve, c->red, c->scal, c->fail};
+                    c->wa, c->wb, c->xe, c->ve, c->pi, c->red, c->scal, c->fail};
     if (c->gexec != nullptr) (void)hipGraphExecDestroy(c->gexec);
     if (c->ev_in != nullptr) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out != nullptr) (void)hipEventDestroy(c->ev_out);

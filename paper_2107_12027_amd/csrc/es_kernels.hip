@@ -220,6 +220,90 @@ __global__ void k_metrics2d(GridDev g, const double* __restrict__ xe, const doub
         J0[iidx(g, i, j, 0)] = (dxi[0] * deta[1] - deta[0] * dxi[1]) / (g.dxi[0] * g.dxi[1]);
 }
 
+// 3D conservative metric method (eq. SCLCoeff): with the products
+//   Pi_{a,j} = delta_a[x_{j+1}] x_{j+2}   (indices mod 3)
+// on the extension box, J dxi_k/dx_j = (delta_{k+2}[Pi_{k+1,j}] - delta_{k+1}[Pi_{k+2,j}])
+// / (dxi_{k+1} dxi_{k+2}).  Pi_{a,.} is formed where the a-coordinate lies within
+// 3 layers of the interior (the metric differences never read it elsewhere).
+__global__ void k_cmm_products(GridDev g, const double* __restrict__ xe, double* __restrict__ pi) {
+    int i, j, k;
+    if (!box_ijk(-2 * NG, -2 * NG, -2 * NG, g.E[0], g.E[1], i, j, k)) return;
+    const long long e = eidx(g, i, j, k);
+    const long long EN = g.enodes;
+    const int c[3] = {i, j, k};
+    const long long st[3] = {1, (long long)g.E[0], (long long)g.E[0] * g.E[1]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool valid = c[a] >= -NG && c[a] < g.n[a] + NG;
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            const int j1 = (jj + 1) % 3, j2 = (jj + 2) % 3;
+            double v = 0.0;
+            if (valid) {
+                const double* xc = xe + j1 * EN + e;
+                double d = 0.0;
+#pragma unroll
+                for (int n = 1; n <= 3; ++n) d += 0.5 * alpha3(n) * (xc[n * st[a]] - xc[-n * st[a]]);
+                v = d * xe[j2 * EN + e];
+            }
+            pi[(a * 3 + jj) * EN + e] = v;
+        }
+    }
+}
+
+__global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const double* __restrict__ ve,
+                            const double* __restrict__ pi, double* __restrict__ met,
+                            double* __restrict__ J0) {
+    int i, j, k;
+    if (!box_ijk(-NG, -NG, -NG, g.P[0], g.P[1], i, j, k)) return;
+    const long long t = pidx(g, i, j, k);
+    const long long e = eidx(g, i, j, k);
+    const long long EN = g.enodes;
+    const long long P = g.pnodes;
+    const long long st[3] = {1, (long long)g.E[0], (long long)g.E[0] * g.E[1]};
+    double m[3][3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        const int k1 = (kk + 1) % 3, k2 = (kk + 2) % 3;
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            const double* pa = pi + (k1 * 3 + jj) * EN + e;   // Pi_{k1, j}, differenced along k2
+            const double* pb = pi + (k2 * 3 + jj) * EN + e;   // Pi_{k2, j}, differenced along k1
+            double ta = 0.0, tb = 0.0;
+#pragma unroll
+            for (int n = 1; n <= 3; ++n) {
+                const double a = 0.5 * alpha3(n);
+                ta += a * (pa[n * st[k2]] - pa[-n * st[k2]]);
+                tb += a * (pb[n * st[k1]] - pb[-n * st[k1]]);
+            }
+            m[kk][jj] = (ta - tb) / (g.dxi[k1] * g.dxi[k2]);
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        double at = 0.0;
+        if (ve != nullptr) {
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) at -= ve[jj * EN + e] * m[kk][jj];
+        }
+        met[(kk * 4) * P + t] = at;
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) met[(kk * 4 + 1 + jj) * P + t] = m[kk][jj];
+    }
+    if (J0 != nullptr && i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] && k >= 0 && k < g.n[2]) {
+        // J = sum_k (J dxi_k/dx_1) delta_k[x_1] / dxi_k
+        double Jv = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            double d = 0.0;
+#pragma unroll
+            for (int n = 1; n <= 3; ++n) d += 0.5 * alpha3(n) * (xe[e + n * st[kk]] - xe[e - n * st[kk]]);
+            Jv += m[kk][0] * d / g.dxi[kk];
+        }
+        J0[iidx(g, i, j, k)] = Jv;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // residual: one direction sweep
 // ---------------------------------------------------------------------------
@@ -774,11 +858,16 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
                           hipStream_t s) {
     const GridDev& g = c->g;
-    if (g.dim != 2) return hipErrorNotSupported;
     const dim3 ge = box_grid(g.E[0], g.E[1], g.E[2]);
     double* ve = xdot != nullptr ? c->ve : nullptr;
-    k_mesh_extend<2><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve);
-    k_metrics2d<<<box_grid(g.P[0], g.P[1], 1), box_block(), 0, s>>>(g, c->xe, ve, met, J0);
+    if (g.dim == 2) {
+        k_mesh_extend<2><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve);
+        k_metrics2d<<<box_grid(g.P[0], g.P[1], 1), box_block(), 0, s>>>(g, c->xe, ve, met, J0);
+    } else {
+        k_mesh_extend<3><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve);
+        k_cmm_products<<<ge, box_block(), 0, s>>>(g, c->xe, c->pi);
+        k_metrics3d<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, c->xe, ve, c->pi, met, J0);
+    }
     return hipGetLastError();
 }
 

@@ -208,8 +208,9 @@ __device__ __forceinline__ void rotation(const double* n, double T[3][3]) {
 // Entropy-stable dissipation d = lambda^ T^{-1} R Y <<V~>> at one face
 // (eq. ESFlux_HO).  nd[0..5] are the stencil nodes i-2..i+3 of the face
 // i+1/2; al, ar the metric vectors (a_t, a_1..a_d) of nodes i and i+1.
-//  * face state: arithmetic mean of (rho, u, p) of nodes i and i+1, face
-//    metrics: arithmetic mean (readings of this build);
+//  * face state: the state whose entropy variables are the mean of those of
+//    nodes i and i+1 (A0 at that state turns [V] into the midpoint rule for [U]);
+//    face metrics: arithmetic mean (readings of this build);
 //  * lambda^ = max |a_t + L lambda_m|, lambda_+- closed form, lambda_0 = v_n;
 //  * R: acoustic columns from the primitive eigenvector (scaled by lambda - v_n)
 //      dp = lambda - v_n, drho = dp/(h c^2), dv_n = (1 - v_n lambda)/(rho h W^2),
@@ -220,8 +221,8 @@ __device__ __forceinline__ void rotation(const double* n, double T[3][3]) {
 //    computed in the coefficient space of the cluster basis with the Gram
 //    matrix G_ab = dU_a . dV_b;
 //  * WENO5-JS of V~ = R^T T V on both sides, Y_l = [<<V~_l>> [V~_l] > 0], with a
-//    jump [V~_l] below Y_TOL times the size of the terms of its projections
-//    counted as zero (sign(0) at rounding level).
+//    jump [V~_l] below Y_TOL |r_l|_1 (|T V_i|_max + |T V_i+1|_max) counted as
+//    zero (sign(0) at rounding level).
 template <int DIM>
 __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRHD<DIM>* nd,
                                               const double* al, const double* ar, double* d) {
@@ -236,37 +237,6 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
     double nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
     double T[3][3];
     rotation<DIM>(nrm, T);
-
-    // face state in the rotated frame
-    const double rho = 0.5 * (nd[2].rho + nd[3].rho);
-    const double p = 0.5 * (nd[2].p + nd[3].p);
-    double ub[DIM], ur[DIM];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) ub[k] = 0.5 * (nd[2].u[k] + nd[3].u[k]);
-    double uu = 0.0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) s += T[a][b] * ub[b];
-        ur[a] = s;
-        uu += s * s;
-    }
-    const double W = sqrt(1.0 + uu);
-    const double iW = 1.0 / W;
-    double v[DIM];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) v[k] = ur[k] * iW;
-    const double v2 = uu * iW * iW;
-    const double vn = v[0];
-    const double h = 1.0 + G / (G - 1.0) * p / rho;
-    const double cs2 = G * p / (rho * h);
-    const double cs = sqrt(cs2);
-    const double disc = sqrt((1.0 - v2) * (1.0 - v2 * cs2 - vn * vn * (1.0 - cs2)));
-    const double iden = 1.0 / (1.0 - v2 * cs2);
-    const double lam_m = (vn * (1.0 - cs2) - cs * disc) * iden;
-    const double lam_p = (vn * (1.0 - cs2) + cs * disc) * iden;
-    const double lhat = fmax(fabs(at + L * lam_m), fmax(fabs(at + L * vn), fabs(at + L * lam_p)));
 
     // rotated entropy variables T V of the six stencil nodes
     double TV[6][M];
@@ -285,9 +255,45 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
         TV[j][M - 1] = -q.beta * q.W;
     }
 
+    // face state in the rotated frame: the state whose entropy variables are the
+    // mean of those of nodes i and i+1 (beta^2 = V_E^2 - |V_u|^2, u = V_u/beta,
+    // W = -V_E/beta, ln rho = V_1 - G/(G-1) - ln(beta)/(G-1) - beta, p = rho/beta)
+    double Vb[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) Vb[c] = 0.5 * (TV[2][c] + TV[3][c]);
+    double vu2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) vu2 += Vb[1 + a] * Vb[1 + a];
+    const double beta_f = sqrt(Vb[M - 1] * Vb[M - 1] - vu2);
+    const double ib = 1.0 / beta_f;
+    const double W = -Vb[M - 1] * ib;
+    const double rho = exp(Vb[0] - c0 - log(beta_f) * c1 - beta_f);
+    const double p = rho * ib;
+    const double iW = 1.0 / W;
+    double v[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) v[k] = Vb[1 + k] * ib * iW;
+    double v2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) v2 += v[k] * v[k];
+    const double vn = v[0];
+    const double h = 1.0 + G / (G - 1.0) * p / rho;
+    const double cs2 = G * p / (rho * h);
+    const double cs = sqrt(cs2);
+    const double disc = sqrt((1.0 - v2) * (1.0 - v2 * cs2 - vn * vn * (1.0 - cs2)));
+    const double iden = 1.0 / (1.0 - v2 * cs2);
+    const double lam_m = (vn * (1.0 - cs2) - cs * disc) * iden;
+    const double lam_p = (vn * (1.0 - cs2) + cs * disc) * iden;
+    const double lhat = fmax(fabs(at + L * lam_m), fmax(fabs(at + L * vn), fabs(at + L * lam_p)));
+
     double dd[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) dd[c] = 0.0;
+    // rounding scale of the projections r . T V at nodes i and i+1
+    double tv2 = 0.0, tv3 = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
+    const double tvmax = tv2 + tv3;
 
     // one column r of R: project, reconstruct, switch, accumulate
     auto column = [&](const double* r) {
@@ -304,10 +310,10 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
         const double jw = vp - vm;
         const double jp = vt[3] - vt[2];
         // a jump within rounding of zero counts as zero (Y = 0)
-        double sc = 0.0;
+        double r1 = 0.0;
 #pragma unroll
-        for (int c = 0; c < M; ++c) sc += fabs(r[c]) * (fabs(TV[2][c]) + fabs(TV[3][c]));
-        if (jw * jp > 0.0 && fabs(jp) > Y_TOL * sc) {
+        for (int c = 0; c < M; ++c) r1 += fabs(r[c]);
+        if (jw * jp > 0.0 && fabs(jp) > Y_TOL * r1 * tvmax) {
 #pragma unroll
             for (int c = 0; c < M; ++c) dd[c] += jw * r[c];
         }

@@ -2,7 +2,7 @@
 //
 // The device arithmetic of es_rhd.h (two-point EC flux and face dissipation)
 // is compiled for the host with an op-counting scalar in place of double and
-// executed on representative node states; each + - * /, sqrt, log, fabs,
+// executed on representative node states; each + - * /, sqrt, log, exp, fabs,
 // fmax/fmin counts one operation and fma counts two.  Per node and direction
 // the residual evaluates one state preparation, three two-point fluxes, one
 // face dissipation and the flux-difference accumulation; these are summed
@@ -36,9 +36,11 @@ inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
 inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
 inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
 inline bool operator>=(Cnt a, Cnt b) { return a.v >= b.v; }
+inline bool operator==(Cnt a, Cnt b) { return a.v == b.v; }
 inline Cnt fma(Cnt a, Cnt b, Cnt c) { Cnt::ops += 2; return Cnt(std::fma(a.v, b.v, c.v)); }
 inline Cnt sqrt(Cnt a) { ++Cnt::ops; return Cnt(std::sqrt(a.v)); }
 inline Cnt log(Cnt a) { ++Cnt::ops; return Cnt(std::log(a.v)); }
+inline Cnt exp(Cnt a) { ++Cnt::ops; return Cnt(std::exp(a.v)); }
 inline Cnt fabs(Cnt a) { ++Cnt::ops; return Cnt(std::fabs(a.v)); }
 inline Cnt fmax(Cnt a, Cnt b) { ++Cnt::ops; return Cnt(std::fmax(a.v, b.v)); }
 inline Cnt fmin(Cnt a, Cnt b) { ++Cnt::ops; return Cnt(std::fmin(a.v, b.v)); }
@@ -49,6 +51,7 @@ using cnt::Cnt;
 using cnt::fma;
 using cnt::sqrt;
 using cnt::log;
+using cnt::exp;
 using cnt::fabs;
 using cnt::fmax;
 using cnt::fmin;

@@ -220,16 +220,16 @@ def rmhd_rotor(n: int = 512, steps: int = 200) -> Workload:
                     Monitor(enabled=0), _prim(rho, v, p, B), x, steps=steps)
 
 
-def blast3d(n: int = 128, seed: int = 0, steps: int = 100) -> Workload:
+def blast3d(n: int = 128, seed: int = 0, steps: int = 100, p_in: float = 1000.0) -> Workload:
     """3D RHD blast wave on [0,1]^3, outflow, adaptive mesh (paper monitor on
     sigma = rho, alpha = 800, 5 sweeps), CFL 0.3: sphere r < 0.1 about the centre
-    with p = 1000, p = 1 outside, rho = 1 + U[-0.01, 0.01] iid noise."""
+    with p = p_in (1000), p = 1 outside, rho = 1 + U[-0.01, 0.01] iid noise."""
     g = make_grid(3, (n, n, n), (OUTFLOW, OUTFLOW, OUTFLOW))
     x = uniform_mesh(g)
     rng = np.random.default_rng(seed)
     rho = 1.0 + rng.uniform(-0.01, 0.01, size=g.shape)
     r = np.sqrt((x[0] - 0.5) ** 2 + (x[1] - 0.5) ** 2 + (x[2] - 0.5) ** 2)
-    p = np.where(r < 0.1, 1000.0, 1.0)
+    p = np.where(r < 0.1, p_in, 1.0)
     v = np.zeros((3,) + g.shape)
     B = np.zeros((3,) + g.shape)
     return Workload("rhd3d_blast_%d" % n, g, Scheme(phys=RHD, cfl=0.3),

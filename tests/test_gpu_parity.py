@@ -16,11 +16,14 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 GRIDS_2D = [((130, 70, 1), (0, 0, 0)), ((64, 123, 1), (1, 1, 0)), ((75, 66, 1), (0, 1, 0)),
             ((8, 9, 1), (1, 0, 0))]
+GRIDS_3D = [((70, 9, 8), (0, 0, 0)), ((10, 66, 9), (1, 1, 1)), ((9, 8, 64), (0, 1, 1)),
+            ((7, 7, 7), (1, 1, 1))]
+GRIDS = [(2,) + g for g in GRIDS_2D] + [(3,) + g for g in GRIDS_3D]
 
 
-@pytest.mark.parametrize("n,bc", GRIDS_2D)
-def test_metrics_and_jacobian(n, bc):
-    case = Case(2, n, bc, seed=1)
+@pytest.mark.parametrize("dim,n,bc", GRIDS)
+def test_metrics_and_jacobian(dim, n, bc):
+    case = Case(dim, n, bc, seed=1)
     c = case.ctx
     met = empty(c.nmet, *c.padded_shape())
     J0 = empty(*c.shape())
@@ -33,9 +36,9 @@ def test_metrics_and_jacobian(n, bc):
     assert np.max(np.abs(host(J0) - Jw)) <= 1e-13 * np.max(np.abs(Jw))
 
 
-@pytest.mark.parametrize("n,bc", GRIDS_2D)
-def test_prim2con_and_con2prim(n, bc):
-    case = Case(2, n, bc, seed=2, vmax=0.99, rho_rng=(0.01, 1.0), p_rng=(0.01, 1.0))
+@pytest.mark.parametrize("dim,n,bc", GRIDS)
+def test_prim2con_and_con2prim(dim, n, bc):
+    case = Case(dim, n, bc, seed=2, vmax=0.99, rho_rng=(0.01, 1.0), p_rng=(0.01, 1.0))
     c = case.ctx
     U, J = case.gpu_state()
     Uo, Jo = case.oracle_state()
@@ -45,7 +48,7 @@ def test_prim2con_and_con2prim(n, bc):
     Po, ok = st.prim_from_cons(case.grid, case.scheme, Uo, Jo)
     assert ok.all()
     Ppad = st.pad_solution(case.grid, Po)
-    want = np.concatenate([Ppad[ph.comps(ph.RHD, 2)], np.log(Ppad[0])[None],
+    want = np.concatenate([Ppad[ph.comps(ph.RHD, dim)], np.log(Ppad[0])[None],
                            np.log(Ppad[0] / Ppad[4])[None]])
     got = host(prim)
     assert np.all(rel_inf(got, want) <= 1e-12), rel_inf(got, want)
@@ -69,10 +72,10 @@ def test_con2prim_reports_inadmissible_node():
     assert c.status()[0] == es.ES_OK       # cleared after reporting
 
 
-@pytest.mark.parametrize("n,bc", GRIDS_2D)
+@pytest.mark.parametrize("dim,n,bc", GRIDS)
 @pytest.mark.parametrize("diss", [0, 1])
-def test_residual(n, bc, diss):
-    case = Case(2, n, bc, seed=4 + diss, dissipation=diss)
+def test_residual(dim, n, bc, diss):
+    case = Case(dim, n, bc, seed=4 + diss, dissipation=diss)
     c = case.ctx
     U, J = case.gpu_state()
     prim = empty(c.nprim, *c.padded_shape())
@@ -91,9 +94,9 @@ def test_residual(n, bc, diss):
     assert rel_inf(host(dJ)[None], dJo[None])[0] <= TOL
 
 
-@pytest.mark.parametrize("n,bc", GRIDS_2D[:3])
-def test_cfl_time_step(n, bc):
-    case = Case(2, n, bc, seed=6, vmax=0.99)
+@pytest.mark.parametrize("dim,n,bc", GRIDS[:3] + GRIDS[4:7])
+def test_cfl_time_step(dim, n, bc):
+    case = Case(dim, n, bc, seed=6, vmax=0.99)
     c = case.ctx
     U, J = case.gpu_state()
     prim = empty(c.nprim, *c.padded_shape())
@@ -108,20 +111,23 @@ def test_cfl_time_step(n, bc):
     assert abs(host(dt)[0] - want) <= 1e-13 * want
 
 
-@pytest.mark.parametrize("n,bc,form,sigma", [((130, 70, 1), (0, 0, 0), 1, 0),
-                                             ((64, 123, 1), (1, 1, 0), 0, 1),
-                                             ((75, 66, 1), (0, 1, 0), 0, 0)])
-def test_mesh_redistribution(n, bc, form, sigma):
+@pytest.mark.parametrize("dim,n,bc,form,sigma", [(2, (130, 70, 1), (0, 0, 0), 1, 0),
+                                                 (2, (64, 123, 1), (1, 1, 0), 0, 1),
+                                                 (2, (75, 66, 1), (0, 1, 0), 0, 0),
+                                                 (3, (70, 9, 8), (0, 0, 0), 0, 0),
+                                                 (3, (10, 66, 9), (1, 1, 1), 0, 1),
+                                                 (3, (9, 8, 64), (0, 1, 1), 1, 0)])
+def test_mesh_redistribution(dim, n, bc, form, sigma):
     mon = wl.Monitor(enabled=1, sigma=sigma, form=form, alpha=10.0 if form else 1200.0,
                      filter_passes=3, sweeps=10)
-    case = Case(2, n, bc, seed=7, smooth=True, monitor=mon)
+    case = Case(dim, n, bc, seed=7, smooth=True, monitor=mon)
     c = case.ctx
     U, J = case.gpu_state()
     prim = empty(c.nprim, *c.padded_shape())
     c.con2prim(U, J, prim)
     dt = dev(np.array([1e-3]))
-    xn = empty(2, *c.shape())
-    xd = empty(2, *c.shape())
+    xn = empty(dim, *c.shape())
+    xd = empty(dim, *c.shape())
     dtau = empty(1)
     c.mesh_redistribute(prim, dev(case.x), dt, xn, xd, dtau)
     Uo, Jo = case.oracle_state()
@@ -184,10 +190,18 @@ def test_quadrant_riemann_multi_step_growth():
     assert np.max(np.abs(x - xo)) <= 1e-10
 
 
-def test_quadrant_seed0_inadmissible_on_both_paths():
-    # the ES scheme has no positivity limiter: the seed-0 states leave the admissible
+def test_rk3_step_blast3d_adaptive():
+    w = wl.blast3d(n=18, seed=0)
+    (U, J, x, xd), (Uo, Jo, xo, xdo) = _run_steps(w, 1)
+    assert np.all(rel_inf(U, Uo) <= TOL), rel_inf(U, Uo)
+    assert rel_inf(J[None], Jo[None])[0] <= TOL
+    assert np.max(np.abs(x - xo)) <= 1e-13
+
+
+def test_quadrant_seed18_inadmissible_on_both_paths():
+    # the ES scheme has no positivity limiter: the seed-18 states leave the admissible
     # set in the first step; both paths must report it rather than continue silently
-    w = wl.quadrant_riemann(n=70, seed=0)
+    w = wl.quadrant_riemann(n=40, seed=18)
     g = w.grid
     ctx = es.Context(g, w.scheme, w.monitor)
     P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])

@@ -64,6 +64,31 @@ def test_scaled_eigenvectors_definition(phys, dim):
 
 
 @pytest.mark.parametrize("phys,dim", CASES)
+def test_scaled_eigenvectors_near_rest(phys, dim):
+    # States at rest up to rounding: velocity components of order 1e-18 (and exact
+    # zeros) put entries of order 1e-50 beside entries of order one in dF/dU; the
+    # eigen-structure must still satisfy its definition there.
+    rng = np.random.default_rng(11 + phys + dim)
+    Pr = rand_P(60, rng, phys, dim, vmax=0.5, lo=0.2)
+    tiny = rng.normal(size=(3, Pr.shape[1])) * 1e-18
+    tiny[:, ::3] = 0.0
+    tiny[1:, 1::3] = 0.0
+    Pr[1:4] = tiny
+    if dim == 2:
+        Pr[3] = 0.0
+    Pr[3, ::5] = -5.6e-3 if dim == 3 else 0.0
+    lam, R = ds.eigensystem(Pr, G, phys, dim)
+    A0, S = _A0_and_S(Pr, phys, dim)
+    RRt = np.einsum("nab,ncb->nac", R, R)
+    rel = np.max(np.abs(RRt - A0), axis=(1, 2)) / np.max(np.abs(A0), axis=(1, 2))
+    assert np.max(rel) < 1e-10
+    A = np.einsum("nab,nbc->nac", S, np.linalg.inv(A0))
+    AR = np.einsum("nab,nbc->nac", A, R)
+    rel = np.max(np.abs(AR - R * lam[:, None, :]), axis=(1, 2)) / np.max(np.abs(R), axis=(1, 2))
+    assert np.max(rel) < 1e-8
+
+
+@pytest.mark.parametrize("phys,dim", CASES)
 def test_cluster_basis_is_canonical(phys, dim):
     # seeds in order; each later cluster column carries no component of an earlier seed:
     # r_q^T A0^{-1} e_{s_j} = 0 for j < q (so the basis does not depend on how the
