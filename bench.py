@@ -32,11 +32,19 @@ PEAK_HBM = 8.0e12                # B/s
 # directions of the 2D RHD ES scheme, p = 3): counted by executing the device
 # arithmetic of the two-point flux and of the face dissipation with an
 # op-counting scalar (paper_2107_12027_amd/csrc/opcount.cpp, run by
-# `python -m paper_2107_12027_amd.build --opcount`): + - * / sqrt log fabs
+# `python -m paper_2107_12027_amd.build --opcount`): + - * / sqrt log exp fabs
 # fmax count 1, fma counts 2.  Per node and direction: 3 two-point fluxes
-# (92.4 each), 1 face dissipation (1559.2), state preparation (6) and the
-# flux-difference accumulation (66): 1908.3; two directions: 3816.7.
-RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3816.7
+# (102.3 each), 1 face dissipation (1490.7), state preparation (6) and the
+# flux-difference accumulation (66): 1869.7; two directions: 3739.5.
+RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3739.5
+
+# HBM bytes of one es_residual call on the 400 x 400 quadrant workload, from the
+# FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run) of
+# k_residual_rhd and k_sum_dirs, scaled by what the same counters read for a
+# 1 GiB device copy (FETCH x 2.000, WRITE x 1.000); the summary with its commands
+# is profiles/es_residual_hbm_counters_rhd2d_quadrant_400.txt.  Valid for the
+# kernels as they were measured; None for other workloads.
+RESIDUAL_TRAFFIC_BYTES_QUADRANT_400 = 57.74e6
 
 
 def parse():
@@ -48,6 +56,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--residual-reps", type=int, default=50)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the timed work, copy one buffer of this size once (a plain copy "
+                         "kernel of known traffic, for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -131,11 +142,21 @@ def main():
     torch.cuda.synchronize()
     res_ms = r0.elapsed_time(r1) / args.residual_reps
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     nodes = g.nnodes
     value = nodes * args.steps / (t_ms * 1e-3)
     flops = RESIDUAL_FLOPS_PER_NODE_2D_RHD
+    traffic = RESIDUAL_TRAFFIC_BYTES_QUADRANT_400 if (args.n, args.seed) == (400, 2) else None
     roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
-            "frac": None, "traffic": None, "kernel": "es_residual (k_residual_rhd x- and y-sweep)",
+            "frac": None, "traffic": traffic, "traffic_unit": "HBM bytes per es_residual call", "kernel": "es_residual (k_residual_rhd, both sweeps in one launch, + k_sum_dirs)",
             "avg_launch_ms": res_ms}
     if flops is not None:
         ach = flops * nodes / (res_ms * 1e-3)

@@ -107,8 +107,7 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = alloc(&c->prim, P * c->nprim);
     if (e == hipSuccess) e = alloc(&c->met, P * c->nmet);
-    if (e == hipSuccess) e = alloc(&c->L, N * c->m);
-    if (e == hipSuccess) e = alloc(&c->LJ, N);
+    if (e == hipSuccess) e = alloc(&c->L, N * (c->m + 1) * d);
     if (e == hipSuccess) e = alloc(&c->Us, N * c->m);
     if (e == hipSuccess) e = alloc(&c->Js, N);
     if (e == hipSuccess) e = alloc(&c->xnew, N * d);
@@ -144,7 +143,7 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
 
 es_status es_destroy(es_ctx* c) {
     if (c == nullptr) return ES_EINVAL;
-    void* bufs[] = {c->prim, c->met, c->L, c->LJ, c->Us, c->Js, c->xnew, c->xa, c->xb,
+    void* bufs[] = {c->prim, c->met, c->L, c->Us, c->Js, c->xnew, c->xa, c->xb,
                     c->wa, c->wb, c->xe, c->ve, c->pi, c->red, c->scal, c->fail};
     if (c->gexec != nullptr) (void)hipGraphExecDestroy(c->gexec);
     if (c->ev_in != nullptr) (void)hipEventDestroy(c->ev_in);
@@ -217,8 +216,8 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
     for (int st = 0; st < 3; ++st) {
         if (st > 0) ES_TRY(es::launch_con2prim(c, c->Us, c->Js, c->prim, 1, s));
         ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s));
-        ES_TRY(es::launch_residual(c, c->prim, c->met, c->L, c->LJ, s));
-        ES_TRY(es::launch_rk_combine(c, st, U, J, c->Us, c->Js, c->L, c->LJ, dt_dev, s));
+        ES_TRY(es::launch_residual_dirs(c, c->prim, c->met, c->L, s));
+        ES_TRY(es::launch_rk_combine(c, st, U, J, c->Us, c->Js, c->L, dt_dev, s));
     }
     ES_TRY(es::launch_copy(x, c->xnew, c->g.nodes * c->g.dim, s));
     return ES_OK;

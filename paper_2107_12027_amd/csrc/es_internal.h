@@ -18,8 +18,7 @@ struct es_ctx {
     // workspace (device)
     double* prim;   // padded, nprim comps
     double* met;    // padded, nmet comps
-    double* L;      // interior, m comps (stage residual)
-    double* LJ;     // interior
+    double* L;      // interior, d slabs of m + 1 comps (stage residual by direction, J last)
     double* Us;     // interior, m comps (stage state)
     double* Js;     // interior
     double* xnew;   // interior, d comps
@@ -57,6 +56,10 @@ int reduction_blocks(const GridDev& g);
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
                           hipStream_t s);
+// residual by direction: slab k of Ld (dim slabs of m + 1 components) holds direction k's part
+hipError_t launch_residual_dirs(const es_ctx* c, const double* prim, const double* met, double* Ld,
+                                hipStream_t s);
+// dU, dJ = sum over directions (through the context's slabs)
 hipError_t launch_residual(const es_ctx* c, const double* prim, const double* met, double* dU,
                            double* dJ, hipStream_t s);
 hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, const double* J,
@@ -66,8 +69,8 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
 hipError_t launch_zero_mesh_velocity(const es_ctx* c, const double* x, double* x_new, double* xdot,
                                      hipStream_t s);
 hipError_t launch_rk_combine(const es_ctx* c, int stage, const double* U0, const double* J0,
-                             double* Us, double* Js, const double* L, const double* LJ,
-                             const double* dt_dev, hipStream_t s);
+                             double* Us, double* Js, const double* Ld, const double* dt_dev,
+                             hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, long long n, hipStream_t s);
 hipError_t launch_diagnostics(const es_ctx* c, const double* prim, const double* U,
                               const double* J, const double* dU, const double* dJ, double* out,

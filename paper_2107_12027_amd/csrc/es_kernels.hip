@@ -305,29 +305,49 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
 }
 
 // ---------------------------------------------------------------------------
-// residual: one direction sweep
+// residual: all direction sweeps in one launch
 // ---------------------------------------------------------------------------
 constexpr int SEG = 61;            // interior nodes per line segment
 constexpr int NLOAD = SEG + 6;     // loaded slots (3-node halo each side)
 constexpr int LINES = 4;           // line segments (wavefronts) per block
 
-template <int DIM, int DIR, bool ES, bool ACC>
-__global__ void __launch_bounds__(256) k_residual_rhd(GridDev g, double G, double eps,
-                                                      const double* __restrict__ prim,
-                                                      const double* __restrict__ met,
-                                                      double* __restrict__ dU,
-                                                      double* __restrict__ dJ, int nseg,
-                                                      long long nlines) {
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8), each
+// with its own L2.  The logical block index gives every XCD one contiguous range
+// of logical blocks, so neighbouring lines, whose halos and cache lines overlap,
+// are read through the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, k = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + k;
+}
+
+template <int DIM>
+struct ResidualLDS {
+    static constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1, NF = 6 + NU + NA;
+    double sd[LINES][NF][NLOAD + 1];
+    double sp[LINES][3][M + 1][64];
+};
+
+// One wavefront per line segment along DIR: loads the segment with its halo into
+// LDS, evaluates the three two-point fluxes owned by each node, the face
+// dissipation and the flux differences, and writes this direction's part of the
+// residual (m components and J) to out.
+template <int DIM, int DIR, bool ES>
+__device__ __forceinline__ void residual_segment(const GridDev& g, double G, double eps,
+                                                 const double* __restrict__ prim,
+                                                 const double* __restrict__ met,
+                                                 double* __restrict__ out, int blk, int nseg,
+                                                 long long nlines, ResidualLDS<DIM>& lds) {
     constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1;
     constexpr int F_RHO = 0, F_P = 1, F_BETA = 2, F_W = 3, F_LR = 4, F_LB = 5, F_U = 6,
-                  F_A = 6 + NU, NF = 6 + NU + NA;
-    __shared__ double sd[LINES][NF][NLOAD + 1];
-    __shared__ double sp[LINES][3][M + 1][64];
+                  F_A = 6 + NU;
+    auto& sd = lds.sd;
+    auto& sp = lds.sp;
 
     const int lane = threadIdx.x & 63;
     const int line = threadIdx.x >> 6;
-    const int seg = blockIdx.x % nseg;
-    const long long lid = (long long)(blockIdx.x / nseg) * LINES + line;
+    const int seg = blk % nseg;
+    const long long lid = (long long)(blk / nseg) * LINES + line;
     const bool active = lid < nlines;
     const int nAlong = g.n[DIR];
     const int s0 = seg * SEG;
@@ -461,11 +481,51 @@ __global__ void __launch_bounds__(256) k_residual_rhd(GridDev g, double G, doubl
     if (owner) {
         const long long o = ibase + (long long)s_own * istride;
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            if (ACC) dU[c * N + o] += R[c]; else dU[c * N + o] = R[c];
-        }
-        if (ACC) dJ[o] += R[M]; else dJ[o] = R[M];
+        for (int c = 0; c <= M; ++c) out[c * N + o] = R[c];
     }
+}
+
+// Residual of all directions: logical blocks [0, nb0) sweep x, [nb0, nb0 + nb1)
+// sweep y, the rest z; direction k writes slab k of Ld (m + 1 components each).
+struct SweepPlan {
+    int nseg[3];          // line segments per line
+    int nblk[3];          // blocks of the sweep
+    long long nlines[3];  // lines of the sweep
+};
+
+template <int DIM, bool ES>
+__global__ void __launch_bounds__(256) k_residual_rhd(GridDev g, double G, double eps,
+                                                      const double* __restrict__ prim,
+                                                      const double* __restrict__ met,
+                                                      double* __restrict__ Ld, SweepPlan sw) {
+    constexpr int M = DIM + 2;
+    __shared__ ResidualLDS<DIM> lds;
+    const long long slab = (long long)(M + 1) * g.nodes;
+    int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    if (b < sw.nblk[0]) {
+        residual_segment<DIM, 0, ES>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
+        return;
+    }
+    b -= sw.nblk[0];
+    if (DIM == 2 || b < sw.nblk[1]) {
+        residual_segment<DIM, 1, ES>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
+        return;
+    }
+    b -= sw.nblk[1];
+    if (DIM == 3)
+        residual_segment<DIM, 2, ES>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
+}
+
+// dU = sum_k Ld_k (components 0..m-1), dJ = sum_k Ld_k (component m), summed in
+// direction order.
+__global__ void k_sum_dirs(long long N, int M, int dim, const double* __restrict__ Ld,
+                           double* __restrict__ dU, double* __restrict__ dJ) {
+    const long long t = gtid();
+    if (t >= N * (M + 1)) return;
+    const long long slab = (long long)(M + 1) * N;
+    double v = Ld[t] + Ld[slab + t];
+    if (dim == 3) v += Ld[2 * slab + t];
+    if (t < N * M) dU[t] = v; else dJ[t - N * M] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -726,21 +786,27 @@ __global__ void k_zero_mesh_velocity(long long n, const double* __restrict__ x, 
 // ---------------------------------------------------------------------------
 // out may alias U0 (last stage writes the new state in place), so no __restrict__.
 // Threads [0, nU) combine Ucurv, threads [nU, nU + nJ) combine J.
-__global__ void k_rk_combine(long long nU, long long nJ, int stage, const double* U0, const double* Us,
-                             const double* __restrict__ L, const double* J0, const double* Js,
-                             const double* __restrict__ LJ, const double* __restrict__ dt_dev,
+// Shu-Osher SSP-RK3 stage combination of U (nU = m N values) and J (nJ = N) with
+// the residual L = sum_k Ld_k summed from the direction slabs in direction order
+// (slab k holds the m components followed by J, so U value t and J value t map
+// to Ld index t and nU + t).
+__global__ void k_rk_combine(long long nU, long long nJ, int dim, int stage, const double* U0,
+                             const double* Us, const double* J0, const double* Js,
+                             const double* __restrict__ Ld, const double* __restrict__ dt_dev,
                              double* outU, double* outJ) {
     long long t = gtid();
     if (t >= nU + nJ) return;
+    const long long slab = nU + nJ;
+    double l = Ld[t] + Ld[slab + t];
+    if (dim == 3) l += Ld[2 * slab + t];
     const double* a = U0;
     const double* b = Us;
-    const double* l = L;
     double* o = outU;
-    if (t >= nU) { t -= nU; a = J0; b = Js; l = LJ; o = outJ; }
+    if (t >= nU) { t -= nU; a = J0; b = Js; o = outJ; }
     const double dt = dt_dev[0];
-    if (stage == 0) o[t] = a[t] + dt * l[t];
-    else if (stage == 1) o[t] = 0.75 * a[t] + 0.25 * (b[t] + dt * l[t]);
-    else o[t] = a[t] / 3.0 + 2.0 / 3.0 * (b[t] + dt * l[t]);
+    if (stage == 0) o[t] = a[t] + dt * l;
+    else if (stage == 1) o[t] = 0.75 * a[t] + 0.25 * (b[t] + dt * l);
+    else o[t] = a[t] / 3.0 + 2.0 / 3.0 * (b[t] + dt * l);
 }
 
 // ---------------------------------------------------------------------------
@@ -871,38 +937,41 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
     return hipGetLastError();
 }
 
-template <int DIM, int DIR>
-static void residual_dir(const es_ctx* c, const double* prim, const double* met, double* dU,
-                         double* dJ, bool acc, hipStream_t s) {
+template <int DIM>
+static void residual_all(const es_ctx* c, const double* prim, const double* met, double* Ld,
+                         hipStream_t s) {
     const GridDev& g = c->g;
-    const int nAlong = g.n[DIR];
-    const int nseg = (nAlong + SEG - 1) / SEG;
-    long long nlines = 1;
-    for (int a = 0; a < DIM; ++a)
-        if (a != DIR) nlines *= g.n[a];
-    const long long ngroups = (nlines + LINES - 1) / LINES;
-    const unsigned nb = (unsigned)(ngroups * nseg);
-    const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
-    const bool es_ = c->scheme.dissipation != 0;
-    if (es_) {
-        if (acc) k_residual_rhd<DIM, DIR, true, true><<<nb, 256, 0, s>>>(g, G, eps, prim, met, dU, dJ, nseg, nlines);
-        else k_residual_rhd<DIM, DIR, true, false><<<nb, 256, 0, s>>>(g, G, eps, prim, met, dU, dJ, nseg, nlines);
-    } else {
-        if (acc) k_residual_rhd<DIM, DIR, false, true><<<nb, 256, 0, s>>>(g, G, eps, prim, met, dU, dJ, nseg, nlines);
-        else k_residual_rhd<DIM, DIR, false, false><<<nb, 256, 0, s>>>(g, G, eps, prim, met, dU, dJ, nseg, nlines);
+    SweepPlan sw{};
+    long long nb = 0;
+    for (int d = 0; d < DIM; ++d) {
+        sw.nseg[d] = (g.n[d] + SEG - 1) / SEG;
+        long long nl = 1;
+        for (int a = 0; a < DIM; ++a)
+            if (a != d) nl *= g.n[a];
+        sw.nlines[d] = nl;
+        sw.nblk[d] = (int)(((nl + LINES - 1) / LINES) * sw.nseg[d]);
+        nb += sw.nblk[d];
     }
+    const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
+    if (c->scheme.dissipation != 0)
+        k_residual_rhd<DIM, true><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else
+        k_residual_rhd<DIM, false><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+}
+
+hipError_t launch_residual_dirs(const es_ctx* c, const double* prim, const double* met, double* Ld,
+                                hipStream_t s) {
+    if (c->g.dim == 2) residual_all<2>(c, prim, met, Ld, s);
+    else residual_all<3>(c, prim, met, Ld, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_residual(const es_ctx* c, const double* prim, const double* met, double* dU,
                            double* dJ, hipStream_t s) {
-    if (c->g.dim == 2) {
-        residual_dir<2, 0>(c, prim, met, dU, dJ, false, s);
-        residual_dir<2, 1>(c, prim, met, dU, dJ, true, s);
-    } else {
-        residual_dir<3, 0>(c, prim, met, dU, dJ, false, s);
-        residual_dir<3, 1>(c, prim, met, dU, dJ, true, s);
-        residual_dir<3, 2>(c, prim, met, dU, dJ, true, s);
-    }
+    hipError_t e = launch_residual_dirs(c, prim, met, c->L, s);
+    if (e != hipSuccess) return e;
+    const long long n = c->g.nodes * (c->m + 1);
+    k_sum_dirs<<<grid_for(n), TPB, 0, s>>>(c->g.nodes, c->m, c->g.dim, c->L, dU, dJ);
     return hipGetLastError();
 }
 
@@ -965,14 +1034,15 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
 }
 
 hipError_t launch_rk_combine(const es_ctx* c, int stage, const double* U0, const double* J0,
-                             double* Us, double* Js, const double* L, const double* LJ,
-                             const double* dt_dev, hipStream_t s) {
+                             double* Us, double* Js, const double* Ld, const double* dt_dev,
+                             hipStream_t s) {
     const long long nU = c->g.nodes * c->m;
     const long long nJ = c->g.nodes;
     // stage 2 writes the new state over U0/J0 (the caller passes them as outputs)
     double* outU = stage == 2 ? const_cast<double*>(U0) : Us;
     double* outJ = stage == 2 ? const_cast<double*>(J0) : Js;
-    k_rk_combine<<<grid_for(nU + nJ), TPB, 0, s>>>(nU, nJ, stage, U0, Us, L, J0, Js, LJ, dt_dev, outU, outJ);
+    k_rk_combine<<<grid_for(nU + nJ), TPB, 0, s>>>(nU, nJ, c->g.dim, stage, U0, Us, J0, Js, Ld, dt_dev,
+                                                   outU, outJ);
     return hipGetLastError();
 }
 

@@ -9,15 +9,32 @@ namespace es {
 
 constexpr double Y_TOL = 1e-10;
 
+// Reciprocal of a finite, nonzero, normal x: the hardware estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - x r), each of which squares the relative
+// error, so the result is within about one ulp of 1/x.  Zero, infinities and
+// denormals are not handled (NaN propagates); the callers pass state quantities.
+__device__ __forceinline__ double frcp(double x) {
+#ifdef ES_OPCOUNT_HOST
+    return 1.0 / x;
+#else
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+#endif
+}
+
 // Logarithmic mean [a]/[ln a] (cited in Section 3.1 to Ismail & Roe) from the
 // values and their precomputed logarithms.  With f = (al - ar)/(al + ar) and
 // u = f^2: for u < 1e-2 the ratio ln(al/ar)/(2f) is replaced by its series
 // sum_{k=0}^{7} u^k/(2k+1) (truncation below 1e-17); otherwise [a]/[ln a].
 __device__ __forceinline__ double log_mean(double al, double ar, double lnal, double lnar) {
     const double s = al + ar;
-    const double f = (al - ar) / s;
-    const double u = f * f;
-    if (u < 1e-2) {
+    const double dif = al - ar;
+    if (dif * dif < 1e-2 * (s * s)) {
+        const double f = dif * frcp(s);
+        const double u = f * f;
         double F = 1.0 / 15.0;
         F = fma(F, u, 1.0 / 13.0);
         F = fma(F, u, 1.0 / 11.0);
@@ -26,9 +43,9 @@ __device__ __forceinline__ double log_mean(double al, double ar, double lnal, do
         F = fma(F, u, 1.0 / 5.0);
         F = fma(F, u, 1.0 / 3.0);
         F = fma(F, u, 1.0);
-        return s / (2.0 * F);
+        return 0.5 * s * frcp(F);
     }
-    return (al - ar) / (lnal - lnar);
+    return dif * frcp(lnal - lnar);
 }
 
 template <int NU>
@@ -65,14 +82,14 @@ __device__ __forceinline__ void pair_flux_rhd(double G, const NodeRHD<NU>& l, co
         uu += um[k] * um[k];
         un += ab[k] * um[k];
     }
-    const double a0 = 1.0 + 1.0 / ((G - 1.0) * beta_ln);
-    const double iden = 1.0 / (W_m * W_m - uu);
-    const double pb = rho_m / beta_m;
+    const double a0 = 1.0 + frcp((G - 1.0) * beta_ln);
+    const double iden = frcp(W_m * W_m - uu);
+    const double pb = rho_m * frcp(beta_m);
     const double U1 = rho_ln * W_m;
     const double U5 = (a0 * U1 * W_m + pb * uu) * iden;
     const double C = W_m * (a0 * rho_ln + pb) * iden;
     F[0] = rho_ln * (at * W_m + un);
-    const double s = (at * (U5 + pb) + C * un) / W_m;
+    const double s = (at * (U5 + pb) + C * un) * frcp(W_m);
 #pragma unroll
     for (int k = 0; k < NU; ++k) F[1 + k] = um[k] * s + ab[k] * pb;
     F[NU + 1] = at * U5 + C * un;
@@ -137,10 +154,13 @@ __device__ __forceinline__ int c2p_rhd(double G, double D, const double* m, doub
 }
 
 // WENO5-JS value at i+1/2 from point values v_{i-2..i+2} = (a, b, c, d, e).
+// The weights d_k/(eps + b_k)^2 are multiplied through by prod_k (eps + b_k)^2,
+// which leaves their ratios unchanged and needs a single reciprocal; with
+// eps = 1e-6 the products stay far inside the FP64 range.
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e, double eps) {
-    const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
-    const double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
-    const double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
+    const double q0 = 2.0 * a - 7.0 * b + 11.0 * c;      // 6 x candidate values
+    const double q1 = -b + 5.0 * c + 2.0 * d;
+    const double q2 = 2.0 * c + 5.0 * d - e;
     const double t0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
     const double t1 = b - 2.0 * c + d, s1 = b - d;
     const double t2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
@@ -148,37 +168,46 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
     const double b1 = 13.0 / 12.0 * t1 * t1 + 0.25 * s1 * s1;
     const double b2 = 13.0 / 12.0 * t2 * t2 + 0.25 * s2 * s2;
     const double e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
-    const double w0 = 0.1 / (e0 * e0);
-    const double w1 = 0.6 / (e1 * e1);
-    const double w2 = 0.3 / (e2 * e2);
-    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+    const double f0 = e0 * e0, f1 = e1 * e1, f2 = e2 * e2;
+    const double w0 = 0.1 * (f1 * f2);
+    const double w1 = 0.6 * (f0 * f2);
+    const double w2 = 0.3 * (f0 * f1);
+    return (w0 * q0 + w1 * q1 + w2 * q2) * frcp(6.0 * (w0 + w1 + w2));
 }
+
+// Face state in the rotated frame with the reciprocals the tangent map reuses.
+template <int DIM>
+struct FaceRHD {
+    double rho, irho, p, ip, beta, W, h, v[DIM];
+};
 
 // Tangent map of the primitive state P = (rho, v, p) (rotated frame, DIM velocity
 // components): dU = (dU/dP) dP and dV = (dV/dP) dP, U = (rho W, rho h W^2 v,
-// rho h W^2 - p), V = (G/(G-1) + ln rho + ln beta/(G-1) + beta, beta W v, -beta W).
+// rho h W^2 - p), V = (G/(G-1) + ln rho + ln beta/(G-1) + beta, beta W v, -beta W);
+// c0 = G/(G-1), c1 = 1/(G-1).
 template <int DIM>
-__device__ __forceinline__ void tangent_rhd(double G, double rho, const double* v, double p,
-                                            double W, double h, double drho, const double* dv,
-                                            double dp, double* dU, double* dV) {
+__device__ __forceinline__ void tangent_rhd(double c0, double c1, const FaceRHD<DIM>& f,
+                                            double drho, const double* dv, double dp, double* dU,
+                                            double* dV) {
     constexpr int M = DIM + 2;
+    const double W = f.W;
     double vdv = 0.0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) vdv += v[k] * dv[k];
+    for (int k = 0; k < DIM; ++k) vdv += f.v[k] * dv[k];
     const double dW = W * W * W * vdv;
-    const double dh = G / (G - 1.0) * (dp - p * drho / rho) / rho;
-    const double Z = rho * h * W * W;
-    const double dZ = drho * h * W * W + rho * dh * W * W + 2.0 * rho * h * W * dW;
-    dU[0] = drho * W + rho * dW;
+    const double dh = c0 * (dp - f.p * drho * f.irho) * f.irho;
+    const double W2 = W * W;
+    const double Z = f.rho * f.h * W2;
+    const double dZ = (drho * f.h + f.rho * dh) * W2 + 2.0 * f.rho * f.h * W * dW;
+    dU[0] = drho * W + f.rho * dW;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) dU[1 + k] = dZ * v[k] + Z * dv[k];
+    for (int k = 0; k < DIM; ++k) dU[1 + k] = dZ * f.v[k] + Z * dv[k];
     dU[M - 1] = dZ - dp;
-    const double beta = rho / p;
-    const double dbeta = drho / p - rho * dp / (p * p);
-    dV[0] = drho / rho + dbeta / (beta * (G - 1.0)) + dbeta;
-    const double dbW = dbeta * W + beta * dW;
+    const double dbeta = (drho - f.beta * dp) * f.ip;
+    dV[0] = drho * f.irho + dbeta * (c1 * f.p * f.irho) + dbeta;
+    const double dbW = dbeta * W + f.beta * dW;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) dV[1 + k] = dbW * v[k] + beta * W * dv[k];
+    for (int k = 0; k < DIM; ++k) dV[1 + k] = dbW * f.v[k] + f.beta * W * dv[k];
     dV[M - 1] = -dbW;
 }
 
@@ -196,7 +225,7 @@ __device__ __forceinline__ void rotation(const double* n, double T[3][3]) {
     const double rp = sqrt(n[0] * n[0] + n[1] * n[1]);
     T[0][0] = n[0]; T[0][1] = n[1]; T[0][2] = n[2];
     if (rp > 0.0) {
-        const double ir = 1.0 / rp;
+        const double ir = frcp(rp);
         T[1][0] = -n[1] * ir; T[1][1] = n[0] * ir; T[1][2] = 0.0;
         T[2][0] = -n[2] * n[0] * ir; T[2][1] = -n[2] * n[1] * ir; T[2][2] = rp;
     } else {
@@ -233,7 +262,7 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
 #pragma unroll
     for (int j = 0; j < DIM; ++j) ax[j] = 0.5 * (al[1 + j] + ar[1 + j]);
     const double L = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
-    const double iL = 1.0 / L;
+    const double iL = frcp(L);
     double nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
     double T[3][3];
     rotation<DIM>(nrm, T);
@@ -265,23 +294,30 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
 #pragma unroll
     for (int a = 0; a < DIM; ++a) vu2 += Vb[1 + a] * Vb[1 + a];
     const double beta_f = sqrt(Vb[M - 1] * Vb[M - 1] - vu2);
-    const double ib = 1.0 / beta_f;
-    const double W = -Vb[M - 1] * ib;
-    const double rho = exp(Vb[0] - c0 - log(beta_f) * c1 - beta_f);
-    const double p = rho * ib;
-    const double iW = 1.0 / W;
-    double v[DIM];
+    const double ib = frcp(beta_f);
+    FaceRHD<DIM> fs;
+    fs.beta = beta_f;
+    fs.W = -Vb[M - 1] * ib;
+    fs.rho = exp(Vb[0] - c0 - log(beta_f) * c1 - beta_f);
+    fs.irho = frcp(fs.rho);
+    fs.p = fs.rho * ib;
+    fs.ip = beta_f * fs.irho;
+    const double iVE = -frcp(Vb[M - 1]);      // 1/(beta W)
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) v[k] = Vb[1 + k] * ib * iW;
+    for (int k = 0; k < DIM; ++k) fs.v[k] = Vb[1 + k] * iVE;
+    const double rho = fs.rho, p = fs.p, W = fs.W;
+    const double* v = fs.v;
     double v2 = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) v2 += v[k] * v[k];
     const double vn = v[0];
-    const double h = 1.0 + G / (G - 1.0) * p / rho;
-    const double cs2 = G * p / (rho * h);
+    // p/rho = 1/beta, so h = 1 + c0/beta and h cs^2 = G/beta
+    const double h = 1.0 + c0 * ib;
+    fs.h = h;
+    const double cs2 = G * ib * frcp(h);
     const double cs = sqrt(cs2);
     const double disc = sqrt((1.0 - v2) * (1.0 - v2 * cs2 - vn * vn * (1.0 - cs2)));
-    const double iden = 1.0 / (1.0 - v2 * cs2);
+    const double iden = frcp(1.0 - v2 * cs2);
     const double lam_m = (vn * (1.0 - cs2) - cs * disc) * iden;
     const double lam_p = (vn * (1.0 - cs2) + cs * disc) * iden;
     const double lhat = fmax(fabs(at + L * lam_m), fmax(fabs(at + L * vn), fabs(at + L * lam_p)));
@@ -324,24 +360,27 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
     double vt2 = 0.0;
 #pragma unroll
     for (int k = 1; k < DIM; ++k) vt2 += v[k] * v[k];
+    const double i_rhW2 = frcp(rho * hW2);
+    const double i_ht = frcp(h * (1.0 + W * W * vt2));
+    const double ig = beta_f / G;                    // 1/(h cs^2)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const double lam = s == 0 ? lam_m : lam_p;
         const double q = lam - vn;
         const double dp = q;
-        const double drho = q / (h * cs2);
+        const double drho = q * ig;
         double dv[DIM];
-        dv[0] = (1.0 - vn * lam) / (rho * hW2);
-        const double dh = G / (G - 1.0) * (dp - p * drho / rho) / rho;
-        const double fac = -(dh + hW2 * vn * dv[0]) / (h * (1.0 + W * W * vt2));
+        dv[0] = (1.0 - vn * lam) * i_rhW2;
+        const double dh = c0 * (dp - p * drho * fs.irho) * fs.irho;
+        const double fac = -(dh + hW2 * vn * dv[0]) * i_ht;
 #pragma unroll
         for (int k = 1; k < DIM; ++k) dv[k] = v[k] * fac;
         double dU[M], dV[M];
-        tangent_rhd<DIM>(G, rho, v, p, W, h, drho, dv, dp, dU, dV);
+        tangent_rhd<DIM>(c0, c1, fs, drho, dv, dp, dU, dV);
         double nn = 0.0;
 #pragma unroll
         for (int c = 0; c < M; ++c) nn += dU[c] * dV[c];
-        const double sc = 1.0 / sqrt(nn);
+        const double sc = frcp(sqrt(nn));
 #pragma unroll
         for (int c = 0; c < M; ++c) dU[c] *= sc;
         column(dU);
@@ -356,7 +395,7 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
         for (int k = 0; k < DIM; ++k) dv[k] = 0.0;
         double drho = 0.0;
         if (a == 0) drho = 1.0; else dv[a] = 1.0;
-        tangent_rhd<DIM>(G, rho, v, p, W, h, drho, dv, 0.0, KU[a], KV[a]);
+        tangent_rhd<DIM>(c0, c1, fs, drho, dv, 0.0, KU[a], KV[a]);
     }
     double Gm[NC][NC];
 #pragma unroll
@@ -371,7 +410,7 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
     double Gi[NC][NC];
     if (NC == 2) {
         const double det = Gm[0][0] * Gm[1][1] - Gm[0][1] * Gm[1][0];
-        const double id = 1.0 / det;
+        const double id = frcp(det);
         Gi[0][0] = Gm[1][1] * id; Gi[1][1] = Gm[0][0] * id;
         Gi[0][1] = -Gm[0][1] * id; Gi[1][0] = -Gm[1][0] * id;
     } else {
@@ -379,7 +418,7 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
         const double c01 = Gm[1][2] * Gm[2][0] - Gm[1][0] * Gm[2][2];
         const double c02 = Gm[1][0] * Gm[2][1] - Gm[1][1] * Gm[2][0];
         const double det = Gm[0][0] * c00 + Gm[0][1] * c01 + Gm[0][2] * c02;
-        const double id = 1.0 / det;
+        const double id = frcp(det);
         Gi[0][0] = c00 * id;
         Gi[0][1] = (Gm[0][2] * Gm[2][1] - Gm[0][1] * Gm[2][2]) * id;
         Gi[0][2] = (Gm[0][1] * Gm[1][2] - Gm[0][2] * Gm[1][1]) * id;
@@ -392,7 +431,7 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
     }
     // seeds: D slot 0, transverse momentum slots 2 (and 3)
     double cf[NC][NC];     // coefficient vectors of the canonical columns
-    double nq[NC];         // their squared A0^{-1} norms
+    double inq[NC];        // reciprocals of their squared A0^{-1} norms
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
         const int seed = q == 0 ? 0 : 1 + q;
@@ -412,7 +451,7 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
             double ip = 0.0;
 #pragma unroll
             for (int a = 0; a < NC; ++a) ip += cf[r][a] * gs[a];
-            const double f = ip / nq[r];
+            const double f = ip * inq[r];
 #pragma unroll
             for (int a = 0; a < NC; ++a) cq[a] -= f * cf[r][a];
         }
@@ -423,8 +462,9 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
             for (int b = 0; b < NC; ++b) nn += cq[a] * Gm[a][b] * cq[b];
 #pragma unroll
         for (int a = 0; a < NC; ++a) cf[q][a] = cq[a];
-        nq[q] = nn;
-        const double sc = 1.0 / sqrt(nn);
+        const double rn = frcp(sqrt(nn));
+        inq[q] = rn * rn;
+        const double sc = rn;
         double r[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
