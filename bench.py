@@ -9,6 +9,11 @@ three Runge-Kutta stages of metrics + con2prim + residual + combination.
 Inputs are resident in HBM before the timed region; the time step stays on the
 device (no host synchronisation inside the timed steps).
 
+The headline value is the FP64 path.  The same workload is then timed in the
+FP32-mixed form (scheme.mixed = 1) and reported under "mixed", with the relative
+L1 error of one step from the initial data against the oracle's step for both
+forms (the oracle step is the cpu_baseline run).
+
 Prints one JSON line (see the repository contract).  ``--gpus N`` with N > 1
 exits: this build runs on one GPU.
 """
@@ -63,8 +68,8 @@ def parse():
 
 
 def cpu_baseline(n, seed):
-    """The oracle as it stands, timed on the host for one RK3 step of the same workload."""
-    import numpy as np
+    """The oracle as it stands, timed on the host for one RK3 step of the same
+    workload; also returns the oracle's state after that step."""
     from oracle import physics as ph, stepper as st
     from paper_2107_12027_amd import workloads as wl
     w = wl.quadrant_riemann(n=n, seed=seed)
@@ -74,10 +79,87 @@ def cpu_baseline(n, seed):
     out = st.rk3_step(w.grid, w.scheme, w.monitor, U, J, w.x)
     t = time.perf_counter() - t0
     if not out["ok"].all():
-        return None
-    return {"value": w.grid.nnodes / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "one SSP-RK3 step of the full %dx%d workload from its initial state "
-                      "(numpy oracle, %.1f s)" % (n, n, t)}
+        return None, None
+    return ({"value": w.grid.nnodes / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+             "sample": "one SSP-RK3 step of the full %dx%d workload from its initial state "
+                       "(numpy oracle, %.1f s)" % (n, n, t)}, out["U"])
+
+
+def l1_rel(a, b):
+    import numpy as np
+    a = np.asarray(a).reshape(a.shape[0], -1)
+    b = np.asarray(b).reshape(b.shape[0], -1)
+    return [float(v) for v in np.abs(a - b).sum(axis=1) / np.abs(b).sum(axis=1)]
+
+
+class Run:
+    """One context and its device state for the workload, from the initial data."""
+
+    def __init__(self, w, mixed):
+        import dataclasses
+        import numpy as np
+        import torch
+        from paper_2107_12027_amd import es
+        self.w = w
+        scheme = dataclasses.replace(w.scheme, mixed=mixed)
+        self.ctx = ctx = es.Context(w.grid, scheme, w.monitor)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+        P = np.concatenate([w.prim["rho"][None], w.prim["u"], w.prim["p"][None], w.prim["B"]])
+        sel = [0, 1, 2, 4]
+        self.met = torch.empty((ctx.nmet,) + ctx.padded_shape(), dtype=torch.float64, device="cuda")
+        self.prim = torch.empty((ctx.nprim,) + ctx.padded_shape(), dtype=torch.float64, device="cuda")
+        self.J = torch.empty(ctx.shape(), dtype=torch.float64, device="cuda")
+        self.x = dev(w.x)
+        ctx.metrics(self.x, None, self.met, self.J)
+        self.U = torch.empty((ctx.m,) + ctx.shape(), dtype=torch.float64, device="cuda")
+        ctx.prim2con(dev(P[sel]), self.J, self.U)
+        self.xdot = torch.empty_like(self.x)
+        self.dt = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def step(self):
+        self.ctx.rk3_step(self.U, self.J, self.x, self.xdot, self.dt)
+
+    def timed(self, steps, warmup):
+        import torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        st0 = self.ctx.status()[0]
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            self.step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        status, nfail, first = self.ctx.status()
+        if st0 != 0 or status != 0:
+            print("bench.py: con2prim failure during the run (status %d, %d nodes, first %d)"
+                  % (status, nfail, first), file=sys.stderr)
+            sys.exit(3)
+        return e0.elapsed_time(e1)
+
+    def residual_ms(self, reps):
+        """Average es_residual time on the current state (HIP events on the launch stream)."""
+        import torch
+        ctx = self.ctx
+        dU = torch.empty_like(self.U)
+        dJ = torch.empty_like(self.J)
+        ctx.con2prim(self.U, self.J, self.prim)
+        ctx.metrics(self.x, self.xdot, self.met)
+        ctx.residual(self.prim, self.met, dU, dJ)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        r0 = torch.cuda.Event(enable_timing=True)
+        r1 = torch.cuda.Event(enable_timing=True)
+        r0.record(stream)
+        for _ in range(reps):
+            ctx.residual(self.prim, self.met, dU, dJ)
+        r1.record(stream)
+        torch.cuda.synchronize()
+        return r0.elapsed_time(r1) / reps
 
 
 def main():
@@ -85,62 +167,32 @@ def main():
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
-    from paper_2107_12027_amd import es, workloads as wl
+    from paper_2107_12027_amd import workloads as wl
 
     torch.cuda.set_device(0)
     w = wl.quadrant_riemann(n=args.n, seed=args.seed)
     g = w.grid
-    ctx = es.Context(g, w.scheme, w.monitor)
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
-    sel = [0, 1, 2, 4]
-    P = np.concatenate([w.prim["rho"][None], w.prim["u"], w.prim["p"][None], w.prim["B"]])
-    met = torch.empty((ctx.nmet,) + ctx.padded_shape(), dtype=torch.float64, device="cuda")
-    prim = torch.empty((ctx.nprim,) + ctx.padded_shape(), dtype=torch.float64, device="cuda")
-    J = torch.empty(ctx.shape(), dtype=torch.float64, device="cuda")
-    x = dev(w.x)
-    ctx.metrics(x, None, met, J)
-    U = torch.empty((ctx.m,) + ctx.shape(), dtype=torch.float64, device="cuda")
-    ctx.prim2con(dev(P[sel]), J, U)
-    xdot = torch.empty_like(x)
-    dt = torch.empty(1, dtype=torch.float64, device="cuda")
 
-    for _ in range(args.warmup):
-        ctx.rk3_step(U, J, x, xdot, dt)
-    torch.cuda.synchronize()
-    st0 = ctx.status()[0]
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ctx.rk3_step(U, J, x, xdot, dt)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_ms = e0.elapsed_time(e1)
-    status, nfail, first = ctx.status()
-    if st0 != es.ES_OK or status != es.ES_OK:
-        print("bench.py: con2prim failure during the run (status %d, %d nodes, first %d)"
-              % (status, nfail, first), file=sys.stderr)
-        sys.exit(3)
+    # accuracy sample: one step from the initial data on both forms (compared with
+    # the oracle's step below, outside every timed region)
+    one_step = {}
+    for mixed in (0, 1):
+        r = Run(w, mixed)
+        r.step()
+        torch.cuda.synchronize()
+        if r.ctx.status()[0] != 0:
+            print("bench.py: con2prim failure in the first step", file=sys.stderr)
+            sys.exit(3)
+        one_step[mixed] = r.U.cpu().numpy()
+        del r
 
-    # dominant kernel: the residual (two directional sweeps) on the final state
-    dU = torch.empty_like(U)
-    dJ = torch.empty_like(J)
-    ctx.con2prim(U, J, prim)
-    ctx.metrics(x, xdot, met)
-    ctx.residual(prim, met, dU, dJ)
-    torch.cuda.synchronize()
-    r0 = torch.cuda.Event(enable_timing=True)
-    r1 = torch.cuda.Event(enable_timing=True)
-    r0.record(stream)
-    for _ in range(args.residual_reps):
-        ctx.residual(prim, met, dU, dJ)
-    r1.record(stream)
-    torch.cuda.synchronize()
-    res_ms = r0.elapsed_time(r1) / args.residual_reps
+    run = Run(w, 0)
+    t_ms = run.timed(args.steps, args.warmup)
+    res_ms = run.residual_ms(args.residual_reps)
+    mrun = Run(w, 1)
+    t_mixed_ms = mrun.timed(args.steps, args.warmup)
+    res_mixed_ms = mrun.residual_ms(args.residual_reps)
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 8
@@ -156,15 +208,25 @@ def main():
     flops = RESIDUAL_FLOPS_PER_NODE_2D_RHD
     traffic = RESIDUAL_TRAFFIC_BYTES_QUADRANT_400 if (args.n, args.seed) == (400, 2) else None
     roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
-            "frac": None, "traffic": traffic, "traffic_unit": "HBM bytes per es_residual call", "kernel": "es_residual (k_residual_rhd, both sweeps in one launch, + k_sum_dirs)",
+            "frac": None, "traffic": traffic, "traffic_unit": "HBM bytes per es_residual call",
+            "kernel": "es_residual (k_residual_rhd, both sweeps in one launch, + k_sum_dirs)",
             "avg_launch_ms": res_ms}
     if flops is not None:
         ach = flops * nodes / (res_ms * 1e-3)
         roof["achieved"] = ach / 1e12
         roof["frac"] = ach / PEAK_FP64_VECTOR
     cpu = None
+    mixed = {"value": nodes * args.steps / (t_mixed_ms * 1e-3), "unit": "cell-updates/s",
+             "ms_per_step": t_mixed_ms / args.steps, "dtype": "f32 pair/dissipation, f64 elsewhere",
+             "es_residual_ms": res_mixed_ms, "speedup_vs_fp64": t_ms / t_mixed_ms,
+             "l1_rel_err_vs_oracle": None, "fp64_l1_rel_err_vs_oracle": None,
+             "err_sample": "one SSP-RK3 step of the %dx%d workload from its initial state, "
+                           "relative L1 per conserved component" % (args.n, args.n)}
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.n, args.seed)
+        cpu, Uo = cpu_baseline(args.n, args.seed)
+        if Uo is not None:
+            mixed["l1_rel_err_vs_oracle"] = l1_rel(one_step[1], Uo)
+            mixed["fp64_l1_rel_err_vs_oracle"] = l1_rel(one_step[0], Uo)
     line = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_ms / args.steps,
@@ -176,6 +238,7 @@ def main():
                    "boundary": "outflow", "precision": "FP64"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "mixed": mixed,
     }
     print(json.dumps(line))
 

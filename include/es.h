@@ -77,7 +77,12 @@ typedef struct {
     double gamma;       /* adiabatic index of the ideal EOS (eq. EOS) */
     int order_p;        /* p of the 2p-th order EC flux; this build supports p = 3 */
     int dissipation;    /* 0: entropy conservative, 1: entropy stable (WENO-(2p-1)) */
-    int mixed;          /* 0: FP64 throughout; 1: FP32 pair/WENO arithmetic, FP64 elsewhere */
+    int mixed;          /* 0: FP64 throughout.  1: FP32-mixed residual: the two-point
+                           pair algebra (except the small-jump branch of the
+                           logarithmic means) and the whole face dissipation (state,
+                           eigenvectors, WENO, switch) in FP32; metrics, their
+                           contraction with the pair algebra, the VCL, the residual
+                           accumulation, con2prim, CFL, mesh and state in FP64 */
     double weno_eps;    /* WENO-JS epsilon */
     double cfl;         /* CFL number of eq. cfl */
 } es_scheme;

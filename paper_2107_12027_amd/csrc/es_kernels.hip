@@ -332,7 +332,7 @@ struct ResidualLDS {
 // LDS, evaluates the three two-point fluxes owned by each node, the face
 // dissipation and the flux differences, and writes this direction's part of the
 // residual (m components and J) to out.
-template <int DIM, int DIR, bool ES>
+template <int DIM, int DIR, bool ES, bool MIXED>
 __device__ __forceinline__ void residual_segment(const GridDev& g, double G, double eps,
                                                  const double* __restrict__ prim,
                                                  const double* __restrict__ met,
@@ -431,7 +431,8 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 #pragma unroll
                 for (int c = 0; c < NA; ++c) ar[c] = sd[line][F_A + c][lane + n];
                 double F[M], Jt;
-                pair_flux_rhd<NU>(G, l, r, al, ar, F, Jt);
+                if (MIXED) pair_flux_rhd_mixed<NU>(G, l, r, al, ar, F, Jt);
+                else pair_flux_rhd<NU>(G, l, r, al, ar, F, Jt);
 #pragma unroll
                 for (int c = 0; c < M; ++c) sp[line][n - 1][c][lane] = F[c];
                 sp[line][n - 1][M][lane] = Jt;
@@ -460,16 +461,43 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
         __syncthreads();
         // ---- face dissipation at s+1/2 for faces s in [s0-1, s_end)
         if (active && lane >= 2 && s_own < s_end) {
-            NodeRHD<NU> st[6];
+            if (MIXED) {
+                // FP32 dissipation from FP32 copies of the stencil states and metrics
+                NodeRHD<NU, float> st[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) st[q] = node_at(lane - 2 + q);
-            double al[NA], ar[NA];
+                for (int q = 0; q < 6; ++q) {
+                    const int k = lane - 2 + q;
+                    st[q].rho = (float)sd[line][F_RHO][k];
+                    st[q].p = (float)sd[line][F_P][k];
+                    st[q].beta = (float)sd[line][F_BETA][k];
+                    st[q].W = (float)sd[line][F_W][k];
+                    st[q].lr = (float)sd[line][F_LR][k];
+                    st[q].lb = (float)sd[line][F_LB][k];
 #pragma unroll
-            for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane]; ar[c] = sd[line][F_A + c][lane + 1]; }
-            double d[M];
-            face_diss_rhd<DIM>(G, eps, st, al, ar, d);
+                    for (int c = 0; c < NU; ++c) st[q].u[c] = (float)sd[line][F_U + c][k];
+                }
+                float al[NA], ar[NA];
 #pragma unroll
-            for (int c = 0; c < M; ++c) sp[line][0][c][lane] = d[c];
+                for (int c = 0; c < NA; ++c) {
+                    al[c] = (float)sd[line][F_A + c][lane];
+                    ar[c] = (float)sd[line][F_A + c][lane + 1];
+                }
+                float d[M];
+                face_diss_rhd<DIM>((float)G, (float)eps, st, al, ar, d);
+#pragma unroll
+                for (int c = 0; c < M; ++c) sp[line][0][c][lane] = (double)d[c];
+            } else {
+                NodeRHD<NU> st[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) st[q] = node_at(lane - 2 + q);
+                double al[NA], ar[NA];
+#pragma unroll
+                for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane]; ar[c] = sd[line][F_A + c][lane + 1]; }
+                double d[M];
+                face_diss_rhd<DIM>(G, eps, st, al, ar, d);
+#pragma unroll
+                for (int c = 0; c < M; ++c) sp[line][0][c][lane] = d[c];
+            }
         }
         __syncthreads();
         if (owner) {
@@ -493,7 +521,7 @@ struct SweepPlan {
     long long nlines[3];  // lines of the sweep
 };
 
-template <int DIM, bool ES>
+template <int DIM, bool ES, bool MIXED>
 __global__ void __launch_bounds__(256) k_residual_rhd(GridDev g, double G, double eps,
                                                       const double* __restrict__ prim,
                                                       const double* __restrict__ met,
@@ -503,17 +531,17 @@ __global__ void __launch_bounds__(256) k_residual_rhd(GridDev g, double G, doubl
     const long long slab = (long long)(M + 1) * g.nodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < sw.nblk[0]) {
-        residual_segment<DIM, 0, ES>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
+        residual_segment<DIM, 0, ES, MIXED>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
         return;
     }
     b -= sw.nblk[0];
     if (DIM == 2 || b < sw.nblk[1]) {
-        residual_segment<DIM, 1, ES>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
+        residual_segment<DIM, 1, ES, MIXED>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
         return;
     }
     b -= sw.nblk[1];
     if (DIM == 3)
-        residual_segment<DIM, 2, ES>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
+        residual_segment<DIM, 2, ES, MIXED>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
 }
 
 // dU = sum_k Ld_k (components 0..m-1), dJ = sum_k Ld_k (component m), summed in
@@ -953,10 +981,15 @@ static void residual_all(const es_ctx* c, const double* prim, const double* met,
         nb += sw.nblk[d];
     }
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
-    if (c->scheme.dissipation != 0)
-        k_residual_rhd<DIM, true><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    const bool es_ = c->scheme.dissipation != 0, mixed = c->scheme.mixed != 0;
+    if (es_ && mixed)
+        k_residual_rhd<DIM, true, true><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else if (es_)
+        k_residual_rhd<DIM, true, false><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else if (mixed)
+        k_residual_rhd<DIM, false, true><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
     else
-        k_residual_rhd<DIM, false><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+        k_residual_rhd<DIM, false, false><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
 }
 
 hipError_t launch_residual_dirs(const es_ctx* c, const double* prim, const double* met, double* Ld,

@@ -7,7 +7,16 @@
 
 namespace es {
 
-constexpr double Y_TOL = 1e-10;
+// Per-precision constants of the face dissipation: the rounding level below which
+// a jump of a characteristic variable counts as zero in the sign switch Y
+// (relative to |r_l|_1 (|T V_i|_max + |T V_i+1|_max)).
+template <typename R>
+struct RealTraits;
+template <>
+struct RealTraits<double> {
+    static constexpr double ytol = 1e-10;
+    static constexpr bool wide_range = true;     // exponent range for WENO's common denominator
+};
 
 // Reciprocal of a finite, nonzero, normal x: the hardware estimate refined by two
 // Newton-Raphson steps r <- r + r (1 - x r), each of which squares the relative
@@ -29,6 +38,24 @@ __device__ __forceinline__ double frcp(double x) {
 // values and their precomputed logarithms.  With f = (al - ar)/(al + ar) and
 // u = f^2: for u < 1e-2 the ratio ln(al/ar)/(2f) is replaced by its series
 // sum_{k=0}^{7} u^k/(2k+1) (truncation below 1e-17); otherwise [a]/[ln a].
+__device__ __forceinline__ double xsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ double xexp(double x) { return exp(x); }
+__device__ __forceinline__ double xlog(double x) { return log(x); }
+
+#ifndef ES_OPCOUNT_HOST
+// FP32 arithmetic of the mixed form: the hardware reciprocal, exp2 and log2
+// (about one ulp), a correctly rounded square root.
+template <>
+struct RealTraits<float> {
+    static constexpr float ytol = 1e-6f;
+    static constexpr bool wide_range = false;
+};
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float xsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ float xexp(float x) { return __expf(x); }
+__device__ __forceinline__ float xlog(float x) { return __logf(x); }
+#endif
+
 __device__ __forceinline__ double log_mean(double al, double ar, double lnal, double lnar) {
     const double s = al + ar;
     const double dif = al - ar;
@@ -48,10 +75,10 @@ __device__ __forceinline__ double log_mean(double al, double ar, double lnal, do
     return dif * frcp(lnal - lnar);
 }
 
-template <int NU>
+template <int NU, typename R = double>
 struct NodeRHD {
-    double rho, p, beta, W, lr, lb;
-    double u[NU];
+    R rho, p, beta, W, lr, lb;
+    R u[NU];
 };
 
 // Two-point EC flux in direction k (eq. ECFluxCurv, eq. UFcircle) for RHD:
@@ -95,6 +122,75 @@ __device__ __forceinline__ void pair_flux_rhd(double G, const NodeRHD<NU>& l, co
     F[NU + 1] = at * U5 + C * un;
     Jt = at;
 }
+
+#ifndef ES_OPCOUNT_HOST
+// Mixed-precision form of pair_flux_rhd: the pair algebra (means, U~, F~_j) in
+// FP32 except the small-jump branch of the logarithmic means, which stays FP64;
+// the contraction with the metrics and the VCL value in FP64.  The FP32 part is
+// written as coefficients K_t, K_j of a_t and a_j (F = a_t K_t + sum_j a_j K_j):
+// equal states give equal coefficients for every pair, so the metric sums cancel
+// in FP64 and a uniform flow stays uniform to FP64 rounding on any mesh that
+// satisfies the discrete SCL and VCL.
+__device__ __forceinline__ float log_mean_mixed(double al, double ar, double lnal, double lnar) {
+    const double s = al + ar;
+    const double dif = al - ar;
+    if (dif * dif < 1e-2 * (s * s)) return (float)log_mean(al, ar, lnal, lnar);
+    return (float)dif * frcp((float)lnal - (float)lnar);
+}
+
+template <int NU>
+__device__ __forceinline__ void pair_flux_rhd_mixed(double G, const NodeRHD<NU>& l, const NodeRHD<NU>& r,
+                                                    const double* al, const double* ar, double* F,
+                                                    double& Jt) {
+    constexpr int M = NU + 2;
+    const float rho_ln = log_mean_mixed(l.rho, r.rho, l.lr, r.lr);
+    const float beta_ln = log_mean_mixed(l.beta, r.beta, l.lb, r.lb);
+    const float rho_m = 0.5f * ((float)l.rho + (float)r.rho);
+    const float beta_m = 0.5f * ((float)l.beta + (float)r.beta);
+    const float W_m = 0.5f * ((float)l.W + (float)r.W);
+    float um[NU];
+    float uu = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        um[k] = 0.5f * ((float)l.u[k] + (float)r.u[k]);
+        uu += um[k] * um[k];
+    }
+    const float a0 = 1.0f + frcp((float)(G - 1.0) * beta_ln);
+    const float iden = frcp(W_m * W_m - uu);
+    const float pb = rho_m * frcp(beta_m);
+    const float U1 = rho_ln * W_m;
+    const float U5 = (a0 * U1 * W_m + pb * uu) * iden;
+    const float C = W_m * (a0 * rho_ln + pb) * iden;
+    const float iW = frcp(W_m);
+    // coefficients of a_t (Kt) and a_j (Kj) per component
+    float Kt[M], Kj[M][NU];
+    Kt[0] = U1;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) Kj[0][j] = rho_ln * um[j];
+    const float sU = (U5 + pb) * iW, sC = C * iW;
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        Kt[1 + k] = um[k] * sU;
+#pragma unroll
+        for (int j = 0; j < NU; ++j) Kj[1 + k][j] = um[k] * sC * um[j] + (j == k ? pb : 0.0f);
+    }
+    Kt[M - 1] = U5;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) Kj[M - 1][j] = C * um[j];
+    const double at = 0.5 * (al[0] + ar[0]);
+    double ab[NU];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) ab[j] = 0.5 * (al[1 + j] + ar[1 + j]);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        double f = at * (double)Kt[c];
+#pragma unroll
+        for (int j = 0; j < NU; ++j) f += ab[j] * (double)Kj[c][j];
+        F[c] = f;
+    }
+    Jt = at;
+}
+#endif
 
 // Conservative -> primitive for RHD (Section 1: a scalar nonlinear equation).
 // Safeguarded Newton on g(p) = (G-1)[(E+p)(1-v^2) - p - D sqrt(1-v^2)] - p,
@@ -154,58 +250,67 @@ __device__ __forceinline__ int c2p_rhd(double G, double D, const double* m, doub
 }
 
 // WENO5-JS value at i+1/2 from point values v_{i-2..i+2} = (a, b, c, d, e).
-// The weights d_k/(eps + b_k)^2 are multiplied through by prod_k (eps + b_k)^2,
-// which leaves their ratios unchanged and needs a single reciprocal; with
-// eps = 1e-6 the products stay far inside the FP64 range.
-__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e, double eps) {
-    const double q0 = 2.0 * a - 7.0 * b + 11.0 * c;      // 6 x candidate values
-    const double q1 = -b + 5.0 * c + 2.0 * d;
-    const double q2 = 2.0 * c + 5.0 * d - e;
-    const double t0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
-    const double t1 = b - 2.0 * c + d, s1 = b - d;
-    const double t2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
-    const double b0 = 13.0 / 12.0 * t0 * t0 + 0.25 * s0 * s0;
-    const double b1 = 13.0 / 12.0 * t1 * t1 + 0.25 * s1 * s1;
-    const double b2 = 13.0 / 12.0 * t2 * t2 + 0.25 * s2 * s2;
-    const double e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
-    const double f0 = e0 * e0, f1 = e1 * e1, f2 = e2 * e2;
-    const double w0 = 0.1 * (f1 * f2);
-    const double w1 = 0.6 * (f0 * f2);
-    const double w2 = 0.3 * (f0 * f1);
-    return (w0 * q0 + w1 * q1 + w2 * q2) * frcp(6.0 * (w0 + w1 + w2));
+// In FP64 the weights d_k/(eps + b_k)^2 are multiplied through by
+// prod_k (eps + b_k)^2, which leaves their ratios unchanged and needs a single
+// reciprocal; with eps = 1e-6 the products stay far inside the FP64 range.
+template <typename R>
+__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
+    const R q0 = R(2.0) * a - R(7.0) * b + R(11.0) * c;      // 6 x candidate values
+    const R q1 = -b + R(5.0) * c + R(2.0) * d;
+    const R q2 = R(2.0) * c + R(5.0) * d - e;
+    const R t0 = a - R(2.0) * b + c, s0 = a - R(4.0) * b + R(3.0) * c;
+    const R t1 = b - R(2.0) * c + d, s1 = b - d;
+    const R t2 = c - R(2.0) * d + e, s2 = R(3.0) * c - R(4.0) * d + e;
+    const R b0 = R(13.0 / 12.0) * t0 * t0 + R(0.25) * s0 * s0;
+    const R b1 = R(13.0 / 12.0) * t1 * t1 + R(0.25) * s1 * s1;
+    const R b2 = R(13.0 / 12.0) * t2 * t2 + R(0.25) * s2 * s2;
+    const R e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
+    const R f0 = e0 * e0, f1 = e1 * e1, f2 = e2 * e2;
+    R w0, w1, w2;
+    if (RealTraits<R>::wide_range) {
+        w0 = R(0.1) * (f1 * f2);
+        w1 = R(0.6) * (f0 * f2);
+        w2 = R(0.3) * (f0 * f1);
+    } else {
+        // FP32: products of the f_k could overflow; the hardware reciprocal is cheap
+        w0 = R(0.1) * frcp(f0);
+        w1 = R(0.6) * frcp(f1);
+        w2 = R(0.3) * frcp(f2);
+    }
+    return (w0 * q0 + w1 * q1 + w2 * q2) * frcp(R(6.0) * (w0 + w1 + w2));
 }
 
 // Face state in the rotated frame with the reciprocals the tangent map reuses.
-template <int DIM>
+template <int DIM, typename R = double>
 struct FaceRHD {
-    double rho, irho, p, ip, beta, W, h, v[DIM];
+    R rho, irho, p, ip, beta, W, h, v[DIM];
 };
 
 // Tangent map of the primitive state P = (rho, v, p) (rotated frame, DIM velocity
 // components): dU = (dU/dP) dP and dV = (dV/dP) dP, U = (rho W, rho h W^2 v,
 // rho h W^2 - p), V = (G/(G-1) + ln rho + ln beta/(G-1) + beta, beta W v, -beta W);
 // c0 = G/(G-1), c1 = 1/(G-1).
-template <int DIM>
-__device__ __forceinline__ void tangent_rhd(double c0, double c1, const FaceRHD<DIM>& f,
-                                            double drho, const double* dv, double dp, double* dU,
-                                            double* dV) {
+template <int DIM, typename R>
+__device__ __forceinline__ void tangent_rhd(R c0, R c1, const FaceRHD<DIM, R>& f,
+                                            R drho, const R* dv, R dp, R* dU,
+                                            R* dV) {
     constexpr int M = DIM + 2;
-    const double W = f.W;
-    double vdv = 0.0;
+    const R W = f.W;
+    R vdv = R(0.0);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) vdv += f.v[k] * dv[k];
-    const double dW = W * W * W * vdv;
-    const double dh = c0 * (dp - f.p * drho * f.irho) * f.irho;
-    const double W2 = W * W;
-    const double Z = f.rho * f.h * W2;
-    const double dZ = (drho * f.h + f.rho * dh) * W2 + 2.0 * f.rho * f.h * W * dW;
+    const R dW = W * W * W * vdv;
+    const R dh = c0 * (dp - f.p * drho * f.irho) * f.irho;
+    const R W2 = W * W;
+    const R Z = f.rho * f.h * W2;
+    const R dZ = (drho * f.h + f.rho * dh) * W2 + R(2.0) * f.rho * f.h * W * dW;
     dU[0] = drho * W + f.rho * dW;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) dU[1 + k] = dZ * f.v[k] + Z * dv[k];
     dU[M - 1] = dZ - dp;
-    const double dbeta = (drho - f.beta * dp) * f.ip;
+    const R dbeta = (drho - f.beta * dp) * f.ip;
     dV[0] = drho * f.irho + dbeta * (c1 * f.p * f.irho) + dbeta;
-    const double dbW = dbeta * W + f.beta * dW;
+    const R dbW = dbeta * W + f.beta * dW;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) dV[1 + k] = dbW * f.v[k] + f.beta * W * dv[k];
     dV[M - 1] = -dbW;
@@ -213,30 +318,30 @@ __device__ __forceinline__ void tangent_rhd(double c0, double c1, const FaceRHD<
 
 // Rotation T_0 with first row n (Section 4), read with atan2 semantics:
 // row 2 = (-n2, n1, 0)/rho_perp, row 3 = (-n3 n1/rho_perp, -n3 n2/rho_perp, rho_perp),
-// rho_perp = sqrt(n1^2 + n2^2); rows (0,1,0), (-n3,0,0) when rho_perp = 0.
-template <int DIM>
-__device__ __forceinline__ void rotation(const double* n, double T[3][3]) {
+// rho_perp = xsqrt(n1^2 + n2^2); rows (0,1,0), (-n3,0,0) when rho_perp = R(0.)
+template <int DIM, typename R>
+__device__ __forceinline__ void rotation(const R* n, R T[3][3]) {
     if (DIM == 2) {
-        T[0][0] = n[0]; T[0][1] = n[1]; T[0][2] = 0.0;
-        T[1][0] = -n[1]; T[1][1] = n[0]; T[1][2] = 0.0;
-        T[2][0] = 0.0; T[2][1] = 0.0; T[2][2] = 1.0;
+        T[0][0] = n[0]; T[0][1] = n[1]; T[0][2] = R(0.0);
+        T[1][0] = -n[1]; T[1][1] = n[0]; T[1][2] = R(0.0);
+        T[2][0] = R(0.0); T[2][1] = R(0.0); T[2][2] = R(1.0);
         return;
     }
-    const double rp = sqrt(n[0] * n[0] + n[1] * n[1]);
+    const R rp = xsqrt(n[0] * n[0] + n[1] * n[1]);
     T[0][0] = n[0]; T[0][1] = n[1]; T[0][2] = n[2];
-    if (rp > 0.0) {
-        const double ir = frcp(rp);
-        T[1][0] = -n[1] * ir; T[1][1] = n[0] * ir; T[1][2] = 0.0;
+    if (rp > R(0.0)) {
+        const R ir = frcp(rp);
+        T[1][0] = -n[1] * ir; T[1][1] = n[0] * ir; T[1][2] = R(0.0);
         T[2][0] = -n[2] * n[0] * ir; T[2][1] = -n[2] * n[1] * ir; T[2][2] = rp;
     } else {
-        T[1][0] = 0.0; T[1][1] = 1.0; T[1][2] = 0.0;
-        T[2][0] = -n[2]; T[2][1] = 0.0; T[2][2] = 0.0;
+        T[1][0] = R(0.0); T[1][1] = R(1.0); T[1][2] = R(0.0);
+        T[2][0] = -n[2]; T[2][1] = R(0.0); T[2][2] = R(0.0);
     }
 }
 
 // Entropy-stable dissipation d = lambda^ T^{-1} R Y <<V~>> at one face
 // (eq. ESFlux_HO).  nd[0..5] are the stencil nodes i-2..i+3 of the face
-// i+1/2; al, ar the metric vectors (a_t, a_1..a_d) of nodes i and i+1.
+// i+1/2; al, ar the metric vectors (a_t, a_1..a_d) of nodes i and i+R(1.)
 //  * face state: the state whose entropy variables are the mean of those of
 //    nodes i and i+1 (A0 at that state turns [V] into the midpoint rule for [U]);
 //    face metrics: arithmetic mean (readings of this build);
@@ -244,7 +349,7 @@ __device__ __forceinline__ void rotation(const double* n, double T[3][3]) {
 //  * R: acoustic columns from the primitive eigenvector (scaled by lambda - v_n)
 //      dp = lambda - v_n, drho = dp/(h c^2), dv_n = (1 - v_n lambda)/(rho h W^2),
 //      dv_t = -v_t (dh + h W^2 v_n dv_n)/(h (1 + W^2 |v_t|^2))   [d(h W v_t) = 0],
-//    normalised by sqrt(dU.dV) so that R R^T = dU/dV; the v_n cluster
+//    normalised by xsqrt(dU.dV) so that R R^T = dU/dV; the v_n cluster
 //    (basis e_rho, e_vt) is replaced by its canonical A0^{-1}-orthonormal basis
 //    from the cluster projector applied to the seeds e_D, e_{m_t1}(, e_{m_t2}),
 //    computed in the coefficient space of the cluster basis with the Gram
@@ -252,31 +357,31 @@ __device__ __forceinline__ void rotation(const double* n, double T[3][3]) {
 //  * WENO5-JS of V~ = R^T T V on both sides, Y_l = [<<V~_l>> [V~_l] > 0], with a
 //    jump [V~_l] below Y_TOL |r_l|_1 (|T V_i|_max + |T V_i+1|_max) counted as
 //    zero (sign(0) at rounding level).
-template <int DIM>
-__device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRHD<DIM>* nd,
-                                              const double* al, const double* ar, double* d) {
+template <int DIM, typename R>
+__device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>* nd,
+                                              const R* al, const R* ar, R* d) {
     constexpr int M = DIM + 2;
     constexpr int NC = DIM;          // cluster size (entropy + transverse shear waves)
-    const double at = 0.5 * (al[0] + ar[0]);
-    double ax[3] = {0.0, 0.0, 0.0};
+    const R at = R(0.5) * (al[0] + ar[0]);
+    R ax[3] = {R(0.0), R(0.0), R(0.0)};
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) ax[j] = 0.5 * (al[1 + j] + ar[1 + j]);
-    const double L = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
-    const double iL = frcp(L);
-    double nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
-    double T[3][3];
+    for (int j = 0; j < DIM; ++j) ax[j] = R(0.5) * (al[1 + j] + ar[1 + j]);
+    const R L = xsqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    const R iL = frcp(L);
+    R nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
+    R T[3][3];
     rotation<DIM>(nrm, T);
 
     // rotated entropy variables T V of the six stencil nodes
-    double TV[6][M];
-    const double c0 = G / (G - 1.0), c1 = 1.0 / (G - 1.0);
+    R TV[6][M];
+    const R c0 = G / (G - R(1.0)), c1 = R(1.0) / (G - R(1.0));
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        const NodeRHD<DIM>& q = nd[j];
+        const NodeRHD<DIM, R>& q = nd[j];
         TV[j][0] = c0 + q.lr + q.lb * c1 + q.beta;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            double s = 0.0;
+            R s = R(0.0);
 #pragma unroll
             for (int b = 0; b < DIM; ++b) s += T[a][b] * q.u[b];
             TV[j][1 + a] = q.beta * s;
@@ -287,138 +392,138 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
     // face state in the rotated frame: the state whose entropy variables are the
     // mean of those of nodes i and i+1 (beta^2 = V_E^2 - |V_u|^2, u = V_u/beta,
     // W = -V_E/beta, ln rho = V_1 - G/(G-1) - ln(beta)/(G-1) - beta, p = rho/beta)
-    double Vb[M];
+    R Vb[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) Vb[c] = 0.5 * (TV[2][c] + TV[3][c]);
-    double vu2 = 0.0;
+    for (int c = 0; c < M; ++c) Vb[c] = R(0.5) * (TV[2][c] + TV[3][c]);
+    R vu2 = R(0.0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) vu2 += Vb[1 + a] * Vb[1 + a];
-    const double beta_f = sqrt(Vb[M - 1] * Vb[M - 1] - vu2);
-    const double ib = frcp(beta_f);
-    FaceRHD<DIM> fs;
+    const R beta_f = xsqrt(Vb[M - 1] * Vb[M - 1] - vu2);
+    const R ib = frcp(beta_f);
+    FaceRHD<DIM, R> fs;
     fs.beta = beta_f;
     fs.W = -Vb[M - 1] * ib;
-    fs.rho = exp(Vb[0] - c0 - log(beta_f) * c1 - beta_f);
+    fs.rho = xexp(Vb[0] - c0 - xlog(beta_f) * c1 - beta_f);
     fs.irho = frcp(fs.rho);
     fs.p = fs.rho * ib;
     fs.ip = beta_f * fs.irho;
-    const double iVE = -frcp(Vb[M - 1]);      // 1/(beta W)
+    const R iVE = -frcp(Vb[M - 1]);      // 1/(beta W)
 #pragma unroll
     for (int k = 0; k < DIM; ++k) fs.v[k] = Vb[1 + k] * iVE;
-    const double rho = fs.rho, p = fs.p, W = fs.W;
-    const double* v = fs.v;
-    double v2 = 0.0;
+    const R rho = fs.rho, p = fs.p, W = fs.W;
+    const R* v = fs.v;
+    R v2 = R(0.0);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) v2 += v[k] * v[k];
-    const double vn = v[0];
+    const R vn = v[0];
     // p/rho = 1/beta, so h = 1 + c0/beta and h cs^2 = G/beta
-    const double h = 1.0 + c0 * ib;
+    const R h = R(1.0) + c0 * ib;
     fs.h = h;
-    const double cs2 = G * ib * frcp(h);
-    const double cs = sqrt(cs2);
-    const double disc = sqrt((1.0 - v2) * (1.0 - v2 * cs2 - vn * vn * (1.0 - cs2)));
-    const double iden = frcp(1.0 - v2 * cs2);
-    const double lam_m = (vn * (1.0 - cs2) - cs * disc) * iden;
-    const double lam_p = (vn * (1.0 - cs2) + cs * disc) * iden;
-    const double lhat = fmax(fabs(at + L * lam_m), fmax(fabs(at + L * vn), fabs(at + L * lam_p)));
+    const R cs2 = G * ib * frcp(h);
+    const R cs = xsqrt(cs2);
+    const R disc = xsqrt((R(1.0) - v2) * (R(1.0) - v2 * cs2 - vn * vn * (R(1.0) - cs2)));
+    const R iden = frcp(R(1.0) - v2 * cs2);
+    const R lam_m = (vn * (R(1.0) - cs2) - cs * disc) * iden;
+    const R lam_p = (vn * (R(1.0) - cs2) + cs * disc) * iden;
+    const R lhat = fmax(fabs(at + L * lam_m), fmax(fabs(at + L * vn), fabs(at + L * lam_p)));
 
-    double dd[M];
+    R dd[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) dd[c] = 0.0;
+    for (int c = 0; c < M; ++c) dd[c] = R(0.0);
     // rounding scale of the projections r . T V at nodes i and i+1
-    double tv2 = 0.0, tv3 = 0.0;
+    R tv2 = R(0.0), tv3 = R(0.0);
 #pragma unroll
     for (int c = 0; c < M; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
-    const double tvmax = tv2 + tv3;
+    const R tvmax = tv2 + tv3;
 
     // one column r of R: project, reconstruct, switch, accumulate
-    auto column = [&](const double* r) {
-        double vt[6];
+    auto column = [&](const R* r) {
+        R vt[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            double s = 0.0;
+            R s = R(0.0);
 #pragma unroll
             for (int c = 0; c < M; ++c) s += r[c] * TV[j][c];
             vt[j] = s;
         }
-        const double vm = weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
-        const double vp = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps);
-        const double jw = vp - vm;
-        const double jp = vt[3] - vt[2];
+        const R vm = weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
+        const R vp = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps);
+        const R jw = vp - vm;
+        const R jp = vt[3] - vt[2];
         // a jump within rounding of zero counts as zero (Y = 0)
-        double r1 = 0.0;
+        R r1 = R(0.0);
 #pragma unroll
         for (int c = 0; c < M; ++c) r1 += fabs(r[c]);
-        if (jw * jp > 0.0 && fabs(jp) > Y_TOL * r1 * tvmax) {
+        if (jw * jp > R(0.0) && fabs(jp) > RealTraits<R>::ytol * r1 * tvmax) {
 #pragma unroll
             for (int c = 0; c < M; ++c) dd[c] += jw * r[c];
         }
     };
 
     // acoustic columns
-    const double hW2 = h * W * W;
-    double vt2 = 0.0;
+    const R hW2 = h * W * W;
+    R vt2 = R(0.0);
 #pragma unroll
     for (int k = 1; k < DIM; ++k) vt2 += v[k] * v[k];
-    const double i_rhW2 = frcp(rho * hW2);
-    const double i_ht = frcp(h * (1.0 + W * W * vt2));
-    const double ig = beta_f / G;                    // 1/(h cs^2)
+    const R i_rhW2 = frcp(rho * hW2);
+    const R i_ht = frcp(h * (R(1.0) + W * W * vt2));
+    const R ig = beta_f / G;                    // 1/(h cs^2)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const double lam = s == 0 ? lam_m : lam_p;
-        const double q = lam - vn;
-        const double dp = q;
-        const double drho = q * ig;
-        double dv[DIM];
-        dv[0] = (1.0 - vn * lam) * i_rhW2;
-        const double dh = c0 * (dp - p * drho * fs.irho) * fs.irho;
-        const double fac = -(dh + hW2 * vn * dv[0]) * i_ht;
+        const R lam = s == 0 ? lam_m : lam_p;
+        const R q = lam - vn;
+        const R dp = q;
+        const R drho = q * ig;
+        R dv[DIM];
+        dv[0] = (R(1.0) - vn * lam) * i_rhW2;
+        const R dh = c0 * (dp - p * drho * fs.irho) * fs.irho;
+        const R fac = -(dh + hW2 * vn * dv[0]) * i_ht;
 #pragma unroll
         for (int k = 1; k < DIM; ++k) dv[k] = v[k] * fac;
-        double dU[M], dV[M];
+        R dU[M], dV[M];
         tangent_rhd<DIM>(c0, c1, fs, drho, dv, dp, dU, dV);
-        double nn = 0.0;
+        R nn = R(0.0);
 #pragma unroll
         for (int c = 0; c < M; ++c) nn += dU[c] * dV[c];
-        const double sc = frcp(sqrt(nn));
+        const R sc = frcp(xsqrt(nn));
 #pragma unroll
         for (int c = 0; c < M; ++c) dU[c] *= sc;
         column(dU);
     }
 
     // v_n cluster: basis e_rho, e_{v_t1}(, e_{v_t2}) in primitive variables
-    double KU[NC][M], KV[NC][M];
+    R KU[NC][M], KV[NC][M];
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
-        double dv[DIM];
+        R dv[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) dv[k] = 0.0;
-        double drho = 0.0;
-        if (a == 0) drho = 1.0; else dv[a] = 1.0;
-        tangent_rhd<DIM>(c0, c1, fs, drho, dv, 0.0, KU[a], KV[a]);
+        for (int k = 0; k < DIM; ++k) dv[k] = R(0.0);
+        R drho = R(0.0);
+        if (a == 0) drho = R(1.0); else dv[a] = R(1.0);
+        tangent_rhd<DIM>(c0, c1, fs, drho, dv, R(0.0), KU[a], KV[a]);
     }
-    double Gm[NC][NC];
+    R Gm[NC][NC];
 #pragma unroll
     for (int a = 0; a < NC; ++a)
 #pragma unroll
         for (int b = 0; b < NC; ++b) {
-            double s = 0.0, t = 0.0;
+            R s = R(0.0), t = R(0.0);
 #pragma unroll
             for (int c = 0; c < M; ++c) { s += KU[a][c] * KV[b][c]; t += KU[b][c] * KV[a][c]; }
-            Gm[a][b] = 0.5 * (s + t);
+            Gm[a][b] = R(0.5) * (s + t);
         }
-    double Gi[NC][NC];
+    R Gi[NC][NC];
     if (NC == 2) {
-        const double det = Gm[0][0] * Gm[1][1] - Gm[0][1] * Gm[1][0];
-        const double id = frcp(det);
+        const R det = Gm[0][0] * Gm[1][1] - Gm[0][1] * Gm[1][0];
+        const R id = frcp(det);
         Gi[0][0] = Gm[1][1] * id; Gi[1][1] = Gm[0][0] * id;
         Gi[0][1] = -Gm[0][1] * id; Gi[1][0] = -Gm[1][0] * id;
     } else {
-        const double c00 = Gm[1][1] * Gm[2][2] - Gm[1][2] * Gm[2][1];
-        const double c01 = Gm[1][2] * Gm[2][0] - Gm[1][0] * Gm[2][2];
-        const double c02 = Gm[1][0] * Gm[2][1] - Gm[1][1] * Gm[2][0];
-        const double det = Gm[0][0] * c00 + Gm[0][1] * c01 + Gm[0][2] * c02;
-        const double id = frcp(det);
+        const R c00 = Gm[1][1] * Gm[2][2] - Gm[1][2] * Gm[2][1];
+        const R c01 = Gm[1][2] * Gm[2][0] - Gm[1][0] * Gm[2][2];
+        const R c02 = Gm[1][0] * Gm[2][1] - Gm[1][1] * Gm[2][0];
+        const R det = Gm[0][0] * c00 + Gm[0][1] * c01 + Gm[0][2] * c02;
+        const R id = frcp(det);
         Gi[0][0] = c00 * id;
         Gi[0][1] = (Gm[0][2] * Gm[2][1] - Gm[0][1] * Gm[2][2]) * id;
         Gi[0][2] = (Gm[0][1] * Gm[1][2] - Gm[0][2] * Gm[1][1]) * id;
@@ -430,45 +535,45 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
         Gi[2][2] = (Gm[0][0] * Gm[1][1] - Gm[0][1] * Gm[1][0]) * id;
     }
     // seeds: D slot 0, transverse momentum slots 2 (and 3)
-    double cf[NC][NC];     // coefficient vectors of the canonical columns
-    double inq[NC];        // reciprocals of their squared A0^{-1} norms
+    R cf[NC][NC];     // coefficient vectors of the canonical columns
+    R inq[NC];        // reciprocals of their squared A0^{-1} norms
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
         const int seed = q == 0 ? 0 : 1 + q;
-        double gs[NC];
+        R gs[NC];
 #pragma unroll
         for (int a = 0; a < NC; ++a) gs[a] = KV[a][seed];
-        double cq[NC];
+        R cq[NC];
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-            double s = 0.0;
+            R s = R(0.0);
 #pragma unroll
             for (int b = 0; b < NC; ++b) s += Gi[a][b] * gs[b];
             cq[a] = s;
         }
 #pragma unroll
         for (int r = 0; r < q; ++r) {
-            double ip = 0.0;
+            R ip = R(0.0);
 #pragma unroll
             for (int a = 0; a < NC; ++a) ip += cf[r][a] * gs[a];
-            const double f = ip * inq[r];
+            const R f = ip * inq[r];
 #pragma unroll
             for (int a = 0; a < NC; ++a) cq[a] -= f * cf[r][a];
         }
-        double nn = 0.0;
+        R nn = R(0.0);
 #pragma unroll
         for (int a = 0; a < NC; ++a)
 #pragma unroll
             for (int b = 0; b < NC; ++b) nn += cq[a] * Gm[a][b] * cq[b];
 #pragma unroll
         for (int a = 0; a < NC; ++a) cf[q][a] = cq[a];
-        const double rn = frcp(sqrt(nn));
+        const R rn = frcp(xsqrt(nn));
         inq[q] = rn * rn;
-        const double sc = rn;
-        double r[M];
+        const R sc = rn;
+        R r[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            double s = 0.0;
+            R s = R(0.0);
 #pragma unroll
             for (int a = 0; a < NC; ++a) s += cq[a] * KU[a][c];
             r[c] = s * sc;
@@ -481,7 +586,7 @@ __device__ __forceinline__ void face_diss_rhd(double G, double eps, const NodeRH
     d[M - 1] = lhat * dd[M - 1];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        double s = 0.0;
+        R s = R(0.0);
 #pragma unroll
         for (int b = 0; b < DIM; ++b) s += T[b][a] * dd[1 + b];
         d[1 + a] = lhat * s;

@@ -3,7 +3,7 @@ call the C ABI through the binding, and compare with the oracle."""
 import numpy as np
 import torch
 
-from oracle import physics as ph, metrics as mt, stepper as st
+from oracle import physics as ph, metrics as mt, residual as rs, stepper as st
 from paper_2107_12027_amd import es, workloads as wl
 
 
@@ -43,19 +43,25 @@ class Case:
     """A grid with a curvilinear (optionally moving) mesh and a primitive state."""
 
     def __init__(self, dim, n, bc, phys=ph.RHD, seed=0, smooth=False, amp=0.03, vmax=0.9,
-                 moving=True, dissipation=1, monitor=None, rho_rng=(0.1, 1.0), p_rng=(0.1, 1.0)):
+                 moving=True, dissipation=1, monitor=None, rho_rng=(0.1, 1.0), p_rng=(0.1, 1.0),
+                 mixed=0, uniform=False):
         rng = np.random.default_rng(seed)
         self.grid = wl.make_grid(dim, n, bc)
         self.x = wl.perturbed_mesh(self.grid, rng, amp=amp)
         self.xdot = (wl.perturbed_mesh(self.grid, rng, amp=0.05) - wl.uniform_mesh(self.grid)) if moving \
             else np.zeros_like(self.x)
-        if smooth:
+        if uniform:
+            pr = wl.random_prim((1,) * dim, rng, phys=phys, dim=dim, vmax=vmax)
+            pr = {k: np.broadcast_to(v.reshape(v.shape[:v.ndim - dim] + (1,) * dim),
+                                     v.shape[:v.ndim - dim] + self.grid.shape).copy()
+                  for k, v in pr.items()}
+        elif smooth:
             pr = wl.smooth_prim(self.x, rng, phys)
         else:
             pr = wl.random_prim(self.grid.shape, rng, phys=phys, dim=dim, vmax=vmax,
                                 rho_rng=rho_rng, p_rng=p_rng)
         self.P = full_P(pr)
-        self.scheme = wl.Scheme(phys=phys, dissipation=dissipation)
+        self.scheme = wl.Scheme(phys=phys, dissipation=dissipation, mixed=mixed)
         self.monitor = monitor if monitor is not None else wl.Monitor(enabled=0)
         self.ctx = es.Context(self.grid, self.scheme, self.monitor)
         self.dim, self.phys = dim, phys
@@ -65,6 +71,25 @@ class Case:
         J = mt.jacobian(self.grid, self.x)
         U = st.cons_from_prim(self.grid, self.scheme, self.P, J)
         return U, J
+
+    def residual(self):
+        """es_con2prim, es_metrics (with the mesh velocity) and es_residual on the GPU."""
+        c = self.ctx
+        U, J = self.gpu_state()
+        prim = empty(c.nprim, *c.padded_shape())
+        met = empty(c.nmet, *c.padded_shape())
+        c.con2prim(U, J, prim)
+        c.metrics(dev(self.x), dev(self.xdot), met)
+        dU = empty(c.m, *c.shape())
+        dJ = empty(*c.shape())
+        c.residual(prim, met, dU, dJ)
+        return U, J, prim, met, dU, dJ
+
+    def oracle_residual(self):
+        Uo, Jo = self.oracle_state()
+        Po, _ = st.prim_from_cons(self.grid, self.scheme, Uo, Jo)
+        meto = mt.metrics(self.grid, self.x, self.xdot)
+        return rs.residual(self.grid, self.scheme, st.pad_solution(self.grid, Po), meto)
 
     def gpu_state(self):
         """J^0 by es_metrics and Ucurv by es_prim2con from the same primitive input."""

@@ -1,0 +1,114 @@
+"""FP32-mixed form of the residual (scheme.mixed = 1) against the FP64 oracle.
+
+The pair algebra and the face dissipation run in FP32 (unit roundoff 6e-8), so
+parity is stated as an error bound, not bitwise: relative L1 errors of order
+1e-7 where the residual is of the size of the fluxes (random states), larger
+where it is a small difference of large fluxes (smooth states: the flux
+difference cancels about two digits at these resolutions), and isolated large
+pointwise differences with dissipation, where an FP32 jump on the other side of
+the sign switch Y (a discontinuous decision) turns one face's term on or off.
+What the design keeps exact is checked at FP64 level: the metric contraction in
+FP64 keeps a uniform flow on a static curvilinear mesh uniform to FP64 rounding
+(Proposition 4.2), and the VCL stays FP64."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import physics as ph, stepper as st  # noqa: E402
+from paper_2107_12027_amd import es, workloads as wl  # noqa: E402
+from gpu_util import Case, dev, host, empty, rel_inf  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [(2, (130, 70, 1), (0, 0, 0)), (2, (64, 123, 1), (1, 1, 0)),
+         (3, (70, 9, 8), (0, 0, 0)), (3, (10, 66, 9), (1, 1, 1))]
+
+
+def l1_rel(a, b):
+    a = np.asarray(a).reshape(a.shape[0], -1)
+    b = np.asarray(b).reshape(b.shape[0], -1)
+    return np.abs(a - b).sum(axis=1) / np.abs(b).sum(axis=1)
+
+
+@pytest.mark.parametrize("dim,n,bc", GRIDS)
+@pytest.mark.parametrize("smooth", [False, True])
+def test_mixed_ec_residual_error(dim, n, bc, smooth):
+    # measured: random 2e-7, smooth 6e-6 (relative L1); VCL exact to FP64
+    case = Case(dim, n, bc, seed=4, dissipation=0, mixed=1, smooth=smooth)
+    _, _, _, _, dU, dJ = case.residual()
+    dUo, dJo = case.oracle_residual()
+    bound = 3e-5 if smooth else 2e-6
+    assert np.all(l1_rel(host(dU), dUo) <= bound), l1_rel(host(dU), dUo)
+    assert rel_inf(host(dJ)[None], dJo[None])[0] <= 1e-12
+
+
+@pytest.mark.parametrize("dim,n,bc", GRIDS)
+@pytest.mark.parametrize("smooth", [False, True])
+def test_mixed_es_residual_error(dim, n, bc, smooth):
+    # measured up to 2.3e-5 relative L1 (sign-switch flips at a few faces)
+    case = Case(dim, n, bc, seed=5, dissipation=1, mixed=1, smooth=smooth)
+    _, _, _, _, dU, dJ = case.residual()
+    dUo, dJo = case.oracle_residual()
+    assert np.all(l1_rel(host(dU), dUo) <= 2e-4), l1_rel(host(dU), dUo)
+    assert rel_inf(host(dJ)[None], dJo[None])[0] <= 1e-12
+
+
+@pytest.mark.parametrize("dim,n,bc", GRIDS)
+@pytest.mark.parametrize("moving", [False, True])
+def test_mixed_free_stream(dim, n, bc, moving):
+    # uniform state on a curvilinear mesh: d(JU)/dt = U dJ/dt.  Static mesh: to FP64
+    # rounding (measured 4e-15 of the flux scale, as the FP64 path); moving mesh: the
+    # FP32 coefficient of a_t is U rounded to FP32 (measured 5e-10 of the scale).
+    case = Case(dim, n, bc, seed=11, uniform=True, moving=moving, mixed=1)
+    U, J, _, met, dU, dJ = case.residual()
+    Uh, Jh, dUh, dJh = host(U), host(J), host(dU), host(dJ)
+    U0 = Uh / Jh
+    err = np.abs(dUh - U0 * dJh).reshape(case.m, -1).max(axis=1)
+    scale = np.abs(U0).reshape(case.m, -1).max(axis=1) * np.abs(host(met)).max() / min(case.grid.dxi[:dim])
+    bound = 1e-8 if moving else 1e-13
+    assert np.all(err <= bound * scale), err / scale
+    if not moving:
+        assert np.abs(dJh).max() == 0.0
+
+
+@pytest.mark.parametrize("dim,n,bc", [GRIDS[0], GRIDS[2]])
+def test_mixed_entropy_conservation(dim, n, bc):
+    # EC residual on a periodic moving mesh: sum(V.dU - phi dJ) / sum|V.dU| measured
+    # 8e-10 (FP64 path: 1e-18)
+    case = Case(dim, n, bc, seed=9, dissipation=0, mixed=1)
+    c = case.ctx
+    U, J, prim, _, dU, dJ = case.residual()
+    out = empty(3 + c.m)
+    c.diagnostics(prim, U, J, dU, dJ, out)
+    Uo, Jo = case.oracle_state()
+    Po, _ = st.prim_from_cons(case.grid, case.scheme, Uo, Jo)
+    V = ph.entropy_vars(Po, case.scheme.gamma)[ph.comps(ph.RHD, dim)]
+    scale = np.sum(np.abs(V * host(dU)))
+    assert abs(host(out)[0]) <= 1e-7 * scale
+
+
+def test_mixed_rk3_step_quadrant():
+    # one adaptive RK3 step of the quadrant problem: measured 3.3e-7 relative L1,
+    # 6.9e-6 max; the time step is FP64 from FP64 con2prim and metrics
+    w = wl.quadrant_riemann(n=70, seed=2)
+    w.scheme.mixed = 1
+    g = w.grid
+    ctx = es.Context(g, w.scheme, w.monitor)
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    met = empty(ctx.nmet, *ctx.padded_shape())
+    J = empty(*ctx.shape())
+    xg = dev(w.x)
+    ctx.metrics(xg, None, met, J)
+    U = empty(ctx.m, *ctx.shape())
+    ctx.prim2con(dev(P[ph.comps(w.scheme.phys, g.dim)]), J, U)
+    xdot = empty(g.dim, *ctx.shape())
+    dt = empty(1)
+    ctx.rk3_step(U, J, xg, xdot, dt)
+    assert ctx.status()[0] == es.ES_OK
+    ref = wl.quadrant_riemann(n=70, seed=2)
+    Uo, Jo = st.initial_state(g, ref.scheme, P, ref.x)
+    out = st.rk3_step(g, ref.scheme, ref.monitor, Uo, Jo, ref.x)
+    assert abs(host(dt)[0] - out["dt"]) <= 1e-13 * out["dt"]
+    assert np.all(l1_rel(host(U), out["U"]) <= 3e-6), l1_rel(host(U), out["U"])
+    assert np.all(rel_inf(host(U), out["U"]) <= 1e-4)
