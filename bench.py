@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--residual-reps", type=int, default=50)
+    ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed work, copy one buffer of this size once (a plain copy "
                          "kernel of known traffic, for scaling HBM counters)")
@@ -162,6 +163,39 @@ class Run:
         return r0.elapsed_time(r1) / reps
 
 
+def adjoint_timing(w, steps, fwd_ms):
+    """Forward steps with checkpoints, then their vector-Jacobian products in
+    reverse order (es_rk3_step_save / es_rk3_step_vjp), timed with HIP events."""
+    import torch
+    run = Run(w, 0)
+    ctx = run.ctx
+    ck = [torch.empty(ctx.ckpt_doubles(), dtype=torch.float64, device="cuda") for _ in range(steps)]
+    lamU = torch.ones_like(run.U)
+    lamJ = torch.zeros_like(run.J)
+    gU = torch.empty_like(run.U)
+    gJ = torch.empty_like(run.J)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(steps):
+        ctx.rk3_step_save(run.U, run.J, run.x, run.xdot, run.dt, ck[k])
+    ev[1].record(stream)
+    for k in reversed(range(steps)):
+        ctx.rk3_step_vjp(ck[k], lamU, lamJ, gU, gJ)
+        lamU, gU = gU, lamU
+        lamJ, gJ = gJ, lamJ
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    if ctx.status()[0] != 0 or not bool(torch.isfinite(lamU).all()):
+        return None
+    save_ms = ev[0].elapsed_time(ev[1]) / steps
+    vjp_ms = ev[1].elapsed_time(ev[2]) / steps
+    return {"steps": steps, "forward_ms_per_step": fwd_ms, "forward_with_checkpoint_ms_per_step": save_ms,
+            "vjp_ms_per_step": vjp_ms, "adjoint_over_forward": vjp_ms / fwd_ms,
+            "note": "VJP of es_rk3_step with the mesh trajectory and dt held fixed; FP64"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -193,6 +227,7 @@ def main():
     mrun = Run(w, 1)
     t_mixed_ms = mrun.timed(args.steps, args.warmup)
     res_mixed_ms = mrun.residual_ms(args.residual_reps)
+    adjoint = adjoint_timing(w, args.adjoint_steps, t_ms / args.steps)
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 8
@@ -239,6 +274,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "adjoint": adjoint,
     }
     print(json.dumps(line))
 

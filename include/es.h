@@ -166,6 +166,41 @@ es_status es_mesh_redistribute(es_ctx* ctx, const double* prim, const double* x,
 es_status es_rk3_step(es_ctx* ctx, double* Ucurv, double* J, double* x, double* xdot,
                       double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
 
+/* Adjoint (FP64 form only; ES_EUNSUPPORTED for scheme.mixed = 1).  The
+ * derivatives are those of the step with the mesh trajectory (x^n, xdot), the
+ * time step dt and every branch decision (the sign switch Y of eq. ESFlux_HO,
+ * the maximum in lambda^, the log-mean series branch) held at their forward
+ * values; for a static mesh (monitor disabled) with a fixed dt this is the
+ * exact derivative of the step.  con2prim is differentiated by the
+ * implicit-function rule, dP/dU = (dU/dP)^{-1}.  The first adjoint call on a
+ * context allocates its adjoint workspace.
+ *
+ * es_ckpt_doubles: size (in doubles) of the checkpoint of one step: the stage
+ * states Ucurv^(0..2) (m comps each) and J^(0..2), x^n, xdot (d comps each) and
+ * dt, all interior.
+ *
+ * es_rk3_step_save: es_rk3_step (always launched eagerly, not as a graph) that
+ * also writes that checkpoint into ckpt (device, caller-owned). */
+size_t es_ckpt_doubles(const es_ctx* ctx);
+es_status es_rk3_step_save(es_ctx* ctx, double* Ucurv, double* J, double* x, double* xdot,
+                           double* dt_dev, const double* fixed_dt_dev, double* ckpt,
+                           hipStream_t stream);
+
+/* Vector-Jacobian product of one saved step: given the cotangents lamU (m
+ * comps) and lamJ of (Ucurv^{n+1}, J^{n+1}), writes the cotangents gU, gJ of
+ * (Ucurv^n, J^n).  ckpt: from es_rk3_step_save on the same context.  Uses the
+ * context's metrics and primitive workspace.  All arrays interior, device. */
+es_status es_rk3_step_vjp(es_ctx* ctx, const double* ckpt, const double* lamU, const double* lamJ,
+                          double* gU, double* gJ, hipStream_t stream);
+
+/* Vector-Jacobian product of the state residual L(Ucurv, J) = residual(
+ * con2prim(Ucurv, J), met) (its m state components; the VCL part does not
+ * depend on the state): gU = (dL/dUcurv)^T lamU, gJ = (dL/dJ)^T lamU.
+ * Ucurv, lamU, gU: interior m comps; J, gJ: interior; met: padded (es_metrics).
+ * Overwrites the context's primitive workspace. */
+es_status es_residual_vjp(es_ctx* ctx, const double* Ucurv, const double* J, const double* met,
+                          const double* lamU, double* gU, double* gJ, hipStream_t stream);
+
 /* Replay es_rk3_step as a HIP graph (default 1) or launch its kernels one by
  * one (0).  In graph mode the step is captured on the context's own stream the
  * first time it is called with a given set of array pointers and replayed

@@ -158,6 +158,14 @@ def eigensystem(Pr, G, phys, dim):
         np.put_along_axis(R, idx_cl[:, q][:, None, None].repeat(m, axis=1),
                           cols[q][:, :, None], axis=2)
         np.put_along_axis(lam, idx_cl[:, q][:, None], vn[:, None], axis=1)
+    # canonical column order: the other eigenvalues ascending, then the cluster
+    # columns in seed order (so that a column index names the same wave at nearby
+    # states)
+    rest = order[:, c:]
+    rest = np.take_along_axis(rest, np.argsort(np.take_along_axis(lam, rest, axis=1), axis=1), axis=1)
+    perm = np.concatenate([rest, idx_cl], axis=1)                     # (N, m)
+    lam = np.take_along_axis(lam, perm, axis=1)
+    R = np.take_along_axis(R, perm[:, None, :].repeat(m, axis=1), axis=2)
     return lam, R
 
 
@@ -175,10 +183,12 @@ def weno5_minus(a, b, c, d, e, eps):
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2)
 
 
-def face_dissipation(Pst, ast, G, phys, dim, eps, details=False):
+def face_dissipation(Pst, ast, G, phys, dim, eps, details=False, Y_fixed=None):
     """ES dissipation vector d = D Y <<V~>> at faces.
     Pst: (6, 8, N) full primitive states of the stencil nodes i-2..i+3 of each face;
     ast: (2, d+1, N) metric vectors of nodes i and i+1.
+    Y_fixed: optional (m, N) sign-switch values to use instead of evaluating Y
+    (the switch held fixed, for difference quotients of the smooth part).
     Returns the full 8-slot d (8, N) (zeros in unused slots)."""
     sel = ph.comps(phys, dim)
     m = len(sel)
@@ -213,6 +223,8 @@ def face_dissipation(Pst, ast, G, phys, dim, eps, details=False):
     Vj = rotate_full(ph.entropy_vars(Pst[3], G), T0, slots)[sel]
     scale = np.sum(np.abs(R), axis=1).T * (np.max(np.abs(Vi), axis=0) + np.max(np.abs(Vj), axis=0))[None, :]
     Y = ((jump_weno * jump > 0) & (np.abs(jump) > Y_TOL * scale)).astype(np.float64)
+    if Y_fixed is not None:
+        Y = Y_fixed
     coef = Y * jump_weno                                                 # (m, N)
     dsel = lhat[None, :] * np.einsum("nab,bn->an", R, coef)              # R (Y <<V~>>)
     dfull = np.zeros((8,) + dsel.shape[1:])

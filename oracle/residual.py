@@ -33,9 +33,11 @@ def _take(a, idx, ax):
     return np.take(a, idx, axis=ax)
 
 
-def residual(grid, scheme, Ppad, met, details=False):
+def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None):
     """Returns (dU (m, *shape), dJ (*shape)) on the interior nodes, optionally with
-    per-direction face fluxes."""
+    per-direction face fluxes and sign switches.  Y_fixed: optional {direction:
+    Y (m, faces)} from an earlier call with details, used instead of evaluating
+    the switch."""
     d = grid.dim
     G = scheme.gamma
     phys = scheme.phys
@@ -72,8 +74,10 @@ def residual(grid, scheme, Ppad, met, details=False):
             ast = np.stack([_take(ak, faces + j, 1 + ax_sp) for j in range(0, 2)])
             Pst = Pst.reshape(6, 8, -1)
             ast = ast.reshape(2, d + 1, -1)
-            dd = ds.face_dissipation(Pst, ast, G, phys, d, scheme.weno_eps)
+            dd, dinfo = ds.face_dissipation(Pst, ast, G, phys, d, scheme.weno_eps, details=True,
+                                            Y_fixed=None if Y_fixed is None else Y_fixed[k])
             Ff = Ff - 0.5 * dd.reshape((8,) + fshape)
+            Yk = dinfo["Y"]
         hi = np.arange(1, nk + 1)
         lo = np.arange(0, nk)
         dxi = grid.dxi[k]
@@ -82,7 +86,7 @@ def residual(grid, scheme, Ppad, met, details=False):
         if phys == ph.RMHD:
             src += (_take(Bf, hi, ax_sp) - _take(Bf, lo, ax_sp)) / dxi
         if details:
-            info[k] = dict(F=Ff, J=Jf, B=Bf)
+            info[k] = dict(F=Ff, J=Jf, B=Bf, Y=Yk if scheme.dissipation else None)
     if phys == ph.RMHD:
         Pin = interior(Ppad, grid)
         dU -= ph.phi_prime(Pin, G) * src

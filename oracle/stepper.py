@@ -73,10 +73,12 @@ def cfl_dt(grid, scheme, Pin, met, J):
     return scheme.cfl / tot
 
 
-def rk3_step(grid, scheme, mon, Ucurv, J, x, dt=None, details=False, xdot=None):
+def rk3_step(grid, scheme, mon, Ucurv, J, x, dt=None, details=False, xdot=None, Y_fixed=None):
     """One SSP-RK3 step of the ES adaptive moving-mesh scheme.  ``xdot`` prescribes
     the mesh velocity instead of the adaptive redistribution (the prescribed-motion
-    tests of Section 6).  Returns dict(U, J, x, xdot, dt, ok)."""
+    tests of Section 6).  ``Y_fixed``: optional per-stage sign switches (the "Y" list
+    of an earlier call with details) used instead of evaluating them.
+    Returns dict(U, J, x, xdot, dt, ok)."""
     P0, ok = prim_from_cons(grid, scheme, Ucurv, J)
     if not ok.all():
         return dict(U=Ucurv, J=J, x=x, xdot=np.zeros_like(x), dt=np.nan, ok=ok, dtau=0.0,
@@ -94,6 +96,7 @@ def rk3_step(grid, scheme, mon, Ucurv, J, x, dt=None, details=False, xdot=None):
     P = P0
     coef = (0.0, 1.0, 0.5)
     Us, Js = U0, J0
+    Ys = []
     for s in range(3):
         if s > 0:
             P, oks = prim_from_cons(grid, scheme, Us, Js)
@@ -103,7 +106,9 @@ def rk3_step(grid, scheme, mon, Ucurv, J, x, dt=None, details=False, xdot=None):
             return dict(U=Ucurv, J=J, x=x, xdot=xdot, dt=dt, ok=ok, dtau=dtau, failed_stage=s)
         xs = x + coef[s] * dt * xdot
         met = mt.metrics(grid, xs, xdot, scheme.order_p)
-        L, LJ = rs.residual(grid, scheme, pad_solution(grid, P), met)
+        L, LJ, info = rs.residual(grid, scheme, pad_solution(grid, P), met, details=True,
+                                  Y_fixed=None if Y_fixed is None else Y_fixed[s])
+        Ys.append({k: info[k]["Y"] for k in info})
         if s == 0:
             Us, Js = U0 + dt * L, J0 + dt * LJ
         elif s == 1:
@@ -113,6 +118,7 @@ def rk3_step(grid, scheme, mon, Ucurv, J, x, dt=None, details=False, xdot=None):
     out = dict(U=Us, J=Js, x=xnew, xdot=xdot, dt=dt, ok=ok, dtau=dtau)
     if details:
         out["omega"] = w
+        out["Y"] = Ys
     return out
 
 

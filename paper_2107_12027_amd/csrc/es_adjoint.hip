@@ -1,0 +1,697 @@
+// Hand-written adjoint (vector-Jacobian products) of the residual and of one
+// SSP-RK3 step, FP64.
+//
+// The step is reversed stage by stage from checkpoints of the stage states.
+// Within a stage the cotangent lambda of the residual L(U, J) = residual(
+// con2prim(U / J), metrics) is pulled back in three parts:
+//   * residual: per direction, the transposed stencil of eq. ECFlux_O2p and of
+//     the dissipation differences -- each two-point flux F(s, s+n) receives
+//     w = alpha_n / dxi (lambda_{s+n} - lambda_s), each face dissipation d_{f+1/2}
+//     receives z = (lambda_f - lambda_{f+1}) / (2 dxi) -- times the local
+//     Jacobians, gathered per node (no atomics, deterministic);
+//   * ghost folding: cotangents of ghost nodes go to the interior nodes they copy;
+//   * con2prim by the implicit-function rule: dP/dU = (dU/dP)^{-1}, so the state
+//     cotangent solves (dU/dP)^T y = g_P at every node.
+// Local Jacobians: the two-point flux by forward-mode dual numbers (one node's
+// primitive variables at a time); the face dissipation by reverse accumulation
+// through the projections, WENO (dual numbers over the six characteristic
+// values) and the final combination, plus forward-mode tangents of the face
+// eigen-structure over the face entropy variables.  The sign switch Y, the branch
+// of lambda^, the time step, the mesh and its velocity are held fixed.
+#include <math.h>
+
+#include "es_internal.h"
+#include "es_launch.h"
+#include "es_rhd.h"
+#include "es_dual.h"
+
+namespace es {
+
+namespace {
+
+// Node state with its derived quantities from primitive (rho, u, p).
+template <int NU, typename R>
+__device__ __forceinline__ NodeRHD<NU, R> node_from_prim(const R& rho, const R* u, const R& p) {
+    NodeRHD<NU, R> n;
+    n.rho = rho;
+    n.p = p;
+    R uu = R(0.0);
+#pragma unroll
+    for (int k = 0; k < NU; ++k) { n.u[k] = u[k]; uu += u[k] * u[k]; }
+    n.W = xsqrt(R(1.0) + uu);
+    n.beta = rho / p;
+    n.lr = xlog(rho);
+    n.lb = xlog(n.beta);
+    return n;
+}
+
+// Cotangents of the primitive states of the two nodes of a pair flux:
+// gl = (dF/dP_l)^T w, gr = (dF/dP_r)^T w  (P = (rho, u_1..u_NU, p)).
+template <int NU>
+__device__ void pair_vjp_rhd(double G, const double* Pl, const double* Pr, const double* al,
+                             const double* ar, const double* w, double* gl, double* gr) {
+    constexpr int M = NU + 2;
+    using D = Dual<M>;
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {
+        D rl = side == 0 ? D::seed(Pl[0], 0) : D(Pl[0]);
+        D pl = side == 0 ? D::seed(Pl[M - 1], M - 1) : D(Pl[M - 1]);
+        D rr = side == 1 ? D::seed(Pr[0], 0) : D(Pr[0]);
+        D pr = side == 1 ? D::seed(Pr[M - 1], M - 1) : D(Pr[M - 1]);
+        D ul[NU], ur[NU];
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            ul[k] = side == 0 ? D::seed(Pl[1 + k], 1 + k) : D(Pl[1 + k]);
+            ur[k] = side == 1 ? D::seed(Pr[1 + k], 1 + k) : D(Pr[1 + k]);
+        }
+        const NodeRHD<NU, D> l = node_from_prim<NU>(rl, ul, pl);
+        const NodeRHD<NU, D> r = node_from_prim<NU>(rr, ur, pr);
+        D F[M];
+        double Jt;
+        pair_flux_rhd<NU>(G, l, r, al, ar, F, Jt);
+        double* g = side == 0 ? gl : gr;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) s += w[c] * F[c].d[i];
+            g[i] = s;
+        }
+    }
+}
+
+// Cotangents g[j] (j = 0..5, primitive slots) of the stencil states of one face
+// dissipation d (face_diss_rhd) for the cotangent z of d.
+template <int DIM>
+__device__ void face_vjp_rhd(double G, double eps, const NodeRHD<DIM>* nd, const double* al,
+                             const double* ar, const double* z, double g[6][DIM + 2]) {
+    constexpr int M = DIM + 2;
+    const double at = 0.5 * (al[0] + ar[0]);
+    double ax[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) ax[j] = 0.5 * (al[1 + j] + ar[1 + j]);
+    const double L = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    const double iL = frcp(L);
+    double nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
+    double T[3][3];
+    rotation<DIM>(nrm, T);
+    const double c0 = G / (G - 1.0), c1 = 1.0 / (G - 1.0);
+
+    double TV[6][M], Tu[6][DIM];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const NodeRHD<DIM>& q = nd[j];
+        TV[j][0] = c0 + q.lr + q.lb * c1 + q.beta;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) s += T[a][b] * q.u[b];
+            Tu[j][a] = s;
+            TV[j][1 + a] = q.beta * s;
+        }
+        TV[j][M - 1] = -q.beta * q.W;
+    }
+
+    // forward: the eigen-structure as a matrix (column q in Rm[q])
+    double Rm[M][M];
+    const double lhat = face_eigen_columns<DIM>(G, TV[2], TV[3], at, L, [&](const double* r, int q) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) Rm[q][c] = r[c];
+    });
+    double tv2 = 0.0, tv3 = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
+    const double tvmax = tv2 + tv3;
+
+    // z in the rotated frame: d = lhat T^T dd, so d(z.d)/d(dd) = lhat T z
+    double zr[M];
+    zr[0] = z[0];
+    zr[M - 1] = z[M - 1];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) s += T[a][b] * z[1 + b];
+        zr[1 + a] = s;
+    }
+
+    double gR[M][M], gTV[6][M], dd[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        dd[c] = 0.0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) gR[q][c] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) gTV[j][c] = 0.0;
+    }
+    using D6 = Dual<6>;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const double* r = Rm[q];
+        D6 vt[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) s += r[c] * TV[j][c];
+            vt[j] = D6::seed(s, j);
+        }
+        const D6 jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], D6(eps)) -
+                      weno5(vt[0], vt[1], vt[2], vt[3], vt[4], D6(eps));
+        const double jp = vt[3].v - vt[2].v;
+        double r1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) r1 += fabs(r[c]);
+        if (jw.v * jp > 0.0 && fabs(jp) > RealTraits<double>::ytol * r1 * tvmax) {
+            double rz = 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) { dd[c] += jw.v * r[c]; rz += r[c] * zr[c]; }
+            const double gjw = lhat * rz;
+#pragma unroll
+            for (int c = 0; c < M; ++c) gR[q][c] += lhat * jw.v * zr[c];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const double gv = gjw * jw.d[j];
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    gTV[j][c] += gv * r[c];
+                    gR[q][c] += gv * TV[j][c];
+                }
+            }
+        }
+    }
+    double glhat = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) glhat += zr[c] * dd[c];
+
+    // face eigen-structure: tangents along each face entropy variable
+    using D1 = Dual<1>;
+    double Vb[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) Vb[c] = 0.5 * (TV[2][c] + TV[3][c]);
+#pragma unroll 1
+    for (int k = 0; k < M; ++k) {
+        D1 Vd[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) Vd[c] = c == k ? D1::seed(Vb[c], 0) : D1(Vb[c]);
+        double dir = 0.0;
+        const D1 lh = face_eigen_columns<DIM>(D1(G), Vd, Vd, D1(at), D1(L), [&](const D1* r, int q) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) dir += gR[q][c] * r[c].d[0];
+        });
+        dir += glhat * lh.d[0];
+        gTV[2][k] += 0.5 * dir;
+        gTV[3][k] += 0.5 * dir;
+    }
+
+    // rotated entropy variables -> primitive (rho, u, p) of each stencil node
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const NodeRHD<DIM>& q = nd[j];
+        const double ip = 1.0 / q.p, irho = 1.0 / q.rho;
+        double su = 0.0, sbu = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) { su += gTV[j][1 + a] * Tu[j][a]; }
+        sbu = q.beta * su;
+        g[j][0] = gTV[j][0] * ((1.0 + c1) * irho + ip) + su * ip - gTV[j][M - 1] * q.W * ip;
+        g[j][M - 1] = -gTV[j][0] * (c1 + q.beta) * ip - sbu * ip + gTV[j][M - 1] * q.beta * q.W * ip;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) s += T[a][b] * gTV[j][1 + a];
+            g[j][1 + b] = q.beta * s - gTV[j][M - 1] * q.beta * q.u[b] / q.W;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// residual VJP: one wavefront per segment of padded positions along a line
+// ---------------------------------------------------------------------------
+constexpr int ASEG = 54;                  // output positions per segment
+constexpr int AHALO = 5;                  // state halo each side
+constexpr int ALOAD = ASEG + 2 * AHALO;   // 64 loaded slots
+constexpr int ALINES = 2;                 // segments per block
+
+template <int DIM>
+struct AdjLDS {
+    static constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1, NF = 6 + NU + NA;
+    double sd[ALINES][NF][ALOAD];
+    double lam[ALINES][M][ALOAD];
+    double buf[ALINES][6][M][64];
+};
+
+struct AdjPlan {
+    int nseg[3];
+    int nblk[3];
+    long long nlines[3];
+};
+
+template <int DIM, int DIR, bool ES>
+__device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G, double eps,
+                                                     const double* __restrict__ prim,
+                                                     const double* __restrict__ met,
+                                                     const double* __restrict__ lam,
+                                                     double* __restrict__ gout, int blk, int nseg,
+                                                     long long nlines, AdjLDS<DIM>& lds) {
+    constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1;
+    constexpr int F_RHO = 0, F_P = 1, F_BETA = 2, F_W = 3, F_LR = 4, F_LB = 5, F_U = 6, F_A = 6 + NU;
+    auto& sd = lds.sd;
+    auto& sl = lds.lam;
+    auto& buf = lds.buf;
+    const int lane = threadIdx.x & 63;
+    const int line = threadIdx.x >> 6;
+    const int seg = blk % nseg;
+    const long long lid = (long long)(blk / nseg) * ALINES + line;
+    const bool active = lid < nlines;
+    const int n = g.n[DIR];
+    const int s0 = -NG + seg * ASEG;                 // first output (padded coordinate)
+    const int s_end = min(s0 + ASEG, n + NG);
+    int ci = 0, cj = 0, ck = 0;
+    if (active) {
+        if (DIR == 0) { cj = (int)(lid % g.n[1]); ck = (int)(lid / g.n[1]); }
+        else if (DIR == 1) { ci = (int)(lid % g.n[0]); ck = (int)(lid / g.n[0]); }
+        else { ci = (int)(lid % g.n[0]); cj = (int)(lid / g.n[0]); }
+    }
+    const long long pstride = DIR == 0 ? 1 : (DIR == 1 ? (long long)g.P[0] : (long long)g.P[0] * g.P[1]);
+    const long long istride = DIR == 0 ? 1 : (DIR == 1 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1]);
+    const long long pbase = pidx(g, ci, cj, ck);
+    const long long ibase = iidx(g, ci, cj, ck);
+    const long long P = g.pnodes, N = g.nodes;
+    const double idxi = 1.0 / g.dxi[DIR];
+
+    // ---- states (positions s0 - 5 .. s0 + 58) and residual cotangents
+    {
+        const int s = s0 - AHALO + lane;
+        double rho = 1.0, p = 1.0, lr = 0.0, lb = 0.0, u[NU], a[NA];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) u[c] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NA; ++c) a[c] = c == 1 ? 1.0 : 0.0;
+        if (active && s >= -NG && s < n + NG) {
+            const long long idx = pbase + (long long)s * pstride;
+            rho = prim[idx];
+#pragma unroll
+            for (int c = 0; c < NU; ++c) u[c] = prim[(1 + c) * P + idx];
+            p = prim[(M - 1) * P + idx];
+            lr = prim[M * P + idx];
+            lb = prim[(M + 1) * P + idx];
+#pragma unroll
+            for (int c = 0; c < NA; ++c) a[c] = met[(DIR * NA + c) * P + idx];
+        }
+        double uu = 0.0;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) uu += u[c] * u[c];
+        sd[line][F_RHO][lane] = rho;
+        sd[line][F_P][lane] = p;
+        sd[line][F_BETA][lane] = rho / p;
+        sd[line][F_W][lane] = sqrt(1.0 + uu);
+        sd[line][F_LR][lane] = lr;
+        sd[line][F_LB][lane] = lb;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) sd[line][F_U + c][lane] = u[c];
+#pragma unroll
+        for (int c = 0; c < NA; ++c) sd[line][F_A + c][lane] = a[c];
+        const bool in = active && s >= 0 && s < n;
+#pragma unroll
+        for (int c = 0; c < M; ++c) sl[line][c][lane] = in ? lam[c * N + ibase + (long long)s * istride] : 0.0;
+    }
+    __syncthreads();
+
+    auto prim_at = [&](int q, double* Pq) {
+        Pq[0] = sd[line][F_RHO][q];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) Pq[1 + c] = sd[line][F_U + c][q];
+        Pq[M - 1] = sd[line][F_P][q];
+    };
+    auto node_at = [&](int q) {
+        NodeRHD<NU> nd;
+        nd.rho = sd[line][F_RHO][q];
+        nd.p = sd[line][F_P][q];
+        nd.beta = sd[line][F_BETA][q];
+        nd.W = sd[line][F_W][q];
+        nd.lr = sd[line][F_LR][q];
+        nd.lb = sd[line][F_LB][q];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) nd.u[c] = sd[line][F_U + c][q];
+        return nd;
+    };
+
+    // ---- pairs (s', s'+n), s' = s0 - 3 + lane, slot of s' = lane + 2
+    const int o = lane;                            // output lane: position s0 + o
+    double acc[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) acc[c] = 0.0;
+    {
+        const int ql = lane + 2;
+        double Pl[M], al[NA];
+        if (lane < ASEG + 3) {
+            prim_at(ql, Pl);
+#pragma unroll
+            for (int c = 0; c < NA; ++c) al[c] = sd[line][F_A + c][ql];
+        }
+#pragma unroll 1
+        for (int nn = 1; nn <= 3; ++nn) {
+            double gl[M], gr[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) { gl[c] = 0.0; gr[c] = 0.0; }
+            if (active && lane < ASEG + 3) {
+                const int qr = ql + nn;
+                double w[M];
+                bool any = false;
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    w[c] = alpha3(nn) * idxi * (sl[line][c][qr] - sl[line][c][ql]);
+                    any |= w[c] != 0.0;
+                }
+                if (any) {
+                    double Pr[M], ar[NA];
+                    prim_at(qr, Pr);
+#pragma unroll
+                    for (int c = 0; c < NA; ++c) ar[c] = sd[line][F_A + c][qr];
+                    pair_vjp_rhd<NU>(G, Pl, Pr, al, ar, w, gl, gr);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                buf[line][nn - 1][c][lane] = gl[c];
+                buf[line][3 + nn - 1][c][lane] = gr[c];
+            }
+        }
+    }
+    __syncthreads();
+    if (o < ASEG) {
+#pragma unroll
+        for (int nn = 1; nn <= 3; ++nn)
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                acc[c] += buf[line][nn - 1][c][o + 3] + buf[line][3 + nn - 1][c][o + 3 - nn];
+    }
+
+    if (ES) {
+        __syncthreads();
+        // ---- faces f = s0 - 3 + lane (stencil slots lane .. lane + 5)
+        double gf[6][M];
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+#pragma unroll
+            for (int c = 0; c < M; ++c) gf[j][c] = 0.0;
+        if (active && lane < ASEG + 5) {
+            double z[M];
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                z[c] = 0.5 * idxi * (sl[line][c][lane + 2] - sl[line][c][lane + 3]);
+                any |= z[c] != 0.0;
+            }
+            if (any) {
+                NodeRHD<NU> st[6];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) st[j] = node_at(lane + j);
+                double al[NA], ar[NA];
+#pragma unroll
+                for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane + 2]; ar[c] = sd[line][F_A + c][lane + 3]; }
+                face_vjp_rhd<DIM>(G, eps, st, al, ar, z, gf);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+#pragma unroll
+            for (int c = 0; c < M; ++c) buf[line][j][c][lane] = gf[j][c];
+        __syncthreads();
+        if (o < ASEG) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+#pragma unroll
+                for (int c = 0; c < M; ++c) acc[c] += buf[line][j][c][o + 5 - j];
+        }
+    }
+
+    const int s = s0 + o;
+    if (active && o < ASEG && s < s_end) {
+        const long long idx = pbase + (long long)s * pstride;
+#pragma unroll
+        for (int c = 0; c < M; ++c) gout[c * P + idx] = acc[c];
+    }
+}
+
+// Cotangents of the padded primitive states, one slab (M comps, padded layout)
+// per direction; only positions along lines through interior transverse
+// coordinates are written.
+template <int DIM, bool ES>
+__global__ void __launch_bounds__(128) k_residual_vjp(GridDev g, double G, double eps,
+                                                      const double* __restrict__ prim,
+                                                      const double* __restrict__ met,
+                                                      const double* __restrict__ lam,
+                                                      double* __restrict__ gdir, AdjPlan pl) {
+    constexpr int M = DIM + 2;
+    __shared__ AdjLDS<DIM> lds;
+    const long long slab = (long long)M * g.pnodes;
+    int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    if (b < pl.nblk[0]) {
+        residual_vjp_segment<DIM, 0, ES>(g, G, eps, prim, met, lam, gdir, b, pl.nseg[0], pl.nlines[0], lds);
+        return;
+    }
+    b -= pl.nblk[0];
+    if (DIM == 2 || b < pl.nblk[1]) {
+        residual_vjp_segment<DIM, 1, ES>(g, G, eps, prim, met, lam, gdir + slab, b, pl.nseg[1], pl.nlines[1], lds);
+        return;
+    }
+    b -= pl.nblk[1];
+    if (DIM == 3)
+        residual_vjp_segment<DIM, 2, ES>(g, G, eps, prim, met, lam, gdir + 2 * slab, b, pl.nseg[2], pl.nlines[2], lds);
+}
+
+// Solve A^T y = b for a small dense A (n x n, row-major) by Gaussian elimination
+// with partial pivoting on A^T.
+template <int n>
+__device__ __forceinline__ void solve_transposed(double A[n][n], const double* b, double* y) {
+    double Mx[n][n + 1];
+#pragma unroll
+    for (int r = 0; r < n; ++r) {
+#pragma unroll
+        for (int c = 0; c < n; ++c) Mx[r][c] = A[c][r];
+        Mx[r][n] = b[r];
+    }
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        double best = fabs(Mx[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < n; ++r)
+            if (fabs(Mx[r][k]) > best) { best = fabs(Mx[r][k]); piv = r; }
+        if (piv != k) {
+#pragma unroll
+            for (int r = k + 1; r < n; ++r) {
+                if (r == piv) {
+#pragma unroll
+                    for (int c = 0; c <= n; ++c) { const double t = Mx[k][c]; Mx[k][c] = Mx[r][c]; Mx[r][c] = t; }
+                }
+            }
+        }
+        const double ik = 1.0 / Mx[k][k];
+#pragma unroll
+        for (int r = k + 1; r < n; ++r) {
+            const double f = Mx[r][k] * ik;
+#pragma unroll
+            for (int c = k; c <= n; ++c) Mx[r][c] -= f * Mx[k][c];
+        }
+    }
+#pragma unroll
+    for (int k = n - 1; k >= 0; --k) {
+        double s = Mx[k][n];
+#pragma unroll
+        for (int c = k + 1; c < n; ++c) s -= Mx[k][c] * y[c];
+        y[k] = s / Mx[k][k];
+    }
+}
+
+// Fold ghost cotangents onto the interior nodes they copy and pull back through
+// con2prim (implicit-function rule) and U = Ucurv / J:
+//   g_Ubar = (dUbar/dP)^{-T} g_P,  g_Ucurv = g_Ubar / J,  g_J = -(g_Ubar . Ucurv) / J^2.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_fold_con2prim_vjp(GridDev g, double G,
+                                                           const double* __restrict__ prim,
+                                                           const double* __restrict__ U,
+                                                           const double* __restrict__ J,
+                                                           const double* __restrict__ gdir,
+                                                           double* __restrict__ gU,
+                                                           double* __restrict__ gJ) {
+    constexpr int NU = DIM, M = DIM + 2;
+    int i, j, k;
+    if (!box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) return;
+    const long long P = g.pnodes, N = g.nodes;
+    const long long slab = (long long)M * P;
+    const long long pi0 = pidx(g, i, j, k);
+    double gP[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) gP[c] = 0.0;
+    const int ijk[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double* gd = gdir + d * slab;
+        const long long str = d == 0 ? 1 : (d == 1 ? (long long)g.P[0] : (long long)g.P[0] * g.P[1]);
+        const int n = g.n[d], me = ijk[d];
+#pragma unroll
+        for (int c = 0; c < M; ++c) gP[c] += gd[c * P + pi0];
+        // ghost positions along d that copy this node
+#pragma unroll
+        for (int q = 0; q < 2 * NG; ++q) {
+            const int gpos = q < NG ? q - NG : n + (q - NG);
+            if (map_sol(gpos, n, g.bc[d]) == me) {
+                const long long gi = pi0 + (long long)(gpos - me) * str;
+#pragma unroll
+                for (int c = 0; c < M; ++c) gP[c] += gd[c * P + gi];
+            }
+        }
+    }
+    // dUbar/dP at the node, P = (rho, u, p): D = rho W, m = (rho + c0 p) W u,
+    // E = (rho + c0 p) W^2 - p
+    const double rho = prim[pi0], p = prim[(M - 1) * P + pi0];
+    double u[NU], uu = 0.0;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) { u[c] = prim[(1 + c) * P + pi0]; uu += u[c] * u[c]; }
+    const double W = sqrt(1.0 + uu), iW = 1.0 / W;
+    const double c0 = G / (G - 1.0);
+    const double rh = rho + c0 * p;
+    double A[M][M];
+    A[0][0] = W;
+#pragma unroll
+    for (int l = 0; l < NU; ++l) A[0][1 + l] = rho * u[l] * iW;
+    A[0][M - 1] = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < NU; ++kk) {
+        A[1 + kk][0] = W * u[kk];
+#pragma unroll
+        for (int l = 0; l < NU; ++l) A[1 + kk][1 + l] = rh * (u[l] * u[kk] * iW + (l == kk ? W : 0.0));
+        A[1 + kk][M - 1] = c0 * W * u[kk];
+    }
+    A[M - 1][0] = W * W;
+#pragma unroll
+    for (int l = 0; l < NU; ++l) A[M - 1][1 + l] = 2.0 * rh * u[l];
+    A[M - 1][M - 1] = c0 * W * W - 1.0;
+    double y[M];
+    solve_transposed<M>(A, gP, y);
+    const long long t = iidx(g, i, j, k);
+    const double Jv = J[t], iJ = 1.0 / Jv;
+    double gj = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        gU[c * N + t] = y[c] * iJ;
+        gj -= y[c] * U[c * N + t];
+    }
+    gJ[t] = gj * iJ * iJ;
+}
+
+// RK3 reverse sweep, elementwise over U (nU values) and J (nJ values).
+// pre:  lamL = cL dt lam (U part), acc (=|+=) cA lam
+__global__ void k_adj_pre(long long nU, long long nJ, double cL, double cA, int first,
+                          const double* __restrict__ dt_dev, const double* __restrict__ lamU,
+                          const double* __restrict__ lamJ, double* __restrict__ lamL,
+                          double* __restrict__ accU, double* __restrict__ accJ) {
+    const long long t = gtid();
+    if (t >= nU + nJ) return;
+    if (t < nU) {
+        lamL[t] = cL * dt_dev[0] * lamU[t];
+        accU[t] = (first ? 0.0 : accU[t]) + cA * lamU[t];
+    } else {
+        const long long q = t - nU;
+        accJ[q] = (first ? 0.0 : accJ[q]) + cA * lamJ[q];
+    }
+}
+
+// post: lam = cK lam + g
+__global__ void k_adj_post(long long nU, long long nJ, double cK, double* __restrict__ lamU,
+                           double* __restrict__ lamJ, const double* __restrict__ gU,
+                           const double* __restrict__ gJ) {
+    const long long t = gtid();
+    if (t >= nU + nJ) return;
+    if (t < nU) lamU[t] = cK * lamU[t] + gU[t];
+    else { const long long q = t - nU; lamJ[q] = cK * lamJ[q] + gJ[q]; }
+}
+
+// final: out = acc + lam + g
+__global__ void k_adj_final(long long nU, long long nJ, const double* __restrict__ accU,
+                            const double* __restrict__ accJ, const double* __restrict__ lamU,
+                            const double* __restrict__ lamJ, const double* __restrict__ gU,
+                            const double* __restrict__ gJ, double* __restrict__ outU,
+                            double* __restrict__ outJ) {
+    const long long t = gtid();
+    if (t >= nU + nJ) return;
+    if (t < nU) outU[t] = accU[t] + lamU[t] + gU[t];
+    else { const long long q = t - nU; outJ[q] = accJ[q] + lamJ[q] + gJ[q]; }
+}
+
+template <int DIM>
+static void residual_vjp_all(const es_ctx* c, const double* prim, const double* met,
+                             const double* lam, double* gdir, hipStream_t s) {
+    const GridDev& g = c->g;
+    AdjPlan pl{};
+    long long nb = 0;
+    for (int d = 0; d < DIM; ++d) {
+        pl.nseg[d] = (g.n[d] + 2 * NG + ASEG - 1) / ASEG;
+        long long nl = 1;
+        for (int a = 0; a < DIM; ++a)
+            if (a != d) nl *= g.n[a];
+        pl.nlines[d] = nl;
+        pl.nblk[d] = (int)(((nl + ALINES - 1) / ALINES) * pl.nseg[d]);
+        nb += pl.nblk[d];
+    }
+    const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
+    const unsigned thr = 64 * ALINES;
+    if (c->scheme.dissipation != 0)
+        k_residual_vjp<DIM, true><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
+    else
+        k_residual_vjp<DIM, false><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
+}
+
+}  // namespace
+
+hipError_t launch_state_residual_vjp(const es_ctx* c, const double* U, const double* J,
+                                     const double* met, const double* lam, double* gU, double* gJ,
+                                     hipStream_t s) {
+    hipError_t e = launch_con2prim(c, U, J, c->prim, 0, s);
+    if (e != hipSuccess) return e;
+    if (c->g.dim == 2) residual_vjp_all<2>(c, c->prim, met, lam, c->gdir, s);
+    else residual_vjp_all<3>(c, c->prim, met, lam, c->gdir, s);
+    const GridDev& g = c->g;
+    const dim3 gr = box_grid(g.n[0], g.n[1], g.n[2]);
+    if (g.dim == 2) k_fold_con2prim_vjp<2><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
+    else k_fold_con2prim_vjp<3><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk3_vjp(const es_ctx* c, const double* ckpt, const double* lamU_in,
+                          const double* lamJ_in, double* gU_out, double* gJ_out, hipStream_t s) {
+    const GridDev& g = c->g;
+    const long long N = g.nodes, nU = N * c->m, nJ = N;
+    const Checkpoint k = checkpoint_layout(c, ckpt);
+    static const double coef[3] = {0.0, 1.0, 0.5};
+    // stage 2: U3 = 1/3 U0 + 2/3 (U2 + dt L2)
+    // stage 1: U2 = 3/4 U0 + 1/4 (U1 + dt L1)
+    // stage 0: U1 = U0 + dt L0
+    static const double cL[3] = {1.0, 0.25, 2.0 / 3.0};
+    static const double cA[3] = {0.0, 0.75, 1.0 / 3.0};
+    static const double cK[3] = {1.0, 0.25, 2.0 / 3.0};
+    hipError_t e = launch_copy(c->adj_lamU, lamU_in, nU, s);
+    if (e == hipSuccess) e = launch_copy(c->adj_lamJ, lamJ_in, nJ, s);
+    if (e != hipSuccess) return e;
+    for (int st = 2; st >= 0; --st) {
+        k_adj_pre<<<grid_for(nU + nJ), TPB, 0, s>>>(nU, nJ, cL[st], cA[st], st == 2, k.dt, c->adj_lamU,
+                                                     c->adj_lamJ, c->adj_lamL, c->adj_accU, c->adj_accJ);
+        e = launch_metrics(c, k.x, k.xdot, k.dt, coef[st], c->met, nullptr, s);
+        if (e == hipSuccess)
+            e = launch_state_residual_vjp(c, k.U[st], k.J[st], c->met, c->adj_lamL, c->adj_gU, c->adj_gJ, s);
+        if (e != hipSuccess) return e;
+        if (st > 0)
+            k_adj_post<<<grid_for(nU + nJ), TPB, 0, s>>>(nU, nJ, cK[st], c->adj_lamU, c->adj_lamJ, c->adj_gU,
+                                                          c->adj_gJ);
+        else
+            k_adj_final<<<grid_for(nU + nJ), TPB, 0, s>>>(nU, nJ, c->adj_accU, c->adj_accJ, c->adj_lamU,
+                                                           c->adj_lamJ, c->adj_gU, c->adj_gJ, gU_out, gJ_out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace es

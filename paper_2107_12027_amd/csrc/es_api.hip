@@ -144,7 +144,9 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
 es_status es_destroy(es_ctx* c) {
     if (c == nullptr) return ES_EINVAL;
     void* bufs[] = {c->prim, c->met, c->L, c->Us, c->Js, c->xnew, c->xa, c->xb,
-                    c->wa, c->wb, c->xe, c->ve, c->pi, c->red, c->scal, c->fail};
+                    c->wa, c->wb, c->xe, c->ve, c->pi, c->red, c->scal, c->fail,
+                    c->adj_lamU, c->adj_lamJ, c->adj_lamL, c->adj_accU, c->adj_accJ,
+                    c->adj_gU, c->adj_gJ, c->gdir};
     if (c->gexec != nullptr) (void)hipGraphExecDestroy(c->gexec);
     if (c->ev_in != nullptr) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out != nullptr) (void)hipEventDestroy(c->ev_out);
@@ -201,7 +203,16 @@ es_status es_mesh_redistribute(es_ctx* c, const double* prim, const double* x, c
 }
 
 static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double* xdot,
-                              double* dt_dev, const double* fixed_dt_dev, hipStream_t s) {
+                              double* dt_dev, const double* fixed_dt_dev, hipStream_t s,
+                              double* ckpt = nullptr) {
+    const long long N = c->g.nodes, nU = N * c->m, nX = N * c->g.dim;
+    const es::Checkpoint k = ckpt ? es::checkpoint_layout(c, ckpt) : es::Checkpoint{};
+    auto w = [](const double* p) { return const_cast<double*>(p); };
+    if (ckpt) {
+        ES_TRY(es::launch_copy(w(k.U[0]), U, nU, s));
+        ES_TRY(es::launch_copy(w(k.J[0]), J, N, s));
+        ES_TRY(es::launch_copy(w(k.x), x, nX, s));
+    }
     // con2prim (the primitive workspace holds the previous stage and seeds the
     // pressure iteration), metrics on x^n (spatial part), CFL step
     ES_TRY(es::launch_con2prim(c, U, J, c->prim, 1, s));
@@ -212,14 +223,22 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
         ES_TRY(es::launch_mesh(c, c->prim, x, dt_dev, c->xnew, xdot, nullptr, s));
     else
         ES_TRY(es::launch_zero_mesh_velocity(c, x, c->xnew, xdot, s));
+    if (ckpt) {
+        ES_TRY(es::launch_copy(w(k.dt), dt_dev, 1, s));
+        ES_TRY(es::launch_copy(w(k.xdot), xdot, nX, s));
+    }
     static const double coef[3] = {0.0, 1.0, 0.5};
     for (int st = 0; st < 3; ++st) {
         if (st > 0) ES_TRY(es::launch_con2prim(c, c->Us, c->Js, c->prim, 1, s));
         ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s));
         ES_TRY(es::launch_residual_dirs(c, c->prim, c->met, c->L, s));
         ES_TRY(es::launch_rk_combine(c, st, U, J, c->Us, c->Js, c->L, dt_dev, s));
+        if (ckpt && st < 2) {
+            ES_TRY(es::launch_copy(w(k.U[st + 1]), c->Us, nU, s));
+            ES_TRY(es::launch_copy(w(k.J[st + 1]), c->Js, N, s));
+        }
     }
-    ES_TRY(es::launch_copy(x, c->xnew, c->g.nodes * c->g.dim, s));
+    ES_TRY(es::launch_copy(x, c->xnew, nX, s));
     return ES_OK;
 }
 
@@ -260,6 +279,59 @@ es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, 
     ES_TRY(hipEventRecord(c->ev_out, c->cap));
     ES_TRY(hipStreamWaitEvent(s, c->ev_out, 0));
     return ES_OK;
+}
+
+size_t es_ckpt_doubles(const es_ctx* c) { return c ? (size_t)es::checkpoint_doubles(c) : 0; }
+
+es_status es_rk3_step_save(es_ctx* c, double* U, double* J, double* x, double* xdot, double* dt_dev,
+                           const double* fixed_dt_dev, double* ckpt, hipStream_t s) {
+    if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
+        dt_dev == nullptr || ckpt == nullptr)
+        return ES_EINVAL;
+    if (c->scheme.mixed != 0) return ES_EUNSUPPORTED;
+    return enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, s, ckpt);
+}
+
+static es_status ensure_adjoint(es_ctx* c) {
+    if (c->adj_lamU != nullptr) return ES_OK;
+    const size_t N = (size_t)c->g.nodes, m = (size_t)c->m;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = alloc(&c->adj_lamU, N * m);
+    if (e == hipSuccess) e = alloc(&c->adj_lamJ, N);
+    if (e == hipSuccess) e = alloc(&c->adj_lamL, N * m);
+    if (e == hipSuccess) e = alloc(&c->adj_accU, N * m);
+    if (e == hipSuccess) e = alloc(&c->adj_accJ, N);
+    if (e == hipSuccess) e = alloc(&c->adj_gU, N * m);
+    if (e == hipSuccess) e = alloc(&c->adj_gJ, N);
+    if (e == hipSuccess) e = alloc(&c->gdir, (size_t)c->g.pnodes * m * (size_t)c->g.dim);
+    if (e != hipSuccess) return ES_EHIP;
+    // positions the residual VJP does not write (ghost corners) are never read;
+    // clear once so the buffer holds no stale values
+    ES_TRY(es::launch_zero(c->gdir, c->g.pnodes * c->m * c->g.dim, nullptr));
+    ES_TRY(hipDeviceSynchronize());
+    return ES_OK;
+}
+
+es_status es_residual_vjp(es_ctx* c, const double* U, const double* J, const double* met,
+                          const double* lamU, double* gU, double* gJ, hipStream_t s) {
+    if (c == nullptr || U == nullptr || J == nullptr || met == nullptr || lamU == nullptr ||
+        gU == nullptr || gJ == nullptr)
+        return ES_EINVAL;
+    if (c->scheme.mixed != 0) return ES_EUNSUPPORTED;
+    const es_status st = ensure_adjoint(c);
+    if (st != ES_OK) return st;
+    return hip_status(es::launch_state_residual_vjp(c, U, J, met, lamU, gU, gJ, s));
+}
+
+es_status es_rk3_step_vjp(es_ctx* c, const double* ckpt, const double* lamU, const double* lamJ,
+                          double* gU, double* gJ, hipStream_t s) {
+    if (c == nullptr || ckpt == nullptr || lamU == nullptr || lamJ == nullptr || gU == nullptr ||
+        gJ == nullptr)
+        return ES_EINVAL;
+    if (c->scheme.mixed != 0) return ES_EUNSUPPORTED;
+    const es_status st = ensure_adjoint(c);
+    if (st != ES_OK) return st;
+    return hip_status(es::launch_rk3_vjp(c, ckpt, lamU, lamJ, gU, gJ, s));
 }
 
 es_status es_set_graph(es_ctx* c, int enable) {

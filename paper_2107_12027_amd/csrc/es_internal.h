@@ -33,6 +33,15 @@ struct es_ctx {
     double* scal;   // device scalars: [0] dt, [1] gmax, [2] dtau, [3..] spare
     unsigned long long* fail;   // [0] count inadmissible, [1] count no-convergence, [2] first index
     int red_blocks;
+    // adjoint workspace (allocated by the first adjoint call)
+    double* adj_lamU;   // interior, m comps: cotangent of the current stage state
+    double* adj_lamJ;   // interior
+    double* adj_lamL;   // interior, m comps: cotangent of the stage residual
+    double* adj_accU;   // interior, m comps: accumulated cotangent of U^n
+    double* adj_accJ;   // interior
+    double* adj_gU;     // interior, m comps: stage residual VJP
+    double* adj_gJ;     // interior
+    double* gdir;       // padded, d slabs of m comps: primitive cotangents by direction
     // HIP graph of one es_rk3_step (replayed while the argument pointers stay the same)
     int use_graph;
     hipStream_t cap;            // capture / replay stream (default priority)
@@ -76,6 +85,39 @@ hipError_t launch_diagnostics(const es_ctx* c, const double* prim, const double*
                               const double* J, const double* dU, const double* dJ, double* out,
                               hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t s);
+
+// Checkpoint of one RK3 step for the adjoint (one caller buffer of
+// checkpoint_doubles() doubles): stage states U^(0..2) (m comps each), J^(0..2),
+// the mesh x^n and its velocity (d comps each) and the time step.
+struct Checkpoint {
+    const double* U[3];
+    const double* J[3];
+    const double* x;
+    const double* xdot;
+    const double* dt;
+};
+inline long long checkpoint_doubles(const es_ctx* c) {
+    const long long N = c->g.nodes;
+    return 3 * (long long)(c->m + 1) * N + 2LL * c->g.dim * N + 1;
+}
+inline Checkpoint checkpoint_layout(const es_ctx* c, const double* base) {
+    const long long N = c->g.nodes;
+    Checkpoint k;
+    for (int s = 0; s < 3; ++s) k.U[s] = base + (long long)s * c->m * N;
+    const double* j0 = base + 3LL * c->m * N;
+    for (int s = 0; s < 3; ++s) k.J[s] = j0 + (long long)s * N;
+    k.x = j0 + 3 * N;
+    k.xdot = k.x + (long long)c->g.dim * N;
+    k.dt = k.xdot + (long long)c->g.dim * N;
+    return k;
+}
+// VJP of L(U, J) = residual(con2prim(U, J), met) (state part): gU, gJ = (dL/d(U, J))^T lam
+hipError_t launch_state_residual_vjp(const es_ctx* c, const double* U, const double* J,
+                                     const double* met, const double* lam, double* gU, double* gJ,
+                                     hipStream_t s);
+// VJP of one RK3 step with the mesh trajectory and the time step held fixed
+hipError_t launch_rk3_vjp(const es_ctx* c, const double* ckpt, const double* lamU_in,
+                          const double* lamJ_in, double* gU_out, double* gJ_out, hipStream_t s);
 hipError_t launch_zero(double* p, long long n, hipStream_t s);
 
 }  // namespace es

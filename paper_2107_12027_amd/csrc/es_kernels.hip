@@ -11,43 +11,12 @@
 #include <math.h>
 
 #include "es_internal.h"
+#include "es_launch.h"
 #include "es_rhd.h"
 
 namespace es {
 
 namespace {
-
-constexpr int TPB = 256;
-constexpr int BX = 64, BY = 4;
-
-inline unsigned grid_for(long long n, int tpb = TPB) {
-    return (unsigned)((n + tpb - 1) / tpb);
-}
-
-inline dim3 box_grid(int e0, int e1, int e2) {
-    return dim3((unsigned)((e0 + BX - 1) / BX), (unsigned)((e1 + BY - 1) / BY), (unsigned)e2);
-}
-
-inline dim3 box_block() { return dim3(BX, BY, 1); }
-
-__device__ __forceinline__ long long gtid() {
-    return (long long)blockIdx.x * blockDim.x + threadIdx.x;
-}
-
-// (i, j, k) of this thread in the box [lo, lo + e); false outside
-__device__ __forceinline__ bool box_ijk(int lo0, int lo1, int lo2, int e0, int e1, int& i, int& j,
-                                        int& k) {
-    i = lo0 + (int)(blockIdx.x * BX + threadIdx.x);
-    j = lo1 + (int)(blockIdx.y * BY + threadIdx.y);
-    k = lo2 + (int)blockIdx.z;
-    return i < lo0 + e0 && j < lo1 + e1;
-}
-
-__device__ __forceinline__ int flat_block() {
-    return (int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
-}
-
-__device__ __forceinline__ int flat_tid() { return (int)(threadIdx.y * blockDim.x + threadIdx.x); }
 
 // index in the mesh-extension box (6 layers beyond the interior on active axes)
 __device__ __forceinline__ long long eidx(const GridDev& g, int i, int j, int k) {
@@ -310,16 +279,6 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
 constexpr int SEG = 61;            // interior nodes per line segment
 constexpr int NLOAD = SEG + 6;     // loaded slots (3-node halo each side)
 constexpr int LINES = 4;           // line segments (wavefronts) per block
-
-// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8), each
-// with its own L2.  The logical block index gives every XCD one contiguous range
-// of logical blocks, so neighbouring lines, whose halos and cache lines overlap,
-// are read through the same L2.
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    const int x = b & 7, k = b >> 3;
-    const int q = nb >> 3, r = nb & 7;
-    return x * q + min(x, r) + k;
-}
 
 template <int DIM>
 struct ResidualLDS {

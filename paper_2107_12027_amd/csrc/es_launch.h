@@ -1,0 +1,53 @@
+// Launch-shape helpers shared by the kernel files: 256-thread 1D grids and
+// 64 x 4 box grids over an index box (no integer division in the index map).
+#pragma once
+
+#include "es_common.h"
+
+namespace es {
+namespace {
+
+constexpr int TPB = 256;
+constexpr int BX = 64, BY = 4;
+
+inline unsigned grid_for(long long n, int tpb = TPB) {
+    return (unsigned)((n + tpb - 1) / tpb);
+}
+
+inline dim3 box_grid(int e0, int e1, int e2) {
+    return dim3((unsigned)((e0 + BX - 1) / BX), (unsigned)((e1 + BY - 1) / BY), (unsigned)e2);
+}
+
+inline dim3 box_block() { return dim3(BX, BY, 1); }
+
+__device__ __forceinline__ long long gtid() {
+    return (long long)blockIdx.x * blockDim.x + threadIdx.x;
+}
+
+// (i, j, k) of this thread in the box [lo, lo + e); false outside
+__device__ __forceinline__ bool box_ijk(int lo0, int lo1, int lo2, int e0, int e1, int& i, int& j,
+                                        int& k) {
+    i = lo0 + (int)(blockIdx.x * BX + threadIdx.x);
+    j = lo1 + (int)(blockIdx.y * BY + threadIdx.y);
+    k = lo2 + (int)blockIdx.z;
+    return i < lo0 + e0 && j < lo1 + e1;
+}
+
+__device__ __forceinline__ int flat_block() {
+    return (int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+}
+
+__device__ __forceinline__ int flat_tid() { return (int)(threadIdx.y * blockDim.x + threadIdx.x); }
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8), each
+// with its own L2.  The logical block index gives every XCD one contiguous range
+// of logical blocks, so neighbouring lines, whose halos and cache lines overlap,
+// are read through the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, k = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + k;
+}
+
+}  // namespace
+}  // namespace es

@@ -56,20 +56,21 @@ __device__ __forceinline__ float xexp(float x) { return __expf(x); }
 __device__ __forceinline__ float xlog(float x) { return __logf(x); }
 #endif
 
-__device__ __forceinline__ double log_mean(double al, double ar, double lnal, double lnar) {
-    const double s = al + ar;
-    const double dif = al - ar;
+template <typename R>
+__device__ __forceinline__ R log_mean(R al, R ar, R lnal, R lnar) {
+    const R s = al + ar;
+    const R dif = al - ar;
     if (dif * dif < 1e-2 * (s * s)) {
-        const double f = dif * frcp(s);
-        const double u = f * f;
-        double F = 1.0 / 15.0;
-        F = fma(F, u, 1.0 / 13.0);
-        F = fma(F, u, 1.0 / 11.0);
-        F = fma(F, u, 1.0 / 9.0);
-        F = fma(F, u, 1.0 / 7.0);
-        F = fma(F, u, 1.0 / 5.0);
-        F = fma(F, u, 1.0 / 3.0);
-        F = fma(F, u, 1.0);
+        const R f = dif * frcp(s);
+        const R u = f * f;
+        R F = R(1.0 / 15.0);
+        F = fma(F, u, R(1.0 / 13.0));
+        F = fma(F, u, R(1.0 / 11.0));
+        F = fma(F, u, R(1.0 / 9.0));
+        F = fma(F, u, R(1.0 / 7.0));
+        F = fma(F, u, R(1.0 / 5.0));
+        F = fma(F, u, R(1.0 / 3.0));
+        F = fma(F, u, R(1.0));
         return 0.5 * s * frcp(F);
     }
     return dif * frcp(lnal - lnar);
@@ -89,17 +90,17 @@ struct NodeRHD {
 //   C = {W} (a0 rho^ln + {rho}/{beta}) / ({W}^2 - |{u}|^2),  a0 = 1 + 1/((Gamma-1) beta^ln),
 // the solution of [V].U~ = [phi], [V].F~_j = [psi_j] with phi = rho W, psi_j = rho u_j.
 // Also returns the VCL pair value a_t (eq. MetricsFlux_O2).
-template <int NU>
-__device__ __forceinline__ void pair_flux_rhd(double G, const NodeRHD<NU>& l, const NodeRHD<NU>& r,
-                                              const double* al, const double* ar, double* F,
+template <int NU, typename R>
+__device__ __forceinline__ void pair_flux_rhd(double G, const NodeRHD<NU, R>& l, const NodeRHD<NU, R>& r,
+                                              const double* al, const double* ar, R* F,
                                               double& Jt) {
-    const double rho_ln = log_mean(l.rho, r.rho, l.lr, r.lr);
-    const double beta_ln = log_mean(l.beta, r.beta, l.lb, r.lb);
-    const double rho_m = 0.5 * (l.rho + r.rho);
-    const double beta_m = 0.5 * (l.beta + r.beta);
-    const double W_m = 0.5 * (l.W + r.W);
-    double um[NU];
-    double uu = 0.0, un = 0.0;
+    const R rho_ln = log_mean(l.rho, r.rho, l.lr, r.lr);
+    const R beta_ln = log_mean(l.beta, r.beta, l.lb, r.lb);
+    const R rho_m = 0.5 * (l.rho + r.rho);
+    const R beta_m = 0.5 * (l.beta + r.beta);
+    const R W_m = 0.5 * (l.W + r.W);
+    R um[NU];
+    R uu = R(0.0), un = R(0.0);
     const double at = 0.5 * (al[0] + ar[0]);
     double ab[NU];
 #pragma unroll
@@ -109,14 +110,14 @@ __device__ __forceinline__ void pair_flux_rhd(double G, const NodeRHD<NU>& l, co
         uu += um[k] * um[k];
         un += ab[k] * um[k];
     }
-    const double a0 = 1.0 + frcp((G - 1.0) * beta_ln);
-    const double iden = frcp(W_m * W_m - uu);
-    const double pb = rho_m * frcp(beta_m);
-    const double U1 = rho_ln * W_m;
-    const double U5 = (a0 * U1 * W_m + pb * uu) * iden;
-    const double C = W_m * (a0 * rho_ln + pb) * iden;
+    const R a0 = 1.0 + frcp((G - 1.0) * beta_ln);
+    const R iden = frcp(W_m * W_m - uu);
+    const R pb = rho_m * frcp(beta_m);
+    const R U1 = rho_ln * W_m;
+    const R U5 = (a0 * U1 * W_m + pb * uu) * iden;
+    const R C = W_m * (a0 * rho_ln + pb) * iden;
     F[0] = rho_ln * (at * W_m + un);
-    const double s = (at * (U5 + pb) + C * un) * frcp(W_m);
+    const R s = (at * (U5 + pb) + C * un) * frcp(W_m);
 #pragma unroll
     for (int k = 0; k < NU; ++k) F[1 + k] = um[k] * s + ab[k] * pb;
     F[NU + 1] = at * U5 + C * un;
@@ -318,7 +319,7 @@ __device__ __forceinline__ void tangent_rhd(R c0, R c1, const FaceRHD<DIM, R>& f
 
 // Rotation T_0 with first row n (Section 4), read with atan2 semantics:
 // row 2 = (-n2, n1, 0)/rho_perp, row 3 = (-n3 n1/rho_perp, -n3 n2/rho_perp, rho_perp),
-// rho_perp = xsqrt(n1^2 + n2^2); rows (0,1,0), (-n3,0,0) when rho_perp = R(0.)
+// rho_perp = sqrt(n1^2 + n2^2); rows (0,1,0), (-n3,0,0) when rho_perp = 0.
 template <int DIM, typename R>
 __device__ __forceinline__ void rotation(const R* n, R T[3][3]) {
     if (DIM == 2) {
@@ -339,62 +340,21 @@ __device__ __forceinline__ void rotation(const R* n, R T[3][3]) {
     }
 }
 
-// Entropy-stable dissipation d = lambda^ T^{-1} R Y <<V~>> at one face
-// (eq. ESFlux_HO).  nd[0..5] are the stencil nodes i-2..i+3 of the face
-// i+1/2; al, ar the metric vectors (a_t, a_1..a_d) of nodes i and i+R(1.)
-//  * face state: the state whose entropy variables are the mean of those of
-//    nodes i and i+1 (A0 at that state turns [V] into the midpoint rule for [U]);
-//    face metrics: arithmetic mean (readings of this build);
-//  * lambda^ = max |a_t + L lambda_m|, lambda_+- closed form, lambda_0 = v_n;
-//  * R: acoustic columns from the primitive eigenvector (scaled by lambda - v_n)
-//      dp = lambda - v_n, drho = dp/(h c^2), dv_n = (1 - v_n lambda)/(rho h W^2),
-//      dv_t = -v_t (dh + h W^2 v_n dv_n)/(h (1 + W^2 |v_t|^2))   [d(h W v_t) = 0],
-//    normalised by xsqrt(dU.dV) so that R R^T = dU/dV; the v_n cluster
-//    (basis e_rho, e_vt) is replaced by its canonical A0^{-1}-orthonormal basis
-//    from the cluster projector applied to the seeds e_D, e_{m_t1}(, e_{m_t2}),
-//    computed in the coefficient space of the cluster basis with the Gram
-//    matrix G_ab = dU_a . dV_b;
-//  * WENO5-JS of V~ = R^T T V on both sides, Y_l = [<<V~_l>> [V~_l] > 0], with a
-//    jump [V~_l] below Y_TOL |r_l|_1 (|T V_i|_max + |T V_i+1|_max) counted as
-//    zero (sign(0) at rounding level).
-template <int DIM, typename R>
-__device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>* nd,
-                                              const R* al, const R* ar, R* d) {
+// Face state and scaled eigenvectors at one face (rotated frame): from the
+// rotated entropy variables V2, V3 of nodes i and i+1 and the face metrics
+// (a_t, L = |a_x|) returns lambda^ and calls col(r, q) for each column r of R,
+// q = 0: acoustic lambda_-, q = 1: acoustic lambda_+, q = 2..: the v_n cluster.
+template <int DIM, typename R, typename Col>
+__device__ __forceinline__ R face_eigen_columns(R G, const R* V2, const R* V3, R at, R L, Col&& col) {
     constexpr int M = DIM + 2;
     constexpr int NC = DIM;          // cluster size (entropy + transverse shear waves)
-    const R at = R(0.5) * (al[0] + ar[0]);
-    R ax[3] = {R(0.0), R(0.0), R(0.0)};
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) ax[j] = R(0.5) * (al[1 + j] + ar[1 + j]);
-    const R L = xsqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
-    const R iL = frcp(L);
-    R nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
-    R T[3][3];
-    rotation<DIM>(nrm, T);
-
-    // rotated entropy variables T V of the six stencil nodes
-    R TV[6][M];
     const R c0 = G / (G - R(1.0)), c1 = R(1.0) / (G - R(1.0));
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const NodeRHD<DIM, R>& q = nd[j];
-        TV[j][0] = c0 + q.lr + q.lb * c1 + q.beta;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            R s = R(0.0);
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) s += T[a][b] * q.u[b];
-            TV[j][1 + a] = q.beta * s;
-        }
-        TV[j][M - 1] = -q.beta * q.W;
-    }
-
     // face state in the rotated frame: the state whose entropy variables are the
     // mean of those of nodes i and i+1 (beta^2 = V_E^2 - |V_u|^2, u = V_u/beta,
     // W = -V_E/beta, ln rho = V_1 - G/(G-1) - ln(beta)/(G-1) - beta, p = rho/beta)
     R Vb[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) Vb[c] = R(0.5) * (TV[2][c] + TV[3][c]);
+    for (int c = 0; c < M; ++c) Vb[c] = R(0.5) * (V2[c] + V3[c]);
     R vu2 = R(0.0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) vu2 += Vb[1 + a] * Vb[1 + a];
@@ -427,38 +387,6 @@ __device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>*
     const R lam_p = (vn * (R(1.0) - cs2) + cs * disc) * iden;
     const R lhat = fmax(fabs(at + L * lam_m), fmax(fabs(at + L * vn), fabs(at + L * lam_p)));
 
-    R dd[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) dd[c] = R(0.0);
-    // rounding scale of the projections r . T V at nodes i and i+1
-    R tv2 = R(0.0), tv3 = R(0.0);
-#pragma unroll
-    for (int c = 0; c < M; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
-    const R tvmax = tv2 + tv3;
-
-    // one column r of R: project, reconstruct, switch, accumulate
-    auto column = [&](const R* r) {
-        R vt[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            R s = R(0.0);
-#pragma unroll
-            for (int c = 0; c < M; ++c) s += r[c] * TV[j][c];
-            vt[j] = s;
-        }
-        const R vm = weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
-        const R vp = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps);
-        const R jw = vp - vm;
-        const R jp = vt[3] - vt[2];
-        // a jump within rounding of zero counts as zero (Y = 0)
-        R r1 = R(0.0);
-#pragma unroll
-        for (int c = 0; c < M; ++c) r1 += fabs(r[c]);
-        if (jw * jp > R(0.0) && fabs(jp) > RealTraits<R>::ytol * r1 * tvmax) {
-#pragma unroll
-            for (int c = 0; c < M; ++c) dd[c] += jw * r[c];
-        }
-    };
 
     // acoustic columns
     const R hW2 = h * W * W;
@@ -488,7 +416,7 @@ __device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>*
         const R sc = frcp(xsqrt(nn));
 #pragma unroll
         for (int c = 0; c < M; ++c) dU[c] *= sc;
-        column(dU);
+        col(dU, s);
     }
 
     // v_n cluster: basis e_rho, e_{v_t1}(, e_{v_t2}) in primitive variables
@@ -578,8 +506,95 @@ __device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>*
             for (int a = 0; a < NC; ++a) s += cq[a] * KU[a][c];
             r[c] = s * sc;
         }
-        column(r);
+        col(r, 2 + q);
     }
+
+    return lhat;
+}
+
+// Entropy-stable dissipation d = lambda^ T^{-1} R Y <<V~>> at one face
+// (eq. ESFlux_HO).  nd[0..5] are the stencil nodes i-2..i+3 of the face
+// i+1/2; al, ar the metric vectors (a_t, a_1..a_d) of nodes i and i+1.
+//  * face state: the state whose entropy variables are the mean of those of
+//    nodes i and i+1 (A0 at that state turns [V] into the midpoint rule for [U]);
+//    face metrics: arithmetic mean (readings of this build);
+//  * lambda^ = max |a_t + L lambda_m|, lambda_+- closed form, lambda_0 = v_n;
+//  * R: acoustic columns from the primitive eigenvector (scaled by lambda - v_n)
+//      dp = lambda - v_n, drho = dp/(h c^2), dv_n = (1 - v_n lambda)/(rho h W^2),
+//      dv_t = -v_t (dh + h W^2 v_n dv_n)/(h (1 + W^2 |v_t|^2))   [d(h W v_t) = 0],
+//    normalised by sqrt(dU.dV) so that R R^T = dU/dV; the v_n cluster
+//    (basis e_rho, e_vt) is replaced by its canonical A0^{-1}-orthonormal basis
+//    from the cluster projector applied to the seeds e_D, e_{m_t1}(, e_{m_t2}),
+//    computed in the coefficient space of the cluster basis with the Gram
+//    matrix G_ab = dU_a . dV_b;
+//  * WENO5-JS of V~ = R^T T V on both sides, Y_l = [<<V~_l>> [V~_l] > 0], with a
+//    jump [V~_l] below Y_TOL |r_l|_1 (|T V_i|_max + |T V_i+1|_max) counted as
+//    zero (sign(0) at rounding level).
+template <int DIM, typename R>
+__device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>* nd,
+                                              const R* al, const R* ar, R* d) {
+    constexpr int M = DIM + 2;
+    const R at = R(0.5) * (al[0] + ar[0]);
+    R ax[3] = {R(0.0), R(0.0), R(0.0)};
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) ax[j] = R(0.5) * (al[1 + j] + ar[1 + j]);
+    const R L = xsqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    const R iL = frcp(L);
+    R nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
+    R T[3][3];
+    rotation<DIM>(nrm, T);
+
+    // rotated entropy variables T V of the six stencil nodes
+    R TV[6][M];
+    const R c0 = G / (G - R(1.0)), c1 = R(1.0) / (G - R(1.0));
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const NodeRHD<DIM, R>& q = nd[j];
+        TV[j][0] = c0 + q.lr + q.lb * c1 + q.beta;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            R s = R(0.0);
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) s += T[a][b] * q.u[b];
+            TV[j][1 + a] = q.beta * s;
+        }
+        TV[j][M - 1] = -q.beta * q.W;
+    }
+
+    R dd[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) dd[c] = R(0.0);
+    // rounding scale of the projections r . T V at nodes i and i+1
+    R tv2 = R(0.0), tv3 = R(0.0);
+#pragma unroll
+    for (int c = 0; c < M; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
+    const R tvmax = tv2 + tv3;
+
+    // one column r of R: project, reconstruct, switch, accumulate
+    auto column = [&](const R* r, int) {
+        R vt[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            R s = R(0.0);
+#pragma unroll
+            for (int c = 0; c < M; ++c) s += r[c] * TV[j][c];
+            vt[j] = s;
+        }
+        const R vm = weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
+        const R vp = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps);
+        const R jw = vp - vm;
+        const R jp = vt[3] - vt[2];
+        // a jump within rounding of zero counts as zero (Y = 0)
+        R r1 = R(0.0);
+#pragma unroll
+        for (int c = 0; c < M; ++c) r1 += fabs(r[c]);
+        if (jw * jp > R(0.0) && fabs(jp) > RealTraits<R>::ytol * r1 * tvmax) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) dd[c] += jw * r[c];
+        }
+    };
+
+    const R lhat = face_eigen_columns<DIM>(G, TV[2], TV[3], at, L, column);
 
     // back to the original frame: d = lambda^ T^{-1} (R Y <<V~>>)
     d[0] = lhat * dd[0];

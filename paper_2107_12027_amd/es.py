@@ -19,7 +19,8 @@ ES_OK, ES_EINVAL, ES_EADMISSIBLE, ES_ENOCONV, ES_EMESH, ES_EHIP, ES_EUNSUPPORTED
 SYMBOLS = ("es_create", "es_destroy", "es_nvars", "es_nprim", "es_nmet", "es_nodes",
            "es_padded_nodes", "es_prim2con", "es_metrics", "es_con2prim", "es_residual",
            "es_cfl", "es_mesh_redistribute", "es_rk3_step", "es_set_graph", "es_diagnostics",
-           "es_ctx_status", "es_status_string")
+           "es_ctx_status", "es_status_string", "es_ckpt_doubles", "es_rk3_step_save",
+           "es_rk3_step_vjp", "es_residual_vjp")
 
 
 class EsError(RuntimeError):
@@ -78,9 +79,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.es_set_graph.argtypes = [vp, ctypes.c_int]
     lib.es_ctx_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(ctypes.c_longlong)]
+    lib.es_ckpt_doubles.argtypes = [vp]
+    lib.es_ckpt_doubles.restype = ctypes.c_size_t
+    lib.es_rk3_step_save.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.es_rk3_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.es_residual_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     for name in ("es_prim2con", "es_metrics", "es_con2prim", "es_residual", "es_cfl",
                  "es_mesh_redistribute", "es_rk3_step", "es_set_graph", "es_diagnostics",
-                 "es_ctx_status"):
+                 "es_ctx_status", "es_rk3_step_save", "es_rk3_step_vjp", "es_residual_vjp"):
         getattr(lib, name).restype = st
     lib.es_status_string.argtypes = [st]
     lib.es_status_string.restype = ctypes.c_char_p
@@ -175,6 +181,21 @@ class Context:
     def rk3_step(self, U, J, x, xdot, dt, fixed_dt=None, stream=None):
         _check(_lib.es_rk3_step(self.h, _ptr(U), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt), _ptr(fixed_dt),
                                 _stream(stream)), "es_rk3_step")
+
+    def ckpt_doubles(self) -> int:
+        return _lib.es_ckpt_doubles(self.h)
+
+    def rk3_step_save(self, U, J, x, xdot, dt, ckpt, fixed_dt=None, stream=None):
+        _check(_lib.es_rk3_step_save(self.h, _ptr(U), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt),
+                                     _ptr(fixed_dt), _ptr(ckpt), _stream(stream)), "es_rk3_step_save")
+
+    def rk3_step_vjp(self, ckpt, lamU, lamJ, gU, gJ, stream=None):
+        _check(_lib.es_rk3_step_vjp(self.h, _ptr(ckpt), _ptr(lamU), _ptr(lamJ), _ptr(gU), _ptr(gJ),
+                                    _stream(stream)), "es_rk3_step_vjp")
+
+    def residual_vjp(self, U, J, met, lamU, gU, gJ, stream=None):
+        _check(_lib.es_residual_vjp(self.h, _ptr(U), _ptr(J), _ptr(met), _ptr(lamU), _ptr(gU), _ptr(gJ),
+                                    _stream(stream)), "es_residual_vjp")
 
     def set_graph(self, enable: bool):
         _check(_lib.es_set_graph(self.h, int(bool(enable))), "es_set_graph")
