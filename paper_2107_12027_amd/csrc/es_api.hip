@@ -73,8 +73,8 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
         if (monitor->form != ES_MON_PAPER && monitor->form != ES_MON_SQGRAD) return ES_EINVAL;
         if (monitor->filter_passes < 0 || monitor->sweeps < 0 || !(monitor->alpha >= 0.0)) return ES_EINVAL;
     }
-    // kernels of this build: RHD, p = 3 (FP64 or FP32-mixed)
-    if (scheme->phys != ES_RHD || scheme->order_p != 3)
+    // kernels of this build: p = 3; RHD in FP64 or FP32-mixed, RMHD in FP64
+    if (scheme->order_p != 3 || (scheme->phys == ES_RMHD && scheme->mixed != 0))
         return ES_EUNSUPPORTED;
 
     es_ctx* c = new (std::nothrow) es_ctx();
@@ -288,7 +288,7 @@ es_status es_rk3_step_save(es_ctx* c, double* U, double* J, double* x, double* x
     if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
         dt_dev == nullptr || ckpt == nullptr)
         return ES_EINVAL;
-    if (c->scheme.mixed != 0) return ES_EUNSUPPORTED;
+    if (c->scheme.mixed != 0 || c->scheme.phys != ES_RHD) return ES_EUNSUPPORTED;
     return enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, s, ckpt);
 }
 
@@ -317,7 +317,7 @@ es_status es_residual_vjp(es_ctx* c, const double* U, const double* J, const dou
     if (c == nullptr || U == nullptr || J == nullptr || met == nullptr || lamU == nullptr ||
         gU == nullptr || gJ == nullptr)
         return ES_EINVAL;
-    if (c->scheme.mixed != 0) return ES_EUNSUPPORTED;
+    if (c->scheme.mixed != 0 || c->scheme.phys != ES_RHD) return ES_EUNSUPPORTED;
     const es_status st = ensure_adjoint(c);
     if (st != ES_OK) return st;
     return hip_status(es::launch_state_residual_vjp(c, U, J, met, lamU, gU, gJ, s));
@@ -328,7 +328,7 @@ es_status es_rk3_step_vjp(es_ctx* c, const double* ckpt, const double* lamU, con
     if (c == nullptr || ckpt == nullptr || lamU == nullptr || lamJ == nullptr || gU == nullptr ||
         gJ == nullptr)
         return ES_EINVAL;
-    if (c->scheme.mixed != 0) return ES_EUNSUPPORTED;
+    if (c->scheme.mixed != 0 || c->scheme.phys != ES_RHD) return ES_EUNSUPPORTED;
     const es_status st = ensure_adjoint(c);
     if (st != ES_OK) return st;
     return hip_status(es::launch_rk3_vjp(c, ckpt, lamU, lamJ, gU, gJ, s));

@@ -86,6 +86,18 @@ hipError_t launch_diagnostics(const es_ctx* c, const double* prim, const double*
                               hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t s);
 
+// RMHD kernels (es_kernels_rmhd.hip), dispatched from the launchers above
+hipError_t launch_prim2con_rmhd(const es_ctx* c, const double* prim, const double* J, double* U,
+                                hipStream_t s);
+hipError_t launch_con2prim_rmhd(const es_ctx* c, const double* U, const double* J, double* prim,
+                                int use_guess, hipStream_t s);
+hipError_t launch_residual_dirs_rmhd(const es_ctx* c, const double* prim, const double* met, double* Ld,
+                                     hipStream_t s);
+hipError_t launch_cfl_partial_rmhd(const es_ctx* c, const double* prim, const double* met,
+                                   const double* J, hipStream_t s);
+hipError_t launch_diag_partial_rmhd(const es_ctx* c, const double* prim, const double* U, const double* J,
+                                    const double* dU, const double* dJ, hipStream_t s);
+
 // Checkpoint of one RK3 step for the adjoint (one caller buffer of
 // checkpoint_doubles() doubles): stage states U^(0..2) (m comps each), J^(0..2),
 // the mesh x^n and its velocity (d comps each) and the time step.

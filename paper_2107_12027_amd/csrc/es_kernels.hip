@@ -23,21 +23,6 @@ __device__ __forceinline__ long long eidx(const GridDev& g, int i, int j, int k)
     return ((long long)(k + g.g6) * g.E[1] + (j + 2 * NG)) * g.E[0] + (i + 2 * NG);
 }
 
-// Block reductions of one double over the whole block (wavefronts of 64).
-template <int OP>   // 0 max, 1 min, 2 sum
-__device__ __forceinline__ double block_reduce(double v, double* sh) {
-    v = OP == 0 ? wave_max(v) : (OP == 1 ? wave_min(v) : wave_sum(v));
-    const int tid = flat_tid();
-    const int w = tid >> 6;
-    if ((tid & 63) == 0) sh[w] = v;
-    __syncthreads();
-    double r = sh[0];
-    const int nw = (int)(blockDim.x * blockDim.y) >> 6;
-    for (int q = 1; q < nw; ++q) r = OP == 0 ? fmax(r, sh[q]) : (OP == 1 ? fmin(r, sh[q]) : r + sh[q]);
-    __syncthreads();
-    return r;
-}
-
 // ---------------------------------------------------------------------------
 // utility kernels
 // ---------------------------------------------------------------------------
@@ -892,6 +877,7 @@ hipError_t launch_copy(double* dst, const double* src, long long n, hipStream_t 
 hipError_t launch_prim2con(const es_ctx* c, const double* prim, const double* J, double* U,
                            hipStream_t s) {
     const double G = c->scheme.gamma;
+    if (c->scheme.phys == ES_RMHD) return launch_prim2con_rmhd(c, prim, J, U, s);
     if (c->g.dim == 2) k_prim2con_rhd<2><<<grid_for(c->g.nodes), TPB, 0, s>>>(c->g, G, prim, J, U);
     else k_prim2con_rhd<3><<<grid_for(c->g.nodes), TPB, 0, s>>>(c->g, G, prim, J, U);
     return hipGetLastError();
@@ -901,6 +887,7 @@ hipError_t launch_con2prim(const es_ctx* c, const double* U, const double* J, do
                            int use_guess, hipStream_t s) {
     const double G = c->scheme.gamma;
     const GridDev& g = c->g;
+    if (c->scheme.phys == ES_RMHD) return launch_con2prim_rmhd(c, U, J, prim, use_guess, s);
     const dim3 gr = box_grid(g.P[0], g.P[1], g.P[2]);
     if (g.dim == 2) k_con2prim_rhd<2><<<gr, box_block(), 0, s>>>(g, G, U, J, prim, use_guess, c->fail);
     else k_con2prim_rhd<3><<<gr, box_block(), 0, s>>>(g, G, U, J, prim, use_guess, c->fail);
@@ -953,6 +940,7 @@ static void residual_all(const es_ctx* c, const double* prim, const double* met,
 
 hipError_t launch_residual_dirs(const es_ctx* c, const double* prim, const double* met, double* Ld,
                                 hipStream_t s) {
+    if (c->scheme.phys == ES_RMHD) return launch_residual_dirs_rmhd(c, prim, met, Ld, s);
     if (c->g.dim == 2) residual_all<2>(c, prim, met, Ld, s);
     else residual_all<3>(c, prim, met, Ld, s);
     return hipGetLastError();
@@ -972,8 +960,14 @@ hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, co
     const GridDev& g = c->g;
     const int nb = interior_blocks(g);
     const double G = c->scheme.gamma;
-    if (g.dim == 2) k_cfl_partial<2><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, c->red);
-    else k_cfl_partial<3><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, c->red);
+    if (c->scheme.phys == ES_RMHD) {
+        const hipError_t e = launch_cfl_partial_rmhd(c, prim, met, J, s);
+        if (e != hipSuccess) return e;
+    } else if (g.dim == 2) {
+        k_cfl_partial<2><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, c->red);
+    } else {
+        k_cfl_partial<3><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, c->red);
+    }
     k_cfl_final<<<1, 256, 0, s>>>(g.dim, nb, c->scheme.cfl, g.dxi[0], g.dxi[1], g.dxi[2],
                                   c->red, fixed_dt_dev, dt_dev);
     return hipGetLastError();
@@ -1044,8 +1038,14 @@ hipError_t launch_diagnostics(const es_ctx* c, const double* prim, const double*
     const GridDev& g = c->g;
     const int nb = interior_blocks(g);
     const double G = c->scheme.gamma;
-    if (g.dim == 2) k_diag_partial<2><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, U, J, dU, dJ, c->red);
-    else k_diag_partial<3><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, U, J, dU, dJ, c->red);
+    if (c->scheme.phys == ES_RMHD) {
+        const hipError_t e = launch_diag_partial_rmhd(c, prim, U, J, dU, dJ, s);
+        if (e != hipSuccess) return e;
+    } else if (g.dim == 2) {
+        k_diag_partial<2><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, U, J, dU, dJ, c->red);
+    } else {
+        k_diag_partial<3><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, U, J, dU, dJ, c->red);
+    }
     k_diag_final<<<1, 256, 0, s>>>(3 + c->m, nb, c->red, out);
     return hipGetLastError();
 }

@@ -49,5 +49,20 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + min(x, r) + k;
 }
 
+// Block reductions of one double over the whole block (wavefronts of 64).
+template <int OP>   // 0 max, 1 min, 2 sum
+__device__ __forceinline__ double block_reduce(double v, double* sh) {
+    v = OP == 0 ? wave_max(v) : (OP == 1 ? wave_min(v) : wave_sum(v));
+    const int tid = flat_tid();
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = sh[0];
+    const int nw = (int)(blockDim.x * blockDim.y) >> 6;
+    for (int q = 1; q < nw; ++q) r = OP == 0 ? fmax(r, sh[q]) : (OP == 1 ? fmin(r, sh[q]) : r + sh[q]);
+    __syncthreads();
+    return r;
+}
+
 }  // namespace
 }  // namespace es

@@ -1,0 +1,683 @@
+// Device physics of the RMHD system: state, conservative variables, flux,
+// entropy variables, conservative-to-primitive recovery, the two-point EC pair
+// flux with its Godunov-Powell source pair, and the ES face dissipation with a
+// numeric scaled eigen-structure.
+//
+// Primitive slots P = (rho, u_1, u_2, u_3, p, B_1, B_2, B_3) with u = W v (all
+// three components kept in 2D), conservative slots U = (D, m_1..3, E, B_1..3).
+#pragma once
+
+#include "es_rhd.h"
+#include "es_dual.h"
+
+namespace es {
+
+// Derived quantities of a primitive state (Section 1): W, v, beta = rho/p,
+// h = 1 + G/(G-1) p/rho, v.B, b^0 = W v.B, b = B/W + W (v.B) v,
+// |b|^2 = |B|^2/W^2 + (v.B)^2.
+template <typename R>
+struct StateRMHD {
+    R rho, p, W, beta, h, vB, b0, bsq, BB;
+    R u[3], v[3], B[3], b[3];
+};
+
+template <typename R>
+__device__ __forceinline__ StateRMHD<R> rmhd_state(double G, const R* P) {
+    StateRMHD<R> s;
+    s.rho = P[0];
+    s.p = P[4];
+    R uu = R(0.0), BB = R(0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        s.u[k] = P[1 + k];
+        s.B[k] = P[5 + k];
+        uu += s.u[k] * s.u[k];
+        BB += s.B[k] * s.B[k];
+    }
+    s.W = xsqrt(R(1.0) + uu);
+    const R iW = R(1.0) / s.W;
+    R vB = R(0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { s.v[k] = s.u[k] * iW; vB += s.v[k] * s.B[k]; }
+    s.vB = vB;
+    s.BB = BB;
+    s.beta = s.rho / s.p;
+    s.h = R(1.0) + (G / (G - 1.0)) * s.p / s.rho;
+    s.b0 = s.W * vB;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.b[k] = s.B[k] * iW + s.W * vB * s.v[k];
+    s.bsq = BB * iW * iW + vB * vB;
+    return s;
+}
+
+// U(P) (eq. RMHDdiv2): D = rho W, m = (Z + |B|^2) v - (v.B) B,
+// E = Z - p - |b|^2/2 + |B|^2, Z = rho h W^2.
+template <typename R>
+__device__ __forceinline__ void rmhd_cons(const StateRMHD<R>& s, R* U) {
+    const R Z = s.rho * s.h * s.W * s.W;
+    U[0] = s.rho * s.W;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) U[1 + k] = (Z + s.BB) * s.v[k] - s.vB * s.B[k];
+    U[4] = Z - s.p - R(0.5) * s.bsq + s.BB;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) U[5 + k] = s.B[k];
+}
+
+// x_1 flux F_1(P) (eq. RMHDdiv2), p_tot = p + |b|^2/2.
+template <typename R>
+__device__ __forceinline__ void rmhd_flux1(const StateRMHD<R>& s, const R* U, R* F) {
+    const R ptot = s.p + R(0.5) * s.bsq;
+    const R iW2 = R(1.0) / (s.W * s.W);
+    F[0] = U[0] * s.v[0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        R val = U[1 + c] * s.v[0] - s.B[0] * (s.B[c] * iW2 + s.vB * s.v[c]);
+        if (c == 0) val = val + ptot;
+        F[1 + c] = val;
+    }
+    F[4] = U[1];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F[5 + c] = s.v[0] * s.B[c] - s.B[0] * s.v[c];
+}
+
+// Entropy variables V = (G/(G-1) + ln rho + ln beta/(G-1) + beta, beta u, -beta W, beta b)
+template <typename R>
+__device__ __forceinline__ void rmhd_entropy_vars(double G, const StateRMHD<R>& s, R* V) {
+    V[0] = (G / (G - 1.0)) + xlog(s.rho) + xlog(s.beta) * (1.0 / (G - 1.0)) + s.beta;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { V[1 + k] = s.beta * s.u[k]; V[5 + k] = s.beta * s.b[k]; }
+    V[4] = -s.beta * s.W;
+}
+
+// Phi'(V) in U slots (eq. Phi): (0, B/W^2 + v (v.B), v.B, v)
+template <typename R>
+__device__ __forceinline__ void rmhd_phi_prime(const StateRMHD<R>& s, R* Pp) {
+    const R iW2 = R(1.0) / (s.W * s.W);
+    Pp[0] = R(0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { Pp[1 + k] = s.B[k] * iW2 + s.v[k] * s.vB; Pp[5 + k] = s.v[k]; }
+    Pp[4] = s.vB;
+}
+
+// Conservative -> primitive (Section 1: a scalar nonlinear equation) in the
+// unknown Z = rho h W^2:  v.B = (m.B)/Z,
+//   |v|^2 = (Z^2 |m|^2 + (m.B)^2 (2Z + |B|^2)) / (Z^2 (Z + |B|^2)^2),
+//   p = (G-1)/G (Z/W^2 - D/W),
+//   f(Z) = Z - p + |B|^2 - |B|^2/(2 W^2) - (m.B)^2/(2 Z^2) - E = 0.
+// Safeguarded Newton (f' by a dual number) on the bracket (0, 2(E+1) + |B|^2],
+// starting from ``guess`` when it lies inside; iterates with |v| >= 1 move the
+// lower end of the bracket.  Returns 0 on success, 1 for an inadmissible state
+// (D <= 0 or p <= 0), 2 without convergence.
+__device__ __forceinline__ int c2p_rmhd(double G, const double* U, double guess, double* P) {
+    const double D = U[0], E = U[4];
+    double mm2 = 0.0, BB = 0.0, mB = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        mm2 += U[1 + k] * U[1 + k];
+        BB += U[5 + k] * U[5 + k];
+        mB += U[1 + k] * U[5 + k];
+    }
+    if (!(D > 0.0) || !(E > 0.0)) return 1;
+    double lo = 0.0, hi = 2.0 * (E + 1.0) + BB;
+    double Z = (guess > lo && guess < hi) ? guess : hi;
+    const double gm1 = (G - 1.0) / G;
+    int conv = 0;
+    using D1 = Dual<1>;
+    for (int it = 0; it < 300; ++it) {
+        const D1 z = D1::seed(Z, 0);
+        const D1 v2 = (z * z * mm2 + mB * mB * (2.0 * z + BB)) / (z * z * (z + BB) * (z + BB));
+        if (!(v2.v < 1.0)) {
+            lo = Z;
+            Z = 0.5 * (lo + hi);
+            if (hi - lo <= 1e-16 * hi) break;
+            continue;
+        }
+        const D1 W2 = 1.0 / (1.0 - v2);
+        const D1 W = xsqrt(W2);
+        const D1 p = gm1 * (z / W2 - D / W);
+        const D1 f = z - p + BB - BB / (2.0 * W2) - mB * mB / (2.0 * z * z) - E;
+        if (f.v == 0.0) { conv = 1; break; }
+        if (f.v < 0.0) lo = Z; else hi = Z;
+        double Zn = Z - f.v / f.d[0];
+        if (!(Zn > lo && Zn < hi)) Zn = 0.5 * (lo + hi);
+        const double dz = fabs(Zn - Z);
+        Z = Zn;
+        if (dz <= 1e-15 * Z || hi - lo <= 1e-15 * hi) { conv = 1; break; }
+    }
+    const double vB = mB / Z;
+    double v[3], v2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { v[k] = (U[1 + k] + vB * U[5 + k]) / (Z + BB); v2 += v[k] * v[k]; }
+    if (!(v2 < 1.0)) return 1;
+    const double W = 1.0 / sqrt(1.0 - v2);
+    const double rho = D / W;
+    const double p = gm1 * (Z / (W * W) - rho);
+    if (!(p > 0.0) || !(p < INFINITY)) return 1;
+    P[0] = rho;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { P[1 + k] = W * v[k]; P[5 + k] = U[5 + k]; }
+    P[4] = p;
+    return conv ? 0 : 2;
+}
+
+// Node data of the residual's line loads: primitive state, logarithms and the
+// derived quantities the pair flux averages.
+struct NodeRMHD {
+    double rho, p, beta, W, lr, lb, b0, Wb0, Wb02, sb, b02;
+    double u[3], B[3], b[3], Wbk2[3], bk2[3];
+};
+
+__device__ __forceinline__ NodeRMHD node_rmhd(double G, const double* P, double lr, double lb) {
+    const StateRMHD<double> s = rmhd_state<double>(G, P);
+    NodeRMHD n;
+    n.rho = s.rho; n.p = s.p; n.beta = s.beta; n.W = s.W; n.lr = lr; n.lb = lb;
+    n.b0 = s.b0;
+    n.Wb0 = s.W * s.b0;
+    n.Wb02 = s.W * s.b0 * s.b0;
+    n.b02 = s.b0 * s.b0;
+    double sb = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        n.u[k] = s.u[k]; n.B[k] = s.B[k]; n.b[k] = s.b[k];
+        n.bk2[k] = s.b[k] * s.b[k];
+        n.Wbk2[k] = s.W * n.bk2[k];
+        sb += n.bk2[k];
+    }
+    n.sb = sb;
+    return n;
+}
+
+// Two-point EC flux for RMHD (eq. ECFluxCurv, eq. UFcircle): F = a_t U~ + sum_j a_j F~_j
+// with U~ the paper's closed form (Section 3.1; R_1 read with the k = 1..3 sum of
+// {W (b^k)^2}/2 - {b^k} U~_{k+5}) and F~_j solving [V].F~_j = [psi_j] - {B_j}[Phi];
+// {.} arithmetic means (of products where products appear), ^ln logarithmic means.
+// Also the source pair B~ = 1/4 sum_j (a_j,l + a_j,r)(B_j,l + B_j,r) (eq. BFlux_O2)
+// and the VCL pair value a_t (eq. MetricsFlux_O2).
+template <int DIM>
+__device__ __forceinline__ void pair_flux_rmhd(double G, const NodeRMHD& l, const NodeRMHD& r,
+                                               const double* al, const double* ar, double* F,
+                                               double& Jt, double& Bt) {
+    const double rho_ln = log_mean(l.rho, r.rho, l.lr, r.lr);
+    const double beta_ln = log_mean(l.beta, r.beta, l.lb, r.lb);
+    const double rho = 0.5 * (l.rho + r.rho), beta = 0.5 * (l.beta + r.beta);
+    const double W = 0.5 * (l.W + r.W), b0 = 0.5 * (l.b0 + r.b0);
+    const double Wb0 = 0.5 * (l.Wb0 + r.Wb0), Wb02 = 0.5 * (l.Wb02 + r.Wb02);
+    const double sb = 0.5 * (l.sb + r.sb), b02 = 0.5 * (l.b02 + r.b02);
+    double u[3], b[3], B[3], Wbk2[3], bk2[3], ujsb[3], ujb02[3];
+    double uu = 0.0, sbk2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        u[k] = 0.5 * (l.u[k] + r.u[k]);
+        b[k] = 0.5 * (l.b[k] + r.b[k]);
+        B[k] = 0.5 * (l.B[k] + r.B[k]);
+        Wbk2[k] = 0.5 * (l.Wbk2[k] + r.Wbk2[k]);
+        bk2[k] = 0.5 * (l.bk2[k] + r.bk2[k]);
+        ujsb[k] = 0.5 * (l.u[k] * l.sb + r.u[k] * r.sb);
+        ujb02[k] = 0.5 * (l.u[k] * l.b02 + r.u[k] * r.b02);
+        uu += u[k] * u[k];
+        sbk2 += bk2[k];
+    }
+    const double iW = 1.0 / W, ib = 1.0 / beta;
+    const double a0 = 1.0 + 1.0 / ((G - 1.0) * beta_ln);
+    const double iden = 1.0 / (W * W - uu);
+    // U~
+    double Ut[8];
+    const double U1 = rho_ln * W;
+    double UB[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) UB[k] = (W * W * b[k] - Wb0 * u[k]) * iW;
+    const double a1 = rho + 0.5 * beta * sbk2 + 0.5 * beta * Wb02 * iW;
+    double R1 = -a0 * U1 - 0.5 * Wb02;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) R1 += 0.5 * Wbk2[k] - b[k] * UB[k];
+    double Rk[3], uR = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { Rk[k] = (a1 * u[k] - beta * Wb0 * b[k]) * iW; uR += u[k] * Rk[k]; }
+    const double Dd = beta * (W * W - uu) * iW;
+    const double U5 = (uR - beta * R1) / Dd;
+    Ut[0] = U1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { Ut[1 + k] = u[k] * U5 * iW + Rk[k] * ib; Ut[5 + k] = UB[k]; }
+    Ut[4] = U5;
+    const double at = 0.5 * (al[0] + ar[0]);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) F[c] = at * Ut[c];
+    double bt = 0.0;
+    // F~_j for the directions of the grid
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+        const double aj = 0.5 * (al[1 + j] + ar[1 + j]);
+        bt += 0.25 * (al[1 + j] + ar[1 + j]) * (l.B[j] + r.B[j]);
+        const double c0 = -beta * (u[j] * b0 + B[j]);
+        const double F1 = rho_ln * u[j];
+        double FB[3], Pk[3], uP = 0.0, bFB = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            FB[k] = u[j] * b[k] + c0 * u[k] * ib * iW;
+            Pk[k] = (c0 * iW) * (b[k] - b0 * u[k] * iW);
+        }
+        Pk[j] += rho + 0.5 * beta * sb - 0.5 * beta * b02;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { uP += u[k] * Pk[k]; bFB += b[k] * FB[k]; }
+        const double Q = 0.5 * ujsb[j] - 0.5 * ujb02[j] - B[j] * b0;
+        const double F5 = W * (a0 * F1 + uP * ib + bFB - Q) * iden;
+        F[0] += aj * F1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { F[1 + k] += aj * (u[k] * F5 * iW + Pk[k] * ib); F[5 + k] += aj * FB[k]; }
+        F[4] += aj * F5;
+    }
+    Jt = at;
+    Bt = bt;
+}
+
+// ---------------------------------------------------------------------------
+// numeric scaled eigen-structure of the (Godunov-Powell modified) x_1 flux
+// Jacobian at a state in the rotated frame
+// ---------------------------------------------------------------------------
+
+// Jacobians dU/dP, dF_1/dP (+ Phi'(V) e_{B_1}^T, the Godunov-Powell term) and
+// dV/dP at the primitive state P by forward-mode dual numbers.
+__device__ __forceinline__ void rmhd_jacobians(double G, const double* P, double JU[8][8],
+                                               double JF[8][8], double JV[8][8], double* Pp) {
+    using D8 = Dual<8>;
+    D8 Pd[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Pd[i] = D8::seed(P[i], i);
+    const StateRMHD<D8> s = rmhd_state<D8>(G, Pd);
+    D8 U[8], F[8], V[8];
+    rmhd_cons<D8>(s, U);
+    rmhd_flux1<D8>(s, U, F);
+    rmhd_entropy_vars<D8>(G, s, V);
+    D8 Ph[8];
+    rmhd_phi_prime<D8>(s, Ph);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        Pp[r] = Ph[r].v;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            JU[r][c] = U[r].d[c];
+            JF[r][c] = F[r].d[c] + (c == 5 ? Ph[r].v : 0.0);
+            JV[r][c] = V[r].d[c];
+        }
+    }
+}
+
+// Inverse of a small dense matrix by Gauss-Jordan elimination with partial pivoting.
+template <int N>
+__device__ __forceinline__ void invert(double A[N][N], double X[N][N]) {
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c) X[r][c] = r == c ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        int piv = k;
+        double best = fabs(A[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < N; ++r)
+            if (fabs(A[r][k]) > best) { best = fabs(A[r][k]); piv = r; }
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            if (r == piv) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    double t = A[k][c]; A[k][c] = A[r][c]; A[r][c] = t;
+                    t = X[k][c]; X[k][c] = X[r][c]; X[r][c] = t;
+                }
+            }
+        }
+        const double ip = 1.0 / A[k][k];
+#pragma unroll
+        for (int c = 0; c < N; ++c) { A[k][c] *= ip; X[k][c] *= ip; }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if (r == k) continue;
+            const double f = A[r][k];
+#pragma unroll
+            for (int c = 0; c < N; ++c) { A[r][c] -= f * A[k][c]; X[r][c] -= f * X[k][c]; }
+        }
+    }
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric matrix A (overwritten by the
+// eigenvalues on its diagonal); Zv (optional) accumulates the rotations, so its
+// columns are the orthonormal eigenvectors.  Stops when the off-diagonal part
+// is below 1e-30 of the diagonal (squared) or after 12 sweeps.
+template <int N, bool VEC>
+__device__ __forceinline__ void jacobi_eigen(double A[N][N], double Zv[N][N]) {
+    if (VEC) {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < N; ++c) Zv[r][c] = r == c ? 1.0 : 0.0;
+    }
+#pragma unroll 1
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        double off = 0.0, dia = 0.0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+            dia += A[p][p] * A[p][p];
+#pragma unroll
+            for (int q = p + 1; q < N; ++q) off += A[p][q] * A[p][q];
+        }
+        if (!(off > 1e-30 * dia)) break;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < N; ++q) {
+                const double apq = A[p][q];
+                if (apq == 0.0) continue;
+                const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+                if (VEC) {
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        const double zkp = Zv[k][p], zkq = Zv[k][q];
+                        Zv[k][p] = c * zkp - s * zkq;
+                        Zv[k][q] = s * zkp + c * zkq;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Symmetric pencil of the eigenproblem in entropy variables: A0 = dU/dV =
+// JU JV^{-1} and S = dF/dV = JF JV^{-1} (both symmetric; symmetrised against
+// rounding); with A0 = L L^T, Q = L^{-1} S L^{-T}; Q = Z diag(lambda) Z^T gives
+// R = L Z with R R^T = A0 and (dF/dU) R = R diag(lambda) (Section 4).
+__device__ __forceinline__ void rmhd_pencil(const double JU[8][8], const double JF[8][8],
+                                            double JV[8][8], double Lc[8][8], double Q[8][8]) {
+    double X[8][8];
+    invert<8>(JV, X);
+    double A0[8][8], S[8][8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            double a = 0.0, f = 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) { a += JU[r][k] * X[k][c]; f += JF[r][k] * X[k][c]; }
+            A0[r][c] = a;
+            S[r][c] = f;
+        }
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = r + 1; c < 8; ++c) {
+            const double a = 0.5 * (A0[r][c] + A0[c][r]), f = 0.5 * (S[r][c] + S[c][r]);
+            A0[r][c] = A0[c][r] = a;
+            S[r][c] = S[c][r] = f;
+        }
+    // Cholesky A0 = L L^T
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) Lc[r][c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        double d = A0[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= Lc[j][k] * Lc[j][k];
+        const double ljj = sqrt(d);
+        Lc[j][j] = ljj;
+        const double il = 1.0 / ljj;
+#pragma unroll
+        for (int i = j + 1; i < 8; ++i) {
+            double s = A0[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= Lc[i][k] * Lc[j][k];
+            Lc[i][j] = s * il;
+        }
+    }
+    // Y = L^{-1} S (forward substitution per column), Q = L^{-1} Y^T
+    double Y[8][8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double s = S[i][c];
+#pragma unroll
+            for (int k = 0; k < i; ++k) s -= Lc[i][k] * Y[k][c];
+            Y[i][c] = s / Lc[i][i];
+        }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double s = Y[c][i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) s -= Lc[i][k] * Q[k][c];
+            Q[i][c] = s / Lc[i][i];
+        }
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = r + 1; c < 8; ++c) {
+            const double q = 0.5 * (Q[r][c] + Q[c][r]);
+            Q[r][c] = Q[c][r] = q;
+        }
+}
+
+// Largest |a_t + L lambda_m| over the eigenvalues of the x_1 flux Jacobian at the
+// rotated state P (the spectral radius of eq. cfl when a_t = 0).
+__device__ __forceinline__ double rmhd_max_speed(double G, const double* P, double at, double L) {
+    double JU[8][8], JF[8][8], JV[8][8], Pp[8], Lc[8][8], Q[8][8];
+    rmhd_jacobians(G, P, JU, JF, JV, Pp);
+    rmhd_pencil(JU, JF, JV, Lc, Q);
+    jacobi_eigen<8, false>(Q, nullptr);
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m = fmax(m, fabs(at + L * Q[k][k]));
+    return m;
+}
+
+// Rotate the vector slots (1..3) and (5..7) of an 8-vector by T (or T^T).
+template <bool TRANSPOSE>
+__device__ __forceinline__ void rotate8(const double T[3][3], const double* a, double* o) {
+    o[0] = a[0];
+    o[4] = a[4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double t = TRANSPOSE ? T[c][r] : T[r][c];
+            s1 += t * a[1 + c];
+            s2 += t * a[5 + c];
+        }
+        o[1 + r] = s1;
+        o[5 + r] = s2;
+    }
+}
+
+// ES dissipation for RMHD at one face (eq. ESFlux_HO): as face_diss_rhd with
+// T = diag{1, T_0, 1, T_0}, the face state from the mean rotated entropy
+// variables (explicit inverse of V: beta^2 = V_5^2 - |V_2..4|^2, u = V_2..4/beta,
+// W = -V_5/beta, ln rho = V_1 - G/(G-1) - ln(beta)/(G-1) - beta, p = rho/beta,
+// b = V_6..8/beta, b^0 = u.b/W, B = W b - b^0 u), and R from the symmetric pencil
+// (A0, S) of the Godunov-Powell modified Jacobian: the two eigenvalues nearest
+// v_n form the cluster, replaced by the canonical A0^{-1}-orthonormal basis from
+// the cluster projector applied to the seeds e_D and e_{B_n}.
+// nodes: the 8 primitive slots of the stencil nodes i-2..i+3.
+template <int DIM>
+__device__ __forceinline__ void face_diss_rmhd(double G, double eps, const double Pn[6][8],
+                                               const double* al, const double* ar, double* d) {
+    const double at = 0.5 * (al[0] + ar[0]);
+    double ax[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) ax[j] = 0.5 * (al[1 + j] + ar[1 + j]);
+    const double L = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    const double iL = 1.0 / L;
+    double nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
+    double T[3][3];
+    rotation<3>(nrm, T);            // n_3 = 0 in 2D gives the 2D rotation
+
+    double TV[6][8];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const StateRMHD<double> s = rmhd_state<double>(G, Pn[j]);
+        double V[8];
+        rmhd_entropy_vars<double>(G, s, V);
+        rotate8<false>(T, V, TV[j]);
+    }
+    // face state (rotated frame)
+    double Vb[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) Vb[c] = 0.5 * (TV[2][c] + TV[3][c]);
+    const double vu2 = Vb[1] * Vb[1] + Vb[2] * Vb[2] + Vb[3] * Vb[3];
+    const double beta = sqrt(Vb[4] * Vb[4] - vu2);
+    const double ib = 1.0 / beta;
+    double Pf[8];
+    const double W = -Vb[4] * ib;
+    const double rho = exp(Vb[0] - G / (G - 1.0) - log(beta) / (G - 1.0) - beta);
+    Pf[0] = rho;
+    Pf[4] = rho * ib;
+    double u[3], b[3], ub = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { u[k] = Vb[1 + k] * ib; b[k] = Vb[5 + k] * ib; ub += u[k] * b[k]; }
+    const double b0 = ub / W;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { Pf[1 + k] = u[k]; Pf[5 + k] = W * b[k] - b0 * u[k]; }
+    const double vn = u[0] / W;
+
+    double JU[8][8], JF[8][8], JV[8][8], Pp[8], Lc[8][8], Q[8][8], Zv[8][8];
+    rmhd_jacobians(G, Pf, JU, JF, JV, Pp);
+    rmhd_pencil(JU, JF, JV, Lc, Q);
+    jacobi_eigen<8, true>(Q, Zv);
+    double lam[8];
+    double lhat = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { lam[k] = Q[k][k]; lhat = fmax(lhat, fabs(at + L * lam[k])); }
+    // cluster: the two eigenvalues nearest v_n
+    int c1 = 0, c2 = 1;
+    {
+        double e1 = 1e300, e2 = 1e300;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double e = fabs(lam[k] - vn);
+            if (e < e1) { e2 = e1; c2 = c1; e1 = e; c1 = k; }
+            else if (e < e2) { e2 = e; c2 = k; }
+        }
+    }
+    // canonical cluster basis: coefficients of the seeds in the orthonormal
+    // cluster basis z_a (r_a = L z_a): w_a,s = z_a . (L^{-1} e_s)
+    double ys[2][8];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int seed = q == 0 ? 0 : 5;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double s = i == seed ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) s -= Lc[i][k] * ys[q][k];
+            ys[q][i] = s / Lc[i][i];
+        }
+    }
+    // the two cluster eigenvectors (selected without dynamic register indexing)
+    double z1[8], z2[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k == c1) s1 = Zv[i][k];
+            if (k == c2) s2 = Zv[i][k];
+        }
+        z1[i] = s1;
+        z2[i] = s2;
+    }
+    double w[2][2];   // w[q][a]
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) { s1 += z1[i] * ys[q][i]; s2 += z2[i] * ys[q][i]; }
+        w[q][0] = s1;
+        w[q][1] = s2;
+    }
+    // Gram-Schmidt in the coefficient space (orthonormal basis), seed order
+    double cq[2][2];
+    {
+        const double n0 = sqrt(w[0][0] * w[0][0] + w[0][1] * w[0][1]);
+        cq[0][0] = w[0][0] / n0;
+        cq[0][1] = w[0][1] / n0;
+        const double ip = w[1][0] * cq[0][0] + w[1][1] * cq[0][1];
+        double x0 = w[1][0] - ip * cq[0][0], x1 = w[1][1] - ip * cq[0][1];
+        const double n1 = sqrt(x0 * x0 + x1 * x1);
+        cq[1][0] = x0 / n1;
+        cq[1][1] = x1 / n1;
+    }
+    double zc[2][8];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) zc[q][i] = cq[q][0] * z1[i] + cq[q][1] * z2[i];
+
+    double tv2 = 0.0, tv3 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
+    const double tvmax = tv2 + tv3;
+    double dd[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) dd[c] = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+        // column r = L z (cluster columns replaced by the canonical basis)
+        double z[8];
+        const int q = k == c1 ? 0 : (k == c2 ? 1 : -1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double zi = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+                if (kk == k) zi = Zv[i][kk];
+            z[i] = q == 0 ? zc[0][i] : (q == 1 ? zc[1][i] : zi);
+        }
+        double r[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int kk = 0; kk <= i; ++kk) s += Lc[i][kk] * z[kk];
+            r[i] = s;
+        }
+        double vt[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s += r[c] * TV[j][c];
+            vt[j] = s;
+        }
+        const double jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps) -
+                          weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
+        const double jp = vt[3] - vt[2];
+        double r1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) r1 += fabs(r[c]);
+        if (jw * jp > 0.0 && fabs(jp) > RealTraits<double>::ytol * r1 * tvmax) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) dd[c] += jw * r[c];
+        }
+    }
+    double o[8];
+    rotate8<true>(T, dd, o);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) d[c] = lhat * o[c];
+}
+
+}  // namespace es
