@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--residual-reps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=20)
+    ap.add_argument("--workload", default="quadrant",
+                    choices=["quadrant", "sine", "rotor", "blast3d", "fourier"],
+                    help="quadrant: the headline 2D RHD problem; the others time the remaining "
+                         "workloads (FP64 step and residual only)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed work, copy one buffer of this size once (a plain copy "
                          "kernel of known traffic, for scaling HBM counters)")
@@ -106,7 +110,10 @@ class Run:
         self.ctx = ctx = es.Context(w.grid, scheme, w.monitor)
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
         P = np.concatenate([w.prim["rho"][None], w.prim["u"], w.prim["p"][None], w.prim["B"]])
-        sel = [0, 1, 2, 4]
+        if w.scheme.phys == 1:
+            sel = list(range(8))
+        else:
+            sel = [0, 1, 2, 4] if w.grid.dim == 2 else [0, 1, 2, 3, 4]
         self.met = torch.empty((ctx.nmet,) + ctx.padded_shape(), dtype=torch.float64, device="cuda")
         self.prim = torch.empty((ctx.nprim,) + ctx.padded_shape(), dtype=torch.float64, device="cuda")
         self.J = torch.empty(ctx.shape(), dtype=torch.float64, device="cuda")
@@ -196,6 +203,41 @@ def adjoint_timing(w, steps, fwd_ms):
             "note": "VJP of es_rk3_step with the mesh trajectory and dt held fixed; FP64"}
 
 
+RESIDUAL_FLOPS_PER_NODE_3D_RHD = 8313.0   # same count, 3 directions (2771.0 each)
+
+
+def other_workload(args):
+    """Time one of the other workloads: FP64 RK3 steps and es_residual."""
+    from paper_2107_12027_amd import workloads as wl
+    make = {"sine": lambda: wl.advected_sine(n=64),
+            "rotor": lambda: wl.rmhd_rotor(n=512),
+            "blast3d": lambda: wl.blast3d(n=128, seed=0),
+            "fourier": lambda: wl.rmhd_fourier(n=256, seed=0)}[args.workload]
+    w = make()
+    run = Run(w, 0)
+    t_ms = run.timed(args.steps, args.warmup)
+    res_ms = run.residual_ms(args.residual_reps)
+    nodes = w.grid.nnodes
+    flops = None
+    if w.scheme.phys == 0:
+        flops = RESIDUAL_FLOPS_PER_NODE_2D_RHD if w.grid.dim == 2 else RESIDUAL_FLOPS_PER_NODE_3D_RHD
+    roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
+            "frac": None, "traffic": None, "kernel": "es_residual", "avg_launch_ms": res_ms}
+    if flops is not None:
+        ach = flops * nodes / (res_ms * 1e-3)
+        roof["achieved"] = ach / 1e12
+        roof["frac"] = ach / PEAK_FP64_VECTOR
+    line = {"metric": METRIC, "value": nodes * args.steps / (t_ms * 1e-3), "unit": "cell-updates/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_ms / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": w.name, "system": ("RMHD" if w.scheme.phys else "RHD") + " %dD" % w.grid.dim,
+                       "grid": list(w.grid.shape[::-1]), "nodes": nodes,
+                       "mesh": "adaptive" if w.monitor.enabled else "static", "precision": "FP64"},
+            "roofline": roof, "cpu_baseline": None}
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -205,6 +247,8 @@ def main():
     from paper_2107_12027_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.workload != "quadrant":
+        return other_workload(args)
     w = wl.quadrant_riemann(n=args.n, seed=args.seed)
     g = w.grid
 

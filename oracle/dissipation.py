@@ -99,6 +99,75 @@ def cluster_seeds(phys, dim):
     return [0, 2] if dim == 2 else [0, 2, 3]
 
 
+# RMHD eigen-groups: eigenvalues closer than GROUP_TOL form one group (the
+# eigenvectors of nearly equal eigenvalues are ill-conditioned, those of equal
+# ones not unique); a seed contributes a basis vector when its projection left
+# after Gram-Schmidt exceeds SEED_TOL times its A0^{-1} norm.
+GROUP_TOL = 1e-6
+SEED_TOL = 1e-3
+SEEDS_CLUSTER = [0, 5, 1, 2, 3, 4, 6, 7]      # e_D, e_{B_n}, then the other slots
+SEEDS_OTHER = [0, 1, 2, 3, 4, 5, 6, 7]
+
+
+def _eigensystem_rmhd(JU, JF, JV, vn):
+    """Scaled eigen-structure of the Godunov-Powell modified RMHD Jacobian with a
+    canonical basis in every group of (nearly) equal eigenvalues.
+
+    In entropy variables A0 = dU/dV = JU JV^{-1} is SPD and S = dF/dV = JF JV^{-1}
+    symmetric; with A0 = L L^T and L^{-1} S L^{-T} = Z diag(lam) Z^T, the columns
+    r = L z satisfy R R^T = A0 and (dF/dU) R = R diag(lam), and r_a^T A0^{-1} r_b =
+    z_a . z_b.  In each group g (connected chains of eigenvalues within GROUP_TOL)
+    the basis is the A0^{-1}-Gram-Schmidt sequence of the projections of unit seeds
+    e_s onto the group's eigenspace, P_g e_s = sum_{a in g} r_a (r_a^T A0^{-1} e_s);
+    the group holding v_n (entropy and div B waves) takes the seeds e_D, e_{B_n}
+    first, every other group e_1, e_2, ...  The result does not depend on how the
+    eigensolver chose bases inside a group.  Columns in ascending eigenvalue order."""
+    N, m, _ = JU.shape
+    X = np.linalg.inv(JV)
+    A0 = np.einsum("nab,nbc->nac", JU, X)
+    S = np.einsum("nab,nbc->nac", JF, X)
+    A0 = 0.5 * (A0 + np.transpose(A0, (0, 2, 1)))
+    S = 0.5 * (S + np.transpose(S, (0, 2, 1)))
+    L = np.linalg.cholesky(A0)
+    Linv = np.linalg.inv(L)
+    Q = np.einsum("nab,nbc,ndc->nad", Linv, S, Linv)
+    Q = 0.5 * (Q + np.transpose(Q, (0, 2, 1)))
+    lam, Z = np.linalg.eigh(Q)                        # ascending; Z columns orthonormal
+    return lam, canonical_group_basis(lam, Z, L, Linv, vn)
+
+
+def canonical_group_basis(lam, Z, L, Linv, vn):
+    """R (N, m, m) from eigenvalues lam (N, m), orthonormal eigenvectors Z of
+    L^{-1} S L^{-T} (columns) and the Cholesky factor L of A0 (see _eigensystem_rmhd)."""
+    N, m = lam.shape
+    rows = np.arange(N)
+    lab = np.tile(np.arange(m), (N, 1))
+    close = np.abs(lam[:, :, None] - lam[:, None, :]) <= GROUP_TOL
+    for _ in range(m):
+        lab = np.min(np.where(close, lab[:, None, :], m), axis=2)
+    lab_c = lab[rows, np.argmin(np.abs(lam - vn[:, None]), axis=1)]
+    C = np.einsum("nia,nis->nas", Z, Linv)            # z_a . (L^{-1} e_s)
+    ynorm = np.sqrt(np.sum(Linv * Linv, axis=1))      # |L^{-1} e_s| (A0^{-1} norm of e_s)
+    canon = np.zeros((N, m, m))                       # canon[:, :, i]: z-space column i
+    for i in range(m):
+        ing = lab == lab[:, i:i + 1]                  # (N, m) members of the group of i
+        is_c = lab[:, i] == lab_c
+        done = np.zeros(N, dtype=bool)
+        for t in range(m):
+            sidx = np.where(is_c, SEEDS_CLUSTER[t], SEEDS_OTHER[t])
+            coef = C[rows, :, sidx] * ing              # (N, m)
+            p = np.einsum("nia,na->ni", Z, coef)
+            for j in range(i):
+                same = (lab[:, j] == lab[:, i])[:, None]
+                qj = canon[:, :, j]
+                p = p - same * np.sum(qj * p, axis=1)[:, None] * qj
+            nrm = np.sqrt(np.sum(p * p, axis=1))
+            acc = (~done) & (nrm > SEED_TOL * ynorm[rows, sidx])
+            canon[acc, :, i] = p[acc] / nrm[acc, None]
+            done |= acc
+    return np.einsum("nab,nbc->nac", L, canon)
+
+
 def eigensystem(Pr, G, phys, dim):
     """Numeric scaled eigen-structure at rotated face states Pr (8, N):
     returns (lam (N, m), R (N, m, m)) with R R^T = dU/dV and (dF_1/dU) R = R diag(lam)."""
@@ -107,14 +176,15 @@ def eigensystem(Pr, G, phys, dim):
     JU = _jac(lambda P: ph.cons(P, G), Pr, sel, G)
     JF = _jac(lambda P: ph.flux(P, G, 0), Pr, sel, G)
     JV = _jac(lambda P: ph.entropy_vars(P, G), Pr, sel, G)
+    vn = Pr[1] / np.sqrt(1.0 + Pr[1] ** 2 + Pr[2] ** 2 + Pr[3] ** 2)
     if phys == ph.RMHD:
         # Godunov-Powell modification: + Phi'(V) (dB_1/dP), B_1 is primitive slot 5
         Phip = ph.phi_prime(Pr, G)[sel].T          # (N, m)
         JF = JF.copy()
         JF[:, :, 5] += Phip
+        return _eigensystem_rmhd(JU, JF, JV, vn)
     AP = np.linalg.solve(JU, JF)
     lam = np.linalg.eigvals(AP).real
-    vn = Pr[1] / np.sqrt(1.0 + Pr[1] ** 2 + Pr[2] ** 2 + Pr[3] ** 2)
     c = cluster_size(phys, dim)
     order = np.argsort(np.abs(lam - vn[:, None]), axis=1)
     # Eigenvectors of the simple eigenvalues: the null vector of A_P - lambda I from

@@ -504,14 +504,119 @@ __device__ __forceinline__ void rotate8(const double T[3][3], const double* a, d
     }
 }
 
+// Eigen-groups of the RMHD pencil: eigenvalues closer than GROUP_TOL (chained)
+// form one group, and each group gets the A0^{-1}-Gram-Schmidt sequence of the
+// projections of unit seeds onto its eigenspace, P_g e_s = sum_{a in g} r_a
+// (r_a^T A0^{-1} e_s); the group of v_n (entropy and div B waves) takes e_D,
+// e_{B_n} first, the others e_1, e_2, ...  A seed contributes when what is left of
+// its projection exceeds SEED_TOL times its A0^{-1} norm.  In z-space (r = L z)
+// the A0^{-1} products are Euclidean and r_a^T A0^{-1} e_s = z_a . (L^{-1} e_s).
+// Writes canon[k] = z-space column of position k (a member of k's group).
+constexpr double GROUP_TOL = 1e-6;
+constexpr double SEED_TOL = 1e-3;
+
+__device__ __forceinline__ void canonical_groups(const double* lam, const double Zv[8][8],
+                                                 const double Lc[8][8], double vn,
+                                                 double canon[8][8]) {
+    // group labels: smallest index reachable through chains of close eigenvalues
+    int lab[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) lab[k] = k;
+#pragma unroll 1
+    for (int it = 0; it < 7; ++it) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int l = lab[k];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (fabs(lam[k] - lam[j]) <= GROUP_TOL && lab[j] < l) l = lab[j];
+            lab[k] = l;
+        }
+    }
+    int labc = lab[0];
+    {
+        double e = fabs(lam[0] - vn);
+#pragma unroll
+        for (int k = 1; k < 8; ++k)
+            if (fabs(lam[k] - vn) < e) { e = fabs(lam[k] - vn); labc = lab[k]; }
+    }
+    // L^{-1} (lower triangular) and the seed coefficients C[a][s] = z_a . L^{-1} e_s
+    double Li[8][8];
+#pragma unroll
+    for (int sd = 0; sd < 8; ++sd)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double v = i == sd ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) v -= Lc[i][k] * Li[k][sd];
+            Li[i][sd] = v / Lc[i][i];
+        }
+    double yn[8], C[8][8];
+#pragma unroll
+    for (int sd = 0; sd < 8; ++sd) {
+        double q = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) q += Li[i][sd] * Li[i][sd];
+        yn[sd] = sqrt(q);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            double c = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) c += Zv[i][a] * Li[i][sd];
+            C[a][sd] = c;
+        }
+    }
+    constexpr int SC[8] = {0, 5, 1, 2, 3, 4, 6, 7};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const bool isc = lab[k] == labc;
+        bool done = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) canon[k][i] = 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            double p[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) p[i] = 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                if (lab[a] != lab[k]) continue;
+                const double coef = isc ? C[a][SC[t]] : C[a][t];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) p[i] += coef * Zv[i][a];
+            }
+#pragma unroll
+            for (int j = 0; j < k; ++j) {
+                if (lab[j] != lab[k]) continue;
+                double ip = 0.0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) ip += canon[j][i] * p[i];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) p[i] -= ip * canon[j][i];
+            }
+            double nn = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) nn += p[i] * p[i];
+            nn = sqrt(nn);
+            const double ys = isc ? yn[SC[t]] : yn[t];
+            if (!done && nn > SEED_TOL * ys) {
+                const double inn = 1.0 / nn;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) canon[k][i] = p[i] * inn;
+                done = true;
+            }
+        }
+    }
+}
+
 // ES dissipation for RMHD at one face (eq. ESFlux_HO): as face_diss_rhd with
 // T = diag{1, T_0, 1, T_0}, the face state from the mean rotated entropy
 // variables (explicit inverse of V: beta^2 = V_5^2 - |V_2..4|^2, u = V_2..4/beta,
 // W = -V_5/beta, ln rho = V_1 - G/(G-1) - ln(beta)/(G-1) - beta, p = rho/beta,
 // b = V_6..8/beta, b^0 = u.b/W, B = W b - b^0 u), and R from the symmetric pencil
-// (A0, S) of the Godunov-Powell modified Jacobian: the two eigenvalues nearest
-// v_n form the cluster, replaced by the canonical A0^{-1}-orthonormal basis from
-// the cluster projector applied to the seeds e_D and e_{B_n}.
+// (A0, S) of the Godunov-Powell modified Jacobian, with the canonical basis in
+// every group of nearly equal eigenvalues (canonical_groups; the group of v_n
+// holds the entropy and div B waves and is seeded with e_D and e_{B_n}).
 // nodes: the 8 primitive slots of the stencil nodes i-2..i+3.
 template <int DIM>
 __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const double Pn[6][8],
@@ -562,70 +667,9 @@ __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const doubl
     double lhat = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) { lam[k] = Q[k][k]; lhat = fmax(lhat, fabs(at + L * lam[k])); }
-    // cluster: the two eigenvalues nearest v_n
-    int c1 = 0, c2 = 1;
-    {
-        double e1 = 1e300, e2 = 1e300;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double e = fabs(lam[k] - vn);
-            if (e < e1) { e2 = e1; c2 = c1; e1 = e; c1 = k; }
-            else if (e < e2) { e2 = e; c2 = k; }
-        }
-    }
-    // canonical cluster basis: coefficients of the seeds in the orthonormal
-    // cluster basis z_a (r_a = L z_a): w_a,s = z_a . (L^{-1} e_s)
-    double ys[2][8];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int seed = q == 0 ? 0 : 5;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            double s = i == seed ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = 0; k < i; ++k) s -= Lc[i][k] * ys[q][k];
-            ys[q][i] = s / Lc[i][i];
-        }
-    }
-    // the two cluster eigenvectors (selected without dynamic register indexing)
-    double z1[8], z2[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k == c1) s1 = Zv[i][k];
-            if (k == c2) s2 = Zv[i][k];
-        }
-        z1[i] = s1;
-        z2[i] = s2;
-    }
-    double w[2][2];   // w[q][a]
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) { s1 += z1[i] * ys[q][i]; s2 += z2[i] * ys[q][i]; }
-        w[q][0] = s1;
-        w[q][1] = s2;
-    }
-    // Gram-Schmidt in the coefficient space (orthonormal basis), seed order
-    double cq[2][2];
-    {
-        const double n0 = sqrt(w[0][0] * w[0][0] + w[0][1] * w[0][1]);
-        cq[0][0] = w[0][0] / n0;
-        cq[0][1] = w[0][1] / n0;
-        const double ip = w[1][0] * cq[0][0] + w[1][1] * cq[0][1];
-        double x0 = w[1][0] - ip * cq[0][0], x1 = w[1][1] - ip * cq[0][1];
-        const double n1 = sqrt(x0 * x0 + x1 * x1);
-        cq[1][0] = x0 / n1;
-        cq[1][1] = x1 / n1;
-    }
-    double zc[2][8];
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) zc[q][i] = cq[q][0] * z1[i] + cq[q][1] * z2[i];
+    // canonical basis in every group of (nearly) equal eigenvalues
+    double canon[8][8];
+    canonical_groups(lam, Zv, Lc, vn, canon);
 
     double tv2 = 0.0, tv3 = 0.0;
 #pragma unroll
@@ -634,25 +678,15 @@ __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const doubl
     double dd[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) dd[c] = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < 8; ++k) {
-        // column r = L z (cluster columns replaced by the canonical basis)
-        double z[8];
-        const int q = k == c1 ? 0 : (k == c2 ? 1 : -1);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            double zi = 0.0;
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk)
-                if (kk == k) zi = Zv[i][kk];
-            z[i] = q == 0 ? zc[0][i] : (q == 1 ? zc[1][i] : zi);
-        }
+        // column r = L z with z the canonical basis vector of position k
         double r[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             double s = 0.0;
 #pragma unroll
-            for (int kk = 0; kk <= i; ++kk) s += Lc[i][kk] * z[kk];
+            for (int kk = 0; kk <= i; ++kk) s += Lc[i][kk] * canon[k][kk];
             r[i] = s;
         }
         double vt[6];

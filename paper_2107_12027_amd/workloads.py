@@ -200,19 +200,26 @@ def quadrant_riemann(n: int = 400, seed: int = 0, steps: int = 300) -> Workload:
 
 
 def rmhd_rotor(n: int = 512, steps: int = 200) -> Workload:
-    """2D RMHD rotor on [0,1]^2, outflow, static mesh: disk r < 0.1 about (0.5, 0.5)
-    with rho = 10 rotating rigidly at |v| = 0.99 r / 0.1; rho = 1 outside; p = 1;
-    B = (1, 0, 0)."""
+    """2D RMHD rotor on [0,1]^2, outflow, static mesh: disk r < r0 = 0.1 about
+    (0.5, 0.5) with rho = 10 rotating rigidly at |v| = 0.99 r/r0; rho = 1 outside
+    r1 = 0.115; p = 1; B = (1, 0, 0).  Between r0 and r1 the density and the
+    speed fall linearly, rho = 1 + 9 f, |v| = 0.99 f with f = (r1 - r)/(r1 - r0),
+    the taper of the usual rotor setups (without it the ES scheme, which has no
+    positivity limiter, leaves the admissible set in the first step from 128^2)."""
     g = make_grid(2, (n, n, 1), (OUTFLOW, OUTFLOW, PERIODIC))
     x = uniform_mesh(g)
     dx = x[0] - 0.5
     dy = x[1] - 0.5
     r = np.sqrt(dx * dx + dy * dy)
-    inside = r < 0.1
-    rho = np.where(inside, 10.0, 1.0)
+    r0, r1 = 0.1, 0.115
+    f = np.clip((r1 - r) / (r1 - r0), 0.0, 1.0)
+    inside = r < r0
+    rho = np.where(inside, 10.0, 1.0 + 9.0 * f)
+    speed = np.where(inside, 0.99 * r / r0, 0.99 * f)
+    rs = np.where(r > 0, r, 1.0)
     v = np.zeros((3,) + g.shape)
-    v[0] = np.where(inside, -0.99 * dy / 0.1, 0.0)
-    v[1] = np.where(inside, 0.99 * dx / 0.1, 0.0)
+    v[0] = -speed * dy / rs
+    v[1] = speed * dx / rs
     p = np.ones(g.shape)
     B = np.zeros((3,) + g.shape)
     B[0] = 1.0

@@ -88,6 +88,79 @@ def test_scaled_eigenvectors_near_rest(phys, dim):
     assert np.max(rel) < 1e-8
 
 
+def _degenerate_rmhd_states(rng, n=40):
+    """States with exactly coinciding RMHD eigenvalues in the x_1 direction: field
+    along the normal (Alfven and slow or fast waves coincide), field across it
+    (Alfven and slow speeds equal v_n), no field, and states at rest."""
+    Pr = rand_P(4 * n, rng, ph.RMHD, 2, vmax=0.6, lo=0.2)
+    Pr[6:8, :n] = 0.0                     # B along the normal
+    Pr[5, n:2 * n] = 0.0                  # B across the normal
+    Pr[5:8, 2 * n:3 * n] = 0.0            # no field
+    Pr[1:4, 3 * n:] = 0.0                 # at rest, B along the normal
+    Pr[6:8, 3 * n:] = 0.0
+    return Pr
+
+
+def test_rmhd_eigenstructure_at_degenerate_states():
+    rng = np.random.default_rng(17)
+    Pr = _degenerate_rmhd_states(rng)
+    lam, R = ds.eigensystem(Pr, G, ph.RMHD, 2)
+    assert np.all(np.isfinite(R))
+    A0, S = _A0_and_S(Pr, ph.RMHD, 2)
+    RRt = np.einsum("nab,ncb->nac", R, R)
+    rel = np.max(np.abs(RRt - A0), axis=(1, 2)) / np.max(np.abs(A0), axis=(1, 2))
+    assert np.max(rel) < 1e-10
+    # inside a group the eigenvalues differ by at most 7 GROUP_TOL (chains), and the
+    # canonical columns mix their eigenvectors: A R = R Lambda up to that spread
+    # (a field along the normal is only nearly degenerate when v has a transverse
+    # part: the fluid-frame field b then has one)
+    A = np.einsum("nab,nbc->nac", S, np.linalg.inv(A0))
+    AR = np.einsum("nab,nbc->nac", A, R)
+    rel = np.max(np.abs(AR - R * lam[:, None, :]), axis=(1, 2)) / np.max(np.abs(R), axis=(1, 2))
+    assert np.max(rel) < 7 * ds.GROUP_TOL
+    spread = np.max(np.abs(lam[:, :, None] - lam[:, None, :]) * (np.abs(lam[:, :, None] - lam[:, None, :])
+                                                                  <= ds.GROUP_TOL), axis=(1, 2))
+    exact = spread < 1e-13
+    assert exact.sum() > 40 and np.max(rel[exact]) < 1e-8
+
+
+@pytest.mark.parametrize("degenerate", [False, True])
+def test_rmhd_group_basis_does_not_depend_on_the_eigensolver_basis(degenerate):
+    # rotate the eigenvectors inside every group of equal eigenvalues (and flip
+    # signs of single ones): the canonical columns must not change
+    rng = np.random.default_rng(23)
+    Pr = _degenerate_rmhd_states(rng) if degenerate else rand_P(200, rng, ph.RMHD, 2, vmax=0.9, lo=0.05)
+    sel = ph.comps(ph.RMHD, 2)
+    JU = ds._jac(lambda P: ph.cons(P, G), Pr, sel, G)
+    JF = ds._jac(lambda P: ph.flux(P, G, 0), Pr, sel, G).copy()
+    JF[:, :, 5] += ph.phi_prime(Pr, G)[sel].T
+    JV = ds._jac(lambda P: ph.entropy_vars(P, G), Pr, sel, G)
+    X = np.linalg.inv(JV)
+    A0 = JU @ X
+    S = JF @ X
+    A0 = 0.5 * (A0 + np.transpose(A0, (0, 2, 1)))
+    S = 0.5 * (S + np.transpose(S, (0, 2, 1)))
+    L = np.linalg.cholesky(A0)
+    Li = np.linalg.inv(L)
+    Q = Li @ S @ np.transpose(Li, (0, 2, 1))
+    lam, Z = np.linalg.eigh(0.5 * (Q + np.transpose(Q, (0, 2, 1))))
+    vn = Pr[1] / np.sqrt(1.0 + Pr[1] ** 2 + Pr[2] ** 2 + Pr[3] ** 2)
+    R1 = ds.canonical_group_basis(lam, Z, L, Li, vn)
+    Z2 = Z.copy()
+    for n in range(Z.shape[0]):
+        i = 0
+        while i < 8:
+            j = i
+            while j + 1 < 8 and lam[n, j + 1] - lam[n, j] <= ds.GROUP_TOL:
+                j += 1
+            k = j - i + 1
+            Qr, _ = np.linalg.qr(rng.normal(size=(k, k)))
+            Z2[n, :, i:j + 1] = Z[n, :, i:j + 1] @ Qr
+            i = j + 1
+    R2 = ds.canonical_group_basis(lam, Z2, L, Li, vn)
+    assert np.max(np.abs(R1 - R2)) <= 1e-10 * np.max(np.abs(R1))
+
+
 @pytest.mark.parametrize("phys,dim", CASES)
 def test_cluster_basis_is_canonical(phys, dim):
     # seeds in order; each later cluster column carries no component of an earlier seed:
