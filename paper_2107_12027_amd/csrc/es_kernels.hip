@@ -131,47 +131,74 @@ __global__ void k_mesh_extend(GridDev g, const double* __restrict__ x, const dou
     }
 }
 
-__global__ void k_metrics2d(GridDev g, const double* __restrict__ xe, const double* __restrict__ ve,
-                            double* __restrict__ met, double* __restrict__ J0) {
-    int i, j, k;
-    if (!box_ijk(-NG, -NG, 0, g.P[0], g.P[1], i, j, k)) return;
-    const long long t = pidx(g, i, j, 0);
-    const long long e = eidx(g, i, j, 0);
-    const long long E0 = g.E[0];
-    const long long EN = g.enodes;
-    double dxi[2], deta[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const double* xc = xe + c * EN + e;
-        double s = 0.0, r = 0.0;
-#pragma unroll
-        for (int n = 1; n <= 3; ++n) {
-            const double a = 0.5 * alpha3(n);
-            s += a * (xc[n] - xc[-n]);
-            r += a * (xc[n * E0] - xc[-n * E0]);
-        }
-        dxi[c] = s;
-        deta[c] = r;
+// 2D metrics with the stage-mesh extension fused in: a block stages the
+// extended stage mesh x + c dt xdot of its 64 x 4 tile of padded nodes plus a
+// 3-node halo in LDS (mesh_value, as k_mesh_extend) and forms the central
+// differences of eq. SCLCoeff (2D form of Appendix B with 1/Delta xi) from
+// there; the mesh velocity is read at the node.
+constexpr int MTX = 64, MTY = 4, MBY = 4;
+constexpr int MRX = MTX + 2 * NG, MRY = MTY + 2 * NG;
+
+__global__ void __launch_bounds__(256) k_metrics2d_fused(GridDev g, const double* __restrict__ x,
+                                                         const double* __restrict__ xd,
+                                                         const double* __restrict__ dt_dev, double coef,
+                                                         double* __restrict__ met, double* __restrict__ J0) {
+    __shared__ double xs[2][MRY][MRX];
+    const int tid = threadIdx.y * MTX + threadIdx.x;
+    const int i0 = -NG + (int)blockIdx.x * MTX, j0 = -NG + (int)blockIdx.y * MTY;
+    const double cdt = dt_dev != nullptr ? coef * dt_dev[0] : 0.0;
+    const double* xsd = dt_dev != nullptr ? xd : nullptr;
+    for (int q = tid; q < MRX * MRY; q += MTX * MBY) {
+        const int ri = q % MRX, rj = q / MRX;
+        const int i = i0 - NG + ri, j = j0 - NG + rj;
+        // positions beyond the extension box are never needed by padded nodes
+        const bool ok = i >= -2 * NG && i < g.n[0] + 2 * NG && j >= -2 * NG && j < g.n[1] + 2 * NG;
+        xs[0][rj][ri] = ok ? mesh_value(g, x, xsd, cdt, 0, i, j, 0, true) : 0.0;
+        xs[1][rj][ri] = ok ? mesh_value(g, x, xsd, cdt, 1, i, j, 0, true) : 0.0;
     }
+    __syncthreads();
     const long long P = g.pnodes;
-    const double xix = deta[1] / g.dxi[1];
-    const double xiy = -deta[0] / g.dxi[1];
-    const double etx = -dxi[1] / g.dxi[0];
-    const double ety = dxi[0] / g.dxi[0];
-    double at0 = 0.0, at1 = 0.0;
-    if (ve != nullptr) {
-        const double vx = ve[e], vy = ve[EN + e];
-        at0 = -(vx * xix + vy * xiy);
-        at1 = -(vx * etx + vy * ety);
+    const int i = i0 + (int)threadIdx.x;
+    if (i >= g.n[0] + NG) return;
+    const int ri = threadIdx.x + NG;
+    for (int row = threadIdx.y; row < MTY; row += MBY) {
+        const int j = j0 + row;
+        if (j >= g.n[1] + NG) break;
+        const int rj = row + NG;
+        double dxi[2], deta[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            double s = 0.0, r = 0.0;
+#pragma unroll
+            for (int n = 1; n <= 3; ++n) {
+                const double a = 0.5 * alpha3(n);
+                s += a * (xs[c][rj][ri + n] - xs[c][rj][ri - n]);
+                r += a * (xs[c][rj + n][ri] - xs[c][rj - n][ri]);
+            }
+            dxi[c] = s;
+            deta[c] = r;
+        }
+        const long long t = pidx(g, i, j, 0);
+        const double xix = deta[1] / g.dxi[1];
+        const double xiy = -deta[0] / g.dxi[1];
+        const double etx = -dxi[1] / g.dxi[0];
+        const double ety = dxi[0] / g.dxi[0];
+        double at0 = 0.0, at1 = 0.0;
+        if (xd != nullptr) {
+            const double vx = mesh_value(g, xd, nullptr, 0.0, 0, i, j, 0, false);
+            const double vy = mesh_value(g, xd, nullptr, 0.0, 1, i, j, 0, false);
+            at0 = -(vx * xix + vy * xiy);
+            at1 = -(vx * etx + vy * ety);
+        }
+        met[0 * P + t] = at0;
+        met[1 * P + t] = xix;
+        met[2 * P + t] = xiy;
+        met[3 * P + t] = at1;
+        met[4 * P + t] = etx;
+        met[5 * P + t] = ety;
+        if (J0 != nullptr && i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1])
+            J0[iidx(g, i, j, 0)] = (dxi[0] * deta[1] - deta[0] * dxi[1]) / (g.dxi[0] * g.dxi[1]);
     }
-    met[0 * P + t] = at0;
-    met[1 * P + t] = xix;
-    met[2 * P + t] = xiy;
-    met[3 * P + t] = at1;
-    met[4 * P + t] = etx;
-    met[5 * P + t] = ety;
-    if (J0 != nullptr && i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1])
-        J0[iidx(g, i, j, 0)] = (dxi[0] * deta[1] - deta[0] * dxi[1]) / (g.dxi[0] * g.dxi[1]);
 }
 
 // 3D conservative metric method (eq. SCLCoeff): with the products
@@ -658,6 +685,70 @@ __global__ void k_filter(GridDev g, const double* __restrict__ win, double* __re
     wout[iidx(g, i, j, k)] = s;
 }
 
+// Monitor normalisation and up to FH low-pass filter passes in one launch (2D):
+// a block stages its 64 x 4 tile of omega plus an FH-node halo in LDS, applies
+// omega = sqrt(1 + alpha |grad sigma| / max |grad sigma|) at load (paper form;
+// apply = 0 when the input already holds omega) and the 3x3 filter of k_filter
+// `passes` times on the shrinking valid region.  Neighbours beyond an outflow
+// edge read the clamped edge value (the zero-gradient ghost); periodic copies
+// are filtered as the originals.
+constexpr int FTX = 64, FTY = 4, FH = 5;
+constexpr int FRX = FTX + 2 * FH, FRY = FTY + 2 * FH;
+
+__global__ void __launch_bounds__(256) k_monitor_filter2d(GridDev g, int apply, double alpha,
+                                                          const double* __restrict__ gmax, int passes,
+                                                          const double* __restrict__ win,
+                                                          double* __restrict__ wout) {
+    __shared__ double ws[2][FRY][FRX];
+    const int tid = threadIdx.y * FTX + threadIdx.x;
+    const int i0 = (int)blockIdx.x * FTX - FH, j0 = (int)blockIdx.y * FTY - FH;
+    const int n0 = g.n[0], n1 = g.n[1];
+    const double m = apply ? gmax[0] : 0.0;
+    for (int q = tid; q < FRX * FRY; q += FTX * FTY) {
+        const int ri = q % FRX, rj = q / FRX;
+        const int ii = map_sol(i0 + ri, n0, g.bc[0]), jj = map_sol(j0 + rj, n1, g.bc[1]);
+        double v = win[(long long)jj * n0 + ii];
+        if (apply) v = m == 0.0 ? 1.0 : sqrt(1.0 + alpha * v / m);
+        ws[0][rj][ri] = v;
+    }
+    __syncthreads();
+    const bool per0 = g.bc[0] == ES_BC_PERIODIC, per1 = g.bc[1] == ES_BC_PERIODIC;
+    // region index of the neighbour read: outflow positions clamp to the domain
+    auto rx = [&](int ri, int o) {
+        int gi = i0 + ri + o;
+        if (!per0) gi = gi < 0 ? 0 : (gi >= n0 ? n0 - 1 : gi);
+        return gi - i0;
+    };
+    auto ry = [&](int rj, int o) {
+        int gj = j0 + rj + o;
+        if (!per1) gj = gj < 0 ? 0 : (gj >= n1 ? n1 - 1 : gj);
+        return gj - j0;
+    };
+    int cur = 0;
+    for (int ps = 1; ps <= passes; ++ps) {
+        for (int q = tid; q < FRX * FRY; q += FTX * FTY) {
+            const int ri = q % FRX, rj = q / FRX;
+            double v = ws[cur][rj][ri];
+            if (ri >= ps && ri < FRX - ps && rj >= ps && rj < FRY - ps) {
+                double s = 0.0;
+                for (int o0 = -1; o0 <= 1; ++o0) {
+                    const int xi = rx(ri, o0);
+                    for (int o1 = -1; o1 <= 1; ++o1) {
+                        const int e = abs(o0) + abs(o1) + 2;
+                        s += ldexp(1.0, -e) * ws[cur][ry(rj, o1)][xi];
+                    }
+                }
+                v = s;
+            }
+            ws[cur ^ 1][rj][ri] = v;
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
+    const int gi = (int)blockIdx.x * FTX + threadIdx.x, gj = (int)blockIdx.y * FTY + threadIdx.y;
+    if (gi < n0 && gj < n1) wout[(long long)gj * n0 + gi] = ws[cur][threadIdx.y + FH][threadIdx.x + FH];
+}
+
 // Value of mesh component q at the neighbour c + s e_a of interior node c: a
 // direct load inside the box, the periodic copy with its shift across a
 // periodic edge (the Jacobi and limiter rules never look across an outflow edge).
@@ -707,6 +798,93 @@ __global__ void k_jacobi(GridDev g, const double* __restrict__ w, const double* 
     for (int q = 0; q < DIM; ++q) {
         const long long o = (long long)q * g.nodes + t;
         xout[o] = (fr[q] && den > 0.0) ? num[q] / den : xin[o];
+    }
+}
+
+// Several Jacobi sweeps in one launch (2D): a block stages its TX x TY tile of
+// outputs with a halo of JS nodes (x and omega) in LDS and applies the sweep of
+// k_jacobi `sweeps` <= JS times to the shrinking valid region; periodic copies
+// carry the coordinate shift (the sweep is an average with weights summing to
+// one, so shifted copies evolve as the shifted originals); positions outside an
+// outflow edge are never read by the nodes a sweep updates.
+constexpr int JTX = 64, JTY = 8, JS = 5;
+constexpr int JRX = JTX + 2 * JS, JRY = JTY + 2 * JS;
+
+__global__ void __launch_bounds__(256) k_jacobi_multi2d(GridDev g, int sweeps, const double* __restrict__ w,
+                                                        const double* __restrict__ xin,
+                                                        double* __restrict__ xout) {
+    __shared__ double xs[2][2][JRY][JRX];
+    __shared__ double ws[JRY][JRX];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * JTX - JS, j0 = blockIdx.y * JTY - JS;
+    const int n0 = g.n[0], n1 = g.n[1];
+    const bool per0 = g.bc[0] == ES_BC_PERIODIC, per1 = g.bc[1] == ES_BC_PERIODIC;
+    for (int q = tid; q < JRX * JRY; q += 256) {
+        const int ri = q % JRX, rj = q / JRX;
+        int gi = i0 + ri, gj = j0 + rj;
+        double sh0 = 0.0, sh1 = 0.0;
+        bool ok = true;
+        if (gi < 0 || gi >= n0) {
+            if (per0) { const int wr = floordiv(gi, n0); gi -= wr * n0; sh0 = wr * g.period[0]; }
+            else ok = false;
+        }
+        if (gj < 0 || gj >= n1) {
+            if (per1) { const int wr = floordiv(gj, n1); gj -= wr * n1; sh1 = wr * g.period[1]; }
+            else ok = false;
+        }
+        double a = 0.0, b = 0.0, ww = 0.0;
+        if (ok) {
+            const long long t = (long long)gj * n0 + gi;
+            a = xin[t] + sh0;
+            b = xin[g.nodes + t] + sh1;
+            ww = w[t];
+        }
+        xs[0][0][rj][ri] = a;
+        xs[0][1][rj][ri] = b;
+        ww = ok ? ww : 1.0;
+        ws[rj][ri] = ww;
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int sw = 1; sw <= sweeps; ++sw) {
+        for (int q = tid; q < JRX * JRY; q += 256) {
+            const int ri = q % JRX, rj = q / JRX;
+            double v0 = xs[cur][0][rj][ri], v1 = xs[cur][1][rj][ri];
+            if (ri >= sw && ri < JRX - sw && rj >= sw && rj < JRY - sw) {
+                const int gi = i0 + ri, gj = j0 + rj;
+                const bool fr0 = per0 || (gi > 0 && gi < n0 - 1);
+                const bool fr1 = per1 || (gj > 0 && gj < n1 - 1);
+                const double wc = ws[rj][ri];
+                double den = 0.0, num0 = 0.0, num1 = 0.0;
+                if (fr0) {
+                    const double wp = ws[rj][ri + 1], wm = ws[rj][ri - 1];
+                    den += 2.0 * wc + wp + wm;
+                    num0 += (wc + wp) * xs[cur][0][rj][ri + 1] + (wc + wm) * xs[cur][0][rj][ri - 1];
+                    num1 += (wc + wp) * xs[cur][1][rj][ri + 1] + (wc + wm) * xs[cur][1][rj][ri - 1];
+                }
+                if (fr1) {
+                    const double wp = ws[rj + 1][ri], wm = ws[rj - 1][ri];
+                    den += 2.0 * wc + wp + wm;
+                    num0 += (wc + wp) * xs[cur][0][rj + 1][ri] + (wc + wm) * xs[cur][0][rj - 1][ri];
+                    num1 += (wc + wp) * xs[cur][1][rj + 1][ri] + (wc + wm) * xs[cur][1][rj - 1][ri];
+                }
+                if (fr0 && den > 0.0) v0 = num0 / den;
+                if (fr1 && den > 0.0) v1 = num1 / den;
+            }
+            xs[cur ^ 1][0][rj][ri] = v0;
+            xs[cur ^ 1][1][rj][ri] = v1;
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
+    for (int q = tid; q < JTX * JTY; q += 256) {
+        const int oi = q % JTX, oj = q / JTX;
+        const int gi = blockIdx.x * JTX + oi, gj = blockIdx.y * JTY + oj;
+        if (gi < n0 && gj < n1) {
+            const long long t = (long long)gj * n0 + gi;
+            xout[t] = xs[cur][0][oj + JS][oi + JS];
+            xout[g.nodes + t] = xs[cur][1][oj + JS][oi + JS];
+        }
     }
 }
 
@@ -901,8 +1079,9 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
     const dim3 ge = box_grid(g.E[0], g.E[1], g.E[2]);
     double* ve = xdot != nullptr ? c->ve : nullptr;
     if (g.dim == 2) {
-        k_mesh_extend<2><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve);
-        k_metrics2d<<<box_grid(g.P[0], g.P[1], 1), box_block(), 0, s>>>(g, c->xe, ve, met, J0);
+        (void)ve;
+        const dim3 gm((unsigned)((g.P[0] + MTX - 1) / MTX), (unsigned)((g.P[1] + MTY - 1) / MTY), 1);
+        k_metrics2d_fused<<<gm, dim3(MTX, MBY, 1), 0, s>>>(g, x, xdot, dt_dev, coef, met, J0);
     } else {
         k_mesh_extend<3><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve);
         k_cmm_products<<<ge, box_block(), 0, s>>>(g, c->xe, c->pi);
@@ -992,23 +1171,42 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
     double* w2 = c->wb;
     if (g.dim == 2) k_monitor_grad<2><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
     else k_monitor_grad<3><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
-    if (!sq) {
-        k_reduce_final<<<1, 256, 0, s>>>(0, nb, c->red, c->scal + SCAL_GMAX);
-        k_monitor_apply<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, c->scal + SCAL_GMAX, w);
-    }
-    for (int f = 0; f < mo.filter_passes; ++f) {
-        if (g.dim == 2) k_filter<2><<<gr, box_block(), 0, s>>>(g, w, w2);
-        else k_filter<3><<<gr, box_block(), 0, s>>>(g, w, w2);
-        double* tmp = w; w = w2; w2 = tmp;
+    if (!sq) k_reduce_final<<<1, 256, 0, s>>>(0, nb, c->red, c->scal + SCAL_GMAX);
+    if (g.dim == 2) {
+        // normalisation and filter passes, FH passes per launch
+        int apply = !sq, left = mo.filter_passes;
+        do {
+            const int k = min(FH, left);
+            k_monitor_filter2d<<<box_grid(g.n[0], g.n[1], 1), box_block(), 0, s>>>(
+                g, apply, mo.alpha, c->scal + SCAL_GMAX, k, w, w2);
+            double* tmp = w; w = w2; w2 = tmp;
+            apply = 0;
+            left -= k;
+        } while (left > 0);
+    } else {
+        if (!sq) k_monitor_apply<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, c->scal + SCAL_GMAX, w);
+        for (int f = 0; f < mo.filter_passes; ++f) {
+            k_filter<3><<<gr, box_block(), 0, s>>>(g, w, w2);
+            double* tmp = w; w = w2; w2 = tmp;
+        }
     }
     const double* xin = x;
     double* xo = c->xa;
     double* xalt = c->xb;
-    for (int it = 0; it < mo.sweeps; ++it) {
-        if (g.dim == 2) k_jacobi<2><<<gr, box_block(), 0, s>>>(g, w, xin, xo);
-        else k_jacobi<3><<<gr, box_block(), 0, s>>>(g, w, xin, xo);
-        xin = xo;
-        double* tmp = xo; xo = xalt; xalt = tmp;
+    if (g.dim == 2) {
+        const dim3 gj((unsigned)((g.n[0] + JTX - 1) / JTX), (unsigned)((g.n[1] + JTY - 1) / JTY), 1);
+        for (int done = 0; done < mo.sweeps; done += JS) {
+            const int k = min(JS, mo.sweeps - done);
+            k_jacobi_multi2d<<<gj, 256, 0, s>>>(g, k, w, xin, xo);
+            xin = xo;
+            double* tmp = xo; xo = xalt; xalt = tmp;
+        }
+    } else {
+        for (int it = 0; it < mo.sweeps; ++it) {
+            k_jacobi<3><<<gr, box_block(), 0, s>>>(g, w, xin, xo);
+            xin = xo;
+            double* tmp = xo; xo = xalt; xalt = tmp;
+        }
     }
     if (g.dim == 2) k_dtau_partial<2><<<gr, box_block(), 0, s>>>(g, x, xin, c->red);
     else k_dtau_partial<3><<<gr, box_block(), 0, s>>>(g, x, xin, c->red);
