@@ -110,6 +110,8 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     if (e == hipSuccess) e = alloc(&c->L, N * (c->m + 1) * d);
     if (e == hipSuccess) e = alloc(&c->Us, N * c->m);
     if (e == hipSuccess) e = alloc(&c->Js, N);
+    if (e == hipSuccess) e = alloc(&c->Us2, N * c->m);
+    if (e == hipSuccess) e = alloc(&c->Js2, N);
     if (e == hipSuccess) e = alloc(&c->xnew, N * d);
     if (e == hipSuccess) e = alloc(&c->xa, N * d);
     if (e == hipSuccess) e = alloc(&c->xb, N * d);
@@ -143,7 +145,7 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
 
 es_status es_destroy(es_ctx* c) {
     if (c == nullptr) return ES_EINVAL;
-    void* bufs[] = {c->prim, c->met, c->L, c->Us, c->Js, c->xnew, c->xa, c->xb,
+    void* bufs[] = {c->prim, c->met, c->L, c->Us, c->Js, c->Us2, c->Js2, c->xnew, c->xa, c->xb,
                     c->wa, c->wb, c->xe, c->ve, c->pi, c->red, c->scal, c->fail,
                     c->adj_lamU, c->adj_lamJ, c->adj_lamL, c->adj_accU, c->adj_accJ,
                     c->adj_gU, c->adj_gJ, c->gdir};
@@ -227,18 +229,26 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
         ES_TRY(es::launch_copy(w(k.dt), dt_dev, 1, s));
         ES_TRY(es::launch_copy(w(k.xdot), xdot, nX, s));
     }
+    // stages: the combinations of stages 0 and 1 are formed inside the next
+    // con2prim (stage states in Us, then Us2); the last one also copies x^{n+1}
     static const double coef[3] = {0.0, 1.0, 0.5};
     for (int st = 0; st < 3; ++st) {
-        if (st > 0) ES_TRY(es::launch_con2prim(c, c->Us, c->Js, c->prim, 1, s));
         ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s));
         ES_TRY(es::launch_residual_dirs(c, c->prim, c->met, c->L, s));
-        ES_TRY(es::launch_rk_combine(c, st, U, J, c->Us, c->Js, c->L, dt_dev, s));
+        if (st == 0) {
+            ES_TRY(es::launch_combine_con2prim(c, 0, U, J, nullptr, nullptr, c->L, dt_dev, c->Us, c->Js,
+                                               c->prim, s));
+        } else if (st == 1) {
+            ES_TRY(es::launch_combine_con2prim(c, 1, U, J, c->Us, c->Js, c->L, dt_dev, c->Us2, c->Js2,
+                                               c->prim, s));
+        } else {
+            ES_TRY(es::launch_rk_combine(c, 2, U, J, c->Us2, c->Js2, c->L, dt_dev, s, c->xnew, x));
+        }
         if (ckpt && st < 2) {
-            ES_TRY(es::launch_copy(w(k.U[st + 1]), c->Us, nU, s));
-            ES_TRY(es::launch_copy(w(k.J[st + 1]), c->Js, N, s));
+            ES_TRY(es::launch_copy(w(k.U[st + 1]), st == 0 ? c->Us : c->Us2, nU, s));
+            ES_TRY(es::launch_copy(w(k.J[st + 1]), st == 0 ? c->Js : c->Js2, N, s));
         }
     }
-    ES_TRY(es::launch_copy(x, c->xnew, nX, s));
     return ES_OK;
 }
 

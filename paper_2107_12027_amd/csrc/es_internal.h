@@ -19,8 +19,10 @@ struct es_ctx {
     double* prim;   // padded, nprim comps
     double* met;    // padded, nmet comps
     double* L;      // interior, d slabs of m + 1 comps (stage residual by direction, J last)
-    double* Us;     // interior, m comps (stage state)
+    double* Us;     // interior, m comps (stage-1 state)
     double* Js;     // interior
+    double* Us2;    // interior, m comps (stage-2 state)
+    double* Js2;    // interior
     double* xnew;   // interior, d comps
     double* xa;     // interior, d comps (Jacobi ping)
     double* xb;     // interior, d comps (Jacobi pong)
@@ -77,9 +79,16 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
                        double* x_new, double* xdot, double* dtau_dev, hipStream_t s);
 hipError_t launch_zero_mesh_velocity(const es_ctx* c, const double* x, double* x_new, double* xdot,
                                      hipStream_t s);
+// xsrc/xdst (optional): copy the new mesh in the same launch (last stage)
 hipError_t launch_rk_combine(const es_ctx* c, int stage, const double* U0, const double* J0,
                              double* Us, double* Js, const double* Ld, const double* dt_dev,
-                             hipStream_t s);
+                             hipStream_t s, const double* xsrc = nullptr, double* xdst = nullptr);
+// stage 0 or 1 combination formed inside con2prim: (Uout, Jout) = combined state,
+// prim = con2prim of it (previous stage's pressure as the Newton guess)
+hipError_t launch_combine_con2prim(const es_ctx* c, int stage, const double* U0, const double* J0,
+                                   const double* Us, const double* Js, const double* Ld,
+                                   const double* dt_dev, double* Uout, double* Jout, double* prim,
+                                   hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, long long n, hipStream_t s);
 hipError_t launch_diagnostics(const es_ctx* c, const double* prim, const double* U,
                               const double* J, const double* dU, const double* dJ, double* out,
@@ -89,8 +98,9 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, h
 // RMHD kernels (es_kernels_rmhd.hip), dispatched from the launchers above
 hipError_t launch_prim2con_rmhd(const es_ctx* c, const double* prim, const double* J, double* U,
                                 hipStream_t s);
-hipError_t launch_con2prim_rmhd(const es_ctx* c, const double* U, const double* J, double* prim,
-                                int use_guess, hipStream_t s);
+// state_src: the StateSrc of the launcher (declared with the kernels)
+hipError_t launch_con2prim_rmhd(const es_ctx* c, const void* state_src, double* prim, int use_guess,
+                                hipStream_t s);
 hipError_t launch_residual_dirs_rmhd(const es_ctx* c, const double* prim, const double* met, double* Ld,
                                      hipStream_t s);
 hipError_t launch_cfl_partial_rmhd(const es_ctx* c, const double* prim, const double* met,

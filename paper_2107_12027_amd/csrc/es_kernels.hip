@@ -71,8 +71,7 @@ __global__ void k_prim2con_rhd(GridDev g, double G, const double* __restrict__ p
 // the Newton iteration when it lies inside the bracket.
 // ---------------------------------------------------------------------------
 template <int DIM>
-__global__ void k_con2prim_rhd(GridDev g, double G, const double* __restrict__ U,
-                               const double* __restrict__ J, double* prim, int use_guess,
+__global__ void k_con2prim_rhd(GridDev g, double G, StateSrc ss, double* prim, int use_guess,
                                unsigned long long* __restrict__ fail) {
     constexpr int M = DIM + 2;
     int i, j, k;
@@ -84,12 +83,20 @@ __global__ void k_con2prim_rhd(GridDev g, double G, const double* __restrict__ U
     const long long src = iidx(g, si, sj, sk);
     const long long N = g.nodes;
     const long long P = g.pnodes;
-    const double Jv = J[src];
-    const double D = U[src] / Jv;
+    double Uc[M + 1];
+#pragma unroll
+    for (int c = 0; c <= M; ++c) Uc[c] = state_value(ss, DIM, M, N, c, src);
+    if (ss.stage >= 0 && si == i && sj == j && sk == k) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) ss.Uout[c * N + src] = Uc[c];
+        ss.Jout[src] = Uc[M];
+    }
+    const double Jv = Uc[M];
+    const double D = Uc[0] / Jv;
     double m[DIM];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) m[c] = U[(1 + c) * N + src] / Jv;
-    const double E = U[(M - 1) * N + src] / Jv;
+    for (int c = 0; c < DIM; ++c) m[c] = Uc[1 + c] / Jv;
+    const double E = Uc[M - 1] / Jv;
     double rho, p, u[DIM];
     const double guess = use_guess ? prim[(M - 1) * P + t] : -1.0;
     const int st = c2p_rhd<DIM>(G, D, m, E, guess, rho, u, p);
@@ -943,9 +950,15 @@ __global__ void k_zero_mesh_velocity(long long n, const double* __restrict__ x, 
 __global__ void k_rk_combine(long long nU, long long nJ, int dim, int stage, const double* U0,
                              const double* Us, const double* J0, const double* Js,
                              const double* __restrict__ Ld, const double* __restrict__ dt_dev,
-                             double* outU, double* outJ) {
+                             double* outU, double* outJ, long long nX, const double* __restrict__ xsrc,
+                             double* __restrict__ xdst) {
     long long t = gtid();
-    if (t >= nU + nJ) return;
+    if (t >= nU + nJ) {
+        // threads beyond the state copy the new mesh (end of the step)
+        t -= nU + nJ;
+        if (t < nX) xdst[t] = xsrc[t];
+        return;
+    }
     const long long slab = nU + nJ;
     double l = Ld[t] + Ld[slab + t];
     if (dim == 3) l += Ld[2 * slab + t];
@@ -1061,15 +1074,41 @@ hipError_t launch_prim2con(const es_ctx* c, const double* prim, const double* J,
     return hipGetLastError();
 }
 
-hipError_t launch_con2prim(const es_ctx* c, const double* U, const double* J, double* prim,
-                           int use_guess, hipStream_t s) {
+static hipError_t con2prim_from(const es_ctx* c, const StateSrc& ss, double* prim, int use_guess,
+                                hipStream_t s) {
     const double G = c->scheme.gamma;
     const GridDev& g = c->g;
-    if (c->scheme.phys == ES_RMHD) return launch_con2prim_rmhd(c, U, J, prim, use_guess, s);
+    if (c->scheme.phys == ES_RMHD) return launch_con2prim_rmhd(c, &ss, prim, use_guess, s);
     const dim3 gr = box_grid(g.P[0], g.P[1], g.P[2]);
-    if (g.dim == 2) k_con2prim_rhd<2><<<gr, box_block(), 0, s>>>(g, G, U, J, prim, use_guess, c->fail);
-    else k_con2prim_rhd<3><<<gr, box_block(), 0, s>>>(g, G, U, J, prim, use_guess, c->fail);
+    if (g.dim == 2) k_con2prim_rhd<2><<<gr, box_block(), 0, s>>>(g, G, ss, prim, use_guess, c->fail);
+    else k_con2prim_rhd<3><<<gr, box_block(), 0, s>>>(g, G, ss, prim, use_guess, c->fail);
     return hipGetLastError();
+}
+
+hipError_t launch_con2prim(const es_ctx* c, const double* U, const double* J, double* prim,
+                           int use_guess, hipStream_t s) {
+    StateSrc ss{};
+    ss.U = U;
+    ss.J = J;
+    ss.stage = -1;
+    return con2prim_from(c, ss, prim, use_guess, s);
+}
+
+hipError_t launch_combine_con2prim(const es_ctx* c, int stage, const double* U0, const double* J0,
+                                   const double* Us, const double* Js, const double* Ld,
+                                   const double* dt_dev, double* Uout, double* Jout, double* prim,
+                                   hipStream_t s) {
+    StateSrc ss{};
+    ss.stage = stage;
+    ss.U0 = U0;
+    ss.J0 = J0;
+    ss.Us = Us;
+    ss.Js = Js;
+    ss.Ld = Ld;
+    ss.dt = dt_dev;
+    ss.Uout = Uout;
+    ss.Jout = Jout;
+    return con2prim_from(c, ss, prim, 1, s);
 }
 
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
@@ -1219,14 +1258,15 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
 
 hipError_t launch_rk_combine(const es_ctx* c, int stage, const double* U0, const double* J0,
                              double* Us, double* Js, const double* Ld, const double* dt_dev,
-                             hipStream_t s) {
+                             hipStream_t s, const double* xsrc, double* xdst) {
     const long long nU = c->g.nodes * c->m;
     const long long nJ = c->g.nodes;
+    const long long nX = xsrc != nullptr ? c->g.nodes * c->g.dim : 0;
     // stage 2 writes the new state over U0/J0 (the caller passes them as outputs)
     double* outU = stage == 2 ? const_cast<double*>(U0) : Us;
     double* outJ = stage == 2 ? const_cast<double*>(J0) : Js;
-    k_rk_combine<<<grid_for(nU + nJ), TPB, 0, s>>>(nU, nJ, c->g.dim, stage, U0, Us, J0, Js, Ld, dt_dev,
-                                                   outU, outJ);
+    k_rk_combine<<<grid_for(nU + nJ + nX), TPB, 0, s>>>(nU, nJ, c->g.dim, stage, U0, Us, J0, Js, Ld, dt_dev,
+                                                        outU, outJ, nX, xsrc, xdst);
     return hipGetLastError();
 }
 

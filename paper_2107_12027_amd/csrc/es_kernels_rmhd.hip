@@ -33,8 +33,7 @@ __global__ void k_prim2con_rmhd(GridDev g, double G, const double* __restrict__ 
 
 // con2prim on the padded box; with use_guess the previous Z = rho h W^2 of the
 // node seeds the iteration.
-__global__ void k_con2prim_rmhd(GridDev g, double G, const double* __restrict__ U,
-                                const double* __restrict__ J, double* prim, int use_guess,
+__global__ void k_con2prim_rmhd(GridDev g, double G, StateSrc ss, double* prim, int use_guess,
                                 unsigned long long* __restrict__ fail) {
     int i, j, k;
     if (!box_ijk(-NG, -NG, -g.g2, g.P[0], g.P[1], i, j, k)) return;
@@ -44,10 +43,18 @@ __global__ void k_con2prim_rmhd(GridDev g, double G, const double* __restrict__ 
     const int sk = g.dim == 3 ? map_sol(k, g.n[2], g.bc[2]) : 0;
     const long long src = iidx(g, si, sj, sk);
     const long long N = g.nodes, P = g.pnodes;
-    const double iJ = 1.0 / J[src];
+    double Us[MR + 1];
+#pragma unroll
+    for (int c = 0; c <= MR; ++c) Us[c] = state_value(ss, g.dim, MR, N, c, src);
+    if (ss.stage >= 0 && si == i && sj == j && sk == k) {
+#pragma unroll
+        for (int c = 0; c < MR; ++c) ss.Uout[c * N + src] = Us[c];
+        ss.Jout[src] = Us[MR];
+    }
+    const double iJ = 1.0 / Us[MR];
     double Uc[MR], Pv[MR];
 #pragma unroll
-    for (int c = 0; c < MR; ++c) Uc[c] = U[c * N + src] * iJ;
+    for (int c = 0; c < MR; ++c) Uc[c] = Us[c] * iJ;
     double guess = -1.0;
     if (use_guess) {
         const double rho = prim[t], p = prim[4 * P + t];
@@ -369,10 +376,11 @@ hipError_t launch_prim2con_rmhd(const es_ctx* c, const double* prim, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_con2prim_rmhd(const es_ctx* c, const double* U, const double* J, double* prim,
-                                int use_guess, hipStream_t s) {
+hipError_t launch_con2prim_rmhd(const es_ctx* c, const void* state_src, double* prim, int use_guess,
+                                hipStream_t s) {
     const GridDev& g = c->g;
-    k_con2prim_rmhd<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, c->scheme.gamma, U, J, prim,
+    const StateSrc ss = *static_cast<const StateSrc*>(state_src);
+    k_con2prim_rmhd<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, c->scheme.gamma, ss, prim,
                                                                               use_guess, c->fail);
     return hipGetLastError();
 }

@@ -64,5 +64,43 @@ __device__ __forceinline__ double block_reduce(double v, double* sh) {
     return r;
 }
 
+// Conservative state read by con2prim: (U, J) directly (stage < 0), or the
+// Shu-Osher combination of Runge-Kutta stage 0 or 1 formed on the fly from U0,
+// the previous stage state Us (stage 1) and the residual L = sum_k Ld_k (slab k
+// holds m components then J), in the order of the stage-combination kernel; the
+// interior nodes also store the combined state in (Uout, Jout).
+struct StateSrc {
+    const double* U;
+    const double* J;
+    int stage;
+    const double* U0;
+    const double* J0;
+    const double* Us;
+    const double* Js;
+    const double* Ld;
+    const double* dt;
+    double* Uout;
+    double* Jout;
+};
+
+__device__ __forceinline__ double rk_stage_value(int stage, double a, double b, double l, double dt) {
+    if (stage == 0) return a + dt * l;
+    if (stage == 1) return 0.75 * a + 0.25 * (b + dt * l);
+    return a / 3.0 + 2.0 / 3.0 * (b + dt * l);
+}
+
+// Component c (0..m-1: U, m: J) of the state at interior node t.
+__device__ __forceinline__ double state_value(const StateSrc& s, int dim, int m, long long N, int c,
+                                              long long t) {
+    if (s.stage < 0) return c < m ? s.U[c * N + t] : s.J[t];
+    const long long slab = (long long)(m + 1) * N;
+    const long long q = (long long)c * N + t;
+    double l = s.Ld[q] + s.Ld[slab + q];
+    if (dim == 3) l += s.Ld[2 * slab + q];
+    const double a = c < m ? s.U0[q] : s.J0[t];
+    const double b = s.stage == 0 ? 0.0 : (c < m ? s.Us[q] : s.Js[t]);
+    return rk_stage_value(s.stage, a, b, l, s.dt[0]);
+}
+
 }  // namespace
 }  // namespace es
