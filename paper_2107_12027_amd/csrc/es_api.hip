@@ -107,6 +107,8 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = alloc(&c->prim, P * c->nprim);
     if (e == hipSuccess) e = alloc(&c->met, P * c->nmet);
+    if (e == hipSuccess && grid->dim == 2) e = alloc(&c->met1, P * c->nmet);
+    if (e == hipSuccess && grid->dim == 2) e = alloc(&c->met2, P * c->nmet);
     if (e == hipSuccess) e = alloc(&c->L, N * (c->m + 1) * d);
     if (e == hipSuccess) e = alloc(&c->Us, N * c->m);
     if (e == hipSuccess) e = alloc(&c->Js, N);
@@ -132,8 +134,6 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     if (e == hipSuccess) e = es::launch_zero(c->prim, (long long)(P * c->nprim), nullptr);
     c->use_graph = 1;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         es_destroy(c);
@@ -145,13 +145,11 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
 
 es_status es_destroy(es_ctx* c) {
     if (c == nullptr) return ES_EINVAL;
-    void* bufs[] = {c->prim, c->met, c->L, c->Us, c->Js, c->Us2, c->Js2, c->xnew, c->xa, c->xb,
+    void* bufs[] = {c->prim, c->met, c->met1, c->met2, c->L, c->Us, c->Js, c->Us2, c->Js2, c->xnew, c->xa, c->xb,
                     c->wa, c->wb, c->xe, c->ve, c->pi, c->red, c->scal, c->fail,
                     c->adj_lamU, c->adj_lamJ, c->adj_lamL, c->adj_accU, c->adj_accJ,
                     c->adj_gU, c->adj_gJ, c->gdir};
     if (c->gexec != nullptr) (void)hipGraphExecDestroy(c->gexec);
-    if (c->ev_in != nullptr) (void)hipEventDestroy(c->ev_in);
-    if (c->ev_out != nullptr) (void)hipEventDestroy(c->ev_out);
     if (c->cap != nullptr) (void)hipStreamDestroy(c->cap);
     for (void* b : bufs)
         if (b != nullptr) (void)hipFree(b);
@@ -232,9 +230,13 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
     // stages: the combinations of stages 0 and 1 are formed inside the next
     // con2prim (stage states in Us, then Us2); the last one also copies x^{n+1}
     static const double coef[3] = {0.0, 1.0, 0.5};
+    const bool batched = es::metrics_stages_batched(c);
+    if (batched) ES_TRY(es::launch_metrics_stages(c, x, xdot, dt_dev, c->met, c->met1, c->met2, s));
     for (int st = 0; st < 3; ++st) {
-        ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s));
-        ES_TRY(es::launch_residual_dirs(c, c->prim, c->met, c->L, s));
+        const double* met = c->met;
+        if (batched) met = st == 0 ? c->met : (st == 1 ? c->met1 : c->met2);
+        else ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s));
+        ES_TRY(es::launch_residual_dirs(c, c->prim, met, c->L, s));
         if (st == 0) {
             ES_TRY(es::launch_combine_con2prim(c, 0, U, J, nullptr, nullptr, c->L, dt_dev, c->Us, c->Js,
                                                c->prim, s));
@@ -282,12 +284,8 @@ es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, 
         }
         memcpy(c->gkey, key, sizeof(key));
     }
-    // order the replay after the caller's stream and the caller's stream after it
-    ES_TRY(hipEventRecord(c->ev_in, s));
-    ES_TRY(hipStreamWaitEvent(c->cap, c->ev_in, 0));
-    ES_TRY(hipGraphLaunch(c->gexec, c->cap));
-    ES_TRY(hipEventRecord(c->ev_out, c->cap));
-    ES_TRY(hipStreamWaitEvent(s, c->ev_out, 0));
+    // the replay goes into the caller's stream (ordered with its other work)
+    ES_TRY(hipGraphLaunch(c->gexec, s));
     return ES_OK;
 }
 

@@ -18,6 +18,8 @@ struct es_ctx {
     // workspace (device)
     double* prim;   // padded, nprim comps
     double* met;    // padded, nmet comps
+    double* met1;   // padded, nmet comps (stage-1 metrics, 2D)
+    double* met2;   // padded, nmet comps (stage-2 metrics, 2D)
     double* L;      // interior, d slabs of m + 1 comps (stage residual by direction, J last)
     double* Us;     // interior, m comps (stage-1 state)
     double* Js;     // interior
@@ -47,7 +49,6 @@ struct es_ctx {
     // HIP graph of one es_rk3_step (replayed while the argument pointers stay the same)
     int use_graph;
     hipStream_t cap;            // capture / replay stream (default priority)
-    hipEvent_t ev_in, ev_out;
     hipGraphExec_t gexec;
     const void* gkey[6];
 };
@@ -67,6 +68,12 @@ int reduction_blocks(const GridDev& g);
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
                           hipStream_t s);
+// the metrics of the three stage meshes x + c dt xdot (c = 0, 1, 1/2) in one launch;
+// met0 holds the spatial metrics of x on entry (only its temporal part is written)
+bool metrics_stages_batched(const es_ctx* c);
+hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double* xdot,
+                                 const double* dt_dev, double* met0, double* met1, double* met2,
+                                 hipStream_t s);
 // residual by direction: slab k of Ld (dim slabs of m + 1 components) holds direction k's part
 hipError_t launch_residual_dirs(const es_ctx* c, const double* prim, const double* met, double* Ld,
                                 hipStream_t s);

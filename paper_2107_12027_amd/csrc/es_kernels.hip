@@ -208,6 +208,79 @@ __global__ void __launch_bounds__(256) k_metrics2d_fused(GridDev g, const double
     }
 }
 
+// The three stage metrics of an RK3 step in one launch (2D): the extended mesh X
+// = x (with the periodic shift) and its velocity V are staged once per tile, the
+// stage meshes are X + c_s dt V (c = 0, 1, 1/2), and the differences and the
+// temporal metrics (velocity V at the node) are those of k_metrics2d_fused.
+// met0 must hold the spatial metrics of x on entry; only its temporal
+// components are written.
+__global__ void __launch_bounds__(256) k_metrics2d_stages(GridDev g, const double* __restrict__ x,
+                                                          const double* __restrict__ xd,
+                                                          const double* __restrict__ dt_dev,
+                                                          double* __restrict__ met0, double* __restrict__ met1,
+                                                          double* __restrict__ met2) {
+    __shared__ double xs[2][MRY][MRX];
+    __shared__ double vs[2][MRY][MRX];
+    const int tid = threadIdx.y * MTX + threadIdx.x;
+    const int i0 = -NG + (int)blockIdx.x * MTX, j0 = -NG + (int)blockIdx.y * MTY;
+    for (int q = tid; q < MRX * MRY; q += MTX * MBY) {
+        const int ri = q % MRX, rj = q / MRX;
+        const int i = i0 - NG + ri, j = j0 - NG + rj;
+        const bool ok = i >= -2 * NG && i < g.n[0] + 2 * NG && j >= -2 * NG && j < g.n[1] + 2 * NG;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            xs[c][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, c, i, j, 0, true) : 0.0;
+            vs[c][rj][ri] = ok ? mesh_value(g, xd, nullptr, 0.0, c, i, j, 0, false) : 0.0;
+        }
+    }
+    __syncthreads();
+    const long long P = g.pnodes;
+    const int i = i0 + (int)threadIdx.x;
+    if (i >= g.n[0] + NG) return;
+    const int ri = threadIdx.x + NG;
+    const double dt = dt_dev[0];
+    for (int row = threadIdx.y; row < MTY; row += MBY) {
+        const int j = j0 + row;
+        if (j >= g.n[1] + NG) break;
+        const int rj = row + NG;
+        const long long t = pidx(g, i, j, 0);
+        const double vx = vs[0][rj][ri], vy = vs[1][rj][ri];
+#pragma unroll
+        for (int st = 0; st < 3; ++st) {
+            const double cdt = (st == 0 ? 0.0 : (st == 1 ? 1.0 : 0.5)) * dt;
+            double dxi[2], deta[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double s = 0.0, r = 0.0;
+#pragma unroll
+                for (int n = 1; n <= 3; ++n) {
+                    const double a = 0.5 * alpha3(n);
+                    s += a * ((xs[c][rj][ri + n] + cdt * vs[c][rj][ri + n]) -
+                              (xs[c][rj][ri - n] + cdt * vs[c][rj][ri - n]));
+                    r += a * ((xs[c][rj + n][ri] + cdt * vs[c][rj + n][ri]) -
+                              (xs[c][rj - n][ri] + cdt * vs[c][rj - n][ri]));
+                }
+                dxi[c] = s;
+                deta[c] = r;
+            }
+            const double xix = deta[1] / g.dxi[1];
+            const double xiy = -deta[0] / g.dxi[1];
+            const double etx = -dxi[1] / g.dxi[0];
+            const double ety = dxi[0] / g.dxi[0];
+            double* met = st == 0 ? met0 : (st == 1 ? met1 : met2);
+            met[0 * P + t] = -(vx * xix + vy * xiy);
+            met[3 * P + t] = -(vx * etx + vy * ety);
+            // met0 already holds the spatial metrics of x (the CFL metrics): the
+            // stage-0 values here are the same numbers (x + 0 v = x)
+            if (st == 0) continue;
+            met[1 * P + t] = xix;
+            met[2 * P + t] = xiy;
+            met[4 * P + t] = etx;
+            met[5 * P + t] = ety;
+        }
+    }
+}
+
 // 3D conservative metric method (eq. SCLCoeff): with the products
 //   Pi_{a,j} = delta_a[x_{j+1}] x_{j+2}   (indices mod 3)
 // on the extension box, J dxi_k/dx_j = (delta_{k+2}[Pi_{k+1,j}] - delta_{k+1}[Pi_{k+2,j}])
@@ -303,13 +376,22 @@ template <int DIM>
 struct ResidualLDS {
     static constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1, NF = 6 + NU + NA;
     double sd[LINES][NF][NLOAD + 1];
-    double sp[LINES][3][M + 1][64];
 };
+
+// Orders the LDS accesses of one wavefront: its lanes exchange data only among
+// themselves (each wavefront owns its line of the LDS buffer), so no block
+// barrier is needed.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // One wavefront per line segment along DIR: loads the segment with its halo into
 // LDS, evaluates the three two-point fluxes owned by each node, the face
 // dissipation and the flux differences, and writes this direction's part of the
-// residual (m components and J) to out.
+// residual (m components and J) to out.  The fluxes F(s-n, s) and the
+// dissipation of face s-1/2 come from the lanes that own them (lane shuffles).
 template <int DIM, int DIR, bool ES, bool MIXED>
 __device__ __forceinline__ void residual_segment(const GridDev& g, double G, double eps,
                                                  const double* __restrict__ prim,
@@ -320,7 +402,6 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
     constexpr int F_RHO = 0, F_P = 1, F_BETA = 2, F_W = 3, F_LR = 4, F_LB = 5, F_U = 6,
                   F_A = 6 + NU;
     auto& sd = lds.sd;
-    auto& sp = lds.sp;
 
     const int lane = threadIdx.x & 63;
     const int line = threadIdx.x >> 6;
@@ -378,7 +459,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 #pragma unroll
         for (int c = 0; c < NA; ++c) sd[line][F_A + c][q] = a[c];
     }
-    __syncthreads();
+    wave_lds_sync();
 
     auto node_at = [&](int q) {
         NodeRHD<NU> nd;
@@ -393,51 +474,54 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
         return nd;
     };
 
-    // ---- two-point fluxes (s, s+n), n = 1..3, owned by the lane of node s
+    // ---- two-point fluxes (s, s+n), n = 1..3, owned by the lane of node s, and
+    // flux differences R_s = -(1/dxi) sum_n alpha_n [F(s,s+n) - F(s-n,s)]
     const int s_own = s0 - NG + lane;
-    {
-        const bool valid = active && s_own < s_end;
-        if (valid) {
-            const NodeRHD<NU> l = node_at(lane);
-            double al[NA];
-#pragma unroll
-            for (int c = 0; c < NA; ++c) al[c] = sd[line][F_A + c][lane];
-#pragma unroll
-            for (int n = 1; n <= 3; ++n) {
-                const NodeRHD<NU> r = node_at(lane + n);
-                double ar[NA];
-#pragma unroll
-                for (int c = 0; c < NA; ++c) ar[c] = sd[line][F_A + c][lane + n];
-                double F[M], Jt;
-                if (MIXED) pair_flux_rhd_mixed<NU>(G, l, r, al, ar, F, Jt);
-                else pair_flux_rhd<NU>(G, l, r, al, ar, F, Jt);
-#pragma unroll
-                for (int c = 0; c < M; ++c) sp[line][n - 1][c][lane] = F[c];
-                sp[line][n - 1][M][lane] = Jt;
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- flux differences: R_s = -(1/dxi) sum_n alpha_n [F(s,s+n) - F(s-n,s)]
+    const bool valid = active && s_own < s_end;
     const bool owner = active && lane >= NG && s_own < s_end;
     const double idxi = 1.0 / g.dxi[DIR];
     double R[M + 1];
 #pragma unroll
     for (int c = 0; c <= M; ++c) R[c] = 0.0;
-    if (owner) {
+    {
+        NodeRHD<NU> l;
+        double al[NA];
+        if (valid) {
+            l = node_at(lane);
 #pragma unroll
-        for (int c = 0; c <= M; ++c) {
-            double s = 0.0;
+            for (int c = 0; c < NA; ++c) al[c] = sd[line][F_A + c][lane];
+        }
 #pragma unroll
-            for (int n = 1; n <= 3; ++n) s += alpha3(n) * (sp[line][n - 1][c][lane] - sp[line][n - 1][c][lane - n]);
-            R[c] = -s * idxi;
+        for (int n = 1; n <= 3; ++n) {
+            double F[M + 1];
+#pragma unroll
+            for (int c = 0; c <= M; ++c) F[c] = 0.0;
+            if (valid) {
+                const NodeRHD<NU> r = node_at(lane + n);
+                double ar[NA];
+#pragma unroll
+                for (int c = 0; c < NA; ++c) ar[c] = sd[line][F_A + c][lane + n];
+                if (MIXED) pair_flux_rhd_mixed<NU>(G, l, r, al, ar, F, F[M]);
+                else pair_flux_rhd<NU>(G, l, r, al, ar, F, F[M]);
+            }
+            // all lanes take part in the shuffle; owners (lane >= 3) read F(s-n, s)
+#pragma unroll
+            for (int c = 0; c <= M; ++c) R[c] += alpha3(n) * (F[c] - __shfl_up(F[c], n, 64));
+            // one pair at a time (interleaving the three raises register pressure)
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
+#pragma unroll
+    for (int c = 0; c <= M; ++c) R[c] = owner ? -R[c] * idxi : 0.0;
 
     if (ES) {
-        __syncthreads();
+        // the fence makes the dissipation reload its stencil from LDS instead of
+        // keeping the flux phase's node values live (register pressure)
+        wave_lds_sync();
         // ---- face dissipation at s+1/2 for faces s in [s0-1, s_end)
+        double d[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) d[c] = 0.0;
         if (active && lane >= 2 && s_own < s_end) {
             if (MIXED) {
                 // FP32 dissipation from FP32 copies of the stencil states and metrics
@@ -460,10 +544,10 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
                     al[c] = (float)sd[line][F_A + c][lane];
                     ar[c] = (float)sd[line][F_A + c][lane + 1];
                 }
-                float d[M];
-                face_diss_rhd<DIM>((float)G, (float)eps, st, al, ar, d);
+                float df[M];
+                face_diss_rhd<DIM>((float)G, (float)eps, st, al, ar, df);
 #pragma unroll
-                for (int c = 0; c < M; ++c) sp[line][0][c][lane] = (double)d[c];
+                for (int c = 0; c < M; ++c) d[c] = (double)df[c];
             } else {
                 NodeRHD<NU> st[6];
 #pragma unroll
@@ -471,16 +555,13 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
                 double al[NA], ar[NA];
 #pragma unroll
                 for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane]; ar[c] = sd[line][F_A + c][lane + 1]; }
-                double d[M];
                 face_diss_rhd<DIM>(G, eps, st, al, ar, d);
-#pragma unroll
-                for (int c = 0; c < M; ++c) sp[line][0][c][lane] = d[c];
             }
         }
-        __syncthreads();
-        if (owner) {
 #pragma unroll
-            for (int c = 0; c < M; ++c) R[c] += 0.5 * (sp[line][0][c][lane] - sp[line][0][c][lane - 1]) * idxi;
+        for (int c = 0; c < M; ++c) {
+            const double dm = __shfl_up(d[c], 1, 64);
+            if (owner) R[c] += 0.5 * (d[c] - dm) * idxi;
         }
     }
 
@@ -1109,6 +1190,17 @@ hipError_t launch_combine_con2prim(const es_ctx* c, int stage, const double* U0,
     ss.Uout = Uout;
     ss.Jout = Jout;
     return con2prim_from(c, ss, prim, 1, s);
+}
+
+bool metrics_stages_batched(const es_ctx* c) { return c->g.dim == 2; }
+
+hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double* xdot,
+                                 const double* dt_dev, double* met0, double* met1, double* met2,
+                                 hipStream_t s) {
+    const GridDev& g = c->g;
+    const dim3 gm((unsigned)((g.P[0] + MTX - 1) / MTX), (unsigned)((g.P[1] + MTY - 1) / MTY), 1);
+    k_metrics2d_stages<<<gm, dim3(MTX, MBY, 1), 0, s>>>(g, x, xdot, dt_dev, met0, met1, met2);
+    return hipGetLastError();
 }
 
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
