@@ -215,12 +215,14 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
     }
     // con2prim (the primitive workspace holds the previous stage and seeds the
     // pressure iteration), metrics on x^n (spatial part), CFL step
+    // (with the adaptive mesh, dt is finalised inside the mesh launches)
     ES_TRY(es::launch_con2prim(c, U, J, c->prim, 1, s));
-    ES_TRY(es::launch_metrics(c, x, nullptr, nullptr, 0.0, c->met, nullptr, s));
-    ES_TRY(es::launch_cfl(c, c->prim, c->met, J, dt_dev, fixed_dt_dev, s));
+    const bool adaptive = c->monitor.enabled != 0;
+    bool grad_done = false;
+    ES_TRY(es::launch_cfl_mesh(c, c->prim, x, J, dt_dev, fixed_dt_dev, s, adaptive, adaptive, &grad_done));
     // mesh redistribution: x^{n+1} into c->xnew, mesh velocity into xdot
-    if (c->monitor.enabled)
-        ES_TRY(es::launch_mesh(c, c->prim, x, dt_dev, c->xnew, xdot, nullptr, s));
+    if (adaptive)
+        ES_TRY(es::launch_mesh(c, c->prim, x, dt_dev, c->xnew, xdot, nullptr, s, true, fixed_dt_dev, grad_done));
     else
         ES_TRY(es::launch_zero_mesh_velocity(c, x, c->xnew, xdot, s));
     if (ckpt) {

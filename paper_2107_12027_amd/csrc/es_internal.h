@@ -48,7 +48,7 @@ struct es_ctx {
     double* gdir;       // padded, d slabs of m comps: primitive cotangents by direction
     // HIP graph of one es_rk3_step (replayed while the argument pointers stay the same)
     int use_graph;
-    hipStream_t cap;            // capture / replay stream (default priority)
+    hipStream_t cap;            // capture stream (default priority)
     hipGraphExec_t gexec;
     const void* gkey[6];
 };
@@ -68,8 +68,7 @@ int reduction_blocks(const GridDev& g);
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
                           hipStream_t s);
-// the metrics of the three stage meshes x + c dt xdot (c = 0, 1, 1/2) in one launch;
-// met0 holds the spatial metrics of x on entry (only its temporal part is written)
+// the metrics of the three stage meshes x + c dt xdot (c = 0, 1, 1/2) in one launch
 bool metrics_stages_batched(const es_ctx* c);
 hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double* xdot,
                                  const double* dt_dev, double* met0, double* met1, double* met2,
@@ -80,10 +79,20 @@ hipError_t launch_residual_dirs(const es_ctx* c, const double* prim, const doubl
 // dU, dJ = sum over directions (through the context's slabs)
 hipError_t launch_residual(const es_ctx* c, const double* prim, const double* met, double* dU,
                            double* dJ, hipStream_t s);
+// defer_final: only the per-block CFL maxima are formed; launch_mesh with
+// dt_pending finalises dt before its first use.
 hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, const double* J,
-                      double* dt_dev, const double* fixed_dt_dev, hipStream_t s);
+                      double* dt_dev, const double* fixed_dt_dev, hipStream_t s, bool defer_final = false);
+// CFL step from the mesh x (spatial metrics formed on the fly; c->met is used as
+// workspace where they are not).  with_monitor: the launch may also form the
+// monitor gradient for launch_mesh; *monitor_done tells whether it did.
+hipError_t launch_cfl_mesh(const es_ctx* c, const double* prim, const double* x, const double* J,
+                           double* dt_dev, const double* fixed_dt_dev, hipStream_t s, bool defer_final,
+                           bool with_monitor, bool* monitor_done);
 hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, const double* dt_dev,
-                       double* x_new, double* xdot, double* dtau_dev, hipStream_t s);
+                       double* x_new, double* xdot, double* dtau_dev, hipStream_t s,
+                       bool dt_pending = false, const double* fixed_dt_dev = nullptr,
+                       bool grad_done = false);
 hipError_t launch_zero_mesh_velocity(const es_ctx* c, const double* x, double* x_new, double* xdot,
                                      hipStream_t s);
 // xsrc/xdst (optional): copy the new mesh in the same launch (last stage)

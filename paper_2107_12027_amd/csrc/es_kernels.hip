@@ -212,8 +212,6 @@ __global__ void __launch_bounds__(256) k_metrics2d_fused(GridDev g, const double
 // = x (with the periodic shift) and its velocity V are staged once per tile, the
 // stage meshes are X + c_s dt V (c = 0, 1, 1/2), and the differences and the
 // temporal metrics (velocity V at the node) are those of k_metrics2d_fused.
-// met0 must hold the spatial metrics of x on entry; only its temporal
-// components are written.
 __global__ void __launch_bounds__(256) k_metrics2d_stages(GridDev g, const double* __restrict__ x,
                                                           const double* __restrict__ xd,
                                                           const double* __restrict__ dt_dev,
@@ -270,9 +268,6 @@ __global__ void __launch_bounds__(256) k_metrics2d_stages(GridDev g, const doubl
             double* met = st == 0 ? met0 : (st == 1 ? met1 : met2);
             met[0 * P + t] = -(vx * xix + vy * xiy);
             met[3 * P + t] = -(vx * etx + vy * ety);
-            // met0 already holds the spatial metrics of x (the CFL metrics): the
-            // stage-0 values here are the same numbers (x + 0 v = x)
-            if (st == 0) continue;
             met[1 * P + t] = xix;
             met[2 * P + t] = xiy;
             met[4 * P + t] = etx;
@@ -615,15 +610,87 @@ __global__ void k_sum_dirs(long long N, int M, int dim, const double* __restrict
     if (t < N * M) dU[t] = v; else dJ[t - N * M] = v;
 }
 
+// Monitor at interior node (i, j, k) (Section 5): |grad sigma| from central
+// differences in computational space (one-sided at outflow edges), stored in w
+// as omega = sqrt(1 + alpha |grad sigma|^2) (sqgrad) or as |grad sigma| for the
+// later normalisation by its maximum; returns the value that enters that maximum.
+template <int DIM>
+__device__ __forceinline__ double monitor_node(const GridDev& g, int M, int sigma_ln, int sqgrad, double alpha,
+                                               const double* __restrict__ prim, double* __restrict__ w,
+                                               int i, int j, int k) {
+    const long long P = g.pnodes;
+    const int c[3] = {i, j, k};
+    const long long pc = pidx(g, i, j, k);
+    const long long off = sigma_ln ? M * P : 0;
+    const long long strides[3] = {1, (long long)g.P[0], (long long)g.P[0] * g.P[1]};
+    double g2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        // neighbours through the solution rule: ghosts of the padded box hold
+        // the periodic copies, so only outflow edges need the one-sided form
+        const double sp = prim[off + pc + strides[a]];
+        const double sm = prim[off + pc - strides[a]];
+        const double s0 = prim[off + pc];
+        double d;
+        if (g.bc[a] == ES_BC_PERIODIC || (c[a] > 0 && c[a] < g.n[a] - 1)) d = (sp - sm) / (2.0 * g.dxi[a]);
+        else if (c[a] == 0) d = (sp - s0) / g.dxi[a];
+        else d = (s0 - sm) / g.dxi[a];
+        g2 += d * d;
+    }
+    const long long t = iidx(g, i, j, k);
+    if (sqgrad) {
+        w[t] = sqrt(1.0 + alpha * g2);
+        return 0.0;
+    }
+    const double gn = sqrt(g2);
+    w[t] = gn;
+    return gn;
+}
+
 // ---------------------------------------------------------------------------
 // CFL (eq. cfl): per-direction maxima of rho_k = L_k max|lambda| / J
 // ---------------------------------------------------------------------------
+// rho_k = L_k max|lambda_pm| / J at padded node pi for the spatial metrics ax[k]
+// (the acoustic speeds bound |v_n|)
+template <int DIM>
+__device__ __forceinline__ void cfl_node(double G, const double* __restrict__ prim, long long P,
+                                         long long pi, double Jv, const double (&ax)[DIM][DIM],
+                                         double* mx) {
+    constexpr int M = DIM + 2;
+    const double rho = prim[pi], p = prim[(M - 1) * P + pi];
+    double u[DIM], uu = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { u[c] = prim[(1 + c) * P + pi]; uu += u[c] * u[c]; }
+    const double W = sqrt(1.0 + uu);
+    const double v2 = uu / (W * W);
+    const double h = 1.0 + G / (G - 1.0) * p / rho;
+    const double cs2 = G * p / (rho * h);
+    const double cs = sqrt(cs2);
+    const double iJ = 1.0 / Jv;
+#pragma unroll
+    for (int kd = 0; kd < DIM; ++kd) {
+        double L2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) L2 += ax[kd][c] * ax[kd][c];
+        const double L = sqrt(L2);
+        double vn = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) vn += ax[kd][c] * u[c];
+        vn = vn / (L * W);
+        const double disc = sqrt((1.0 - v2) * (1.0 - v2 * cs2 - vn * vn * (1.0 - cs2)));
+        const double iden = 1.0 / (1.0 - v2 * cs2);
+        const double lm = (vn * (1.0 - cs2) - cs * disc) * iden;
+        const double lp = (vn * (1.0 - cs2) + cs * disc) * iden;
+        mx[kd] = L * fmax(fabs(lm), fabs(lp)) * iJ;
+    }
+}
+
 template <int DIM>
 __global__ void __launch_bounds__(256) k_cfl_partial(GridDev g, double G, const double* __restrict__ prim,
                                                      const double* __restrict__ met,
                                                      const double* __restrict__ J,
                                                      double* __restrict__ partial) {
-    constexpr int M = DIM + 2, NA = DIM + 1;
+    constexpr int NA = DIM + 1;
     __shared__ double sh[8];
     double mx[DIM];
 #pragma unroll
@@ -632,32 +699,12 @@ __global__ void __launch_bounds__(256) k_cfl_partial(GridDev g, double G, const 
     int i, j, k;
     if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
         const long long pi = pidx(g, i, j, k);
-        const double rho = prim[pi], p = prim[(M - 1) * P + pi];
-        double u[DIM], uu = 0.0;
+        double ax[DIM][DIM];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) { u[c] = prim[(1 + c) * P + pi]; uu += u[c] * u[c]; }
-        const double W = sqrt(1.0 + uu);
-        const double v2 = uu / (W * W);
-        const double h = 1.0 + G / (G - 1.0) * p / rho;
-        const double cs2 = G * p / (rho * h);
-        const double cs = sqrt(cs2);
-        const double iJ = 1.0 / J[iidx(g, i, j, k)];
+        for (int kd = 0; kd < DIM; ++kd)
 #pragma unroll
-        for (int kd = 0; kd < DIM; ++kd) {
-            double ax[DIM], L2 = 0.0;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) { ax[c] = met[(kd * NA + 1 + c) * P + pi]; L2 += ax[c] * ax[c]; }
-            const double L = sqrt(L2);
-            double vn = 0.0;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) vn += ax[c] * u[c];
-            vn = vn / (L * W);
-            const double disc = sqrt((1.0 - v2) * (1.0 - v2 * cs2 - vn * vn * (1.0 - cs2)));
-            const double iden = 1.0 / (1.0 - v2 * cs2);
-            const double lm = (vn * (1.0 - cs2) - cs * disc) * iden;
-            const double lp = (vn * (1.0 - cs2) + cs * disc) * iden;
-            mx[kd] = L * fmax(fabs(lm), fabs(lp)) * iJ;
-        }
+            for (int c = 0; c < DIM; ++c) ax[kd][c] = met[(kd * NA + 1 + c) * P + pi];
+        cfl_node<DIM>(G, prim, P, pi, J[iidx(g, i, j, k)], ax, mx);
     }
     const int nb = (int)(gridDim.x * gridDim.y * gridDim.z);
 #pragma unroll
@@ -667,19 +714,94 @@ __global__ void __launch_bounds__(256) k_cfl_partial(GridDev g, double G, const 
     }
 }
 
-__global__ void __launch_bounds__(256) k_cfl_final(int dim, int nb, double cfl, double dx0, double dx1,
-                                                   double dx2, const double* __restrict__ partial,
-                                                   const double* __restrict__ fixed_dt,
-                                                   double* __restrict__ dt_out) {
+// CFL maxima with the spatial metrics of x formed in the kernel (2D): a block
+// stages the extended mesh of its 64 x 4 interior tile plus a 3-node halo in
+// LDS (as k_metrics2d_fused) and evaluates the metrics at its nodes from there.
+struct MonitorArgs {
+    int enabled, M, sigma_ln, sqgrad;
+    double alpha;
+    double* w;         // interior omega (or |grad sigma|)
+    double* partial;   // block maxima of |grad sigma|
+};
+
+__global__ void __launch_bounds__(256) k_cfl_partial2d_mesh(GridDev g, double G, const double* __restrict__ prim,
+                                                            const double* __restrict__ x,
+                                                            const double* __restrict__ J,
+                                                            double* __restrict__ partial, MonitorArgs mon) {
+    __shared__ double xs[2][MRY][MRX];
     __shared__ double sh[8];
-    double tot = 0.0;
-    for (int kd = 0; kd < dim; ++kd) {
-        double m = 0.0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) m = fmax(m, partial[kd * nb + b]);
-        m = block_reduce<0>(m, sh);
-        tot += m / (kd == 0 ? dx0 : (kd == 1 ? dx1 : dx2));
+    const int tid = threadIdx.y * MTX + threadIdx.x;
+    const int i0 = (int)blockIdx.x * MTX, j0 = (int)blockIdx.y * MBY;
+    const int i = i0 + (int)threadIdx.x, j = j0 + (int)threadIdx.y;
+    const bool inside = i < g.n[0] && j < g.n[1];
+    // the monitor needs no metrics: its loads overlap the mesh staging
+    double gmx = 0.0;
+    if (mon.enabled && inside) gmx = monitor_node<2>(g, mon.M, mon.sigma_ln, mon.sqgrad, mon.alpha, prim, mon.w, i, j, 0);
+    for (int q = tid; q < MRX * (MBY + 2 * NG); q += MTX * MBY) {
+        const int ri = q % MRX, rj = q / MRX;
+        const int i = i0 - NG + ri, j = j0 - NG + rj;
+        const bool ok = i < g.n[0] + 2 * NG && j < g.n[1] + 2 * NG;
+        xs[0][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, 0, i, j, 0, true) : 0.0;
+        xs[1][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, 1, i, j, 0, true) : 0.0;
     }
-    if (threadIdx.x == 0) dt_out[0] = fixed_dt != nullptr ? fixed_dt[0] : cfl / tot;
+    __syncthreads();
+    double mx[2] = {0.0, 0.0};
+    if (inside) {
+        const int ri = threadIdx.x + NG, rj = threadIdx.y + NG;
+        double dxi[2], deta[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            double s = 0.0, r = 0.0;
+#pragma unroll
+            for (int n = 1; n <= 3; ++n) {
+                const double a = 0.5 * alpha3(n);
+                s += a * (xs[c][rj][ri + n] - xs[c][rj][ri - n]);
+                r += a * (xs[c][rj + n][ri] - xs[c][rj - n][ri]);
+            }
+            dxi[c] = s;
+            deta[c] = r;
+        }
+        const double ax[2][2] = {{deta[1] / g.dxi[1], -deta[0] / g.dxi[1]},
+                                 {-dxi[1] / g.dxi[0], dxi[0] / g.dxi[0]}};
+        cfl_node<2>(G, prim, g.pnodes, pidx(g, i, j, 0), J[iidx(g, i, j, 0)], ax, mx);
+    }
+    const int nb = (int)(gridDim.x * gridDim.y);
+#pragma unroll
+    for (int kd = 0; kd < 2; ++kd) {
+        const double r = block_reduce<0>(mx[kd], sh);
+        if (tid == 0) partial[kd * nb + flat_block()] = r;
+    }
+    if (mon.enabled) {
+        const double r = block_reduce<0>(gmx, sh);
+        if (tid == 0) mon.partial[flat_block()] = r;
+    }
+}
+
+// Final reduction of the CFL partial maxima into dt (one block; every thread of
+// the block must call it).
+struct DtFinal {
+    const double* partial;   // dim slabs of nb block maxima
+    int nb, dim;
+    double cfl, dx[3];
+    const double* fixed_dt;  // optional prescribed dt
+    double* dt_out;
+};
+
+__device__ __forceinline__ void finalize_dt(const DtFinal& f, double* sh) {
+    double tot = 0.0;
+    const int tid = flat_tid(), nt = (int)(blockDim.x * blockDim.y * blockDim.z);
+    for (int kd = 0; kd < f.dim; ++kd) {
+        double m = 0.0;
+        for (int b = tid; b < f.nb; b += nt) m = fmax(m, f.partial[kd * f.nb + b]);
+        m = block_reduce<0>(m, sh);
+        tot += m / f.dx[kd];
+    }
+    if (tid == 0) f.dt_out[0] = f.fixed_dt != nullptr ? f.fixed_dt[0] : f.cfl / tot;
+}
+
+__global__ void __launch_bounds__(256) k_cfl_final(DtFinal f) {
+    __shared__ double sh[8];
+    finalize_dt(f, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -690,37 +812,9 @@ __global__ void __launch_bounds__(256) k_monitor_grad(GridDev g, int M, int sigm
                                                       double alpha, const double* __restrict__ prim,
                                                       double* __restrict__ w, double* __restrict__ partial) {
     __shared__ double sh[8];
-    const long long P = g.pnodes;
     double mx = 0.0;
     int i, j, k;
-    if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
-        const int c[3] = {i, j, k};
-        const long long pc = pidx(g, i, j, k);
-        const long long off = sigma_ln ? M * P : 0;
-        const long long strides[3] = {1, (long long)g.P[0], (long long)g.P[0] * g.P[1]};
-        double g2 = 0.0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            // neighbours through the solution rule: ghosts of the padded box hold
-            // the periodic copies, so only outflow edges need the one-sided form
-            const double sp = prim[off + pc + strides[a]];
-            const double sm = prim[off + pc - strides[a]];
-            const double s0 = prim[off + pc];
-            double d;
-            if (g.bc[a] == ES_BC_PERIODIC || (c[a] > 0 && c[a] < g.n[a] - 1)) d = (sp - sm) / (2.0 * g.dxi[a]);
-            else if (c[a] == 0) d = (sp - s0) / g.dxi[a];
-            else d = (s0 - sm) / g.dxi[a];
-            g2 += d * d;
-        }
-        const long long t = iidx(g, i, j, k);
-        if (sqgrad) {
-            w[t] = sqrt(1.0 + alpha * g2);
-        } else {
-            const double gn = sqrt(g2);
-            w[t] = gn;
-            mx = gn;
-        }
-    }
+    if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) mx = monitor_node<DIM>(g, M, sigma_ln, sqgrad, alpha, prim, w, i, j, k);
     const double r = block_reduce<0>(mx, sh);
     if (flat_tid() == 0) partial[flat_block()] = r;
 }
@@ -783,15 +877,23 @@ __global__ void k_filter(GridDev g, const double* __restrict__ win, double* __re
 constexpr int FTX = 64, FTY = 4, FH = 5;
 constexpr int FRX = FTX + 2 * FH, FRY = FTY + 2 * FH;
 
+// With apply, every block reduces the nb partial maxima of |grad sigma| itself
+// (no separate reduction launch); with dt_fin, block 0 also finalises dt.
 __global__ void __launch_bounds__(256) k_monitor_filter2d(GridDev g, int apply, double alpha,
-                                                          const double* __restrict__ gmax, int passes,
-                                                          const double* __restrict__ win,
-                                                          double* __restrict__ wout) {
+                                                          const double* __restrict__ gpart, int nb,
+                                                          int passes, const double* __restrict__ win,
+                                                          double* __restrict__ wout, DtFinal dt_fin) {
     __shared__ double ws[2][FRY][FRX];
+    __shared__ double sh[8];
     const int tid = threadIdx.y * FTX + threadIdx.x;
     const int i0 = (int)blockIdx.x * FTX - FH, j0 = (int)blockIdx.y * FTY - FH;
     const int n0 = g.n[0], n1 = g.n[1];
-    const double m = apply ? gmax[0] : 0.0;
+    if (dt_fin.dt_out != nullptr && blockIdx.x == 0 && blockIdx.y == 0) finalize_dt(dt_fin, sh);
+    double m = 0.0;
+    if (apply) {
+        for (int b = tid; b < nb; b += FTX * FTY) m = fmax(m, gpart[b]);
+        m = block_reduce<0>(m, sh);
+    }
     for (int q = tid; q < FRX * FRY; q += FTX * FTY) {
         const int ri = q % FRX, rj = q / FRX;
         const int ii = map_sol(i0 + ri, n0, g.bc[0]), jj = map_sol(j0 + rj, n1, g.bc[1]);
@@ -889,6 +991,25 @@ __global__ void k_jacobi(GridDev g, const double* __restrict__ w, const double* 
     }
 }
 
+// Largest admissible pseudo-time fraction at interior node c (index t) for the
+// relaxed coordinates xm_a (eq. dtau): a node moves at most half-way towards its
+// neighbour along each coordinate direction.
+template <int DIM>
+__device__ __forceinline__ double dtau_bound(const GridDev& g, const double* __restrict__ x,
+                                             const int* c, long long t, const double* xm) {
+    double best = 1.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const long long o = (long long)a * g.nodes + t;
+        const double dk = xm[a] - x[o];
+        if (dk == 0.0) continue;       // fixed coordinates (outflow edges) never move
+        const double nb = mesh_nb<DIM>(g, x, a, c, a, dk > 0.0 ? 1 : -1);
+        const double b = dk < 0.0 ? -(x[o] - nb) / (2.0 * dk) : (nb - x[o]) / (2.0 * dk);
+        best = fmin(best, b);
+    }
+    return best;
+}
+
 // Several Jacobi sweeps in one launch (2D): a block stages its TX x TY tile of
 // outputs with a halo of JS nodes (x and omega) in LDS and applies the sweep of
 // k_jacobi `sweeps` <= JS times to the shrinking valid region; periodic copies
@@ -898,11 +1019,16 @@ __global__ void k_jacobi(GridDev g, const double* __restrict__ w, const double* 
 constexpr int JTX = 64, JTY = 8, JS = 5;
 constexpr int JRX = JTX + 2 * JS, JRY = JTY + 2 * JS;
 
+// With dtau_part (last launch), each block also writes the minimum of the
+// Delta tau bound over its tile (x0: the mesh before the sweeps).
 __global__ void __launch_bounds__(256) k_jacobi_multi2d(GridDev g, int sweeps, const double* __restrict__ w,
                                                         const double* __restrict__ xin,
-                                                        double* __restrict__ xout) {
+                                                        double* __restrict__ xout,
+                                                        const double* __restrict__ x0,
+                                                        double* __restrict__ dtau_part) {
     __shared__ double xs[2][2][JRY][JRX];
     __shared__ double ws[JRY][JRX];
+    __shared__ double sh[8];
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x * JTX - JS, j0 = blockIdx.y * JTY - JS;
     const int n0 = g.n[0], n1 = g.n[1];
@@ -933,46 +1059,94 @@ __global__ void __launch_bounds__(256) k_jacobi_multi2d(GridDev g, int sweeps, c
         ws[rj][ri] = ww;
     }
     __syncthreads();
-    int cur = 0;
-    for (int sw = 1; sw <= sweeps; ++sw) {
-        for (int q = tid; q < JRX * JRY; q += 256) {
+    // each thread keeps the sweep coefficients of its region positions in
+    // registers: x_new = sum_k c_k x_k over the four neighbours, c_k = (w_c +
+    // w_k) / den over the free axes; flags: bit 0 / 1 = component 0 / 1 is
+    // updated (its axis is free and den > 0), bits 2.. = depth in the region
+    // (the position is valid for sweeps up to its depth)
+    constexpr int NQ = (JRX * JRY + 255) / 256;
+    double cf[NQ][4];
+    int fl[NQ];
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+        const int q = tid + 256 * r;
+        cf[r][0] = cf[r][1] = cf[r][2] = cf[r][3] = 0.0;
+        fl[r] = 0;
+        if (q < JRX * JRY) {
             const int ri = q % JRX, rj = q / JRX;
-            double v0 = xs[cur][0][rj][ri], v1 = xs[cur][1][rj][ri];
-            if (ri >= sw && ri < JRX - sw && rj >= sw && rj < JRY - sw) {
+            const int depth = min(min(ri, JRX - 1 - ri), min(rj, JRY - 1 - rj));
+            if (depth >= 1) {
                 const int gi = i0 + ri, gj = j0 + rj;
                 const bool fr0 = per0 || (gi > 0 && gi < n0 - 1);
                 const bool fr1 = per1 || (gj > 0 && gj < n1 - 1);
                 const double wc = ws[rj][ri];
-                double den = 0.0, num0 = 0.0, num1 = 0.0;
+                double den = 0.0;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
                 if (fr0) {
                     const double wp = ws[rj][ri + 1], wm = ws[rj][ri - 1];
                     den += 2.0 * wc + wp + wm;
-                    num0 += (wc + wp) * xs[cur][0][rj][ri + 1] + (wc + wm) * xs[cur][0][rj][ri - 1];
-                    num1 += (wc + wp) * xs[cur][1][rj][ri + 1] + (wc + wm) * xs[cur][1][rj][ri - 1];
+                    a0 = wc + wp;
+                    a1 = wc + wm;
                 }
                 if (fr1) {
                     const double wp = ws[rj + 1][ri], wm = ws[rj - 1][ri];
                     den += 2.0 * wc + wp + wm;
-                    num0 += (wc + wp) * xs[cur][0][rj + 1][ri] + (wc + wm) * xs[cur][0][rj - 1][ri];
-                    num1 += (wc + wp) * xs[cur][1][rj + 1][ri] + (wc + wm) * xs[cur][1][rj - 1][ri];
+                    a2 = wc + wp;
+                    a3 = wc + wm;
                 }
-                if (fr0 && den > 0.0) v0 = num0 / den;
-                if (fr1 && den > 0.0) v1 = num1 / den;
+                if (den > 0.0) {
+                    const double id = 1.0 / den;
+                    cf[r][0] = a0 * id;
+                    cf[r][1] = a1 * id;
+                    cf[r][2] = a2 * id;
+                    cf[r][3] = a3 * id;
+                    fl[r] = (fr0 ? 1 : 0) | (fr1 ? 2 : 0);
+                }
+                fl[r] |= depth << 2;
             }
-            xs[cur ^ 1][0][rj][ri] = v0;
-            xs[cur ^ 1][1][rj][ri] = v1;
+        }
+    }
+    int cur = 0;
+    for (int sw = 1; sw <= sweeps; ++sw) {
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+            const int q = tid + 256 * r;
+            if (q < JRX * JRY) {
+                const int ri = q % JRX, rj = q / JRX;
+                double v0 = xs[cur][0][rj][ri], v1 = xs[cur][1][rj][ri];
+                if ((fl[r] >> 2) >= sw) {
+                    if (fl[r] & 1)
+                        v0 = cf[r][0] * xs[cur][0][rj][ri + 1] + cf[r][1] * xs[cur][0][rj][ri - 1] +
+                             cf[r][2] * xs[cur][0][rj + 1][ri] + cf[r][3] * xs[cur][0][rj - 1][ri];
+                    if (fl[r] & 2)
+                        v1 = cf[r][0] * xs[cur][1][rj][ri + 1] + cf[r][1] * xs[cur][1][rj][ri - 1] +
+                             cf[r][2] * xs[cur][1][rj + 1][ri] + cf[r][3] * xs[cur][1][rj - 1][ri];
+                }
+                xs[cur ^ 1][0][rj][ri] = v0;
+                xs[cur ^ 1][1][rj][ri] = v1;
+            }
         }
         cur ^= 1;
         __syncthreads();
     }
+    double best = 1.0;
     for (int q = tid; q < JTX * JTY; q += 256) {
         const int oi = q % JTX, oj = q / JTX;
         const int gi = blockIdx.x * JTX + oi, gj = blockIdx.y * JTY + oj;
         if (gi < n0 && gj < n1) {
             const long long t = (long long)gj * n0 + gi;
-            xout[t] = xs[cur][0][oj + JS][oi + JS];
-            xout[g.nodes + t] = xs[cur][1][oj + JS][oi + JS];
+            const double xm[2] = {xs[cur][0][oj + JS][oi + JS], xs[cur][1][oj + JS][oi + JS]};
+            xout[t] = xm[0];
+            xout[g.nodes + t] = xm[1];
+            if (dtau_part != nullptr) {
+                const int c[3] = {gi, gj, 0};
+                best = fmin(best, dtau_bound<2>(g, x0, c, t, xm));
+            }
         }
+    }
+    if (dtau_part != nullptr) {
+        best = block_reduce<1>(best, sh);
+        if (tid == 0) dtau_part[blockIdx.y * gridDim.x + blockIdx.x] = best;
     }
 }
 
@@ -986,27 +1160,36 @@ __global__ void __launch_bounds__(256) k_dtau_partial(GridDev g, const double* _
     if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
         const int c[3] = {i, j, k};
         const long long t = iidx(g, i, j, k);
+        double xv[DIM];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const long long o = (long long)a * g.nodes + t;
-            const double dk = xm[o] - x[o];
-            if (dk == 0.0) continue;       // fixed coordinates (outflow edges) never move
-            const double nb = mesh_nb<DIM>(g, x, a, c, a, dk > 0.0 ? 1 : -1);
-            const double b = dk < 0.0 ? -(x[o] - nb) / (2.0 * dk) : (nb - x[o]) / (2.0 * dk);
-            best = fmin(best, b);
-        }
+        for (int a = 0; a < DIM; ++a) xv[a] = xm[(long long)a * g.nodes + t];
+        best = dtau_bound<DIM>(g, x, c, t, xv);
     }
     const double r = block_reduce<1>(best, sh);
     if (flat_tid() == 0) partial[flat_block()] = r;
 }
 
-__global__ void k_mesh_update(long long n, const double* __restrict__ x, const double* __restrict__ xm,
-                              const double* __restrict__ dtau, const double* __restrict__ dt,
-                              double* __restrict__ xnew, double* __restrict__ xdot) {
+// x^{n+1} = x + dtau (xm - x), xdot = dtau (xm - x) / dt.  With nb > 0 every
+// block reduces the nb partial minima of the Delta tau bound itself (capped at
+// 1) and block 0 stores the result in dtau; otherwise dtau holds it.
+__global__ void __launch_bounds__(256) k_mesh_update(long long n, const double* __restrict__ x,
+                                                     const double* __restrict__ xm, double* __restrict__ dtau,
+                                                     const double* __restrict__ part, int nb,
+                                                     const double* __restrict__ dt, double* __restrict__ xnew,
+                                                     double* __restrict__ xdot) {
+    __shared__ double sh[8];
+    double a;
+    if (nb > 0) {
+        a = 1.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) a = fmin(a, part[b]);
+        a = block_reduce<1>(a, sh);
+        if (blockIdx.x == 0 && threadIdx.x == 0) dtau[0] = a;
+    } else {
+        a = dtau[0];
+    }
     const long long t = gtid();
     if (t >= n) return;
     const double dx = xm[t] - x[t];
-    const double a = dtau[0];
     xnew[t] = x[t] + a * dx;
     xdot[t] = a * dx / dt[0];
 }
@@ -1265,8 +1448,54 @@ hipError_t launch_residual(const es_ctx* c, const double* prim, const double* me
     return hipGetLastError();
 }
 
+// reduction partials in c->red: CFL maxima (dim slabs), monitor maxima, Delta tau minima
+inline double* red_cfl(const es_ctx* c) { return c->red; }
+inline double* red_monitor(const es_ctx* c) { return c->red + 3 * (long long)c->red_blocks; }
+inline double* red_dtau(const es_ctx* c) { return c->red + 4 * (long long)c->red_blocks; }
+
+inline DtFinal cfl_final_args(const es_ctx* c, const double* fixed_dt_dev, double* dt_dev) {
+    const GridDev& g = c->g;
+    DtFinal f;
+    f.partial = red_cfl(c);
+    f.nb = interior_blocks(g);
+    f.dim = g.dim;
+    f.cfl = c->scheme.cfl;
+    f.dx[0] = g.dxi[0];
+    f.dx[1] = g.dxi[1];
+    f.dx[2] = g.dxi[2];
+    f.fixed_dt = fixed_dt_dev;
+    f.dt_out = dt_dev;
+    return f;
+}
+
+hipError_t launch_cfl_mesh(const es_ctx* c, const double* prim, const double* x, const double* J,
+                           double* dt_dev, const double* fixed_dt_dev, hipStream_t s, bool defer_final,
+                           bool with_monitor, bool* monitor_done) {
+    const GridDev& g = c->g;
+    if (monitor_done != nullptr) *monitor_done = false;
+    if (c->scheme.phys == ES_RMHD || g.dim != 2) {
+        const hipError_t e = launch_metrics(c, x, nullptr, nullptr, 0.0, c->met, nullptr, s);
+        if (e != hipSuccess) return e;
+        return launch_cfl(c, prim, c->met, J, dt_dev, fixed_dt_dev, s, defer_final);
+    }
+    MonitorArgs mon{};
+    if (with_monitor) {
+        mon.enabled = 1;
+        mon.M = c->m;
+        mon.sigma_ln = c->monitor.sigma == ES_SIGMA_LNRHO;
+        mon.sqgrad = c->monitor.form == ES_MON_SQGRAD;
+        mon.alpha = c->monitor.alpha;
+        mon.w = c->wa;
+        mon.partial = red_monitor(c);
+    }
+    k_cfl_partial2d_mesh<<<interior_grid(g), box_block(), 0, s>>>(g, c->scheme.gamma, prim, x, J, red_cfl(c), mon);
+    if (!defer_final) k_cfl_final<<<1, 256, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
+    if (monitor_done != nullptr) *monitor_done = with_monitor;
+    return hipGetLastError();
+}
+
 hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, const double* J,
-                      double* dt_dev, const double* fixed_dt_dev, hipStream_t s) {
+                      double* dt_dev, const double* fixed_dt_dev, hipStream_t s, bool defer_final) {
     const GridDev& g = c->g;
     const int nb = interior_blocks(g);
     const double G = c->scheme.gamma;
@@ -1274,12 +1503,11 @@ hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, co
         const hipError_t e = launch_cfl_partial_rmhd(c, prim, met, J, s);
         if (e != hipSuccess) return e;
     } else if (g.dim == 2) {
-        k_cfl_partial<2><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, c->red);
+        k_cfl_partial<2><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, red_cfl(c));
     } else {
-        k_cfl_partial<3><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, c->red);
+        k_cfl_partial<3><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, red_cfl(c));
     }
-    k_cfl_final<<<1, 256, 0, s>>>(g.dim, nb, c->scheme.cfl, g.dxi[0], g.dxi[1], g.dxi[2],
-                                  c->red, fixed_dt_dev, dt_dev);
+    if (!defer_final) k_cfl_final<<<1, 256, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
     return hipGetLastError();
 }
 
@@ -1291,7 +1519,8 @@ hipError_t launch_zero_mesh_velocity(const es_ctx* c, const double* x, double* x
 }
 
 hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, const double* dt_dev,
-                       double* x_new, double* xdot, double* dtau_dev, hipStream_t s) {
+                       double* x_new, double* xdot, double* dtau_dev, hipStream_t s, bool dt_pending,
+                       const double* fixed_dt_dev, bool grad_done) {
     const GridDev& g = c->g;
     const es_monitor& mo = c->monitor;
     const int nb = interior_blocks(g);
@@ -1300,22 +1529,35 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
     const int sq = mo.form == ES_MON_SQGRAD;
     double* w = c->wa;
     double* w2 = c->wb;
-    if (g.dim == 2) k_monitor_grad<2><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
-    else k_monitor_grad<3><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, c->red);
-    if (!sq) k_reduce_final<<<1, 256, 0, s>>>(0, nb, c->red, c->scal + SCAL_GMAX);
+    double* gpart = red_monitor(c);
+    // 2D: the first filter launch finalises a pending dt (block 0); 3D: a launch of its own
+    // (dt_dev is written only when dt is pending: the step's own buffer)
+    DtFinal dt_fin = cfl_final_args(c, fixed_dt_dev, dt_pending ? const_cast<double*>(dt_dev) : nullptr);
+    if (dt_pending && g.dim != 2) k_cfl_final<<<1, 256, 0, s>>>(dt_fin);
+    if (grad_done) {
+        // omega (or |grad sigma|) in c->wa and its block maxima came with the CFL launch
+    } else if (g.dim == 2) {
+        k_monitor_grad<2><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, gpart);
+    } else {
+        k_monitor_grad<3><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, gpart);
+    }
     if (g.dim == 2) {
-        // normalisation and filter passes, FH passes per launch
+        // normalisation (maximum reduced in each block) and filter passes, FH per launch
         int apply = !sq, left = mo.filter_passes;
         do {
             const int k = min(FH, left);
             k_monitor_filter2d<<<box_grid(g.n[0], g.n[1], 1), box_block(), 0, s>>>(
-                g, apply, mo.alpha, c->scal + SCAL_GMAX, k, w, w2);
+                g, apply, mo.alpha, gpart, nb, k, w, w2, dt_fin);
             double* tmp = w; w = w2; w2 = tmp;
             apply = 0;
+            dt_fin.dt_out = nullptr;
             left -= k;
         } while (left > 0);
     } else {
-        if (!sq) k_monitor_apply<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, c->scal + SCAL_GMAX, w);
+        if (!sq) {
+            k_reduce_final<<<1, 256, 0, s>>>(0, nb, gpart, c->scal + SCAL_GMAX);
+            k_monitor_apply<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, c->scal + SCAL_GMAX, w);
+        }
         for (int f = 0; f < mo.filter_passes; ++f) {
             k_filter<3><<<gr, box_block(), 0, s>>>(g, w, w2);
             double* tmp = w; w = w2; w2 = tmp;
@@ -1324,27 +1566,32 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
     const double* xin = x;
     double* xo = c->xa;
     double* xalt = c->xb;
-    if (g.dim == 2) {
+    double* dtau = dtau_dev != nullptr ? dtau_dev : c->scal + SCAL_DTAU;
+    const long long n = g.nodes * g.dim;
+    int nbt = 0;   // Delta tau partials left for k_mesh_update to reduce
+    if (g.dim == 2 && mo.sweeps > 0) {
+        // the last multi-sweep launch also forms the Delta tau block minima
         const dim3 gj((unsigned)((g.n[0] + JTX - 1) / JTX), (unsigned)((g.n[1] + JTY - 1) / JTY), 1);
         for (int done = 0; done < mo.sweeps; done += JS) {
             const int k = min(JS, mo.sweeps - done);
-            k_jacobi_multi2d<<<gj, 256, 0, s>>>(g, k, w, xin, xo);
+            const bool last = done + k >= mo.sweeps;
+            k_jacobi_multi2d<<<gj, 256, 0, s>>>(g, k, w, xin, xo, x, last ? red_dtau(c) : nullptr);
             xin = xo;
             double* tmp = xo; xo = xalt; xalt = tmp;
         }
+        nbt = (int)(gj.x * gj.y);
     } else {
         for (int it = 0; it < mo.sweeps; ++it) {
-            k_jacobi<3><<<gr, box_block(), 0, s>>>(g, w, xin, xo);
+            if (g.dim == 2) k_jacobi<2><<<gr, box_block(), 0, s>>>(g, w, xin, xo);
+            else k_jacobi<3><<<gr, box_block(), 0, s>>>(g, w, xin, xo);
             xin = xo;
             double* tmp = xo; xo = xalt; xalt = tmp;
         }
+        if (g.dim == 2) k_dtau_partial<2><<<gr, box_block(), 0, s>>>(g, x, xin, red_dtau(c));
+        else k_dtau_partial<3><<<gr, box_block(), 0, s>>>(g, x, xin, red_dtau(c));
+        k_reduce_final<<<1, 256, 0, s>>>(1, nb, red_dtau(c), dtau);
     }
-    if (g.dim == 2) k_dtau_partial<2><<<gr, box_block(), 0, s>>>(g, x, xin, c->red);
-    else k_dtau_partial<3><<<gr, box_block(), 0, s>>>(g, x, xin, c->red);
-    double* dtau = dtau_dev != nullptr ? dtau_dev : c->scal + SCAL_DTAU;
-    k_reduce_final<<<1, 256, 0, s>>>(1, nb, c->red, dtau);
-    const long long n = g.nodes * g.dim;
-    k_mesh_update<<<grid_for(n), TPB, 0, s>>>(n, x, xin, dtau, dt_dev, x_new, xdot);
+    k_mesh_update<<<grid_for(n), TPB, 0, s>>>(n, x, xin, dtau, red_dtau(c), nbt, dt_dev, x_new, xdot);
     return hipGetLastError();
 }
 
