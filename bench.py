@@ -66,6 +66,10 @@ def parse():
                     choices=["quadrant", "sine", "rotor", "blast3d", "fourier"],
                     help="quadrant: the headline 2D RHD problem; the others time the remaining "
                          "workloads (FP64 step and residual only)")
+    ap.add_argument("--paper-case", default=None, choices=["rp1", "rp2", "rp3", "rmhd_blast"],
+                    help="run one of the paper's 2D examples to its end time as MM-O5 (adaptive) and "
+                         "UM-O5 (uniform, finer) and report the GPU time-to-solution ratio beside the "
+                         "paper's CPU ratio (not a headline line)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed work, copy one buffer of this size once (a plain copy "
                          "kernel of known traffic, for scaling HBM counters)")
@@ -238,6 +242,61 @@ def other_workload(args):
     print(json.dumps(line))
 
 
+def run_to_end(w, check_every=32, max_wall_s=240.0):
+    """Advance ``w`` with es_rk3_step until t >= t_end (the last step is not
+    clipped); dt is summed on the device and read back every ``check_every``
+    steps, then every step once t_end is within reach.  Returns a dict with the
+    wall time (host clock, from initial data resident in HBM to the final
+    synchronisation), the GPU time between HIP events, the step count and t
+    (a run that exceeds max_wall_s stops early and reports t < t_end)."""
+    import torch
+    run = Run(w, 0)
+    tsum = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx = run.ctx
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    steps, t, dt_last, every = 0, 0.0, None, check_every
+    while t < w.t_end:
+        for _ in range(every):
+            run.step()
+            tsum.add_(run.dt)
+        steps += every
+        t_new = float(tsum.item())
+        dt_last = (t_new - t) / every
+        t = t_new
+        if ctx.status()[0] != 0 or time.perf_counter() - t_wall > max_wall_s:
+            break
+        if t + check_every * dt_last >= w.t_end:
+            every = 1
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    status, nfail, first = ctx.status()
+    return {"workload": w.name, "grid": list(w.grid.shape[::-1]), "steps": steps, "t": t,
+            "wall_s": wall, "gpu_s": e0.elapsed_time(e1) * 1e-3, "status": int(status),
+            "failed_nodes": int(nfail), "ms_per_step": e0.elapsed_time(e1) / max(steps, 1)}
+
+
+def paper_case(args):
+    """MM-O5 vs UM-O5 time to solution for one of the paper's 2D examples."""
+    from paper_2107_12027_amd import workloads as wl
+    make, n_mm, n_um, paper_ratio = wl.PAPER_COMPARISONS[args.paper_case]
+    mm = run_to_end(make(n_mm, True))
+    um = run_to_end(make(n_um, False))
+    um_same = run_to_end(make(n_mm, False))     # the moving-mesh overhead at equal resolution
+    ok = mm["status"] == 0 and um["status"] == 0
+    line = {"paper_case": args.paper_case, "t_end": make(8, True).t_end, "mm_o5": mm, "um_o5": um,
+            "um_o5_same_grid": um_same,
+            "gpu_time_ratio_mm_over_um": mm["gpu_s"] / um["gpu_s"] if ok else None,
+            "wall_time_ratio_mm_over_um": mm["wall_s"] / um["wall_s"] if ok else None,
+            "paper_cpu_time_ratio": paper_ratio, "dtype": "f64", "data": "synthetic (the paper's initial data)"}
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -247,6 +306,8 @@ def main():
     from paper_2107_12027_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.paper_case is not None:
+        return paper_case(args)
     if args.workload != "quadrant":
         return other_workload(args)
     w = wl.quadrant_riemann(n=args.n, seed=args.seed)

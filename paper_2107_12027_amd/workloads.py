@@ -284,6 +284,79 @@ def rmhd_fourier(n: int = 256, seed: int = 0, steps: int = 100, eps: float = 0.0
 
 
 # ---------------------------------------------------------------------------
+# The paper's fixed-state 2D examples, run as MM-O5 (adaptive) and UM-O5 (the
+# same scheme on the static uniform mesh) for the time-to-solution comparison.
+# ---------------------------------------------------------------------------
+
+# Section 6, RHD Riemann problems I-III: (rho, v1, v2, p) in the quadrants
+# x1 > 0.5 & x2 > 0.5, x1 < 0.5 & x2 > 0.5, x1 < 0.5 & x2 < 0.5, x1 > 0.5 & x2 < 0.5
+RIEMANN_2D = {
+    1: ((0.5, 0.5, -0.5, 5.0), (1.0, 0.5, 0.5, 5.0), (3.0, -0.5, 0.5, 5.0), (1.5, -0.5, -0.5, 5.0)),
+    2: ((1.0, 0.0, 0.0, 1.0), (0.5771, -0.3529, 0.0, 0.4), (1.0, -0.3529, -0.3529, 1.0),
+        (0.5771, 0.0, -0.3529, 0.4)),
+    3: ((0.035145216124503, 0.0, 0.0, 0.162931056509027), (0.1, 0.7, 0.0, 1.0), (0.5, 0.0, 0.0, 1.0),
+        (0.1, 0.0, 0.7, 1.0)),
+}
+
+
+def riemann2d(case: int, n: int = 200, adaptive: bool = True) -> Workload:
+    """2D RHD Riemann problem I, II or III of Section 6 on [0,1]^2 with outflow
+    boundaries, Gamma = 5/3, CFL 0.4, run to t = 0.4.  Adaptive mesh (MM-O5): the
+    paper monitor with alpha = 1200 on sigma = ln rho, 3 filter passes, 10 Jacobi
+    sweeps; adaptive = False gives UM-O5."""
+    g = make_grid(2, (n, n, 1), (OUTFLOW, OUTFLOW, PERIODIC))
+    x = uniform_mesh(g)
+    east = x[0] > 0.5
+    north = x[1] > 0.5
+    quads = [east & north, (~east) & north, (~east) & (~north), east & (~north)]
+    rho = np.zeros(g.shape)
+    p = np.zeros(g.shape)
+    v = np.zeros((3,) + g.shape)
+    for q, (r, vx, vy, pr) in zip(quads, RIEMANN_2D[case]):
+        rho[q] = r
+        v[0][q] = vx
+        v[1][q] = vy
+        p[q] = pr
+    B = np.zeros((3,) + g.shape)
+    mon = (Monitor(enabled=1, sigma=SIGMA_LNRHO, form=MON_PAPER, alpha=1200.0, filter_passes=3, sweeps=10)
+           if adaptive else Monitor(enabled=0))
+    return Workload("rhd2d_riemann%d_%s_%d" % (case, "mm" if adaptive else "um", n), g,
+                    Scheme(phys=RHD, gamma=5.0 / 3.0, cfl=0.4), mon, _prim(rho, v, p, B), x,
+                    steps=0, t_end=0.4)
+
+
+def rmhd_blast2d(n: int = 150, adaptive: bool = True) -> Workload:
+    """2D RMHD blast of Section 6 on [-6,6]^2 with outflow boundaries, Gamma = 4/3,
+    CFL 0.4, run to t = 4: rho = 0.01, p = 1 for r < 0.8; rho = 1e-4, p = 5e-4 for
+    r > 1; linear in r in between; v = 0; B = (0.1, 0, 0).  Adaptive mesh (MM-O5):
+    the paper monitor with alpha = 800 on sigma = ln rho, 3 filter passes, 10
+    Jacobi sweeps; adaptive = False gives UM-O5."""
+    g = make_grid(2, (n, n, 1), (OUTFLOW, OUTFLOW, PERIODIC), lo=(-6.0, -6.0, 0.0), length=(12.0, 12.0, 1.0))
+    x = uniform_mesh(g)
+    r = np.sqrt(x[0] * x[0] + x[1] * x[1])
+    f = np.clip((1.0 - r) / 0.2, 0.0, 1.0)       # 1 inside r = 0.8, 0 outside r = 1
+    rho = 1e-4 + (0.01 - 1e-4) * f
+    p = 5e-4 + (1.0 - 5e-4) * f
+    v = np.zeros((3,) + g.shape)
+    B = np.zeros((3,) + g.shape)
+    B[0] = 0.1
+    mon = (Monitor(enabled=1, sigma=SIGMA_LNRHO, form=MON_PAPER, alpha=800.0, filter_passes=3, sweeps=10)
+           if adaptive else Monitor(enabled=0))
+    return Workload("rmhd2d_blast_%s_%d" % ("mm" if adaptive else "um", n), g,
+                    Scheme(phys=RMHD, gamma=4.0 / 3.0, cfl=0.4), mon, _prim(rho, v, p, B), x,
+                    steps=0, t_end=4.0)
+
+
+# (MM-O5 size, UM-O5 size, the paper's MM-O5 / UM-O5 CPU-time ratio)
+PAPER_COMPARISONS = {
+    "rp1": (lambda n, a: riemann2d(1, n, a), 200, 500, 0.178),
+    "rp2": (lambda n, a: riemann2d(2, n, a), 200, 500, 0.306),
+    "rp3": (lambda n, a: riemann2d(3, n, a), 200, 600, 0.137),
+    "rmhd_blast": (lambda n, a: rmhd_blast2d(n, a), 150, 600, 0.0726),
+}
+
+
+# ---------------------------------------------------------------------------
 # Random test inputs (parity and invariant tests).
 # ---------------------------------------------------------------------------
 

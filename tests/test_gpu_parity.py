@@ -198,6 +198,16 @@ def test_rk3_step_blast3d_adaptive():
     assert np.max(np.abs(x - xo)) <= 1e-13
 
 
+@pytest.mark.parametrize("case", [1, 2, 3])
+def test_rk3_step_paper_riemann_problems(case):
+    # the initial data of the paper's RHD Riemann problems I-III (MM-O5 setup)
+    w = wl.riemann2d(case, n=48)
+    (U, J, x, xd), (Uo, Jo, xo, xdo) = _run_steps(w, 1)
+    assert np.all(rel_inf(U, Uo) <= TOL), rel_inf(U, Uo)
+    assert rel_inf(J[None], Jo[None])[0] <= TOL
+    assert np.max(np.abs(x - xo)) <= 1e-13
+
+
 def test_quadrant_seed18_inadmissible_on_both_paths():
     # the ES scheme has no positivity limiter: the seed-18 states leave the admissible
     # set in the first step; both paths must report it rather than continue silently

@@ -154,3 +154,29 @@ def test_rmhd_rk3_step_rotor_degenerate_states():
     for c in range(ctx.m):
         sc = max(np.max(np.abs(out["U"][c])), 1e-3 * big)
         assert np.max(np.abs(Ug[c] - out["U"][c])) <= 2e-9 * sc, (c, np.max(np.abs(Ug[c] - out["U"][c])) / sc)
+
+
+def test_rmhd_blast_inadmissible_on_both_paths():
+    # the paper's 2D RMHD blast (rho 0.01 / 1e-4, p 1 / 5e-4, B = (0.1, 0, 0), taper
+    # over 0.8 < r < 1) on a 100^2 uniform mesh: the first Euler stage leaves the
+    # admissible set just outside the taper (E - |B|^2/2 < sqrt(D^2 + |m|^2) with
+    # v parallel to B) on the oracle, and the GPU path must report it as well
+    w = wl.rmhd_blast2d(n=100, adaptive=False)
+    g = w.grid
+    ctx = es.Context(g, w.scheme, w.monitor)
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    met = empty(ctx.nmet, *ctx.padded_shape())
+    J = empty(*ctx.shape())
+    x = dev(w.x)
+    ctx.metrics(x, None, met, J)
+    U = empty(ctx.m, *ctx.shape())
+    ctx.prim2con(dev(P), J, U)
+    xd = empty(g.dim, *ctx.shape())
+    dt = empty(1)
+    ctx.rk3_step(U, J, x, xd, dt)
+    status, nfail, first = ctx.status()
+    # (an inadmissible state, or one for which the pressure iteration finds no root)
+    assert status in (es.ES_EADMISSIBLE, es.ES_ENOCONV) and nfail > 0 and first >= 0
+    Uo, Jo = st.initial_state(g, w.scheme, P, w.x)
+    out = st.rk3_step(g, w.scheme, w.monitor, Uo, Jo, w.x)
+    assert not out["ok"].all() and out["failed_stage"] == 1
