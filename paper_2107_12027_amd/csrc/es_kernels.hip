@@ -212,16 +212,19 @@ __global__ void __launch_bounds__(256) k_metrics2d_fused(GridDev g, const double
 // = x (with the periodic shift) and its velocity V are staged once per tile, the
 // stage meshes are X + c_s dt V (c = 0, 1, 1/2), and the differences and the
 // temporal metrics (velocity V at the node) are those of k_metrics2d_fused.
-__global__ void __launch_bounds__(256) k_metrics2d_stages(GridDev g, const double* __restrict__ x,
-                                                          const double* __restrict__ xd,
-                                                          const double* __restrict__ dt_dev,
-                                                          double* __restrict__ met0, double* __restrict__ met1,
-                                                          double* __restrict__ met2) {
+constexpr int MSY = 3 * MTY;   // threads per column: one per (stage, tile row)
+
+__global__ void __launch_bounds__(MTX * MSY) k_metrics2d_stages(GridDev g, const double* __restrict__ x,
+                                                               const double* __restrict__ xd,
+                                                               const double* __restrict__ dt_dev,
+                                                               double* __restrict__ met0,
+                                                               double* __restrict__ met1,
+                                                               double* __restrict__ met2) {
     __shared__ double xs[2][MRY][MRX];
     __shared__ double vs[2][MRY][MRX];
     const int tid = threadIdx.y * MTX + threadIdx.x;
     const int i0 = -NG + (int)blockIdx.x * MTX, j0 = -NG + (int)blockIdx.y * MTY;
-    for (int q = tid; q < MRX * MRY; q += MTX * MBY) {
+    for (int q = tid; q < MRX * MRY; q += MTX * MSY) {
         const int ri = q % MRX, rj = q / MRX;
         const int i = i0 - NG + ri, j = j0 - NG + rj;
         const bool ok = i >= -2 * NG && i < g.n[0] + 2 * NG && j >= -2 * NG && j < g.n[1] + 2 * NG;
@@ -234,46 +237,37 @@ __global__ void __launch_bounds__(256) k_metrics2d_stages(GridDev g, const doubl
     __syncthreads();
     const long long P = g.pnodes;
     const int i = i0 + (int)threadIdx.x;
-    if (i >= g.n[0] + NG) return;
-    const int ri = threadIdx.x + NG;
-    const double dt = dt_dev[0];
-    for (int row = threadIdx.y; row < MTY; row += MBY) {
-        const int j = j0 + row;
-        if (j >= g.n[1] + NG) break;
-        const int rj = row + NG;
-        const long long t = pidx(g, i, j, 0);
-        const double vx = vs[0][rj][ri], vy = vs[1][rj][ri];
+    const int row = (int)threadIdx.y % MTY, st = (int)threadIdx.y / MTY;
+    const int j = j0 + row;
+    if (i >= g.n[0] + NG || j >= g.n[1] + NG) return;
+    const int ri = threadIdx.x + NG, rj = row + NG;
+    const double cdt = (st == 0 ? 0.0 : (st == 1 ? 1.0 : 0.5)) * dt_dev[0];
+    const long long t = pidx(g, i, j, 0);
+    const double vx = vs[0][rj][ri], vy = vs[1][rj][ri];
+    double dxi[2], deta[2];
 #pragma unroll
-        for (int st = 0; st < 3; ++st) {
-            const double cdt = (st == 0 ? 0.0 : (st == 1 ? 1.0 : 0.5)) * dt;
-            double dxi[2], deta[2];
+    for (int c = 0; c < 2; ++c) {
+        double s = 0.0, r = 0.0;
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                double s = 0.0, r = 0.0;
-#pragma unroll
-                for (int n = 1; n <= 3; ++n) {
-                    const double a = 0.5 * alpha3(n);
-                    s += a * ((xs[c][rj][ri + n] + cdt * vs[c][rj][ri + n]) -
-                              (xs[c][rj][ri - n] + cdt * vs[c][rj][ri - n]));
-                    r += a * ((xs[c][rj + n][ri] + cdt * vs[c][rj + n][ri]) -
-                              (xs[c][rj - n][ri] + cdt * vs[c][rj - n][ri]));
-                }
-                dxi[c] = s;
-                deta[c] = r;
-            }
-            const double xix = deta[1] / g.dxi[1];
-            const double xiy = -deta[0] / g.dxi[1];
-            const double etx = -dxi[1] / g.dxi[0];
-            const double ety = dxi[0] / g.dxi[0];
-            double* met = st == 0 ? met0 : (st == 1 ? met1 : met2);
-            met[0 * P + t] = -(vx * xix + vy * xiy);
-            met[3 * P + t] = -(vx * etx + vy * ety);
-            met[1 * P + t] = xix;
-            met[2 * P + t] = xiy;
-            met[4 * P + t] = etx;
-            met[5 * P + t] = ety;
+        for (int n = 1; n <= 3; ++n) {
+            const double a = 0.5 * alpha3(n);
+            s += a * ((xs[c][rj][ri + n] + cdt * vs[c][rj][ri + n]) - (xs[c][rj][ri - n] + cdt * vs[c][rj][ri - n]));
+            r += a * ((xs[c][rj + n][ri] + cdt * vs[c][rj + n][ri]) - (xs[c][rj - n][ri] + cdt * vs[c][rj - n][ri]));
         }
+        dxi[c] = s;
+        deta[c] = r;
     }
+    const double xix = deta[1] / g.dxi[1];
+    const double xiy = -deta[0] / g.dxi[1];
+    const double etx = -dxi[1] / g.dxi[0];
+    const double ety = dxi[0] / g.dxi[0];
+    double* met = st == 0 ? met0 : (st == 1 ? met1 : met2);
+    met[0 * P + t] = -(vx * xix + vy * xiy);
+    met[1 * P + t] = xix;
+    met[2 * P + t] = xiy;
+    met[3 * P + t] = -(vx * etx + vy * ety);
+    met[4 * P + t] = etx;
+    met[5 * P + t] = ety;
 }
 
 // 3D conservative metric method (eq. SCLCoeff): with the products
@@ -724,29 +718,36 @@ struct MonitorArgs {
     double* partial;   // block maxima of |grad sigma|
 };
 
-__global__ void __launch_bounds__(256) k_cfl_partial2d_mesh(GridDev g, double G, const double* __restrict__ prim,
-                                                            const double* __restrict__ x,
-                                                            const double* __restrict__ J,
-                                                            double* __restrict__ partial, MonitorArgs mon) {
+// 64 x 8 threads per 64 x 4 tile: all stage the mesh (about two positions each);
+// rows 0-3 then evaluate the CFL speeds, rows 4-7 the monitor.
+constexpr int CBY = 8;
+
+__global__ void __launch_bounds__(MTX * CBY) k_cfl_partial2d_mesh(GridDev g, double G,
+                                                                 const double* __restrict__ prim,
+                                                                 const double* __restrict__ x,
+                                                                 const double* __restrict__ J,
+                                                                 double* __restrict__ partial, MonitorArgs mon) {
     __shared__ double xs[2][MRY][MRX];
-    __shared__ double sh[8];
+    __shared__ double sh[MTX * CBY / 64];
     const int tid = threadIdx.y * MTX + threadIdx.x;
     const int i0 = (int)blockIdx.x * MTX, j0 = (int)blockIdx.y * MBY;
-    const int i = i0 + (int)threadIdx.x, j = j0 + (int)threadIdx.y;
+    const int role = (int)threadIdx.y / MBY;       // 0: CFL, 1: monitor, 2: staging only
+    const int i = i0 + (int)threadIdx.x, j = j0 + (int)threadIdx.y % MBY;
     const bool inside = i < g.n[0] && j < g.n[1];
     // the monitor needs no metrics: its loads overlap the mesh staging
     double gmx = 0.0;
-    if (mon.enabled && inside) gmx = monitor_node<2>(g, mon.M, mon.sigma_ln, mon.sqgrad, mon.alpha, prim, mon.w, i, j, 0);
-    for (int q = tid; q < MRX * (MBY + 2 * NG); q += MTX * MBY) {
+    if (role == 1 && mon.enabled && inside)
+        gmx = monitor_node<2>(g, mon.M, mon.sigma_ln, mon.sqgrad, mon.alpha, prim, mon.w, i, j, 0);
+    for (int q = tid; q < MRX * (MBY + 2 * NG); q += MTX * CBY) {
         const int ri = q % MRX, rj = q / MRX;
-        const int i = i0 - NG + ri, j = j0 - NG + rj;
-        const bool ok = i < g.n[0] + 2 * NG && j < g.n[1] + 2 * NG;
-        xs[0][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, 0, i, j, 0, true) : 0.0;
-        xs[1][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, 1, i, j, 0, true) : 0.0;
+        const int ii = i0 - NG + ri, jj = j0 - NG + rj;
+        const bool ok = ii < g.n[0] + 2 * NG && jj < g.n[1] + 2 * NG;
+        xs[0][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, 0, ii, jj, 0, true) : 0.0;
+        xs[1][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, 1, ii, jj, 0, true) : 0.0;
     }
     __syncthreads();
     double mx[2] = {0.0, 0.0};
-    if (inside) {
+    if (role == 0 && inside) {
         const int ri = threadIdx.x + NG, rj = threadIdx.y + NG;
         double dxi[2], deta[2];
 #pragma unroll
@@ -876,25 +877,26 @@ __global__ void k_filter(GridDev g, const double* __restrict__ win, double* __re
 // are filtered as the originals.
 constexpr int FTX = 64, FTY = 4, FH = 5;
 constexpr int FRX = FTX + 2 * FH, FRY = FTY + 2 * FH;
+constexpr int FBY = 8;    // 64 x 8 threads: about two region positions per thread
 
 // With apply, every block reduces the nb partial maxima of |grad sigma| itself
 // (no separate reduction launch); with dt_fin, block 0 also finalises dt.
-__global__ void __launch_bounds__(256) k_monitor_filter2d(GridDev g, int apply, double alpha,
+__global__ void __launch_bounds__(FTX * FBY) k_monitor_filter2d(GridDev g, int apply, double alpha,
                                                           const double* __restrict__ gpart, int nb,
                                                           int passes, const double* __restrict__ win,
                                                           double* __restrict__ wout, DtFinal dt_fin) {
     __shared__ double ws[2][FRY][FRX];
-    __shared__ double sh[8];
+    __shared__ double sh[FTX * FBY / 64];
     const int tid = threadIdx.y * FTX + threadIdx.x;
     const int i0 = (int)blockIdx.x * FTX - FH, j0 = (int)blockIdx.y * FTY - FH;
     const int n0 = g.n[0], n1 = g.n[1];
     if (dt_fin.dt_out != nullptr && blockIdx.x == 0 && blockIdx.y == 0) finalize_dt(dt_fin, sh);
     double m = 0.0;
     if (apply) {
-        for (int b = tid; b < nb; b += FTX * FTY) m = fmax(m, gpart[b]);
+        for (int b = tid; b < nb; b += FTX * FBY) m = fmax(m, gpart[b]);
         m = block_reduce<0>(m, sh);
     }
-    for (int q = tid; q < FRX * FRY; q += FTX * FTY) {
+    for (int q = tid; q < FRX * FRY; q += FTX * FBY) {
         const int ri = q % FRX, rj = q / FRX;
         const int ii = map_sol(i0 + ri, n0, g.bc[0]), jj = map_sol(j0 + rj, n1, g.bc[1]);
         double v = win[(long long)jj * n0 + ii];
@@ -916,7 +918,7 @@ __global__ void __launch_bounds__(256) k_monitor_filter2d(GridDev g, int apply, 
     };
     int cur = 0;
     for (int ps = 1; ps <= passes; ++ps) {
-        for (int q = tid; q < FRX * FRY; q += FTX * FTY) {
+        for (int q = tid; q < FRX * FRY; q += FTX * FBY) {
             const int ri = q % FRX, rj = q / FRX;
             double v = ws[cur][rj][ri];
             if (ri >= ps && ri < FRX - ps && rj >= ps && rj < FRY - ps) {
@@ -936,7 +938,8 @@ __global__ void __launch_bounds__(256) k_monitor_filter2d(GridDev g, int apply, 
         __syncthreads();
     }
     const int gi = (int)blockIdx.x * FTX + threadIdx.x, gj = (int)blockIdx.y * FTY + threadIdx.y;
-    if (gi < n0 && gj < n1) wout[(long long)gj * n0 + gi] = ws[cur][threadIdx.y + FH][threadIdx.x + FH];
+    if (threadIdx.y < FTY && gi < n0 && gj < n1)
+        wout[(long long)gj * n0 + gi] = ws[cur][threadIdx.y + FH][threadIdx.x + FH];
 }
 
 // Value of mesh component q at the neighbour c + s e_a of interior node c: a
@@ -1018,22 +1021,23 @@ __device__ __forceinline__ double dtau_bound(const GridDev& g, const double* __r
 // outflow edge are never read by the nodes a sweep updates.
 constexpr int JTX = 64, JTY = 8, JS = 5;
 constexpr int JRX = JTX + 2 * JS, JRY = JTY + 2 * JS;
+constexpr int JNT = 1024;   // threads per block: about one region position per thread
 
 // With dtau_part (last launch), each block also writes the minimum of the
 // Delta tau bound over its tile (x0: the mesh before the sweeps).
-__global__ void __launch_bounds__(256) k_jacobi_multi2d(GridDev g, int sweeps, const double* __restrict__ w,
+__global__ void __launch_bounds__(JNT) k_jacobi_multi2d(GridDev g, int sweeps, const double* __restrict__ w,
                                                         const double* __restrict__ xin,
                                                         double* __restrict__ xout,
                                                         const double* __restrict__ x0,
                                                         double* __restrict__ dtau_part) {
     __shared__ double xs[2][2][JRY][JRX];
     __shared__ double ws[JRY][JRX];
-    __shared__ double sh[8];
+    __shared__ double sh[JNT / 64];
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x * JTX - JS, j0 = blockIdx.y * JTY - JS;
     const int n0 = g.n[0], n1 = g.n[1];
     const bool per0 = g.bc[0] == ES_BC_PERIODIC, per1 = g.bc[1] == ES_BC_PERIODIC;
-    for (int q = tid; q < JRX * JRY; q += 256) {
+    for (int q = tid; q < JRX * JRY; q += JNT) {
         const int ri = q % JRX, rj = q / JRX;
         int gi = i0 + ri, gj = j0 + rj;
         double sh0 = 0.0, sh1 = 0.0;
@@ -1064,12 +1068,12 @@ __global__ void __launch_bounds__(256) k_jacobi_multi2d(GridDev g, int sweeps, c
     // w_k) / den over the free axes; flags: bit 0 / 1 = component 0 / 1 is
     // updated (its axis is free and den > 0), bits 2.. = depth in the region
     // (the position is valid for sweeps up to its depth)
-    constexpr int NQ = (JRX * JRY + 255) / 256;
+    constexpr int NQ = (JRX * JRY + JNT - 1) / JNT;
     double cf[NQ][4];
     int fl[NQ];
 #pragma unroll
     for (int r = 0; r < NQ; ++r) {
-        const int q = tid + 256 * r;
+        const int q = tid + JNT * r;
         cf[r][0] = cf[r][1] = cf[r][2] = cf[r][3] = 0.0;
         fl[r] = 0;
         if (q < JRX * JRY) {
@@ -1110,7 +1114,7 @@ __global__ void __launch_bounds__(256) k_jacobi_multi2d(GridDev g, int sweeps, c
     for (int sw = 1; sw <= sweeps; ++sw) {
 #pragma unroll
         for (int r = 0; r < NQ; ++r) {
-            const int q = tid + 256 * r;
+            const int q = tid + JNT * r;
             if (q < JRX * JRY) {
                 const int ri = q % JRX, rj = q / JRX;
                 double v0 = xs[cur][0][rj][ri], v1 = xs[cur][1][rj][ri];
@@ -1130,7 +1134,7 @@ __global__ void __launch_bounds__(256) k_jacobi_multi2d(GridDev g, int sweeps, c
         __syncthreads();
     }
     double best = 1.0;
-    for (int q = tid; q < JTX * JTY; q += 256) {
+    for (int q = tid; q < JTX * JTY; q += JNT) {
         const int oi = q % JTX, oj = q / JTX;
         const int gi = blockIdx.x * JTX + oi, gj = blockIdx.y * JTY + oj;
         if (gi < n0 && gj < n1) {
@@ -1382,7 +1386,7 @@ hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double*
                                  hipStream_t s) {
     const GridDev& g = c->g;
     const dim3 gm((unsigned)((g.P[0] + MTX - 1) / MTX), (unsigned)((g.P[1] + MTY - 1) / MTY), 1);
-    k_metrics2d_stages<<<gm, dim3(MTX, MBY, 1), 0, s>>>(g, x, xdot, dt_dev, met0, met1, met2);
+    k_metrics2d_stages<<<gm, dim3(MTX, MSY, 1), 0, s>>>(g, x, xdot, dt_dev, met0, met1, met2);
     return hipGetLastError();
 }
 
@@ -1488,7 +1492,8 @@ hipError_t launch_cfl_mesh(const es_ctx* c, const double* prim, const double* x,
         mon.w = c->wa;
         mon.partial = red_monitor(c);
     }
-    k_cfl_partial2d_mesh<<<interior_grid(g), box_block(), 0, s>>>(g, c->scheme.gamma, prim, x, J, red_cfl(c), mon);
+    k_cfl_partial2d_mesh<<<interior_grid(g), dim3(MTX, CBY, 1), 0, s>>>(g, c->scheme.gamma, prim, x, J, red_cfl(c),
+                                                                         mon);
     if (!defer_final) k_cfl_final<<<1, 256, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
     if (monitor_done != nullptr) *monitor_done = with_monitor;
     return hipGetLastError();
@@ -1546,7 +1551,7 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
         int apply = !sq, left = mo.filter_passes;
         do {
             const int k = min(FH, left);
-            k_monitor_filter2d<<<box_grid(g.n[0], g.n[1], 1), box_block(), 0, s>>>(
+            k_monitor_filter2d<<<box_grid(g.n[0], g.n[1], 1), dim3(FTX, FBY, 1), 0, s>>>(
                 g, apply, mo.alpha, gpart, nb, k, w, w2, dt_fin);
             double* tmp = w; w = w2; w2 = tmp;
             apply = 0;
@@ -1575,7 +1580,7 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
         for (int done = 0; done < mo.sweeps; done += JS) {
             const int k = min(JS, mo.sweeps - done);
             const bool last = done + k >= mo.sweeps;
-            k_jacobi_multi2d<<<gj, 256, 0, s>>>(g, k, w, xin, xo, x, last ? red_dtau(c) : nullptr);
+            k_jacobi_multi2d<<<gj, JNT, 0, s>>>(g, k, w, xin, xo, x, last ? red_dtau(c) : nullptr);
             xin = xo;
             double* tmp = xo; xo = xalt; xalt = tmp;
         }
