@@ -39,9 +39,9 @@ PEAK_HBM = 8.0e12                # B/s
 # op-counting scalar (paper_2107_12027_amd/csrc/opcount.cpp, run by
 # `python -m paper_2107_12027_amd.build --opcount`): + - * / sqrt log exp fabs
 # fmax count 1, fma counts 2.  Per node and direction: 3 two-point fluxes
-# (102.3 each), 1 face dissipation (1490.7), state preparation (6) and the
-# flux-difference accumulation (66): 1869.7; two directions: 3739.5.
-RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3739.5
+# (102.3 each), 1 face dissipation (1494.7), state preparation (6) and the
+# flux-difference accumulation (66): 1873.7; two directions: 3747.5.
+RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3747.5
 
 # HBM bytes of one es_residual call on the 400 x 400 quadrant workload, from the
 # FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run) of
@@ -49,7 +49,7 @@ RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3739.5
 # 1 GiB device copy (FETCH x 2.000, WRITE x 1.000); the summary with its commands
 # is profiles/es_residual_hbm_counters_rhd2d_quadrant_400.txt.  Valid for the
 # kernels as they were measured; None for other workloads.
-RESIDUAL_TRAFFIC_BYTES_QUADRANT_400 = 57.74e6
+RESIDUAL_TRAFFIC_BYTES_QUADRANT_400 = 57.75e6
 
 
 def parse():
