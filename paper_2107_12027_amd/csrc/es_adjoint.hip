@@ -82,9 +82,42 @@ __device__ void pair_vjp_rhd(double G, const double* Pl, const double* Pr, const
 
 // Cotangents g[j] (j = 0..5, primitive slots) of the stencil states of one face
 // dissipation d (face_diss_rhd) for the cotangent z of d.
-template <int DIM>
-__device__ void face_vjp_rhd(double G, double eps, const NodeRHD<DIM>* nd, const double* al,
-                             const double* ar, const double* z, double g[6][DIM + 2]) {
+// Gradient of the WENO5-JS value weno5(a, b, c, d, e) with respect to its five
+// inputs, from the weights w_k = d_k / (eps + beta_k)^2 written out: with
+// S = sum_k w_k and v = sum_k w_k q_k / (6 S) (q_k the six-fold candidate values),
+// dv = [sum_k w_k dq_k + sum_k (q_k - 6 v) dw_k] / (6 S) and
+// dw_k = -2 w_k dbeta_k / (eps + beta_k).
+__device__ __forceinline__ void weno5_grad(double a, double b, double c, double d, double e, double eps,
+                                           double* gr) {
+    const double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
+    const double q1 = -b + 5.0 * c + 2.0 * d;
+    const double q2 = 2.0 * c + 5.0 * d - e;
+    const double t0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
+    const double t1 = b - 2.0 * c + d, s1 = b - d;
+    const double t2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
+    const double e0 = eps + (13.0 / 12.0) * t0 * t0 + 0.25 * s0 * s0;
+    const double e1 = eps + (13.0 / 12.0) * t1 * t1 + 0.25 * s1 * s1;
+    const double e2 = eps + (13.0 / 12.0) * t2 * t2 + 0.25 * s2 * s2;
+    const double ie0 = 1.0 / e0, ie1 = 1.0 / e1, ie2 = 1.0 / e2;
+    const double w0 = 0.1 * ie0 * ie0, w1 = 0.6 * ie1 * ie1, w2 = 0.3 * ie2 * ie2;
+    const double S = w0 + w1 + w2;
+    const double iS6 = 1.0 / (6.0 * S);
+    const double v6 = (w0 * q0 + w1 * q1 + w2 * q2) / S;      // 6 v
+    // c_k dbeta_k with c_k = -2 w_k (q_k - 6 v) / (eps + beta_k), split over t_k and s_k
+    const double c0 = -2.0 * w0 * (q0 - v6) * ie0, c1 = -2.0 * w1 * (q1 - v6) * ie1, c2 = -2.0 * w2 * (q2 - v6) * ie2;
+    const double u0 = c0 * (13.0 / 6.0) * t0, v0 = c0 * 0.5 * s0;
+    const double u1 = c1 * (13.0 / 6.0) * t1, v1 = c1 * 0.5 * s1;
+    const double u2 = c2 * (13.0 / 6.0) * t2, v2 = c2 * 0.5 * s2;
+    gr[0] = (2.0 * w0 + u0 + v0) * iS6;
+    gr[1] = (-7.0 * w0 - w1 - 2.0 * u0 - 4.0 * v0 + u1 + v1) * iS6;
+    gr[2] = (11.0 * w0 + 5.0 * w1 + 2.0 * w2 + u0 + 3.0 * v0 - 2.0 * u1 + u2 + 3.0 * v2) * iS6;
+    gr[3] = (2.0 * w1 + 5.0 * w2 + u1 - v1 - 2.0 * u2 - 4.0 * v2) * iS6;
+    gr[4] = (-w2 + u2 + v2) * iS6;
+}
+
+template <int DIM, typename NodeFn, typename Sync, typename Out>
+__device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, const double* al,
+                             const double* ar, const double* z, Out&& out) {
     constexpr int M = DIM + 2;
     const double at = 0.5 * (al[0] + ar[0]);
     double ax[3] = {0.0, 0.0, 0.0};
@@ -97,17 +130,18 @@ __device__ void face_vjp_rhd(double G, double eps, const NodeRHD<DIM>* nd, const
     rotation<DIM>(nrm, T);
     const double c0 = G / (G - 1.0), c1 = 1.0 / (G - 1.0);
 
-    double TV[6][M], Tu[6][DIM];
+    // (the stencil states are read through node(j) here and again at the end, so
+    // that they need not stay in registers in between)
+    double TV[6][M];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        const NodeRHD<DIM>& q = nd[j];
+        const NodeRHD<DIM> q = node(j);
         TV[j][0] = c0 + q.lr + q.lb * c1 + q.beta;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             double s = 0.0;
 #pragma unroll
             for (int b = 0; b < DIM; ++b) s += T[a][b] * q.u[b];
-            Tu[j][a] = s;
             TV[j][1 + a] = q.beta * s;
         }
         TV[j][M - 1] = -q.beta * q.W;
@@ -145,34 +179,43 @@ __device__ void face_vjp_rhd(double G, double eps, const NodeRHD<DIM>* nd, const
 #pragma unroll
         for (int j = 0; j < 6; ++j) gTV[j][c] = 0.0;
     }
-    using D6 = Dual<6>;
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < M; ++q) {
         const double* r = Rm[q];
-        D6 vt[6];
+        double vt[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
             double s = 0.0;
 #pragma unroll
             for (int c = 0; c < M; ++c) s += r[c] * TV[j][c];
-            vt[j] = D6::seed(s, j);
+            vt[j] = s;
         }
-        const D6 jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], D6(eps)) -
-                      weno5(vt[0], vt[1], vt[2], vt[3], vt[4], D6(eps));
-        const double jp = vt[3].v - vt[2].v;
+        // the jump and its switch exactly as in the forward dissipation
+        const double jwv = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps) - weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
+        const double jp = vt[3] - vt[2];
         double r1 = 0.0;
 #pragma unroll
         for (int c = 0; c < M; ++c) r1 += fabs(r[c]);
-        if (jw.v * jp > 0.0 && fabs(jp) > RealTraits<double>::ytol * r1 * tvmax) {
+        if (jwv * jp > 0.0 && fabs(jp) > RealTraits<double>::ytol * r1 * tvmax) {
+            // d(jw)/d(vt_j): the upwind-from-the-right value minus the one from the left
+            double gp[5], gm[5], djw[6];
+            weno5_grad(vt[5], vt[4], vt[3], vt[2], vt[1], eps, gp);
+            weno5_grad(vt[0], vt[1], vt[2], vt[3], vt[4], eps, gm);
+            djw[0] = -gm[0];
+            djw[1] = gp[4] - gm[1];
+            djw[2] = gp[3] - gm[2];
+            djw[3] = gp[2] - gm[3];
+            djw[4] = gp[1] - gm[4];
+            djw[5] = gp[0];
             double rz = 0.0;
 #pragma unroll
-            for (int c = 0; c < M; ++c) { dd[c] += jw.v * r[c]; rz += r[c] * zr[c]; }
+            for (int c = 0; c < M; ++c) { dd[c] += jwv * r[c]; rz += r[c] * zr[c]; }
             const double gjw = lhat * rz;
 #pragma unroll
-            for (int c = 0; c < M; ++c) gR[q][c] += lhat * jw.v * zr[c];
+            for (int c = 0; c < M; ++c) gR[q][c] += lhat * jwv * zr[c];
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
-                const double gv = gjw * jw.d[j];
+                const double gv = gjw * djw[j];
 #pragma unroll
                 for (int c = 0; c < M; ++c) {
                     gTV[j][c] += gv * r[c];
@@ -185,7 +228,39 @@ __device__ void face_vjp_rhd(double G, double eps, const NodeRHD<DIM>* nd, const
 #pragma unroll
     for (int c = 0; c < M; ++c) glhat += zr[c] * dd[c];
 
-    // face eigen-structure: tangents along each face entropy variable
+    // rotated entropy variables -> primitive (rho, u, p) of stencil node j, handed
+    // to out(j, c, value)
+    auto to_prim = [&](int j) {
+        const NodeRHD<DIM> q = node(j);
+        const double ip = 1.0 / q.p, irho = 1.0 / q.rho;
+        double su = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            double tu = 0.0;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) tu += T[a][b] * q.u[b];
+            su += gTV[j][1 + a] * tu;
+        }
+        const double sbu = q.beta * su;
+        out(j, 0, gTV[j][0] * ((1.0 + c1) * irho + ip) + su * ip - gTV[j][M - 1] * q.W * ip);
+        out(j, M - 1, -gTV[j][0] * (c1 + q.beta) * ip - sbu * ip + gTV[j][M - 1] * q.beta * q.W * ip);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) s += T[a][b] * gTV[j][1 + a];
+            out(j, 1 + b, q.beta * s - gTV[j][M - 1] * q.beta * q.u[b] / q.W);
+        }
+    };
+    // the outer stencil nodes are complete before the eigen-structure tangents
+    sync();
+    to_prim(0);
+    to_prim(1);
+    to_prim(4);
+    to_prim(5);
+
+    // face eigen-structure: tangents along each face entropy variable (they
+    // reach nodes i and i+1 through the face mean of the entropy variables)
     using D1 = Dual<1>;
     double Vb[M];
 #pragma unroll
@@ -204,26 +279,9 @@ __device__ void face_vjp_rhd(double G, double eps, const NodeRHD<DIM>* nd, const
         gTV[2][k] += 0.5 * dir;
         gTV[3][k] += 0.5 * dir;
     }
-
-    // rotated entropy variables -> primitive (rho, u, p) of each stencil node
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const NodeRHD<DIM>& q = nd[j];
-        const double ip = 1.0 / q.p, irho = 1.0 / q.rho;
-        double su = 0.0, sbu = 0.0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) { su += gTV[j][1 + a] * Tu[j][a]; }
-        sbu = q.beta * su;
-        g[j][0] = gTV[j][0] * ((1.0 + c1) * irho + ip) + su * ip - gTV[j][M - 1] * q.W * ip;
-        g[j][M - 1] = -gTV[j][0] * (c1 + q.beta) * ip - sbu * ip + gTV[j][M - 1] * q.beta * q.W * ip;
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) s += T[a][b] * gTV[j][1 + a];
-            g[j][1 + b] = q.beta * s - gTV[j][M - 1] * q.beta * q.u[b] / q.W;
-        }
-    }
+    sync();
+    to_prim(2);
+    to_prim(3);
 }
 
 // ---------------------------------------------------------------------------
@@ -391,34 +449,31 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
 
     if (ES) {
         __syncthreads();
-        // ---- faces f = s0 - 3 + lane (stencil slots lane .. lane + 5)
-        double gf[6][M];
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-#pragma unroll
-            for (int c = 0; c < M; ++c) gf[j][c] = 0.0;
+        // ---- faces f = s0 - 3 + lane (stencil slots lane .. lane + 5); the
+        // cotangents of the six stencil states go to buf[j][.][lane]
+        bool any = false;
+        double z[M];
         if (active && lane < ASEG + 5) {
-            double z[M];
-            bool any = false;
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 z[c] = 0.5 * idxi * (sl[line][c][lane + 2] - sl[line][c][lane + 3]);
                 any |= z[c] != 0.0;
             }
-            if (any) {
-                NodeRHD<NU> st[6];
-#pragma unroll
-                for (int j = 0; j < 6; ++j) st[j] = node_at(lane + j);
-                double al[NA], ar[NA];
-#pragma unroll
-                for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane + 2]; ar[c] = sd[line][F_A + c][lane + 3]; }
-                face_vjp_rhd<DIM>(G, eps, st, al, ar, z, gf);
-            }
         }
+        if (any) {
+            double al[NA], ar[NA];
 #pragma unroll
-        for (int j = 0; j < 6; ++j)
+            for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane + 2]; ar[c] = sd[line][F_A + c][lane + 3]; }
+            // the fence makes the later stages reread the stencil from LDS
+            face_vjp_rhd<DIM>(G, eps, [&](int j) { return node_at(lane + j); },
+                              [] { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); }, al, ar, z,
+                              [&](int j, int c, double v) { buf[line][j][c][lane] = v; });
+        } else {
 #pragma unroll
-            for (int c = 0; c < M; ++c) buf[line][j][c][lane] = gf[j][c];
+            for (int j = 0; j < 6; ++j)
+#pragma unroll
+                for (int c = 0; c < M; ++c) buf[line][j][c][lane] = 0.0;
+        }
         __syncthreads();
         if (o < ASEG) {
 #pragma unroll
