@@ -211,7 +211,9 @@ RESIDUAL_FLOPS_PER_NODE_3D_RHD = 8313.0   # same count, 3 directions (2771.0 eac
 
 
 def other_workload(args):
-    """Time one of the other workloads: FP64 RK3 steps and es_residual."""
+    """Time one of the other workloads: RK3 steps and es_residual, FP64 and
+    FP32-mixed."""
+    import numpy as np
     from paper_2107_12027_amd import workloads as wl
     make = {"sine": lambda: wl.advected_sine(n=64),
             "rotor": lambda: wl.rmhd_rotor(n=512),
@@ -221,6 +223,19 @@ def other_workload(args):
     run = Run(w, 0)
     t_ms = run.timed(args.steps, args.warmup)
     res_ms = run.residual_ms(args.residual_reps)
+    # the FP32-mixed form over the same steps from the same initial data, and the
+    # relative L1 difference of the final states (per conserved component)
+    mrun = Run(w, 1)
+    t_mixed_ms = mrun.timed(args.steps, args.warmup)
+    res_mixed_ms = mrun.residual_ms(args.residual_reps)
+    a, b = mrun.U.cpu().numpy(), run.U.cpu().numpy()
+    a, b = a.reshape(a.shape[0], -1), b.reshape(b.shape[0], -1)
+    den = np.maximum(np.abs(b).sum(axis=1), 1e-300)
+    mixed = {"ms_per_step": t_mixed_ms / args.steps, "es_residual_ms": res_mixed_ms,
+             "speedup_vs_fp64": t_ms / t_mixed_ms,
+             "l1_rel_diff_vs_fp64": (np.abs(a - b).sum(axis=1) / den).tolist(),
+             "diff_sample": "final states after the %d warm-up and %d timed steps of both forms"
+                            % (args.warmup, args.steps)}
     nodes = w.grid.nnodes
     flops = None
     if w.scheme.phys == 0:
@@ -238,7 +253,7 @@ def other_workload(args):
             "config": {"workload": w.name, "system": ("RMHD" if w.scheme.phys else "RHD") + " %dD" % w.grid.dim,
                        "grid": list(w.grid.shape[::-1]), "nodes": nodes,
                        "mesh": "adaptive" if w.monitor.enabled else "static", "precision": "FP64"},
-            "roofline": roof, "cpu_baseline": None}
+            "roofline": roof, "cpu_baseline": None, "mixed": mixed}
     print(json.dumps(line))
 
 

@@ -79,10 +79,12 @@ typedef struct {
     int dissipation;    /* 0: entropy conservative, 1: entropy stable (WENO-(2p-1)) */
     int mixed;          /* 0: FP64 throughout.  1: FP32-mixed residual: the two-point
                            pair algebra (except the small-jump branch of the
-                           logarithmic means) and the whole face dissipation (state,
-                           eigenvectors, WENO, switch) in FP32; metrics, their
-                           contraction with the pair algebra, the VCL, the residual
-                           accumulation, con2prim, CFL, mesh and state in FP64 */
+                           logarithmic means) in FP32; the face dissipation in FP32
+                           (RHD: state, eigenvectors, WENO, switch; RMHD: the
+                           projections, WENO and switch, the numeric eigen-structure
+                           staying FP64); metrics, their contraction with the pair
+                           algebra, the Godunov-Powell source pair, the VCL, the
+                           residual accumulation, con2prim, CFL, mesh and state in FP64 */
     double weno_eps;    /* WENO-JS epsilon */
     double cfl;         /* CFL number of eq. cfl */
 } es_scheme;
@@ -166,7 +168,7 @@ es_status es_mesh_redistribute(es_ctx* ctx, const double* prim, const double* x,
 es_status es_rk3_step(es_ctx* ctx, double* Ucurv, double* J, double* x, double* xdot,
                       double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
 
-/* Adjoint (FP64 form only; ES_EUNSUPPORTED for scheme.mixed = 1).  The
+/* Adjoint (RHD, FP64 form only; ES_EUNSUPPORTED for scheme.mixed = 1 or RMHD).  The
  * derivatives are those of the step with the mesh trajectory (x^n, xdot), the
  * time step dt and every branch decision (the sign switch Y of eq. ESFlux_HO,
  * the maximum in lambda^, the log-mean series branch) held at their forward

@@ -73,9 +73,8 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
         if (monitor->form != ES_MON_PAPER && monitor->form != ES_MON_SQGRAD) return ES_EINVAL;
         if (monitor->filter_passes < 0 || monitor->sweeps < 0 || !(monitor->alpha >= 0.0)) return ES_EINVAL;
     }
-    // kernels of this build: p = 3; RHD in FP64 or FP32-mixed, RMHD in FP64
-    if (scheme->order_p != 3 || (scheme->phys == ES_RMHD && scheme->mixed != 0))
-        return ES_EUNSUPPORTED;
+    // kernels of this build: p = 3 (RHD and RMHD, FP64 or FP32-mixed)
+    if (scheme->order_p != 3) return ES_EUNSUPPORTED;
 
     es_ctx* c = new (std::nothrow) es_ctx();
     if (c == nullptr) return ES_EHIP;

@@ -98,7 +98,7 @@ struct SweepPlanM {
     long long nlines[3];
 };
 
-template <int DIM, int DIR, bool ES>
+template <int DIM, int DIR, bool ES, bool MIXED>
 __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G, double eps,
                                                       const double* __restrict__ prim,
                                                       const double* __restrict__ met,
@@ -171,7 +171,8 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
 #pragma unroll
             for (int c = 0; c < NA; ++c) ar[c] = sd[line][F_A + c][lane + n];
             double F[MR], Jt, Bt;
-            pair_flux_rmhd<DIM>(G, l, r, al, ar, F, Jt, Bt);
+            pair_flux_rmhd<DIM, typename std::conditional<MIXED, float, double>::type>(G, l, r, al, ar, F, Jt,
+                                                                                         Bt);
 #pragma unroll
             for (int c = 0; c < MR; ++c) sp[line][n - 1][c][lane] = F[c];
             sp[line][n - 1][MR][lane] = Jt;
@@ -215,7 +216,7 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
 #pragma unroll
             for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane]; ar[c] = sd[line][F_A + c][lane + 1]; }
             double d[MR];
-            face_diss_rmhd<DIM>(G, eps, Pn, al, ar, d);
+            face_diss_rmhd<DIM, MIXED>(G, eps, Pn, al, ar, d);
 #pragma unroll
             for (int c = 0; c < MR; ++c) sp[line][0][c][lane] = d[c];
         }
@@ -233,7 +234,7 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
     }
 }
 
-template <int DIM, bool ES>
+template <int DIM, bool ES, bool MIXED>
 __global__ void __launch_bounds__(128) k_residual_rmhd(GridDev g, double G, double eps,
                                                        const double* __restrict__ prim,
                                                        const double* __restrict__ met,
@@ -242,17 +243,17 @@ __global__ void __launch_bounds__(128) k_residual_rmhd(GridDev g, double G, doub
     const long long slab = (long long)(MR + 1) * g.nodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < sw.nblk[0]) {
-        residual_segment_rmhd<DIM, 0, ES>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
+        residual_segment_rmhd<DIM, 0, ES, MIXED>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
         return;
     }
     b -= sw.nblk[0];
     if (DIM == 2 || b < sw.nblk[1]) {
-        residual_segment_rmhd<DIM, 1, ES>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
+        residual_segment_rmhd<DIM, 1, ES, MIXED>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
         return;
     }
     b -= sw.nblk[1];
     if (DIM == 3)
-        residual_segment_rmhd<DIM, 2, ES>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
+        residual_segment_rmhd<DIM, 2, ES, MIXED>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
 }
 
 // CFL partial maxima: rho_k = L_k max_m |lambda_m| / J per direction (eq. cfl), the
@@ -362,10 +363,12 @@ static void residual_all_rmhd(const es_ctx* c, const double* prim, const double*
         nb += sw.nblk[d];
     }
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
-    if (c->scheme.dissipation != 0)
-        k_residual_rmhd<DIM, true><<<(unsigned)nb, 64 * RLINES, 0, s>>>(g, G, eps, prim, met, Ld, sw);
-    else
-        k_residual_rmhd<DIM, false><<<(unsigned)nb, 64 * RLINES, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    const dim3 grid((unsigned)nb), block(64 * RLINES);
+    const bool es = c->scheme.dissipation != 0, mixed = c->scheme.mixed != 0;
+    if (es && mixed) k_residual_rmhd<DIM, true, true><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else if (es) k_residual_rmhd<DIM, true, false><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else if (mixed) k_residual_rmhd<DIM, false, true><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else k_residual_rmhd<DIM, false, false><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
 }
 
 }  // namespace

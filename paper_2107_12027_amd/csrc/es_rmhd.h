@@ -7,6 +7,8 @@
 // three components kept in 2D), conservative slots U = (D, m_1..3, E, B_1..3).
 #pragma once
 
+#include <type_traits>
+
 #include "es_rhd.h"
 #include "es_dual.h"
 
@@ -193,78 +195,106 @@ __device__ __forceinline__ NodeRMHD node_rmhd(double G, const double* P, double 
 // {.} arithmetic means (of products where products appear), ^ln logarithmic means.
 // Also the source pair B~ = 1/4 sum_j (a_j,l + a_j,r)(B_j,l + B_j,r) (eq. BFlux_O2)
 // and the VCL pair value a_t (eq. MetricsFlux_O2).
-template <int DIM>
+//
+// R = float is the mixed form: the pair algebra in FP32 except the small-jump
+// branch of the logarithmic means (FP64), written as coefficients K_t = U~ and
+// K_j = F~_j that are contracted with the metrics in FP64 (as the RHD mixed
+// form: equal states give equal coefficients, so the metric sums cancel in FP64);
+// B~ and a_t stay FP64.
+template <int DIM, typename R = double>
 __device__ __forceinline__ void pair_flux_rmhd(double G, const NodeRMHD& l, const NodeRMHD& r,
                                                const double* al, const double* ar, double* F,
                                                double& Jt, double& Bt) {
-    const double rho_ln = log_mean(l.rho, r.rho, l.lr, r.lr);
-    const double beta_ln = log_mean(l.beta, r.beta, l.lb, r.lb);
-    const double rho = 0.5 * (l.rho + r.rho), beta = 0.5 * (l.beta + r.beta);
-    const double W = 0.5 * (l.W + r.W), b0 = 0.5 * (l.b0 + r.b0);
-    const double Wb0 = 0.5 * (l.Wb0 + r.Wb0), Wb02 = 0.5 * (l.Wb02 + r.Wb02);
-    const double sb = 0.5 * (l.sb + r.sb), b02 = 0.5 * (l.b02 + r.b02);
-    double u[3], b[3], B[3], Wbk2[3], bk2[3], ujsb[3], ujb02[3];
-    double uu = 0.0, sbk2 = 0.0;
+    constexpr bool F32 = !std::is_same<R, double>::value;
+    R rho_ln, beta_ln;
+    if constexpr (F32) {
+        rho_ln = log_mean_mixed(l.rho, r.rho, l.lr, r.lr);
+        beta_ln = log_mean_mixed(l.beta, r.beta, l.lb, r.lb);
+    } else {
+        rho_ln = log_mean(l.rho, r.rho, l.lr, r.lr);
+        beta_ln = log_mean(l.beta, r.beta, l.lb, r.lb);
+    }
+    auto mean = [](double a, double b) { return R(0.5) * (R(a) + R(b)); };
+    const R rho = mean(l.rho, r.rho), beta = mean(l.beta, r.beta);
+    const R W = mean(l.W, r.W), b0 = mean(l.b0, r.b0);
+    const R Wb0 = mean(l.Wb0, r.Wb0), Wb02 = mean(l.Wb02, r.Wb02);
+    const R sb = mean(l.sb, r.sb), b02 = mean(l.b02, r.b02);
+    R u[3], b[3], B[3], Wbk2[3], bk2[3], ujsb[3], ujb02[3];
+    R uu = R(0.0), sbk2 = R(0.0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        u[k] = 0.5 * (l.u[k] + r.u[k]);
-        b[k] = 0.5 * (l.b[k] + r.b[k]);
-        B[k] = 0.5 * (l.B[k] + r.B[k]);
-        Wbk2[k] = 0.5 * (l.Wbk2[k] + r.Wbk2[k]);
-        bk2[k] = 0.5 * (l.bk2[k] + r.bk2[k]);
-        ujsb[k] = 0.5 * (l.u[k] * l.sb + r.u[k] * r.sb);
-        ujb02[k] = 0.5 * (l.u[k] * l.b02 + r.u[k] * r.b02);
+        u[k] = mean(l.u[k], r.u[k]);
+        b[k] = mean(l.b[k], r.b[k]);
+        B[k] = mean(l.B[k], r.B[k]);
+        Wbk2[k] = mean(l.Wbk2[k], r.Wbk2[k]);
+        bk2[k] = mean(l.bk2[k], r.bk2[k]);
+        ujsb[k] = R(0.5) * (R(l.u[k]) * R(l.sb) + R(r.u[k]) * R(r.sb));
+        ujb02[k] = R(0.5) * (R(l.u[k]) * R(l.b02) + R(r.u[k]) * R(r.b02));
         uu += u[k] * u[k];
         sbk2 += bk2[k];
     }
-    const double iW = 1.0 / W, ib = 1.0 / beta;
-    const double a0 = 1.0 + 1.0 / ((G - 1.0) * beta_ln);
-    const double iden = 1.0 / (W * W - uu);
+    R iW, ib, a0, iden;
+    if constexpr (F32) {
+        iW = frcp(W);
+        ib = frcp(beta);
+        a0 = R(1.0) + frcp(R(G - 1.0) * beta_ln);
+        iden = frcp(W * W - uu);
+    } else {
+        iW = 1.0 / W;
+        ib = 1.0 / beta;
+        a0 = 1.0 + 1.0 / ((G - 1.0) * beta_ln);
+        iden = 1.0 / (W * W - uu);
+    }
     // U~
-    double Ut[8];
-    const double U1 = rho_ln * W;
-    double UB[3];
+    R Ut[8];
+    const R U1 = rho_ln * W;
+    R UB[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) UB[k] = (W * W * b[k] - Wb0 * u[k]) * iW;
-    const double a1 = rho + 0.5 * beta * sbk2 + 0.5 * beta * Wb02 * iW;
-    double R1 = -a0 * U1 - 0.5 * Wb02;
+    const R a1 = rho + R(0.5) * beta * sbk2 + R(0.5) * beta * Wb02 * iW;
+    R R1 = -a0 * U1 - R(0.5) * Wb02;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) R1 += 0.5 * Wbk2[k] - b[k] * UB[k];
-    double Rk[3], uR = 0.0;
+    for (int k = 0; k < 3; ++k) R1 += R(0.5) * Wbk2[k] - b[k] * UB[k];
+    R Rk[3], uR = R(0.0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) { Rk[k] = (a1 * u[k] - beta * Wb0 * b[k]) * iW; uR += u[k] * Rk[k]; }
-    const double Dd = beta * (W * W - uu) * iW;
-    const double U5 = (uR - beta * R1) / Dd;
+    const R Dd = beta * (W * W - uu) * iW;
+    R U5;
+    if constexpr (F32) U5 = (uR - beta * R1) * frcp(Dd);
+    else U5 = (uR - beta * R1) / Dd;
     Ut[0] = U1;
 #pragma unroll
     for (int k = 0; k < 3; ++k) { Ut[1 + k] = u[k] * U5 * iW + Rk[k] * ib; Ut[5 + k] = UB[k]; }
     Ut[4] = U5;
     const double at = 0.5 * (al[0] + ar[0]);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) F[c] = at * Ut[c];
+    for (int c = 0; c < 8; ++c) F[c] = at * (double)Ut[c];
     double bt = 0.0;
     // F~_j for the directions of the grid
 #pragma unroll
     for (int j = 0; j < DIM; ++j) {
         const double aj = 0.5 * (al[1 + j] + ar[1 + j]);
         bt += 0.25 * (al[1 + j] + ar[1 + j]) * (l.B[j] + r.B[j]);
-        const double c0 = -beta * (u[j] * b0 + B[j]);
-        const double F1 = rho_ln * u[j];
-        double FB[3], Pk[3], uP = 0.0, bFB = 0.0;
+        const R c0 = -beta * (u[j] * b0 + B[j]);
+        const R F1 = rho_ln * u[j];
+        R FB[3], Pk[3], uP = R(0.0), bFB = R(0.0);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             FB[k] = u[j] * b[k] + c0 * u[k] * ib * iW;
             Pk[k] = (c0 * iW) * (b[k] - b0 * u[k] * iW);
         }
-        Pk[j] += rho + 0.5 * beta * sb - 0.5 * beta * b02;
+        Pk[j] += rho + R(0.5) * beta * sb - R(0.5) * beta * b02;
 #pragma unroll
         for (int k = 0; k < 3; ++k) { uP += u[k] * Pk[k]; bFB += b[k] * FB[k]; }
-        const double Q = 0.5 * ujsb[j] - 0.5 * ujb02[j] - B[j] * b0;
-        const double F5 = W * (a0 * F1 + uP * ib + bFB - Q) * iden;
-        F[0] += aj * F1;
+        const R Q = R(0.5) * ujsb[j] - R(0.5) * ujb02[j] - B[j] * b0;
+        const R F5 = W * (a0 * F1 + uP * ib + bFB - Q) * iden;
+        F[0] += aj * (double)F1;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { F[1 + k] += aj * (u[k] * F5 * iW + Pk[k] * ib); F[5 + k] += aj * FB[k]; }
-        F[4] += aj * F5;
+        for (int k = 0; k < 3; ++k) {
+            F[1 + k] += aj * (double)(u[k] * F5 * iW + Pk[k] * ib);
+            F[5 + k] += aj * (double)FB[k];
+        }
+        F[4] += aj * (double)F5;
     }
     Jt = at;
     Bt = bt;
@@ -618,7 +648,7 @@ __device__ __forceinline__ void canonical_groups(const double* lam, const double
 // every group of nearly equal eigenvalues (canonical_groups; the group of v_n
 // holds the entropy and div B waves and is seeded with e_D and e_{B_n}).
 // nodes: the 8 primitive slots of the stencil nodes i-2..i+3.
-template <int DIM>
+template <int DIM, bool MIXED = false>
 __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const double Pn[6][8],
                                                const double* al, const double* ar, double* d) {
     const double at = 0.5 * (al[0] + ar[0]);
@@ -675,41 +705,51 @@ __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const doubl
 #pragma unroll
     for (int c = 0; c < 8; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
     const double tvmax = tv2 + tv3;
-    double dd[8];
+    // projections, WENO5, the switch and the accumulation: FP64, or FP32 in the
+    // mixed form (the eigen-structure above stays FP64 there)
+    using RW = typename std::conditional<MIXED, float, double>::type;
+    RW TVw[6][8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) dd[c] = 0.0;
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) TVw[j][c] = (RW)TV[j][c];
+    RW dd[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) dd[c] = RW(0.0);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         // column r = L z with z the canonical basis vector of position k
-        double r[8];
+        RW r[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             double s = 0.0;
 #pragma unroll
             for (int kk = 0; kk <= i; ++kk) s += Lc[i][kk] * canon[k][kk];
-            r[i] = s;
+            r[i] = (RW)s;
         }
-        double vt[6];
+        RW vt[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            double s = 0.0;
+            RW s = RW(0.0);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) s += r[c] * TV[j][c];
+            for (int c = 0; c < 8; ++c) s += r[c] * TVw[j][c];
             vt[j] = s;
         }
-        const double jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps) -
-                          weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
-        const double jp = vt[3] - vt[2];
-        double r1 = 0.0;
+        const RW jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], (RW)eps) -
+                      weno5(vt[0], vt[1], vt[2], vt[3], vt[4], (RW)eps);
+        const RW jp = vt[3] - vt[2];
+        RW r1 = RW(0.0);
 #pragma unroll
         for (int c = 0; c < 8; ++c) r1 += fabs(r[c]);
-        if (jw * jp > 0.0 && fabs(jp) > RealTraits<double>::ytol * r1 * tvmax) {
+        if (jw * jp > RW(0.0) && fabs(jp) > RealTraits<RW>::ytol * r1 * (RW)tvmax) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) dd[c] += jw * r[c];
         }
     }
-    double o[8];
-    rotate8<true>(T, dd, o);
+    double ddd[8], o[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) ddd[c] = (double)dd[c];
+    rotate8<true>(T, ddd, o);
 #pragma unroll
     for (int c = 0; c < 8; ++c) d[c] = lhat * o[c];
 }

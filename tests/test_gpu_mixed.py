@@ -112,3 +112,67 @@ def test_mixed_rk3_step_quadrant():
     assert abs(host(dt)[0] - out["dt"]) <= 1e-13 * out["dt"]
     assert np.all(l1_rel(host(U), out["U"]) <= 3e-6), l1_rel(host(U), out["U"])
     assert np.all(rel_inf(host(U), out["U"]) <= 1e-4)
+
+
+# ---------------------------------------------------------------------------
+# RMHD mixed form: FP32 pair algebra (coefficients contracted in FP64, B~ pair
+# in FP64) and FP32 projections / WENO5 / switch of the dissipation on the
+# FP64 numeric eigen-structure
+# ---------------------------------------------------------------------------
+RGRIDS = [(2, (130, 70, 1), (0, 0, 0)), (2, (64, 67, 1), (1, 1, 0)), (3, (66, 9, 8), (0, 1, 0))]
+
+
+@pytest.mark.parametrize("dim,n,bc", RGRIDS)
+@pytest.mark.parametrize("diss", [0, 1])
+def test_mixed_rmhd_residual_error(dim, n, bc, diss):
+    case = Case(dim, n, bc, phys=ph.RMHD, seed=4 + diss, dissipation=diss, mixed=1)
+    _, _, _, _, dU, dJ = case.residual()
+    dUo, dJo = case.oracle_residual()
+    err = l1_rel(host(dU), dUo)
+    assert np.all(err <= (2e-4 if diss else 2e-6)), err
+    assert rel_inf(host(dJ)[None], dJo[None])[0] <= 1e-12
+
+
+@pytest.mark.parametrize("dim,n,bc", RGRIDS)
+def test_mixed_rmhd_free_stream(dim, n, bc):
+    # uniform RMHD state on a static curvilinear mesh: the FP64 contraction keeps it
+    # uniform to FP64 rounding (the Godunov-Powell source pair is FP64 and its
+    # discrete divergence of B vanishes with the metric identities)
+    case = Case(dim, n, bc, phys=ph.RMHD, seed=11, uniform=True, moving=False, mixed=1)
+    U, J, _, met, dU, dJ = case.residual()
+    Uh, Jh, dUh, dJh = host(U), host(J), host(dU), host(dJ)
+    U0 = Uh / Jh
+    err = np.abs(dUh - U0 * dJh).reshape(case.m, -1).max(axis=1)
+    scale = np.abs(U0).reshape(case.m, -1).max() * np.abs(host(met)).max() / min(case.grid.dxi[:dim])
+    assert np.all(err <= 1e-13 * scale), err / scale
+    assert np.abs(dJh).max() == 0.0
+
+
+def test_mixed_rmhd_rk3_step_rotor():
+    # one RK3 step of the rotor (degenerate eigen-groups outside the disk)
+    w = wl.rmhd_rotor(n=40)
+    g = w.grid
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    out = []
+    for mixed in (0, 1):
+        w.scheme.mixed = mixed
+        ctx = es.Context(g, w.scheme, w.monitor)
+        met = empty(ctx.nmet, *ctx.padded_shape())
+        J = empty(*ctx.shape())
+        x = dev(w.x)
+        ctx.metrics(x, None, met, J)
+        U = empty(ctx.m, *ctx.shape())
+        ctx.prim2con(dev(P), J, U)
+        xd = empty(g.dim, *ctx.shape())
+        dt = empty(1)
+        ctx.rk3_step(U, J, x, xd, dt)
+        assert ctx.status()[0] == es.ES_OK
+        out.append((host(U), host(dt)[0]))
+    w.scheme.mixed = 0
+    Uo, Jo = st.initial_state(g, w.scheme, P, w.x)
+    ref = st.rk3_step(g, w.scheme, w.monitor, Uo, Jo, w.x)
+    assert out[1][1] == out[0][1]                       # dt from the FP64 CFL
+    big = np.max(np.abs(ref["U"]))
+    for c in range(8):
+        sc = max(np.sum(np.abs(ref["U"][c])), 1e-3 * big * ref["U"][c].size)
+        assert np.sum(np.abs(out[1][0][c] - ref["U"][c])) <= 1e-5 * sc, c
