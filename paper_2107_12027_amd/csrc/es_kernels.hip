@@ -512,21 +512,22 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 #pragma unroll
         for (int c = 0; c < M; ++c) d[c] = 0.0;
         if (active && lane >= 2 && s_own < s_end) {
+            // the stencil states are read from LDS where they are used
             if (MIXED) {
                 // FP32 dissipation from FP32 copies of the stencil states and metrics
-                NodeRHD<NU, float> st[6];
-#pragma unroll
-                for (int q = 0; q < 6; ++q) {
+                auto node_f = [&](int q) {
                     const int k = lane - 2 + q;
-                    st[q].rho = (float)sd[line][F_RHO][k];
-                    st[q].p = (float)sd[line][F_P][k];
-                    st[q].beta = (float)sd[line][F_BETA][k];
-                    st[q].W = (float)sd[line][F_W][k];
-                    st[q].lr = (float)sd[line][F_LR][k];
-                    st[q].lb = (float)sd[line][F_LB][k];
+                    NodeRHD<NU, float> nd;
+                    nd.rho = (float)sd[line][F_RHO][k];
+                    nd.p = (float)sd[line][F_P][k];
+                    nd.beta = (float)sd[line][F_BETA][k];
+                    nd.W = (float)sd[line][F_W][k];
+                    nd.lr = (float)sd[line][F_LR][k];
+                    nd.lb = (float)sd[line][F_LB][k];
 #pragma unroll
-                    for (int c = 0; c < NU; ++c) st[q].u[c] = (float)sd[line][F_U + c][k];
-                }
+                    for (int c = 0; c < NU; ++c) nd.u[c] = (float)sd[line][F_U + c][k];
+                    return nd;
+                };
                 float al[NA], ar[NA];
 #pragma unroll
                 for (int c = 0; c < NA; ++c) {
@@ -534,17 +535,14 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
                     ar[c] = (float)sd[line][F_A + c][lane + 1];
                 }
                 float df[M];
-                face_diss_rhd<DIM>((float)G, (float)eps, st, al, ar, df);
+                face_diss_rhd_fn<DIM, float>((float)G, (float)eps, node_f, al, ar, df);
 #pragma unroll
                 for (int c = 0; c < M; ++c) d[c] = (double)df[c];
             } else {
-                NodeRHD<NU> st[6];
-#pragma unroll
-                for (int q = 0; q < 6; ++q) st[q] = node_at(lane - 2 + q);
                 double al[NA], ar[NA];
 #pragma unroll
                 for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane]; ar[c] = sd[line][F_A + c][lane + 1]; }
-                face_diss_rhd<DIM>(G, eps, st, al, ar, d);
+                face_diss_rhd_fn<DIM, double>(G, eps, [&](int q) { return node_at(lane - 2 + q); }, al, ar, d);
             }
         }
 #pragma unroll

@@ -530,9 +530,13 @@ __device__ __forceinline__ R face_eigen_columns(R G, const R* V2, const R* V3, R
 //  * WENO5-JS of V~ = R^T T V on both sides, Y_l = [<<V~_l>> [V~_l] > 0], with a
 //    jump [V~_l] below Y_TOL |r_l|_1 (|T V_i|_max + |T V_i+1|_max) counted as
 //    zero (sign(0) at rounding level).
-template <int DIM, typename R>
-__device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>* nd,
-                                              const R* al, const R* ar, R* d) {
+//
+// The stencil states come from node(j), j = 0..5 (nodes i-2..i+3).  The face
+// eigen-structure is formed first from nodes i and i+1 alone; the six rotated
+// entropy vectors are formed afterwards and projected onto the columns at once,
+// so that they are not held while the eigen-structure is built (register use).
+template <int DIM, typename R, typename NodeFn>
+__device__ __forceinline__ void face_diss_rhd_fn(R G, R eps, NodeFn&& node, const R* al, const R* ar, R* d) {
     constexpr int M = DIM + 2;
     const R at = R(0.5) * (al[0] + ar[0]);
     R ax[3] = {R(0.0), R(0.0), R(0.0)};
@@ -544,46 +548,76 @@ __device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>*
     R T[3][3];
     rotation<DIM>(nrm, T);
 
-    // rotated entropy variables T V of the six stencil nodes
-    R TV[6][M];
+    // rotated entropy variables T V of stencil node j
     const R c0 = G / (G - R(1.0)), c1 = R(1.0) / (G - R(1.0));
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const NodeRHD<DIM, R>& q = nd[j];
-        TV[j][0] = c0 + q.lr + q.lb * c1 + q.beta;
+    auto tv = [&](int j, R* out) {
+        const NodeRHD<DIM, R> q = node(j);
+        out[0] = c0 + q.lr + q.lb * c1 + q.beta;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             R s = R(0.0);
 #pragma unroll
             for (int b = 0; b < DIM; ++b) s += T[a][b] * q.u[b];
-            TV[j][1 + a] = q.beta * s;
+            out[1 + a] = q.beta * s;
         }
-        TV[j][M - 1] = -q.beta * q.W;
-    }
-
-    R dd[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) dd[c] = R(0.0);
+        out[M - 1] = -q.beta * q.W;
+    };
+    R TV2[M], TV3[M];
+    tv(2, TV2);
+    tv(3, TV3);
     // rounding scale of the projections r . T V at nodes i and i+1
     R tv2 = R(0.0), tv3 = R(0.0);
 #pragma unroll
-    for (int c = 0; c < M; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
+    for (int c = 0; c < M; ++c) { tv2 = fmax(tv2, fabs(TV2[c])); tv3 = fmax(tv3, fabs(TV3[c])); }
     const R tvmax = tv2 + tv3;
 
-    // one column r of R: project, reconstruct, switch, accumulate
-    auto column = [&](const R* r, int) {
-        R vt[6];
+    R Rm[M][M];
+    const R lhat = face_eigen_columns<DIM>(G, TV2, TV3, at, L, [&](const R* r, int q) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
+        for (int c = 0; c < M; ++c) Rm[q][c] = r[c];
+    });
+
+    // projections of the six stencil states onto the columns (the fence keeps
+    // the reads of the other four states after the eigen-structure)
+#ifndef ES_OPCOUNT_HOST
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#endif
+    R vt[M][6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        R TVj[M];
+        if (j == 2) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) TVj[c] = TV2[c];
+        } else if (j == 3) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) TVj[c] = TV3[c];
+        } else {
+            tv(j, TVj);
+        }
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
             R s = R(0.0);
 #pragma unroll
-            for (int c = 0; c < M; ++c) s += r[c] * TV[j][c];
-            vt[j] = s;
+            for (int c = 0; c < M; ++c) s += Rm[q][c] * TVj[c];
+            vt[q][j] = s;
         }
-        const R vm = weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
-        const R vp = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps);
+#ifndef ES_OPCOUNT_HOST
+        __builtin_amdgcn_sched_barrier(0);   // one stencil state at a time
+#endif
+    }
+
+    // per column: reconstruct, switch, accumulate (in column order)
+    R dd[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) dd[c] = R(0.0);
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const R* r = Rm[q];
+        const R vm = weno5(vt[q][0], vt[q][1], vt[q][2], vt[q][3], vt[q][4], eps);
+        const R vp = weno5(vt[q][5], vt[q][4], vt[q][3], vt[q][2], vt[q][1], eps);
         const R jw = vp - vm;
-        const R jp = vt[3] - vt[2];
+        const R jp = vt[q][3] - vt[q][2];
         // a jump within rounding of zero counts as zero (Y = 0)
         R r1 = R(0.0);
 #pragma unroll
@@ -592,9 +626,11 @@ __device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>*
 #pragma unroll
             for (int c = 0; c < M; ++c) dd[c] += jw * r[c];
         }
-    };
-
-    const R lhat = face_eigen_columns<DIM>(G, TV[2], TV[3], at, L, column);
+#ifndef ES_OPCOUNT_HOST
+        // one column at a time (interleaving the columns' WENO raises register use)
+        __builtin_amdgcn_sched_barrier(0);
+#endif
+    }
 
     // back to the original frame: d = lambda^ T^{-1} (R Y <<V~>>)
     d[0] = lhat * dd[0];
@@ -606,6 +642,12 @@ __device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>*
         for (int b = 0; b < DIM; ++b) s += T[b][a] * dd[1 + b];
         d[1 + a] = lhat * s;
     }
+}
+
+template <int DIM, typename R>
+__device__ __forceinline__ void face_diss_rhd(R G, R eps, const NodeRHD<DIM, R>* nd,
+                                              const R* al, const R* ar, R* d) {
+    face_diss_rhd_fn<DIM, R>(G, eps, [&](int j) { return nd[j]; }, al, ar, d);
 }
 
 }  // namespace es
