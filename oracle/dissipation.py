@@ -253,9 +253,30 @@ def weno5_minus(a, b, c, d, e, eps):
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2)
 
 
+def weno3_minus(a, b, c, eps):
+    """WENO3-JS value at i+1/2 from v_{i-1..i+1} = (a, b, c) (Jiang-Shu 1996, w = 3):
+    candidates (3b - a)/2 and (b + c)/2 with linear weights 1/3, 2/3 and
+    smoothness indicators (b - a)^2, (c - b)^2."""
+    q0 = (-a + 3 * b) / 2.0
+    q1 = (b + c) / 2.0
+    a0 = (1.0 / 3.0) / (eps + (b - a) ** 2) ** 2
+    a1 = (2.0 / 3.0) / (eps + (c - b) ** 2) ** 2
+    return (a0 * q0 + a1 * q1) / (a0 + a1)
+
+
+def weno_minus(vs, eps):
+    """The w-th order WENO-JS value at i+1/2 from the w values v_{i-(w-1)/2..i+(w-1)/2}."""
+    if len(vs) == 5:
+        return weno5_minus(*vs, eps)
+    if len(vs) == 3:
+        return weno3_minus(*vs, eps)
+    raise ValueError("WENO order %d is not implemented" % len(vs))
+
+
 def face_dissipation(Pst, ast, G, phys, dim, eps, details=False, Y_fixed=None):
     """ES dissipation vector d = D Y <<V~>> at faces.
-    Pst: (6, 8, N) full primitive states of the stencil nodes i-2..i+3 of each face;
+    Pst: (2p, 8, N) full primitive states of the stencil nodes i-p+1..i+p of each
+    face (p = 3: WENO5 on i-2..i+3; p = 2: WENO3 on i-1..i+2, w = 2p - 1);
     ast: (2, d+1, N) metric vectors of nodes i and i+1.
     Y_fixed: optional (m, N) sign-switch values to use instead of evaluating Y
     (the switch held fixed, for difference quotients of the smooth part).
@@ -270,7 +291,9 @@ def face_dissipation(Pst, ast, G, phys, dim, eps, details=False, Y_fixed=None):
     T0 = rotation(n)
     slots = [1, 5] if phys == ph.RMHD else [1]
     # face state: the state whose entropy variables are the mean of the two nodes'
-    Vbar = 0.5 * (ph.entropy_vars(Pst[2], G) + ph.entropy_vars(Pst[3], G))
+    ns = len(Pst)
+    ci = ns // 2 - 1                      # stencil index of node i (i+1 is ci + 1)
+    Vbar = 0.5 * (ph.entropy_vars(Pst[ci], G) + ph.entropy_vars(Pst[ci + 1], G))
     Pbar = ph.prim_from_entropy_vars(Vbar, G)
     if phys == ph.RHD:
         Pbar[5:8] = 0.0
@@ -278,19 +301,19 @@ def face_dissipation(Pst, ast, G, phys, dim, eps, details=False, Y_fixed=None):
     lam, R = eigensystem(Pr, G, phys, dim)
     lhat = np.max(np.abs(abar[0][:, None] + L[:, None] * lam), axis=1)
     Vt = []
-    for j in range(6):
+    for j in range(ns):
         Vj = rotate_full(ph.entropy_vars(Pst[j], G), T0, slots)[sel]   # (m, N)
         Vt.append(np.einsum("nab,an->bn", R, Vj))                       # R^T T V
-    vm = weno5_minus(Vt[0], Vt[1], Vt[2], Vt[3], Vt[4], eps)
-    vp = weno5_minus(Vt[5], Vt[4], Vt[3], Vt[2], Vt[1], eps)
+    vm = weno_minus(Vt[0:ns - 1], eps)                                  # from the left
+    vp = weno_minus(Vt[ns - 1:0:-1], eps)                               # from the right
     jump_weno = vp - vm
-    jump = Vt[3] - Vt[2]
+    jump = Vt[ci + 1] - Vt[ci]
     # sign(0) reading: a jump [V~_l] within rounding of zero counts as zero, so Y_l = 0.
     # Rounding level: Y_TOL times |r_l|_1 (|T V_i|_max + |T V_i+1|_max), a scale that
     # does not shrink with the components a column happens to touch (the transverse
     # momentum entries of a state at rest are themselves rounding residue).
-    Vi = rotate_full(ph.entropy_vars(Pst[2], G), T0, slots)[sel]
-    Vj = rotate_full(ph.entropy_vars(Pst[3], G), T0, slots)[sel]
+    Vi = rotate_full(ph.entropy_vars(Pst[ci], G), T0, slots)[sel]
+    Vj = rotate_full(ph.entropy_vars(Pst[ci + 1], G), T0, slots)[sel]
     scale = np.sum(np.abs(R), axis=1).T * (np.max(np.abs(Vi), axis=0) + np.max(np.abs(Vj), axis=0))[None, :]
     Y = ((jump_weno * jump > 0) & (np.abs(jump) > Y_TOL * scale)).astype(np.float64)
     if Y_fixed is not None:

@@ -70,9 +70,10 @@ def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None):
                 Jf = Jf + al[n - 1] * ec.curvilinear_pair_Jt(aL, aR)
         if scheme.dissipation:
             fshape = Ff.shape[1:]
-            Pst = np.stack([_take(Pk, faces + j, 1 + ax_sp) for j in range(-2, 4)])
+            # WENO-(2p-1) on the 2p nodes i-p+1..i+p of each face
+            Pst = np.stack([_take(Pk, faces + j, 1 + ax_sp) for j in range(1 - p, p + 1)])
             ast = np.stack([_take(ak, faces + j, 1 + ax_sp) for j in range(0, 2)])
-            Pst = Pst.reshape(6, 8, -1)
+            Pst = Pst.reshape(2 * p, 8, -1)
             ast = ast.reshape(2, d + 1, -1)
             dd, dinfo = ds.face_dissipation(Pst, ast, G, phys, d, scheme.weno_eps, details=True,
                                             Y_fixed=None if Y_fixed is None else Y_fixed[k])
