@@ -75,7 +75,9 @@ typedef struct {
 typedef struct {
     int phys;           /* ES_RHD / ES_RMHD */
     double gamma;       /* adiabatic index of the ideal EOS (eq. EOS) */
-    int order_p;        /* p of the 2p-th order EC flux; this build supports p = 3 */
+    int order_p;        /* p of the 2p-th order EC flux and metrics with WENO of order
+                           2p - 1 (Section 4): p = 3 (RHD, RMHD) or p = 2 (RHD; not
+                           the adjoint entry points); others give ES_EUNSUPPORTED */
     int dissipation;    /* 0: entropy conservative, 1: entropy stable (WENO-(2p-1)) */
     int mixed;          /* 0: FP64 throughout.  1: FP32-mixed residual: the two-point
                            pair algebra (except the small-jump branch of the
@@ -168,7 +170,8 @@ es_status es_mesh_redistribute(es_ctx* ctx, const double* prim, const double* x,
 es_status es_rk3_step(es_ctx* ctx, double* Ucurv, double* J, double* x, double* xdot,
                       double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
 
-/* Adjoint (RHD, FP64 form only; ES_EUNSUPPORTED for scheme.mixed = 1 or RMHD).  The
+/* Adjoint (RHD, p = 3, FP64 form only; ES_EUNSUPPORTED for scheme.mixed = 1, RMHD
+ * or p = 2).  The
  * derivatives are those of the step with the mesh trajectory (x^n, xdot), the
  * time step dt and every branch decision (the sign switch Y of eq. ESFlux_HO,
  * the maximum in lambda^, the log-mean series branch) held at their forward

@@ -73,8 +73,8 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
         if (monitor->form != ES_MON_PAPER && monitor->form != ES_MON_SQGRAD) return ES_EINVAL;
         if (monitor->filter_passes < 0 || monitor->sweeps < 0 || !(monitor->alpha >= 0.0)) return ES_EINVAL;
     }
-    // kernels of this build: p = 3 (RHD and RMHD, FP64 or FP32-mixed)
-    if (scheme->order_p != 3) return ES_EUNSUPPORTED;
+    // kernels of this build: p = 3 (RHD and RMHD, FP64 or FP32-mixed) and p = 2 (RHD)
+    if (scheme->order_p != 3 && !(scheme->order_p == 2 && scheme->phys == ES_RHD)) return ES_EUNSUPPORTED;
 
     es_ctx* c = new (std::nothrow) es_ctx();
     if (c == nullptr) return ES_EHIP;
@@ -97,6 +97,7 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     g.nodes = (long long)g.n[0] * g.n[1] * g.n[2];
     g.pnodes = (long long)g.P[0] * g.P[1] * g.P[2];
     g.enodes = (long long)g.E[0] * g.E[1] * g.E[2];
+    g.p = scheme->order_p;
     c->m = scheme->phys == ES_RMHD ? 8 : grid->dim + 2;
     c->nprim = c->m + 2;
     c->nmet = grid->dim * (grid->dim + 1);
@@ -297,7 +298,7 @@ es_status es_rk3_step_save(es_ctx* c, double* U, double* J, double* x, double* x
     if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
         dt_dev == nullptr || ckpt == nullptr)
         return ES_EINVAL;
-    if (c->scheme.mixed != 0 || c->scheme.phys != ES_RHD) return ES_EUNSUPPORTED;
+    if (c->scheme.mixed != 0 || c->scheme.phys != ES_RHD || c->scheme.order_p != 3) return ES_EUNSUPPORTED;
     return enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, s, ckpt);
 }
 
@@ -326,7 +327,7 @@ es_status es_residual_vjp(es_ctx* c, const double* U, const double* J, const dou
     if (c == nullptr || U == nullptr || J == nullptr || met == nullptr || lamU == nullptr ||
         gU == nullptr || gJ == nullptr)
         return ES_EINVAL;
-    if (c->scheme.mixed != 0 || c->scheme.phys != ES_RHD) return ES_EUNSUPPORTED;
+    if (c->scheme.mixed != 0 || c->scheme.phys != ES_RHD || c->scheme.order_p != 3) return ES_EUNSUPPORTED;
     const es_status st = ensure_adjoint(c);
     if (st != ES_OK) return st;
     return hip_status(es::launch_state_residual_vjp(c, U, J, met, lamU, gU, gJ, s));
@@ -337,7 +338,7 @@ es_status es_rk3_step_vjp(es_ctx* c, const double* ckpt, const double* lamU, con
     if (c == nullptr || ckpt == nullptr || lamU == nullptr || lamJ == nullptr || gU == nullptr ||
         gJ == nullptr)
         return ES_EINVAL;
-    if (c->scheme.mixed != 0 || c->scheme.phys != ES_RHD) return ES_EUNSUPPORTED;
+    if (c->scheme.mixed != 0 || c->scheme.phys != ES_RHD || c->scheme.order_p != 3) return ES_EUNSUPPORTED;
     const es_status st = ensure_adjoint(c);
     if (st != ES_OK) return st;
     return hip_status(es::launch_rk3_vjp(c, ckpt, lamU, lamJ, gU, gJ, s));

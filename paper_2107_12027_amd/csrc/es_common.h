@@ -17,6 +17,12 @@ __device__ __host__ constexpr double alpha3(int n) {
     return n == 1 ? 1.5 : (n == 2 ? -0.3 : 1.0 / 30.0);
 }
 
+// alpha_{p,n} of eq. HOCoeff for p = 2 (4/3, -1/6) and p = 3, zero for n > p (so a
+// sum over n = 1..3 is the p-term sum, exactly: the extra terms add zero).
+__device__ __host__ constexpr double alpha_pn(int p, int n) {
+    return p == 2 ? (n == 1 ? 4.0 / 3.0 : (n == 2 ? -1.0 / 6.0 : 0.0)) : alpha3(n);
+}
+
 struct GridDev {
     int dim;
     int n[3];
@@ -30,6 +36,7 @@ struct GridDev {
     long long nodes;        // interior nodes
     long long pnodes;       // padded nodes
     long long enodes;       // mesh-extension box nodes
+    int p;                  // order parameter: 2p-th order EC flux and metrics (2 or 3)
 };
 
 __device__ __forceinline__ long long pidx(const GridDev& g, int i, int j, int k) {

@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) k_metrics2d_fused(GridDev g, const double
             double s = 0.0, r = 0.0;
 #pragma unroll
             for (int n = 1; n <= 3; ++n) {
-                const double a = 0.5 * alpha3(n);
+                const double a = 0.5 * alpha_pn(g.p, n);
                 s += a * (xs[c][rj][ri + n] - xs[c][rj][ri - n]);
                 r += a * (xs[c][rj + n][ri] - xs[c][rj - n][ri]);
             }
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(MTX * MSY) k_metrics2d_stages(GridDev g, const
         double s = 0.0, r = 0.0;
 #pragma unroll
         for (int n = 1; n <= 3; ++n) {
-            const double a = 0.5 * alpha3(n);
+            const double a = 0.5 * alpha_pn(g.p, n);
             s += a * ((xs[c][rj][ri + n] + cdt * vs[c][rj][ri + n]) - (xs[c][rj][ri - n] + cdt * vs[c][rj][ri - n]));
             r += a * ((xs[c][rj + n][ri] + cdt * vs[c][rj + n][ri]) - (xs[c][rj - n][ri] + cdt * vs[c][rj - n][ri]));
         }
@@ -293,7 +293,7 @@ __global__ void k_cmm_products(GridDev g, const double* __restrict__ xe, double*
                 const double* xc = xe + j1 * EN + e;
                 double d = 0.0;
 #pragma unroll
-                for (int n = 1; n <= 3; ++n) d += 0.5 * alpha3(n) * (xc[n * st[a]] - xc[-n * st[a]]);
+                for (int n = 1; n <= 3; ++n) d += 0.5 * alpha_pn(g.p, n) * (xc[n * st[a]] - xc[-n * st[a]]);
                 v = d * xe[j2 * EN + e];
             }
             pi[(a * 3 + jj) * EN + e] = v;
@@ -322,7 +322,7 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
             double ta = 0.0, tb = 0.0;
 #pragma unroll
             for (int n = 1; n <= 3; ++n) {
-                const double a = 0.5 * alpha3(n);
+                const double a = 0.5 * alpha_pn(g.p, n);
                 ta += a * (pa[n * st[k2]] - pa[-n * st[k2]]);
                 tb += a * (pb[n * st[k1]] - pb[-n * st[k1]]);
             }
@@ -347,7 +347,7 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
         for (int kk = 0; kk < 3; ++kk) {
             double d = 0.0;
 #pragma unroll
-            for (int n = 1; n <= 3; ++n) d += 0.5 * alpha3(n) * (xe[e + n * st[kk]] - xe[e - n * st[kk]]);
+            for (int n = 1; n <= 3; ++n) d += 0.5 * alpha_pn(g.p, n) * (xe[e + n * st[kk]] - xe[e - n * st[kk]]);
             Jv += m[kk][0] * d / g.dxi[kk];
         }
         J0[iidx(g, i, j, k)] = Jv;
@@ -381,7 +381,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // dissipation and the flux differences, and writes this direction's part of the
 // residual (m components and J) to out.  The fluxes F(s-n, s) and the
 // dissipation of face s-1/2 come from the lanes that own them (lane shuffles).
-template <int DIM, int DIR, bool ES, bool MIXED>
+template <int DIM, int DIR, bool ES, bool MIXED, int PO>
 __device__ __forceinline__ void residual_segment(const GridDev& g, double G, double eps,
                                                  const double* __restrict__ prim,
                                                  const double* __restrict__ met,
@@ -481,7 +481,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
             for (int c = 0; c < NA; ++c) al[c] = sd[line][F_A + c][lane];
         }
 #pragma unroll
-        for (int n = 1; n <= 3; ++n) {
+        for (int n = 1; n <= PO; ++n) {
             double F[M + 1];
 #pragma unroll
             for (int c = 0; c <= M; ++c) F[c] = 0.0;
@@ -495,7 +495,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
             }
             // all lanes take part in the shuffle; owners (lane >= 3) read F(s-n, s)
 #pragma unroll
-            for (int c = 0; c <= M; ++c) R[c] += alpha3(n) * (F[c] - __shfl_up(F[c], n, 64));
+            for (int c = 0; c <= M; ++c) R[c] += alpha_pn(PO, n) * (F[c] - __shfl_up(F[c], n, 64));
             // one pair at a time (interleaving the three raises register pressure)
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -516,7 +516,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
             if (MIXED) {
                 // FP32 dissipation from FP32 copies of the stencil states and metrics
                 auto node_f = [&](int q) {
-                    const int k = lane - 2 + q;
+                    const int k = lane - (PO - 1) + q;
                     NodeRHD<NU, float> nd;
                     nd.rho = (float)sd[line][F_RHO][k];
                     nd.p = (float)sd[line][F_P][k];
@@ -535,14 +535,15 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
                     ar[c] = (float)sd[line][F_A + c][lane + 1];
                 }
                 float df[M];
-                face_diss_rhd_fn<DIM, float>((float)G, (float)eps, node_f, al, ar, df);
+                face_diss_rhd_fn<DIM, float, PO>((float)G, (float)eps, node_f, al, ar, df);
 #pragma unroll
                 for (int c = 0; c < M; ++c) d[c] = (double)df[c];
             } else {
                 double al[NA], ar[NA];
 #pragma unroll
                 for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane]; ar[c] = sd[line][F_A + c][lane + 1]; }
-                face_diss_rhd_fn<DIM, double>(G, eps, [&](int q) { return node_at(lane - 2 + q); }, al, ar, d);
+                face_diss_rhd_fn<DIM, double, PO>(G, eps, [&](int q) { return node_at(lane - (PO - 1) + q); }, al, ar,
+                                                  d);
             }
         }
 #pragma unroll
@@ -567,7 +568,7 @@ struct SweepPlan {
     long long nlines[3];  // lines of the sweep
 };
 
-template <int DIM, bool ES, bool MIXED>
+template <int DIM, bool ES, bool MIXED, int PO>
 __global__ void __launch_bounds__(256) k_residual_rhd(GridDev g, double G, double eps,
                                                       const double* __restrict__ prim,
                                                       const double* __restrict__ met,
@@ -577,17 +578,17 @@ __global__ void __launch_bounds__(256) k_residual_rhd(GridDev g, double G, doubl
     const long long slab = (long long)(M + 1) * g.nodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < sw.nblk[0]) {
-        residual_segment<DIM, 0, ES, MIXED>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
+        residual_segment<DIM, 0, ES, MIXED, PO>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
         return;
     }
     b -= sw.nblk[0];
     if (DIM == 2 || b < sw.nblk[1]) {
-        residual_segment<DIM, 1, ES, MIXED>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
+        residual_segment<DIM, 1, ES, MIXED, PO>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
         return;
     }
     b -= sw.nblk[1];
     if (DIM == 3)
-        residual_segment<DIM, 2, ES, MIXED>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
+        residual_segment<DIM, 2, ES, MIXED, PO>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
 }
 
 // dU = sum_k Ld_k (components 0..m-1), dJ = sum_k Ld_k (component m), summed in
@@ -753,7 +754,7 @@ __global__ void __launch_bounds__(MTX * CBY) k_cfl_partial2d_mesh(GridDev g, dou
             double s = 0.0, r = 0.0;
 #pragma unroll
             for (int n = 1; n <= 3; ++n) {
-                const double a = 0.5 * alpha3(n);
+                const double a = 0.5 * alpha_pn(g.p, n);
                 s += a * (xs[c][rj][ri + n] - xs[c][rj][ri - n]);
                 r += a * (xs[c][rj + n][ri] - xs[c][rj - n][ri]);
             }
@@ -1406,6 +1407,15 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
     return hipGetLastError();
 }
 
+template <int DIM, int PO>
+static void residual_launch(bool es_, bool mixed, unsigned nb, hipStream_t s, const GridDev& g, double G,
+                            double eps, const double* prim, const double* met, double* Ld, const SweepPlan& sw) {
+    if (es_ && mixed) k_residual_rhd<DIM, true, true, PO><<<nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else if (es_) k_residual_rhd<DIM, true, false, PO><<<nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else if (mixed) k_residual_rhd<DIM, false, true, PO><<<nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else k_residual_rhd<DIM, false, false, PO><<<nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+}
+
 template <int DIM>
 static void residual_all(const es_ctx* c, const double* prim, const double* met, double* Ld,
                          hipStream_t s) {
@@ -1423,14 +1433,8 @@ static void residual_all(const es_ctx* c, const double* prim, const double* met,
     }
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
     const bool es_ = c->scheme.dissipation != 0, mixed = c->scheme.mixed != 0;
-    if (es_ && mixed)
-        k_residual_rhd<DIM, true, true><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
-    else if (es_)
-        k_residual_rhd<DIM, true, false><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
-    else if (mixed)
-        k_residual_rhd<DIM, false, true><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
-    else
-        k_residual_rhd<DIM, false, false><<<(unsigned)nb, 256, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    if (g.p == 2) residual_launch<DIM, 2>(es_, mixed, (unsigned)nb, s, g, G, eps, prim, met, Ld, sw);
+    else residual_launch<DIM, 3>(es_, mixed, (unsigned)nb, s, g, G, eps, prim, met, Ld, sw);
 }
 
 hipError_t launch_residual_dirs(const es_ctx* c, const double* prim, const double* met, double* Ld,

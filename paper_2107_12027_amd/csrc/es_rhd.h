@@ -281,6 +281,26 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
     return (w0 * q0 + w1 * q1 + w2 * q2) * frcp(R(6.0) * (w0 + w1 + w2));
 }
 
+// WENO3-JS value at i+1/2 from v_{i-1..i+1} = (a, b, c): candidates (3b - a)/2 and
+// (b + c)/2, linear weights 1/3 and 2/3, smoothness indicators (b - a)^2 and
+// (c - b)^2; in FP64 over a common denominator as weno5.
+template <typename R>
+__device__ __forceinline__ R weno3(R a, R b, R c, R eps) {
+    const R q0 = R(3.0) * b - a;          // 2 x candidate values
+    const R q1 = b + c;
+    const R e0 = eps + (b - a) * (b - a), e1 = eps + (c - b) * (c - b);
+    const R f0 = e0 * e0, f1 = e1 * e1;
+    R w0, w1;
+    if (RealTraits<R>::wide_range) {
+        w0 = R(1.0 / 3.0) * f1;
+        w1 = R(2.0 / 3.0) * f0;
+    } else {
+        w0 = R(1.0 / 3.0) * frcp(f0);
+        w1 = R(2.0 / 3.0) * frcp(f1);
+    }
+    return (w0 * q0 + w1 * q1) * frcp(R(2.0) * (w0 + w1));
+}
+
 // Face state in the rotated frame with the reciprocals the tangent map reuses.
 template <int DIM, typename R = double>
 struct FaceRHD {
@@ -531,13 +551,15 @@ __device__ __forceinline__ R face_eigen_columns(R G, const R* V2, const R* V3, R
 //    jump [V~_l] below Y_TOL |r_l|_1 (|T V_i|_max + |T V_i+1|_max) counted as
 //    zero (sign(0) at rounding level).
 //
-// The stencil states come from node(j), j = 0..5 (nodes i-2..i+3).  The face
-// eigen-structure is formed first from nodes i and i+1 alone; the six rotated
-// entropy vectors are formed afterwards and projected onto the columns at once,
-// so that they are not held while the eigen-structure is built (register use).
-template <int DIM, typename R, typename NodeFn>
+// The stencil states come from node(j), j = 0..2P-1 (nodes i-P+1..i+P; WENO of
+// order w = 2P - 1: WENO5 for P = 3, WENO3 for P = 2).  The face eigen-structure
+// is formed first from nodes i and i+1 alone; the rotated entropy vectors of the
+// stencil are formed afterwards and projected onto the columns at once, so that
+// they are not held while the eigen-structure is built (register use).
+template <int DIM, typename R, int P = 3, typename NodeFn>
 __device__ __forceinline__ void face_diss_rhd_fn(R G, R eps, NodeFn&& node, const R* al, const R* ar, R* d) {
     constexpr int M = DIM + 2;
+    constexpr int NS = 2 * P, CI = P - 1;    // stencil size, index of node i
     const R at = R(0.5) * (al[0] + ar[0]);
     R ax[3] = {R(0.0), R(0.0), R(0.0)};
 #pragma unroll
@@ -562,9 +584,9 @@ __device__ __forceinline__ void face_diss_rhd_fn(R G, R eps, NodeFn&& node, cons
         }
         out[M - 1] = -q.beta * q.W;
     };
-    R TV2[M], TV3[M];
-    tv(2, TV2);
-    tv(3, TV3);
+    R TV2[M], TV3[M];      // nodes i and i+1
+    tv(CI, TV2);
+    tv(CI + 1, TV3);
     // rounding scale of the projections r . T V at nodes i and i+1
     R tv2 = R(0.0), tv3 = R(0.0);
 #pragma unroll
@@ -582,14 +604,14 @@ __device__ __forceinline__ void face_diss_rhd_fn(R G, R eps, NodeFn&& node, cons
 #ifndef ES_OPCOUNT_HOST
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #endif
-    R vt[M][6];
+    R vt[M][NS];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
+    for (int j = 0; j < NS; ++j) {
         R TVj[M];
-        if (j == 2) {
+        if (j == CI) {
 #pragma unroll
             for (int c = 0; c < M; ++c) TVj[c] = TV2[c];
-        } else if (j == 3) {
+        } else if (j == CI + 1) {
 #pragma unroll
             for (int c = 0; c < M; ++c) TVj[c] = TV3[c];
         } else {
@@ -614,10 +636,16 @@ __device__ __forceinline__ void face_diss_rhd_fn(R G, R eps, NodeFn&& node, cons
 #pragma unroll
     for (int q = 0; q < M; ++q) {
         const R* r = Rm[q];
-        const R vm = weno5(vt[q][0], vt[q][1], vt[q][2], vt[q][3], vt[q][4], eps);
-        const R vp = weno5(vt[q][5], vt[q][4], vt[q][3], vt[q][2], vt[q][1], eps);
+        R vm, vp;
+        if (P == 3) {
+            vm = weno5(vt[q][0], vt[q][1], vt[q][2], vt[q][3], vt[q][4], eps);
+            vp = weno5(vt[q][5], vt[q][4], vt[q][3], vt[q][2], vt[q][1], eps);
+        } else {
+            vm = weno3(vt[q][0], vt[q][1], vt[q][2], eps);
+            vp = weno3(vt[q][3], vt[q][2], vt[q][1], eps);
+        }
         const R jw = vp - vm;
-        const R jp = vt[q][3] - vt[q][2];
+        const R jp = vt[q][CI + 1] - vt[q][CI];
         // a jump within rounding of zero counts as zero (Y = 0)
         R r1 = R(0.0);
 #pragma unroll

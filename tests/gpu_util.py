@@ -44,7 +44,7 @@ class Case:
 
     def __init__(self, dim, n, bc, phys=ph.RHD, seed=0, smooth=False, amp=0.03, vmax=0.9,
                  moving=True, dissipation=1, monitor=None, rho_rng=(0.1, 1.0), p_rng=(0.1, 1.0),
-                 mixed=0, uniform=False):
+                 mixed=0, uniform=False, p=3):
         rng = np.random.default_rng(seed)
         self.grid = wl.make_grid(dim, n, bc)
         self.x = wl.perturbed_mesh(self.grid, rng, amp=amp)
@@ -61,14 +61,14 @@ class Case:
             pr = wl.random_prim(self.grid.shape, rng, phys=phys, dim=dim, vmax=vmax,
                                 rho_rng=rho_rng, p_rng=p_rng)
         self.P = full_P(pr)
-        self.scheme = wl.Scheme(phys=phys, dissipation=dissipation, mixed=mixed)
+        self.scheme = wl.Scheme(phys=phys, dissipation=dissipation, mixed=mixed, order_p=p)
         self.monitor = monitor if monitor is not None else wl.Monitor(enabled=0)
         self.ctx = es.Context(self.grid, self.scheme, self.monitor)
         self.dim, self.phys = dim, phys
         self.m = self.ctx.m
 
     def oracle_state(self):
-        J = mt.jacobian(self.grid, self.x)
+        J = mt.jacobian(self.grid, self.x, self.scheme.order_p)
         U = st.cons_from_prim(self.grid, self.scheme, self.P, J)
         return U, J
 
@@ -88,7 +88,7 @@ class Case:
     def oracle_residual(self):
         Uo, Jo = self.oracle_state()
         Po, _ = st.prim_from_cons(self.grid, self.scheme, Uo, Jo)
-        meto = mt.metrics(self.grid, self.x, self.xdot)
+        meto = mt.metrics(self.grid, self.x, self.xdot, self.scheme.order_p)
         return rs.residual(self.grid, self.scheme, st.pad_solution(self.grid, Po), meto)
 
     def gpu_state(self):

@@ -58,8 +58,8 @@ def _create(grid, scheme, monitor):
     (lambda g, s, m: setattr(s, "cfl", 0.0), es.ES_EINVAL),
     (lambda g, s, m: setattr(s, "dissipation", 2), es.ES_EINVAL),
     (lambda g, s, m: setattr(m, "form", 7), es.ES_EINVAL),
-    (lambda g, s, m: setattr(s, "order_p", 2), es.ES_EUNSUPPORTED),
     (lambda g, s, m: setattr(s, "order_p", 4), es.ES_EUNSUPPORTED),
+    (lambda g, s, m: (setattr(s, "order_p", 2), setattr(s, "phys", 1)), es.ES_EUNSUPPORTED),
     (lambda g, s, m: setattr(s, "phys", 2), es.ES_EINVAL),
 ])
 def test_create_rejects_bad_options_before_device_work(mutate, expect):
