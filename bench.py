@@ -178,6 +178,8 @@ def adjoint_timing(w, steps, fwd_ms):
     """Forward steps with checkpoints, then their vector-Jacobian products in
     reverse order (es_rk3_step_save / es_rk3_step_vjp), timed with HIP events."""
     import torch
+    if steps <= 0:
+        return None
     run = Run(w, 0)
     ctx = run.ctx
     ck = [torch.empty(ctx.ckpt_doubles(), dtype=torch.float64, device="cuda") for _ in range(steps)]
@@ -205,6 +207,77 @@ def adjoint_timing(w, steps, fwd_ms):
     return {"steps": steps, "forward_ms_per_step": fwd_ms, "forward_with_checkpoint_ms_per_step": save_ms,
             "vjp_ms_per_step": vjp_ms, "adjoint_over_forward": vjp_ms / fwd_ms,
             "note": "VJP of es_rk3_step with the mesh trajectory and dt held fixed; FP64"}
+
+
+def fourier_gradient(n=256, steps=100, h=1e-6, eps=0.05):
+    """Gradient of L = integral of rho^2 over [0.4,0.6]^2 after `steps` steps with
+    respect to the 8 density-mode coefficients of the Fourier-mode workload (2D RHD
+    counterpart of the adjoint configuration; static periodic mesh, the time step
+    fixed at the CFL step of the initial state): forward with per-step checkpoints,
+    the adjoint chain in reverse, and central differences of the forward (h) for
+    every coefficient.  Timed with HIP events (forward with checkpoints, reverse)."""
+    import numpy as np
+    import torch
+    from paper_2107_12027_amd import es, losses, workloads as wl
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    _, _, c0 = wl.fourier_modes(0)
+
+    def start(c):
+        w = wl.rhd_fourier(n=n, coeffs=c)
+        run = Run(w, 0)
+        xs = w.x
+        inside = (xs[0] >= 0.4) & (xs[0] <= 0.6) & (xs[1] >= 0.4) & (xs[1] <= 0.6)
+        return w, run, dev(inside * (1.0 / (n * n)))
+
+    w, run, weight = start(c0)
+    ctx = run.ctx
+    ctx.cfl(*_cfl_inputs(run), run.dt)
+    fixed = run.dt.clone()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ck = [torch.empty(ctx.ckpt_doubles(), dtype=torch.float64, device="cuda") for _ in range(steps)]
+    J0 = run.J.clone()
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(steps):
+        ctx.rk3_step_save(run.U, run.J, run.x, run.xdot, run.dt, ck[k], fixed)
+    ev[1].record(stream)
+    L, gU, gJ = losses.density_squared(ctx, run.U, run.J, weight)
+    ev[2].record(stream)
+    oU, oJ = torch.empty_like(gU), torch.empty_like(gJ)
+    for k in reversed(range(steps)):
+        ctx.rk3_step_vjp(ck[k], gU, gJ, oU, oJ)
+        gU, oU = oU, gU
+        gJ, oJ = oJ, gJ
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    P0 = dev(np.stack([w.prim["rho"], w.prim["u"][0], w.prim["u"][1], w.prim["p"]]))
+    tang = losses.density_mode_tangents(ctx, P0, J0, dev(wl.fourier_basis(w.x)), eps)
+    grad = (tang * gU[None]).sum(dim=(1, 2, 3)).cpu().numpy()
+    del ck
+
+    def loss(c):
+        _, r, wt = start(c)
+        for _ in range(steps):
+            r.ctx.rk3_step(r.U, r.J, r.x, r.xdot, r.dt, fixed)
+        return float(losses.density_squared(r.ctx, r.U, r.J, wt)[0])
+
+    fd = np.array([(loss(c0 + h * e) - loss(c0 - h * e)) / (2 * h) for e in np.eye(8)])
+    fwd_ms = ev[0].elapsed_time(ev[1]) / steps
+    rev_ms = ev[2].elapsed_time(ev[3]) / steps
+    return {"workload": w.name + " (RHD counterpart of the RMHD adjoint configuration)",
+            "steps": steps, "loss": float(L), "grad": grad.tolist(), "fd_grad": fd.tolist(), "fd_h": h,
+            "max_rel_diff_vs_fd": float(np.max(np.abs(grad - fd)) / np.max(np.abs(fd))),
+            "forward_with_checkpoint_ms_per_step": fwd_ms, "vjp_ms_per_step": rev_ms,
+            "adjoint_over_forward": rev_ms / fwd_ms,
+            "note": "static mesh, dt fixed at the CFL step of the initial state; FP64"}
+
+
+def _cfl_inputs(run):
+    """prim, met, J of the run's current state for es_cfl."""
+    run.ctx.con2prim(run.U, run.J, run.prim)
+    run.ctx.metrics(run.x, None, run.met)
+    return run.prim, run.met, run.J
 
 
 RESIDUAL_FLOPS_PER_NODE_3D_RHD = 8313.0   # same count, 3 directions (2771.0 each)
@@ -348,6 +421,7 @@ def main():
     t_mixed_ms = mrun.timed(args.steps, args.warmup)
     res_mixed_ms = mrun.residual_ms(args.residual_reps)
     adjoint = adjoint_timing(w, args.adjoint_steps, t_ms / args.steps)
+    adjoint_fourier = fourier_gradient() if args.adjoint_steps > 0 else None
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 8
@@ -395,6 +469,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "adjoint": adjoint,
+        "adjoint_fourier": adjoint_fourier,
     }
     print(json.dumps(line))
 

@@ -257,6 +257,34 @@ def fourier_modes(seed: int = 0, nmodes: int = 8):
     return kl, theta, c
 
 
+def fourier_basis(x: np.ndarray, seed: int = 0) -> np.ndarray:
+    """The 8 density modes phi_m = (1/8) cos(2 pi (k_m x + l_m y) + theta_m) on the
+    mesh x, shape (8, *shape): rho = 1 + eps sum_m c_m phi_m."""
+    kl, theta, c = fourier_modes(seed)
+    return np.stack([np.cos(2 * np.pi * (kl[m, 0] * x[0] + kl[m, 1] * x[1]) + theta[m]) / len(c)
+                     for m in range(len(c))])
+
+
+def rhd_fourier(n: int = 256, seed: int = 0, steps: int = 100, eps: float = 0.05,
+                coeffs: Optional[np.ndarray] = None) -> Workload:
+    """The RHD counterpart of rmhd_fourier (B = 0): 2D RHD, periodic [0,1)^2,
+    static mesh, rho = 1 + eps f(x, y) from the same 8 seeded modes, p = 1,
+    v = (0.3, 0.2)."""
+    g = make_grid(2, (n, n, 1), (PERIODIC, PERIODIC, PERIODIC))
+    x = uniform_mesh(g)
+    _, _, c = fourier_modes(seed)
+    if coeffs is not None:
+        c = np.asarray(coeffs, dtype=np.float64)
+    rho = 1.0 + eps * np.tensordot(c, fourier_basis(x, seed), axes=1)
+    v = np.zeros((3,) + g.shape)
+    v[0] = 0.3
+    v[1] = 0.2
+    p = np.ones(g.shape)
+    B = np.zeros((3,) + g.shape)
+    return Workload("rhd2d_fourier_%d" % n, g, Scheme(phys=RHD, cfl=0.4),
+                    Monitor(enabled=0), _prim(rho, v, p, B), x, steps=steps)
+
+
 def rmhd_fourier(n: int = 256, seed: int = 0, steps: int = 100, eps: float = 0.05,
                  coeffs: Optional[np.ndarray] = None) -> Workload:
     """2D RMHD, periodic [0,1)^2, static mesh: rho = 1 + eps f(x, y) with

@@ -161,3 +161,76 @@ def test_autograd_function_two_steps():
     adj = float((gU * v).sum())
     assert abs(adj - float(fd)) <= 1e-7 * abs(float(fd)), (adj, float(fd))
     assert torch.isfinite(gJ).all()
+
+
+def _fourier_forward(n, steps, coeffs, dt, ckpts=None):
+    """GPU forward of the RHD Fourier-mode workload with a fixed time step; returns
+    (ctx, U, J, prim0 interior, mask weight) after `steps` steps."""
+    from paper_2107_12027_amd import losses
+    w = wl.rhd_fourier(n=n, coeffs=coeffs)
+    ctx = es.Context(w.grid, w.scheme, w.monitor)
+    U, J, x = _gpu_state(w, ctx)
+    P0 = dev(np.stack([w.prim["rho"], w.prim["u"][0], w.prim["u"][1], w.prim["p"]]))
+    xd = empty(2, *ctx.shape())
+    dtv = empty(1)
+    fixed = dev(np.array([dt]))
+    for k in range(steps):
+        if ckpts is not None:
+            ck = empty(ctx.ckpt_doubles())
+            ctx.rk3_step_save(U, J, x, xd, dtv, ck, fixed)
+            ckpts.append(ck)
+        else:
+            ctx.rk3_step(U, J, x, xd, dtv, fixed)
+    xs = w.x
+    inside = (xs[0] >= 0.4) & (xs[0] <= 0.6) & (xs[1] >= 0.4) & (xs[1] <= 0.6)
+    weight = dev(inside * (1.0 / (n * n)))
+    return ctx, U, J, P0, weight, losses
+
+
+def test_fourier_mode_gradient_against_differences():
+    # the gradient of L = integral of rho^2 over [0.4,0.6]^2 after K steps with
+    # respect to the 8 density-mode coefficients (RHD counterpart of the Fourier
+    # workload, static mesh, fixed dt): adjoint chain (es_rk3_step_save /
+    # es_rk3_step_vjp, con2prim by the implicit-function rule at both ends) against
+    # central differences h = 1e-6 of the GPU forward and, for two coefficients, of
+    # the oracle's forward
+    n, K, dt, h = 32, 4, 6.25e-3, 1e-6
+    _, _, c0 = wl.fourier_modes(0)
+    ck = []
+    ctx, U, J, P0, weight, losses = _fourier_forward(n, K, c0, dt, ck)
+    L, gU, gJ = losses.density_squared(ctx, U, J, weight)
+    for k in reversed(range(K)):
+        oU, oJ = empty(*gU.shape), empty(*gJ.shape)
+        ctx.rk3_step_vjp(ck[k], gU, gJ, oU, oJ)
+        gU, gJ = oU, oJ
+    w0 = wl.rhd_fourier(n=n, coeffs=c0)
+    J0 = dev(mt.jacobian(w0.grid, w0.x))
+    phi = dev(wl.fourier_basis(w0.x))
+    tang = losses.density_mode_tangents(ctx, P0, J0, phi, 0.05)
+    grad = (tang * gU[None]).sum(dim=(1, 2, 3)).cpu().numpy()
+
+    def loss_gpu(c):
+        cx, Ux, Jx, _, wx, _ = _fourier_forward(n, K, c, dt)
+        return float(losses.density_squared(cx, Ux, Jx, wx)[0])
+
+    fd = np.array([(loss_gpu(c0 + h * e) - loss_gpu(c0 - h * e)) / (2 * h) for e in np.eye(8)])
+    scale = np.max(np.abs(fd))
+    assert np.max(np.abs(grad - fd)) <= 1e-6 * scale, (grad, fd)
+
+    # the oracle's forward (same inputs, prescribed zero mesh velocity and the same dt)
+    def loss_oracle(c):
+        wx = wl.rhd_fourier(n=n, coeffs=c)
+        Px = ph.full_prim(wx.prim["rho"], wx.prim["u"], wx.prim["p"], wx.prim["B"])
+        Uo, Jo = st.initial_state(wx.grid, wx.scheme, Px, wx.x)
+        xo = wx.x
+        for _ in range(K):
+            out = st.rk3_step(wx.grid, wx.scheme, None, Uo, Jo, xo, dt=dt, xdot=np.zeros_like(xo))
+            Uo, Jo, xo = out["U"], out["J"], out["x"]
+        Po, ok = st.prim_from_cons(wx.grid, wx.scheme, Uo, Jo)
+        assert ok.all()
+        return float(np.sum(host(weight) * Po[0] ** 2))
+
+    for m in (0, 5):
+        e = np.eye(8)[m]
+        fo = (loss_oracle(c0 + h * e) - loss_oracle(c0 - h * e)) / (2 * h)
+        assert abs(grad[m] - fo) <= 1e-6 * scale, (m, grad[m], fo)
