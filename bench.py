@@ -209,21 +209,23 @@ def adjoint_timing(w, steps, fwd_ms):
             "note": "VJP of es_rk3_step with the mesh trajectory and dt held fixed; FP64"}
 
 
-def fourier_gradient(n=256, steps=100, h=1e-6, eps=0.05):
+def fourier_gradient(n=256, steps=100, h=1e-6, eps=0.05, rmhd=True):
     """Gradient of L = integral of rho^2 over [0.4,0.6]^2 after `steps` steps with
-    respect to the 8 density-mode coefficients of the Fourier-mode workload (2D RHD
-    counterpart of the adjoint configuration; static periodic mesh, the time step
-    fixed at the CFL step of the initial state): forward with per-step checkpoints,
-    the adjoint chain in reverse, and central differences of the forward (h) for
-    every coefficient.  Timed with HIP events (forward with checkpoints, reverse)."""
+    respect to the 8 density-mode coefficients of the Fourier-mode workload (the
+    adjoint configuration: 2D RMHD; rmhd=False: its RHD counterpart; static
+    periodic mesh, the time step fixed at the CFL step of the initial state):
+    forward with per-step checkpoints, the adjoint chain in reverse, and central
+    differences of the forward (h) for every coefficient.  Timed with HIP events
+    (forward with checkpoints, reverse)."""
     import numpy as np
     import torch
     from paper_2107_12027_amd import es, losses, workloads as wl
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
     _, _, c0 = wl.fourier_modes(0)
+    make = wl.rmhd_fourier if rmhd else wl.rhd_fourier
 
     def start(c):
-        w = wl.rhd_fourier(n=n, coeffs=c)
+        w = make(n=n, coeffs=c)
         run = Run(w, 0)
         xs = w.x
         inside = (xs[0] >= 0.4) & (xs[0] <= 0.6) & (xs[1] >= 0.4) & (xs[1] <= 0.6)
@@ -251,7 +253,10 @@ def fourier_gradient(n=256, steps=100, h=1e-6, eps=0.05):
         gJ, oJ = oJ, gJ
     ev[3].record(stream)
     torch.cuda.synchronize()
-    P0 = dev(np.stack([w.prim["rho"], w.prim["u"][0], w.prim["u"][1], w.prim["p"]]))
+    if rmhd:
+        P0 = dev(np.concatenate([w.prim["rho"][None], w.prim["u"], w.prim["p"][None], w.prim["B"]]))
+    else:
+        P0 = dev(np.stack([w.prim["rho"], w.prim["u"][0], w.prim["u"][1], w.prim["p"]]))
     tang = losses.density_mode_tangents(ctx, P0, J0, dev(wl.fourier_basis(w.x)), eps)
     grad = (tang * gU[None]).sum(dim=(1, 2, 3)).cpu().numpy()
     del ck
@@ -265,12 +270,13 @@ def fourier_gradient(n=256, steps=100, h=1e-6, eps=0.05):
     fd = np.array([(loss(c0 + h * e) - loss(c0 - h * e)) / (2 * h) for e in np.eye(8)])
     fwd_ms = ev[0].elapsed_time(ev[1]) / steps
     rev_ms = ev[2].elapsed_time(ev[3]) / steps
-    return {"workload": w.name + " (RHD counterpart of the RMHD adjoint configuration)",
+    return {"workload": w.name + ("" if rmhd else " (RHD counterpart of the RMHD configuration)"),
             "steps": steps, "loss": float(L), "grad": grad.tolist(), "fd_grad": fd.tolist(), "fd_h": h,
             "max_rel_diff_vs_fd": float(np.max(np.abs(grad - fd)) / np.max(np.abs(fd))),
             "forward_with_checkpoint_ms_per_step": fwd_ms, "vjp_ms_per_step": rev_ms,
             "adjoint_over_forward": rev_ms / fwd_ms,
-            "note": "static mesh, dt fixed at the CFL step of the initial state; FP64"}
+            "note": "static mesh, dt fixed at the CFL step of the initial state; FP64" +
+                    ("; the adjoint holds the face eigen-structure of the ES dissipation" if rmhd else "")}
 
 
 def _cfl_inputs(run):
@@ -421,7 +427,8 @@ def main():
     t_mixed_ms = mrun.timed(args.steps, args.warmup)
     res_mixed_ms = mrun.residual_ms(args.residual_reps)
     adjoint = adjoint_timing(w, args.adjoint_steps, t_ms / args.steps)
-    adjoint_fourier = fourier_gradient() if args.adjoint_steps > 0 else None
+    adjoint_fourier = fourier_gradient(rmhd=True) if args.adjoint_steps > 0 else None
+    adjoint_fourier_rhd = fourier_gradient(rmhd=False) if args.adjoint_steps > 0 else None
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 8
@@ -470,6 +477,7 @@ def main():
         "mixed": mixed,
         "adjoint": adjoint,
         "adjoint_fourier": adjoint_fourier,
+        "adjoint_fourier_rhd": adjoint_fourier_rhd,
     }
     print(json.dumps(line))
 

@@ -170,8 +170,11 @@ es_status es_mesh_redistribute(es_ctx* ctx, const double* prim, const double* x,
 es_status es_rk3_step(es_ctx* ctx, double* Ucurv, double* J, double* x, double* xdot,
                       double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
 
-/* Adjoint (RHD, p = 3, FP64 form only; ES_EUNSUPPORTED for scheme.mixed = 1, RMHD
- * or p = 2).  The
+/* Adjoint (p = 3, FP64 form only; ES_EUNSUPPORTED for scheme.mixed = 1 or p = 2).
+ * For RMHD the ES dissipation's face eigen-structure (the columns of R and
+ * lambda^) is held at its forward value as well: the pair fluxes, the
+ * Godunov-Powell source and the projections/WENO/accumulation of the dissipation
+ * are differentiated, the numeric eigen-decomposition is not.  The
  * derivatives are those of the step with the mesh trajectory (x^n, xdot), the
  * time step dt and every branch decision (the sign switch Y of eq. ESFlux_HO,
  * the maximum in lambda^, the log-mean series branch) held at their forward

@@ -273,13 +273,15 @@ def weno_minus(vs, eps):
     raise ValueError("WENO order %d is not implemented" % len(vs))
 
 
-def face_dissipation(Pst, ast, G, phys, dim, eps, details=False, Y_fixed=None):
+def face_dissipation(Pst, ast, G, phys, dim, eps, details=False, Y_fixed=None, eig_fixed=None):
     """ES dissipation vector d = D Y <<V~>> at faces.
     Pst: (2p, 8, N) full primitive states of the stencil nodes i-p+1..i+p of each
     face (p = 3: WENO5 on i-2..i+3; p = 2: WENO3 on i-1..i+2, w = 2p - 1);
     ast: (2, d+1, N) metric vectors of nodes i and i+1.
     Y_fixed: optional (m, N) sign-switch values to use instead of evaluating Y
     (the switch held fixed, for difference quotients of the smooth part).
+    eig_fixed: optional (R, lhat) of an earlier call, used instead of the face
+    eigen-structure (held fixed for the same purpose).
     Returns the full 8-slot d (8, N) (zeros in unused slots)."""
     sel = ph.comps(phys, dim)
     m = len(sel)
@@ -300,6 +302,8 @@ def face_dissipation(Pst, ast, G, phys, dim, eps, details=False, Y_fixed=None):
     Pr = rotate_full(Pbar, T0, slots)
     lam, R = eigensystem(Pr, G, phys, dim)
     lhat = np.max(np.abs(abar[0][:, None] + L[:, None] * lam), axis=1)
+    if eig_fixed is not None:
+        R, lhat = eig_fixed
     Vt = []
     for j in range(ns):
         Vj = rotate_full(ph.entropy_vars(Pst[j], G), T0, slots)[sel]   # (m, N)

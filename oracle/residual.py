@@ -33,11 +33,13 @@ def _take(a, idx, ax):
     return np.take(a, idx, axis=ax)
 
 
-def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None):
+def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None, eig_fixed=None):
     """Returns (dU (m, *shape), dJ (*shape)) on the interior nodes, optionally with
     per-direction face fluxes and sign switches.  Y_fixed: optional {direction:
     Y (m, faces)} from an earlier call with details, used instead of evaluating
-    the switch."""
+    the switch.  eig_fixed: optional {direction: (R, lhat)} from an earlier call
+    with details, used instead of the face eigen-structure (both for difference
+    quotients with the decisions and the eigen-structure held)."""
     d = grid.dim
     G = scheme.gamma
     phys = scheme.phys
@@ -76,9 +78,11 @@ def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None):
             Pst = Pst.reshape(2 * p, 8, -1)
             ast = ast.reshape(2, d + 1, -1)
             dd, dinfo = ds.face_dissipation(Pst, ast, G, phys, d, scheme.weno_eps, details=True,
-                                            Y_fixed=None if Y_fixed is None else Y_fixed[k])
+                                            Y_fixed=None if Y_fixed is None else Y_fixed[k],
+                                            eig_fixed=None if eig_fixed is None else eig_fixed[k])
             Ff = Ff - 0.5 * dd.reshape((8,) + fshape)
             Yk = dinfo["Y"]
+            eigk = (dinfo["R"], dinfo["lhat"])
         hi = np.arange(1, nk + 1)
         lo = np.arange(0, nk)
         dxi = grid.dxi[k]
@@ -87,7 +91,8 @@ def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None):
         if phys == ph.RMHD:
             src += (_take(Bf, hi, ax_sp) - _take(Bf, lo, ax_sp)) / dxi
         if details:
-            info[k] = dict(F=Ff, J=Jf, B=Bf, Y=Yk if scheme.dissipation else None)
+            info[k] = dict(F=Ff, J=Jf, B=Bf, Y=Yk if scheme.dissipation else None,
+                           eig=eigk if scheme.dissipation else None)
     if phys == ph.RMHD:
         Pin = interior(Ppad, grid)
         dU -= ph.phi_prime(Pin, G) * src

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libes.so")
 ARCH = "gfx950"
 
-SOURCES = ["es_api.hip", "es_kernels.hip", "es_kernels_rmhd.hip", "es_adjoint.hip"]
+SOURCES = ["es_api.hip", "es_kernels.hip", "es_kernels_rmhd.hip", "es_adjoint.hip", "es_adjoint_rmhd.hip"]
 HEADERS = ["es_common.h", "es_internal.h", "es_rhd.h"]
 
 

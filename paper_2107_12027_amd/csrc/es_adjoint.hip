@@ -708,6 +708,7 @@ hipError_t launch_state_residual_vjp(const es_ctx* c, const double* U, const dou
                                      hipStream_t s) {
     hipError_t e = launch_con2prim(c, U, J, c->prim, 0, s);
     if (e != hipSuccess) return e;
+    if (c->scheme.phys == ES_RMHD) return launch_residual_fold_vjp_rmhd(c, U, J, met, lam, gU, gJ, s);
     if (c->g.dim == 2) residual_vjp_all<2>(c, c->prim, met, lam, c->gdir, s);
     else residual_vjp_all<3>(c, c->prim, met, lam, c->gdir, s);
     const GridDev& g = c->g;

@@ -148,6 +148,9 @@ __device__ __forceinline__ Dual<K> fma(const Dual<K>& a, const Dual<K>& b, const
 template <int K> __device__ __forceinline__ Dual<K> fma(const Dual<K>& a, double b, double c) { return a * b + c; }
 template <int K> __device__ __forceinline__ Dual<K> fma(const Dual<K>& a, const Dual<K>& b, double c) { return a * b + c; }
 
+template <int K>
+__device__ __forceinline__ double value_of(const Dual<K>& x) { return x.v; }
+
 template <typename R>
 struct RealTraits;
 template <int K>

@@ -119,6 +119,10 @@ hipError_t launch_con2prim_rmhd(const es_ctx* c, const void* state_src, double* 
                                 hipStream_t s);
 hipError_t launch_residual_dirs_rmhd(const es_ctx* c, const double* prim, const double* met, double* Ld,
                                      hipStream_t s);
+// residual VJP of the RMHD system on c->prim (con2prim done by the caller), with
+// the ghost folding and the con2prim pull-back into (gU, gJ)
+hipError_t launch_residual_fold_vjp_rmhd(const es_ctx* c, const double* U, const double* J, const double* met,
+                                         const double* lam, double* gU, double* gJ, hipStream_t s);
 hipError_t launch_cfl_partial_rmhd(const es_ctx* c, const double* prim, const double* met,
                                    const double* J, hipStream_t s);
 hipError_t launch_diag_partial_rmhd(const es_ctx* c, const double* prim, const double* U, const double* J,

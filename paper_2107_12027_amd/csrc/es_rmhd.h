@@ -163,21 +163,27 @@ __device__ __forceinline__ int c2p_rmhd(double G, const double* U, double guess,
 }
 
 // Node data of the residual's line loads: primitive state, logarithms and the
-// derived quantities the pair flux averages.
-struct NodeRMHD {
-    double rho, p, beta, W, lr, lb, b0, Wb0, Wb02, sb, b02;
-    double u[3], B[3], b[3], Wbk2[3], bk2[3];
+// derived quantities the pair flux averages (R = double, or dual numbers for the
+// adjoint's local Jacobians).
+template <typename R = double>
+struct NodeRMHDT {
+    R rho, p, beta, W, lr, lb, b0, Wb0, Wb02, sb, b02;
+    R u[3], B[3], b[3], Wbk2[3], bk2[3];
 };
+using NodeRMHD = NodeRMHDT<double>;
 
-__device__ __forceinline__ NodeRMHD node_rmhd(double G, const double* P, double lr, double lb) {
-    const StateRMHD<double> s = rmhd_state<double>(G, P);
-    NodeRMHD n;
+__device__ __forceinline__ double value_of(double x) { return x; }
+
+template <typename R = double>
+__device__ __forceinline__ NodeRMHDT<R> node_rmhd(double G, const R* P, R lr, R lb) {
+    const StateRMHD<R> s = rmhd_state<R>(G, P);
+    NodeRMHDT<R> n;
     n.rho = s.rho; n.p = s.p; n.beta = s.beta; n.W = s.W; n.lr = lr; n.lb = lb;
     n.b0 = s.b0;
     n.Wb0 = s.W * s.b0;
     n.Wb02 = s.W * s.b0 * s.b0;
     n.b02 = s.b0 * s.b0;
-    double sb = 0.0;
+    R sb = R(0.0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         n.u[k] = s.u[k]; n.B[k] = s.B[k]; n.b[k] = s.b[k];
@@ -201,11 +207,16 @@ __device__ __forceinline__ NodeRMHD node_rmhd(double G, const double* P, double 
 // K_j = F~_j that are contracted with the metrics in FP64 (as the RHD mixed
 // form: equal states give equal coefficients, so the metric sums cancel in FP64);
 // B~ and a_t stay FP64.
-template <int DIM, typename R = double>
-__device__ __forceinline__ void pair_flux_rmhd(double G, const NodeRMHD& l, const NodeRMHD& r,
-                                               const double* al, const double* ar, double* F,
+// NR: the node type (double, or the dual numbers of the adjoint, then R = NR and
+// F holds dual numbers too).
+template <int DIM, typename R = double, typename NR = double>
+__device__ __forceinline__ void pair_flux_rmhd(double G, const NodeRMHDT<NR>& l, const NodeRMHDT<NR>& r,
+                                               const double* al, const double* ar,
+                                               typename std::conditional<std::is_same<R, float>::value, double,
+                                                                         R>::type* F,
                                                double& Jt, double& Bt) {
-    constexpr bool F32 = !std::is_same<R, double>::value;
+    constexpr bool F32 = std::is_same<R, float>::value;
+    using OT = typename std::conditional<F32, double, R>::type;
     R rho_ln, beta_ln;
     if constexpr (F32) {
         rho_ln = log_mean_mixed(l.rho, r.rho, l.lr, r.lr);
@@ -214,7 +225,7 @@ __device__ __forceinline__ void pair_flux_rmhd(double G, const NodeRMHD& l, cons
         rho_ln = log_mean(l.rho, r.rho, l.lr, r.lr);
         beta_ln = log_mean(l.beta, r.beta, l.lb, r.lb);
     }
-    auto mean = [](double a, double b) { return R(0.5) * (R(a) + R(b)); };
+    auto mean = [](const NR& a, const NR& b) { return R(0.5) * (R(a) + R(b)); };
     const R rho = mean(l.rho, r.rho), beta = mean(l.beta, r.beta);
     const R W = mean(l.W, r.W), b0 = mean(l.b0, r.b0);
     const R Wb0 = mean(l.Wb0, r.Wb0), Wb02 = mean(l.Wb02, r.Wb02);
@@ -268,13 +279,13 @@ __device__ __forceinline__ void pair_flux_rmhd(double G, const NodeRMHD& l, cons
     Ut[4] = U5;
     const double at = 0.5 * (al[0] + ar[0]);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) F[c] = at * (double)Ut[c];
+    for (int c = 0; c < 8; ++c) F[c] = at * OT(Ut[c]);
     double bt = 0.0;
     // F~_j for the directions of the grid
 #pragma unroll
     for (int j = 0; j < DIM; ++j) {
         const double aj = 0.5 * (al[1 + j] + ar[1 + j]);
-        bt += 0.25 * (al[1 + j] + ar[1 + j]) * (l.B[j] + r.B[j]);
+        bt += 0.25 * (al[1 + j] + ar[1 + j]) * (value_of(l.B[j]) + value_of(r.B[j]));
         const R c0 = -beta * (u[j] * b0 + B[j]);
         const R F1 = rho_ln * u[j];
         R FB[3], Pk[3], uP = R(0.0), bFB = R(0.0);
@@ -288,13 +299,13 @@ __device__ __forceinline__ void pair_flux_rmhd(double G, const NodeRMHD& l, cons
         for (int k = 0; k < 3; ++k) { uP += u[k] * Pk[k]; bFB += b[k] * FB[k]; }
         const R Q = R(0.5) * ujsb[j] - R(0.5) * ujb02[j] - B[j] * b0;
         const R F5 = W * (a0 * F1 + uP * ib + bFB - Q) * iden;
-        F[0] += aj * (double)F1;
+        F[0] += aj * OT(F1);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            F[1 + k] += aj * (double)(u[k] * F5 * iW + Pk[k] * ib);
-            F[5 + k] += aj * (double)FB[k];
+            F[1 + k] += aj * OT(u[k] * F5 * iW + Pk[k] * ib);
+            F[5 + k] += aj * OT(FB[k]);
         }
-        F[4] += aj * (double)F5;
+        F[4] += aj * OT(F5);
     }
     Jt = at;
     Bt = bt;
@@ -639,18 +650,14 @@ __device__ __forceinline__ void canonical_groups(const double* lam, const double
     }
 }
 
-// ES dissipation for RMHD at one face (eq. ESFlux_HO): as face_diss_rhd with
-// T = diag{1, T_0, 1, T_0}, the face state from the mean rotated entropy
-// variables (explicit inverse of V: beta^2 = V_5^2 - |V_2..4|^2, u = V_2..4/beta,
-// W = -V_5/beta, ln rho = V_1 - G/(G-1) - ln(beta)/(G-1) - beta, p = rho/beta,
-// b = V_6..8/beta, b^0 = u.b/W, B = W b - b^0 u), and R from the symmetric pencil
-// (A0, S) of the Godunov-Powell modified Jacobian, with the canonical basis in
-// every group of nearly equal eigenvalues (canonical_groups; the group of v_n
-// holds the entropy and div B waves and is seeded with e_D and e_{B_n}).
-// nodes: the 8 primitive slots of the stencil nodes i-2..i+3.
-template <int DIM, bool MIXED = false>
-__device__ __forceinline__ void face_diss_rmhd(double G, double eps, const double Pn[6][8],
-                                               const double* al, const double* ar, double* d) {
+// Face frame and eigen-structure of the RMHD dissipation at face i+1/2 (shared by
+// face_diss_rmhd and its adjoint): the rotation T of the face metric normal, the
+// rotated entropy variables TV2, TV3 of nodes i and i+1, lambda^ and the columns
+// Rc[k] = L z_k of R (z_k the canonical basis vector of position k).
+template <int DIM>
+__device__ __forceinline__ void face_eigen_rmhd(double G, const double* P2, const double* P3, const double* al,
+                                                const double* ar, double T[3][3], double* TV2, double* TV3,
+                                                double& lhat, double Rc[8][8]) {
     const double at = 0.5 * (al[0] + ar[0]);
     double ax[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -658,21 +665,18 @@ __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const doubl
     const double L = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
     const double iL = 1.0 / L;
     double nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
-    double T[3][3];
     rotation<3>(nrm, T);            // n_3 = 0 in 2D gives the 2D rotation
-
-    double TV[6][8];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const StateRMHD<double> s = rmhd_state<double>(G, Pn[j]);
+    for (int q = 0; q < 2; ++q) {
+        const StateRMHD<double> s = rmhd_state<double>(G, q == 0 ? P2 : P3);
         double V[8];
         rmhd_entropy_vars<double>(G, s, V);
-        rotate8<false>(T, V, TV[j]);
+        rotate8<false>(T, V, q == 0 ? TV2 : TV3);
     }
     // face state (rotated frame)
     double Vb[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) Vb[c] = 0.5 * (TV[2][c] + TV[3][c]);
+    for (int c = 0; c < 8; ++c) Vb[c] = 0.5 * (TV2[c] + TV3[c]);
     const double vu2 = Vb[1] * Vb[1] + Vb[2] * Vb[2] + Vb[3] * Vb[3];
     const double beta = sqrt(Vb[4] * Vb[4] - vu2);
     const double ib = 1.0 / beta;
@@ -694,13 +698,45 @@ __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const doubl
     rmhd_pencil(JU, JF, JV, Lc, Q);
     jacobi_eigen<8, true>(Q, Zv);
     double lam[8];
-    double lhat = 0.0;
+    lhat = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) { lam[k] = Q[k][k]; lhat = fmax(lhat, fabs(at + L * lam[k])); }
     // canonical basis in every group of (nearly) equal eigenvalues
     double canon[8][8];
     canonical_groups(lam, Zv, Lc, vn, canon);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double sum = 0.0;
+#pragma unroll
+            for (int kk = 0; kk <= i; ++kk) sum += Lc[i][kk] * canon[k][kk];
+            Rc[k][i] = sum;
+        }
+}
 
+// ES dissipation for RMHD at one face (eq. ESFlux_HO): as face_diss_rhd with
+// T = diag{1, T_0, 1, T_0}, the face state from the mean rotated entropy
+// variables (explicit inverse of V: beta^2 = V_5^2 - |V_2..4|^2, u = V_2..4/beta,
+// W = -V_5/beta, ln rho = V_1 - G/(G-1) - ln(beta)/(G-1) - beta, p = rho/beta,
+// b = V_6..8/beta, b^0 = u.b/W, B = W b - b^0 u), and R from the symmetric pencil
+// (A0, S) of the Godunov-Powell modified Jacobian, with the canonical basis in
+// every group of nearly equal eigenvalues (canonical_groups; the group of v_n
+// holds the entropy and div B waves and is seeded with e_D, e_{B_n}).
+// nodes: the 8 primitive slots of the stencil nodes i-2..i+3.
+template <int DIM, bool MIXED = false>
+__device__ __forceinline__ void face_diss_rmhd(double G, double eps, const double Pn[6][8],
+                                               const double* al, const double* ar, double* d) {
+    double T[3][3], TV[6][8], lhat, Rc[8][8];
+    face_eigen_rmhd<DIM>(G, Pn[2], Pn[3], al, ar, T, TV[2], TV[3], lhat, Rc);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        if (j == 2 || j == 3) continue;
+        const StateRMHD<double> s = rmhd_state<double>(G, Pn[j]);
+        double V[8];
+        rmhd_entropy_vars<double>(G, s, V);
+        rotate8<false>(T, V, TV[j]);
+    }
     double tv2 = 0.0, tv3 = 0.0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
@@ -718,15 +754,9 @@ __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const doubl
     for (int c = 0; c < 8; ++c) dd[c] = RW(0.0);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        // column r = L z with z the canonical basis vector of position k
         RW r[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int kk = 0; kk <= i; ++kk) s += Lc[i][kk] * canon[k][kk];
-            r[i] = (RW)s;
-        }
+        for (int i = 0; i < 8; ++i) r[i] = (RW)Rc[k][i];
         RW vt[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {

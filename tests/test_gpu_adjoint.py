@@ -163,14 +163,16 @@ def test_autograd_function_two_steps():
     assert torch.isfinite(gJ).all()
 
 
-def _fourier_forward(n, steps, coeffs, dt, ckpts=None):
-    """GPU forward of the RHD Fourier-mode workload with a fixed time step; returns
-    (ctx, U, J, prim0 interior, mask weight) after `steps` steps."""
+def _fourier_forward(n, steps, coeffs, dt, ckpts=None, phys=ph.RHD):
+    """GPU forward of the Fourier-mode workload (RHD, or RMHD as in the adjoint
+    configuration) with a fixed time step; returns (ctx, U, J, prim0 interior,
+    mask weight) after `steps` steps."""
     from paper_2107_12027_amd import losses
-    w = wl.rhd_fourier(n=n, coeffs=coeffs)
+    w = (wl.rhd_fourier if phys == ph.RHD else wl.rmhd_fourier)(n=n, coeffs=coeffs)
     ctx = es.Context(w.grid, w.scheme, w.monitor)
     U, J, x = _gpu_state(w, ctx)
-    P0 = dev(np.stack([w.prim["rho"], w.prim["u"][0], w.prim["u"][1], w.prim["p"]]))
+    Pfull = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    P0 = dev(Pfull[ph.comps(w.scheme.phys, 2)] if phys == ph.RHD else Pfull)
     xd = empty(2, *ctx.shape())
     dtv = empty(1)
     fixed = dev(np.array([dt]))
@@ -187,39 +189,42 @@ def _fourier_forward(n, steps, coeffs, dt, ckpts=None):
     return ctx, U, J, P0, weight, losses
 
 
-def test_fourier_mode_gradient_against_differences():
+@pytest.mark.parametrize("phys,K,tol", [(ph.RHD, 4, 1e-6), (ph.RMHD, 3, 1e-5)])
+def test_fourier_mode_gradient_against_differences(phys, K, tol):
     # the gradient of L = integral of rho^2 over [0.4,0.6]^2 after K steps with
-    # respect to the 8 density-mode coefficients (RHD counterpart of the Fourier
-    # workload, static mesh, fixed dt): adjoint chain (es_rk3_step_save /
-    # es_rk3_step_vjp, con2prim by the implicit-function rule at both ends) against
-    # central differences h = 1e-6 of the GPU forward and, for two coefficients, of
-    # the oracle's forward
-    n, K, dt, h = 32, 4, 6.25e-3, 1e-6
+    # respect to the 8 density-mode coefficients (the adjoint configuration's loss on
+    # its RMHD workload, and on the RHD counterpart; static mesh, fixed dt): adjoint
+    # chain (es_rk3_step_save / es_rk3_step_vjp, con2prim by the implicit-function
+    # rule at both ends) against central differences h = 1e-6 of the GPU forward and,
+    # for two coefficients, of the oracle's forward.  RMHD: the adjoint holds the face
+    # eigen-structure, whose variation multiplies the WENO jumps of this smooth flow
+    n, dt, h = 32, 6.25e-3, 1e-6
+    make = wl.rhd_fourier if phys == ph.RHD else wl.rmhd_fourier
     _, _, c0 = wl.fourier_modes(0)
     ck = []
-    ctx, U, J, P0, weight, losses = _fourier_forward(n, K, c0, dt, ck)
+    ctx, U, J, P0, weight, losses = _fourier_forward(n, K, c0, dt, ck, phys)
     L, gU, gJ = losses.density_squared(ctx, U, J, weight)
     for k in reversed(range(K)):
         oU, oJ = empty(*gU.shape), empty(*gJ.shape)
         ctx.rk3_step_vjp(ck[k], gU, gJ, oU, oJ)
         gU, gJ = oU, oJ
-    w0 = wl.rhd_fourier(n=n, coeffs=c0)
+    w0 = make(n=n, coeffs=c0)
     J0 = dev(mt.jacobian(w0.grid, w0.x))
     phi = dev(wl.fourier_basis(w0.x))
     tang = losses.density_mode_tangents(ctx, P0, J0, phi, 0.05)
     grad = (tang * gU[None]).sum(dim=(1, 2, 3)).cpu().numpy()
 
     def loss_gpu(c):
-        cx, Ux, Jx, _, wx, _ = _fourier_forward(n, K, c, dt)
+        cx, Ux, Jx, _, wx, _ = _fourier_forward(n, K, c, dt, None, phys)
         return float(losses.density_squared(cx, Ux, Jx, wx)[0])
 
     fd = np.array([(loss_gpu(c0 + h * e) - loss_gpu(c0 - h * e)) / (2 * h) for e in np.eye(8)])
     scale = np.max(np.abs(fd))
-    assert np.max(np.abs(grad - fd)) <= 1e-6 * scale, (grad, fd)
+    assert np.max(np.abs(grad - fd)) <= tol * scale, (grad, fd)
 
     # the oracle's forward (same inputs, prescribed zero mesh velocity and the same dt)
     def loss_oracle(c):
-        wx = wl.rhd_fourier(n=n, coeffs=c)
+        wx = make(n=n, coeffs=c)
         Px = ph.full_prim(wx.prim["rho"], wx.prim["u"], wx.prim["p"], wx.prim["B"])
         Uo, Jo = st.initial_state(wx.grid, wx.scheme, Px, wx.x)
         xo = wx.x
@@ -233,4 +238,49 @@ def test_fourier_mode_gradient_against_differences():
     for m in (0, 5):
         e = np.eye(8)[m]
         fo = (loss_oracle(c0 + h * e) - loss_oracle(c0 - h * e)) / (2 * h)
-        assert abs(grad[m] - fo) <= 1e-6 * scale, (m, grad[m], fo)
+        assert abs(grad[m] - fo) <= tol * scale, (m, grad[m], fo)
+
+
+# ---------------------------------------------------------------------------
+# RMHD: the pair fluxes, the Godunov-Powell source and the face dissipation with
+# its eigen-structure held (as well as Y); the oracle's difference quotients hold
+# both through Y_fixed and eig_fixed
+# ---------------------------------------------------------------------------
+RCASES = [(2, (40, 36, 1), (0, 0, 0), True), (2, (30, 33, 1), (1, 1, 0), False),
+          (3, (10, 9, 8), (0, 0, 0), True)]
+
+
+@pytest.mark.parametrize("dim,n,bc,smooth", RCASES)
+@pytest.mark.parametrize("diss", [0, 1])
+def test_rmhd_residual_vjp_against_oracle_differences(dim, n, bc, smooth, diss):
+    case = Case(dim, n, bc, phys=ph.RMHD, seed=23, dissipation=diss, smooth=smooth, moving=True)
+    c = case.ctx
+    U, J = case.gpu_state()
+    met = empty(c.nmet, *c.padded_shape())
+    c.metrics(dev(case.x), dev(case.xdot), met)
+    rng = np.random.default_rng(6)
+    lam = rng.normal(size=(c.m,) + c.shape())
+    gU = empty(c.m, *c.shape())
+    gJ = empty(*c.shape())
+    c.residual_vjp(U, J, met, dev(lam), gU, gJ)
+    Uo, Jo = host(U), host(J)
+    vU = Uo * rng.normal(size=Uo.shape) * 1e-2
+    vJ = Jo * rng.normal(size=Jo.shape) * 1e-2
+    adj = float(np.sum(host(gU) * vU) + np.sum(host(gJ) * vJ))
+    meto = mt.metrics(case.grid, case.x, case.xdot)
+    Y = eig = None
+    if diss:
+        _, _, info = _oracle_L(case, Uo, Jo, meto, details=True)
+        Y = {k: info[k]["Y"] for k in range(dim)}
+        eig = {k: info[k]["eig"] for k in range(dim)}
+
+    def Lo(Ux, Jx):
+        P, ok = st.prim_from_cons(case.grid, case.scheme, Ux, Jx)
+        assert ok.all()
+        return rs.residual(case.grid, case.scheme, st.pad_solution(case.grid, P), meto, Y_fixed=Y, eig_fixed=eig)
+
+    h = 1e-6
+    Lp, _ = Lo(Uo + h * vU, Jo + h * vJ)
+    Lm, _ = Lo(Uo - h * vU, Jo - h * vJ)
+    fd = float(np.sum(lam * (Lp - Lm))) / (2 * h)
+    assert abs(adj - fd) <= 1e-6 * abs(fd), (adj, fd)
