@@ -70,6 +70,8 @@ def parse():
                     help="run one of the paper's 2D examples to its end time as MM-O5 (adaptive) and "
                          "UM-O5 (uniform, finer) and report the GPU time-to-solution ratio beside the "
                          "paper's CPU ratio (not a headline line)")
+    ap.add_argument("--no-fourier-gradient", action="store_true",
+                    help="skip the gradient study of the adjoint configuration (objects adjoint_fourier*)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed work, copy one buffer of this size once (a plain copy "
                          "kernel of known traffic, for scaling HBM counters)")
@@ -427,8 +429,9 @@ def main():
     t_mixed_ms = mrun.timed(args.steps, args.warmup)
     res_mixed_ms = mrun.residual_ms(args.residual_reps)
     adjoint = adjoint_timing(w, args.adjoint_steps, t_ms / args.steps)
-    adjoint_fourier = fourier_gradient(rmhd=True) if args.adjoint_steps > 0 else None
-    adjoint_fourier_rhd = fourier_gradient(rmhd=False) if args.adjoint_steps > 0 else None
+    study = args.adjoint_steps > 0 and not args.no_fourier_gradient
+    adjoint_fourier = fourier_gradient(rmhd=True) if study else None
+    adjoint_fourier_rhd = fourier_gradient(rmhd=False) if study else None
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 8
