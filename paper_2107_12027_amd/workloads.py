@@ -375,12 +375,46 @@ def rmhd_blast2d(n: int = 150, adaptive: bool = True) -> Workload:
                     steps=0, t_end=4.0)
 
 
+def rmhd_shock_cloud(n: Sequence[int] = (210, 150), adaptive: bool = True) -> Workload:
+    """2D RMHD shock-cloud interaction of Section 6 on [-0.2, 1.2] x [0, 1], Gamma =
+    5/3, CFL 0.4, run to t = 1.2: a planar shock at x_1 = 0.05 with the post-shock
+    state (rho, v, p, B) = (3.86859, (0.68, 0, 0), 1.25115, (0, 0.84981, -0.84981))
+    on its left and, on its right, rho = 1, v = 0, p = 0.05, B = (0, 0.16106,
+    0.16106) (the printed right tuple ends 0, 0.16106, 0.16106, 0.05, which gives
+    p = 0 in the order of the left tuple; read here as B followed by p); a cloud of
+    radius 0.15 about (0.25, 0.5) with rho = 30 in the right state.  The paper specifies inflow on the left boundary: the
+    left state is super-fast there (every characteristic speed of the x_1
+    Jacobian is positive, the slowest being about 0.12), so the zero-gradient
+    outflow rule leaves it unchanged and stands in for the inflow condition while
+    no wave reaches that boundary.  Adaptive mesh (MM-O5): the paper monitor with
+    alpha = 800 on sigma = ln rho, 3 filter passes, 10 Jacobi sweeps."""
+    nx, ny = int(n[0]), int(n[1])
+    g = make_grid(2, (nx, ny, 1), (OUTFLOW, OUTFLOW, PERIODIC), lo=(-0.2, 0.0, 0.0), length=(1.4, 1.0, 1.0))
+    x = uniform_mesh(g)
+    left = x[0] < 0.05
+    rho = np.where(left, 3.86859, 1.0)
+    p = np.where(left, 1.25115, 0.05)
+    v = np.zeros((3,) + g.shape)
+    v[0] = np.where(left, 0.68, 0.0)
+    B = np.zeros((3,) + g.shape)
+    B[1] = np.where(left, 0.84981, 0.16106)
+    B[2] = np.where(left, -0.84981, 0.16106)
+    cloud = (x[0] - 0.25) ** 2 + (x[1] - 0.5) ** 2 < 0.15 ** 2
+    rho = np.where(cloud, 30.0, rho)
+    mon = (Monitor(enabled=1, sigma=SIGMA_LNRHO, form=MON_PAPER, alpha=800.0, filter_passes=3, sweeps=10)
+           if adaptive else Monitor(enabled=0))
+    return Workload("rmhd2d_shock_cloud_%s_%dx%d" % ("mm" if adaptive else "um", nx, ny), g,
+                    Scheme(phys=RMHD, gamma=5.0 / 3.0, cfl=0.4), mon, _prim(rho, v, p, B), x,
+                    steps=0, t_end=1.2)
+
+
 # (MM-O5 size, UM-O5 size, the paper's MM-O5 / UM-O5 CPU-time ratio)
 PAPER_COMPARISONS = {
     "rp1": (lambda n, a: riemann2d(1, n, a), 200, 500, 0.178),
     "rp2": (lambda n, a: riemann2d(2, n, a), 200, 500, 0.306),
     "rp3": (lambda n, a: riemann2d(3, n, a), 200, 600, 0.137),
     "rmhd_blast": (lambda n, a: rmhd_blast2d(n, a), 150, 600, 0.0726),
+    "shock_cloud": (lambda n, a: rmhd_shock_cloud(n, a), (210, 150), (560, 400), 0.105),
 }
 
 

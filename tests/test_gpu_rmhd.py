@@ -180,3 +180,33 @@ def test_rmhd_blast_inadmissible_on_both_paths():
     Uo, Jo = st.initial_state(g, w.scheme, P, w.x)
     out = st.rk3_step(g, w.scheme, w.monitor, Uo, Jo, w.x)
     assert not out["ok"].all() and out["failed_stage"] == 1
+
+
+def test_rmhd_shock_cloud_first_step():
+    # the paper's shock-cloud initial data (strong shock, dense cloud, B_1 = 0: every
+    # x-face sees a field across its normal) on a coarse adaptive mesh: one step
+    # against the oracle's step, per-component bar as for the rotor
+    w = wl.rmhd_shock_cloud(n=(42, 30))
+    g = w.grid
+    ctx = es.Context(g, w.scheme, w.monitor)
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    met = empty(ctx.nmet, *ctx.padded_shape())
+    J = empty(*ctx.shape())
+    x = dev(w.x)
+    ctx.metrics(x, None, met, J)
+    U = empty(ctx.m, *ctx.shape())
+    ctx.prim2con(dev(P), J, U)
+    xd = empty(g.dim, *ctx.shape())
+    dt = empty(1)
+    ctx.rk3_step(U, J, x, xd, dt)
+    assert ctx.status()[0] == es.ES_OK
+    Uo, Jo = st.initial_state(g, w.scheme, P, w.x)
+    out = st.rk3_step(g, w.scheme, w.monitor, Uo, Jo, w.x)
+    assert out["ok"].all()
+    assert abs(host(dt)[0] - out["dt"]) <= 1e-12 * out["dt"]
+    Ug = host(U)
+    big = np.max(np.abs(out["U"]))
+    for c in range(ctx.m):
+        sc = max(np.max(np.abs(out["U"][c])), 1e-3 * big)
+        assert np.max(np.abs(Ug[c] - out["U"][c])) <= 2e-9 * sc, (c, np.max(np.abs(Ug[c] - out["U"][c])) / sc)
+    assert np.max(np.abs(host(x) - out["x"])) <= 1e-12
