@@ -52,3 +52,47 @@ def prim(x1, x2, t):
     By = 0.5 * ((s2 + 1) * Bt2 - (s2 - 1) * Bt1)
     z = 0.0 * rho
     return rho, np.stack([v1, v2, z]), p, np.stack([Bx, By, z])
+
+
+def prim3d(x1, x2, x3, t):
+    """(rho, v (3), p, B (3)) of the 3D RMHD vortex of Section 6 (example
+    RMHD_3DVortex) on the periodic domain [-R, R]^2 x [-5R, 5R]: the rest-frame
+    vortex above (same f, kappa and, by the same reading, B~ = B_0 e^{(1-r^2)/2}
+    (-x~_2, x~_1)) seen from a frame moving with velocity (1, 1, 1)/2 (W = 2):
+      x^_k = x_k + (x_1 + x_2 + x_3)/3 + t,
+      (x~_1, x~_2) = (x^_1, x^_2) + k_1 (40/3, 10/3) + k_2 (10/3, 40/3),
+      v = (4 v~_1 + v~_2 - 3, 4 v~_2 + v~_1 - 3, v~_1 + v~_2 - 3) / (6 - 3 (v~_1 + v~_2)),
+      B = (5 B~_1 - B~_2, 5 B~_2 - B~_1, -B~_1 - B~_2) / 3.
+    The lattice (k_1, k_2) is the image of the domain's periods (2R, 0, 0),
+    (0, 2R, 0) and (0, 0, 10R) in the rest frame; the representative taken is the
+    image nearest to the vortex axis (the paper's Omega_0 is not spelled out; the
+    other images differ by less than 1e-9 where they meet)."""
+    S = (x1 + x2 + x3) / 3.0
+    xh1 = x1 + S + t
+    xh2 = x2 + S + t
+    best = None
+    for k1 in range(-3, 4):
+        for k2 in range(-3, 4):
+            a1 = xh1 + (40.0 * k1 + 10.0 * k2) / 3.0
+            a2 = xh2 + (10.0 * k1 + 40.0 * k2) / 3.0
+            rr = np.real(a1) ** 2 + np.real(a2) ** 2
+            if best is None:
+                best, xt1, xt2 = rr, a1, a2
+            else:
+                sel = rr < best
+                best = np.where(sel, rr, best)
+                xt1 = np.where(sel, a1, xt1)
+                xt2 = np.where(sel, a2, xt2)
+    r2 = xt1 * xt1 + xt2 * xt2
+    e = np.exp(1.0 - r2)
+    rho = (1.0 - SIGMA * e) ** (1.0 / (G - 1.0))
+    p = rho ** G
+    kappa = 2 * G * SIGMA * rho + (G - 1.0) * B0 ** 2 * (2.0 - r2)
+    f = np.sqrt(kappa * e / (kappa * r2 * e + (G - 1.0) * rho + G * p))
+    vt1, vt2 = -xt2 * f, xt1 * f
+    den = 6.0 - 3.0 * (vt1 + vt2)
+    v = np.stack([4 * vt1 + vt2 - 3.0, 4 * vt2 + vt1 - 3.0, vt1 + vt2 - 3.0]) / den
+    eb = np.exp(0.5 * (1.0 - r2))
+    Bt1, Bt2 = -B0 * eb * xt2, B0 * eb * xt1
+    B = np.stack([5 * Bt1 - Bt2, 5 * Bt2 - Bt1, -Bt1 - Bt2]) / 3.0
+    return rho, v, p, B
