@@ -170,6 +170,15 @@ es_status es_mesh_redistribute(es_ctx* ctx, const double* prim, const double* x,
 es_status es_rk3_step(es_ctx* ctx, double* Ucurv, double* J, double* x, double* xdot,
                       double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
 
+/* One SSP-RK3 step on a prescribed moving mesh (the accuracy tests of Section 6
+ * move the nodes by a given formula instead of the redistribution of Section 5):
+ * as es_rk3_step, with the mesh velocity xdot (interior, d comps, device, read
+ * only) given by the caller and held over the step; the stage meshes are
+ * x + c dt xdot and x is advanced in place to x + dt xdot.  The monitor of the
+ * context is not used.  Errors as es_rk3_step. */
+es_status es_rk3_step_moving(es_ctx* ctx, double* Ucurv, double* J, double* x, const double* xdot,
+                             double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
+
 /* Adjoint (p = 3, FP64 form only; ES_EUNSUPPORTED for scheme.mixed = 1 or p = 2).
  * For RMHD the ES dissipation's face eigen-structure (the columns of R and
  * lambda^) is held at its forward value as well: the pair fluxes, the

@@ -202,9 +202,11 @@ es_status es_mesh_redistribute(es_ctx* c, const double* prim, const double* x, c
     return hip_status(es::launch_mesh(c, prim, x, dt_dev, x_new, xdot, dtau_dev, s));
 }
 
+// xdot_in: NULL for the scheme's own mesh (adaptive redistribution, or a static
+// mesh), else the caller's mesh velocity, held over the step (xdot unused then)
 static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double* xdot,
                               double* dt_dev, const double* fixed_dt_dev, hipStream_t s,
-                              double* ckpt = nullptr) {
+                              double* ckpt = nullptr, const double* xdot_in = nullptr) {
     const long long N = c->g.nodes, nU = N * c->m, nX = N * c->g.dim;
     const es::Checkpoint k = ckpt ? es::checkpoint_layout(c, ckpt) : es::Checkpoint{};
     auto w = [](const double* p) { return const_cast<double*>(p); };
@@ -217,14 +219,18 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
     // pressure iteration), metrics on x^n (spatial part), CFL step
     // (with the adaptive mesh, dt is finalised inside the mesh launches)
     ES_TRY(es::launch_con2prim(c, U, J, c->prim, 1, s));
-    const bool adaptive = c->monitor.enabled != 0;
+    const bool adaptive = c->monitor.enabled != 0 && xdot_in == nullptr;
     bool grad_done = false;
     ES_TRY(es::launch_cfl_mesh(c, c->prim, x, J, dt_dev, fixed_dt_dev, s, adaptive, adaptive, &grad_done));
     // mesh redistribution: x^{n+1} into c->xnew, mesh velocity into xdot
-    if (adaptive)
+    if (xdot_in != nullptr) {
+        xdot = const_cast<double*>(xdot_in);
+        ES_TRY(es::launch_mesh_advance(c, x, xdot_in, dt_dev, c->xnew, s));
+    } else if (adaptive) {
         ES_TRY(es::launch_mesh(c, c->prim, x, dt_dev, c->xnew, xdot, nullptr, s, true, fixed_dt_dev, grad_done));
-    else
+    } else {
         ES_TRY(es::launch_zero_mesh_velocity(c, x, c->xnew, xdot, s));
+    }
     if (ckpt) {
         ES_TRY(es::launch_copy(w(k.dt), dt_dev, 1, s));
         ES_TRY(es::launch_copy(w(k.xdot), xdot, nX, s));
@@ -256,13 +262,11 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
     return ES_OK;
 }
 
-es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, double* dt_dev,
-                      const double* fixed_dt_dev, hipStream_t s) {
-    if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
-        dt_dev == nullptr)
-        return ES_EINVAL;
-    if (!c->use_graph) return enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, s);
-    const void* key[6] = {U, J, x, xdot, dt_dev, fixed_dt_dev};
+// one step through the context's HIP graph, captured again when the arguments change
+static es_status graph_step(es_ctx* c, double* U, double* J, double* x, double* xdot, double* dt_dev,
+                            const double* fixed_dt_dev, const double* xdot_in, hipStream_t s) {
+    if (!c->use_graph) return enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, s, nullptr, xdot_in);
+    const void* key[7] = {U, J, x, xdot, dt_dev, fixed_dt_dev, xdot_in};
     if (c->gexec == nullptr || memcmp(key, c->gkey, sizeof(key)) != 0) {
         if (c->gexec != nullptr) {
             ES_TRY(hipGraphExecDestroy(c->gexec));
@@ -271,7 +275,7 @@ es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, 
         // the capture stream must not depend on earlier work while capturing
         ES_TRY(hipStreamSynchronize(c->cap));
         ES_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-        const es_status st = enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, c->cap);
+        const es_status st = enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, c->cap, nullptr, xdot_in);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(c->cap, &graph);
         if (st != ES_OK || e != hipSuccess || graph == nullptr) {
@@ -289,6 +293,22 @@ es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, 
     // the replay goes into the caller's stream (ordered with its other work)
     ES_TRY(hipGraphLaunch(c->gexec, s));
     return ES_OK;
+}
+
+es_status es_rk3_step(es_ctx* c, double* U, double* J, double* x, double* xdot, double* dt_dev,
+                      const double* fixed_dt_dev, hipStream_t s) {
+    if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
+        dt_dev == nullptr)
+        return ES_EINVAL;
+    return graph_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, nullptr, s);
+}
+
+es_status es_rk3_step_moving(es_ctx* c, double* U, double* J, double* x, const double* xdot,
+                             double* dt_dev, const double* fixed_dt_dev, hipStream_t s) {
+    if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
+        dt_dev == nullptr)
+        return ES_EINVAL;
+    return graph_step(c, U, J, x, nullptr, dt_dev, fixed_dt_dev, xdot, s);
 }
 
 size_t es_ckpt_doubles(const es_ctx* c) { return c ? (size_t)es::checkpoint_doubles(c) : 0; }

@@ -50,7 +50,7 @@ struct es_ctx {
     int use_graph;
     hipStream_t cap;            // capture stream (default priority)
     hipGraphExec_t gexec;
-    const void* gkey[6];
+    const void* gkey[7];
 };
 
 namespace es {
@@ -93,6 +93,8 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
                        double* x_new, double* xdot, double* dtau_dev, hipStream_t s,
                        bool dt_pending = false, const double* fixed_dt_dev = nullptr,
                        bool grad_done = false);
+hipError_t launch_mesh_advance(const es_ctx* c, const double* x, const double* xdot,
+                               const double* dt_dev, double* x_new, hipStream_t s);
 hipError_t launch_zero_mesh_velocity(const es_ctx* c, const double* x, double* x_new, double* xdot,
                                      hipStream_t s);
 // xsrc/xdst (optional): copy the new mesh in the same launch (last stage)

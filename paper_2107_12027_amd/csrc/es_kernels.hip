@@ -1205,6 +1205,13 @@ __global__ void k_zero_mesh_velocity(long long n, const double* __restrict__ x, 
     xdot[t] = 0.0;
 }
 
+__global__ void k_mesh_advance(long long n, const double* __restrict__ x, const double* __restrict__ xdot,
+                               const double* __restrict__ dt_dev, double* __restrict__ xnew) {
+    const long long t = gtid();
+    if (t >= n) return;
+    xnew[t] = x[t] + dt_dev[0] * xdot[t];
+}
+
 // ---------------------------------------------------------------------------
 // SSP-RK3 stage combinations (Shu-Osher form)
 // ---------------------------------------------------------------------------
@@ -1522,6 +1529,13 @@ hipError_t launch_zero_mesh_velocity(const es_ctx* c, const double* x, double* x
                                      hipStream_t s) {
     const long long n = c->g.nodes * c->g.dim;
     k_zero_mesh_velocity<<<grid_for(n), TPB, 0, s>>>(n, x, x_new, xdot);
+    return hipGetLastError();
+}
+
+hipError_t launch_mesh_advance(const es_ctx* c, const double* x, const double* xdot,
+                               const double* dt_dev, double* x_new, hipStream_t s) {
+    const long long n = c->g.nodes * c->g.dim;
+    k_mesh_advance<<<grid_for(n), TPB, 0, s>>>(n, x, xdot, dt_dev, x_new);
     return hipGetLastError();
 }
 

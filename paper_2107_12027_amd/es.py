@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(HERE, "libes.so")
 ES_OK, ES_EINVAL, ES_EADMISSIBLE, ES_ENOCONV, ES_EMESH, ES_EHIP, ES_EUNSUPPORTED = range(7)
 SYMBOLS = ("es_create", "es_destroy", "es_nvars", "es_nprim", "es_nmet", "es_nodes",
            "es_padded_nodes", "es_prim2con", "es_metrics", "es_con2prim", "es_residual",
-           "es_cfl", "es_mesh_redistribute", "es_rk3_step", "es_set_graph", "es_diagnostics",
-           "es_ctx_status", "es_status_string", "es_ckpt_doubles", "es_rk3_step_save",
+           "es_cfl", "es_mesh_redistribute", "es_rk3_step", "es_rk3_step_moving", "es_set_graph",
+           "es_diagnostics", "es_ctx_status", "es_status_string", "es_ckpt_doubles", "es_rk3_step_save",
            "es_rk3_step_vjp", "es_residual_vjp")
 
 
@@ -75,6 +75,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.es_cfl.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.es_mesh_redistribute.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.es_rk3_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.es_rk3_step_moving.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.es_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.es_set_graph.argtypes = [vp, ctypes.c_int]
     lib.es_ctx_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_longlong),
@@ -85,8 +86,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.es_rk3_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.es_residual_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     for name in ("es_prim2con", "es_metrics", "es_con2prim", "es_residual", "es_cfl",
-                 "es_mesh_redistribute", "es_rk3_step", "es_set_graph", "es_diagnostics",
-                 "es_ctx_status", "es_rk3_step_save", "es_rk3_step_vjp", "es_residual_vjp"):
+                 "es_mesh_redistribute", "es_rk3_step", "es_rk3_step_moving", "es_set_graph",
+                 "es_diagnostics", "es_ctx_status", "es_rk3_step_save", "es_rk3_step_vjp", "es_residual_vjp"):
         getattr(lib, name).restype = st
     lib.es_status_string.argtypes = [st]
     lib.es_status_string.restype = ctypes.c_char_p
@@ -181,6 +182,11 @@ class Context:
     def rk3_step(self, U, J, x, xdot, dt, fixed_dt=None, stream=None):
         _check(_lib.es_rk3_step(self.h, _ptr(U), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt), _ptr(fixed_dt),
                                 _stream(stream)), "es_rk3_step")
+
+    def rk3_step_moving(self, U, J, x, xdot, dt, fixed_dt=None, stream=None):
+        """One step with the caller's mesh velocity ``xdot`` held over the step."""
+        _check(_lib.es_rk3_step_moving(self.h, _ptr(U), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt),
+                                       _ptr(fixed_dt), _stream(stream)), "es_rk3_step_moving")
 
     def ckpt_doubles(self) -> int:
         return _lib.es_ckpt_doubles(self.h)

@@ -190,21 +190,20 @@ def _vortex_errors(diss, Ns):
     # the semi-discrete residual against the exact d(J U)/dt of the RMHD vortex at
     # t = 0 (complex-step derivative of the closed form in t) on static uniform
     # periodic meshes of [-5, 5]^2
-    import exact_vortex as ev
     errs = []
     for n in Ns:
         g = wl.make_grid(2, (n, n, 1), (0, 0, 0), lo=(-5.0, -5.0, 0.0), length=(10.0, 10.0, 1.0))
         x = wl.uniform_mesh(g)
-        rho, v, p, B = ev.prim(x[0], x[1], 0.0)
+        rho, v, p, B = wl.vortex2d_state(x[0], x[1], 0.0)
         W = 1.0 / np.sqrt(1.0 - np.sum(v * v, axis=0))
         P = ph.full_prim(rho, W * v, p, B)
         met = mt.metrics(g, x, None)
         J = mt.jacobian(g, x)
         dU, dJ = rs.residual(g, wl.Scheme(phys=ph.RMHD, dissipation=diss), st.pad_solution(g, P), met)
         hc = 1e-30
-        rc, vc, pc, Bc = ev.prim(x[0].astype(complex), x[1].astype(complex), 1j * hc)
+        rc, vc, pc, Bc = wl.vortex2d_state(x[0].astype(complex), x[1].astype(complex), 1j * hc)
         Wc = 1.0 / np.sqrt(1.0 - np.sum(vc * vc, axis=0))
-        Uc = ph.cons(ph.full_prim(rc, Wc * vc, pc, Bc), ev.G)
+        Uc = ph.cons(ph.full_prim(rc, Wc * vc, pc, Bc), wl.VORTEX_GAMMA)
         exact = np.imag(Uc) / hc
         errs.append(np.mean(np.abs(dU / J - exact[:8])))
     return np.array(errs)
@@ -234,30 +233,20 @@ def _vortex3d_errors(Ns, t=1.0):
     # the mesh velocity is not zero) against the exact semi-discrete rate: along a
     # node path d(J U)/dt = J (dU/dt + xdot . grad U) + U dJ/dt, with the discrete
     # dJ/dt of the VCL and the material derivative by a complex step along (xdot, 1)
-    import exact_vortex as ev
-    R = ev.R
     errs = []
     for n in Ns:
-        g = wl.make_grid(3, (n, n, 5 * n), (0, 0, 0), lo=(-R, -R, -5 * R),
-                         length=(2 * R, 2 * R, 10 * R))
-        xr = wl.uniform_mesh(g)
-        s1 = np.sin(3 * np.pi * xr[0] / R)
-        s2 = np.sin(3 * np.pi * xr[1] / R)
-        s3 = np.sin(3 * np.pi * xr[2] / (5 * R))
-        shape = np.stack([s2 * s3, s3 * s1, s1 * s2])
-        x = xr + 0.2 * np.cos(np.pi * t / 4) * shape
-        xd = -0.05 * np.pi * np.sin(np.pi * t / 4) * shape
-        rho, v, p, B = ev.prim3d(x[0], x[1], x[2], t)
-        W = 1.0 / np.sqrt(1.0 - np.sum(v * v, axis=0))
+        w = wl.rmhd_vortex(3, n, t=t, dissipation=0)
+        g, x = w.grid, w.x
+        _, xd = wl.vortex_mesh(g, t)
         met = mt.metrics(g, x, xd)
         J = mt.jacobian(g, x)
-        dU, dJ = rs.residual(g, wl.Scheme(phys=ph.RMHD, dissipation=0),
-                             st.pad_solution(g, ph.full_prim(rho, W * v, p, B)), met)
+        P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+        dU, dJ = rs.residual(g, w.scheme, st.pad_solution(g, P), met)
         hc = 1e-30
         xc = x + 1j * hc * xd
-        rc, vc, pc, Bc = ev.prim3d(xc[0], xc[1], xc[2], t + 1j * hc)
+        rc, vc, pc, Bc = wl.vortex3d_state(xc[0], xc[1], xc[2], t + 1j * hc)
         Wc = 1.0 / np.sqrt(1.0 - np.sum(vc * vc, axis=0))
-        Uc = ph.cons(ph.full_prim(rc, Wc * vc, pc, Bc), ev.G)
+        Uc = ph.cons(ph.full_prim(rc, Wc * vc, pc, Bc), wl.VORTEX_GAMMA)
         errs.append(np.mean(np.abs((dU - np.real(Uc) * dJ) / J - np.imag(Uc) / hc)))
     return np.array(errs)
 
