@@ -57,7 +57,7 @@ typedef enum {
 enum { ES_RHD = 0, ES_RMHD = 1 };
 enum { ES_BC_PERIODIC = 0, ES_BC_OUTFLOW = 1 };
 enum { ES_SIGMA_RHO = 0, ES_SIGMA_LNRHO = 1 };
-enum { ES_MON_PAPER = 0, ES_MON_SQGRAD = 1 };
+enum { ES_MON_PAPER = 0, ES_MON_SQGRAD = 1, ES_MON_GRADLAP = 2 };
 
 /* Computational grid: a fixed orthogonal index box with constant spacing
  * (Section 3.2).  Periodic axes wrap the solution and shift the mesh
@@ -96,10 +96,16 @@ typedef struct {
     int enabled;        /* 0: static mesh (xdot = 0) */
     int sigma;          /* ES_SIGMA_RHO / ES_SIGMA_LNRHO: monitored variable */
     int form;           /* ES_MON_PAPER: sqrt(1 + alpha |grad s| / max |grad s|) (eq. monitor);
-                           ES_MON_SQGRAD: sqrt(1 + alpha |grad s|^2) */
+                           ES_MON_SQGRAD: sqrt(1 + alpha |grad s|^2);
+                           ES_MON_GRADLAP: sqrt(1 + alpha |grad s| / max |grad s|
+                             + alpha2 |Lap s| / max |Lap s|) (eq. RMHD_2DVortex_Monitor),
+                           gradient and Laplacian in xi by second-order central
+                           differences (one-sided on outflow edges); a term whose
+                           maximum is zero is dropped */
     double alpha;
     int filter_passes;  /* low-pass filter passes */
     int sweeps;         /* Jacobi sweeps mu */
+    double alpha2;      /* Laplacian weight of ES_MON_GRADLAP (unused by the other forms) */
 } es_monitor;
 
 typedef struct es_ctx es_ctx;

@@ -14,7 +14,7 @@ import numpy as np
 from .metrics import extend, crop
 
 SIGMA_RHO, SIGMA_LNRHO = 0, 1
-MON_PAPER, MON_SQGRAD = 0, 1
+MON_PAPER, MON_SQGRAD, MON_GRADLAP = 0, 1, 2
 
 
 def _shift(a, grid, k, s, ax):
@@ -43,10 +43,37 @@ def _free_mask(grid, k):
     return m
 
 
+def laplacian_xi(grid, sigma):
+    """sum_k d^2 sigma / d xi_k^2 by the three-point second difference: central in
+    the interior and on periodic axes, one-sided (the three nearest nodes on the
+    axis) on bounded edges."""
+    lap = np.zeros(grid.shape)
+    for k in range(grid.dim):
+        ax = grid.dim - 1 - k
+        n = grid.n[k]
+        h2 = grid.dxi[k] ** 2
+        if grid.bc[k] == 0:
+            lap = lap + (np.roll(sigma, -1, axis=ax) - 2 * sigma + np.roll(sigma, 1, axis=ax)) / h2
+            continue
+        d = np.zeros(grid.shape)
+        for i in range(n):
+            j = min(max(i, 1), n - 2)          # centre of the three-point stencil
+            idx = [slice(None)] * grid.dim
+            idx[ax] = i
+            d[tuple(idx)] = (np.take(sigma, j + 1, axis=ax) - 2 * np.take(sigma, j, axis=ax)
+                             + np.take(sigma, j - 1, axis=ax)) / h2
+        lap = lap + d
+    return lap
+
+
 def monitor(grid, mon, Pin):
     """omega = sqrt(1 + alpha |grad_xi sigma| / max |grad_xi sigma|) (eq. monitor), or
-    omega = sqrt(1 + alpha |grad_xi sigma|^2); second-order central differences in xi,
-    one-sided on bounded edges; omega = 1 when the gradient vanishes everywhere."""
+    omega = sqrt(1 + alpha |grad_xi sigma|^2), or (eq. RMHD_2DVortex_Monitor)
+    omega = sqrt(1 + alpha |grad_xi sigma| / max |grad_xi sigma|
+                   + alpha2 |Lap_xi sigma| / max |Lap_xi sigma|);
+    second-order central differences in xi, one-sided on bounded edges; a
+    normalised term whose maximum is zero is left out (omega = 1 for a constant
+    sigma)."""
     sigma = Pin[0] if mon.sigma == SIGMA_RHO else np.log(Pin[0])
     g2 = np.zeros(grid.shape)
     for k in range(grid.dim):
@@ -71,9 +98,15 @@ def monitor(grid, mon, Pin):
         return np.sqrt(1.0 + mon.alpha * g2)
     g = np.sqrt(g2)
     mx = float(np.max(g))
-    if mx == 0.0:
-        return np.ones(grid.shape)
-    return np.sqrt(1.0 + mon.alpha * g / mx)
+    w2 = np.ones(grid.shape)
+    if mx > 0.0:
+        w2 = w2 + mon.alpha * g / mx
+    if mon.form == MON_GRADLAP:
+        lap = np.abs(laplacian_xi(grid, sigma))
+        ml = float(np.max(lap))
+        if ml > 0.0:
+            w2 = w2 + mon.alpha2 * lap / ml
+    return np.sqrt(w2)
 
 
 def lowpass(grid, w):

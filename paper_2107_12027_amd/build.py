@@ -31,25 +31,46 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libes.so)")
 
 
-def command(out: str = LIB):
-    return [hipcc(), "-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-shared",
-            # packed FP32 instructions are kept out of all device code
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
-            "-I" + INCLUDE, "-I" + CSRC, "-o", out] + [os.path.join(CSRC, s) for s in SOURCES]
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC",
+         # packed FP32 instructions are kept out of all device code
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+         "-I" + INCLUDE, "-I" + CSRC]
+
+
+def compile_command(src: str, obj: str):
+    return [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+
+
+def link_command(objs, out: str = LIB):
+    return [hipcc(), "--offload-arch=" + ARCH, "-fPIC", "-shared", "-o", out] + list(objs)
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source (one hipcc process each, in parallel) and link libes.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(ROOT, "_build", "obj")
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+
+    def run(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return subprocess.run(cmd, capture_output=True, text=True)
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), max(1, (os.cpu_count() or 1) // 2))) as ex:
+        results = list(ex.map(run, [compile_command(s, o) for s, o in zip(SOURCES, objs)]))
+    for src, res in zip(SOURCES, results):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed compiling %s" % src)
+        if verbose and res.stderr.strip():
+            sys.stderr.write(res.stderr)
     tmp = LIB + ".tmp"
-    cmd = command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
+    res = run(link_command(objs, tmp))
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libes.so")
-    if verbose and res.stderr.strip():
-        sys.stderr.write(res.stderr)
+        raise RuntimeError("hipcc failed linking libes.so")
     os.replace(tmp, LIB)
     return LIB
 

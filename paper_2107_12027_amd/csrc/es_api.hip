@@ -70,8 +70,12 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     if (scheme->mixed != 0 && scheme->mixed != 1) return ES_EINVAL;
     if (monitor->enabled) {
         if (monitor->sigma != ES_SIGMA_RHO && monitor->sigma != ES_SIGMA_LNRHO) return ES_EINVAL;
-        if (monitor->form != ES_MON_PAPER && monitor->form != ES_MON_SQGRAD) return ES_EINVAL;
-        if (monitor->filter_passes < 0 || monitor->sweeps < 0 || !(monitor->alpha >= 0.0)) return ES_EINVAL;
+        if (monitor->form != ES_MON_PAPER && monitor->form != ES_MON_SQGRAD &&
+            monitor->form != ES_MON_GRADLAP)
+            return ES_EINVAL;
+        if (monitor->filter_passes < 0 || monitor->sweeps < 0 || !(monitor->alpha >= 0.0) ||
+            !(monitor->alpha2 >= 0.0))
+            return ES_EINVAL;
     }
     // kernels of this build: p = 3 (RHD and RMHD, FP64 or FP32-mixed) and p = 2 (RHD)
     if (scheme->order_p != 3 && !(scheme->order_p == 2 && scheme->phys == ES_RHD)) return ES_EUNSUPPORTED;

@@ -58,6 +58,7 @@ namespace es {
 constexpr int SCAL_DT = 0;
 constexpr int SCAL_GMAX = 1;
 constexpr int SCAL_DTAU = 2;
+constexpr int SCAL_LMAX = 3;
 constexpr int NSCAL = 8;
 
 hipError_t launch_prim2con(const es_ctx* c, const double* prim, const double* J, double* U,

@@ -819,6 +819,65 @@ __global__ void __launch_bounds__(256) k_monitor_grad(GridDev g, int M, int sigm
     if (flat_tid() == 0) partial[flat_block()] = r;
 }
 
+// |Lap_xi sigma| at an interior node (eq. RMHD_2DVortex_Monitor): three-point
+// second differences, central where both neighbours are on the axis (ghosts of
+// periodic axes hold the periodic copies), else the three nearest nodes
+template <int DIM>
+__device__ __forceinline__ double laplacian_node(const GridDev& g, int M, int sigma_ln,
+                                                 const double* __restrict__ prim, int i, int j, int k) {
+    const long long P = g.pnodes;
+    const int c[3] = {i, j, k};
+    const long long pc = pidx(g, i, j, k);
+    const long long off = sigma_ln ? M * P : 0;
+    const long long strides[3] = {1, (long long)g.P[0], (long long)g.P[0] * g.P[1]};
+    double lap = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        long long ctr = pc;
+        if (g.bc[a] != ES_BC_PERIODIC) {
+            if (c[a] == 0) ctr += strides[a];
+            else if (c[a] == g.n[a] - 1) ctr -= strides[a];
+        }
+        const double d2 = prim[off + ctr + strides[a]] - 2.0 * prim[off + ctr] + prim[off + ctr - strides[a]];
+        lap += d2 / (g.dxi[a] * g.dxi[a]);
+    }
+    return fabs(lap);
+}
+
+// gradient + Laplacian monitor: |grad sigma| into w, |Lap sigma| into w2 and the
+// block maxima of both (partial: grad slab, then Laplacian slab of nb entries)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_monitor_gradlap(GridDev g, int M, int sigma_ln,
+                                                         const double* __restrict__ prim,
+                                                         double* __restrict__ w, double* __restrict__ w2,
+                                                         double* __restrict__ pgrad, double* __restrict__ plap) {
+    __shared__ double sh[8];
+    double mg = 0.0, ml = 0.0;
+    int i, j, k;
+    if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
+        mg = monitor_node<DIM>(g, M, sigma_ln, 0, 0.0, prim, w, i, j, k);
+        ml = laplacian_node<DIM>(g, M, sigma_ln, prim, i, j, k);
+        w2[iidx(g, i, j, k)] = ml;
+    }
+    const double rg = block_reduce<0>(mg, sh);
+    if (flat_tid() == 0) pgrad[flat_block()] = rg;
+    const double rl = block_reduce<0>(ml, sh);
+    if (flat_tid() == 0) plap[flat_block()] = rl;
+}
+
+// omega = sqrt(1 + alpha g / max g + alpha2 l / max l), a term with a zero maximum dropped
+__global__ void k_monitor_apply_gradlap(long long n, double alpha, double alpha2,
+                                        const double* __restrict__ gmax, const double* __restrict__ lmax,
+                                        double* __restrict__ w, const double* __restrict__ w2) {
+    const long long t = gtid();
+    if (t >= n) return;
+    const double mg = gmax[0], ml = lmax[0];
+    double v = 1.0;
+    if (mg > 0.0) v += alpha * w[t] / mg;
+    if (ml > 0.0) v += alpha2 * w2[t] / ml;
+    w[t] = sqrt(v);
+}
+
 // one-block reduction of partial maxima (op 0) or minima capped at 1 (op 1)
 __global__ void __launch_bounds__(256) k_reduce_final(int op, int nb, const double* __restrict__ partial,
                                                       double* __restrict__ out) {
@@ -1461,10 +1520,12 @@ hipError_t launch_residual(const es_ctx* c, const double* prim, const double* me
     return hipGetLastError();
 }
 
-// reduction partials in c->red: CFL maxima (dim slabs), monitor maxima, Delta tau minima
+// reduction partials in c->red: CFL maxima (dim slabs), monitor maxima, Delta tau
+// minima, Laplacian maxima of the gradient + Laplacian monitor
 inline double* red_cfl(const es_ctx* c) { return c->red; }
 inline double* red_monitor(const es_ctx* c) { return c->red + 3 * (long long)c->red_blocks; }
 inline double* red_dtau(const es_ctx* c) { return c->red + 4 * (long long)c->red_blocks; }
+inline double* red_laplacian(const es_ctx* c) { return c->red + 5 * (long long)c->red_blocks; }
 
 inline DtFinal cfl_final_args(const es_ctx* c, const double* fixed_dt_dev, double* dt_dev) {
     const GridDev& g = c->g;
@@ -1492,7 +1553,8 @@ hipError_t launch_cfl_mesh(const es_ctx* c, const double* prim, const double* x,
         return launch_cfl(c, prim, c->met, J, dt_dev, fixed_dt_dev, s, defer_final);
     }
     MonitorArgs mon{};
-    if (with_monitor) {
+    // the gradient + Laplacian monitor is formed by the mesh launches
+    if (with_monitor && c->monitor.form != ES_MON_GRADLAP) {
         mon.enabled = 1;
         mon.M = c->m;
         mon.sigma_ln = c->monitor.sigma == ES_SIGMA_LNRHO;
@@ -1504,7 +1566,7 @@ hipError_t launch_cfl_mesh(const es_ctx* c, const double* prim, const double* x,
     k_cfl_partial2d_mesh<<<interior_grid(g), dim3(MTX, CBY, 1), 0, s>>>(g, c->scheme.gamma, prim, x, J, red_cfl(c),
                                                                          mon);
     if (!defer_final) k_cfl_final<<<1, 256, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
-    if (monitor_done != nullptr) *monitor_done = with_monitor;
+    if (monitor_done != nullptr) *monitor_done = mon.enabled != 0;
     return hipGetLastError();
 }
 
@@ -1548,6 +1610,7 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
     const dim3 gr = interior_grid(g);
     const int sig_ln = mo.sigma == ES_SIGMA_LNRHO;
     const int sq = mo.form == ES_MON_SQGRAD;
+    const bool gradlap = mo.form == ES_MON_GRADLAP;
     double* w = c->wa;
     double* w2 = c->wb;
     double* gpart = red_monitor(c);
@@ -1557,6 +1620,16 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
     if (dt_pending && g.dim != 2) k_cfl_final<<<1, 256, 0, s>>>(dt_fin);
     if (grad_done) {
         // omega (or |grad sigma|) in c->wa and its block maxima came with the CFL launch
+    } else if (gradlap) {
+        // omega formed here; the filter passes below take it as it is
+        if (g.dim == 2)
+            k_monitor_gradlap<2><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, prim, w, w2, gpart, red_laplacian(c));
+        else
+            k_monitor_gradlap<3><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, prim, w, w2, gpart, red_laplacian(c));
+        k_reduce_final<<<1, 256, 0, s>>>(0, nb, gpart, c->scal + SCAL_GMAX);
+        k_reduce_final<<<1, 256, 0, s>>>(0, nb, red_laplacian(c), c->scal + SCAL_LMAX);
+        k_monitor_apply_gradlap<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, mo.alpha2, c->scal + SCAL_GMAX,
+                                                                   c->scal + SCAL_LMAX, w, w2);
     } else if (g.dim == 2) {
         k_monitor_grad<2><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, sq, mo.alpha, prim, w, gpart);
     } else {
@@ -1564,7 +1637,7 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
     }
     if (g.dim == 2) {
         // normalisation (maximum reduced in each block) and filter passes, FH per launch
-        int apply = !sq, left = mo.filter_passes;
+        int apply = !sq && !gradlap, left = mo.filter_passes;
         do {
             const int k = min(FH, left);
             k_monitor_filter2d<<<box_grid(g.n[0], g.n[1], 1), dim3(FTX, FBY, 1), 0, s>>>(
@@ -1575,7 +1648,7 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
             left -= k;
         } while (left > 0);
     } else {
-        if (!sq) {
+        if (!sq && !gradlap) {
             k_reduce_final<<<1, 256, 0, s>>>(0, nb, gpart, c->scal + SCAL_GMAX);
             k_monitor_apply<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, c->scal + SCAL_GMAX, w);
         }

@@ -43,7 +43,7 @@ class Scheme(ctypes.Structure):
 class Monitor(ctypes.Structure):
     _fields_ = [("enabled", ctypes.c_int), ("sigma", ctypes.c_int), ("form", ctypes.c_int),
                 ("alpha", ctypes.c_double), ("filter_passes", ctypes.c_int),
-                ("sweeps", ctypes.c_int)]
+                ("sweeps", ctypes.c_int), ("alpha2", ctypes.c_double)]
 
 
 _lib = None
@@ -126,7 +126,7 @@ class Context:
         self.scheme_c = Scheme(scheme.phys, scheme.gamma, scheme.order_p, scheme.dissipation,
                                scheme.mixed, scheme.weno_eps, scheme.cfl)
         self.monitor_c = Monitor(monitor.enabled, monitor.sigma, monitor.form, monitor.alpha,
-                                 monitor.filter_passes, monitor.sweeps)
+                                 monitor.filter_passes, monitor.sweeps, monitor.alpha2)
         h = ctypes.c_void_p()
         _check(lib.es_create(ctypes.byref(self.grid_c), ctypes.byref(self.scheme_c),
                              ctypes.byref(self.monitor_c), ctypes.byref(h)), "es_create")

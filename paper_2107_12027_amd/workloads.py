@@ -36,6 +36,7 @@ SIGMA_RHO = 0
 SIGMA_LNRHO = 1
 MON_PAPER = 0     # omega = sqrt(1 + alpha |grad sigma| / max |grad sigma|)
 MON_SQGRAD = 1    # omega = sqrt(1 + alpha |grad sigma|^2)
+MON_GRADLAP = 2   # omega = sqrt(1 + alpha |grad sigma| / max + alpha2 |Lap sigma| / max)
 
 
 @dataclasses.dataclass
@@ -79,6 +80,7 @@ class Monitor:
     alpha: float = 0.0
     filter_passes: int = 3
     sweeps: int = 10
+    alpha2: float = 0.0         # Laplacian weight of MON_GRADLAP
 
 
 @dataclasses.dataclass
@@ -546,11 +548,17 @@ def vortex_mesh(grid: Grid, t: float):
     return x, xdot
 
 
-def rmhd_vortex(dim: int, n: int, t: float = 0.0, dissipation: int = 0) -> Workload:
+def rmhd_vortex(dim: int, n: int, t: float = 0.0, dissipation: int = 0,
+                adaptive: bool = False) -> Workload:
     """The RMHD vortex example of Section 6 in 2D (N x N nodes on [-R, R]^2, run to
     t = 4) or 3D (N x N x 5N nodes on [-R, R]^2 x [-5R, 5R], run to t = 0.1),
-    periodic, Gamma = 5/3, at time t on the prescribed moving mesh at t (the EC
-    scheme MM-O6 by default; dissipation = 1 gives the ES scheme on that mesh)."""
+    periodic, Gamma = 5/3, CFL 0.4, with the state at time t.  adaptive = False: the
+    prescribed moving mesh at t (MM-O6 with the EC scheme, dissipation = 0;
+    dissipation = 1 runs the ES scheme on it).  adaptive = True: the uniform mesh
+    and the adaptive redistribution with the monitor of eq.
+    RMHD_2DVortex_Monitor, sigma = rho, alpha = 20 on the gradient and 10 on the
+    Laplacian, 3 filter passes and 10 Jacobi sweeps (MM-O5 with dissipation = 1;
+    the 3D example takes a monitor like the 2D one)."""
     R = VORTEX_R
     if dim == 2:
         g = make_grid(2, (n, n, 1), (PERIODIC, PERIODIC, PERIODIC), lo=(-R, -R, 0.0),
@@ -558,15 +566,20 @@ def rmhd_vortex(dim: int, n: int, t: float = 0.0, dissipation: int = 0) -> Workl
     else:
         g = make_grid(3, (n, n, 5 * n), (PERIODIC, PERIODIC, PERIODIC), lo=(-R, -R, -5 * R),
                       length=(2 * R, 2 * R, 10 * R))
-    x, _ = vortex_mesh(g, t)
+    if adaptive:
+        x = uniform_mesh(g)
+        mon = Monitor(enabled=1, sigma=SIGMA_RHO, form=MON_GRADLAP, alpha=20.0, alpha2=10.0,
+                      filter_passes=3, sweeps=10)
+    else:
+        x, _ = vortex_mesh(g, t)
+        mon = Monitor(enabled=0)
     if dim == 2:
         rho, v, p, B = vortex2d_state(x[0], x[1], t)
     else:
         rho, v, p, B = vortex3d_state(x[0], x[1], x[2], t)
-    return Workload("rmhd%dd_vortex_%d" % (dim, n), g,
-                    Scheme(phys=RMHD, gamma=VORTEX_GAMMA, cfl=0.4, dissipation=dissipation),
-                    Monitor(enabled=0), _prim(rho, v, p, B), x, steps=0,
-                    t_end=4.0 if dim == 2 else 0.1)
+    return Workload("rmhd%dd_vortex_%s_%d" % (dim, "mm_adaptive" if adaptive else "mm_prescribed", n), g,
+                    Scheme(phys=RMHD, gamma=VORTEX_GAMMA, cfl=0.4, dissipation=dissipation), mon,
+                    _prim(rho, v, p, B), x, steps=0, t_end=4.0 if dim == 2 else 0.1)
 
 
 # ---------------------------------------------------------------------------

@@ -116,10 +116,15 @@ def test_cfl_time_step(dim, n, bc):
                                                  (2, (75, 66, 1), (0, 1, 0), 0, 0),
                                                  (3, (70, 9, 8), (0, 0, 0), 0, 0),
                                                  (3, (10, 66, 9), (1, 1, 1), 0, 1),
-                                                 (3, (9, 8, 64), (0, 1, 1), 1, 0)])
+                                                 (3, (9, 8, 64), (0, 1, 1), 1, 0),
+                                                 (2, (75, 66, 1), (0, 1, 0), 2, 0),
+                                                 (2, (64, 70, 1), (1, 1, 0), 2, 1),
+                                                 (3, (10, 66, 9), (1, 0, 1), 2, 0)])
 def test_mesh_redistribution(dim, n, bc, form, sigma):
-    mon = wl.Monitor(enabled=1, sigma=sigma, form=form, alpha=10.0 if form else 1200.0,
-                     filter_passes=3, sweeps=10)
+    # forms: 0 paper (alpha 1200), 1 squared gradient (alpha 10), 2 gradient +
+    # Laplacian (alpha 20 and 10, the vortex examples)
+    mon = wl.Monitor(enabled=1, sigma=sigma, form=form, alpha=(1200.0, 10.0, 20.0)[form],
+                     filter_passes=3, sweeps=10, alpha2=10.0)
     case = Case(dim, n, bc, seed=7, smooth=True, monitor=mon)
     c = case.ctx
     U, J = case.gpu_state()

@@ -4,8 +4,11 @@
   against the oracle's step with the same mesh velocity and dt, in 2D and 3D, EC
   and ES, on the prescribed moving mesh of the example at t = 1 (mesh velocity
   not zero).
-* The EC scheme on the prescribed moving mesh (MM-O6) run to t = 0.1 on the 3D
-  vortex: the error of rho against the closed form falls at the design order.
+* One adaptive step (ES scheme, gradient + Laplacian monitor: MM-O5) against the
+  oracle's step, in 2D and 3D.
+* The EC scheme on the prescribed moving mesh (MM-O6) and the ES scheme on the
+  adaptive mesh (MM-O5) run to t = 0.1 on the 3D vortex: the error of rho against
+  the closed form falls at the design order.
 """
 import numpy as np
 import pytest
@@ -65,13 +68,47 @@ def test_rk3_step_moving_matches_oracle(dim, n, diss):
             assert np.max(np.abs(Ug[c] - out["U"][c])) <= tol * sc, (c, np.max(np.abs(Ug[c] - out["U"][c])) / sc)
 
 
-def _vortex3d_rho_error(n, t_end=0.1, steps=100):
-    w = wl.rmhd_vortex(3, n, t=0.0, dissipation=0)
+# the EC scheme leaves the admissible set in its first stage at the CFL step on
+# the coarse 3D meshes (the oracle too, up to N = 12); it is compared at N = 16
+# with a quarter of the CFL step
+@pytest.mark.parametrize("dim,n,diss,dt_fixed", [(2, 40, 0, None), (2, 40, 1, None),
+                                                 (3, 16, 0, 0.024), (3, 10, 1, None)])
+def test_rk3_step_vortex_adaptive_matches_oracle(dim, n, diss, dt_fixed):
+    w = wl.rmhd_vortex(dim, n, dissipation=diss, adaptive=True)
+    ctx, P, U, J, x = _gpu_setup(w)
+    xd = empty(dim, *ctx.shape())
+    dt = empty(1)
+    ctx.rk3_step(U, J, x, xd, dt, None if dt_fixed is None else dev(np.array([dt_fixed])))
+    assert ctx.status()[0] == es.ES_OK
+    Uo, Jo = st.initial_state(w.grid, w.scheme, P, w.x)
+    out = st.rk3_step(w.grid, w.scheme, w.monitor, Uo, Jo, w.x, dt=dt_fixed)
+    assert out["ok"].all()
+    assert abs(host(dt)[0] - out["dt"]) <= 1e-12 * out["dt"]
+    assert np.max(np.abs(host(x) - out["x"])) <= 1e-12
+    assert np.max(np.abs(host(x) - w.x)) > 1e-4          # the mesh did move
+    Ug = host(U)
+    big = np.max(np.abs(out["U"]))
+    # ES: for a 1e-15 relative perturbation of its input the oracle's own adaptive
+    # step moves by up to 1e-7 (B_2, this coarse 3D vortex: weak field, so the
+    # Alfven and slow speeds sit close to the entropy speed); the bar is ten times
+    # that.  EC: no eigen-structure, the per-call bar.
+    tol = ((2e-9 if dim == 2 else 1e-6) if diss else 1e-12)
+    for c in range(ctx.m):
+        sc = max(np.max(np.abs(out["U"][c])), 1e-3 * big)
+        assert np.max(np.abs(Ug[c] - out["U"][c])) <= tol * sc, (c, np.max(np.abs(Ug[c] - out["U"][c])) / sc)
+
+
+def _vortex3d_rho_error(n, adaptive=False, t_end=0.1, steps=100):
+    w = wl.rmhd_vortex(3, n, t=0.0, dissipation=int(adaptive), adaptive=adaptive)
     ctx, _, U, J, x = _gpu_setup(w)
     dt = t_end / steps
     dt_dev = empty(1)
     fixed = dev(np.array([dt]))
+    xd = empty(3, *ctx.shape())
     for k in range(steps):
+        if adaptive:
+            ctx.rk3_step(U, J, x, xd, dt_dev, fixed)
+            continue
         # the mesh velocity that carries the nodes from the prescribed mesh at t_k to
         # the one at t_k + dt
         xa, _ = wl.vortex_mesh(w.grid, k * dt)
@@ -82,9 +119,21 @@ def _vortex3d_rho_error(n, t_end=0.1, steps=100):
     assert ctx.status()[0] == es.ES_OK
     rho = host(prim)[0, 3:-3, 3:-3, 3:-3]
     xe = host(x)
-    np.testing.assert_allclose(xe, wl.vortex_mesh(w.grid, t_end)[0], rtol=0, atol=1e-12)
+    if not adaptive:
+        np.testing.assert_allclose(xe, wl.vortex_mesh(w.grid, t_end)[0], rtol=0, atol=1e-12)
     exact = wl.vortex3d_state(xe[0], xe[1], xe[2], t_end)[0]
     return np.mean(np.abs(rho - exact))
+
+
+def test_vortex3d_es_adaptive_mesh_order():
+    # MM-O5 of the 3D example (ES scheme, adaptive mesh with the gradient +
+    # Laplacian monitor, fixed small dt): on these meshes the WENO weights still
+    # lose accuracy at the profile's extrema and the rate climbs towards 5
+    # (observed 3.1 from 24 to 32, 3.4 from 32 to 48)
+    e = np.array([_vortex3d_rho_error(n, adaptive=True) for n in (24, 32, 48)])
+    rates = np.log(e[:-1] / e[1:]) / np.log(np.array([32 / 24, 48 / 32]))
+    print("vortex3d MM-O5 rho L1 errors", e, "rates", rates)
+    assert np.all(np.diff(e) < 0) and rates[-1] > 3.0, (e, rates)
 
 
 def test_vortex3d_ec_moving_mesh_order():

@@ -95,6 +95,54 @@ def test_monitor_forms_on_linear_sigma():
     np.testing.assert_array_equal(msh.monitor(g, mon, P), 1.0)
 
 
+def test_laplacian_xi_closed_forms():
+    # a quadratic on a bounded grid: every three-point second difference (central
+    # or one-sided) is exact, Lap_xi sigma = 2 a L_1^2 + 2 b L_2^2 (x = lo + L xi)
+    g = wl.make_grid(2, (9, 7, 1), (1, 1, 0), lo=(0.3, -0.2, 0.0), length=(2.0, 1.5, 1.0))
+    x = wl.uniform_mesh(g)
+    s = 0.7 * x[0] ** 2 - 1.1 * x[1] ** 2 + 0.4 * x[0] * x[1] + x[0]
+    np.testing.assert_allclose(msh.laplacian_xi(g, s), 2 * 0.7 * 4.0 - 2 * 1.1 * 2.25, rtol=1e-12)
+    # a sinusoid on a periodic 3D grid: the central difference scales it by
+    # (2 cos(2 pi k h) - 2) / h^2 per axis
+    g = wl.make_grid(3, (8, 10, 12), (0, 0, 0))
+    x = wl.uniform_mesh(g)
+    s = np.sin(2 * np.pi * (x[0] + 2 * x[1] + 3 * x[2]))
+    fac = sum((2 * np.cos(2 * np.pi * k / n) - 2) * n * n for k, n in ((1, 8), (2, 10), (3, 12)))
+    np.testing.assert_allclose(msh.laplacian_xi(g, s), fac * s, rtol=1e-10, atol=1e-9)
+
+
+def test_gradlap_monitor_matches_brute_force():
+    # node-by-node loops with explicit index wrap / one-sided stencils on a tiny
+    # mixed-boundary grid
+    rng = np.random.default_rng(5)
+    g = wl.make_grid(2, (7, 6, 1), (0, 1, 0))
+    P = np.zeros((8,) + g.shape)
+    P[0] = rng.uniform(0.5, 2.0, g.shape)
+    mon = wl.Monitor(enabled=1, sigma=1, form=2, alpha=20.0, alpha2=10.0)
+    sig = np.log(P[0])
+    n0, n1 = g.n[0], g.n[1]
+    h0, h1 = g.dxi[0], g.dxi[1]
+    grad = np.zeros(g.shape)
+    lap = np.zeros(g.shape)
+    for j in range(n1):
+        for i in range(n0):
+            d0 = (sig[j, (i + 1) % n0] - sig[j, (i - 1) % n0]) / (2 * h0)
+            l0 = (sig[j, (i + 1) % n0] - 2 * sig[j, i] + sig[j, (i - 1) % n0]) / h0 ** 2
+            if j == 0:
+                d1 = (sig[1, i] - sig[0, i]) / h1
+                l1 = (sig[2, i] - 2 * sig[1, i] + sig[0, i]) / h1 ** 2
+            elif j == n1 - 1:
+                d1 = (sig[j, i] - sig[j - 1, i]) / h1
+                l1 = (sig[j, i] - 2 * sig[j - 1, i] + sig[j - 2, i]) / h1 ** 2
+            else:
+                d1 = (sig[j + 1, i] - sig[j - 1, i]) / (2 * h1)
+                l1 = (sig[j + 1, i] - 2 * sig[j, i] + sig[j - 1, i]) / h1 ** 2
+            grad[j, i] = np.hypot(d0, d1)
+            lap[j, i] = abs(l0 + l1)
+    want = np.sqrt(1 + 20 * grad / grad.max() + 10 * lap / lap.max())
+    np.testing.assert_allclose(msh.monitor(g, mon, P), want, rtol=1e-13)
+
+
 def test_move_limiter_matches_brute_force_and_keeps_order():
     rng = np.random.default_rng(3)
     for bc in ((0, 0, 0), (1, 1, 0)):
