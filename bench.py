@@ -66,10 +66,14 @@ def parse():
                     choices=["quadrant", "sine", "rotor", "blast3d", "fourier"],
                     help="quadrant: the headline 2D RHD problem; the others time the remaining "
                          "workloads (FP64 step and residual only)")
-    ap.add_argument("--paper-case", default=None, choices=["rp1", "rp2", "rp3", "rmhd_blast", "shock_cloud"],
+    ap.add_argument("--paper-case", default=None,
+                    choices=["rp1", "rp2", "rp3", "rmhd_blast", "shock_cloud", "vortex3d"],
                     help="run one of the paper's 2D examples to its end time as MM-O5 (adaptive) and "
                          "UM-O5 (uniform, finer) and report the GPU time-to-solution ratio beside the "
-                         "paper's CPU ratio (not a headline line)")
+                         "paper's CPU ratio; vortex3d: errors and orders of MM-O6 and MM-O5 on the 3D "
+                         "RMHD vortex (not headline lines)")
+    ap.add_argument("--vortex-n", default="16,24,32,48,64",
+                    help="mesh sizes N (N x N x 5N nodes) of the vortex3d study")
     ap.add_argument("--no-fourier-gradient", action="store_true",
                     help="skip the gradient study of the adjoint configuration (objects adjoint_fourier*)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -395,6 +399,78 @@ def paper_case(args):
     print(json.dumps(line))
 
 
+def vortex_run(n, adaptive, t_end=0.1, max_wall_s=150.0):
+    """The 3D RMHD vortex to t_end: MM-O6 (EC scheme, prescribed mesh, dt = CFL
+    dxi^2) or MM-O5 (ES scheme, adaptive mesh with the gradient + Laplacian
+    monitor, dt = CFL dxi^(5/3)), dxi = 1/N the computational spacing, the last
+    step shortened so that the run ends at t_end.  Returns the L1 and max errors
+    of rho against the closed form and the GPU time (HIP events)."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2107_12027_amd import workloads as wl
+    w = wl.rmhd_vortex(3, n, 0.0, dissipation=int(adaptive), adaptive=adaptive)
+    run = Run(w, 0)
+    ctx = run.ctx
+    power = 5.0 / 3.0 if adaptive else 2.0
+    steps = int(math.ceil(t_end / (w.scheme.cfl * (1.0 / n) ** power) - 1e-9))
+    dt = t_end / steps
+    fixed = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    shape = torch.from_numpy(wl.vortex_mesh_shape(w.grid)[1]).cuda()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    done = 0
+    while done < steps:
+        for k in range(done, min(steps, done + 64)):
+            if adaptive:
+                ctx.rk3_step(run.U, run.J, run.x, run.xdot, run.dt, fixed)
+            else:
+                da = wl.vortex_mesh_amplitude((k + 1) * dt) - wl.vortex_mesh_amplitude(k * dt)
+                torch.mul(shape, da / dt, out=run.xdot)
+                ctx.rk3_step_moving(run.U, run.J, run.x, run.xdot, run.dt, fixed)
+        done = min(steps, done + 64)
+        torch.cuda.synchronize()
+        if time.perf_counter() - t_wall > max_wall_s:
+            break
+    e1.record(stream)
+    torch.cuda.synchronize()
+    status, nfail, _ = ctx.status()
+    out = {"n": n, "nodes": w.grid.nnodes, "steps": done, "dt": dt, "t": done * dt,
+           "gpu_s": e0.elapsed_time(e1) * 1e-3, "status": int(status)}
+    if status == 0 and done == steps:
+        ctx.con2prim(run.U, run.J, run.prim)
+        rho = run.prim[0, 3:-3, 3:-3, 3:-3].cpu().numpy()
+        x = run.x.cpu().numpy()
+        exact = wl.vortex3d_state(x[0], x[1], x[2], t_end)[0]
+        out["l1_rho"] = float(np.mean(np.abs(rho - exact)))
+        out["linf_rho"] = float(np.max(np.abs(rho - exact)))
+    return out
+
+
+def vortex_study(args):
+    """Errors and orders of MM-O6 and MM-O5 on the 3D RMHD vortex (Section 6)."""
+    import math
+    ns = [int(v) for v in args.vortex_n.split(",")]
+    line = {"paper_case": "vortex3d", "t_end": 0.1, "dtype": "f64",
+            "data": "synthetic (the paper's closed-form initial data)"}
+    for name, adaptive in (("mm_o6", False), ("mm_o5", True)):
+        runs = []
+        for n in ns:
+            r = vortex_run(n, adaptive)
+            runs.append(r)
+            print("vortex3d %s N=%d: %s" % (name, n, json.dumps(r)), file=sys.stderr, flush=True)
+        rates = []
+        for a, b in zip(runs[:-1], runs[1:]):
+            ok = "l1_rho" in a and "l1_rho" in b
+            rates.append(math.log(a["l1_rho"] / b["l1_rho"]) / math.log(b["n"] / a["n"]) if ok else None)
+        line[name] = {"runs": runs, "rates_l1_rho": rates}
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -404,6 +480,8 @@ def main():
     from paper_2107_12027_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.paper_case == "vortex3d":
+        return vortex_study(args)
     if args.paper_case is not None:
         return paper_case(args)
     if args.workload != "quadrant":

@@ -525,15 +525,15 @@ def vortex3d_state(x1, x2, x3, t):
     return rho, v, p, B
 
 
-def vortex_mesh(grid: Grid, t: float):
-    """Prescribed node motion of the vortex accuracy tests (eq.
-    RMHD_2DVortex_MovingMesh, eq. RMHD_3DVortex_MovingMesh): the nodes x° of the
-    uniform periodic mesh displaced by 0.2 cos(pi t / 4) times
-    (sin(3 pi x°_2/R), sin(3 pi x°_1/R)) in 2D and
-    (s_2 s_3, s_3 s_1, s_1 s_2), s_k = sin(3 pi x°_k / L_k) with L = (R, R, 5R), in
-    3D.  Returns (x, xdot) at time t.  The paper's x° = 2 i R/(N-1) lists both ends
-    of a period on a periodic axis; the nodes here are x° = -R + i L/N of the
-    periodic grid (same displacement field up to its sign)."""
+def vortex_mesh_shape(grid: Grid):
+    """(x°, s) of the prescribed node motion of the vortex accuracy tests (eq.
+    RMHD_2DVortex_MovingMesh, eq. RMHD_3DVortex_MovingMesh): the mesh at time t is
+    x° + a(t) s with a(t) = 0.2 cos(pi t / 4), x° the nodes of the uniform periodic
+    mesh and s = (sin(3 pi x°_2/R), sin(3 pi x°_1/R)) in 2D,
+    (s_2 s_3, s_3 s_1, s_1 s_2), s_k = sin(3 pi x°_k / L_k), L = (R, R, 5R), in 3D.
+    The paper's x° = 2 i R/(N-1) lists both ends of a period on a periodic axis;
+    the nodes here are x° = -R + i L/N of the periodic grid (the same displacement
+    field up to its sign)."""
     xr = uniform_mesh(grid)
     R = VORTEX_R
     if grid.dim == 2:
@@ -543,9 +543,18 @@ def vortex_mesh(grid: Grid, t: float):
         s2 = np.sin(3 * np.pi * xr[1] / R)
         s3 = np.sin(3 * np.pi * xr[2] / (5 * R))
         shape = np.stack([s2 * s3, s3 * s1, s1 * s2])
-    x = xr + 0.2 * np.cos(np.pi * t / 4) * shape
-    xdot = -0.05 * np.pi * np.sin(np.pi * t / 4) * shape
-    return x, xdot
+    return xr, shape
+
+
+def vortex_mesh_amplitude(t: float) -> float:
+    """a(t) = 0.2 cos(pi t / 4) of the prescribed vortex mesh motion."""
+    return 0.2 * math.cos(math.pi * t / 4.0)
+
+
+def vortex_mesh(grid: Grid, t: float):
+    """(x, xdot) of the prescribed vortex mesh motion at time t."""
+    xr, shape = vortex_mesh_shape(grid)
+    return xr + vortex_mesh_amplitude(t) * shape, -0.05 * math.pi * math.sin(math.pi * t / 4.0) * shape
 
 
 def rmhd_vortex(dim: int, n: int, t: float = 0.0, dissipation: int = 0,

@@ -105,15 +105,16 @@ def _vortex3d_rho_error(n, adaptive=False, t_end=0.1, steps=100):
     dt_dev = empty(1)
     fixed = dev(np.array([dt]))
     xd = empty(3, *ctx.shape())
+    shape = dev(wl.vortex_mesh_shape(w.grid)[1])
     for k in range(steps):
         if adaptive:
             ctx.rk3_step(U, J, x, xd, dt_dev, fixed)
             continue
         # the mesh velocity that carries the nodes from the prescribed mesh at t_k to
         # the one at t_k + dt
-        xa, _ = wl.vortex_mesh(w.grid, k * dt)
-        xb, _ = wl.vortex_mesh(w.grid, (k + 1) * dt)
-        ctx.rk3_step_moving(U, J, x, dev((xb - xa) / dt), dt_dev, fixed)
+        da = wl.vortex_mesh_amplitude((k + 1) * dt) - wl.vortex_mesh_amplitude(k * dt)
+        torch.mul(shape, da / dt, out=xd)
+        ctx.rk3_step_moving(U, J, x, xd, dt_dev, fixed)
     prim = empty(ctx.nprim, *ctx.padded_shape())
     ctx.con2prim(U, J, prim)
     assert ctx.status()[0] == es.ES_OK
