@@ -224,11 +224,12 @@ es_status es_rk3_step_vjp(es_ctx* ctx, const double* ckpt, const double* lamU, c
 es_status es_residual_vjp(es_ctx* ctx, const double* Ucurv, const double* J, const double* met,
                           const double* lamU, double* gU, double* gJ, hipStream_t stream);
 
-/* Replay es_rk3_step as a HIP graph (default 1) or launch its kernels one by
- * one (0).  In graph mode the step is captured on the context's own stream the
- * first time it is called with a given set of array pointers and replayed
- * afterwards, ordered after and before the caller's stream with events; the
- * results are those of the eager launch sequence. */
+/* Replay es_rk3_step and es_rk3_step_moving as a HIP graph (default 1) or
+ * launch their kernels one by one (0).  In graph mode the step is captured on
+ * the context's own stream the first time it is called with a given set of
+ * array pointers (captured again when they change) and the graph is launched
+ * into the caller's stream, ordered with its other work; the results are those
+ * of the eager launch sequence. */
 es_status es_set_graph(es_ctx* ctx, int enable);
 
 /* FP64 diagnostics on the interior (Theorem 4.1 / 5.1, Section 6 total entropy):
