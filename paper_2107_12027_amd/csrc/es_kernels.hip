@@ -788,6 +788,11 @@ struct DtFinal {
 };
 
 __device__ __forceinline__ void finalize_dt(const DtFinal& f, double* sh) {
+    // a prescribed dt needs no reduction (the same branch for the whole block)
+    if (f.fixed_dt != nullptr) {
+        if (flat_tid() == 0) f.dt_out[0] = f.fixed_dt[0];
+        return;
+    }
     double tot = 0.0;
     const int tid = flat_tid(), nt = (int)(blockDim.x * blockDim.y * blockDim.z);
     for (int kd = 0; kd < f.dim; ++kd) {
@@ -1548,6 +1553,11 @@ hipError_t launch_cfl_mesh(const es_ctx* c, const double* prim, const double* x,
     const GridDev& g = c->g;
     if (monitor_done != nullptr) *monitor_done = false;
     if (c->scheme.phys == ES_RMHD || g.dim != 2) {
+        if (fixed_dt_dev != nullptr) {
+            // a prescribed dt: no speeds needed (finalised here or by the mesh launches)
+            if (!defer_final) k_cfl_final<<<1, 256, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
+            return hipGetLastError();
+        }
         const hipError_t e = launch_metrics(c, x, nullptr, nullptr, 0.0, c->met, nullptr, s);
         if (e != hipSuccess) return e;
         return launch_cfl(c, prim, c->met, J, dt_dev, fixed_dt_dev, s, defer_final);

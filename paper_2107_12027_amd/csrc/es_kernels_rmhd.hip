@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(256) k_cfl_partial_rmhd(GridDev g, double G, c
             rotation<3>(n, T);
             double Pr[MR];
             rotate8<false>(T, Pv, Pr);
-            const double r = L * rmhd_max_speed(G, Pr, 0.0, 1.0) * iJ;
+            const double r = L * rmhd_max_speed(G, Pr) * iJ;
             if (kd == 0) mx[0] = r;
             else if (kd == 1) mx[DIM > 1 ? 1 : 0] = r;
             else mx[DIM - 1] = r;
