@@ -380,60 +380,72 @@ __device__ __forceinline__ void invert(double A[N][N], double X[N][N]) {
     }
 }
 
-// Cyclic Jacobi eigen-decomposition of a symmetric matrix A (overwritten by the
-// eigenvalues on its diagonal); Zv (optional) accumulates the rotations, so its
-// columns are the orthonormal eigenvectors.  Stops when the off-diagonal part
-// is below 1e-30 of the diagonal (squared) or after 12 sweeps.
-template <int N, bool VEC>
-__device__ __forceinline__ void jacobi_eigen(double A[N][N], double Zv[N][N]) {
-    if (VEC) {
+// Cyclic Jacobi eigen-decomposition of the symmetric 8x8 matrix Q held as its
+// lower triangle (36 entries: only what a symmetric rotation changes is
+// updated).  lam receives the eigenvalues, the columns of Zv the orthonormal
+// eigenvectors.  Rotation (p, q): t = sgn(th)/(|th| + sqrt(th^2 + 1)),
+// th = (a_qq - a_pp)/(2 a_pq), c = 1/sqrt(t^2 + 1), s = t c, tau = s/(1 + c):
+// a_pp -= t a_pq, a_qq += t a_pq, a_pq = 0, and for r != p, q
+// a_rp -= s (a_rq + tau a_rp), a_rq += s (a_rp - tau a_rq) (the same for the
+// rows of Zv).  An element below 1e-18 of its diagonal pair is set to zero
+// instead of rotated; the sweeps stop when the off-diagonal part is below
+// 1e-30 of the diagonal (squared) or after 12 sweeps.
+__device__ __forceinline__ constexpr int tri8(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+__device__ __forceinline__ void jacobi_eigen_sym8(const double Q[8][8], double lam[8], double Zv[8][8]) {
+    double a[36];
 #pragma unroll
-        for (int r = 0; r < N; ++r)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-            for (int c = 0; c < N; ++c) Zv[r][c] = r == c ? 1.0 : 0.0;
-    }
+        for (int j = 0; j <= i; ++j) a[tri8(i, j)] = Q[i][j];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) Zv[r][c] = r == c ? 1.0 : 0.0;
 #pragma unroll 1
     for (int sweep = 0; sweep < 12; ++sweep) {
         double off = 0.0, dia = 0.0;
 #pragma unroll
-        for (int p = 0; p < N; ++p) {
-            dia += A[p][p] * A[p][p];
+        for (int i = 0; i < 8; ++i) {
+            dia += a[tri8(i, i)] * a[tri8(i, i)];
 #pragma unroll
-            for (int q = p + 1; q < N; ++q) off += A[p][q] * A[p][q];
+            for (int j = 0; j < i; ++j) off += a[tri8(i, j)] * a[tri8(i, j)];
         }
         if (!(off > 1e-30 * dia)) break;
 #pragma unroll
-        for (int p = 0; p < N; ++p) {
+        for (int p = 0; p < 8; ++p) {
 #pragma unroll
-            for (int q = p + 1; q < N; ++q) {
-                const double apq = A[p][q];
-                if (apq == 0.0) continue;
-                const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+            for (int q = p + 1; q < 8; ++q) {
+                const double apq = a[tri8(q, p)];
+                const double app = a[tri8(p, p)], aqq = a[tri8(q, q)];
+                if (fabs(apq) <= 1e-18 * (fabs(app) + fabs(aqq))) {
+                    a[tri8(q, p)] = 0.0;
+                    continue;
+                }
+                const double th = (aqq - app) / (2.0 * apq);
                 const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c, tau = sn / (1.0 + c);
+                a[tri8(p, p)] = app - t * apq;
+                a[tri8(q, q)] = aqq + t * apq;
+                a[tri8(q, p)] = 0.0;
 #pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    const double akp = A[k][p], akq = A[k][q];
-                    A[k][p] = c * akp - s * akq;
-                    A[k][q] = s * akp + c * akq;
+                for (int r = 0; r < 8; ++r) {
+                    if (r == p || r == q) continue;
+                    const double arp = a[tri8(r, p)], arq = a[tri8(r, q)];
+                    a[tri8(r, p)] = arp - sn * (arq + tau * arp);
+                    a[tri8(r, q)] = arq + sn * (arp - tau * arq);
                 }
 #pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    const double apk = A[p][k], aqk = A[q][k];
-                    A[p][k] = c * apk - s * aqk;
-                    A[q][k] = s * apk + c * aqk;
-                }
-                if (VEC) {
-#pragma unroll
-                    for (int k = 0; k < N; ++k) {
-                        const double zkp = Zv[k][p], zkq = Zv[k][q];
-                        Zv[k][p] = c * zkp - s * zkq;
-                        Zv[k][q] = s * zkp + c * zkq;
-                    }
+                for (int r = 0; r < 8; ++r) {
+                    const double zp = Zv[r][p], zq = Zv[r][q];
+                    Zv[r][p] = zp - sn * (zq + tau * zp);
+                    Zv[r][q] = zq + sn * (zp - tau * zq);
                 }
             }
         }
     }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lam[i] = a[tri8(i, i)];
 }
 
 // Symmetric pencil of the eigenproblem in entropy variables: A0 = dU/dV =
@@ -588,13 +600,13 @@ __device__ __forceinline__ void rotate8(const double T[3][3], const double* a, d
 // e_{B_n} first, the others e_1, e_2, ...  A seed contributes when what is left of
 // its projection exceeds SEED_TOL times its A0^{-1} norm.  In z-space (r = L z)
 // the A0^{-1} products are Euclidean and r_a^T A0^{-1} e_s = z_a . (L^{-1} e_s).
-// Writes canon[k] = z-space column of position k (a member of k's group).
+// Writes Rc[k] = L z for the canonical vector z of position k (a member of k's
+// group); Zv (the eigenvectors z_a as columns) is overwritten by R = L Z.
 constexpr double GROUP_TOL = 1e-6;
 constexpr double SEED_TOL = 1e-3;
 
-__device__ __forceinline__ void canonical_groups(const double* lam, const double Zv[8][8],
-                                                 const double Lc[8][8], double vn,
-                                                 double canon[8][8]) {
+__device__ __forceinline__ void canonical_columns(const double* lam, double Zv[8][8],
+                                                  const double Lc[8][8], double vn, double Rc[8][8]) {
     // group labels: smallest index reachable through chains of close eigenvalues
     int lab[8];
 #pragma unroll
@@ -617,73 +629,105 @@ __device__ __forceinline__ void canonical_groups(const double* lam, const double
         for (int k = 1; k < 8; ++k)
             if (fabs(lam[k] - vn) < e) { e = fabs(lam[k] - vn); labc = lab[k]; }
     }
-    // L^{-1} (lower triangular) and the seed coefficients C[a][s] = z_a . L^{-1} e_s
-    double Li[8][8];
+    // seed coefficients C[a][s] = z_a . (L^{-1} e_s) and |L^{-1} e_s|
+    double C[8][8], yn[8];
 #pragma unroll
-    for (int sd = 0; sd < 8; ++sd)
+    for (int sd = 0; sd < 8; ++sd) {
+        double li[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             double v = i == sd ? 1.0 : 0.0;
 #pragma unroll
-            for (int k = 0; k < i; ++k) v -= Lc[i][k] * Li[k][sd];
-            Li[i][sd] = v / Lc[i][i];
+            for (int k = 0; k < i; ++k) v -= Lc[i][k] * li[k];
+            li[i] = v / Lc[i][i];
         }
-    double yn[8], C[8][8];
-#pragma unroll
-    for (int sd = 0; sd < 8; ++sd) {
         double q = 0.0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) q += Li[i][sd] * Li[i][sd];
+        for (int i = 0; i < 8; ++i) q += li[i] * li[i];
         yn[sd] = sqrt(q);
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
             double c = 0.0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) c += Zv[i][a] * Li[i][sd];
+            for (int i = 0; i < 8; ++i) c += Zv[i][a] * li[i];
             C[a][sd] = c;
         }
     }
+    // R = L Z in place (row i of R needs rows 0..i of Z)
+#pragma unroll
+    for (int i = 7; i >= 0; --i)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k <= i; ++k) sum += Lc[i][k] * Zv[k][a];
+            Zv[i][a] = sum;
+        }
+    // Gram-Schmidt in the coordinates of the orthonormal z_a: at slot t every group
+    // projects its seed of slot t (e_D, e_{B_n}, e_1, ... for the group of v_n; e_t
+    // for the others), removes the components along its members accepted so far,
+    // and gives the remainder, normalised, to its next member when it exceeds
+    // SEED_TOL |L^{-1} e_s| (the groups have disjoint supports, so they proceed
+    // side by side).  W[k] holds the coordinates of the basis vector of position k.
     constexpr int SC[8] = {0, 5, 1, 2, 3, 4, 6, 7};
+    double W[8][8];
+    bool acc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const bool isc = lab[k] == labc;
-        bool done = false;
+        acc[k] = false;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) canon[k][i] = 0.0;
+        for (int a = 0; a < 8; ++a) W[k][a] = 0.0;
+    }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            double p[8];
+    for (int t = 0; t < 8; ++t) {
+        double r[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) p[i] = 0.0;
+        for (int a = 0; a < 8; ++a) r[a] = lab[a] == labc ? C[a][SC[t]] : C[a][t];
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                if (lab[a] != lab[k]) continue;
-                const double coef = isc ? C[a][SC[t]] : C[a][t];
+        for (int k = 0; k < 8; ++k) {
+            if (!acc[k]) continue;
+            double ip = 0.0;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) p[i] += coef * Zv[i][a];
-            }
+            for (int a = 0; a < 8; ++a) ip += W[k][a] * r[a];
 #pragma unroll
-            for (int j = 0; j < k; ++j) {
-                if (lab[j] != lab[k]) continue;
-                double ip = 0.0;
+            for (int a = 0; a < 8; ++a) r[a] -= ip * W[k][a];
+        }
+        bool placed[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) ip += canon[j][i] * p[i];
+        for (int k = 0; k < 8; ++k) placed[k] = acc[k];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) p[i] -= ip * canon[j][i];
-            }
+        for (int k = 0; k < 8; ++k) {
+            if (acc[k]) continue;
+            // k may take this slot when all earlier members of its group were placed
+            // at earlier slots (one member per group and slot)
+            bool next = true;
+#pragma unroll
+            for (int j = 0; j < k; ++j)
+                if (lab[j] == lab[k] && !placed[j]) next = false;
+            if (!next) continue;
             double nn = 0.0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) nn += p[i] * p[i];
+            for (int a = 0; a < 8; ++a) nn += lab[a] == lab[k] ? r[a] * r[a] : 0.0;
             nn = sqrt(nn);
-            const double ys = isc ? yn[SC[t]] : yn[t];
-            if (!done && nn > SEED_TOL * ys) {
+            const double ys = lab[k] == labc ? yn[SC[t]] : yn[t];
+            if (nn > SEED_TOL * ys) {
                 const double inn = 1.0 / nn;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) canon[k][i] = p[i] * inn;
-                done = true;
+                for (int a = 0; a < 8; ++a) W[k][a] = lab[a] == lab[k] ? r[a] * inn : 0.0;
+                acc[k] = true;
             }
         }
     }
+    // columns of R for the canonical basis: R_c[k] = R W[k]
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double sum = 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; ++a) sum += Zv[i][a] * W[k][a];
+            Rc[k][i] = sum;
+        }
 }
 
 // Face frame and eigen-structure of the RMHD dissipation at face i+1/2 (shared by
@@ -732,23 +776,13 @@ __device__ __forceinline__ void face_eigen_rmhd(double G, const double* P2, cons
     double JU[8][8], JF[8][8], JV[8][8], Pp[8], Lc[8][8], Q[8][8], Zv[8][8];
     rmhd_jacobians(G, Pf, JU, JF, JV, Pp);
     rmhd_pencil(JU, JF, JV, Lc, Q);
-    jacobi_eigen<8, true>(Q, Zv);
     double lam[8];
+    jacobi_eigen_sym8(Q, lam, Zv);
     lhat = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) { lam[k] = Q[k][k]; lhat = fmax(lhat, fabs(at + L * lam[k])); }
+    for (int k = 0; k < 8; ++k) lhat = fmax(lhat, fabs(at + L * lam[k]));
     // canonical basis in every group of (nearly) equal eigenvalues
-    double canon[8][8];
-    canonical_groups(lam, Zv, Lc, vn, canon);
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            double sum = 0.0;
-#pragma unroll
-            for (int kk = 0; kk <= i; ++kk) sum += Lc[i][kk] * canon[k][kk];
-            Rc[k][i] = sum;
-        }
+    canonical_columns(lam, Zv, Lc, vn, Rc);
 }
 
 // ES dissipation for RMHD at one face (eq. ESFlux_HO): as face_diss_rhd with
@@ -757,7 +791,7 @@ __device__ __forceinline__ void face_eigen_rmhd(double G, const double* P2, cons
 // W = -V_5/beta, ln rho = V_1 - G/(G-1) - ln(beta)/(G-1) - beta, p = rho/beta,
 // b = V_6..8/beta, b^0 = u.b/W, B = W b - b^0 u), and R from the symmetric pencil
 // (A0, S) of the Godunov-Powell modified Jacobian, with the canonical basis in
-// every group of nearly equal eigenvalues (canonical_groups; the group of v_n
+// every group of nearly equal eigenvalues (canonical_columns; the group of v_n
 // holds the entropy and div B waves and is seeded with e_D, e_{B_n}).
 // nodes: the 8 primitive slots of the stencil nodes i-2..i+3.
 template <int DIM, bool MIXED = false>
