@@ -281,7 +281,7 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
 #pragma unroll
                 for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane + 2]; ar[c] = sd[line][F_A + c][lane + 3]; }
                 double T[3][3], TV[6][8], lhat, Rc[8][8];
-                face_eigen_rmhd<DIM>(G, P2, P3, al, ar, T, TV[2], TV[3], lhat, Rc);
+                face_eigen_rmhd<DIM, true>(G, P2, P3, al, ar, T, TV[2], TV[3], lhat, Rc);
 #pragma unroll
                 for (int j = 0; j < 6; ++j) {
                     if (j == 2 || j == 3) continue;
