@@ -49,7 +49,7 @@ RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3747.5
 # 1 GiB device copy (FETCH x 2.000, WRITE x 1.000); the summary with its commands
 # is profiles/es_residual_hbm_counters_rhd2d_quadrant_400.txt.  Valid for the
 # kernels as they were measured; None for other workloads.
-RESIDUAL_TRAFFIC_BYTES_QUADRANT_400 = 57.75e6
+RESIDUAL_TRAFFIC_BYTES_QUADRANT_400 = 57.73e6
 
 
 def parse():
