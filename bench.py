@@ -424,6 +424,7 @@ def vortex_run(n, adaptive, t_end=0.1, max_wall_s=150.0):
     t_wall = time.perf_counter()
     e0.record(stream)
     done = 0
+    t_print = t_wall
     while done < steps:
         for k in range(done, min(steps, done + 64)):
             if adaptive:
@@ -434,7 +435,11 @@ def vortex_run(n, adaptive, t_end=0.1, max_wall_s=150.0):
                 ctx.rk3_step_moving(run.U, run.J, run.x, run.xdot, run.dt, fixed)
         done = min(steps, done + 64)
         torch.cuda.synchronize()
-        if time.perf_counter() - t_wall > max_wall_s:
+        now = time.perf_counter()
+        if now - t_print > 30.0:
+            print("vortex3d N=%d: %d of %d steps" % (n, done, steps), file=sys.stderr, flush=True)
+            t_print = now
+        if now - t_wall > max_wall_s:
             break
     e1.record(stream)
     torch.cuda.synchronize()

@@ -561,7 +561,8 @@ def rmhd_vortex(dim: int, n: int, t: float = 0.0, dissipation: int = 0,
                 adaptive: bool = False) -> Workload:
     """The RMHD vortex example of Section 6 in 2D (N x N nodes on [-R, R]^2, run to
     t = 4) or 3D (N x N x 5N nodes on [-R, R]^2 x [-5R, 5R], run to t = 0.1),
-    periodic, Gamma = 5/3, CFL 0.4, with the state at time t.  adaptive = False: the
+    periodic, Gamma = 5/3, CFL 0.4 in 2D and 0.3 in 3D (the paper's numbers for its
+    2D and 3D tests), with the state at time t.  adaptive = False: the
     prescribed moving mesh at t (MM-O6 with the EC scheme, dissipation = 0;
     dissipation = 1 runs the ES scheme on it).  adaptive = True: the uniform mesh
     and the adaptive redistribution with the monitor of eq.
@@ -587,7 +588,8 @@ def rmhd_vortex(dim: int, n: int, t: float = 0.0, dissipation: int = 0,
     else:
         rho, v, p, B = vortex3d_state(x[0], x[1], x[2], t)
     return Workload("rmhd%dd_vortex_%s_%d" % (dim, "mm_adaptive" if adaptive else "mm_prescribed", n), g,
-                    Scheme(phys=RMHD, gamma=VORTEX_GAMMA, cfl=0.4, dissipation=dissipation), mon,
+                    Scheme(phys=RMHD, gamma=VORTEX_GAMMA, cfl=0.4 if dim == 2 else 0.3,
+                           dissipation=dissipation), mon,
                     _prim(rho, v, p, B), x, steps=0, t_end=4.0 if dim == 2 else 0.1)
 
 
