@@ -365,6 +365,9 @@ template <int DIM>
 struct ResidualLDS {
     static constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1, NF = 6 + NU + NA;
     double sd[LINES][NF][NLOAD + 1];
+    // 3D: the flux differences of each lane wait here while the face dissipation
+    // runs (register pressure)
+    double rs[DIM == 3 ? LINES : 1][M + 1][64];
 };
 
 // Orders the LDS accesses of one wavefront: its lanes exchange data only among
@@ -504,6 +507,11 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
     for (int c = 0; c <= M; ++c) R[c] = owner ? -R[c] * idxi : 0.0;
 
     if (ES) {
+        constexpr bool STASH = DIM == 3;
+        if (STASH) {
+#pragma unroll
+            for (int c = 0; c <= M; ++c) lds.rs[line][c][lane] = R[c];
+        }
         // the fence makes the dissipation reload its stencil from LDS instead of
         // keeping the flux phase's node values live (register pressure)
         wave_lds_sync();
@@ -546,6 +554,10 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
                                                   d);
             }
         }
+        if (STASH) {
+#pragma unroll
+            for (int c = 0; c <= M; ++c) R[c] = lds.rs[line][c][lane];
+        }
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             const double dm = __shfl_up(d[c], 1, 64);
@@ -569,7 +581,7 @@ struct SweepPlan {
 };
 
 template <int DIM, bool ES, bool MIXED, int PO>
-__global__ void __launch_bounds__(256) k_residual_rhd(GridDev g, double G, double eps,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_residual_rhd(GridDev g, double G, double eps,
                                                       const double* __restrict__ prim,
                                                       const double* __restrict__ met,
                                                       double* __restrict__ Ld, SweepPlan sw) {
