@@ -208,6 +208,12 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
 
     if (ES) {
         __syncthreads();
+        // the flux differences wait in the (now free) pair slot 1 while the face
+        // dissipation runs (register pressure)
+        if (owner) {
+#pragma unroll
+            for (int c = 0; c <= MR; ++c) sp[line][1][c][lane] = R[c];
+        }
         if (active && lane >= 2 && s_own < s_end) {
             double Pn[6][MR];
 #pragma unroll
@@ -222,6 +228,8 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
         }
         __syncthreads();
         if (owner) {
+#pragma unroll
+            for (int c = 0; c <= MR; ++c) R[c] = sp[line][1][c][lane];
 #pragma unroll
             for (int c = 0; c < MR; ++c) R[c] += 0.5 * (sp[line][0][c][lane] - sp[line][0][c][lane - 1]) * idxi;
         }
