@@ -67,13 +67,14 @@ def parse():
                     help="quadrant: the headline 2D RHD problem; the others time the remaining "
                          "workloads (FP64 step and residual only)")
     ap.add_argument("--paper-case", default=None,
-                    choices=["rp1", "rp2", "rp3", "rmhd_blast", "shock_cloud", "vortex3d"],
+                    choices=["rp1", "rp2", "rp3", "rmhd_blast", "shock_cloud", "vortex2d", "vortex3d"],
                     help="run one of the paper's 2D examples to its end time as MM-O5 (adaptive) and "
                          "UM-O5 (uniform, finer) and report the GPU time-to-solution ratio beside the "
-                         "paper's CPU ratio; vortex3d: errors and orders of MM-O6 and MM-O5 on the 3D "
-                         "RMHD vortex (not headline lines)")
-    ap.add_argument("--vortex-n", default="16,24,32,48,64",
-                    help="mesh sizes N (N x N x 5N nodes) of the vortex3d study")
+                         "paper's CPU ratio; vortex2d / vortex3d: errors and orders of MM-O6 and MM-O5 "
+                         "on the RMHD vortex (not headline lines)")
+    ap.add_argument("--vortex-n", default=None,
+                    help="mesh sizes N of the vortex study (2D: N x N, default 20,40,80,160; "
+                         "3D: N x N x 5N, default 16,24,32,48,64)")
     ap.add_argument("--no-fourier-gradient", action="store_true",
                     help="skip the gradient study of the adjoint configuration (objects adjoint_fourier*)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -399,17 +400,19 @@ def paper_case(args):
     print(json.dumps(line))
 
 
-def vortex_run(n, adaptive, t_end=0.1, max_wall_s=150.0):
-    """The 3D RMHD vortex to t_end: MM-O6 (EC scheme, prescribed mesh, dt = CFL
-    dxi^2) or MM-O5 (ES scheme, adaptive mesh with the gradient + Laplacian
-    monitor, dt = CFL dxi^(5/3)), dxi = 1/N the computational spacing, the last
-    step shortened so that the run ends at t_end.  Returns the L1 and max errors
-    of rho against the closed form and the GPU time (HIP events)."""
+def vortex_run(dim, n, adaptive, max_wall_s=150.0):
+    """The RMHD vortex of Section 6 (2D: N x N nodes to t = 4; 3D: N x N x 5N
+    nodes to t = 0.1): MM-O6 (EC scheme, prescribed mesh, dt = CFL dxi^2) or MM-O5
+    (ES scheme, adaptive mesh with the gradient + Laplacian monitor, dt = CFL
+    dxi^(5/3)), dxi = 1/N the computational spacing, the step count rounded up so
+    that the run ends at the end time.  Returns the L1 and max errors of rho
+    against the closed form and the GPU time (HIP events)."""
     import math
     import numpy as np
     import torch
     from paper_2107_12027_amd import workloads as wl
-    w = wl.rmhd_vortex(3, n, 0.0, dissipation=int(adaptive), adaptive=adaptive)
+    w = wl.rmhd_vortex(dim, n, 0.0, dissipation=int(adaptive), adaptive=adaptive)
+    t_end = w.t_end
     run = Run(w, 0)
     ctx = run.ctx
     power = 5.0 / 3.0 if adaptive else 2.0
@@ -426,18 +429,18 @@ def vortex_run(n, adaptive, t_end=0.1, max_wall_s=150.0):
     done = 0
     t_print = t_wall
     while done < steps:
-        for k in range(done, min(steps, done + 64)):
+        for k in range(done, min(steps, done + 256)):
             if adaptive:
                 ctx.rk3_step(run.U, run.J, run.x, run.xdot, run.dt, fixed)
             else:
                 da = wl.vortex_mesh_amplitude((k + 1) * dt) - wl.vortex_mesh_amplitude(k * dt)
                 torch.mul(shape, da / dt, out=run.xdot)
                 ctx.rk3_step_moving(run.U, run.J, run.x, run.xdot, run.dt, fixed)
-        done = min(steps, done + 64)
+        done = min(steps, done + 256)
         torch.cuda.synchronize()
         now = time.perf_counter()
         if now - t_print > 30.0:
-            print("vortex3d N=%d: %d of %d steps" % (n, done, steps), file=sys.stderr, flush=True)
+            print("vortex%dd N=%d: %d of %d steps" % (dim, n, done, steps), file=sys.stderr, flush=True)
             t_print = now
         if now - t_wall > max_wall_s:
             break
@@ -445,29 +448,35 @@ def vortex_run(n, adaptive, t_end=0.1, max_wall_s=150.0):
     torch.cuda.synchronize()
     status, nfail, _ = ctx.status()
     out = {"n": n, "nodes": w.grid.nnodes, "steps": done, "dt": dt, "t": done * dt,
-           "gpu_s": e0.elapsed_time(e1) * 1e-3, "status": int(status)}
+           "gpu_s": e0.elapsed_time(e1) * 1e-3, "wall_s": time.perf_counter() - t_wall, "status": int(status)}
     if status == 0 and done == steps:
         ctx.con2prim(run.U, run.J, run.prim)
-        rho = run.prim[0, 3:-3, 3:-3, 3:-3].cpu().numpy()
         x = run.x.cpu().numpy()
-        exact = wl.vortex3d_state(x[0], x[1], x[2], t_end)[0]
+        if dim == 2:
+            rho = run.prim[0, 3:-3, 3:-3].cpu().numpy()
+            exact = wl.vortex2d_state(x[0], x[1], t_end)[0]
+        else:
+            rho = run.prim[0, 3:-3, 3:-3, 3:-3].cpu().numpy()
+            exact = wl.vortex3d_state(x[0], x[1], x[2], t_end)[0]
         out["l1_rho"] = float(np.mean(np.abs(rho - exact)))
         out["linf_rho"] = float(np.max(np.abs(rho - exact)))
     return out
 
 
-def vortex_study(args):
-    """Errors and orders of MM-O6 and MM-O5 on the 3D RMHD vortex (Section 6)."""
+def vortex_study(args, dim):
+    """Errors and orders of MM-O6 and MM-O5 on the 2D or 3D RMHD vortex (Section 6)."""
     import math
-    ns = [int(v) for v in args.vortex_n.split(",")]
-    line = {"paper_case": "vortex3d", "t_end": 0.1, "dtype": "f64",
+    spec = args.vortex_n or ("20,40,80,160" if dim == 2 else "16,24,32,48,64")
+    ns = [int(v) for v in spec.split(",")]
+    name_case = "vortex%dd" % dim
+    line = {"paper_case": name_case, "t_end": 4.0 if dim == 2 else 0.1, "dtype": "f64",
             "data": "synthetic (the paper's closed-form initial data)"}
     for name, adaptive in (("mm_o6", False), ("mm_o5", True)):
         runs = []
         for n in ns:
-            r = vortex_run(n, adaptive)
+            r = vortex_run(dim, n, adaptive)
             runs.append(r)
-            print("vortex3d %s N=%d: %s" % (name, n, json.dumps(r)), file=sys.stderr, flush=True)
+            print("%s %s N=%d: %s" % (name_case, name, n, json.dumps(r)), file=sys.stderr, flush=True)
         rates = []
         for a, b in zip(runs[:-1], runs[1:]):
             ok = "l1_rho" in a and "l1_rho" in b
@@ -485,8 +494,8 @@ def main():
     from paper_2107_12027_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    if args.paper_case == "vortex3d":
-        return vortex_study(args)
+    if args.paper_case in ("vortex2d", "vortex3d"):
+        return vortex_study(args, 2 if args.paper_case == "vortex2d" else 3)
     if args.paper_case is not None:
         return paper_case(args)
     if args.workload != "quadrant":
