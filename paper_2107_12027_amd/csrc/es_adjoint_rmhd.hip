@@ -82,32 +82,37 @@ __device__ __forceinline__ void weno5_grad_m(double a, double b, double c, doubl
 }
 
 // (dF/dP_l)^T w and (dF/dP_r)^T w for the RMHD two-point flux F(l, r).
+template <int DIM, int SIDE>
+__device__ __forceinline__ void pair_vjp_rmhd_side(double G, const double* Pl, const double* Pr, const double* al,
+                                                   const double* ar, const double* w, double* g) {
+    using D = Dual<8>;
+    D Pdl[8], Pdr[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        Pdl[c] = SIDE == 0 ? D::seed(Pl[c], c) : D(Pl[c]);
+        Pdr[c] = SIDE == 1 ? D::seed(Pr[c], c) : D(Pr[c]);
+    }
+    const NodeRMHDT<D> l = node_rmhd<D>(G, Pdl, xlog(Pdl[0]), xlog(Pdl[0] / Pdl[4]));
+    const NodeRMHDT<D> r = node_rmhd<D>(G, Pdr, xlog(Pdr[0]), xlog(Pdr[0] / Pdr[4]));
+    D F[8];
+    double Jt, Bt;
+    pair_flux_rmhd<DIM, D, D>(G, l, r, al, ar, F, Jt, Bt);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s += w[c] * F[c].d[k];
+        g[k] = s;
+    }
+}
+
+// (the side is a template parameter so that the unseeded node's zero tangents
+// fold away)
 template <int DIM>
 __device__ void pair_vjp_rmhd(double G, const double* Pl, const double* Pr, const double* al, const double* ar,
                               const double* w, double* gl, double* gr) {
-    using D = Dual<8>;
-#pragma unroll 1
-    for (int side = 0; side < 2; ++side) {
-        D Pdl[8], Pdr[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            Pdl[c] = side == 0 ? D::seed(Pl[c], c) : D(Pl[c]);
-            Pdr[c] = side == 1 ? D::seed(Pr[c], c) : D(Pr[c]);
-        }
-        const NodeRMHDT<D> l = node_rmhd<D>(G, Pdl, xlog(Pdl[0]), xlog(Pdl[0] / Pdl[4]));
-        const NodeRMHDT<D> r = node_rmhd<D>(G, Pdr, xlog(Pdr[0]), xlog(Pdr[0] / Pdr[4]));
-        D F[8];
-        double Jt, Bt;
-        pair_flux_rmhd<DIM, D, D>(G, l, r, al, ar, F, Jt, Bt);
-        double* g = side == 0 ? gl : gr;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            double s = 0.0;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) s += w[c] * F[c].d[k];
-            g[k] = s;
-        }
-    }
+    pair_vjp_rmhd_side<DIM, 0>(G, Pl, Pr, al, ar, w, gl);
+    pair_vjp_rmhd_side<DIM, 1>(G, Pl, Pr, al, ar, w, gr);
 }
 
 template <int DIM, int DIR, bool ES>
