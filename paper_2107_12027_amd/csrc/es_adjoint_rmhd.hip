@@ -51,6 +51,54 @@ struct AdjPlanM {
     long long nlines[3];
 };
 
+// Face eigen-structure of the ES dissipation held by the adjoint: for direction d,
+// interior transverse line l and face f = p + 1 (face p+1/2 between positions p
+// and p + 1 along the line, p = -1 .. n_d - 1), the 64 entries Rc[k][i] (k*8 + i)
+// and lambda^ (entry 64) at eig[base[d] + (e * nlines[d] + l) * nface[d] + f].
+constexpr int NEIG = 65;
+struct FaceEigPlan {
+    long long base[3];
+    long long nlines[3];
+    int nface[3];
+    long long nthreads[3];   // faces of each direction
+};
+
+template <int DIM>
+__global__ void __launch_bounds__(64) k_face_eigen_rmhd(GridDev g, double G, const double* __restrict__ prim,
+                                                        const double* __restrict__ met, double* __restrict__ eig,
+                                                        FaceEigPlan fp) {
+    constexpr int NA = DIM + 1;
+    long long t = (long long)blockIdx.x * 64 + threadIdx.x;
+    int d = 0;
+    while (d < DIM - 1 && t >= fp.nthreads[d]) { t -= fp.nthreads[d]; ++d; }
+    if (t >= fp.nthreads[d]) return;
+    const long long l = t / fp.nface[d];
+    const int f = (int)(t % fp.nface[d]);
+    const int p = f - 1;
+    int ci = 0, cj = 0, ck = 0;
+    if (d == 0) { cj = (int)(l % g.n[1]); ck = (int)(l / g.n[1]); }
+    else if (d == 1) { ci = (int)(l % g.n[0]); ck = (int)(l / g.n[0]); }
+    else { ci = (int)(l % g.n[0]); cj = (int)(l / g.n[0]); }
+    const long long P = g.pnodes;
+    const long long pstride = d == 0 ? 1 : (d == 1 ? (long long)g.P[0] : (long long)g.P[0] * g.P[1]);
+    const long long i2 = pidx(g, ci, cj, ck) + (long long)p * pstride;
+    const long long i3 = i2 + pstride;
+    double P2[8], P3[8], al[NA], ar[NA];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) { P2[c] = prim[c * P + i2]; P3[c] = prim[c * P + i3]; }
+#pragma unroll
+    for (int c = 0; c < NA; ++c) { al[c] = met[(d * NA + c) * P + i2]; ar[c] = met[(d * NA + c) * P + i3]; }
+    double T[3][3], TV2[8], TV3[8], lhat, Rc[8][8];
+    face_eigen_rmhd<DIM>(G, P2, P3, al, ar, T, TV2, TV3, lhat, Rc);
+    double* o = eig + fp.base[d] + l * fp.nface[d] + f;
+    const long long es = fp.nlines[d] * fp.nface[d];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[(k * 8 + i) * es] = Rc[k][i];
+    o[64 * es] = lhat;
+}
+
 // Gradient of the WENO5-JS value weno5(a, b, c, d, e) with respect to its five
 // inputs: with w_k = d_k / (eps + beta_k)^2, S = sum_k w_k, v = sum_k w_k q_k / (6 S),
 // dv = [sum_k w_k dq_k + sum_k (q_k - 6 v) dw_k] / (6 S), dw_k = -2 w_k dbeta_k / (eps + beta_k).
@@ -121,7 +169,8 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
                                                           const double* __restrict__ met,
                                                           const double* __restrict__ lam,
                                                           double* __restrict__ gout, int blk, int nseg,
-                                                          long long nlines, AdjLDSM<DIM>& lds) {
+                                                          long long nlines, AdjLDSM<DIM>& lds,
+                                                          const double* __restrict__ eig, long long enf) {
     constexpr int NA = DIM + 1;
     constexpr int F_LR = 8, F_LB = 9, F_A = 10, F_PP = 10 + NA;
     auto& sd = lds.sd;
@@ -285,8 +334,16 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
                 prim_at(lane + 3, P3);
 #pragma unroll
                 for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane + 2]; ar[c] = sd[line][F_A + c][lane + 3]; }
-                double T[3][3], TV[6][8], lhat, Rc[8][8];
-                face_eigen_rmhd<DIM, true>(G, P2, P3, al, ar, T, TV[2], TV[3], lhat, Rc);
+                // the eigen-structure of this face (held at its forward value) from
+                // k_face_eigen_rmhd: face f = p + 1 of line lid, p = s0 - 3 + lane
+                double T[3][3], TV[6][8], at, L, Rc[8][8];
+                face_frame_rmhd<DIM>(G, P2, P3, al, ar, T, TV[2], TV[3], at, L);
+                const double* ef = eig + lid * (n + 1) + (s0 - 2 + lane);
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) Rc[k][i] = ef[(k * 8 + i) * enf];
+                const double lhat = ef[64 * enf];
 #pragma unroll
                 for (int j = 0; j < 6; ++j) {
                     if (j == 2 || j == 3) continue;
@@ -408,24 +465,26 @@ __global__ void __launch_bounds__(128) k_residual_vjp_rmhd(GridDev g, double G, 
                                                            const double* __restrict__ prim,
                                                            const double* __restrict__ met,
                                                            const double* __restrict__ lam,
-                                                           double* __restrict__ gdir, AdjPlanM pl) {
+                                                           double* __restrict__ gdir, AdjPlanM pl,
+                                                           const double* __restrict__ eig, FaceEigPlan fp) {
     __shared__ AdjLDSM<DIM> lds;
     const long long slab = 8LL * g.pnodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < pl.nblk[0]) {
-        residual_vjp_segment_rmhd<DIM, 0, ES>(g, G, eps, prim, met, lam, gdir, b, pl.nseg[0], pl.nlines[0], lds);
+        residual_vjp_segment_rmhd<DIM, 0, ES>(g, G, eps, prim, met, lam, gdir, b, pl.nseg[0], pl.nlines[0], lds,
+                                              eig + fp.base[0], fp.nlines[0] * fp.nface[0]);
         return;
     }
     b -= pl.nblk[0];
     if (DIM == 2 || b < pl.nblk[1]) {
         residual_vjp_segment_rmhd<DIM, 1, ES>(g, G, eps, prim, met, lam, gdir + slab, b, pl.nseg[1], pl.nlines[1],
-                                              lds);
+                                              lds, eig + fp.base[1], fp.nlines[1] * fp.nface[1]);
         return;
     }
     b -= pl.nblk[1];
     if (DIM == 3)
         residual_vjp_segment_rmhd<DIM, 2, ES>(g, G, eps, prim, met, lam, gdir + 2 * slab, b, pl.nseg[2],
-                                              pl.nlines[2], lds);
+                                              pl.nlines[2], lds, eig + fp.base[2], fp.nlines[2] * fp.nface[2]);
 }
 
 // Solve A^T y = b (8 x 8) by Gaussian elimination with partial pivoting on A^T.
@@ -530,6 +589,22 @@ __global__ void __launch_bounds__(256) k_fold_con2prim_vjp_rmhd(GridDev g, doubl
     gJ[t] = gj * iJ * iJ;
 }
 
+FaceEigPlan face_eig_plan(const GridDev& g) {
+    FaceEigPlan fp{};
+    long long base = 0;
+    for (int d = 0; d < g.dim; ++d) {
+        long long nl = 1;
+        for (int a = 0; a < g.dim; ++a)
+            if (a != d) nl *= g.n[a];
+        fp.base[d] = base;
+        fp.nlines[d] = nl;
+        fp.nface[d] = g.n[d] + 1;
+        fp.nthreads[d] = nl * fp.nface[d];
+        base += (long long)NEIG * fp.nthreads[d];
+    }
+    return fp;
+}
+
 template <int DIM>
 static void residual_vjp_all_rmhd(const es_ctx* c, const double* prim, const double* met, const double* lam,
                                   double* gdir, hipStream_t s) {
@@ -547,13 +622,27 @@ static void residual_vjp_all_rmhd(const es_ctx* c, const double* prim, const dou
     }
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
     const unsigned thr = 64 * QLINES;
-    if (c->scheme.dissipation != 0)
-        k_residual_vjp_rmhd<DIM, true><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
-    else
-        k_residual_vjp_rmhd<DIM, false><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
+    const FaceEigPlan fp = face_eig_plan(g);
+    if (c->scheme.dissipation != 0) {
+        long long nt = 0;
+        for (int d = 0; d < DIM; ++d) nt += fp.nthreads[d];
+        k_face_eigen_rmhd<DIM><<<(unsigned)((nt + 63) / 64), 64, 0, s>>>(g, G, prim, met, c->adj_eig, fp);
+        k_residual_vjp_rmhd<DIM, true><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl,
+                                                                     c->adj_eig, fp);
+    } else {
+        k_residual_vjp_rmhd<DIM, false><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl,
+                                                                      nullptr, fp);
+    }
 }
 
 }  // namespace
+
+size_t face_eig_doubles_rmhd(const es_ctx* c) {
+    const FaceEigPlan fp = face_eig_plan(c->g);
+    size_t n = 0;
+    for (int d = 0; d < c->g.dim; ++d) n += (size_t)NEIG * (size_t)fp.nthreads[d];
+    return n;
+}
 
 hipError_t launch_residual_fold_vjp_rmhd(const es_ctx* c, const double* U, const double* J, const double* met,
                                          const double* lam, double* gU, double* gJ, hipStream_t s) {

@@ -152,7 +152,7 @@ es_status es_destroy(es_ctx* c) {
     void* bufs[] = {c->prim, c->met, c->met1, c->met2, c->L, c->Us, c->Js, c->Us2, c->Js2, c->xnew, c->xa, c->xb,
                     c->wa, c->wb, c->xe, c->ve, c->pi, c->red, c->scal, c->fail,
                     c->adj_lamU, c->adj_lamJ, c->adj_lamL, c->adj_accU, c->adj_accJ,
-                    c->adj_gU, c->adj_gJ, c->gdir};
+                    c->adj_gU, c->adj_gJ, c->gdir, c->adj_eig};
     if (c->gexec != nullptr) (void)hipGraphExecDestroy(c->gexec);
     if (c->cap != nullptr) (void)hipStreamDestroy(c->cap);
     for (void* b : bufs)
@@ -338,6 +338,8 @@ static es_status ensure_adjoint(es_ctx* c) {
     if (e == hipSuccess) e = alloc(&c->adj_gU, N * m);
     if (e == hipSuccess) e = alloc(&c->adj_gJ, N);
     if (e == hipSuccess) e = alloc(&c->gdir, (size_t)c->g.pnodes * m * (size_t)c->g.dim);
+    if (e == hipSuccess && c->scheme.phys == ES_RMHD && c->scheme.dissipation != 0)
+        e = alloc(&c->adj_eig, es::face_eig_doubles_rmhd(c));
     if (e != hipSuccess) return ES_EHIP;
     // positions the residual VJP does not write (ghost corners) are never read;
     // clear once so the buffer holds no stale values

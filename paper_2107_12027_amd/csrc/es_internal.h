@@ -46,6 +46,7 @@ struct es_ctx {
     double* adj_gU;     // interior, m comps: stage residual VJP
     double* adj_gJ;     // interior
     double* gdir;       // padded, d slabs of m comps: primitive cotangents by direction
+    double* adj_eig;    // RMHD ES: face eigen-structure held by the residual VJP (face_eig_doubles_rmhd)
     // HIP graph of one es_rk3_step (replayed while the argument pointers stay the same)
     int use_graph;
     hipStream_t cap;            // capture stream (default priority)
@@ -124,6 +125,7 @@ hipError_t launch_residual_dirs_rmhd(const es_ctx* c, const double* prim, const 
                                      hipStream_t s);
 // residual VJP of the RMHD system on c->prim (con2prim done by the caller), with
 // the ghost folding and the con2prim pull-back into (gU, gJ)
+size_t face_eig_doubles_rmhd(const es_ctx* c);
 hipError_t launch_residual_fold_vjp_rmhd(const es_ctx* c, const double* U, const double* J, const double* met,
                                          const double* lam, double* gU, double* gJ, hipStream_t s);
 hipError_t launch_cfl_partial_rmhd(const es_ctx* c, const double* prim, const double* met,

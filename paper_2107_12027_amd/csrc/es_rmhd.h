@@ -730,120 +730,21 @@ __device__ __forceinline__ void canonical_columns(const double* lam, double Zv[8
         }
 }
 
-// The same canonical bases position by position: for each k the projections of
-// all seeds onto k's group are formed again and reduced against the members
-// before k (the sequence canonical_columns forms slot by slot; equal up to
-// rounding).  More arithmetic, but in the adjoint kernel, whose own live state
-// is large, the compiler spills less around it and the kernel runs faster.
-// Writes canon[k] = z-space column of position k.
-__device__ __forceinline__ void canonical_groups(const double* lam, const double Zv[8][8],
-                                                 const double Lc[8][8], double vn,
-                                                 double canon[8][8]) {
-    // group labels: smallest index reachable through chains of close eigenvalues
-    int lab[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) lab[k] = k;
-#pragma unroll 1
-    for (int it = 0; it < 7; ++it) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            int l = lab[k];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (fabs(lam[k] - lam[j]) <= GROUP_TOL && lab[j] < l) l = lab[j];
-            lab[k] = l;
-        }
-    }
-    int labc = lab[0];
-    {
-        double e = fabs(lam[0] - vn);
-#pragma unroll
-        for (int k = 1; k < 8; ++k)
-            if (fabs(lam[k] - vn) < e) { e = fabs(lam[k] - vn); labc = lab[k]; }
-    }
-    // L^{-1} (lower triangular) and the seed coefficients C[a][s] = z_a . L^{-1} e_s
-    double Li[8][8];
-#pragma unroll
-    for (int sd = 0; sd < 8; ++sd)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            double v = i == sd ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = 0; k < i; ++k) v -= Lc[i][k] * Li[k][sd];
-            Li[i][sd] = v / Lc[i][i];
-        }
-    double yn[8], C[8][8];
-#pragma unroll
-    for (int sd = 0; sd < 8; ++sd) {
-        double q = 0.0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) q += Li[i][sd] * Li[i][sd];
-        yn[sd] = sqrt(q);
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            double c = 0.0;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) c += Zv[i][a] * Li[i][sd];
-            C[a][sd] = c;
-        }
-    }
-    constexpr int SC[8] = {0, 5, 1, 2, 3, 4, 6, 7};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const bool isc = lab[k] == labc;
-        bool done = false;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) canon[k][i] = 0.0;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            double p[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) p[i] = 0.0;
-#pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                if (lab[a] != lab[k]) continue;
-                const double coef = isc ? C[a][SC[t]] : C[a][t];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) p[i] += coef * Zv[i][a];
-            }
-#pragma unroll
-            for (int j = 0; j < k; ++j) {
-                if (lab[j] != lab[k]) continue;
-                double ip = 0.0;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) ip += canon[j][i] * p[i];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) p[i] -= ip * canon[j][i];
-            }
-            double nn = 0.0;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) nn += p[i] * p[i];
-            nn = sqrt(nn);
-            const double ys = isc ? yn[SC[t]] : yn[t];
-            if (!done && nn > SEED_TOL * ys) {
-                const double inn = 1.0 / nn;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) canon[k][i] = p[i] * inn;
-                done = true;
-            }
-        }
-    }
-}
-
 // Face frame and eigen-structure of the RMHD dissipation at face i+1/2 (shared by
 // face_diss_rmhd and its adjoint): the rotation T of the face metric normal, the
 // rotated entropy variables TV2, TV3 of nodes i and i+1, lambda^ and the columns
 // Rc[k] = L z_k of R (z_k the canonical basis vector of position k).
-// PER_POSITION selects canonical_groups (the adjoint) instead of canonical_columns.
-template <int DIM, bool PER_POSITION = false>
-__device__ __forceinline__ void face_eigen_rmhd(double G, const double* P2, const double* P3, const double* al,
+// Frame of face i+1/2: the rotation T of the mean metric normal (a_t, L n) of
+// nodes i and i+1 and their rotated entropy variables TV2, TV3.
+template <int DIM>
+__device__ __forceinline__ void face_frame_rmhd(double G, const double* P2, const double* P3, const double* al,
                                                 const double* ar, double T[3][3], double* TV2, double* TV3,
-                                                double& lhat, double Rc[8][8]) {
-    const double at = 0.5 * (al[0] + ar[0]);
+                                                double& at, double& L) {
+    at = 0.5 * (al[0] + ar[0]);
     double ax[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < DIM; ++j) ax[j] = 0.5 * (al[1 + j] + ar[1 + j]);
-    const double L = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    L = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
     const double iL = 1.0 / L;
     double nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
     rotation<3>(nrm, T);            // n_3 = 0 in 2D gives the 2D rotation
@@ -854,6 +755,14 @@ __device__ __forceinline__ void face_eigen_rmhd(double G, const double* P2, cons
         rmhd_entropy_vars<double>(G, s, V);
         rotate8<false>(T, V, q == 0 ? TV2 : TV3);
     }
+}
+
+template <int DIM>
+__device__ __forceinline__ void face_eigen_rmhd(double G, const double* P2, const double* P3, const double* al,
+                                                const double* ar, double T[3][3], double* TV2, double* TV3,
+                                                double& lhat, double Rc[8][8]) {
+    double at, L;
+    face_frame_rmhd<DIM>(G, P2, P3, al, ar, T, TV2, TV3, at, L);
     // face state (rotated frame)
     double Vb[8];
 #pragma unroll
@@ -883,21 +792,7 @@ __device__ __forceinline__ void face_eigen_rmhd(double G, const double* P2, cons
 #pragma unroll
     for (int k = 0; k < 8; ++k) lhat = fmax(lhat, fabs(at + L * lam[k]));
     // canonical basis in every group of (nearly) equal eigenvalues
-    if (PER_POSITION) {
-        double canon[8][8];
-        canonical_groups(lam, Zv, Lc, vn, canon);
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                double sum = 0.0;
-#pragma unroll
-                for (int kk = 0; kk <= i; ++kk) sum += Lc[i][kk] * canon[k][kk];
-                Rc[k][i] = sum;
-            }
-    } else {
-        canonical_columns(lam, Zv, Lc, vn, Rc);
-    }
+    canonical_columns(lam, Zv, Lc, vn, Rc);
 }
 
 // ES dissipation for RMHD at one face (eq. ESFlux_HO): as face_diss_rhd with
