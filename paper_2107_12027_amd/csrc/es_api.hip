@@ -244,9 +244,13 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
     static const double coef[3] = {0.0, 1.0, 0.5};
     const bool batched = es::metrics_stages_batched(c);
     if (batched) ES_TRY(es::launch_metrics_stages(c, x, xdot, dt_dev, c->met, c->met1, c->met2, s));
+    // 3D: the CFL launch left the spatial metrics of x^n in c->met (unless dt was
+    // prescribed), so stage 0, on the same mesh, adds only its temporal part
+    const bool met0_spatial = !batched && fixed_dt_dev == nullptr;
     for (int st = 0; st < 3; ++st) {
         const double* met = c->met;
         if (batched) met = st == 0 ? c->met : (st == 1 ? c->met1 : c->met2);
+        else if (st == 0 && met0_spatial) ES_TRY(es::launch_temporal_metrics3d(c, xdot, c->met, s));
         else ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s));
         ES_TRY(es::launch_residual_dirs(c, c->prim, met, c->L, s));
         if (st == 0) {

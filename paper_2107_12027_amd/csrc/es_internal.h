@@ -67,6 +67,7 @@ hipError_t launch_prim2con(const es_ctx* c, const double* prim, const double* J,
 hipError_t launch_con2prim(const es_ctx* c, const double* U, const double* J, double* prim,
                            int use_guess, hipStream_t s);
 int reduction_blocks(const GridDev& g);
+hipError_t launch_temporal_metrics3d(const es_ctx* c, const double* xdot, double* met, hipStream_t s);
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
                           hipStream_t s);

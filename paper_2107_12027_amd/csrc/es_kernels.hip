@@ -354,6 +354,26 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
     }
 }
 
+// Temporal metrics J dxi_k/dt = -sum_j xdot_j (J dxi_k/dx_j) of a mesh whose
+// spatial metrics are already in met (padded nodes; the mesh velocity extended
+// as in k_mesh_extend): stage 0 of a 3D step, whose mesh is x^n.
+__global__ void k_temporal_metrics3d(GridDev g, const double* __restrict__ xd, double* __restrict__ met) {
+    int i, j, k;
+    if (!box_ijk(-NG, -NG, -NG, g.P[0], g.P[1], i, j, k)) return;
+    const long long t = pidx(g, i, j, k);
+    const long long P = g.pnodes;
+    double v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = mesh_value(g, xd, nullptr, 0.0, c, i, j, k, false);
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        double at = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) at -= v[jj] * met[(kk * 4 + 1 + jj) * P + t];
+        met[(kk * 4) * P + t] = at;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // residual: all direction sweeps in one launch
 // ---------------------------------------------------------------------------
@@ -1469,6 +1489,12 @@ hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double*
     const GridDev& g = c->g;
     const dim3 gm((unsigned)((g.P[0] + MTX - 1) / MTX), (unsigned)((g.P[1] + MTY - 1) / MTY), 1);
     k_metrics2d_stages<<<gm, dim3(MTX, MSY, 1), 0, s>>>(g, x, xdot, dt_dev, met0, met1, met2);
+    return hipGetLastError();
+}
+
+hipError_t launch_temporal_metrics3d(const es_ctx* c, const double* xdot, double* met, hipStream_t s) {
+    const GridDev& g = c->g;
+    k_temporal_metrics3d<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, xdot, met);
     return hipGetLastError();
 }
 
