@@ -194,3 +194,29 @@ def test_vortex3d_total_entropy():
     print("total entropy per node: EC", ec, "ES", es_)
     assert np.all(np.diff(es_) < 0), d_es
     assert np.max(np.abs(d_ec)) < 1e-3 * abs(d_es[-1]), (d_ec, d_es)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 24), (3, 8)])
+def test_rk3_step_moving_with_zero_velocity_is_the_static_step(dim, n):
+    # with the monitor off, es_rk3_step keeps the mesh (x_new = x, xdot = 0); the
+    # prescribed-motion step with xdot = 0 must give the same bits
+    w = wl.rmhd_vortex(dim, n, t=0.5, dissipation=1)
+    ctx_a, _, Ua, Ja, xa = _gpu_setup(w)
+    ctx_b, _, Ub, Jb, xb = _gpu_setup(w)
+    dta, dtb = empty(1), empty(1)
+    xd_out = empty(dim, *ctx_a.shape())
+    for _ in range(2):
+        ctx_a.rk3_step(Ua, Ja, xa, xd_out, dta)
+        ctx_b.rk3_step_moving(Ub, Jb, xb, torch.zeros_like(xb), dtb)
+    assert ctx_a.status()[0] == es.ES_OK and ctx_b.status()[0] == es.ES_OK
+    assert host(dta)[0] == host(dtb)[0]
+    assert np.array_equal(host(Ua), host(Ub)) and np.array_equal(host(Ja), host(Jb))
+    assert np.array_equal(host(xa), host(xb))
+
+
+def test_rk3_step_moving_rejects_missing_velocity():
+    w = wl.rmhd_vortex(2, 16)
+    ctx, _, U, J, x = _gpu_setup(w)
+    with pytest.raises(es.EsError) as err:
+        ctx.rk3_step_moving(U, J, x, None, empty(1))
+    assert err.value.status == es.ES_EINVAL
