@@ -76,8 +76,9 @@ typedef struct {
     int phys;           /* ES_RHD / ES_RMHD */
     double gamma;       /* adiabatic index of the ideal EOS (eq. EOS) */
     int order_p;        /* p of the 2p-th order EC flux and metrics with WENO of order
-                           2p - 1 (Section 4): p = 3 (RHD, RMHD) or p = 2 (RHD; not
-                           the adjoint entry points); others give ES_EUNSUPPORTED */
+                           2p - 1 (Section 4): p = 3 or p = 2 (RHD and RMHD; p = 2
+                           not for the adjoint entry points); others give
+                           ES_EUNSUPPORTED */
     int dissipation;    /* 0: entropy conservative, 1: entropy stable (WENO-(2p-1)) */
     int mixed;          /* 0: FP64 throughout.  1: FP32-mixed residual: the two-point
                            pair algebra (except the small-jump branch of the

@@ -77,8 +77,8 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
             !(monitor->alpha2 >= 0.0))
             return ES_EINVAL;
     }
-    // kernels of this build: p = 3 (RHD and RMHD, FP64 or FP32-mixed) and p = 2 (RHD)
-    if (scheme->order_p != 3 && !(scheme->order_p == 2 && scheme->phys == ES_RHD)) return ES_EUNSUPPORTED;
+    // kernels of this build: p = 3 and p = 2 (RHD and RMHD, FP64 or FP32-mixed)
+    if (scheme->order_p != 3 && scheme->order_p != 2) return ES_EUNSUPPORTED;
 
     es_ctx* c = new (std::nothrow) es_ctx();
     if (c == nullptr) return ES_EHIP;

@@ -98,7 +98,7 @@ struct SweepPlanM {
     long long nlines[3];
 };
 
-template <int DIM, int DIR, bool ES, bool MIXED>
+template <int DIM, int DIR, bool ES, bool MIXED, int PO>
 __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G, double eps,
                                                       const double* __restrict__ prim,
                                                       const double* __restrict__ met,
@@ -165,7 +165,7 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
 #pragma unroll
         for (int c = 0; c < NA; ++c) al[c] = sd[line][F_A + c][lane];
 #pragma unroll 1
-        for (int n = 1; n <= 3; ++n) {
+        for (int n = 1; n <= PO; ++n) {
             const NodeRMHD r = node_at(lane + n);
             double ar[NA];
 #pragma unroll
@@ -192,7 +192,8 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
         for (int c = 0; c < MR + 2; ++c) {
             double s = 0.0;
 #pragma unroll
-            for (int n = 1; n <= 3; ++n) s += alpha3(n) * (sp[line][n - 1][c][lane] - sp[line][n - 1][c][lane - n]);
+            for (int n = 1; n <= PO; ++n)
+                s += alpha_pn(PO, n) * (sp[line][n - 1][c][lane] - sp[line][n - 1][c][lane - n]);
             diff[c] = s * idxi;
         }
         // flux differences and the Godunov-Powell source -Phi'(V_i) (B~ differences)
@@ -214,15 +215,15 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
 #pragma unroll
             for (int c = 0; c <= MR; ++c) sp[line][1][c][lane] = R[c];
         }
-        if (active && lane >= 2 && s_own < s_end) {
-            double Pn[6][MR];
+        if (active && lane >= PO - 1 && s_own < s_end) {
+            double Pn[2 * PO][MR];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) prim_at(lane - 2 + q, Pn[q]);
+            for (int q = 0; q < 2 * PO; ++q) prim_at(lane - (PO - 1) + q, Pn[q]);
             double al[NA], ar[NA];
 #pragma unroll
             for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane]; ar[c] = sd[line][F_A + c][lane + 1]; }
             double d[MR];
-            face_diss_rmhd<DIM, MIXED>(G, eps, Pn, al, ar, d);
+            face_diss_rmhd<DIM, MIXED, PO>(G, eps, Pn, al, ar, d);
 #pragma unroll
             for (int c = 0; c < MR; ++c) sp[line][0][c][lane] = d[c];
         }
@@ -242,7 +243,7 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
     }
 }
 
-template <int DIM, bool ES, bool MIXED>
+template <int DIM, bool ES, bool MIXED, int PO>
 __global__ void __launch_bounds__(128) k_residual_rmhd(GridDev g, double G, double eps,
                                                        const double* __restrict__ prim,
                                                        const double* __restrict__ met,
@@ -251,17 +252,17 @@ __global__ void __launch_bounds__(128) k_residual_rmhd(GridDev g, double G, doub
     const long long slab = (long long)(MR + 1) * g.nodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < sw.nblk[0]) {
-        residual_segment_rmhd<DIM, 0, ES, MIXED>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
+        residual_segment_rmhd<DIM, 0, ES, MIXED, PO>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
         return;
     }
     b -= sw.nblk[0];
     if (DIM == 2 || b < sw.nblk[1]) {
-        residual_segment_rmhd<DIM, 1, ES, MIXED>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
+        residual_segment_rmhd<DIM, 1, ES, MIXED, PO>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
         return;
     }
     b -= sw.nblk[1];
     if (DIM == 3)
-        residual_segment_rmhd<DIM, 2, ES, MIXED>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
+        residual_segment_rmhd<DIM, 2, ES, MIXED, PO>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
 }
 
 // CFL partial maxima: rho_k = L_k max_m |lambda_m| / J per direction (eq. cfl), the
@@ -373,10 +374,17 @@ static void residual_all_rmhd(const es_ctx* c, const double* prim, const double*
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
     const dim3 grid((unsigned)nb), block(64 * RLINES);
     const bool es = c->scheme.dissipation != 0, mixed = c->scheme.mixed != 0;
-    if (es && mixed) k_residual_rmhd<DIM, true, true><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
-    else if (es) k_residual_rmhd<DIM, true, false><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
-    else if (mixed) k_residual_rmhd<DIM, false, true><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
-    else k_residual_rmhd<DIM, false, false><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    if (c->scheme.order_p == 2) {
+        if (es && mixed) k_residual_rmhd<DIM, true, true, 2><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+        else if (es) k_residual_rmhd<DIM, true, false, 2><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+        else if (mixed) k_residual_rmhd<DIM, false, true, 2><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+        else k_residual_rmhd<DIM, false, false, 2><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+        return;
+    }
+    if (es && mixed) k_residual_rmhd<DIM, true, true, 3><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else if (es) k_residual_rmhd<DIM, true, false, 3><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else if (mixed) k_residual_rmhd<DIM, false, true, 3><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+    else k_residual_rmhd<DIM, false, false, 3><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
 }
 
 }  // namespace

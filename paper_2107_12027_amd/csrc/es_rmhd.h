@@ -804,14 +804,16 @@ __device__ __forceinline__ void face_eigen_rmhd(double G, const double* P2, cons
 // every group of nearly equal eigenvalues (canonical_columns; the group of v_n
 // holds the entropy and div B waves and is seeded with e_D, e_{B_n}).
 // nodes: the 8 primitive slots of the stencil nodes i-2..i+3.
-template <int DIM, bool MIXED = false>
-__device__ __forceinline__ void face_diss_rmhd(double G, double eps, const double Pn[6][8],
+// P: the order parameter p (stencil of 2p nodes i-p+1 .. i+p, WENO of order 2p-1).
+template <int DIM, bool MIXED = false, int P = 3>
+__device__ __forceinline__ void face_diss_rmhd(double G, double eps, const double Pn[2 * P][8],
                                                const double* al, const double* ar, double* d) {
-    double T[3][3], TV[6][8], lhat, Rc[8][8];
-    face_eigen_rmhd<DIM>(G, Pn[2], Pn[3], al, ar, T, TV[2], TV[3], lhat, Rc);
+    constexpr int NS = 2 * P, CI = P - 1;    // stencil size, index of node i
+    double T[3][3], TV[NS][8], lhat, Rc[8][8];
+    face_eigen_rmhd<DIM>(G, Pn[CI], Pn[CI + 1], al, ar, T, TV[CI], TV[CI + 1], lhat, Rc);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        if (j == 2 || j == 3) continue;
+    for (int j = 0; j < NS; ++j) {
+        if (j == CI || j == CI + 1) continue;
         const StateRMHD<double> s = rmhd_state<double>(G, Pn[j]);
         double V[8];
         rmhd_entropy_vars<double>(G, s, V);
@@ -819,14 +821,14 @@ __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const doubl
     }
     double tv2 = 0.0, tv3 = 0.0;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
+    for (int c = 0; c < 8; ++c) { tv2 = fmax(tv2, fabs(TV[CI][c])); tv3 = fmax(tv3, fabs(TV[CI + 1][c])); }
     const double tvmax = tv2 + tv3;
     // projections, WENO5, the switch and the accumulation: FP64, or FP32 in the
     // mixed form (the eigen-structure above stays FP64 there)
     using RW = typename std::conditional<MIXED, float, double>::type;
-    RW TVw[6][8];
+    RW TVw[NS][8];
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
+    for (int j = 0; j < NS; ++j)
 #pragma unroll
         for (int c = 0; c < 8; ++c) TVw[j][c] = (RW)TV[j][c];
     RW dd[8];
@@ -837,17 +839,20 @@ __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const doubl
         RW r[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) r[i] = (RW)Rc[k][i];
-        RW vt[6];
+        RW vt[NS];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
+        for (int j = 0; j < NS; ++j) {
             RW s = RW(0.0);
 #pragma unroll
             for (int c = 0; c < 8; ++c) s += r[c] * TVw[j][c];
             vt[j] = s;
         }
-        const RW jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], (RW)eps) -
-                      weno5(vt[0], vt[1], vt[2], vt[3], vt[4], (RW)eps);
-        const RW jp = vt[3] - vt[2];
+        RW jw;
+        if (P == 3)
+            jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], (RW)eps) - weno5(vt[0], vt[1], vt[2], vt[3], vt[4], (RW)eps);
+        else
+            jw = weno3(vt[3], vt[2], vt[1], (RW)eps) - weno3(vt[0], vt[1], vt[2], (RW)eps);
+        const RW jp = vt[CI + 1] - vt[CI];
         RW r1 = RW(0.0);
 #pragma unroll
         for (int c = 0; c < 8; ++c) r1 += fabs(r[c]);

@@ -46,7 +46,7 @@ def _create(grid, scheme, monitor):
     s = es.Scheme(scheme.phys, scheme.gamma, scheme.order_p, scheme.dissipation, scheme.mixed,
                   scheme.weno_eps, scheme.cfl)
     m = es.Monitor(monitor.enabled, monitor.sigma, monitor.form, monitor.alpha,
-                   monitor.filter_passes, monitor.sweeps)
+                   monitor.filter_passes, monitor.sweeps, monitor.alpha2)
     h = ctypes.c_void_p()
     return lib.es_create(ctypes.byref(g), ctypes.byref(s), ctypes.byref(m), ctypes.byref(h)), h
 
@@ -59,7 +59,9 @@ def _create(grid, scheme, monitor):
     (lambda g, s, m: setattr(s, "dissipation", 2), es.ES_EINVAL),
     (lambda g, s, m: setattr(m, "form", 7), es.ES_EINVAL),
     (lambda g, s, m: setattr(s, "order_p", 4), es.ES_EUNSUPPORTED),
-    (lambda g, s, m: (setattr(s, "order_p", 2), setattr(s, "phys", 1)), es.ES_EUNSUPPORTED),
+    (lambda g, s, m: (setattr(s, "order_p", 1), setattr(s, "phys", 1)), es.ES_EUNSUPPORTED),
+    (lambda g, s, m: (setattr(m, "enabled", 1), setattr(m, "form", 2), setattr(m, "alpha2", -1.0)),
+     es.ES_EINVAL),
     (lambda g, s, m: setattr(s, "phys", 2), es.ES_EINVAL),
 ])
 def test_create_rejects_bad_options_before_device_work(mutate, expect):

@@ -78,3 +78,60 @@ def test_p2_adjoint_unsupported():
     with pytest.raises(es.EsError) as err:
         ctx.rk3_step_save(*t)
     assert err.value.status == es.ES_EUNSUPPORTED
+
+
+RMHD_GRIDS = [(2, (130, 70, 1), (0, 0, 0)), (2, (64, 67, 1), (1, 1, 0)), (3, (66, 9, 8), (0, 1, 0))]
+
+
+@pytest.mark.parametrize("dim,n,bc", RMHD_GRIDS)
+@pytest.mark.parametrize("diss", [0, 1])
+def test_p2_rmhd_residual(dim, n, bc, diss):
+    # the RMHD bars of the p = 3 path: 1e-12 for EC, 1e-10 for ES (the numeric
+    # eigen-structure's conditioning, measured on the oracle itself)
+    case = Case(dim, n, bc, phys=ph.RMHD, seed=4 + diss, dissipation=diss, p=2)
+    _, _, _, _, dU, dJ = case.residual()
+    dUo, dJo = case.oracle_residual()
+    r = rel_inf(host(dU), dUo)
+    assert np.all(r <= (1e-10 if diss else TOL)), r
+    assert rel_inf(host(dJ)[None], dJo[None])[0] <= TOL
+
+
+def test_p2_rmhd_rk3_step_fourier():
+    w = wl.rmhd_fourier(n=48, seed=0)
+    w.scheme.order_p = 2
+    g = w.grid
+    ctx = es.Context(g, w.scheme, w.monitor)
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    met = empty(ctx.nmet, *ctx.padded_shape())
+    J = empty(*ctx.shape())
+    x = dev(w.x)
+    ctx.metrics(x, None, met, J)
+    U = empty(ctx.m, *ctx.shape())
+    ctx.prim2con(dev(P), J, U)
+    xd = empty(g.dim, *ctx.shape())
+    dt = empty(1)
+    Uo, Jo = st.initial_state(g, w.scheme, P, w.x)
+    xo = w.x.copy()
+    for _ in range(2):
+        ctx.rk3_step(U, J, x, xd, dt)
+        out = st.rk3_step(g, w.scheme, w.monitor, Uo, Jo, xo)
+        Uo, Jo, xo = out["U"], out["J"], out["x"]
+        assert abs(host(dt)[0] - out["dt"]) <= 1e-12 * out["dt"]
+    assert ctx.status()[0] == es.ES_OK
+    Ug = host(U)
+    big = np.max(np.abs(Uo))
+    for c in range(ctx.m):
+        sc = max(np.max(np.abs(Uo[c])), 1e-3 * big)
+        assert np.max(np.abs(Ug[c] - Uo[c])) <= 1e-11 * sc, (c, np.max(np.abs(Ug[c] - Uo[c])) / sc)
+
+
+def test_p2_adjoint_unsupported():
+    w = wl.rmhd_fourier(n=16, seed=0)
+    w.scheme.order_p = 2
+    ctx = es.Context(w.grid, w.scheme, w.monitor)
+    assert ctx.ckpt_doubles() > 0
+    with pytest.raises(es.EsError) as err:
+        U = empty(ctx.m, *ctx.shape())
+        ctx.rk3_step_save(U, empty(*ctx.shape()), empty(2, *ctx.shape()), empty(2, *ctx.shape()), empty(1),
+                          empty(ctx.ckpt_doubles()))
+    assert err.value.status == es.ES_EUNSUPPORTED

@@ -186,7 +186,7 @@ def test_p2_entropy_and_free_stream(phys, dim, n):
         assert np.max(np.abs(dU - U0 * dJ)) < 1e-13 * np.max(np.abs(U0)) * np.max(np.abs(met)) / min(g.dxi[:dim])
 
 
-def _vortex_errors(diss, Ns):
+def _vortex_errors(diss, Ns, order=3):
     # the semi-discrete residual against the exact d(J U)/dt of the RMHD vortex at
     # t = 0 (complex-step derivative of the closed form in t) on static uniform
     # periodic meshes of [-5, 5]^2
@@ -197,9 +197,10 @@ def _vortex_errors(diss, Ns):
         rho, v, p, B = wl.vortex2d_state(x[0], x[1], 0.0)
         W = 1.0 / np.sqrt(1.0 - np.sum(v * v, axis=0))
         P = ph.full_prim(rho, W * v, p, B)
-        met = mt.metrics(g, x, None)
-        J = mt.jacobian(g, x)
-        dU, dJ = rs.residual(g, wl.Scheme(phys=ph.RMHD, dissipation=diss), st.pad_solution(g, P), met)
+        met = mt.metrics(g, x, None, order)
+        J = mt.jacobian(g, x, order)
+        dU, dJ = rs.residual(g, wl.Scheme(phys=ph.RMHD, dissipation=diss, order_p=order), st.pad_solution(g, P),
+                             met)
         hc = 1e-30
         rc, vc, pc, Bc = wl.vortex2d_state(x[0].astype(complex), x[1].astype(complex), 1j * hc)
         Wc = 1.0 / np.sqrt(1.0 - np.sum(vc * vc, axis=0))
@@ -259,3 +260,11 @@ def test_rmhd_vortex3d_ec_on_prescribed_moving_mesh():
     e = _vortex3d_errors((32, 48))
     rate = np.log(e[0] / e[1]) / np.log(1.5)
     assert rate > 4.8, (e, rate)
+
+
+def test_rmhd_vortex_ec_fourth_order_p2():
+    # p = 2: the 4th-order EC residual (pair coefficients 4/3, -1/6, metrics of the
+    # same order) converges to the vortex's time derivative at order 4
+    e = _vortex_errors(0, (24, 48, 96), order=2)
+    rates = np.log2(e[:-1] / e[1:])
+    assert rates[-1] > 3.7, (e, rates)
