@@ -548,6 +548,10 @@ def main():
         ach = flops * nodes / (res_ms * 1e-3)
         roof["achieved"] = ach / 1e12
         roof["frac"] = ach / PEAK_FP64_VECTOR
+    if traffic is not None:
+        # the HBM side of the same call: counter bytes over the measured duration
+        roof["hbm_achieved_gbs"] = traffic / (res_ms * 1e-3) / 1e9
+        roof["hbm_frac"] = traffic / (res_ms * 1e-3) / PEAK_HBM
     cpu = None
     mixed = {"value": nodes * args.steps / (t_mixed_ms * 1e-3), "unit": "cell-updates/s",
              "ms_per_step": t_mixed_ms / args.steps, "dtype": "f32 pair/dissipation, f64 elsewhere",
