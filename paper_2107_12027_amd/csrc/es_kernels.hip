@@ -127,7 +127,7 @@ __global__ void k_mesh_extend(GridDev g, const double* __restrict__ x, const dou
                               const double* __restrict__ dt_dev, double coef, double* __restrict__ xe,
                               double* __restrict__ ve) {
     int i, j, k;
-    if (!box_ijk(-2 * NG, -2 * NG, -g.g6, g.E[0], g.E[1], i, j, k)) return;
+    if (!box_ijk_xcd(-2 * NG, -2 * NG, -g.g6, g.E[0], g.E[1], i, j, k)) return;
     const long long t = eidx(g, i, j, k);
     const double cdt = dt_dev != nullptr ? coef * dt_dev[0] : 0.0;
     const double* xs = dt_dev != nullptr ? xd : nullptr;
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(MTX * MSY) k_metrics2d_stages(GridDev g, const
 // 3 layers of the interior (the metric differences never read it elsewhere).
 __global__ void k_cmm_products(GridDev g, const double* __restrict__ xe, double* __restrict__ pi) {
     int i, j, k;
-    if (!box_ijk(-2 * NG, -2 * NG, -2 * NG, g.E[0], g.E[1], i, j, k)) return;
+    if (!box_ijk_xcd(-2 * NG, -2 * NG, -2 * NG, g.E[0], g.E[1], i, j, k)) return;
     const long long e = eidx(g, i, j, k);
     const long long EN = g.enodes;
     const int c[3] = {i, j, k};
@@ -305,7 +305,7 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
                             const double* __restrict__ pi, double* __restrict__ met,
                             double* __restrict__ J0) {
     int i, j, k;
-    if (!box_ijk(-NG, -NG, -NG, g.P[0], g.P[1], i, j, k)) return;
+    if (!box_ijk_xcd(-NG, -NG, -NG, g.P[0], g.P[1], i, j, k)) return;
     const long long t = pidx(g, i, j, k);
     const long long e = eidx(g, i, j, k);
     const long long EN = g.enodes;

@@ -49,6 +49,23 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + min(x, r) + k;
 }
 
+// box_ijk with the blocks of a (BX, BY, 1) x (gx, gy, gz) launch renumbered so that
+// each XCD owns one contiguous range of (x fastest, then y, then z) blocks: stencils
+// that reach across neighbouring z planes then read them through the same L2.
+__device__ __forceinline__ bool box_ijk_xcd(int lo0, int lo1, int lo2, int e0, int e1, int& i, int& j,
+                                            int& k) {
+    const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+    const int nb = gx * gy * (int)gridDim.z;
+    const int b = (int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+    const int lb = xcd_block(b, nb);
+    const int bx = lb % gx, by = (lb / gx) % gy, bz = lb / (gx * gy);
+    i = lo0 + bx * BX + (int)threadIdx.x;
+    j = lo1 + by * BY + (int)threadIdx.y;
+    k = lo2 + bz;
+    return i < lo0 + e0 && j < lo1 + e1;
+}
+
+
 // Block reductions of one double over the whole block (wavefronts of 64).
 template <int OP>   // 0 max, 1 min, 2 sum
 __device__ __forceinline__ double block_reduce(double v, double* sh) {
