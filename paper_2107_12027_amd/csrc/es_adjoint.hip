@@ -120,10 +120,30 @@ __device__ __forceinline__ void weno5_grad(double a, double b, double c, double 
     gr[4] = (-w2 + u2 + v2) * iS6;
 }
 
-template <int DIM, typename NodeFn, typename Sync, typename Out>
+// Gradient of the WENO3 value weno3(a, b, c) = (w0 q0 + w1 q1) / (2 S) with
+// q0 = 3b - a, q1 = b + c, w_k = d_k / e_k^2 (d = 1/3, 2/3), e0 = eps + (b - a)^2,
+// e1 = eps + (c - b)^2, S = w0 + w1 (any common factor of the w_k cancels):
+// dv = [w0 dq0 + w1 dq1 + (q0 - 2v) dw0 + (q1 - 2v) dw1] / (2 S), dw_k = -2 w_k de_k / e_k.
+__device__ __forceinline__ void weno3_grad(double a, double b, double c, double eps, double* gr) {
+    const double q0 = 3.0 * b - a, q1 = b + c;
+    const double e0 = eps + (b - a) * (b - a), e1 = eps + (c - b) * (c - b);
+    const double w0 = (1.0 / 3.0) * (e1 * e1), w1 = (2.0 / 3.0) * (e0 * e0);   // both times e0^2 e1^2
+    const double S = w0 + w1;
+    const double v2 = (w0 * q0 + w1 * q1) / S;                                   // 2 v
+    const double c0 = -4.0 * w0 * (q0 - v2) * (b - a) / e0;                     // times (db - da)
+    const double c1 = -4.0 * w1 * (q1 - v2) * (c - b) / e1;                     // times (dc - db)
+    const double i2S = 1.0 / (2.0 * S);
+    gr[0] = (-w0 - c0) * i2S;
+    gr[1] = (3.0 * w0 + w1 + c0 - c1) * i2S;
+    gr[2] = (w1 + c1) * i2S;
+}
+
+// P: the order parameter p (stencil of 2p nodes, WENO of order 2p - 1).
+template <int DIM, int P, typename NodeFn, typename Sync, typename Out>
 __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, const double* al,
                              const double* ar, const double* z, Out&& out) {
     constexpr int M = DIM + 2;
+    constexpr int NS = 2 * P, CI = P - 1;
     const double at = 0.5 * (al[0] + ar[0]);
     double ax[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -137,9 +157,9 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
 
     // (the stencil states are read through node(j) here and again at the end, so
     // that they need not stay in registers in between)
-    double TV[6][M];
+    double TV[NS][M];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
+    for (int j = 0; j < NS; ++j) {
         const NodeRHD<DIM> q = node(j);
         TV[j][0] = c0 + q.lr + q.lb * c1 + q.beta;
 #pragma unroll
@@ -154,13 +174,13 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
 
     // forward: the eigen-structure as a matrix (column q in Rm[q])
     double Rm[M][M];
-    const double lhat = face_eigen_columns<DIM>(G, TV[2], TV[3], at, L, [&](const double* r, int q) {
+    const double lhat = face_eigen_columns<DIM>(G, TV[CI], TV[CI + 1], at, L, [&](const double* r, int q) {
 #pragma unroll
         for (int c = 0; c < M; ++c) Rm[q][c] = r[c];
     });
     double tv2 = 0.0, tv3 = 0.0;
 #pragma unroll
-    for (int c = 0; c < M; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
+    for (int c = 0; c < M; ++c) { tv2 = fmax(tv2, fabs(TV[CI][c])); tv3 = fmax(tv3, fabs(TV[CI + 1][c])); }
     const double tvmax = tv2 + tv3;
 
     // z in the rotated frame: d = lhat T^T dd, so d(z.d)/d(dd) = lhat T z
@@ -175,43 +195,58 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
         zr[1 + a] = s;
     }
 
-    double gR[M][M], gTV[6][M], dd[M];
+    double gR[M][M], gTV[NS][M], dd[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
         dd[c] = 0.0;
 #pragma unroll
         for (int q = 0; q < M; ++q) gR[q][c] = 0.0;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) gTV[j][c] = 0.0;
+        for (int j = 0; j < NS; ++j) gTV[j][c] = 0.0;
     }
 #pragma unroll 1
     for (int q = 0; q < M; ++q) {
         const double* r = Rm[q];
-        double vt[6];
+        double vt[NS];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
+        for (int j = 0; j < NS; ++j) {
             double s = 0.0;
 #pragma unroll
             for (int c = 0; c < M; ++c) s += r[c] * TV[j][c];
             vt[j] = s;
         }
         // the jump and its switch exactly as in the forward dissipation
-        const double jwv = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps) - weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
-        const double jp = vt[3] - vt[2];
+        double jwv;
+        if (P == 3)
+            jwv = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps) - weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
+        else
+            jwv = weno3(vt[3], vt[2], vt[1], eps) - weno3(vt[0], vt[1], vt[2], eps);
+        const double jp = vt[CI + 1] - vt[CI];
         double r1 = 0.0;
 #pragma unroll
         for (int c = 0; c < M; ++c) r1 += fabs(r[c]);
         if (jwv * jp > 0.0 && fabs(jp) > RealTraits<double>::ytol * r1 * tvmax) {
             // d(jw)/d(vt_j): the upwind-from-the-right value minus the one from the left
-            double gp[5], gm[5], djw[6];
-            weno5_grad(vt[5], vt[4], vt[3], vt[2], vt[1], eps, gp);
-            weno5_grad(vt[0], vt[1], vt[2], vt[3], vt[4], eps, gm);
-            djw[0] = -gm[0];
-            djw[1] = gp[4] - gm[1];
-            djw[2] = gp[3] - gm[2];
-            djw[3] = gp[2] - gm[3];
-            djw[4] = gp[1] - gm[4];
-            djw[5] = gp[0];
+            double djw[NS];
+            if (P == 3) {
+                double gp[5], gm[5];
+                weno5_grad(vt[5], vt[4], vt[3], vt[2], vt[1], eps, gp);
+                weno5_grad(vt[0], vt[1], vt[2], vt[3], vt[4], eps, gm);
+                djw[0] = -gm[0];
+                djw[1] = gp[4] - gm[1];
+                djw[2] = gp[3] - gm[2];
+                djw[3] = gp[2] - gm[3];
+                djw[4] = gp[1] - gm[4];
+                djw[NS - 1] = gp[0];
+            } else {
+                double gp[3], gm[3];
+                weno3_grad(vt[3], vt[2], vt[1], eps, gp);
+                weno3_grad(vt[0], vt[1], vt[2], eps, gm);
+                djw[0] = -gm[0];
+                djw[1] = gp[2] - gm[1];
+                djw[2] = gp[1] - gm[2];
+                djw[NS - 1] = gp[0];
+            }
             double rz = 0.0;
 #pragma unroll
             for (int c = 0; c < M; ++c) { dd[c] += jwv * r[c]; rz += r[c] * zr[c]; }
@@ -219,7 +254,7 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
 #pragma unroll
             for (int c = 0; c < M; ++c) gR[q][c] += lhat * jwv * zr[c];
 #pragma unroll
-            for (int j = 0; j < 6; ++j) {
+            for (int j = 0; j < NS; ++j) {
                 const double gv = gjw * djw[j];
 #pragma unroll
                 for (int c = 0; c < M; ++c) {
@@ -259,17 +294,16 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
     };
     // the outer stencil nodes are complete before the eigen-structure tangents
     sync();
-    to_prim(0);
-    to_prim(1);
-    to_prim(4);
-    to_prim(5);
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+        if (j != CI && j != CI + 1) to_prim(j);
 
     // face eigen-structure: tangents along each face entropy variable (they
     // reach nodes i and i+1 through the face mean of the entropy variables)
     using D1 = Dual<1>;
     double Vb[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) Vb[c] = 0.5 * (TV[2][c] + TV[3][c]);
+    for (int c = 0; c < M; ++c) Vb[c] = 0.5 * (TV[CI][c] + TV[CI + 1][c]);
 #pragma unroll 1
     for (int k = 0; k < M; ++k) {
         D1 Vd[M];
@@ -281,12 +315,12 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
             for (int c = 0; c < M; ++c) dir += gR[q][c] * r[c].d[0];
         });
         dir += glhat * lh.d[0];
-        gTV[2][k] += 0.5 * dir;
-        gTV[3][k] += 0.5 * dir;
+        gTV[CI][k] += 0.5 * dir;
+        gTV[CI + 1][k] += 0.5 * dir;
     }
     sync();
-    to_prim(2);
-    to_prim(3);
+    to_prim(CI);
+    to_prim(CI + 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -311,7 +345,7 @@ struct AdjPlan {
     long long nlines[3];
 };
 
-template <int DIM, int DIR, bool ES>
+template <int DIM, int DIR, bool ES, int PO>
 __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G, double eps,
                                                      const double* __restrict__ prim,
                                                      const double* __restrict__ met,
@@ -415,7 +449,7 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
             for (int c = 0; c < NA; ++c) al[c] = sd[line][F_A + c][ql];
         }
 #pragma unroll 1
-        for (int nn = 1; nn <= 3; ++nn) {
+        for (int nn = 1; nn <= PO; ++nn) {
             double gl[M], gr[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) { gl[c] = 0.0; gr[c] = 0.0; }
@@ -425,7 +459,7 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
                 bool any = false;
 #pragma unroll
                 for (int c = 0; c < M; ++c) {
-                    w[c] = alpha3(nn) * idxi * (sl[line][c][qr] - sl[line][c][ql]);
+                    w[c] = alpha_pn(PO, nn) * idxi * (sl[line][c][qr] - sl[line][c][ql]);
                     any |= w[c] != 0.0;
                 }
                 if (any) {
@@ -446,7 +480,7 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
     __syncthreads();
     if (o < ASEG) {
 #pragma unroll
-        for (int nn = 1; nn <= 3; ++nn)
+        for (int nn = 1; nn <= PO; ++nn)
 #pragma unroll
             for (int c = 0; c < M; ++c)
                 acc[c] += buf[line][nn - 1][c][o + 3] + buf[line][3 + nn - 1][c][o + 3 - nn];
@@ -454,8 +488,8 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
 
     if (ES) {
         __syncthreads();
-        // ---- faces f = s0 - 3 + lane (stencil slots lane .. lane + 5); the
-        // cotangents of the six stencil states go to buf[j][.][lane]
+        // ---- faces f = s0 - 3 + lane (stencil slots lane + 3 - PO .. lane + 2 + PO); the
+        // cotangents of the 2 PO stencil states go to buf[j][.][lane]
         bool any = false;
         double z[M];
         if (active && lane < ASEG + 5) {
@@ -470,21 +504,21 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
 #pragma unroll
             for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane + 2]; ar[c] = sd[line][F_A + c][lane + 3]; }
             // the fence makes the later stages reread the stencil from LDS
-            face_vjp_rhd<DIM>(G, eps, [&](int j) { return node_at(lane + j); },
+            face_vjp_rhd<DIM, PO>(G, eps, [&](int j) { return node_at(lane + 3 - PO + j); },
                               [] { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); }, al, ar, z,
                               [&](int j, int c, double v) { buf[line][j][c][lane] = v; });
         } else {
 #pragma unroll
-            for (int j = 0; j < 6; ++j)
+            for (int j = 0; j < 2 * PO; ++j)
 #pragma unroll
                 for (int c = 0; c < M; ++c) buf[line][j][c][lane] = 0.0;
         }
         __syncthreads();
         if (o < ASEG) {
 #pragma unroll
-            for (int j = 0; j < 6; ++j)
+            for (int j = 0; j < 2 * PO; ++j)
 #pragma unroll
-                for (int c = 0; c < M; ++c) acc[c] += buf[line][j][c][o + 5 - j];
+                for (int c = 0; c < M; ++c) acc[c] += buf[line][j][c][o + 2 + PO - j];
         }
     }
 
@@ -499,7 +533,7 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
 // Cotangents of the padded primitive states, one slab (M comps, padded layout)
 // per direction; only positions along lines through interior transverse
 // coordinates are written.
-template <int DIM, bool ES>
+template <int DIM, bool ES, int PO>
 __global__ void __launch_bounds__(128) k_residual_vjp(GridDev g, double G, double eps,
                                                       const double* __restrict__ prim,
                                                       const double* __restrict__ met,
@@ -510,17 +544,17 @@ __global__ void __launch_bounds__(128) k_residual_vjp(GridDev g, double G, doubl
     const long long slab = (long long)M * g.pnodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < pl.nblk[0]) {
-        residual_vjp_segment<DIM, 0, ES>(g, G, eps, prim, met, lam, gdir, b, pl.nseg[0], pl.nlines[0], lds);
+        residual_vjp_segment<DIM, 0, ES, PO>(g, G, eps, prim, met, lam, gdir, b, pl.nseg[0], pl.nlines[0], lds);
         return;
     }
     b -= pl.nblk[0];
     if (DIM == 2 || b < pl.nblk[1]) {
-        residual_vjp_segment<DIM, 1, ES>(g, G, eps, prim, met, lam, gdir + slab, b, pl.nseg[1], pl.nlines[1], lds);
+        residual_vjp_segment<DIM, 1, ES, PO>(g, G, eps, prim, met, lam, gdir + slab, b, pl.nseg[1], pl.nlines[1], lds);
         return;
     }
     b -= pl.nblk[1];
     if (DIM == 3)
-        residual_vjp_segment<DIM, 2, ES>(g, G, eps, prim, met, lam, gdir + 2 * slab, b, pl.nseg[2], pl.nlines[2], lds);
+        residual_vjp_segment<DIM, 2, ES, PO>(g, G, eps, prim, met, lam, gdir + 2 * slab, b, pl.nseg[2], pl.nlines[2], lds);
 }
 
 // Solve A^T y = b for a small dense A (n x n, row-major) by Gaussian elimination
@@ -700,10 +734,17 @@ static void residual_vjp_all(const es_ctx* c, const double* prim, const double* 
     }
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
     const unsigned thr = 64 * ALINES;
-    if (c->scheme.dissipation != 0)
-        k_residual_vjp<DIM, true><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
-    else
-        k_residual_vjp<DIM, false><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
+    const bool es = c->scheme.dissipation != 0;
+    if (c->scheme.order_p == 2) {
+        if (es)
+            k_residual_vjp<DIM, true, 2><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
+        else
+            k_residual_vjp<DIM, false, 2><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
+    } else if (es) {
+        k_residual_vjp<DIM, true, 3><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
+    } else {
+        k_residual_vjp<DIM, false, 3><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl);
+    }
 }
 
 }  // namespace

@@ -319,6 +319,12 @@ es_status es_rk3_step_moving(es_ctx* c, double* U, double* J, double* x, const d
     return graph_step(c, U, J, x, nullptr, dt_dev, fixed_dt_dev, xdot, s);
 }
 
+// the adjoint covers the FP64 form; p = 2 for RHD, p = 3 for both systems
+static bool adjoint_supported(const es_ctx* c) {
+    if (c->scheme.mixed != 0) return false;
+    return c->scheme.order_p == 3 || (c->scheme.order_p == 2 && c->scheme.phys == ES_RHD);
+}
+
 size_t es_ckpt_doubles(const es_ctx* c) { return c ? (size_t)es::checkpoint_doubles(c) : 0; }
 
 es_status es_rk3_step_save(es_ctx* c, double* U, double* J, double* x, double* xdot, double* dt_dev,
@@ -326,7 +332,7 @@ es_status es_rk3_step_save(es_ctx* c, double* U, double* J, double* x, double* x
     if (c == nullptr || U == nullptr || J == nullptr || x == nullptr || xdot == nullptr ||
         dt_dev == nullptr || ckpt == nullptr)
         return ES_EINVAL;
-    if (c->scheme.mixed != 0 || c->scheme.order_p != 3) return ES_EUNSUPPORTED;
+    if (!adjoint_supported(c)) return ES_EUNSUPPORTED;
     return enqueue_step(c, U, J, x, xdot, dt_dev, fixed_dt_dev, s, ckpt);
 }
 
@@ -357,7 +363,7 @@ es_status es_residual_vjp(es_ctx* c, const double* U, const double* J, const dou
     if (c == nullptr || U == nullptr || J == nullptr || met == nullptr || lamU == nullptr ||
         gU == nullptr || gJ == nullptr)
         return ES_EINVAL;
-    if (c->scheme.mixed != 0 || c->scheme.order_p != 3) return ES_EUNSUPPORTED;
+    if (!adjoint_supported(c)) return ES_EUNSUPPORTED;
     const es_status st = ensure_adjoint(c);
     if (st != ES_OK) return st;
     return hip_status(es::launch_state_residual_vjp(c, U, J, met, lamU, gU, gJ, s));
@@ -368,7 +374,7 @@ es_status es_rk3_step_vjp(es_ctx* c, const double* ckpt, const double* lamU, con
     if (c == nullptr || ckpt == nullptr || lamU == nullptr || lamJ == nullptr || gU == nullptr ||
         gJ == nullptr)
         return ES_EINVAL;
-    if (c->scheme.mixed != 0 || c->scheme.order_p != 3) return ES_EUNSUPPORTED;
+    if (!adjoint_supported(c)) return ES_EUNSUPPORTED;
     const es_status st = ensure_adjoint(c);
     if (st != ES_OK) return st;
     return hip_status(es::launch_rk3_vjp(c, ckpt, lamU, lamJ, gU, gJ, s));

@@ -1,13 +1,14 @@
 """The p = 2 scheme on the GPU (4th-order EC flux and metrics, WENO3 dissipation;
 w = 2p - 1) against the oracle on identical seeded inputs: metrics and Jacobian,
 the EC and ES residuals on random curvilinear moving meshes (2D and 3D), and
-adaptive RK3 steps.  Same bars as the p = 3 path."""
+adaptive RK3 steps, and the RHD adjoint (residual and step VJPs) against the
+oracle's difference quotients.  Same bars as the p = 3 path."""
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import physics as ph, metrics as mt, stepper as st  # noqa: E402
+from oracle import physics as ph, metrics as mt, stepper as st, residual as rs  # noqa: E402
 from paper_2107_12027_amd import es, workloads as wl  # noqa: E402
 from gpu_util import Case, dev, host, empty, rel_inf  # noqa: E402
 
@@ -68,11 +69,90 @@ def test_p2_rk3_step_adaptive(name):
     assert np.max(np.abs(host(xg) - out["x"])) <= 1e-13
 
 
-def test_p2_adjoint_unsupported():
-    # the adjoint kernels carry the p = 3 stencils only: the entry points refuse p = 2
+def _oracle_L(case, U, J, met, Y=None, details=False):
+    P, ok = st.prim_from_cons(case.grid, case.scheme, U, J)
+    assert ok.all()
+    return rs.residual(case.grid, case.scheme, st.pad_solution(case.grid, P), met, details=details, Y_fixed=Y)
+
+
+@pytest.mark.parametrize("dim,n,bc,smooth", [(2, (40, 36, 1), (0, 0, 0), True), (2, (70, 66, 1), (1, 0, 0), True),
+                                             (2, (30, 33, 1), (1, 1, 0), False),
+                                             (3, (12, 10, 9), (0, 0, 0), True), (3, (12, 10, 9), (1, 1, 1), False)])
+@pytest.mark.parametrize("diss", [0, 1])
+def test_p2_residual_vjp_against_oracle_differences(dim, n, bc, smooth, diss):
+    # <gU, vU> + <gJ, vJ> against the oracle's central difference of <lam, L> along
+    # (vU, vJ), the ES switch Y held at the unperturbed state's values (the p = 3
+    # test's construction and bar)
+    case = Case(dim, n, bc, seed=21, dissipation=diss, smooth=smooth, moving=True, p=2)
+    c = case.ctx
+    U, J = case.gpu_state()
+    met = empty(c.nmet, *c.padded_shape())
+    c.metrics(dev(case.x), dev(case.xdot), met)
+    rng = np.random.default_rng(5)
+    lam = rng.normal(size=(c.m,) + c.shape())
+    gU = empty(c.m, *c.shape())
+    gJ = empty(*c.shape())
+    c.residual_vjp(U, J, met, dev(lam), gU, gJ)
+    Uo, Jo = host(U), host(J)
+    vU = Uo * rng.normal(size=Uo.shape)
+    vJ = Jo * rng.normal(size=Jo.shape)
+    adj = float(np.sum(host(gU) * vU) + np.sum(host(gJ) * vJ))
+    meto = mt.metrics(case.grid, case.x, case.xdot, 2)
+    Y = None
+    if diss:
+        _, _, info = _oracle_L(case, Uo, Jo, meto, details=True)
+        Y = {k: info[k]["Y"] for k in range(dim)}
+    h = 1e-7
+    Lp, _ = _oracle_L(case, Uo + h * vU, Jo + h * vJ, meto, Y)
+    Lm, _ = _oracle_L(case, Uo - h * vU, Jo - h * vJ, meto, Y)
+    fd = float(np.sum(lam * (Lp - Lm))) / (2 * h)
+    assert abs(adj - fd) <= 5e-7 * abs(fd), (adj, fd)
+
+
+def test_p2_rk3_step_vjp_against_oracle_differences():
+    # one adaptive quadrant step: the adjoint holds the recorded mesh velocity and
+    # dt, the oracle step is run with them prescribed and Y held
+    w = wl.quadrant_riemann(n=40, seed=2)
+    w.scheme.order_p = 2
+    g = w.grid
+    ctx = es.Context(g, w.scheme, w.monitor)
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    met = empty(ctx.nmet, *ctx.padded_shape())
+    J = empty(*ctx.shape())
+    x = dev(w.x)
+    ctx.metrics(x, None, met, J)
+    U = empty(ctx.m, *ctx.shape())
+    ctx.prim2con(dev(P[ph.comps(w.scheme.phys, g.dim)]), J, U)
+    Uo, Jo, xo = host(U).copy(), host(J).copy(), host(x).copy()
+    ck = empty(ctx.ckpt_doubles())
+    xd = empty(g.dim, *ctx.shape())
+    dt = empty(1)
+    ctx.rk3_step_save(U, J, x, xd, dt, ck)
+    assert ctx.status()[0] == es.ES_OK
+    rng = np.random.default_rng(8)
+    lamU = rng.normal(size=Uo.shape)
+    lamJ = rng.normal(size=Jo.shape)
+    gU = empty(ctx.m, *ctx.shape())
+    gJ = empty(*ctx.shape())
+    ctx.rk3_step_vjp(ck, dev(lamU), dev(lamJ), gU, gJ)
+    dt0, xdot0 = float(host(dt)[0]), host(xd)
+    base = st.rk3_step(g, w.scheme, None, Uo, Jo, xo, dt=dt0, xdot=xdot0, details=True)
+    h = 1e-8
+    for vU, vJ in ((Uo * rng.normal(size=Uo.shape), 0.0 * Jo), (0.0 * Uo, Jo * rng.normal(size=Jo.shape))):
+        adj = float(np.sum(host(gU) * vU) + np.sum(host(gJ) * vJ))
+        op = st.rk3_step(g, w.scheme, None, Uo + h * vU, Jo + h * vJ, xo, dt=dt0, xdot=xdot0, Y_fixed=base["Y"])
+        om = st.rk3_step(g, w.scheme, None, Uo - h * vU, Jo - h * vJ, xo, dt=dt0, xdot=xdot0, Y_fixed=base["Y"])
+        assert op["ok"].all() and om["ok"].all()
+        fd = float(np.sum(lamU * (op["U"] - om["U"])) + np.sum(lamJ * (op["J"] - om["J"]))) / (2 * h)
+        assert abs(adj - fd) <= 1e-6 * abs(fd), (adj, fd)
+
+
+def test_p2_mixed_adjoint_unsupported():
+    # the adjoint covers the FP64 form only: the entry points refuse the mixed form
     # before any device work
     w = wl.quadrant_riemann(n=20, seed=2)
     w.scheme.order_p = 2
+    w.scheme.mixed = 1
     ctx = es.Context(w.grid, w.scheme, w.monitor)
     t = [empty(1) for _ in range(6)]
     with pytest.raises(es.EsError) as err:
@@ -125,7 +205,8 @@ def test_p2_rmhd_rk3_step_fourier():
         assert np.max(np.abs(Ug[c] - Uo[c])) <= 1e-11 * sc, (c, np.max(np.abs(Ug[c] - Uo[c])) / sc)
 
 
-def test_p2_adjoint_unsupported():
+def test_p2_rmhd_adjoint_unsupported():
+    # the RMHD adjoint kernels carry the p = 3 stencils only
     w = wl.rmhd_fourier(n=16, seed=0)
     w.scheme.order_p = 2
     ctx = es.Context(w.grid, w.scheme, w.monitor)
