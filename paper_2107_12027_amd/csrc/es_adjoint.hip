@@ -206,7 +206,14 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
     }
 #pragma unroll 1
     for (int q = 0; q < M; ++q) {
-        const double* r = Rm[q];
+        // column q and its cotangent row through selects (no dynamic register indexing)
+        double r[M], gRq[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) { r[c] = 0.0; gRq[c] = 0.0; }
+#pragma unroll
+        for (int qq = 0; qq < M; ++qq)
+#pragma unroll
+            for (int c = 0; c < M; ++c) r[c] = qq == q ? Rm[qq][c] : r[c];
         double vt[NS];
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
@@ -252,17 +259,21 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
             for (int c = 0; c < M; ++c) { dd[c] += jwv * r[c]; rz += r[c] * zr[c]; }
             const double gjw = lhat * rz;
 #pragma unroll
-            for (int c = 0; c < M; ++c) gR[q][c] += lhat * jwv * zr[c];
+            for (int c = 0; c < M; ++c) gRq[c] += lhat * jwv * zr[c];
 #pragma unroll
             for (int j = 0; j < NS; ++j) {
                 const double gv = gjw * djw[j];
 #pragma unroll
                 for (int c = 0; c < M; ++c) {
                     gTV[j][c] += gv * r[c];
-                    gR[q][c] += gv * TV[j][c];
+                    gRq[c] += gv * TV[j][c];
                 }
             }
         }
+#pragma unroll
+        for (int qq = 0; qq < M; ++qq)
+#pragma unroll
+            for (int c = 0; c < M; ++c) gR[qq][c] = qq == q ? gRq[c] : gR[qq][c];
     }
     double glhat = 0.0;
 #pragma unroll
@@ -315,8 +326,12 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
             for (int c = 0; c < M; ++c) dir += gR[q][c] * r[c].d[0];
         });
         dir += glhat * lh.d[0];
-        gTV[CI][k] += 0.5 * dir;
-        gTV[CI + 1][k] += 0.5 * dir;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const double a = c == k ? 0.5 * dir : 0.0;
+            gTV[CI][c] += a;
+            gTV[CI + 1][c] += a;
+        }
     }
     sync();
     to_prim(CI);
