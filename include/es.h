@@ -76,9 +76,9 @@ typedef struct {
     int phys;           /* ES_RHD / ES_RMHD */
     double gamma;       /* adiabatic index of the ideal EOS (eq. EOS) */
     int order_p;        /* p of the 2p-th order EC flux and metrics with WENO of order
-                           2p - 1 (Section 4): p = 3 or p = 2 (RHD and RMHD; the
-                           adjoint entry points take p = 2 for RHD only);
-                           others give ES_EUNSUPPORTED */
+                           2p - 1 (Section 4): p = 3 or p = 2 (RHD and RMHD, the
+                           adjoint entry points included); others give
+                           ES_EUNSUPPORTED */
     int dissipation;    /* 0: entropy conservative, 1: entropy stable (WENO-(2p-1)) */
     int mixed;          /* 0: FP64 throughout.  1: FP32-mixed residual: the two-point
                            pair algebra (except the small-jump branch of the
@@ -186,7 +186,7 @@ es_status es_rk3_step(es_ctx* ctx, double* Ucurv, double* J, double* x, double* 
 es_status es_rk3_step_moving(es_ctx* ctx, double* Ucurv, double* J, double* x, const double* xdot,
                              double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
 
-/* Adjoint (FP64 form only, p = 3, or p = 2 for RHD; ES_EUNSUPPORTED otherwise).
+/* Adjoint (FP64 form only, p = 3 or p = 2; ES_EUNSUPPORTED for scheme.mixed = 1).
  * For RMHD the ES dissipation's face eigen-structure (the columns of R and
  * lambda^) is held at its forward value as well: the pair fluxes, the
  * Godunov-Powell source and the projections/WENO/accumulation of the dissipation

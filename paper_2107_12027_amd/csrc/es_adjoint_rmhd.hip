@@ -129,6 +129,23 @@ __device__ __forceinline__ void weno5_grad_m(double a, double b, double c, doubl
     gr[4] = (-w2 + u2 + v2) * iS6;
 }
 
+// Gradient of the WENO3-JS value weno3(a, b, c) = (w0 q0 + w1 q1) / (2 S), q0 = 3b - a,
+// q1 = b + c, w_k = d_k / e_k^2 (d = 1/3, 2/3), e0 = eps + (b - a)^2, e1 = eps + (c - b)^2:
+// dv = [sum_k w_k dq_k + sum_k (q_k - 2 v) dw_k] / (2 S), dw_k = -2 w_k de_k / e_k.
+__device__ __forceinline__ void weno3_grad_m(double a, double b, double c, double eps, double* gr) {
+    const double q0 = 3.0 * b - a, q1 = b + c;
+    const double e0 = eps + (b - a) * (b - a), e1 = eps + (c - b) * (c - b);
+    const double w0 = (1.0 / 3.0) * (e1 * e1), w1 = (2.0 / 3.0) * (e0 * e0);   // both times e0^2 e1^2
+    const double S = w0 + w1;
+    const double v2 = (w0 * q0 + w1 * q1) / S;
+    const double c0 = -4.0 * w0 * (q0 - v2) * (b - a) / e0;
+    const double c1 = -4.0 * w1 * (q1 - v2) * (c - b) / e1;
+    const double i2S = 1.0 / (2.0 * S);
+    gr[0] = (-w0 - c0) * i2S;
+    gr[1] = (3.0 * w0 + w1 + c0 - c1) * i2S;
+    gr[2] = (w1 + c1) * i2S;
+}
+
 // (dF/dP_l)^T w and (dF/dP_r)^T w for the RMHD two-point flux F(l, r).
 template <int DIM, int SIDE>
 __device__ __forceinline__ void pair_vjp_rmhd_side(double G, const double* Pl, const double* Pr, const double* al,
@@ -163,7 +180,8 @@ __device__ void pair_vjp_rmhd(double G, const double* Pl, const double* Pr, cons
     pair_vjp_rmhd_side<DIM, 1>(G, Pl, Pr, al, ar, w, gr);
 }
 
-template <int DIM, int DIR, bool ES>
+// PO: the order parameter p (pairs n = 1..p, face stencils of 2p nodes).
+template <int DIM, int DIR, bool ES, int PO>
 __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, double G, double eps,
                                                           const double* __restrict__ prim,
                                                           const double* __restrict__ met,
@@ -262,7 +280,7 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
             for (int c = 0; c < NA; ++c) al[c] = sd[line][F_A + c][ql];
         }
 #pragma unroll 1
-        for (int nn = 1; nn <= 3; ++nn) {
+        for (int nn = 1; nn <= PO; ++nn) {
             double gl[8], gr[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) { gl[c] = 0.0; gr[c] = 0.0; }
@@ -272,7 +290,7 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
                 bool any = false;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    w[c] = alpha3(nn) * idxi * (sl[line][c][qr] - sl[line][c][ql]);
+                    w[c] = alpha_pn(PO, nn) * idxi * (sl[line][c][qr] - sl[line][c][ql]);
                     any |= w[c] != 0.0;
                 }
                 double ar[NA];
@@ -284,7 +302,7 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
                     pair_vjp_rmhd<DIM>(G, Pl, Pr, al, ar, w, gl, gr);
                 }
                 // source pair B~: linear in B_j of both nodes
-                const double wB = alpha3(nn) * idxi * (lamPp(qr) - lamPp(ql));
+                const double wB = alpha_pn(PO, nn) * idxi * (lamPp(qr) - lamPp(ql));
 #pragma unroll
                 for (int j = 0; j < DIM; ++j) {
                     const double cb = 0.25 * wB * (al[1 + j] + ar[1 + j]);
@@ -302,7 +320,7 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
     __syncthreads();
     if (o < QSEG) {
 #pragma unroll
-        for (int nn = 1; nn <= 3; ++nn)
+        for (int nn = 1; nn <= PO; ++nn)
 #pragma unroll
             for (int c = 0; c < 8; ++c)
                 acc[c] += buf[line][nn - 1][c][o + 3] + buf[line][3 + nn - 1][c][o + 3 - nn];
@@ -314,10 +332,12 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
     for (int c = 0; c < 8; ++c) gV[c] = 0.0;
     if (ES) {
         __syncthreads();
-        // faces f = s0 - 3 + lane (stencil slots lane .. lane + 5, nodes i, i+1 at lane + 2, lane + 3)
-        double gw[6][8];
+        // faces f = s0 - 3 + lane (stencil slots lane + 3 - PO .. lane + 2 + PO, nodes i, i+1 at
+        // lane + 2, lane + 3); stencil node j at slot lane + 3 - PO + j, CI = PO - 1 the node i
+        constexpr int NS = 2 * PO, CI = PO - 1, J0 = 3 - PO;
+        double gw[NS][8];
 #pragma unroll
-        for (int j = 0; j < 6; ++j)
+        for (int j = 0; j < NS; ++j)
 #pragma unroll
             for (int c = 0; c < 8; ++c) gw[j][c] = 0.0;
         if (active && lane < QSEG + 5) {
@@ -336,8 +356,8 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
                 for (int c = 0; c < NA; ++c) { al[c] = sd[line][F_A + c][lane + 2]; ar[c] = sd[line][F_A + c][lane + 3]; }
                 // the eigen-structure of this face (held at its forward value) from
                 // k_face_eigen_rmhd: face f = p + 1 of line lid, p = s0 - 3 + lane
-                double T[3][3], TV[6][8], at, L, Rc[8][8];
-                face_frame_rmhd<DIM>(G, P2, P3, al, ar, T, TV[2], TV[3], at, L);
+                double T[3][3], TV[NS][8], at, L, Rc[8][8];
+                face_frame_rmhd<DIM>(G, P2, P3, al, ar, T, TV[CI], TV[CI + 1], at, L);
                 const double* ef = eig + lid * (n + 1) + (s0 - 2 + lane);
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
@@ -345,42 +365,46 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
                     for (int i = 0; i < 8; ++i) Rc[k][i] = ef[(k * 8 + i) * enf];
                 const double lhat = ef[64 * enf];
 #pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    if (j == 2 || j == 3) continue;
+                for (int j = 0; j < NS; ++j) {
+                    if (j == CI || j == CI + 1) continue;
                     double Pj[8], V[8];
-                    prim_at(lane + j, Pj);
+                    prim_at(lane + J0 + j, Pj);
                     const StateRMHD<double> st = rmhd_state<double>(G, Pj);
                     rmhd_entropy_vars<double>(G, st, V);
                     rotate8<false>(T, V, TV[j]);
                 }
                 double tv2 = 0.0, tv3 = 0.0;
 #pragma unroll
-                for (int c = 0; c < 8; ++c) { tv2 = fmax(tv2, fabs(TV[2][c])); tv3 = fmax(tv3, fabs(TV[3][c])); }
+                for (int c = 0; c < 8; ++c) { tv2 = fmax(tv2, fabs(TV[CI][c])); tv3 = fmax(tv3, fabs(TV[CI + 1][c])); }
                 const double tvmax = tv2 + tv3;
                 // d = lhat T^T dd: cotangent of dd
                 double gdd[8];
                 rotate8<false>(T, z, gdd);
 #pragma unroll
                 for (int c = 0; c < 8; ++c) gdd[c] *= lhat;
-                double gTV[6][8];
+                double gTV[NS][8];
 #pragma unroll
-                for (int j = 0; j < 6; ++j)
+                for (int j = 0; j < NS; ++j)
 #pragma unroll
                     for (int c = 0; c < 8; ++c) gTV[j][c] = 0.0;
 #pragma unroll 1
                 for (int k = 0; k < 8; ++k) {
                     const double* r = Rc[k];
-                    double vt[6];
+                    double vt[NS];
 #pragma unroll
-                    for (int j = 0; j < 6; ++j) {
+                    for (int j = 0; j < NS; ++j) {
                         double s = 0.0;
 #pragma unroll
                         for (int c = 0; c < 8; ++c) s += r[c] * TV[j][c];
                         vt[j] = s;
                     }
-                    const double jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps) -
-                                      weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
-                    const double jp = vt[3] - vt[2];
+                    double jw;
+                    if (PO == 3)
+                        jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], eps) -
+                             weno5(vt[0], vt[1], vt[2], vt[3], vt[4], eps);
+                    else
+                        jw = weno3(vt[3], vt[2], vt[1], eps) - weno3(vt[0], vt[1], vt[2], eps);
+                    const double jp = vt[CI + 1] - vt[CI];
                     double r1 = 0.0;
 #pragma unroll
                     for (int c = 0; c < 8; ++c) r1 += fabs(r[c]);
@@ -388,17 +412,28 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
                         double gjw = 0.0;
 #pragma unroll
                         for (int c = 0; c < 8; ++c) gjw += gdd[c] * r[c];
-                        double gp[5], gm[5], djw[6];
-                        weno5_grad_m(vt[5], vt[4], vt[3], vt[2], vt[1], eps, gp);
-                        weno5_grad_m(vt[0], vt[1], vt[2], vt[3], vt[4], eps, gm);
-                        djw[0] = -gm[0];
-                        djw[1] = gp[4] - gm[1];
-                        djw[2] = gp[3] - gm[2];
-                        djw[3] = gp[2] - gm[3];
-                        djw[4] = gp[1] - gm[4];
-                        djw[5] = gp[0];
+                        double djw[NS];
+                        if (PO == 3) {
+                            double gp[5], gm[5];
+                            weno5_grad_m(vt[5], vt[4], vt[3], vt[2], vt[1], eps, gp);
+                            weno5_grad_m(vt[0], vt[1], vt[2], vt[3], vt[4], eps, gm);
+                            djw[0] = -gm[0];
+                            djw[1] = gp[4] - gm[1];
+                            djw[2] = gp[3] - gm[2];
+                            djw[3] = gp[2] - gm[3];
+                            djw[4] = gp[1] - gm[4];
+                            djw[NS - 1] = gp[0];
+                        } else {
+                            double gp[3], gm[3];
+                            weno3_grad_m(vt[3], vt[2], vt[1], eps, gp);
+                            weno3_grad_m(vt[0], vt[1], vt[2], eps, gm);
+                            djw[0] = -gm[0];
+                            djw[1] = gp[2] - gm[1];
+                            djw[2] = gp[1] - gm[2];
+                            djw[NS - 1] = gp[0];
+                        }
 #pragma unroll
-                        for (int j = 0; j < 6; ++j) {
+                        for (int j = 0; j < NS; ++j) {
                             const double gv = gjw * djw[j];
 #pragma unroll
                             for (int c = 0; c < 8; ++c) gTV[j][c] += gv * r[c];
@@ -407,19 +442,19 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
                 }
                 // TV_j = T V_j: cotangent of V_j
 #pragma unroll
-                for (int j = 0; j < 6; ++j) rotate8<true>(T, gTV[j], gw[j]);
+                for (int j = 0; j < NS; ++j) rotate8<true>(T, gTV[j], gw[j]);
             }
         }
 #pragma unroll
-        for (int j = 0; j < 6; ++j)
+        for (int j = 0; j < NS; ++j)
 #pragma unroll
             for (int c = 0; c < 8; ++c) buf[line][j][c][lane] = gw[j][c];
         __syncthreads();
         if (o < QSEG) {
 #pragma unroll
-            for (int j = 0; j < 6; ++j)
+            for (int j = 0; j < NS; ++j)
 #pragma unroll
-                for (int c = 0; c < 8; ++c) gV[c] += buf[line][j][c][o + 5 - j];
+                for (int c = 0; c < 8; ++c) gV[c] += buf[line][j][c][o + 5 - J0 - j];
         }
     }
 
@@ -430,7 +465,7 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
         const int q = o + 5;
         double dB = 0.0;
 #pragma unroll
-        for (int nn = 1; nn <= 3; ++nn) dB += alpha3(nn) * (bpair(q, q + nn) - bpair(q - nn, q));
+        for (int nn = 1; nn <= PO; ++nn) dB += alpha_pn(PO, nn) * (bpair(q, q + nn) - bpair(q - nn, q));
         dB *= idxi;
         double lq[8];
 #pragma unroll
@@ -460,7 +495,7 @@ __device__ __forceinline__ void residual_vjp_segment_rmhd(const GridDev& g, doub
     }
 }
 
-template <int DIM, bool ES>
+template <int DIM, bool ES, int PO>
 __global__ void __launch_bounds__(128) k_residual_vjp_rmhd(GridDev g, double G, double eps,
                                                            const double* __restrict__ prim,
                                                            const double* __restrict__ met,
@@ -471,19 +506,19 @@ __global__ void __launch_bounds__(128) k_residual_vjp_rmhd(GridDev g, double G, 
     const long long slab = 8LL * g.pnodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < pl.nblk[0]) {
-        residual_vjp_segment_rmhd<DIM, 0, ES>(g, G, eps, prim, met, lam, gdir, b, pl.nseg[0], pl.nlines[0], lds,
+        residual_vjp_segment_rmhd<DIM, 0, ES, PO>(g, G, eps, prim, met, lam, gdir, b, pl.nseg[0], pl.nlines[0], lds,
                                               eig + fp.base[0], fp.nlines[0] * fp.nface[0]);
         return;
     }
     b -= pl.nblk[0];
     if (DIM == 2 || b < pl.nblk[1]) {
-        residual_vjp_segment_rmhd<DIM, 1, ES>(g, G, eps, prim, met, lam, gdir + slab, b, pl.nseg[1], pl.nlines[1],
+        residual_vjp_segment_rmhd<DIM, 1, ES, PO>(g, G, eps, prim, met, lam, gdir + slab, b, pl.nseg[1], pl.nlines[1],
                                               lds, eig + fp.base[1], fp.nlines[1] * fp.nface[1]);
         return;
     }
     b -= pl.nblk[1];
     if (DIM == 3)
-        residual_vjp_segment_rmhd<DIM, 2, ES>(g, G, eps, prim, met, lam, gdir + 2 * slab, b, pl.nseg[2],
+        residual_vjp_segment_rmhd<DIM, 2, ES, PO>(g, G, eps, prim, met, lam, gdir + 2 * slab, b, pl.nseg[2],
                                               pl.nlines[2], lds, eig + fp.base[2], fp.nlines[2] * fp.nface[2]);
 }
 
@@ -627,11 +662,18 @@ static void residual_vjp_all_rmhd(const es_ctx* c, const double* prim, const dou
         long long nt = 0;
         for (int d = 0; d < DIM; ++d) nt += fp.nthreads[d];
         k_face_eigen_rmhd<DIM><<<(unsigned)((nt + 63) / 64), 64, 0, s>>>(g, G, prim, met, c->adj_eig, fp);
-        k_residual_vjp_rmhd<DIM, true><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl,
-                                                                     c->adj_eig, fp);
+        if (c->scheme.order_p == 2)
+            k_residual_vjp_rmhd<DIM, true, 2><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl,
+                                                                            c->adj_eig, fp);
+        else
+            k_residual_vjp_rmhd<DIM, true, 3><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl,
+                                                                            c->adj_eig, fp);
+    } else if (c->scheme.order_p == 2) {
+        k_residual_vjp_rmhd<DIM, false, 2><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl,
+                                                                         nullptr, fp);
     } else {
-        k_residual_vjp_rmhd<DIM, false><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl,
-                                                                      nullptr, fp);
+        k_residual_vjp_rmhd<DIM, false, 3><<<(unsigned)nb, thr, 0, s>>>(g, G, eps, prim, met, lam, gdir, pl,
+                                                                         nullptr, fp);
     }
 }
 

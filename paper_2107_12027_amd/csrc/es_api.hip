@@ -319,10 +319,9 @@ es_status es_rk3_step_moving(es_ctx* c, double* U, double* J, double* x, const d
     return graph_step(c, U, J, x, nullptr, dt_dev, fixed_dt_dev, xdot, s);
 }
 
-// the adjoint covers the FP64 form; p = 2 for RHD, p = 3 for both systems
+// the adjoint covers the FP64 form, p = 2 and p = 3
 static bool adjoint_supported(const es_ctx* c) {
-    if (c->scheme.mixed != 0) return false;
-    return c->scheme.order_p == 3 || (c->scheme.order_p == 2 && c->scheme.phys == ES_RHD);
+    return c->scheme.mixed == 0 && (c->scheme.order_p == 3 || c->scheme.order_p == 2);
 }
 
 size_t es_ckpt_doubles(const es_ctx* c) { return c ? (size_t)es::checkpoint_doubles(c) : 0; }

@@ -252,8 +252,8 @@ RCASES = [(2, (40, 36, 1), (0, 0, 0), True), (2, (30, 33, 1), (1, 1, 0), False),
 
 @pytest.mark.parametrize("dim,n,bc,smooth", RCASES)
 @pytest.mark.parametrize("diss", [0, 1])
-def test_rmhd_residual_vjp_against_oracle_differences(dim, n, bc, smooth, diss):
-    case = Case(dim, n, bc, phys=ph.RMHD, seed=23, dissipation=diss, smooth=smooth, moving=True)
+def test_rmhd_residual_vjp_against_oracle_differences(dim, n, bc, smooth, diss, p=3):
+    case = Case(dim, n, bc, phys=ph.RMHD, seed=23, dissipation=diss, smooth=smooth, moving=True, p=p)
     c = case.ctx
     U, J = case.gpu_state()
     met = empty(c.nmet, *c.padded_shape())
@@ -267,7 +267,7 @@ def test_rmhd_residual_vjp_against_oracle_differences(dim, n, bc, smooth, diss):
     vU = Uo * rng.normal(size=Uo.shape) * 1e-2
     vJ = Jo * rng.normal(size=Jo.shape) * 1e-2
     adj = float(np.sum(host(gU) * vU) + np.sum(host(gJ) * vJ))
-    meto = mt.metrics(case.grid, case.x, case.xdot)
+    meto = mt.metrics(case.grid, case.x, case.xdot, p)
     Y = eig = None
     if diss:
         _, _, info = _oracle_L(case, Uo, Jo, meto, details=True)

@@ -205,14 +205,11 @@ def test_p2_rmhd_rk3_step_fourier():
         assert np.max(np.abs(Ug[c] - Uo[c])) <= 1e-11 * sc, (c, np.max(np.abs(Ug[c] - Uo[c])) / sc)
 
 
-def test_p2_rmhd_adjoint_unsupported():
-    # the RMHD adjoint kernels carry the p = 3 stencils only
-    w = wl.rmhd_fourier(n=16, seed=0)
-    w.scheme.order_p = 2
-    ctx = es.Context(w.grid, w.scheme, w.monitor)
-    assert ctx.ckpt_doubles() > 0
-    with pytest.raises(es.EsError) as err:
-        U = empty(ctx.m, *ctx.shape())
-        ctx.rk3_step_save(U, empty(*ctx.shape()), empty(2, *ctx.shape()), empty(2, *ctx.shape()), empty(1),
-                          empty(ctx.ckpt_doubles()))
-    assert err.value.status == es.ES_EUNSUPPORTED
+def test_p2_rmhd_residual_vjp_against_oracle_differences():
+    # the RMHD residual VJP at p = 2 (EC and ES, 2D and 3D) against the oracle's
+    # central differences with Y and the face eigen-structure held at the
+    # unperturbed state (the p = 3 test's construction and bar)
+    from test_gpu_adjoint import test_rmhd_residual_vjp_against_oracle_differences as p3
+    for dim, n, bc, smooth in [(2, (40, 36, 1), (0, 0, 0), True), (3, (12, 10, 9), (0, 1, 0), True)]:
+        for diss in (0, 1):
+            p3(dim, n, bc, smooth, diss, p=2)
