@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import physics as ph, dissipation as ds
-from oracle_util import rand_P, prim_from_V
+from oracle_util import rand_P
 
 G = 5.0 / 3.0
 CASES = [(ph.RHD, 2), (ph.RHD, 3), (ph.RMHD, 2)]
@@ -25,7 +25,8 @@ def test_rotation_orthogonal_first_row_normal():
 
 def _A0_and_S(Pr, phys, dim):
     """A0 = dU/dV and S = dF_1/dV (+ Godunov-Powell term) by complex step through the
-    explicit inverse V -> P, an independent route from the oracle's primitive one."""
+    explicit inverse V -> P (physics.prim_from_entropy_vars, pinned by its round
+    trip in test_oracle_pins), a route independent of the oracle's primitive one."""
     sel = ph.comps(phys, dim)
     V = ph.entropy_vars(Pr, G)
     N = Pr.shape[1]
@@ -37,7 +38,7 @@ def _A0_and_S(Pr, phys, dim):
     for b, sb in enumerate(sel):
         Vc = V.astype(complex)
         Vc[sb] += 1j * h
-        Pc = prim_from_V(Vc, G, phys, dim)
+        Pc = ph.prim_from_entropy_vars(Vc, G)
         A0[:, :, b] = (ph.cons(Pc, G)[sel].imag / h).T
         S[:, :, b] = (ph.flux(Pc, G, 0)[sel].imag / h).T
     if phys == ph.RMHD:
