@@ -1,18 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark: cell-updates/s of one SSP-RK3 step of the entropy-stable adaptive
-moving-mesh scheme (2D RHD quadrant Riemann problem, 400 x 400 nodes, adaptive
-mesh with 10 Jacobi sweeps, FP64) on one MI355X.
+moving-mesh scheme on one MI355X.
 
-One step = the whole hot path: con2prim, CFL step, mesh redistribution
-(monitor, filter, Jacobi sweeps, Delta_tau, new mesh and mesh velocity) and
-three Runge-Kutta stages of metrics + con2prim + residual + combination.
-Inputs are resident in HBM before the timed region; the time step stays on the
-device (no host synchronisation inside the timed steps).
+Headline workload (default): 3D RHD blast wave, 128^3 nodes on [0,1]^3,
+outflow, adaptive mesh (paper monitor on rho, alpha 800, 3 filter passes, 5
+Jacobi sweeps), CFL 0.3, seed 0, 100 RK3 steps, FP64 -- the largest
+single-GPU workload of the set.  One step = the whole hot path: con2prim, CFL
+step, mesh redistribution (monitor, filter, Jacobi sweeps, Delta_tau, new mesh
+and mesh velocity) and three Runge-Kutta stages of metrics + con2prim +
+residual + combination.  Inputs are resident in HBM before the timed region;
+the time step stays on the device (no host synchronisation inside the timed
+steps).  The W warm-up steps run first; the state is then reset to the initial
+data and exactly K steps are timed, so with the default K = 100 the timed run
+is the workload's 100 steps.
 
-The headline value is the FP64 path.  The same workload is then timed in the
-FP32-mixed form (scheme.mixed = 1) and reported under "mixed", with the relative
-L1 error of one step from the initial data against the oracle's step for both
-forms (the oracle step is the cpu_baseline run).
+The same K steps are timed in the FP32-mixed form (scheme.mixed = 1) and the
+relative L1 difference of the final states (mixed vs FP64) is reported per
+conserved component under "mixed".  "cpu_baseline" is the oracle (numpy,
+limited to one thread) timed on one step of the same blast recipe at a small
+size (32^3 by default); the GPU FP64 and mixed steps of that sample are compared
+with the oracle's step.  The other workloads (advected sine, quadrant seeds 0-3,
+RMHD rotor, the RMHD adjoint configuration) are reported as extra objects.
 
 Prints one JSON line (see the repository contract).  ``--gpus N`` with N > 1
 exits: this build runs on one GPU.
@@ -33,39 +41,47 @@ METRIC = "cell-updates/s per RK3 step, FP64 vs FP32-mixed at stated L1 err; adjo
 PEAK_FP64_VECTOR = 78.6e12       # FLOP/s, MI355X FP64 vector (FMA = 2 flops)
 PEAK_HBM = 8.0e12                # B/s
 
-# Algorithmic FP64 operations of one es_residual call per interior node (both
-# directions of the 2D RHD ES scheme, p = 3): counted by executing the device
-# arithmetic of the two-point flux and of the face dissipation with an
-# op-counting scalar (paper_2107_12027_amd/csrc/opcount.cpp, run by
-# `python -m paper_2107_12027_amd.build --opcount`): + - * / sqrt log exp fabs
-# fmax count 1, fma counts 2.  Per node and direction: 3 two-point fluxes
-# (102.3 each), 1 face dissipation (1494.7), state preparation (6) and the
-# flux-difference accumulation (66): 1873.7; two directions: 3747.5.
+# Algorithmic FP64 operations of one es_residual call per interior node: counted
+# by executing the device arithmetic of the two-point flux and of the face
+# dissipation with an op-counting scalar (paper_2107_12027_amd/csrc/opcount.cpp,
+# run by `python -m paper_2107_12027_amd.build --opcount`): + - * / sqrt log exp
+# fabs fmax count 1, fma counts 2.  2D RHD ES, p = 3, per node and direction: 3
+# two-point fluxes (102.3 each), 1 face dissipation (1494.7), state preparation
+# (6) and the flux-difference accumulation (66): 1873.7; two directions: 3747.5.
+# 3D RHD ES: 2771.0 per direction, 8313.0 for the three.
 RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3747.5
+RESIDUAL_FLOPS_PER_NODE_3D_RHD = 8313.0
 
-# HBM bytes of one es_residual call on the 400 x 400 quadrant workload, from the
-# FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run) of
-# k_residual_rhd and k_sum_dirs, scaled by what the same counters read for a
-# 1 GiB device copy (FETCH x 2.000, WRITE x 1.000); the summary with its commands
-# is profiles/es_residual_hbm_counters_rhd2d_quadrant_400.txt.  Valid for the
-# kernels as they were measured; None for other workloads.
-RESIDUAL_TRAFFIC_BYTES_QUADRANT_400 = 57.73e6
+# HBM bytes of one es_residual call, from the FETCH_SIZE and WRITE_SIZE counters
+# (rocprofv3 --pmc, one counter per run) of the residual kernel and k_sum_dirs,
+# scaled by what the same counters read for a 1 GiB device copy (FETCH x 2.000,
+# WRITE x 1.000).  Valid for the kernels as they were measured; the summaries
+# with their commands are the es_residual_hbm_counters_* files under profiles/.
+RESIDUAL_TRAFFIC_BYTES = {
+    "rhd2d_quadrant_riemann_400_seed2": 57.73e6,
+}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=400)
-    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=None,
+                    help="grid size of the workload (default: 128 for the 3D blast, 400 for the quadrant)")
+    ap.add_argument("--seed", type=int, default=None,
+                    help="seed of the workload (default: 0 for the 3D blast, 2 for the quadrant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--residual-reps", type=int, default=50)
-    ap.add_argument("--adjoint-steps", type=int, default=20)
-    ap.add_argument("--workload", default="quadrant",
-                    choices=["quadrant", "sine", "rotor", "blast3d", "fourier"],
-                    help="quadrant: the headline 2D RHD problem; the others time the remaining "
-                         "workloads (FP64 step and residual only)")
+    ap.add_argument("--cpu-n", type=int, default=32,
+                    help="size n^3 of the blast sample the oracle is timed on (cpu_baseline)")
+    ap.add_argument("--residual-reps", type=int, default=20)
+    ap.add_argument("--adjoint-steps", type=int, default=10)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the extra objects (advected sine, quadrant seeds, rotor, adjoint configuration)")
+    ap.add_argument("--workload", default="blast3d",
+                    choices=["blast3d", "quadrant", "sine", "rotor", "fourier"],
+                    help="blast3d: the headline 3D RHD blast; the others time one of the remaining "
+                         "workloads alone (FP64 and mixed step, residual)")
     ap.add_argument("--paper-case", default=None,
                     choices=["rp1", "rp2", "rp3", "rmhd_blast", "shock_cloud", "vortex2d", "vortex3d"],
                     help="run one of the paper's 2D examples to its end time as MM-O5 (adaptive) and "
@@ -76,36 +92,37 @@ def parse():
                     help="mesh sizes N of the vortex study (2D: N x N, default 20,40,80,160; "
                          "3D: N x N x 5N, default 16,24,32,48,64)")
     ap.add_argument("--no-fourier-gradient", action="store_true",
-                    help="skip the gradient study of the adjoint configuration (objects adjoint_fourier*)")
+                    help="skip the gradient study of the adjoint configuration (object c5_adjoint)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed work, copy one buffer of this size once (a plain copy "
                          "kernel of known traffic, for scaling HBM counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(n, seed):
-    """The oracle as it stands, timed on the host for one RK3 step of the same
-    workload; also returns the oracle's state after that step."""
+def oracle_step(w):
+    """One RK3 step of workload ``w`` by the oracle as it stands (numpy, BLAS and
+    OpenMP pools limited to one thread), timed on the host.  Returns (seconds,
+    Ucurv after the step or None if con2prim failed)."""
+    from threadpoolctl import threadpool_limits
     from oracle import physics as ph, stepper as st
-    from paper_2107_12027_amd import workloads as wl
-    w = wl.quadrant_riemann(n=n, seed=seed)
     P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
-    U, J = st.initial_state(w.grid, w.scheme, P, w.x)
-    t0 = time.perf_counter()
-    out = st.rk3_step(w.grid, w.scheme, w.monitor, U, J, w.x)
-    t = time.perf_counter() - t0
-    if not out["ok"].all():
-        return None, None
-    return ({"value": w.grid.nnodes / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-             "sample": "one SSP-RK3 step of the full %dx%d workload from its initial state "
-                       "(numpy oracle, %.1f s)" % (n, n, t)}, out["U"])
+    with threadpool_limits(limits=1):
+        U, J = st.initial_state(w.grid, w.scheme, P, w.x)
+        t0 = time.perf_counter()
+        out = st.rk3_step(w.grid, w.scheme, w.monitor, U, J, w.x)
+        t = time.perf_counter() - t0
+    return t, (out["U"] if out["ok"].all() else None)
 
 
-def l1_rel(a, b):
-    import numpy as np
-    a = np.asarray(a).reshape(a.shape[0], -1)
-    b = np.asarray(b).reshape(b.shape[0], -1)
-    return [float(v) for v in np.abs(a - b).sum(axis=1) / np.abs(b).sum(axis=1)]
+def cpu_baseline(w):
+    """cpu_baseline object: the oracle timed on one step of the sample workload."""
+    t, Uo = oracle_step(w)
+    shape = "x".join(str(s) for s in w.grid.shape[::-1])
+    cpu = {"value": w.grid.nnodes / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+           "host_cpus": os.cpu_count(),
+           "sample": "one SSP-RK3 step of %s (%s nodes, the headline recipe at a smaller size) from its "
+                     "initial state: numpy oracle limited to one thread, %.1f s" % (w.name, shape, t)}
+    return cpu, Uo
 
 
 class Run:
@@ -134,31 +151,50 @@ class Run:
         ctx.prim2con(dev(P[sel]), self.J, self.U)
         self.xdot = torch.empty_like(self.x)
         self.dt = torch.empty(1, dtype=torch.float64, device="cuda")
+        self.init = (self.U.clone(), self.J.clone(), self.x.clone())
+
+    def reset(self):
+        """Back to the initial data (same tensors, so a captured step graph stays valid)."""
+        U0, J0, x0 = self.init
+        self.U.copy_(U0)
+        self.J.copy_(J0)
+        self.x.copy_(x0)
 
     def step(self):
         self.ctx.rk3_step(self.U, self.J, self.x, self.xdot, self.dt)
 
-    def timed(self, steps, warmup):
+    def timed(self, steps, warmup, reset=True):
+        """W warm-up steps, then (reset=True) back to the initial data, then K timed
+        steps between HIP events on the current stream.  Returns (GPU ms for the K
+        steps, host wall seconds of the same region)."""
         import torch
         for _ in range(warmup):
             self.step()
         torch.cuda.synchronize()
-        st0 = self.ctx.status()[0]
+        st0, nf0, ff0 = self.ctx.status()
+        if st0 != 0:
+            print("bench.py: failure in the warm-up steps (status %d, %d nodes, first %d)" % (st0, nf0, ff0),
+                  file=sys.stderr)
+            sys.exit(3)
+        if reset:
+            self.reset()
         stream = torch.cuda.current_stream()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
         e0.record(stream)
         for _ in range(steps):
             self.step()
         e1.record(stream)
         torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
         status, nfail, first = self.ctx.status()
-        if st0 != 0 or status != 0:
-            print("bench.py: con2prim failure during the run (status %d, %d nodes, first %d)"
+        if status != 0:
+            print("bench.py: failure during the timed steps (status %d, %d nodes, first %d)"
                   % (status, nfail, first), file=sys.stderr)
             sys.exit(3)
-        return e0.elapsed_time(e1)
+        return e0.elapsed_time(e1), wall
 
     def residual_ms(self, reps):
         """Average es_residual time on the current state (HIP events on the launch stream)."""
@@ -264,8 +300,7 @@ def fourier_gradient(n=256, steps=100, h=1e-6, eps=0.05, rmhd=True):
         P0 = dev(np.concatenate([w.prim["rho"][None], w.prim["u"], w.prim["p"][None], w.prim["B"]]))
     else:
         P0 = dev(np.stack([w.prim["rho"], w.prim["u"][0], w.prim["u"][1], w.prim["p"]]))
-    tang = losses.density_mode_tangents(ctx, P0, J0, dev(wl.fourier_basis(w.x)), eps)
-    grad = (tang * gU[None]).sum(dim=(1, 2, 3)).cpu().numpy()
+    grad = losses.density_mode_gradient(ctx, P0, J0, gU, dev(wl.fourier_basis(w.x)), eps).cpu().numpy()
     del ck
 
     def loss(c):
@@ -293,53 +328,275 @@ def _cfl_inputs(run):
     return run.prim, run.met, run.J
 
 
-RESIDUAL_FLOPS_PER_NODE_3D_RHD = 8313.0   # same count, 3 directions (2771.0 each)
+def residual_flops(w):
+    """Algorithmic FP64 ops of one es_residual call per interior node (RHD ES, p = 3)."""
+    if w.scheme.phys != 0 or w.scheme.order_p != 3 or w.scheme.dissipation != 1:
+        return None
+    return RESIDUAL_FLOPS_PER_NODE_2D_RHD if w.grid.dim == 2 else RESIDUAL_FLOPS_PER_NODE_3D_RHD
 
 
-def other_workload(args):
-    """Time one of the other workloads: RK3 steps and es_residual, FP64 and
-    FP32-mixed."""
+def l1_rel_diff(a, b):
+    """Relative L1 difference per component of two (comps, ...) arrays: sum|a - b| / sum|b|
+    (components with sum|b| = 0 report the absolute mean difference)."""
     import numpy as np
-    from paper_2107_12027_amd import workloads as wl
-    make = {"sine": lambda: wl.advected_sine(n=64),
-            "rotor": lambda: wl.rmhd_rotor(n=512),
-            "blast3d": lambda: wl.blast3d(n=128, seed=0),
-            "fourier": lambda: wl.rmhd_fourier(n=256, seed=0)}[args.workload]
-    w = make()
+    a = np.asarray(a).reshape(a.shape[0], -1)
+    b = np.asarray(b).reshape(b.shape[0], -1)
+    den = np.abs(b).sum(axis=1)
+    num = np.abs(a - b).sum(axis=1)
+    return [float(n / d) if d > 0 else float(n / a.shape[1]) for n, d in zip(num, den)]
+
+
+def fp64_and_mixed(w, steps, warmup, reps):
+    """K timed steps of workload ``w`` in the FP64 and the FP32-mixed forms from the
+    same initial data, es_residual timing on the FP64 run's final state, and the
+    relative L1 difference of the two final states per conserved component."""
     run = Run(w, 0)
-    t_ms = run.timed(args.steps, args.warmup)
-    res_ms = run.residual_ms(args.residual_reps)
-    # the FP32-mixed form over the same steps from the same initial data, and the
-    # relative L1 difference of the final states (per conserved component)
+    t_ms, wall = run.timed(steps, warmup)
+    res_ms = run.residual_ms(reps)
     mrun = Run(w, 1)
-    t_mixed_ms = mrun.timed(args.steps, args.warmup)
-    res_mixed_ms = mrun.residual_ms(args.residual_reps)
-    a, b = mrun.U.cpu().numpy(), run.U.cpu().numpy()
-    a, b = a.reshape(a.shape[0], -1), b.reshape(b.shape[0], -1)
-    den = np.maximum(np.abs(b).sum(axis=1), 1e-300)
-    mixed = {"ms_per_step": t_mixed_ms / args.steps, "es_residual_ms": res_mixed_ms,
-             "speedup_vs_fp64": t_ms / t_mixed_ms,
-             "l1_rel_diff_vs_fp64": (np.abs(a - b).sum(axis=1) / den).tolist(),
-             "diff_sample": "final states after the %d warm-up and %d timed steps of both forms"
-                            % (args.warmup, args.steps)}
+    t_mixed_ms, _ = mrun.timed(steps, warmup)
+    res_mixed_ms = mrun.residual_ms(reps)
+    diff = l1_rel_diff(mrun.U.cpu().numpy(), run.U.cpu().numpy())
     nodes = w.grid.nnodes
-    flops = None
-    if w.scheme.phys == 0:
-        flops = RESIDUAL_FLOPS_PER_NODE_2D_RHD if w.grid.dim == 2 else RESIDUAL_FLOPS_PER_NODE_3D_RHD
+    mixed = {"value": nodes * steps / (t_mixed_ms * 1e-3), "unit": "cell-updates/s",
+             "ms_per_step": t_mixed_ms / steps, "es_residual_ms": res_mixed_ms,
+             "speedup_vs_fp64": t_ms / t_mixed_ms,
+             "dtype": "f32 pair algebra and dissipation, f64 elsewhere",
+             "l1_rel_diff_vs_fp64": diff,
+             "diff_sample": "final conserved states (Ucurv components in order) after the same %d steps "
+                            "from the initial data in both forms" % steps}
+    flops = residual_flops(w)
     roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
-            "frac": None, "traffic": None, "kernel": "es_residual", "avg_launch_ms": res_ms}
+            "frac": None, "traffic": RESIDUAL_TRAFFIC_BYTES.get(w.name),
+            "traffic_unit": "HBM bytes per es_residual call",
+            "kernel": "es_residual (the residual kernel, all directions in one launch, + k_sum_dirs)",
+            "avg_launch_ms": res_ms, "flops_per_node": flops}
     if flops is not None:
         ach = flops * nodes / (res_ms * 1e-3)
         roof["achieved"] = ach / 1e12
         roof["frac"] = ach / PEAK_FP64_VECTOR
-    line = {"metric": METRIC, "value": nodes * args.steps / (t_ms * 1e-3), "unit": "cell-updates/s",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_ms / args.steps,
+    if roof["traffic"] is not None:
+        roof["hbm_achieved_gbs"] = roof["traffic"] / (res_ms * 1e-3) / 1e9
+        roof["hbm_frac"] = roof["traffic"] / (res_ms * 1e-3) / PEAK_HBM
+    return {"t_ms": t_ms, "wall_s": wall, "res_ms": res_ms, "mixed": mixed, "roofline": roof, "run": run}
+
+
+def describe(w):
+    g, s, m = w.grid, w.scheme, w.monitor
+    cfg = {"workload": w.name, "system": "%dD %s, Gamma %.4g" % (g.dim, "RMHD" if s.phys else "RHD", s.gamma),
+           "grid": list(g.shape[::-1]), "nodes": g.nnodes,
+           "scheme": "%s: %d-th order EC flux%s, SSP-RK3, CFL %.2g" % (
+               "ES" if s.dissipation else "EC", 2 * s.order_p,
+               " + WENO%d dissipation" % (2 * s.order_p - 1) if s.dissipation else "", s.cfl),
+           "boundary": "periodic" if g.bc[0] == 0 else "outflow", "precision": "FP64"}
+    if m.enabled:
+        cfg["mesh"] = "adaptive: monitor form %d, alpha %g on %s, %d filter passes, %d Jacobi sweeps" % (
+            m.form, m.alpha, "ln rho" if m.sigma == 1 else "rho", m.filter_passes, m.sweeps)
+    else:
+        cfg["mesh"] = "static"
+    return cfg
+
+
+def other_workload(args):
+    """Time one workload alone: RK3 steps and es_residual, FP64 and FP32-mixed."""
+    from paper_2107_12027_amd import workloads as wl
+    make = {"sine": lambda: wl.advected_sine(n=args.n or 64),
+            "quadrant": lambda: wl.quadrant_riemann(n=args.n or 400, seed=2 if args.seed is None else args.seed),
+            "rotor": lambda: wl.rmhd_rotor(n=args.n or 512),
+            "fourier": lambda: wl.rmhd_fourier(n=args.n or 256, seed=0)}[args.workload]
+    w = make()
+    r = fp64_and_mixed(w, args.steps, args.warmup, args.residual_reps)
+    nodes = w.grid.nnodes
+    line = {"metric": METRIC, "value": nodes * args.steps / (r["t_ms"] * 1e-3), "unit": "cell-updates/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["t_ms"] / args.steps,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-            "data": "synthetic",
-            "config": {"workload": w.name, "system": ("RMHD" if w.scheme.phys else "RHD") + " %dD" % w.grid.dim,
-                       "grid": list(w.grid.shape[::-1]), "nodes": nodes,
-                       "mesh": "adaptive" if w.monitor.enabled else "static", "precision": "FP64"},
-            "roofline": roof, "cpu_baseline": None, "mixed": mixed}
+            "data": "synthetic", "config": describe(w), "roofline": r["roofline"], "cpu_baseline": None,
+            "mixed": r["mixed"]}
+    print(json.dumps(line))
+
+
+def c1_sine(n=64):
+    """Advected sine (64^2, adaptive mesh) run to t = 0.2, the last step shortened
+    to end there; L1 error of rho against the exact advected profile
+    rho = 1 + 0.2 sin 2pi(x + y - 0.4 t) at the final mesh nodes."""
+    import numpy as np
+    import torch
+    from paper_2107_12027_amd import workloads as wl
+    w = wl.advected_sine(n=n)
+    run = Run(w, 0)
+    ctx = run.ctx
+    t_sum = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    steps, t = 0, 0.0
+    while True:
+        # steps of the scheme's own dt while at least 2 more fit, checked every 8 steps
+        for _ in range(8):
+            run.step()
+            t_sum.add_(run.dt)
+        steps += 8
+        t = float(t_sum.item())
+        if t + 16 * float(run.dt.item()) >= w.t_end:
+            break
+    while True:
+        ctx.cfl(*_cfl_inputs(run), run.dt)
+        dt = float(run.dt.item())
+        last = t + dt >= w.t_end
+        fixed = torch.tensor([w.t_end - t if last else dt], dtype=torch.float64, device="cuda")
+        run.ctx.rk3_step(run.U, run.J, run.x, run.xdot, run.dt, fixed)
+        t += float(fixed.item())
+        steps += 1
+        if last:
+            break
+    e1.record(stream)
+    torch.cuda.synchronize()
+    status = ctx.status()[0]
+    ctx.con2prim(run.U, run.J, run.prim)
+    x = run.x.cpu().numpy()
+    rho = run.prim[0, 3:-3, 3:-3].cpu().numpy()
+    exact = 1.0 + 0.2 * np.sin(2 * np.pi * (x[0] + x[1] - 0.4 * t))
+    return {"workload": w.name, "t": t, "steps": steps, "status": int(status),
+            "ms_per_step": e0.elapsed_time(e1) / steps,
+            "value": w.grid.nnodes * steps / (e0.elapsed_time(e1) * 1e-3), "unit": "cell-updates/s",
+            "l1_err_rho_vs_exact": float(np.mean(np.abs(rho - exact))),
+            "linf_err_rho_vs_exact": float(np.max(np.abs(rho - exact))),
+            "note": "FP64; the last step is shortened to end at t = 0.2 (its dt from es_cfl)"}
+
+
+def c2_quadrant_seeds(n=400, steps=300, seeds=(0, 1, 2, 3), chunk=10):
+    """The quadrant Riemann problem for seeds 0-3 (400^2, adaptive, 300 steps):
+    per seed the outcome (con2prim status, checked every ``chunk`` steps) and the
+    GPU time per step."""
+    import torch
+    from paper_2107_12027_amd import workloads as wl
+    out = []
+    for seed in seeds:
+        w = wl.quadrant_riemann(n=n, seed=seed, steps=steps)
+        run = Run(w, 0)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        done, status, first = 0, 0, -1
+        while done < steps:
+            k = min(chunk, steps - done)
+            for _ in range(k):
+                run.step()
+            status, _, first = run.ctx.status()
+            if status != 0:
+                break
+            done += k
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rec = {"seed": seed, "status": int(status), "steps_completed": done,
+               "ms_per_step": e0.elapsed_time(e1) / max(done + (chunk if status else 0), 1)}
+        if status == 0:
+            rec["value"] = w.grid.nnodes * done / (e0.elapsed_time(e1) * 1e-3)
+        else:
+            rec["failed_between_steps"] = [done + 1, done + chunk]
+            rec["first_failed_node"] = int(first)
+        out.append(rec)
+        del run
+    return {"workload": "rhd2d_quadrant_riemann_%d" % n, "steps": steps, "seeds": out,
+            "note": "FP64, status checked every %d steps (es_ctx_status synchronises); 0 = ok, "
+                    "2 = inadmissible state reached con2prim" % chunk}
+
+
+def c3_rotor(n=512, steps=200, warmup=2, reps=10):
+    """RMHD rotor 512^2, 200 steps, FP64 and FP32-mixed."""
+    from paper_2107_12027_amd import workloads as wl
+    w = wl.rmhd_rotor(n=n, steps=steps)
+    r = fp64_and_mixed(w, steps, warmup, reps)
+    return {"workload": w.name, "steps": steps, "value": w.grid.nnodes * steps / (r["t_ms"] * 1e-3),
+            "unit": "cell-updates/s", "ms_per_step": r["t_ms"] / steps, "es_residual_ms": r["res_ms"],
+            "mixed": r["mixed"], "config": describe(w)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2107_12027_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    if args.paper_case in ("vortex2d", "vortex3d"):
+        return vortex_study(args, 2 if args.paper_case == "vortex2d" else 3)
+    if args.paper_case is not None:
+        return paper_case(args)
+    if args.workload != "blast3d":
+        return other_workload(args)
+
+    n = args.n or 128
+    seed = 0 if args.seed is None else args.seed
+    w = wl.blast3d(n=n, seed=seed)
+    print("bench.py: %s, %d warm-up + %d timed steps, FP64 and mixed" % (w.name, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    r = fp64_and_mixed(w, args.steps, args.warmup, args.residual_reps)
+    t_ms = r["t_ms"]
+    nodes = w.grid.nnodes
+    fwd_ms = t_ms / args.steps
+    del r["run"]
+    torch.cuda.empty_cache()
+    print("bench.py: headline done (%.3f ms per step)" % fwd_ms, file=sys.stderr, flush=True)
+    adjoint = adjoint_timing(w, args.adjoint_steps, fwd_ms)
+    torch.cuda.empty_cache()
+
+    extras = {}
+    if not args.no_extras:
+        for name, fn in (("c1_advected_sine", c1_sine), ("c2_quadrant_seeds", c2_quadrant_seeds),
+                         ("c3_rotor", c3_rotor)):
+            extras[name] = fn()
+            torch.cuda.empty_cache()
+            print("bench.py: %s done" % name, file=sys.stderr, flush=True)
+        if args.adjoint_steps > 0 and not args.no_fourier_gradient:
+            extras["c5_adjoint"] = fourier_gradient(rmhd=True)
+            print("bench.py: c5_adjoint done", file=sys.stderr, flush=True)
+
+    if args.copy_calibration_mib > 0:
+        m = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(m, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    cpu = None
+    mixed = r["mixed"]
+    if not args.no_cpu_baseline:
+        # the oracle on a sample of the same recipe, and the GPU forms' first step on it
+        ws = wl.blast3d(n=args.cpu_n, seed=seed)
+        one = {}
+        for mx in (0, 1):
+            rs_ = Run(ws, mx)
+            rs_.step()
+            torch.cuda.synchronize()
+            one[mx] = rs_.U.cpu().numpy() if rs_.ctx.status()[0] == 0 else None
+            del rs_
+        cpu, Uo = cpu_baseline(ws)
+        if Uo is not None and one[0] is not None and one[1] is not None:
+            mixed["sample_l1_rel_err_vs_oracle"] = l1_rel_diff(one[1], Uo)
+            mixed["sample_fp64_l1_rel_err_vs_oracle"] = l1_rel_diff(one[0], Uo)
+            mixed["sample"] = "one step of %s from its initial data, GPU forms vs the oracle" % ws.name
+
+    cfg = describe(w)
+    cfg["seed"] = seed
+    line = {
+        "metric": METRIC, "value": nodes * args.steps / (t_ms * 1e-3), "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": fwd_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": cfg,
+        "timed_wall_s": r["wall_s"],
+        "roofline": r["roofline"],
+        "cpu_baseline": cpu,
+        "mixed": mixed,
+        "adjoint": adjoint,
+    }
+    line.update(extras)
     print(json.dumps(line))
 
 
@@ -482,104 +739,6 @@ def vortex_study(args, dim):
             ok = "l1_rho" in a and "l1_rho" in b
             rates.append(math.log(a["l1_rho"] / b["l1_rho"]) / math.log(b["n"] / a["n"]) if ok else None)
         line[name] = {"runs": runs, "rates_l1_rho": rates}
-    print(json.dumps(line))
-
-
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU (no multi-GPU path); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_2107_12027_amd import workloads as wl
-
-    torch.cuda.set_device(0)
-    if args.paper_case in ("vortex2d", "vortex3d"):
-        return vortex_study(args, 2 if args.paper_case == "vortex2d" else 3)
-    if args.paper_case is not None:
-        return paper_case(args)
-    if args.workload != "quadrant":
-        return other_workload(args)
-    w = wl.quadrant_riemann(n=args.n, seed=args.seed)
-    g = w.grid
-
-    # accuracy sample: one step from the initial data on both forms (compared with
-    # the oracle's step below, outside every timed region)
-    one_step = {}
-    for mixed in (0, 1):
-        r = Run(w, mixed)
-        r.step()
-        torch.cuda.synchronize()
-        if r.ctx.status()[0] != 0:
-            print("bench.py: con2prim failure in the first step", file=sys.stderr)
-            sys.exit(3)
-        one_step[mixed] = r.U.cpu().numpy()
-        del r
-
-    run = Run(w, 0)
-    t_ms = run.timed(args.steps, args.warmup)
-    res_ms = run.residual_ms(args.residual_reps)
-    mrun = Run(w, 1)
-    t_mixed_ms = mrun.timed(args.steps, args.warmup)
-    res_mixed_ms = mrun.residual_ms(args.residual_reps)
-    adjoint = adjoint_timing(w, args.adjoint_steps, t_ms / args.steps)
-    study = args.adjoint_steps > 0 and not args.no_fourier_gradient
-    adjoint_fourier = fourier_gradient(rmhd=True) if study else None
-    adjoint_fourier_rhd = fourier_gradient(rmhd=False) if study else None
-
-    if args.copy_calibration_mib > 0:
-        n = args.copy_calibration_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    nodes = g.nnodes
-    value = nodes * args.steps / (t_ms * 1e-3)
-    flops = RESIDUAL_FLOPS_PER_NODE_2D_RHD
-    traffic = RESIDUAL_TRAFFIC_BYTES_QUADRANT_400 if (args.n, args.seed) == (400, 2) else None
-    roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
-            "frac": None, "traffic": traffic, "traffic_unit": "HBM bytes per es_residual call",
-            "kernel": "es_residual (k_residual_rhd, both sweeps in one launch, + k_sum_dirs)",
-            "avg_launch_ms": res_ms}
-    if flops is not None:
-        ach = flops * nodes / (res_ms * 1e-3)
-        roof["achieved"] = ach / 1e12
-        roof["frac"] = ach / PEAK_FP64_VECTOR
-    if traffic is not None:
-        # the HBM side of the same call: counter bytes over the measured duration
-        roof["hbm_achieved_gbs"] = traffic / (res_ms * 1e-3) / 1e9
-        roof["hbm_frac"] = traffic / (res_ms * 1e-3) / PEAK_HBM
-    cpu = None
-    mixed = {"value": nodes * args.steps / (t_mixed_ms * 1e-3), "unit": "cell-updates/s",
-             "ms_per_step": t_mixed_ms / args.steps, "dtype": "f32 pair/dissipation, f64 elsewhere",
-             "es_residual_ms": res_mixed_ms, "speedup_vs_fp64": t_ms / t_mixed_ms,
-             "l1_rel_err_vs_oracle": None, "fp64_l1_rel_err_vs_oracle": None,
-             "err_sample": "one SSP-RK3 step of the %dx%d workload from its initial state, "
-                           "relative L1 per conserved component" % (args.n, args.n)}
-    if not args.no_cpu_baseline:
-        cpu, Uo = cpu_baseline(args.n, args.seed)
-        if Uo is not None:
-            mixed["l1_rel_err_vs_oracle"] = l1_rel(one_step[1], Uo)
-            mixed["fp64_l1_rel_err_vs_oracle"] = l1_rel(one_step[0], Uo)
-    line = {
-        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_ms / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": w.name, "system": "2D RHD, Gamma 5/3", "grid": [args.n, args.n],
-                   "nodes": nodes, "scheme": "ES: 6th-order EC flux + WENO5 dissipation, SSP-RK3, CFL 0.4",
-                   "mesh": "adaptive, monitor alpha 1200 on ln rho, 3 filter passes, 10 Jacobi sweeps",
-                   "boundary": "outflow", "precision": "FP64"},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "mixed": mixed,
-        "adjoint": adjoint,
-        "adjoint_fourier": adjoint_fourier,
-        "adjoint_fourier_rhd": adjoint_fourier_rhd,
-    }
     print(json.dumps(line))
 
 

@@ -30,9 +30,10 @@
  *   J dxi_k/dt, comp k*(d+1)+1+j is J dxi_k/dx_j (Section 3.3).
  * Errors.  Every entry point returns es_status; no C++ exception crosses the
  *   ABI.  Invalid arguments give ES_EINVAL before anything is enqueued.  A HIP
- *   launch error gives ES_EHIP.  Conservative-to-primitive failures are
- *   recorded on the device (count and first failing interior node, the
- *   primitive output is NaN there) and reported by es_ctx_status().
+ *   launch error gives ES_EHIP.  Conservative-to-primitive failures, and
+ *   nodes whose Jacobian is not positive, are recorded on the device (count
+ *   and first failing interior node, the primitive output is NaN there) and
+ *   reported by es_ctx_status().
  */
 #ifndef ES_H
 #define ES_H
@@ -49,7 +50,7 @@ typedef enum {
     ES_EINVAL = 1,        /* bad argument (sizes, null pointer, unsupported option) */
     ES_EADMISSIBLE = 2,   /* a state outside the admissible set reached con2prim */
     ES_ENOCONV = 3,       /* con2prim iteration did not converge */
-    ES_EMESH = 4,         /* non-positive Jacobian */
+    ES_EMESH = 4,         /* non-positive Jacobian (tangled mesh), reported by es_ctx_status */
     ES_EHIP = 5,          /* HIP runtime error */
     ES_EUNSUPPORTED = 6   /* valid option not built into this library */
 } es_status;
@@ -225,6 +226,25 @@ es_status es_rk3_step_vjp(es_ctx* ctx, const double* ckpt, const double* lamU, c
 es_status es_residual_vjp(es_ctx* ctx, const double* Ucurv, const double* J, const double* met,
                           const double* lamU, double* gU, double* gJ, hipStream_t stream);
 
+/* Vector-Jacobian product of the conservative-to-primitive recovery at the
+ * interior nodes (the implicit-function rule, as inside the adjoint): with
+ * P(U) the primitive state (rho, u, p[, B]) that con2prim recovers from
+ * U = Ucurv / J, gU = (dP/dUcurv)^T gprim and gJ = (dP/dJ)^T gprim, i.e.
+ * y = (dU/dP)^{-T} gprim at the converged state, gU = y / J, gJ = -(y . Ucurv) / J^2.
+ * Ucurv, gU: interior m comps; J, gJ: interior; gprim: interior, m comps in the
+ * primitive slots (the layout es_prim2con reads).  Runs es_con2prim into the
+ * context's primitive workspace first; failures are recorded as there
+ * (es_ctx_status).  Any scheme of the context (FP64 or mixed, any p). */
+es_status es_con2prim_vjp(es_ctx* ctx, const double* Ucurv, const double* J, const double* gprim,
+                          double* gU, double* gJ, hipStream_t stream);
+
+/* Vector-Jacobian product of es_prim2con, Ucurv = J U(prim) (eq. RMHDdiv2,
+ * eq. RMHDCurv): gprim = J (dU/dP)^T gUcurv and, if gJ is not NULL,
+ * gJ = U(prim) . gUcurv.  prim: interior, m comps (as es_prim2con); J: interior;
+ * gUcurv: interior m comps; gprim: interior m comps (output). */
+es_status es_prim2con_vjp(es_ctx* ctx, const double* prim, const double* J, const double* gUcurv,
+                          double* gprim, double* gJ, hipStream_t stream);
+
 /* Replay es_rk3_step and es_rk3_step_moving as a HIP graph (default 1) or
  * launch their kernels one by one (0).  In graph mode the step is captured on
  * the context's own stream the first time it is called with a given set of
@@ -243,9 +263,14 @@ es_status es_diagnostics(es_ctx* ctx, const double* prim, const double* Ucurv, c
                          const double* dUcurv, const double* dJ, double* out_dev,
                          hipStream_t stream);
 
-/* Synchronise the stream and report recorded con2prim failures since the last
- * call (then clear them): ES_OK, ES_EADMISSIBLE or ES_ENOCONV.  n_fail and
- * first_fail (interior node index) may be NULL. */
+/* Synchronise the stream and report the failures recorded by con2prim since the
+ * last call (then clear them): ES_EMESH if some node's Jacobian J was not
+ * positive (a tangled mesh: every con2prim of a step, i.e. of every stage
+ * state, checks the evolved J of eq. RMHDSemiJ_O2p_ES before recovering the
+ * state; the node's primitive output is NaN), else ES_EADMISSIBLE (a state
+ * outside the admissible set), else ES_ENOCONV, else ES_OK.  n_fail (all
+ * failing interior nodes) and first_fail (the smallest failing interior node
+ * index) may be NULL. */
 es_status es_ctx_status(es_ctx* ctx, hipStream_t stream, long long* n_fail, long long* first_fail);
 
 const char* es_status_string(es_status s);

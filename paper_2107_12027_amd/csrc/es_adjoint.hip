@@ -616,15 +616,47 @@ __device__ __forceinline__ void solve_transposed(double A[n][n], const double* b
     }
 }
 
-// Fold ghost cotangents onto the interior nodes they copy and pull back through
-// con2prim (implicit-function rule) and U = Ucurv / J:
-//   g_Ubar = (dUbar/dP)^{-T} g_P,  g_Ucurv = g_Ubar / J,  g_J = -(g_Ubar . Ucurv) / J^2.
+// dUbar/dP of the RHD map at one node, P = (rho, u, p): D = rho W,
+// m = (rho + c0 p) W u, E = (rho + c0 p) W^2 - p, c0 = Gamma/(Gamma-1), W^2 = 1 + |u|^2.
 template <int DIM>
+__device__ __forceinline__ void rhd_dU_dP(double G, double rho, const double* u, double p,
+                                          double A[DIM + 2][DIM + 2]) {
+    constexpr int NU = DIM, M = DIM + 2;
+    double uu = 0.0;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) uu += u[c] * u[c];
+    const double W = sqrt(1.0 + uu), iW = 1.0 / W;
+    const double c0 = G / (G - 1.0);
+    const double rh = rho + c0 * p;
+    A[0][0] = W;
+#pragma unroll
+    for (int l = 0; l < NU; ++l) A[0][1 + l] = rho * u[l] * iW;
+    A[0][M - 1] = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < NU; ++kk) {
+        A[1 + kk][0] = W * u[kk];
+#pragma unroll
+        for (int l = 0; l < NU; ++l) A[1 + kk][1 + l] = rh * (u[l] * u[kk] * iW + (l == kk ? W : 0.0));
+        A[1 + kk][M - 1] = c0 * W * u[kk];
+    }
+    A[M - 1][0] = W * W;
+#pragma unroll
+    for (int l = 0; l < NU; ++l) A[M - 1][1 + l] = 2.0 * rh * u[l];
+    A[M - 1][M - 1] = c0 * W * W - 1.0;
+}
+
+// Pull a primitive cotangent back through con2prim (implicit-function rule) and
+// U = Ucurv / J:
+//   g_Ubar = (dUbar/dP)^{-T} g_P,  g_Ucurv = g_Ubar / J,  g_J = -(g_Ubar . Ucurv) / J^2.
+// FOLD: g_P is the residual VJP's padded cotangent by direction (gsrc = gdir),
+// ghost cotangents folded onto the interior nodes they copy; otherwise g_P is an
+// interior field of m components (gsrc = the caller's cotangent).
+template <int DIM, bool FOLD>
 __global__ void __launch_bounds__(256) k_fold_con2prim_vjp(GridDev g, double G,
                                                            const double* __restrict__ prim,
                                                            const double* __restrict__ U,
                                                            const double* __restrict__ J,
-                                                           const double* __restrict__ gdir,
+                                                           const double* __restrict__ gsrc,
                                                            double* __restrict__ gU,
                                                            double* __restrict__ gJ) {
     constexpr int NU = DIM, M = DIM + 2;
@@ -633,12 +665,14 @@ __global__ void __launch_bounds__(256) k_fold_con2prim_vjp(GridDev g, double G,
     const long long P = g.pnodes, N = g.nodes;
     const long long slab = (long long)M * P;
     const long long pi0 = pidx(g, i, j, k);
+    const long long t = iidx(g, i, j, k);
     double gP[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) gP[c] = 0.0;
+    for (int c = 0; c < M; ++c) gP[c] = FOLD ? 0.0 : gsrc[c * N + t];
     const int ijk[3] = {i, j, k};
+    const double* gdir = gsrc;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
+    for (int d = 0; d < (FOLD ? DIM : 0); ++d) {
         const double* gd = gdir + d * slab;
         const long long str = d == 0 ? 1 : (d == 1 ? (long long)g.P[0] : (long long)g.P[0] * g.P[1]);
         const int n = g.n[d], me = ijk[d];
@@ -655,34 +689,14 @@ __global__ void __launch_bounds__(256) k_fold_con2prim_vjp(GridDev g, double G,
             }
         }
     }
-    // dUbar/dP at the node, P = (rho, u, p): D = rho W, m = (rho + c0 p) W u,
-    // E = (rho + c0 p) W^2 - p
     const double rho = prim[pi0], p = prim[(M - 1) * P + pi0];
-    double u[NU], uu = 0.0;
+    double u[NU];
 #pragma unroll
-    for (int c = 0; c < NU; ++c) { u[c] = prim[(1 + c) * P + pi0]; uu += u[c] * u[c]; }
-    const double W = sqrt(1.0 + uu), iW = 1.0 / W;
-    const double c0 = G / (G - 1.0);
-    const double rh = rho + c0 * p;
+    for (int c = 0; c < NU; ++c) u[c] = prim[(1 + c) * P + pi0];
     double A[M][M];
-    A[0][0] = W;
-#pragma unroll
-    for (int l = 0; l < NU; ++l) A[0][1 + l] = rho * u[l] * iW;
-    A[0][M - 1] = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < NU; ++kk) {
-        A[1 + kk][0] = W * u[kk];
-#pragma unroll
-        for (int l = 0; l < NU; ++l) A[1 + kk][1 + l] = rh * (u[l] * u[kk] * iW + (l == kk ? W : 0.0));
-        A[1 + kk][M - 1] = c0 * W * u[kk];
-    }
-    A[M - 1][0] = W * W;
-#pragma unroll
-    for (int l = 0; l < NU; ++l) A[M - 1][1 + l] = 2.0 * rh * u[l];
-    A[M - 1][M - 1] = c0 * W * W - 1.0;
+    rhd_dU_dP<DIM>(G, rho, u, p, A);
     double y[M];
     solve_transposed<M>(A, gP, y);
-    const long long t = iidx(g, i, j, k);
     const double Jv = J[t], iJ = 1.0 / Jv;
     double gj = 0.0;
 #pragma unroll
@@ -691,6 +705,47 @@ __global__ void __launch_bounds__(256) k_fold_con2prim_vjp(GridDev g, double G,
         gj -= y[c] * U[c * N + t];
     }
     gJ[t] = gj * iJ * iJ;
+}
+
+// VJP of Ucurv = J U(P) at the interior nodes: g_P = J (dU/dP)^T g_Ucurv,
+// g_J = U(P) . g_Ucurv (gJ may be null).  prim: interior, m comps (rho, u, p).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_prim2con_vjp_rhd(GridDev g, double G,
+                                                          const double* __restrict__ prim,
+                                                          const double* __restrict__ J,
+                                                          const double* __restrict__ gUc,
+                                                          double* __restrict__ gP,
+                                                          double* __restrict__ gJ) {
+    constexpr int NU = DIM, M = DIM + 2;
+    const long long t = gtid();
+    if (t >= g.nodes) return;
+    const long long N = g.nodes;
+    const double rho = prim[t], p = prim[(M - 1) * N + t];
+    double u[NU], uu = 0.0;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) { u[c] = prim[(1 + c) * N + t]; uu += u[c] * u[c]; }
+    double A[M][M];
+    rhd_dU_dP<DIM>(G, rho, u, p, A);
+    double gu[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) gu[r] = gUc[r * N + t];
+    const double Jv = J[t];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc += A[r][c] * gu[r];
+        gP[c * N + t] = Jv * acc;
+    }
+    if (gJ != nullptr) {
+        // U(P): D = rho W, m = rho h W u, E = rho h W^2 - p
+        const double W = sqrt(1.0 + uu);
+        const double rh = rho + G / (G - 1.0) * p;
+        double acc = rho * W * gu[0] + (rh * W * W - p) * gu[M - 1];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) acc += rh * W * u[c] * gu[1 + c];
+        gJ[t] = acc;
+    }
 }
 
 // RK3 reverse sweep, elementwise over U (nU values) and J (nJ values).
@@ -774,8 +829,29 @@ hipError_t launch_state_residual_vjp(const es_ctx* c, const double* U, const dou
     else residual_vjp_all<3>(c, c->prim, met, lam, c->gdir, s);
     const GridDev& g = c->g;
     const dim3 gr = box_grid(g.n[0], g.n[1], g.n[2]);
-    if (g.dim == 2) k_fold_con2prim_vjp<2><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
-    else k_fold_con2prim_vjp<3><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
+    if (g.dim == 2) k_fold_con2prim_vjp<2, true><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
+    else k_fold_con2prim_vjp<3, true><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
+    return hipGetLastError();
+}
+
+hipError_t launch_con2prim_vjp(const es_ctx* c, const double* U, const double* J, const double* gprim,
+                               double* gU, double* gJ, hipStream_t s) {
+    hipError_t e = launch_con2prim(c, U, J, c->prim, 0, s);
+    if (e != hipSuccess) return e;
+    if (c->scheme.phys == ES_RMHD) return launch_con2prim_vjp_rmhd(c, U, J, gprim, gU, gJ, s);
+    const GridDev& g = c->g;
+    const dim3 gr = box_grid(g.n[0], g.n[1], g.n[2]);
+    if (g.dim == 2) k_fold_con2prim_vjp<2, false><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, gprim, gU, gJ);
+    else k_fold_con2prim_vjp<3, false><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, gprim, gU, gJ);
+    return hipGetLastError();
+}
+
+hipError_t launch_prim2con_vjp(const es_ctx* c, const double* prim, const double* J, const double* gUc,
+                               double* gprim, double* gJ, hipStream_t s) {
+    if (c->scheme.phys == ES_RMHD) return launch_prim2con_vjp_rmhd(c, prim, J, gUc, gprim, gJ, s);
+    const GridDev& g = c->g;
+    if (g.dim == 2) k_prim2con_vjp_rhd<2><<<grid_for(g.nodes), TPB, 0, s>>>(g, c->scheme.gamma, prim, J, gUc, gprim, gJ);
+    else k_prim2con_vjp_rhd<3><<<grid_for(g.nodes), TPB, 0, s>>>(g, c->scheme.gamma, prim, J, gUc, gprim, gJ);
     return hipGetLastError();
 }
 

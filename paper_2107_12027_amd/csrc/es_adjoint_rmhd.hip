@@ -562,15 +562,17 @@ __device__ __forceinline__ void solve_transposed8(const double A[8][8], const do
     }
 }
 
-// Fold ghost cotangents onto the interior nodes they copy and pull back through
-// con2prim by the implicit-function rule, (dUbar/dP)^T y = g_P with dUbar/dP by
-// dual numbers (U(P) of eq. RMHDdiv2), then g_Ucurv = y / J, g_J = -(y . Ucurv) / J^2.
-template <int DIM>
+// Pull a primitive cotangent back through con2prim by the implicit-function rule,
+// (dUbar/dP)^T y = g_P with dUbar/dP by dual numbers (U(P) of eq. RMHDdiv2), then
+// g_Ucurv = y / J, g_J = -(y . Ucurv) / J^2.  FOLD: g_P is the residual VJP's padded
+// cotangent by direction, ghost cotangents folded onto the interior nodes they
+// copy; otherwise an interior field of 8 components.
+template <int DIM, bool FOLD>
 __global__ void __launch_bounds__(256) k_fold_con2prim_vjp_rmhd(GridDev g, double G,
                                                                 const double* __restrict__ prim,
                                                                 const double* __restrict__ U,
                                                                 const double* __restrict__ J,
-                                                                const double* __restrict__ gdir,
+                                                                const double* __restrict__ gsrc,
                                                                 double* __restrict__ gU,
                                                                 double* __restrict__ gJ) {
     int i, j, k;
@@ -578,12 +580,14 @@ __global__ void __launch_bounds__(256) k_fold_con2prim_vjp_rmhd(GridDev g, doubl
     const long long P = g.pnodes, N = g.nodes;
     const long long slab = 8LL * P;
     const long long pi0 = pidx(g, i, j, k);
+    const long long t = iidx(g, i, j, k);
     double gP[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) gP[c] = 0.0;
+    for (int c = 0; c < 8; ++c) gP[c] = FOLD ? 0.0 : gsrc[c * N + t];
     const int ijk[3] = {i, j, k};
+    const double* gdir = gsrc;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
+    for (int d = 0; d < (FOLD ? DIM : 0); ++d) {
         const double* gd = gdir + d * slab;
         const long long str = d == 0 ? 1 : (d == 1 ? (long long)g.P[0] : (long long)g.P[0] * g.P[1]);
         const int n = g.n[d], me = ijk[d];
@@ -613,7 +617,6 @@ __global__ void __launch_bounds__(256) k_fold_con2prim_vjp_rmhd(GridDev g, doubl
         for (int c = 0; c < 8; ++c) A[r][c] = Ud[r].d[c];
     double y[8];
     solve_transposed8(A, gP, y);
-    const long long t = iidx(g, i, j, k);
     const double iJ = 1.0 / J[t];
     double gj = 0.0;
 #pragma unroll
@@ -622,6 +625,43 @@ __global__ void __launch_bounds__(256) k_fold_con2prim_vjp_rmhd(GridDev g, doubl
         gj -= y[c] * U[c * N + t];
     }
     gJ[t] = gj * iJ * iJ;
+}
+
+// VJP of Ucurv = J U(P) at the interior nodes: g_P = J (dU/dP)^T g_Ucurv with dU/dP
+// by dual numbers, g_J = U(P) . g_Ucurv (gJ may be null).  prim: interior, 8 comps.
+__global__ void __launch_bounds__(256) k_prim2con_vjp_rmhd(GridDev g, double G,
+                                                           const double* __restrict__ prim,
+                                                           const double* __restrict__ J,
+                                                           const double* __restrict__ gUc,
+                                                           double* __restrict__ gP,
+                                                           double* __restrict__ gJ) {
+    const long long t = gtid();
+    if (t >= g.nodes) return;
+    const long long N = g.nodes;
+    using D = Dual<8>;
+    D Pd[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) Pd[c] = D::seed(prim[c * N + t], c);
+    const StateRMHD<D> st = rmhd_state<D>(G, Pd);
+    D Ud[8];
+    rmhd_cons<D>(st, Ud);
+    double gu[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) gu[r] = gUc[r * N + t];
+    const double Jv = J[t];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc += Ud[r].d[c] * gu[r];
+        gP[c * N + t] = Jv * acc;
+    }
+    if (gJ != nullptr) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc += Ud[r].v * gu[r];
+        gJ[t] = acc;
+    }
 }
 
 FaceEigPlan face_eig_plan(const GridDev& g) {
@@ -693,9 +733,27 @@ hipError_t launch_residual_fold_vjp_rmhd(const es_ctx* c, const double* U, const
     else residual_vjp_all_rmhd<3>(c, c->prim, met, lam, c->gdir, s);
     const dim3 gr = box_grid(g.n[0], g.n[1], g.n[2]);
     if (g.dim == 2)
-        k_fold_con2prim_vjp_rmhd<2><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
+        k_fold_con2prim_vjp_rmhd<2, true><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
     else
-        k_fold_con2prim_vjp_rmhd<3><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
+        k_fold_con2prim_vjp_rmhd<3, true><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, c->gdir, gU, gJ);
+    return hipGetLastError();
+}
+
+hipError_t launch_con2prim_vjp_rmhd(const es_ctx* c, const double* U, const double* J, const double* gprim,
+                                    double* gU, double* gJ, hipStream_t s) {
+    const GridDev& g = c->g;
+    const dim3 gr = box_grid(g.n[0], g.n[1], g.n[2]);
+    if (g.dim == 2)
+        k_fold_con2prim_vjp_rmhd<2, false><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, gprim, gU, gJ);
+    else
+        k_fold_con2prim_vjp_rmhd<3, false><<<gr, box_block(), 0, s>>>(g, c->scheme.gamma, c->prim, U, J, gprim, gU, gJ);
+    return hipGetLastError();
+}
+
+hipError_t launch_prim2con_vjp_rmhd(const es_ctx* c, const double* prim, const double* J, const double* gUc,
+                                    double* gprim, double* gJ, hipStream_t s) {
+    const GridDev& g = c->g;
+    k_prim2con_vjp_rmhd<<<grid_for(g.nodes), TPB, 0, s>>>(g, c->scheme.gamma, prim, J, gUc, gprim, gJ);
     return hipGetLastError();
 }
 

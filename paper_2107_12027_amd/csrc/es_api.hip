@@ -41,6 +41,34 @@ hipError_t alloc(T** p, size_t n) {
     return hipMalloc((void**)p, (n > 0 ? n : 1) * sizeof(T));
 }
 
+// The host part of a context: options and the device grid description (no
+// device memory).
+void describe(es_ctx* c, const es_grid* grid, const es_scheme* scheme, const es_monitor* monitor) {
+    memset(c, 0, sizeof(*c));
+    c->grid = *grid;
+    c->scheme = *scheme;
+    if (monitor != nullptr) c->monitor = *monitor;
+    GridDev& g = c->g;
+    g.dim = grid->dim;
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = grid->n[k];
+        g.bc[k] = grid->bc[k];
+        g.dxi[k] = grid->dxi[k];
+        g.period[k] = grid->period[k];
+        g.P[k] = (k < grid->dim) ? grid->n[k] + 2 * es::NG : 1;
+    }
+    g.g2 = grid->dim == 3 ? es::NG : 0;
+    for (int k = 0; k < 3; ++k) g.E[k] = (k < grid->dim) ? grid->n[k] + 4 * es::NG : 1;
+    g.g6 = grid->dim == 3 ? 2 * es::NG : 0;
+    g.nodes = (long long)g.n[0] * g.n[1] * g.n[2];
+    g.pnodes = (long long)g.P[0] * g.P[1] * g.P[2];
+    g.enodes = (long long)g.E[0] * g.E[1] * g.E[2];
+    g.p = scheme->order_p;
+    c->m = scheme->phys == ES_RMHD ? 8 : grid->dim + 2;
+    c->nprim = c->m + 2;
+    c->nmet = grid->dim * (grid->dim + 1);
+}
+
 }  // namespace
 
 extern "C" {
@@ -82,29 +110,8 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
 
     es_ctx* c = new (std::nothrow) es_ctx();
     if (c == nullptr) return ES_EHIP;
-    memset(c, 0, sizeof(*c));
-    c->grid = *grid;
-    c->scheme = *scheme;
-    c->monitor = *monitor;
-    GridDev& g = c->g;
-    g.dim = grid->dim;
-    for (int k = 0; k < 3; ++k) {
-        g.n[k] = grid->n[k];
-        g.bc[k] = grid->bc[k];
-        g.dxi[k] = grid->dxi[k];
-        g.period[k] = grid->period[k];
-        g.P[k] = (k < grid->dim) ? grid->n[k] + 2 * es::NG : 1;
-    }
-    g.g2 = grid->dim == 3 ? es::NG : 0;
-    for (int k = 0; k < 3; ++k) g.E[k] = (k < grid->dim) ? grid->n[k] + 4 * es::NG : 1;
-    g.g6 = grid->dim == 3 ? 2 * es::NG : 0;
-    g.nodes = (long long)g.n[0] * g.n[1] * g.n[2];
-    g.pnodes = (long long)g.P[0] * g.P[1] * g.P[2];
-    g.enodes = (long long)g.E[0] * g.E[1] * g.E[2];
-    g.p = scheme->order_p;
-    c->m = scheme->phys == ES_RMHD ? 8 : grid->dim + 2;
-    c->nprim = c->m + 2;
-    c->nmet = grid->dim * (grid->dim + 1);
+    describe(c, grid, scheme, monitor);
+    const GridDev& g = c->g;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return ES_EHIP; }
     c->red_blocks = es::reduction_blocks(g);
     const size_t N = (size_t)g.nodes, P = (size_t)g.pnodes, d = (size_t)grid->dim;
@@ -131,6 +138,7 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     if (e == hipSuccess) e = alloc(&c->fail, (size_t)4);
     if (e == hipSuccess) {
         (void)es::launch_fill_u64(c->fail, 0ull, 2, nullptr);
+        (void)es::launch_fill_u64(c->fail + 3, 0ull, 1, nullptr);
         e = es::launch_fill_u64(c->fail + 2, ULLONG_MAX, 1, nullptr);
     }
     // the primitive workspace seeds the pressure iteration of the next step: start
@@ -379,6 +387,20 @@ es_status es_rk3_step_vjp(es_ctx* c, const double* ckpt, const double* lamU, con
     return hip_status(es::launch_rk3_vjp(c, ckpt, lamU, lamJ, gU, gJ, s));
 }
 
+es_status es_con2prim_vjp(es_ctx* c, const double* U, const double* J, const double* gprim, double* gU,
+                          double* gJ, hipStream_t s) {
+    if (c == nullptr || U == nullptr || J == nullptr || gprim == nullptr || gU == nullptr || gJ == nullptr)
+        return ES_EINVAL;
+    return hip_status(es::launch_con2prim_vjp(c, U, J, gprim, gU, gJ, s));
+}
+
+es_status es_prim2con_vjp(es_ctx* c, const double* prim, const double* J, const double* gU, double* gprim,
+                          double* gJ, hipStream_t s) {
+    if (c == nullptr || prim == nullptr || J == nullptr || gU == nullptr || gprim == nullptr)
+        return ES_EINVAL;
+    return hip_status(es::launch_prim2con_vjp(c, prim, J, gU, gprim, gJ, s));
+}
+
 es_status es_set_graph(es_ctx* c, int enable) {
     if (c == nullptr || (enable != 0 && enable != 1)) return ES_EINVAL;
     c->use_graph = enable;
@@ -396,13 +418,15 @@ es_status es_diagnostics(es_ctx* c, const double* prim, const double* U, const d
 es_status es_ctx_status(es_ctx* c, hipStream_t s, long long* n_fail, long long* first_fail) {
     if (c == nullptr) return ES_EINVAL;
     if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
-    unsigned long long h[3];
+    unsigned long long h[4];
     if (hipMemcpy(h, c->fail, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return ES_EHIP;
-    if (n_fail) *n_fail = (long long)(h[0] + h[1]);
+    if (n_fail) *n_fail = (long long)(h[0] + h[1] + h[3]);
     if (first_fail) *first_fail = h[2] == ULLONG_MAX ? -1 : (long long)h[2];
     (void)es::launch_fill_u64(c->fail, 0ull, 2, s);
     (void)es::launch_fill_u64(c->fail + 2, ULLONG_MAX, 1, s);
+    (void)es::launch_fill_u64(c->fail + 3, 0ull, 1, s);
     if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
+    if (h[3] > 0) return ES_EMESH;
     if (h[0] > 0) return ES_EADMISSIBLE;
     if (h[1] > 0) return ES_ENOCONV;
     return ES_OK;

@@ -134,6 +134,17 @@ __device__ __forceinline__ double mesh_value(const GridDev& g, const double* __r
     return v;
 }
 
+// Failure record of the conservative-to-primitive recovery (device array of 4
+// unsigned 64-bit counters): [0] inadmissible states, [1] iterations that did not
+// converge, [2] smallest failing interior node index, [3] nodes whose evolved
+// Jacobian is not positive (a tangled mesh).  Codes: 1 inadmissible, 2 no
+// convergence, FAIL_MESH non-positive Jacobian.
+constexpr int FAIL_MESH = 3;
+__device__ __forceinline__ void record_failure(unsigned long long* fail, int st, long long node) {
+    atomicAdd(&fail[st == 1 ? 0 : (st == FAIL_MESH ? 3 : 1)], 1ull);
+    atomicMin(&fail[2], (unsigned long long)node);
+}
+
 // Exact max/min reductions of non-negative doubles: order independent.
 __device__ __forceinline__ double wave_max(double v) {
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));

@@ -166,6 +166,17 @@ hipError_t launch_state_residual_vjp(const es_ctx* c, const double* U, const dou
 // VJP of one RK3 step with the mesh trajectory and the time step held fixed
 hipError_t launch_rk3_vjp(const es_ctx* c, const double* ckpt, const double* lamU_in,
                           const double* lamJ_in, double* gU_out, double* gJ_out, hipStream_t s);
+// con2prim VJP at the interior nodes (con2prim of (U, J) into c->prim first):
+// gU = (dU/dP)^{-T} gprim / J, gJ = -(that . Ucurv) / J^2
+hipError_t launch_con2prim_vjp(const es_ctx* c, const double* U, const double* J, const double* gprim,
+                               double* gU, double* gJ, hipStream_t s);
+hipError_t launch_con2prim_vjp_rmhd(const es_ctx* c, const double* U, const double* J, const double* gprim,
+                                    double* gU, double* gJ, hipStream_t s);
+// prim2con VJP: gprim = J (dU/dP)^T gUc, gJ = U(P) . gUc (gJ may be null)
+hipError_t launch_prim2con_vjp(const es_ctx* c, const double* prim, const double* J, const double* gUc,
+                               double* gprim, double* gJ, hipStream_t s);
+hipError_t launch_prim2con_vjp_rmhd(const es_ctx* c, const double* prim, const double* J, const double* gUc,
+                                    double* gprim, double* gJ, hipStream_t s);
 hipError_t launch_zero(double* p, long long n, hipStream_t s);
 
 }  // namespace es

@@ -99,15 +99,13 @@ __global__ void k_con2prim_rhd(GridDev g, double G, StateSrc ss, double* prim, i
     const double E = Uc[M - 1] / Jv;
     double rho, p, u[DIM];
     const double guess = use_guess ? prim[(M - 1) * P + t] : -1.0;
-    const int st = c2p_rhd<DIM>(G, D, m, E, guess, rho, u, p);
+    // a non-positive (or non-finite) Jacobian is a tangled mesh: recorded as such
+    const int st = Jv > 0.0 && Jv < INFINITY ? c2p_rhd<DIM>(G, D, m, E, guess, rho, u, p) : FAIL_MESH;
     if (st != 0) {
         rho = p = __builtin_nan("");
 #pragma unroll
         for (int c = 0; c < DIM; ++c) u[c] = __builtin_nan("");
-        if (si == i && sj == j && sk == k) {
-            atomicAdd(&fail[st == 1 ? 0 : 1], 1ull);
-            atomicMin(&fail[2], (unsigned long long)src);
-        }
+        if (si == i && sj == j && sk == k) record_failure(fail, st, src);
     }
     prim[t] = rho;
 #pragma unroll

@@ -63,14 +63,12 @@ __global__ void k_con2prim_rmhd(GridDev g, double G, StateSrc ss, double* prim, 
         for (int c = 0; c < 3; ++c) { const double u = prim[(1 + c) * P + t]; uu += u * u; }
         guess = (rho + G / (G - 1.0) * p) * (1.0 + uu);
     }
-    const int st = c2p_rmhd(G, Uc, guess, Pv);
+    const double Jv = Us[MR];
+    const int st = Jv > 0.0 && Jv < INFINITY ? c2p_rmhd(G, Uc, guess, Pv) : FAIL_MESH;
     if (st != 0) {
 #pragma unroll
         for (int c = 0; c < MR; ++c) Pv[c] = __builtin_nan("");
-        if (si == i && sj == j && sk == k) {
-            atomicAdd(&fail[st == 1 ? 0 : 1], 1ull);
-            atomicMin(&fail[2], (unsigned long long)src);
-        }
+        if (si == i && sj == j && sk == k) record_failure(fail, st, src);
     }
 #pragma unroll
     for (int c = 0; c < MR; ++c) prim[c * P + t] = Pv[c];

@@ -20,7 +20,7 @@ SYMBOLS = ("es_create", "es_destroy", "es_nvars", "es_nprim", "es_nmet", "es_nod
            "es_padded_nodes", "es_prim2con", "es_metrics", "es_con2prim", "es_residual",
            "es_cfl", "es_mesh_redistribute", "es_rk3_step", "es_rk3_step_moving", "es_set_graph",
            "es_diagnostics", "es_ctx_status", "es_status_string", "es_ckpt_doubles", "es_rk3_step_save",
-           "es_rk3_step_vjp", "es_residual_vjp")
+           "es_rk3_step_vjp", "es_residual_vjp", "es_con2prim_vjp", "es_prim2con_vjp")
 
 
 class EsError(RuntimeError):
@@ -85,9 +85,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.es_rk3_step_save.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.es_rk3_step_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.es_residual_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.es_con2prim_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.es_prim2con_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     for name in ("es_prim2con", "es_metrics", "es_con2prim", "es_residual", "es_cfl",
                  "es_mesh_redistribute", "es_rk3_step", "es_rk3_step_moving", "es_set_graph",
-                 "es_diagnostics", "es_ctx_status", "es_rk3_step_save", "es_rk3_step_vjp", "es_residual_vjp"):
+                 "es_diagnostics", "es_ctx_status", "es_rk3_step_save", "es_rk3_step_vjp", "es_residual_vjp",
+                 "es_con2prim_vjp", "es_prim2con_vjp"):
         getattr(lib, name).restype = st
     lib.es_status_string.argtypes = [st]
     lib.es_status_string.restype = ctypes.c_char_p
@@ -101,12 +104,17 @@ def _check(status: int, where: str):
         raise EsError(status, where, msg)
 
 
-def _ptr(t) -> Optional[int]:
+def _ptr(t, numel: Optional[int] = None, name: str = "array") -> Optional[int]:
+    """Device pointer of a contiguous float64 GPU tensor; with ``numel`` the tensor
+    must hold exactly that many elements (the library reads and writes that many
+    through the pointer)."""
     if t is None:
         return None
     import torch
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise ValueError("expected a contiguous float64 GPU tensor")
+        raise ValueError("%s: expected a contiguous float64 GPU tensor" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s: expected %d elements, got %d" % (name, numel, t.numel()))
     return t.data_ptr()
 
 
@@ -157,65 +165,107 @@ class Context:
     def padded_shape(self):
         return tuple(s + 6 for s in self.grid.shape)
 
+    # sizes of the documented layouts ---------------------------------------
+    def _int(self, comps=1):
+        return comps * self.nodes
+
+    def _pad(self, comps):
+        return comps * self.pnodes
+
     # entry points ---------------------------------------------------------
     def prim2con(self, prim, J, U, stream=None):
-        _check(_lib.es_prim2con(self.h, _ptr(prim), _ptr(J), _ptr(U), _stream(stream)), "es_prim2con")
+        _check(_lib.es_prim2con(self.h, _ptr(prim, self._int(self.m), "prim"), _ptr(J, self._int(), "J"),
+                                _ptr(U, self._int(self.m), "U"), _stream(stream)), "es_prim2con")
 
     def metrics(self, x, xdot, met, J0=None, stream=None):
-        _check(_lib.es_metrics(self.h, _ptr(x), _ptr(xdot), _ptr(met), _ptr(J0), _stream(stream)),
-               "es_metrics")
+        d = self.dim
+        _check(_lib.es_metrics(self.h, _ptr(x, self._int(d), "x"), _ptr(xdot, self._int(d), "xdot"),
+                               _ptr(met, self._pad(self.nmet), "met"), _ptr(J0, self._int(), "J0"),
+                               _stream(stream)), "es_metrics")
 
     def con2prim(self, U, J, prim, stream=None):
-        _check(_lib.es_con2prim(self.h, _ptr(U), _ptr(J), _ptr(prim), _stream(stream)), "es_con2prim")
+        _check(_lib.es_con2prim(self.h, _ptr(U, self._int(self.m), "U"), _ptr(J, self._int(), "J"),
+                                _ptr(prim, self._pad(self.nprim), "prim"), _stream(stream)), "es_con2prim")
 
     def residual(self, prim, met, dU, dJ, stream=None):
-        _check(_lib.es_residual(self.h, _ptr(prim), _ptr(met), _ptr(dU), _ptr(dJ), _stream(stream)),
-               "es_residual")
+        _check(_lib.es_residual(self.h, _ptr(prim, self._pad(self.nprim), "prim"),
+                                _ptr(met, self._pad(self.nmet), "met"), _ptr(dU, self._int(self.m), "dU"),
+                                _ptr(dJ, self._int(), "dJ"), _stream(stream)), "es_residual")
 
     def cfl(self, prim, met, J, dt, stream=None):
-        _check(_lib.es_cfl(self.h, _ptr(prim), _ptr(met), _ptr(J), _ptr(dt), _stream(stream)), "es_cfl")
+        _check(_lib.es_cfl(self.h, _ptr(prim, self._pad(self.nprim), "prim"), _ptr(met, self._pad(self.nmet), "met"),
+                           _ptr(J, self._int(), "J"), _ptr(dt, 1, "dt"), _stream(stream)), "es_cfl")
 
     def mesh_redistribute(self, prim, x, dt, x_new, xdot, dtau=None, stream=None):
-        _check(_lib.es_mesh_redistribute(self.h, _ptr(prim), _ptr(x), _ptr(dt), _ptr(x_new), _ptr(xdot),
-                                         _ptr(dtau), _stream(stream)), "es_mesh_redistribute")
+        d = self.dim
+        _check(_lib.es_mesh_redistribute(self.h, _ptr(prim, self._pad(self.nprim), "prim"),
+                                         _ptr(x, self._int(d), "x"), _ptr(dt, 1, "dt"),
+                                         _ptr(x_new, self._int(d), "x_new"), _ptr(xdot, self._int(d), "xdot"),
+                                         _ptr(dtau, 1, "dtau"), _stream(stream)), "es_mesh_redistribute")
+
+    def _step_ptrs(self, U, J, x, xdot, dt, fixed_dt):
+        d = self.dim
+        return (_ptr(U, self._int(self.m), "U"), _ptr(J, self._int(), "J"), _ptr(x, self._int(d), "x"),
+                _ptr(xdot, self._int(d), "xdot"), _ptr(dt, 1, "dt"), _ptr(fixed_dt, 1, "fixed_dt"))
 
     def rk3_step(self, U, J, x, xdot, dt, fixed_dt=None, stream=None):
-        _check(_lib.es_rk3_step(self.h, _ptr(U), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt), _ptr(fixed_dt),
-                                _stream(stream)), "es_rk3_step")
+        _check(_lib.es_rk3_step(self.h, *self._step_ptrs(U, J, x, xdot, dt, fixed_dt), _stream(stream)),
+               "es_rk3_step")
 
     def rk3_step_moving(self, U, J, x, xdot, dt, fixed_dt=None, stream=None):
         """One step with the caller's mesh velocity ``xdot`` held over the step."""
-        _check(_lib.es_rk3_step_moving(self.h, _ptr(U), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt),
-                                       _ptr(fixed_dt), _stream(stream)), "es_rk3_step_moving")
+        _check(_lib.es_rk3_step_moving(self.h, *self._step_ptrs(U, J, x, xdot, dt, fixed_dt), _stream(stream)),
+               "es_rk3_step_moving")
 
     def ckpt_doubles(self) -> int:
         return _lib.es_ckpt_doubles(self.h)
 
     def rk3_step_save(self, U, J, x, xdot, dt, ckpt, fixed_dt=None, stream=None):
-        _check(_lib.es_rk3_step_save(self.h, _ptr(U), _ptr(J), _ptr(x), _ptr(xdot), _ptr(dt),
-                                     _ptr(fixed_dt), _ptr(ckpt), _stream(stream)), "es_rk3_step_save")
+        _check(_lib.es_rk3_step_save(self.h, *self._step_ptrs(U, J, x, xdot, dt, fixed_dt),
+                                     _ptr(ckpt, self.ckpt_doubles(), "ckpt"), _stream(stream)), "es_rk3_step_save")
 
     def rk3_step_vjp(self, ckpt, lamU, lamJ, gU, gJ, stream=None):
-        _check(_lib.es_rk3_step_vjp(self.h, _ptr(ckpt), _ptr(lamU), _ptr(lamJ), _ptr(gU), _ptr(gJ),
+        nU, nJ = self._int(self.m), self._int()
+        _check(_lib.es_rk3_step_vjp(self.h, _ptr(ckpt, self.ckpt_doubles(), "ckpt"), _ptr(lamU, nU, "lamU"),
+                                    _ptr(lamJ, nJ, "lamJ"), _ptr(gU, nU, "gU"), _ptr(gJ, nJ, "gJ"),
                                     _stream(stream)), "es_rk3_step_vjp")
 
     def residual_vjp(self, U, J, met, lamU, gU, gJ, stream=None):
-        _check(_lib.es_residual_vjp(self.h, _ptr(U), _ptr(J), _ptr(met), _ptr(lamU), _ptr(gU), _ptr(gJ),
+        nU, nJ = self._int(self.m), self._int()
+        _check(_lib.es_residual_vjp(self.h, _ptr(U, nU, "U"), _ptr(J, nJ, "J"), _ptr(met, self._pad(self.nmet), "met"),
+                                    _ptr(lamU, nU, "lamU"), _ptr(gU, nU, "gU"), _ptr(gJ, nJ, "gJ"),
                                     _stream(stream)), "es_residual_vjp")
+
+    def con2prim_vjp(self, U, J, gprim, gU, gJ, stream=None):
+        """gU, gJ = cotangents of (Ucurv, J) from the cotangent gprim of the interior
+        primitive state recovered by con2prim (implicit-function rule)."""
+        nU, nJ = self._int(self.m), self._int()
+        _check(_lib.es_con2prim_vjp(self.h, _ptr(U, nU, "U"), _ptr(J, nJ, "J"), _ptr(gprim, nU, "gprim"),
+                                    _ptr(gU, nU, "gU"), _ptr(gJ, nJ, "gJ"), _stream(stream)), "es_con2prim_vjp")
+
+    def prim2con_vjp(self, prim, J, gU, gprim, gJ=None, stream=None):
+        """gprim (and gJ) = cotangents of (prim, J) of Ucurv = J U(prim) from gU."""
+        nU, nJ = self._int(self.m), self._int()
+        _check(_lib.es_prim2con_vjp(self.h, _ptr(prim, nU, "prim"), _ptr(J, nJ, "J"), _ptr(gU, nU, "gU"),
+                                    _ptr(gprim, nU, "gprim"), _ptr(gJ, nJ, "gJ"), _stream(stream)),
+               "es_prim2con_vjp")
 
     def set_graph(self, enable: bool):
         _check(_lib.es_set_graph(self.h, int(bool(enable))), "es_set_graph")
 
     def diagnostics(self, prim, U, J, dU, dJ, out, stream=None):
-        _check(_lib.es_diagnostics(self.h, _ptr(prim), _ptr(U), _ptr(J), _ptr(dU), _ptr(dJ), _ptr(out),
-                                   _stream(stream)), "es_diagnostics")
+        nU, nJ = self._int(self.m), self._int()
+        _check(_lib.es_diagnostics(self.h, _ptr(prim, self._pad(self.nprim), "prim"), _ptr(U, nU, "U"),
+                                   _ptr(J, nJ, "J"), _ptr(dU, nU, "dU"), _ptr(dJ, nJ, "dJ"),
+                                   _ptr(out, 3 + self.m, "out"), _stream(stream)), "es_diagnostics")
 
     def status(self, stream=None):
-        """Synchronise and return (status, n_fail, first_fail) of recorded con2prim failures."""
+        """Synchronise and return (status, n_fail, first_fail) of the failures recorded
+        by con2prim (ES_EMESH: a non-positive Jacobian; ES_EADMISSIBLE; ES_ENOCONV)."""
         nf = ctypes.c_longlong()
         ff = ctypes.c_longlong()
         st = _lib.es_ctx_status(self.h, _stream(stream), ctypes.byref(nf), ctypes.byref(ff))
-        if st not in (ES_OK, ES_EADMISSIBLE, ES_ENOCONV):
+        if st not in (ES_OK, ES_EADMISSIBLE, ES_ENOCONV, ES_EMESH):
             _check(st, "es_ctx_status")
         return st, nf.value, ff.value
 

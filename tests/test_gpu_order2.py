@@ -154,10 +154,16 @@ def test_p2_mixed_adjoint_unsupported():
     w.scheme.order_p = 2
     w.scheme.mixed = 1
     ctx = es.Context(w.grid, w.scheme, w.monitor)
-    t = [empty(1) for _ in range(6)]
+    # buffers of the documented sizes, so that nothing could run out of bounds even
+    # if the library accepted the call
+    U, J, x, xdot = empty(ctx.m, *ctx.shape()), empty(*ctx.shape()), empty(2, *ctx.shape()), empty(2, *ctx.shape())
+    dt, ck = empty(1), empty(ctx.ckpt_doubles())
     with pytest.raises(es.EsError) as err:
-        ctx.rk3_step_save(*t)
+        ctx.rk3_step_save(U, J, x, xdot, dt, ck)
     assert err.value.status == es.ES_EUNSUPPORTED
+    # a buffer of the wrong size is refused by the binding before the library is called
+    with pytest.raises(ValueError):
+        ctx.rk3_step_save(U, J, x, xdot, dt, empty(1))
 
 
 RMHD_GRIDS = [(2, (130, 70, 1), (0, 0, 0)), (2, (64, 67, 1), (1, 1, 0)), (3, (66, 9, 8), (0, 1, 0))]
