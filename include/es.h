@@ -52,7 +52,8 @@ typedef enum {
     ES_ENOCONV = 3,       /* con2prim iteration did not converge */
     ES_EMESH = 4,         /* non-positive Jacobian (tangled mesh), reported by es_ctx_status */
     ES_EHIP = 5,          /* HIP runtime error */
-    ES_EUNSUPPORTED = 6   /* valid option not built into this library */
+    ES_EUNSUPPORTED = 6,  /* valid option not built into this library */
+    ES_ETOOLARGE = 7      /* grid exceeds the static scratch of an allocation-free entry point */
 } es_status;
 
 enum { ES_RHD = 0, ES_RMHD = 1 };
@@ -159,6 +160,24 @@ es_status es_residual(es_ctx* ctx, const double* prim, const double* met, double
  * prim, met: padded; J: interior; dt_dev: one device double (output). */
 es_status es_cfl(es_ctx* ctx, const double* prim, const double* met, const double* J,
                  double* dt_dev, hipStream_t stream);
+
+/* Allocation-free CFL step, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the computation of es_cfl on a grid and scheme given directly,
+ * without a context.  The per-block maxima of the reduction live in a static
+ * device array of 3 * ES_CFL_STATIC_MAX_BLOCKS doubles (3 MiB) that every GPU
+ * the library runs on holds until the process ends; no call allocates or frees
+ * memory.  Grids needing more blocks than ES_CFL_STATIC_MAX_BLOCKS
+ * (es_cfl_static_blocks: ceil(n0/64) * ceil(n1/4) * n2) return ES_ETOOLARGE
+ * before anything is enqueued.  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU (different streams or threads without ordering)
+ * race and must not be issued.  The array needs no clearing: each call writes
+ * every entry it reads.  prim, met: padded (es_con2prim / es_metrics layouts);
+ * J: interior; dt_dev: one device double (output).  Other errors as es_cfl. */
+#define ES_CFL_STATIC_MAX_BLOCKS 131072
+size_t es_cfl_static_blocks(const es_grid* grid);
+es_status es_cfl_noalloc(const es_grid* grid, const es_scheme* scheme, const double* prim,
+                         const double* met, const double* J, double* dt_dev, hipStream_t stream);
 
 /* Mesh redistribution (Section 5): monitor, low-pass filter, Jacobi sweeps,
  * move limiter Delta_tau, x_new = x + Delta_tau (x^[mu] - x),

@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "es_internal.h"
@@ -69,6 +70,38 @@ void describe(es_ctx* c, const es_grid* grid, const es_scheme* scheme, const es_
     c->nmet = grid->dim * (grid->dim + 1);
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free CFL step: the per-block maxima of the CFL
+// kernels (dim slabs of one double per block) in a static device array.  Every
+// GPU the library runs on holds its own copy until the process ends; host code
+// never passes the array's name to a kernel (in host code it is a stand-in, not
+// a device address) but the address hipGetSymbolAddress returns for the
+// current device, resolved once per device and kept.
+// ---------------------------------------------------------------------------
+constexpr long long kCflScratchDoubles = 3LL * ES_CFL_STATIC_MAX_BLOCKS;
+static __device__ __align__(256) double scratch[kCflScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+double* scratch_dev[kMaxDevices];   // device address of `scratch` per device (null: not resolved yet)
+
+hipError_t scratch_address(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (scratch_dev[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = scratch_dev[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -82,6 +115,7 @@ const char* es_status_string(es_status s) {
         case ES_EMESH: return "non-positive Jacobian";
         case ES_EHIP: return "HIP runtime error";
         case ES_EUNSUPPORTED: return "option not supported by this build";
+        case ES_ETOOLARGE: return "grid exceeds the static scratch of an allocation-free entry point";
     }
     return "unknown status";
 }
@@ -203,6 +237,32 @@ es_status es_cfl(es_ctx* c, const double* prim, const double* met, const double*
     if (c == nullptr || prim == nullptr || met == nullptr || J == nullptr || dt_dev == nullptr)
         return ES_EINVAL;
     return hip_status(es::launch_cfl(c, prim, met, J, dt_dev, nullptr, s));
+}
+
+size_t es_cfl_static_blocks(const es_grid* grid) {
+    if (!valid_grid(grid)) return 0;
+    return (size_t)((grid->n[0] + 63) / 64) * (size_t)((grid->n[1] + 3) / 4) * (size_t)grid->n[2];
+}
+
+es_status es_cfl_noalloc(const es_grid* grid, const es_scheme* scheme, const double* prim, const double* met,
+                         const double* J, double* dt_dev, hipStream_t s) {
+    if (grid == nullptr || scheme == nullptr || prim == nullptr || met == nullptr || J == nullptr ||
+        dt_dev == nullptr)
+        return ES_EINVAL;
+    if (!valid_grid(grid)) return ES_EINVAL;
+    if (scheme->phys != ES_RHD && scheme->phys != ES_RMHD) return ES_EINVAL;
+    if (!(scheme->gamma > 1.0 && scheme->gamma <= 2.0) || !(scheme->cfl > 0.0)) return ES_EINVAL;
+    if (es_cfl_static_blocks(grid) > (size_t)ES_CFL_STATIC_MAX_BLOCKS) return ES_ETOOLARGE;
+    double* red = nullptr;
+    ES_TRY(scratch_address(&red));
+    // a context on the stack that owns no device memory: the CFL kernels read its
+    // grid, scheme and reduction buffer only
+    es_ctx tmp;
+    describe(&tmp, grid, scheme, nullptr);
+    tmp.red = red;
+    tmp.red_blocks = es::reduction_blocks(tmp.g);
+    if ((size_t)tmp.red_blocks != es_cfl_static_blocks(grid)) return ES_EINVAL;
+    return hip_status(es::launch_cfl(&tmp, prim, met, J, dt_dev, nullptr, s));
 }
 
 es_status es_mesh_redistribute(es_ctx* c, const double* prim, const double* x, const double* dt_dev,

@@ -15,12 +15,13 @@ from typing import Optional
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libes.so")
 
-ES_OK, ES_EINVAL, ES_EADMISSIBLE, ES_ENOCONV, ES_EMESH, ES_EHIP, ES_EUNSUPPORTED = range(7)
+ES_OK, ES_EINVAL, ES_EADMISSIBLE, ES_ENOCONV, ES_EMESH, ES_EHIP, ES_EUNSUPPORTED, ES_ETOOLARGE = range(8)
 SYMBOLS = ("es_create", "es_destroy", "es_nvars", "es_nprim", "es_nmet", "es_nodes",
            "es_padded_nodes", "es_prim2con", "es_metrics", "es_con2prim", "es_residual",
            "es_cfl", "es_mesh_redistribute", "es_rk3_step", "es_rk3_step_moving", "es_set_graph",
            "es_diagnostics", "es_ctx_status", "es_status_string", "es_ckpt_doubles", "es_rk3_step_save",
-           "es_rk3_step_vjp", "es_residual_vjp", "es_con2prim_vjp", "es_prim2con_vjp")
+           "es_rk3_step_vjp", "es_residual_vjp", "es_con2prim_vjp", "es_prim2con_vjp",
+           "es_cfl_static_blocks", "es_cfl_noalloc")
 
 
 class EsError(RuntimeError):
@@ -87,10 +88,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.es_residual_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.es_con2prim_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.es_prim2con_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.es_cfl_static_blocks.argtypes = [ctypes.POINTER(Grid)]
+    lib.es_cfl_static_blocks.restype = ctypes.c_size_t
+    lib.es_cfl_noalloc.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Scheme), vp, vp, vp, vp, vp]
     for name in ("es_prim2con", "es_metrics", "es_con2prim", "es_residual", "es_cfl",
                  "es_mesh_redistribute", "es_rk3_step", "es_rk3_step_moving", "es_set_graph",
                  "es_diagnostics", "es_ctx_status", "es_rk3_step_save", "es_rk3_step_vjp", "es_residual_vjp",
-                 "es_con2prim_vjp", "es_prim2con_vjp"):
+                 "es_con2prim_vjp", "es_prim2con_vjp", "es_cfl_noalloc"):
         getattr(lib, name).restype = st
     lib.es_status_string.argtypes = [st]
     lib.es_status_string.restype = ctypes.c_char_p
@@ -249,6 +253,13 @@ class Context:
         _check(_lib.es_prim2con_vjp(self.h, _ptr(prim, nU, "prim"), _ptr(J, nJ, "J"), _ptr(gU, nU, "gU"),
                                     _ptr(gprim, nU, "gprim"), _ptr(gJ, nJ, "gJ"), _stream(stream)),
                "es_prim2con_vjp")
+
+    def cfl_noalloc(self, prim, met, J, dt, stream=None):
+        """es_cfl_noalloc on this context's grid and scheme (the library call takes no
+        context and allocates nothing: its block maxima live in a static device array)."""
+        _check(_lib.es_cfl_noalloc(ctypes.byref(self.grid_c), ctypes.byref(self.scheme_c),
+                                   _ptr(prim, self._pad(self.nprim), "prim"), _ptr(met, self._pad(self.nmet), "met"),
+                                   _ptr(J, self._int(), "J"), _ptr(dt, 1, "dt"), _stream(stream)), "es_cfl_noalloc")
 
     def set_graph(self, enable: bool):
         _check(_lib.es_set_graph(self.h, int(bool(enable))), "es_set_graph")
