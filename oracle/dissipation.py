@@ -136,19 +136,33 @@ def _eigensystem_rmhd(JU, JF, JV, vn):
     return lam, canonical_group_basis(lam, Z, L, Linv, vn)
 
 
+def group_labels(lam):
+    """Eigen-groups of (N, m) ascending eigenvalues: label of each eigenvalue = the
+    smallest index of its chain of neighbours closer than GROUP_TOL."""
+    N, m = lam.shape
+    lab = np.tile(np.arange(m), (N, 1))
+    close = np.abs(lam[:, :, None] - lam[:, None, :]) <= GROUP_TOL
+    for _ in range(m):
+        lab = np.min(np.where(close, lab[:, None, :], m), axis=2)
+    return lab
+
+
+# the group labels and the seed slot accepted for every column of the last
+# canonical_group_basis call (for studies of the decisions' sensitivity)
+last_group_decisions = {}
+
+
 def canonical_group_basis(lam, Z, L, Linv, vn):
     """R (N, m, m) from eigenvalues lam (N, m), orthonormal eigenvectors Z of
     L^{-1} S L^{-T} (columns) and the Cholesky factor L of A0 (see _eigensystem_rmhd)."""
     N, m = lam.shape
     rows = np.arange(N)
-    lab = np.tile(np.arange(m), (N, 1))
-    close = np.abs(lam[:, :, None] - lam[:, None, :]) <= GROUP_TOL
-    for _ in range(m):
-        lab = np.min(np.where(close, lab[:, None, :], m), axis=2)
+    lab = group_labels(lam)
     lab_c = lab[rows, np.argmin(np.abs(lam - vn[:, None]), axis=1)]
     C = np.einsum("nia,nis->nas", Z, Linv)            # z_a . (L^{-1} e_s)
     ynorm = np.sqrt(np.sum(Linv * Linv, axis=1))      # |L^{-1} e_s| (A0^{-1} norm of e_s)
     canon = np.zeros((N, m, m))                       # canon[:, :, i]: z-space column i
+    seed_of = np.full((N, m), -1)
     for i in range(m):
         ing = lab == lab[:, i:i + 1]                  # (N, m) members of the group of i
         is_c = lab[:, i] == lab_c
@@ -164,7 +178,10 @@ def canonical_group_basis(lam, Z, L, Linv, vn):
             nrm = np.sqrt(np.sum(p * p, axis=1))
             acc = (~done) & (nrm > SEED_TOL * ynorm[rows, sidx])
             canon[acc, :, i] = p[acc] / nrm[acc, None]
+            seed_of[acc, i] = sidx[acc]
             done |= acc
+    last_group_decisions["labels"] = lab
+    last_group_decisions["seeds"] = seed_of
     return np.einsum("nab,nbc->nac", L, canon)
 
 

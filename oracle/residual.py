@@ -83,6 +83,8 @@ def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None, eig_fixed=Non
             Ff = Ff - 0.5 * dd.reshape((8,) + fshape)
             Yk = dinfo["Y"]
             eigk = (dinfo["R"], dinfo["lhat"])
+            lamk = dinfo["lam"]
+            groupk = dict(ds.last_group_decisions) if phys == ph.RMHD else None
         hi = np.arange(1, nk + 1)
         lo = np.arange(0, nk)
         dxi = grid.dxi[k]
@@ -92,7 +94,9 @@ def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None, eig_fixed=Non
             src += (_take(Bf, hi, ax_sp) - _take(Bf, lo, ax_sp)) / dxi
         if details:
             info[k] = dict(F=Ff, J=Jf, B=Bf, Y=Yk if scheme.dissipation else None,
-                           eig=eigk if scheme.dissipation else None)
+                           eig=eigk if scheme.dissipation else None,
+                           lam=lamk if scheme.dissipation else None,
+                           groups=groupk if scheme.dissipation else None)
     if phys == ph.RMHD:
         Pin = interior(Ppad, grid)
         dU -= ph.phi_prime(Pin, G) * src

@@ -100,3 +100,28 @@ class Case:
         U = empty(c.m, *c.shape())
         c.prim2con(dev(prim_interior(self.P, self.phys, self.dim)), J, U)
         return U, J
+
+
+def run_steps(w, nsteps, x0=None):
+    """Run nsteps of es_rk3_step and of the oracle from the same workload."""
+    g = w.grid
+    ctx = es.Context(g, w.scheme, w.monitor)
+    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
+    x = w.x if x0 is None else x0
+    met = empty(ctx.nmet, *ctx.padded_shape())
+    J = empty(*ctx.shape())
+    xg = dev(x)
+    ctx.metrics(xg, None, met, J)
+    U = empty(ctx.m, *ctx.shape())
+    ctx.prim2con(dev(P[ph.comps(w.scheme.phys, g.dim)]), J, U)
+    xdot = empty(g.dim, *ctx.shape())
+    dt = empty(1)
+    Uo, Jo = st.initial_state(g, w.scheme, P, x)
+    xo = x.copy()
+    for _ in range(nsteps):
+        ctx.rk3_step(U, J, xg, xdot, dt)
+        out = st.rk3_step(g, w.scheme, w.monitor, Uo, Jo, xo)
+        Uo, Jo, xo = out["U"], out["J"], out["x"]
+        assert abs(host(dt)[0] - out["dt"]) <= 1e-12 * out["dt"]
+    assert ctx.status()[0] == es.ES_OK
+    return (host(U), host(J), host(xg), host(xdot)), (Uo, Jo, xo, out["xdot"])

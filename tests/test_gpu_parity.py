@@ -9,7 +9,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import physics as ph, metrics as mt, residual as rs, stepper as st, mesh as msh  # noqa: E402
 from paper_2107_12027_amd import es, workloads as wl  # noqa: E402
-from gpu_util import Case, dev, host, empty, rel_inf, prim_interior  # noqa: E402
+from gpu_util import Case, dev, host, empty, rel_inf, prim_interior, run_steps  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -143,34 +143,9 @@ def test_mesh_redistribution(dim, n, bc, form, sigma):
     assert np.max(np.abs(host(xd) - xdo)) <= 1e-12 * max(1.0, np.max(np.abs(xdo)))
 
 
-def _run_steps(w, nsteps, x0=None):
-    """Run nsteps of es_rk3_step and of the oracle from the same workload."""
-    g = w.grid
-    ctx = es.Context(g, w.scheme, w.monitor)
-    P = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
-    x = w.x if x0 is None else x0
-    met = empty(ctx.nmet, *ctx.padded_shape())
-    J = empty(*ctx.shape())
-    xg = dev(x)
-    ctx.metrics(xg, None, met, J)
-    U = empty(ctx.m, *ctx.shape())
-    ctx.prim2con(dev(P[ph.comps(w.scheme.phys, g.dim)]), J, U)
-    xdot = empty(g.dim, *ctx.shape())
-    dt = empty(1)
-    Uo, Jo = st.initial_state(g, w.scheme, P, x)
-    xo = x.copy()
-    for _ in range(nsteps):
-        ctx.rk3_step(U, J, xg, xdot, dt)
-        out = st.rk3_step(g, w.scheme, w.monitor, Uo, Jo, xo)
-        Uo, Jo, xo = out["U"], out["J"], out["x"]
-        assert abs(host(dt)[0] - out["dt"]) <= 1e-12 * out["dt"]
-    assert ctx.status()[0] == es.ES_OK
-    return (host(U), host(J), host(xg), host(xdot)), (Uo, Jo, xo, out["xdot"])
-
-
 def test_rk3_step_advected_sine_adaptive():
     w = wl.advected_sine(n=72)
-    (U, J, x, xd), (Uo, Jo, xo, xdo) = _run_steps(w, 2)
+    (U, J, x, xd), (Uo, Jo, xo, xdo) = run_steps(w, 2)
     assert np.all(rel_inf(U, Uo) <= TOL), rel_inf(U, Uo)
     assert rel_inf(J[None], Jo[None])[0] <= TOL
     assert np.max(np.abs(x - xo)) <= 1e-13
@@ -179,7 +154,7 @@ def test_rk3_step_advected_sine_adaptive():
 def test_rk3_step_quadrant_riemann_adaptive():
     # one full step from the same initial data meets the per-call bar
     w = wl.quadrant_riemann(n=70, seed=2)
-    (U, J, x, xd), (Uo, Jo, xo, xdo) = _run_steps(w, 1)
+    (U, J, x, xd), (Uo, Jo, xo, xdo) = run_steps(w, 1)
     assert np.all(rel_inf(U, Uo) <= TOL), rel_inf(U, Uo)
     assert rel_inf(J[None], Jo[None])[0] <= TOL
     assert np.max(np.abs(x - xo)) <= 1e-13
@@ -190,14 +165,14 @@ def test_quadrant_riemann_multi_step_growth():
     # the alpha = 1200 monitor (the oracle alone moves by ~1e-12 for a 1e-15 input
     # perturbation per step); the primitive solution stays within 1e-10.
     w = wl.quadrant_riemann(n=70, seed=2)
-    (U, J, x, xd), (Uo, Jo, xo, xdo) = _run_steps(w, 4)
+    (U, J, x, xd), (Uo, Jo, xo, xdo) = run_steps(w, 4)
     assert np.all(rel_inf(U / J, Uo / Jo) <= 1e-10), rel_inf(U / J, Uo / Jo)
     assert np.max(np.abs(x - xo)) <= 1e-10
 
 
 def test_rk3_step_blast3d_adaptive():
     w = wl.blast3d(n=18, seed=0)
-    (U, J, x, xd), (Uo, Jo, xo, xdo) = _run_steps(w, 1)
+    (U, J, x, xd), (Uo, Jo, xo, xdo) = run_steps(w, 1)
     assert np.all(rel_inf(U, Uo) <= TOL), rel_inf(U, Uo)
     assert rel_inf(J[None], Jo[None])[0] <= TOL
     assert np.max(np.abs(x - xo)) <= 1e-13
@@ -207,7 +182,7 @@ def test_rk3_step_blast3d_adaptive():
 def test_rk3_step_paper_riemann_problems(case):
     # the initial data of the paper's RHD Riemann problems I-III (MM-O5 setup)
     w = wl.riemann2d(case, n=48)
-    (U, J, x, xd), (Uo, Jo, xo, xdo) = _run_steps(w, 1)
+    (U, J, x, xd), (Uo, Jo, xo, xdo) = run_steps(w, 1)
     assert np.all(rel_inf(U, Uo) <= TOL), rel_inf(U, Uo)
     assert rel_inf(J[None], Jo[None])[0] <= TOL
     assert np.max(np.abs(x - xo)) <= 1e-13
