@@ -59,6 +59,7 @@ RESIDUAL_FLOPS_PER_NODE_3D_RHD = 8313.0
 # with their commands are the es_residual_hbm_counters_* files under profiles/.
 RESIDUAL_TRAFFIC_BYTES = {
     "rhd2d_quadrant_riemann_400_seed2": 57.73e6,
+    "rhd3d_blast_128": 1325.73e6,
 }
 
 
