@@ -281,12 +281,127 @@ def weno3_minus(a, b, c, eps):
     return (a0 * q0 + a1 * q1) / (a0 + a1)
 
 
+def _frac_solve(A, b):
+    """Exact solution of A y = b over the rationals (Gauss-Jordan, no pivoting needed
+    for the nonsingular Vandermonde-like systems below beyond a nonzero search)."""
+    from fractions import Fraction
+    n = len(A)
+    M = [[Fraction(v) for v in row] + [Fraction(b[r])] for r, row in enumerate(A)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[piv] = M[piv], M[c]
+        inv = 1 / M[c][c]
+        M[c] = [v * inv for v in M[c]]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c]
+                M[r] = [a - f * b_ for a, b_ in zip(M[r], M[c])]
+    return [M[r][n] for r in range(n)]
+
+
+def weno_js_tables(r):
+    """The WENO-JS scheme of order 2r - 1 (Jiang and Shu 1996; Balsara and Shu 2000 for
+    r = 4) written out from its definition, in exact rational arithmetic, for the value
+    at x_{i+1/2} from v_{i-r+1..i+r-1} (unit spacing, node i at x = 0, v read as the
+    averages over the cells [l - 1/2, l + 1/2], as finite-difference WENO does):
+      * candidate k = 0..r-1 on the cells i-r+1+k..i+k: the polynomial p_k of degree
+        r-1 with those averages, evaluated at x = 1/2: q_k = c_k . v_{S_k};
+      * its smoothness indicator beta_k = sum_{l=1}^{r-1} int_{-1/2}^{1/2} (p_k^(l))^2 dx,
+        a quadratic form v_{S_k}^T B_k v_{S_k};
+      * linear weights d_k with sum_k d_k q_k = the value of the degree 2r-2 polynomial
+        with the averages of all 2r-1 cells.
+    Returns (c, B, d): c (r, r), B (r, r, r), d (r,) as Fractions."""
+    from fractions import Fraction
+
+    def cell_avg_row(l, deg):
+        # int_{l-1/2}^{l+1/2} x^m dx for m = 0..deg
+        a, b = Fraction(2 * l - 1, 2), Fraction(2 * l + 1, 2)
+        return [(b ** (m + 1) - a ** (m + 1)) / (m + 1) for m in range(deg + 1)]
+
+    def value_weights(cells, x0):
+        # weights w with p(x0) = w . averages for the interpolating polynomial of the cells
+        deg = len(cells) - 1
+        A = [cell_avg_row(l, deg) for l in cells]              # averages = A coef
+        At = [[A[rr][cc] for rr in range(len(cells))] for cc in range(deg + 1)]
+        e = [x0 ** m for m in range(deg + 1)]                  # p(x0) = e . coef = e . A^{-1} avg
+        return _frac_solve(At, e)                              # w = A^{-T} e
+
+    half = Fraction(1, 2)
+    c, B = [], []
+    for k in range(r):
+        cells = list(range(-r + 1 + k, k + 1))
+        c.append(value_weights(cells, half))
+        # beta_k: coefficients of p_k are A^{-1} v; the l-th derivative and the
+        # integrals of products of monomials over [-1/2, 1/2]
+        deg = r - 1
+        A = [cell_avg_row(l, deg) for l in cells]
+        Ainv_cols = []
+        for j in range(r):
+            ej = [Fraction(int(i == j)) for i in range(r)]
+            Ainv_cols.append(_frac_solve(A, ej))                # coefficients of the basis p with avg e_j
+        Q = [[Fraction(0)] * r for _ in range(r)]
+        for l in range(1, r):
+            # derivative of order l of the monomial coefficient vectors
+            def deriv(coef):
+                out = list(coef)
+                for _ in range(l):
+                    out = [out[m] * m for m in range(1, len(out))]
+                return out
+            D = [deriv(col) for col in Ainv_cols]
+            for a in range(r):
+                for b in range(r):
+                    acc = Fraction(0)
+                    for m1, u in enumerate(D[a]):
+                        for m2, w in enumerate(D[b]):
+                            if (m1 + m2) % 2 == 0:              # odd powers integrate to 0
+                                acc += u * w * 2 * half ** (m1 + m2 + 1) / (m1 + m2 + 1)
+                    Q[a][b] += acc
+        B.append(Q)
+    big = value_weights(list(range(-r + 1, r)), half)          # 2r - 1 cells
+    # sum_k d_k (c_k placed at offset k) = big: an overdetermined consistent system,
+    # solved on the first r rows (the cells i-r+1..i) where the triangular structure
+    # fixes d_0, d_1, ... in turn, then checked on all rows
+    M = [[c[k][row - k] if 0 <= row - k < r else Fraction(0) for k in range(r)] for row in range(2 * r - 1)]
+    d = _frac_solve(M[:r], big[:r])
+    for row in range(2 * r - 1):
+        assert sum(M[row][k] * d[k] for k in range(r)) == big[row]
+    return c, B, d
+
+
+_WENO_TABLES = {}
+
+
+def weno_js_minus(vs, eps):
+    """The WENO-JS value at i+1/2 (order 2r - 1) from the 2r - 1 values v_{i-r+1..i+r-1},
+    with the tables of weno_js_tables: nonlinear weights d_k / (eps + beta_k)^2."""
+    r = (len(vs) + 1) // 2
+    if r not in _WENO_TABLES:
+        c, B, d = weno_js_tables(r)
+        _WENO_TABLES[r] = (np.array([[float(v) for v in row] for row in c]),
+                           np.array([[[float(v) for v in row] for row in Q] for Q in B]),
+                           np.array([float(v) for v in d]))
+    c, B, d = _WENO_TABLES[r]
+    num = 0.0
+    den = 0.0
+    for k in range(r):
+        S = vs[k:k + r]
+        q = sum(c[k][j] * S[j] for j in range(r))
+        beta = sum(B[k][a][b] * S[a] * S[b] for a in range(r) for b in range(r))
+        alpha = d[k] / (eps + beta) ** 2
+        num = num + alpha * q
+        den = den + alpha
+    return num / den
+
+
 def weno_minus(vs, eps):
-    """The w-th order WENO-JS value at i+1/2 from the w values v_{i-(w-1)/2..i+(w-1)/2}."""
+    """The w-th order WENO-JS value at i+1/2 from the w values v_{i-(w-1)/2..i+(w-1)/2}:
+    WENO5 and WENO3 in their published closed forms, WENO7 from weno_js_tables."""
     if len(vs) == 5:
         return weno5_minus(*vs, eps)
     if len(vs) == 3:
         return weno3_minus(*vs, eps)
+    if len(vs) == 7:
+        return weno_js_minus(vs, eps)
     raise ValueError("WENO order %d is not implemented" % len(vs))
 
 

@@ -8,19 +8,27 @@ the 2D explicit form of Appendix B with the 1/Delta xi factors of eq. SCLCoeff.
 
 Ghost handling (a reading; the paper does not fix it): the mesh is extended beyond the index
 box by a periodic copy plus the period shift, or by odd reflection
-x_{-a} = 2 x_0 - x_a on bounded axes; the metrics on the 3-wide ghost strips
-are evaluated from that extended mesh with the same formula as inside.
+x_{-a} = 2 x_0 - x_a on bounded axes; the metrics on the ghost strips (ghost(p)
+wide) are evaluated from that extended mesh with the same formula as inside.
 
 Array layout: node fields are C-ordered [z][y][x]; index axis k (xi_{k+1}) is
 array axis ndim-1-k.  ``met`` has d(d+1) components on the ghost-padded box
-(each axis grown by 3 on both sides): met[k(d+1)] = J dxi_k/dt and
+(each axis grown by ghost(p) on both sides): met[k(d+1)] = J dxi_k/dt and
 met[k(d+1)+1+j] = J dxi_k/dx_j.
 """
 from __future__ import annotations
 
 import numpy as np
 
-NG = 3
+NG = 3      # ghost layers of the padded box for p <= 3
+
+
+def ghost(p: int) -> int:
+    """Ghost layers of the padded box for the 2p-th order scheme: its stencils reach
+    p nodes past an edge (the EC pairs (i, i+n), n <= p, the metrics' delta_k and,
+    for the dissipation, WENO-(2p-1) on nodes i-p+1..i+p); p = 2 keeps the layout
+    of p = 3."""
+    return max(NG, p)
 
 
 def alpha(p: int):
@@ -85,7 +93,8 @@ def crop(a, ax, c):
 def spatial_metrics(grid, x, p=3):
     """J dxi_k/dx_j on the ghost-padded box: list [k][j]."""
     d = grid.dim
-    xe = [extend(x[c], grid, 2 * NG, "mesh", comp=c) for c in range(d)]
+    ng = ghost(p)
+    xe = [extend(x[c], grid, 2 * ng, "mesh", comp=c) for c in range(d)]
     nd = xe[0].ndim
     dxi = grid.dxi
     if d == 2:
@@ -93,10 +102,10 @@ def spatial_metrics(grid, x, p=3):
         # Appendix B: J xi_x = delta_eta[y]/deta, J xi_y = -delta_eta[x]/deta,
         #             J eta_x = -delta_xi[y]/dxi, J eta_y = delta_xi[x]/dxi
         def d_eta(f):
-            return crop(crop(delta(f, ax1, p), ax1, NG - p), ax0, NG)
+            return crop(crop(delta(f, ax1, p), ax1, ng - p), ax0, ng)
 
         def d_xi(f):
-            return crop(crop(delta(f, ax0, p), ax0, NG - p), ax1, NG)
+            return crop(crop(delta(f, ax0, p), ax0, ng - p), ax1, ng)
         return [[d_eta(xe[1]) / dxi[1], -d_eta(xe[0]) / dxi[1]],
                 [-d_xi(xe[1]) / dxi[0], d_xi(xe[0]) / dxi[0]]]
     # 3D: eq. SCLCoeff, J dxi_k/dx_j = (d_k2[d_k1[x_j1] x_j2] - d_k1[d_k2[x_j1] x_j2]) / (dxi_k1 dxi_k2)
@@ -112,10 +121,10 @@ def spatial_metrics(grid, x, p=3):
             t = delta(xe[j1], a2, p) * crop(xe[j2], a2, p)
             tB = delta(t, a1, p)
             val = (tA - tB) / (dxi[k1] * dxi[k2])
-            # shrink axis k by 2*NG - NG and axes k1, k2 by (2*NG - p) - NG
-            val = crop(val, a_k, NG)
-            val = crop(val, a1, NG - p)
-            val = crop(val, a2, NG - p)
+            # shrink axis k by 2 ng - ng and axes k1, k2 by (2 ng - p) - ng
+            val = crop(val, a_k, ng)
+            val = crop(val, a1, ng - p)
+            val = crop(val, a2, ng - p)
             out[k][j] = val
     return out
 
@@ -128,7 +137,7 @@ def metrics(grid, x, xdot=None, p=3):
     pshape = S[0][0].shape
     met = np.zeros((d * (d + 1),) + pshape)
     if xdot is not None:
-        xde = [extend(xdot[c], grid, NG, "velocity") for c in range(d)]
+        xde = [extend(xdot[c], grid, ghost(p), "velocity") for c in range(d)]
     for k in range(d):
         at = np.zeros(pshape)
         for j in range(d):
@@ -163,6 +172,6 @@ def jacobian(grid, x, p=3):
                 dk = crop(dk, _ax(nd, kk), p)
         Sk = S[k][0]
         for kk in range(3):
-            Sk = crop(Sk, _ax(nd, kk), NG)
+            Sk = crop(Sk, _ax(nd, kk), ghost(p))
         J = J + Sk * dk / grid.dxi[k]
     return J

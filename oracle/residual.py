@@ -16,16 +16,17 @@ import numpy as np
 from . import physics as ph
 from . import ecflux as ec
 from . import dissipation as ds
-from .metrics import NG, alpha, crop
+from .metrics import alpha, crop, ghost
 
 
-def _line_view(arr, grid, k, lead):
-    """Crop every axis except k to the interior; ``lead`` leading non-spatial axes."""
+def _line_view(arr, grid, k, lead, ng=3):
+    """Crop every axis except k to the interior (``ng`` ghost layers); ``lead``
+    leading non-spatial axes."""
     out = arr
     nd = arr.ndim - lead
     for kk in range(grid.dim):
         if kk != k:
-            out = crop(out, lead + nd - 1 - kk, NG)
+            out = crop(out, lead + nd - 1 - kk, ng)
     return out
 
 
@@ -44,6 +45,7 @@ def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None, eig_fixed=Non
     G = scheme.gamma
     phys = scheme.phys
     p = scheme.order_p
+    ng = ghost(p)
     al = alpha(p)
     sel = ph.comps(phys, d)
     shape = grid.shape
@@ -53,10 +55,10 @@ def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None, eig_fixed=Non
     info = {}
     for k in range(d):
         ax_sp = d - 1 - k                     # spatial axis of direction k
-        Pk = _line_view(Ppad, grid, k, 1)     # (8, ..., n_k+6, ...)
-        ak = _line_view(met[k * (d + 1):(k + 1) * (d + 1)], grid, k, 1)
+        Pk = _line_view(Ppad, grid, k, 1, ng)     # (8, ..., n_k + 2 ng, ...)
+        ak = _line_view(met[k * (d + 1):(k + 1) * (d + 1)], grid, k, 1, ng)
         nk = grid.n[k]
-        faces = np.arange(NG - 1, NG + nk)    # face I+1/2 between padded nodes I, I+1
+        faces = np.arange(ng - 1, ng + nk)    # face I+1/2 between padded nodes I, I+1
         Ff = 0.0
         Bf = 0.0
         Jf = 0.0
@@ -98,17 +100,18 @@ def residual(grid, scheme, Ppad, met, details=False, Y_fixed=None, eig_fixed=Non
                            lam=lamk if scheme.dissipation else None,
                            groups=groupk if scheme.dissipation else None)
     if phys == ph.RMHD:
-        Pin = interior(Ppad, grid)
+        Pin = interior(Ppad, grid, ng)
         dU -= ph.phi_prime(Pin, G) * src
     if details:
         return dU[sel], dJ, info
     return dU[sel], dJ
 
 
-def interior(Ppad, grid):
+def interior(Ppad, grid, ng=3):
+    """The interior nodes of a field on the box padded by ``ng`` ghost layers."""
     out = Ppad
     for k in range(grid.dim):
-        out = crop(out, out.ndim - 1 - k, NG)
+        out = crop(out, out.ndim - 1 - k, ng)
     return out
 
 

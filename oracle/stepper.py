@@ -33,8 +33,9 @@ def cons_from_prim(grid, scheme, P, J):
     return J * ph.cons(P, scheme.gamma)[sel]
 
 
-def pad_solution(grid, P):
-    return np.stack([mt.extend(P[c], grid, mt.NG, "solution") for c in range(8)])
+def pad_solution(grid, P, p=3):
+    """The primitive state on the box padded by ghost(p) layers (solution rule)."""
+    return np.stack([mt.extend(P[c], grid, mt.ghost(p), "solution") for c in range(8)])
 
 
 def speeds(P, G, phys, dim):
@@ -55,7 +56,7 @@ def spectral_radius(grid, scheme, Pin, met, J):
     out = []
     Pflat = Pin.reshape(8, -1)
     for k in range(d):
-        a = rs.interior(met[k * (d + 1):(k + 1) * (d + 1)], grid).reshape(d + 1, -1)
+        a = rs.interior(met[k * (d + 1):(k + 1) * (d + 1)], grid, mt.ghost(scheme.order_p)).reshape(d + 1, -1)
         ax = np.zeros((3, a.shape[1]))
         ax[:d] = a[1:]
         L = np.sqrt(np.sum(ax * ax, axis=0))
@@ -106,7 +107,7 @@ def rk3_step(grid, scheme, mon, Ucurv, J, x, dt=None, details=False, xdot=None, 
             return dict(U=Ucurv, J=J, x=x, xdot=xdot, dt=dt, ok=ok, dtau=dtau, failed_stage=s)
         xs = x + coef[s] * dt * xdot
         met = mt.metrics(grid, xs, xdot, scheme.order_p)
-        L, LJ, info = rs.residual(grid, scheme, pad_solution(grid, P), met, details=True,
+        L, LJ, info = rs.residual(grid, scheme, pad_solution(grid, P, scheme.order_p), met, details=True,
                                   Y_fixed=None if Y_fixed is None else Y_fixed[s])
         Ys.append({k: info[k]["Y"] for k in info})
         if s == 0:

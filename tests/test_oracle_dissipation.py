@@ -305,3 +305,70 @@ def test_rmhd_group_decisions_stable_under_rounding(case):
         assert np.max(np.abs(dU1 - dU0).reshape(dU0.shape[0], -1).max(axis=1) / scale) < 1e-12
     else:
         assert min(gaps) == 0.0        # exactly degenerate groups are present
+
+
+# ---------------------------------------------------------------------------
+# WENO7 (w = 2p - 1 for p = 4) from the WENO-JS definition: the generic
+# construction must reproduce the published WENO5 and WENO3 closed forms, and
+# WENO7 must show its design properties
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("r,closed", [(3, "weno5_minus"), (2, "weno3_minus")])
+def test_weno_definition_reproduces_published_weno5_and_weno3(r, closed):
+    rng = np.random.default_rng(40 + r)
+    v = rng.normal(size=(2 * r - 1, 2000)) * rng.uniform(0.01, 10, size=2000)
+    for eps in (1e-6, 1e-2, 1e30):
+        a = ds.weno_js_minus(list(v), eps)
+        b = getattr(ds, closed)(*v, eps)
+        np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-13 * np.max(np.abs(v)))
+
+
+def test_weno7_published_tables():
+    # Balsara and Shu (2000): linear weights and candidate coefficients
+    from fractions import Fraction as Fr
+    c, B, d = ds.weno_js_tables(4)
+    assert d == [Fr(1, 35), Fr(12, 35), Fr(18, 35), Fr(4, 35)]
+    assert c[0] == [Fr(-3, 12), Fr(13, 12), Fr(-23, 12), Fr(25, 12)]
+    assert c[3] == [Fr(3, 12), Fr(13, 12), Fr(-5, 12), Fr(1, 12)]
+    # the indicator of the first candidate: 240 beta_0 = v0 (547 v0 - 3882 v1 + 4642 v2 - 1854 v3)
+    # + v1 (7043 v1 - 17246 v2 + 7042 v3) + v2 (11003 v2 - 9402 v3) + 2107 v3^2
+    Q = [[240 * x for x in row] for row in B[0]]
+    assert [Q[0][0], 2 * Q[0][1], 2 * Q[0][2], 2 * Q[0][3]] == [547, -3882, 4642, -1854]
+    assert [Q[1][1], 2 * Q[1][2], 2 * Q[1][3], Q[2][2], 2 * Q[2][3], Q[3][3]] == [7043, -17246, 7042, 11003, -9402, 2107]
+
+
+def test_weno7_linear_weights_exact_for_degree_six():
+    rng = np.random.default_rng(5)
+    x = np.arange(-3, 5) * 1.0
+    for deg in range(8):
+        c = rng.normal(size=deg + 1)
+        Hc = np.polyint(c)
+        v = np.polyval(Hc, x + 0.5) - np.polyval(Hc, x - 0.5)      # cell averages of c
+        vm = ds.weno_minus(list(v[0:7]), 1e30)
+        vp = ds.weno_minus(list(v[7:0:-1]), 1e30)
+        exact = np.polyval(c, 0.5)
+        if deg <= 6:
+            assert abs(vm - exact) < 1e-11 * (1 + abs(exact))
+            assert abs(vp - exact) < 1e-11 * (1 + abs(exact))
+        w = np.polyval(c, x)                                         # point samples
+        jm = ds.weno_minus(list(w[0:7]), 1e30)
+        jp = ds.weno_minus(list(w[7:0:-1]), 1e30)
+        if deg <= 6:
+            assert abs(jp - jm) < 1e-11 * (1 + np.max(np.abs(w)))
+        else:
+            assert abs(jp - jm) > 1e-6
+
+
+def test_weno7_jump_seventh_order_on_smooth_data():
+    # (JS weights with eps = 1e-6 cost some accuracy near the extrema on coarse
+    # meshes: rates 5.0, 6.1, 6.4, 7.2 from 10 to 160 points per period)
+    errs = []
+    for n in (40, 80, 160):
+        h = 1.0 / n
+        x = (np.arange(-3, 5) * h)[:, None] + np.linspace(0, 1, 50)[None, :]
+        v = np.sin(2 * np.pi * x) + 0.3 * np.cos(6 * np.pi * x)
+        vm = ds.weno_minus(list(v[0:7]), 1e-6)
+        vp = ds.weno_minus(list(v[7:0:-1]), 1e-6)
+        errs.append(np.max(np.abs(vp - vm)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] > 6.8, (errs, rates)
