@@ -18,7 +18,7 @@ The same K steps are timed in the FP32-mixed form (scheme.mixed = 1) and the
 relative L1 difference of the final states (mixed vs FP64) is reported per
 conserved component under "mixed".  "cpu_baseline" is the oracle (numpy,
 limited to one thread) timed on one step of the same blast recipe at a small
-size (32^3 by default); the GPU FP64 and mixed steps of that sample are compared
+size (40^3 by default); the GPU FP64 and mixed steps of that sample are compared
 with the oracle's step.  The other workloads (advected sine, quadrant seeds 0-3,
 RMHD rotor, the RMHD adjoint configuration) are reported as extra objects.
 
@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=None,
                     help="seed of the workload (default: 0 for the 3D blast, 2 for the quadrant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=32,
+    ap.add_argument("--cpu-n", type=int, default=40,
                     help="size n^3 of the blast sample the oracle is timed on (cpu_baseline)")
     ap.add_argument("--residual-reps", type=int, default=20)
     ap.add_argument("--adjoint-steps", type=int, default=10)

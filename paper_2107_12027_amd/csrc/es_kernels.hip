@@ -352,6 +352,105 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
     }
 }
 
+// The same metrics marching along xi_3: each thread owns one (i, j) column of the
+// padded box and a run of kz consecutive planes.  The products differenced along
+// xi_3 (Pi_{1,.} for J dxi_1/dx_., Pi_{0,.} for J dxi_2/dx_.) stay in a register
+// window of 2H + 1 planes, so each is read once per plane instead of 2H times;
+// the differences within a plane read their neighbours through L1/L2.  Columns
+// are taken in XCD-contiguous block ranges (x fastest, then y, then the run), so
+// the rows that a block's y-differences reach are read through one L2.
+template <int H>
+__global__ void __launch_bounds__(256) k_metrics3d_march(GridDev g, const double* __restrict__ ve,
+                                                         const double* __restrict__ pi,
+                                                         double* __restrict__ met, int kz) {
+    const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+    const int nb = gx * gy * (int)gridDim.z;
+    const int lb = xcd_block((int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x), nb);
+    const int bx = lb % gx, by = (lb / gx) % gy, bz = lb / (gx * gy);
+    const int i = -NG + bx * BX + (int)threadIdx.x;
+    const int j = -NG + by * BY + (int)threadIdx.y;
+    if (i >= g.n[0] + NG || j >= g.n[1] + NG) return;
+    const int kb = -NG + bz * kz;
+    const int ke = min(kb + kz, g.n[2] + NG);
+    const long long EN = g.enodes, P = g.pnodes;
+    const long long sx = 1, sy = g.E[0], sz = (long long)g.E[0] * g.E[1];
+    double a[H + 1];
+#pragma unroll
+    for (int n = 1; n <= H; ++n) a[n] = 0.5 * alpha_pn(g.p, n);
+    const double c01 = 1.0 / (g.dxi[1] * g.dxi[2]), c20 = 1.0 / (g.dxi[2] * g.dxi[0]),
+                 c12 = 1.0 / (g.dxi[0] * g.dxi[1]);
+    const double* p0 = pi;              // Pi_{0, jj} at comps 0..2
+    const double* p1 = pi + 3 * EN;     // Pi_{1, jj} at comps 3..5
+    const double* p2 = pi + 6 * EN;     // Pi_{2, jj} at comps 6..8
+    // window of the xi_3-differenced products at planes k - H .. k + H
+    double w0[2 * H + 1][3], w1[2 * H + 1][3];
+    long long e = eidx(g, i, j, kb);
+#pragma unroll
+    for (int q = 0; q < 2 * H; ++q) {
+        const long long eq = e + (long long)(q - H) * sz;
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            w0[q][jj] = p0[jj * EN + eq];
+            w1[q][jj] = p1[jj * EN + eq];
+        }
+    }
+    long long t = pidx(g, i, j, kb);
+    const long long tz = (long long)g.P[0] * g.P[1];
+    for (int k = kb; k < ke; ++k, e += sz, t += tz) {
+        const long long en = e + (long long)H * sz;
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            w0[2 * H][jj] = p0[jj * EN + en];
+            w1[2 * H][jj] = p1[jj * EN + en];
+        }
+        double m[3][3];
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            double ta0 = 0.0, tb0 = 0.0, ta1 = 0.0, tb1 = 0.0, ta2 = 0.0, tb2 = 0.0;
+            const double* q0 = p0 + jj * EN + e;
+            const double* q1 = p1 + jj * EN + e;
+            const double* q2 = p2 + jj * EN + e;
+#pragma unroll
+            for (int n = 1; n <= H; ++n) {
+                // row 0 (k1 = 1, k2 = 2): Pi_{1,jj} along xi_3 minus Pi_{2,jj} along xi_2
+                ta0 += a[n] * (w1[H + n][jj] - w1[H - n][jj]);
+                tb0 += a[n] * (q2[n * sy] - q2[-n * sy]);
+                // row 1 (k1 = 2, k2 = 0): Pi_{2,jj} along xi_1 minus Pi_{0,jj} along xi_3
+                ta1 += a[n] * (q2[n * sx] - q2[-n * sx]);
+                tb1 += a[n] * (w0[H + n][jj] - w0[H - n][jj]);
+                // row 2 (k1 = 0, k2 = 1): Pi_{0,jj} along xi_2 minus Pi_{1,jj} along xi_1
+                ta2 += a[n] * (q0[n * sy] - q0[-n * sy]);
+                tb2 += a[n] * (q1[n * sx] - q1[-n * sx]);
+            }
+            m[0][jj] = (ta0 - tb0) * c01;
+            m[1][jj] = (ta1 - tb1) * c20;
+            m[2][jj] = (ta2 - tb2) * c12;
+        }
+        double v[3] = {0.0, 0.0, 0.0};
+        if (ve != nullptr) {
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) v[jj] = ve[jj * EN + e];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            double at = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) at -= v[jj] * m[kk][jj];
+            met[(kk * 4) * P + t] = at;
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) met[(kk * 4 + 1 + jj) * P + t] = m[kk][jj];
+        }
+#pragma unroll
+        for (int q = 0; q < 2 * H; ++q) {
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+                w0[q][jj] = w0[q + 1][jj];
+                w1[q][jj] = w1[q + 1][jj];
+            }
+        }
+    }
+}
+
 // Temporal metrics J dxi_k/dt = -sum_j xdot_j (J dxi_k/dx_j) of a mesh whose
 // spatial metrics are already in met (padded nodes; the mesh velocity extended
 // as in k_mesh_extend): stage 0 of a 3D step, whose mesh is x^n.
@@ -1481,6 +1580,9 @@ hipError_t launch_combine_con2prim(const es_ctx* c, int stage, const double* U0,
 
 bool metrics_stages_batched(const es_ctx* c) { return c->g.dim == 2; }
 
+// planes per thread of the marching 3D metric kernel
+constexpr int KZ_MARCH = 12;
+
 hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double* xdot,
                                  const double* dt_dev, double* met0, double* met1, double* met2,
                                  hipStream_t s) {
@@ -1509,7 +1611,13 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
     } else {
         k_mesh_extend<3><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve);
         k_cmm_products<<<ge, box_block(), 0, s>>>(g, c->xe, c->pi);
-        k_metrics3d<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, c->xe, ve, c->pi, met, J0);
+        if (J0 != nullptr) {
+            k_metrics3d<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, c->xe, ve, c->pi, met, J0);
+        } else {
+            const dim3 gm((unsigned)((g.P[0] + BX - 1) / BX), (unsigned)((g.P[1] + BY - 1) / BY),
+                          (unsigned)((g.P[2] + KZ_MARCH - 1) / KZ_MARCH));
+            k_metrics3d_march<NG><<<gm, box_block(), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
+        }
     }
     return hipGetLastError();
 }
