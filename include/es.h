@@ -17,9 +17,11 @@
  * Layout.  All fields are float64, component-major structure-of-arrays:
  *   a[c * nodes + node].  Interior node fields ("interior", nodes = n0*n1*n2)
  *   index node = (k*n1 + j)*n0 + i with i fastest along xi_1.  Padded fields
- *   ("padded") cover the box grown by NG = 3 ghost layers on each side of every
- *   active axis: P0 = n0+6, P1 = n1+6, P2 = n2+6 (3D) or 1 (2D), node =
- *   ((k+g)*P1 + (j+3))*P0 + (i+3) with g = 3 in 3D and 0 in 2D.
+ *   ("padded") cover the box grown by ng ghost layers on each side of every
+ *   active axis, ng = es_ghost_layers() = 3 for p = 2 and p = 3 and 4 for p = 4
+ *   (the 2p-th order stencils reach p nodes past an edge): P0 = n0+2ng,
+ *   P1 = n1+2ng, P2 = n2+2ng (3D) or 1 (2D), node = ((k+g)*P1 + (j+ng))*P0 + (i+ng)
+ *   with g = ng in 3D and 0 in 2D.
  * Variables.  m = es_nvars(): 2D RHD (D, m1, m2, E); 3D RHD (D, m1, m2, m3, E);
  *   RMHD (D, m1, m2, m3, E, B1, B2, B3) (eq. RMHDdiv2).  Ucurv = J U (eq. RMHDCurv).
  *   Primitive interior input (es_prim2con): (rho, u_1..u_nu, p[, B1, B2, B3])
@@ -78,8 +80,10 @@ typedef struct {
     int phys;           /* ES_RHD / ES_RMHD */
     double gamma;       /* adiabatic index of the ideal EOS (eq. EOS) */
     int order_p;        /* p of the 2p-th order EC flux and metrics with WENO of order
-                           2p - 1 (Section 4): p = 3 or p = 2 (RHD and RMHD, the
-                           adjoint entry points included); others give
+                           2p - 1 (Section 4): p = 2, 3 or 4 (RHD and RMHD, FP64 and
+                           FP32-mixed; the adjoint entry points take p = 2 and 3 and
+                           give ES_EUNSUPPORTED for p = 4); outflow axes need at
+                           least 2 ng + 1 nodes (ES_EINVAL); other p give
                            ES_EUNSUPPORTED */
     int dissipation;    /* 0: entropy conservative, 1: entropy stable (WENO-(2p-1)) */
     int mixed;          /* 0: FP64 throughout.  1: FP32-mixed residual: the two-point
@@ -124,6 +128,7 @@ size_t es_nprim(const es_ctx* ctx);          /* m + 2 */
 size_t es_nmet(const es_ctx* ctx);           /* d (d + 1) */
 size_t es_nodes(const es_ctx* ctx);          /* interior nodes */
 size_t es_padded_nodes(const es_ctx* ctx);   /* padded nodes */
+size_t es_ghost_layers(const es_ctx* ctx);   /* ng of the padded layout: 3 (p <= 3) or 4 (p = 4) */
 
 /* Ucurv = J U(prim) on the interior (eq. RMHDdiv2, eq. RMHDCurv).
  * prim: interior, m comps (rho, u, p[, B]); J: interior; Ucurv: interior, m comps. */
@@ -206,7 +211,7 @@ es_status es_rk3_step(es_ctx* ctx, double* Ucurv, double* J, double* x, double* 
 es_status es_rk3_step_moving(es_ctx* ctx, double* Ucurv, double* J, double* x, const double* xdot,
                              double* dt_dev, const double* fixed_dt_dev, hipStream_t stream);
 
-/* Adjoint (FP64 form only, p = 3 or p = 2; ES_EUNSUPPORTED for scheme.mixed = 1).
+/* Adjoint (FP64 form only, p = 3 or p = 2; ES_EUNSUPPORTED for scheme.mixed = 1 or p = 4).
  * For RMHD the ES dissipation's face eigen-structure (the columns of R and
  * lambda^) is held at its forward value as well: the pair fluxes, the
  * Godunov-Powell source and the projections/WENO/accumulation of the dissipation

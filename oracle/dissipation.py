@@ -310,7 +310,8 @@ def weno_js_tables(r):
         a quadratic form v_{S_k}^T B_k v_{S_k};
       * linear weights d_k with sum_k d_k q_k = the value of the degree 2r-2 polynomial
         with the averages of all 2r-1 cells.
-    Returns (c, B, d): c (r, r), B (r, r, r), d (r,) as Fractions."""
+    Returns (c, B, d): c (r, r), B (r, r, r), d (r,) as Fractions.  (For evaluation
+    see weno_js_squares: B_k written as a weighted sum of squares.)"""
     from fractions import Fraction
 
     def cell_avg_row(l, deg):
@@ -368,25 +369,74 @@ def weno_js_tables(r):
     return c, B, d
 
 
+def weno_js_squares(r):
+    """beta_k of weno_js_tables as a weighted sum of squares, beta_k = sum_m D_m (w_km . v)^2:
+    the integrals of the squared derivatives are a positive definite quadratic form
+    G in the non-constant Taylor coefficients (c_1..c_{r-1}) of p_k at the cell
+    centre, G = L diag(D) L^T (exact LDL^T), and w_km = (L^T)_m (those coefficients as
+    linear forms in the stencil values).  Each w_km annihilates constants, so the
+    squares are of differences of v: this evaluation has none of the cancellation of
+    the expanded quadratic form, whose terms are larger than beta by the square of
+    the data over its variation.  Returns (D (r-1,), W (r, r-1, r)) as Fractions."""
+    from fractions import Fraction
+    half = Fraction(1, 2)
+    deg = r - 1
+
+    def mono_int(e):       # int_{-1/2}^{1/2} x^e dx
+        return Fraction(0) if e % 2 else 2 * half ** (e + 1) / (e + 1)
+
+    # G[a][b] over monomials a, b = 1..deg: sum_l int (x^a)^(l) (x^b)^(l)
+    def falling(a, l):
+        out = 1
+        for t in range(l):
+            out *= a - t
+        return out
+    G = [[sum(falling(a, l) * falling(b, l) * mono_int(a + b - 2 * l)
+              for l in range(1, deg + 1) if l <= a and l <= b)
+          for b in range(1, deg + 1)] for a in range(1, deg + 1)]
+    # LDL^T
+    n = deg
+    L = [[Fraction(int(i == j)) for j in range(n)] for i in range(n)]
+    D = [Fraction(0)] * n
+    for j in range(n):
+        D[j] = G[j][j] - sum(L[j][t] ** 2 * D[t] for t in range(j))
+        for i in range(j + 1, n):
+            L[i][j] = (G[i][j] - sum(L[i][t] * L[j][t] * D[t] for t in range(j))) / D[j]
+    W = []
+    for k in range(r):
+        cells = list(range(-r + 1 + k, k + 1))
+        A = [[(Fraction(2 * l + 1, 2) ** (m + 1) - Fraction(2 * l - 1, 2) ** (m + 1)) / (m + 1)
+              for m in range(r)] for l in cells]
+        # rows 1..deg of A^{-1}: the Taylor coefficients c_1..c_deg as linear forms
+        inv_cols = [_frac_solve(A, [Fraction(int(i == j)) for i in range(r)]) for j in range(r)]
+        Crow = [[inv_cols[j][m] for j in range(r)] for m in range(1, r)]
+        Wk = [[sum(L[t][mm] * Crow[t][j] for t in range(n)) for j in range(r)] for mm in range(n)]
+        W.append(Wk)
+    return D, W
+
+
 _WENO_TABLES = {}
 
 
 def weno_js_minus(vs, eps):
     """The WENO-JS value at i+1/2 (order 2r - 1) from the 2r - 1 values v_{i-r+1..i+r-1},
-    with the tables of weno_js_tables: nonlinear weights d_k / (eps + beta_k)^2."""
+    with the tables of weno_js_tables (beta_k by weno_js_squares): nonlinear weights
+    d_k / (eps + beta_k)^2."""
     r = (len(vs) + 1) // 2
     if r not in _WENO_TABLES:
-        c, B, d = weno_js_tables(r)
+        c, _, d = weno_js_tables(r)
+        Dm, W = weno_js_squares(r)
         _WENO_TABLES[r] = (np.array([[float(v) for v in row] for row in c]),
-                           np.array([[[float(v) for v in row] for row in Q] for Q in B]),
+                           np.array([float(v) for v in Dm]),
+                           np.array([[[float(v) for v in row] for row in Wk] for Wk in W]),
                            np.array([float(v) for v in d]))
-    c, B, d = _WENO_TABLES[r]
+    c, Dm, W, d = _WENO_TABLES[r]
     num = 0.0
     den = 0.0
     for k in range(r):
         S = vs[k:k + r]
         q = sum(c[k][j] * S[j] for j in range(r))
-        beta = sum(B[k][a][b] * S[a] * S[b] for a in range(r) for b in range(r))
+        beta = sum(Dm[m] * sum(W[k][m][j] * S[j] for j in range(r)) ** 2 for m in range(r - 1))
         alpha = d[k] / (eps + beta) ** 2
         num = num + alpha * q
         den = den + alpha

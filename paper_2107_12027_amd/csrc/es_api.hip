@@ -29,7 +29,8 @@ bool valid_grid(const es_grid* g) {
         }
         if (g->bc[k] != ES_BC_PERIODIC && g->bc[k] != ES_BC_OUTFLOW) return false;
         if (!(g->dxi[k] > 0.0)) return false;
-        // the mesh extension by reflection reaches 2*NG = 6 nodes past an edge
+        // the mesh extension by reflection reaches 2 ng nodes past an edge (6 for
+        // p <= 3; es_create asks for 9 when p = 4)
         if (g->bc[k] == ES_BC_OUTFLOW && g->n[k] < 7) return false;
         if (g->bc[k] == ES_BC_PERIODIC && (g->n[k] < 1 || !(g->period[k] > 0.0))) return false;
         if (g->n[k] > (1 << 24)) return false;
@@ -51,16 +52,17 @@ void describe(es_ctx* c, const es_grid* grid, const es_scheme* scheme, const es_
     if (monitor != nullptr) c->monitor = *monitor;
     GridDev& g = c->g;
     g.dim = grid->dim;
+    g.ng = es::ghost_layers(scheme->order_p);
     for (int k = 0; k < 3; ++k) {
         g.n[k] = grid->n[k];
         g.bc[k] = grid->bc[k];
         g.dxi[k] = grid->dxi[k];
         g.period[k] = grid->period[k];
-        g.P[k] = (k < grid->dim) ? grid->n[k] + 2 * es::NG : 1;
+        g.P[k] = (k < grid->dim) ? grid->n[k] + 2 * g.ng : 1;
     }
-    g.g2 = grid->dim == 3 ? es::NG : 0;
-    for (int k = 0; k < 3; ++k) g.E[k] = (k < grid->dim) ? grid->n[k] + 4 * es::NG : 1;
-    g.g6 = grid->dim == 3 ? 2 * es::NG : 0;
+    g.g2 = grid->dim == 3 ? g.ng : 0;
+    for (int k = 0; k < 3; ++k) g.E[k] = (k < grid->dim) ? grid->n[k] + 4 * g.ng : 1;
+    g.g6 = grid->dim == 3 ? 2 * g.ng : 0;
     g.nodes = (long long)g.n[0] * g.n[1] * g.n[2];
     g.pnodes = (long long)g.P[0] * g.P[1] * g.P[2];
     g.enodes = (long long)g.E[0] * g.E[1] * g.E[2];
@@ -139,8 +141,10 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
             !(monitor->alpha2 >= 0.0))
             return ES_EINVAL;
     }
-    // kernels of this build: p = 3 and p = 2 (RHD and RMHD, FP64 or FP32-mixed)
-    if (scheme->order_p != 3 && scheme->order_p != 2) return ES_EUNSUPPORTED;
+    // kernels of this build: p = 2, 3 and 4 (RHD and RMHD, FP64 or FP32-mixed)
+    if (scheme->order_p != 3 && scheme->order_p != 2 && scheme->order_p != 4) return ES_EUNSUPPORTED;
+    for (int k = 0; k < grid->dim; ++k)
+        if (grid->bc[k] == ES_BC_OUTFLOW && grid->n[k] < 2 * es::ghost_layers(scheme->order_p) + 1) return ES_EINVAL;
 
     es_ctx* c = new (std::nothrow) es_ctx();
     if (c == nullptr) return ES_EHIP;
@@ -208,6 +212,7 @@ size_t es_nprim(const es_ctx* c) { return c ? (size_t)c->nprim : 0; }
 size_t es_nmet(const es_ctx* c) { return c ? (size_t)c->nmet : 0; }
 size_t es_nodes(const es_ctx* c) { return c ? (size_t)c->g.nodes : 0; }
 size_t es_padded_nodes(const es_ctx* c) { return c ? (size_t)c->g.pnodes : 0; }
+size_t es_ghost_layers(const es_ctx* c) { return c ? (size_t)c->g.ng : 0; }
 
 es_status es_prim2con(es_ctx* c, const double* prim, const double* J, double* U, hipStream_t s) {
     if (c == nullptr || prim == nullptr || J == nullptr || U == nullptr) return ES_EINVAL;
@@ -252,6 +257,7 @@ es_status es_cfl_noalloc(const es_grid* grid, const es_scheme* scheme, const dou
     if (!valid_grid(grid)) return ES_EINVAL;
     if (scheme->phys != ES_RHD && scheme->phys != ES_RMHD) return ES_EINVAL;
     if (!(scheme->gamma > 1.0 && scheme->gamma <= 2.0) || !(scheme->cfl > 0.0)) return ES_EINVAL;
+    if (scheme->order_p != 2 && scheme->order_p != 3 && scheme->order_p != 4) return ES_EINVAL;
     if (es_cfl_static_blocks(grid) > (size_t)ES_CFL_STATIC_MAX_BLOCKS) return ES_ETOOLARGE;
     double* red = nullptr;
     ES_TRY(scratch_address(&red));
@@ -387,7 +393,7 @@ es_status es_rk3_step_moving(es_ctx* c, double* U, double* J, double* x, const d
     return graph_step(c, U, J, x, nullptr, dt_dev, fixed_dt_dev, xdot, s);
 }
 
-// the adjoint covers the FP64 form, p = 2 and p = 3
+// the adjoint covers the FP64 form, p = 2 and p = 3 (the ghost width of p <= 3)
 static bool adjoint_supported(const es_ctx* c) {
     return c->scheme.mixed == 0 && (c->scheme.order_p == 3 || c->scheme.order_p == 2);
 }

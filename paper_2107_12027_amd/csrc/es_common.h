@@ -9,18 +9,33 @@
 
 namespace es {
 
-constexpr int NG = 3;            // ghost layers = p for p = 3 (stencil i-2..i+3)
+// Ghost layers of the padded box: the 2p-th order stencils reach p nodes past an
+// edge (the EC pairs (i, i+n), n <= p; the metrics' central differences; WENO of
+// order 2p - 1 on nodes i-p+1..i+p), so ng = 3 for p = 2 and p = 3 (one layout)
+// and ng = 4 for p = 4.  NG_MAX sizes the fixed-size staging arrays.
+constexpr int NG = 3;
+constexpr int NG_MAX = 4;
 constexpr int RED_BLOCK = 256;   // threads per block of the reduction kernels
+
+__device__ __host__ constexpr int ghost_layers(int p) { return p > NG ? p : NG; }
+
+// Line segments of the residual kernels (one wavefront each): ng = ghost_layers(p)
+// halo nodes on each side of 64 - ng owned nodes (61 for p <= 3, 60 for p = 4), so
+// that every owned node's stencil lies within the 64 + ng loaded slots.
+__host__ __device__ constexpr int seg_nodes(int po) { return 64 - ghost_layers(po); }
+__host__ __device__ constexpr int seg_loads(int po) { return seg_nodes(po) + 2 * ghost_layers(po); }
 
 // 2p-th order coefficients alpha_{3,n} of eq. HOCoeff: (3/2, -3/10, 1/30).
 __device__ __host__ constexpr double alpha3(int n) {
-    return n == 1 ? 1.5 : (n == 2 ? -0.3 : 1.0 / 30.0);
+    return n == 1 ? 1.5 : (n == 2 ? -0.3 : (n == 3 ? 1.0 / 30.0 : 0.0));
 }
 
-// alpha_{p,n} of eq. HOCoeff for p = 2 (4/3, -1/6) and p = 3, zero for n > p (so a
-// sum over n = 1..3 is the p-term sum, exactly: the extra terms add zero).
+// alpha_{p,n} of eq. HOCoeff for p = 2 (4/3, -1/6), p = 3 and p = 4 (8/5, -2/5, 8/105,
+// -1/140), zero for n > p.
 __device__ __host__ constexpr double alpha_pn(int p, int n) {
-    return p == 2 ? (n == 1 ? 4.0 / 3.0 : (n == 2 ? -1.0 / 6.0 : 0.0)) : alpha3(n);
+    return p == 2   ? (n == 1 ? 4.0 / 3.0 : (n == 2 ? -1.0 / 6.0 : 0.0))
+           : p == 4 ? (n == 1 ? 1.6 : (n == 2 ? -0.4 : (n == 3 ? 8.0 / 105.0 : (n == 4 ? -1.0 / 140.0 : 0.0))))
+                    : alpha3(n);
 }
 
 struct GridDev {
@@ -29,18 +44,19 @@ struct GridDev {
     int bc[3];
     double dxi[3];
     double period[3];
-    int P[3];               // padded extents (n+6, or 1 for the unused 3rd axis in 2D)
-    int g2;                 // ghost offset of the third axis (3 in 3D, 0 in 2D)
-    int E[3];               // mesh-extension box extents (n+12, or 1)
-    int g6;                 // extension offset of the third axis (6 in 3D, 0 in 2D)
+    int P[3];               // padded extents (n + 2 ng, or 1 for the unused 3rd axis in 2D)
+    int g2;                 // ghost offset of the third axis (ng in 3D, 0 in 2D)
+    int E[3];               // mesh-extension box extents (n + 4 ng, or 1)
+    int g6;                 // extension offset of the third axis (2 ng in 3D, 0 in 2D)
     long long nodes;        // interior nodes
     long long pnodes;       // padded nodes
     long long enodes;       // mesh-extension box nodes
-    int p;                  // order parameter: 2p-th order EC flux and metrics (2 or 3)
+    int p;                  // order parameter: 2p-th order EC flux and metrics (2, 3 or 4)
+    int ng;                 // ghost layers, ghost_layers(p)
 };
 
 __device__ __forceinline__ long long pidx(const GridDev& g, int i, int j, int k) {
-    return ((long long)(k + g.g2) * g.P[1] + (j + NG)) * g.P[0] + (i + NG);
+    return ((long long)(k + g.g2) * g.P[1] + (j + g.ng)) * g.P[0] + (i + g.ng);
 }
 
 __device__ __forceinline__ long long iidx(const GridDev& g, int i, int j, int k) {
@@ -87,7 +103,7 @@ __device__ __forceinline__ AxisTerms axis_terms(int i, int n, int bc) {
 }
 
 // Value of component c of the (stage) mesh x + cdt * xd at index (i, j, k),
-// which may lie up to 2*NG outside the interior box.  With shift = false the
+// which may lie up to 2 ng outside the interior box.  With shift = false the
 // periodic coordinate shift is omitted (mesh velocity).
 __device__ __forceinline__ double mesh_value(const GridDev& g, const double* __restrict__ x,
                                              const double* __restrict__ xd, double cdt, int c,

@@ -20,7 +20,7 @@ namespace {
 
 // index in the mesh-extension box (6 layers beyond the interior on active axes)
 __device__ __forceinline__ long long eidx(const GridDev& g, int i, int j, int k) {
-    return ((long long)(k + g.g6) * g.E[1] + (j + 2 * NG)) * g.E[0] + (i + 2 * NG);
+    return ((long long)(k + g.g6) * g.E[1] + (j + 2 * g.ng)) * g.E[0] + (i + 2 * g.ng);
 }
 
 // ---------------------------------------------------------------------------
@@ -75,7 +75,7 @@ __global__ void k_con2prim_rhd(GridDev g, double G, StateSrc ss, double* prim, i
                                unsigned long long* __restrict__ fail) {
     constexpr int M = DIM + 2;
     int i, j, k;
-    if (!box_ijk(-NG, -NG, -g.g2, g.P[0], g.P[1], i, j, k)) return;
+    if (!box_ijk(-g.ng, -g.ng, -g.g2, g.P[0], g.P[1], i, j, k)) return;
     const long long t = pidx(g, i, j, k);
     const int si = map_sol(i, g.n[0], g.bc[0]);
     const int sj = map_sol(j, g.n[1], g.bc[1]);
@@ -125,7 +125,7 @@ __global__ void k_mesh_extend(GridDev g, const double* __restrict__ x, const dou
                               const double* __restrict__ dt_dev, double coef, double* __restrict__ xe,
                               double* __restrict__ ve) {
     int i, j, k;
-    if (!box_ijk_xcd(-2 * NG, -2 * NG, -g.g6, g.E[0], g.E[1], i, j, k)) return;
+    if (!box_ijk_xcd(-2 * g.ng, -2 * g.ng, -g.g6, g.E[0], g.E[1], i, j, k)) return;
     const long long t = eidx(g, i, j, k);
     const double cdt = dt_dev != nullptr ? coef * dt_dev[0] : 0.0;
     const double* xs = dt_dev != nullptr ? xd : nullptr;
@@ -142,7 +142,7 @@ __global__ void k_mesh_extend(GridDev g, const double* __restrict__ x, const dou
 // differences of eq. SCLCoeff (2D form of Appendix B with 1/Delta xi) from
 // there; the mesh velocity is read at the node.
 constexpr int MTX = 64, MTY = 4, MBY = 4;
-constexpr int MRX = MTX + 2 * NG, MRY = MTY + 2 * NG;
+constexpr int MRX = MTX + 2 * NG_MAX, MRY = MTY + 2 * NG_MAX;
 
 __global__ void __launch_bounds__(256) k_metrics2d_fused(GridDev g, const double* __restrict__ x,
                                                          const double* __restrict__ xd,
@@ -150,32 +150,33 @@ __global__ void __launch_bounds__(256) k_metrics2d_fused(GridDev g, const double
                                                          double* __restrict__ met, double* __restrict__ J0) {
     __shared__ double xs[2][MRY][MRX];
     const int tid = threadIdx.y * MTX + threadIdx.x;
-    const int i0 = -NG + (int)blockIdx.x * MTX, j0 = -NG + (int)blockIdx.y * MTY;
+    const int i0 = -g.ng + (int)blockIdx.x * MTX, j0 = -g.ng + (int)blockIdx.y * MTY;
     const double cdt = dt_dev != nullptr ? coef * dt_dev[0] : 0.0;
     const double* xsd = dt_dev != nullptr ? xd : nullptr;
     for (int q = tid; q < MRX * MRY; q += MTX * MBY) {
         const int ri = q % MRX, rj = q / MRX;
-        const int i = i0 - NG + ri, j = j0 - NG + rj;
+        const int i = i0 - g.ng + ri, j = j0 - g.ng + rj;
         // positions beyond the extension box are never needed by padded nodes
-        const bool ok = i >= -2 * NG && i < g.n[0] + 2 * NG && j >= -2 * NG && j < g.n[1] + 2 * NG;
+        const bool ok = i >= -2 * g.ng && i < g.n[0] + 2 * g.ng && j >= -2 * g.ng && j < g.n[1] + 2 * g.ng;
         xs[0][rj][ri] = ok ? mesh_value(g, x, xsd, cdt, 0, i, j, 0, true) : 0.0;
         xs[1][rj][ri] = ok ? mesh_value(g, x, xsd, cdt, 1, i, j, 0, true) : 0.0;
     }
     __syncthreads();
     const long long P = g.pnodes;
     const int i = i0 + (int)threadIdx.x;
-    if (i >= g.n[0] + NG) return;
-    const int ri = threadIdx.x + NG;
+    if (i >= g.n[0] + g.ng) return;
+    const int ri = threadIdx.x + g.ng;
     for (int row = threadIdx.y; row < MTY; row += MBY) {
         const int j = j0 + row;
-        if (j >= g.n[1] + NG) break;
-        const int rj = row + NG;
+        if (j >= g.n[1] + g.ng) break;
+        const int rj = row + g.ng;
         double dxi[2], deta[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             double s = 0.0, r = 0.0;
 #pragma unroll
-            for (int n = 1; n <= 3; ++n) {
+            for (int n = 1; n <= NG_MAX; ++n) {
+                if (n > g.p) break;
                 const double a = 0.5 * alpha_pn(g.p, n);
                 s += a * (xs[c][rj][ri + n] - xs[c][rj][ri - n]);
                 r += a * (xs[c][rj + n][ri] - xs[c][rj - n][ri]);
@@ -221,11 +222,11 @@ __global__ void __launch_bounds__(MTX * MSY) k_metrics2d_stages(GridDev g, const
     __shared__ double xs[2][MRY][MRX];
     __shared__ double vs[2][MRY][MRX];
     const int tid = threadIdx.y * MTX + threadIdx.x;
-    const int i0 = -NG + (int)blockIdx.x * MTX, j0 = -NG + (int)blockIdx.y * MTY;
+    const int i0 = -g.ng + (int)blockIdx.x * MTX, j0 = -g.ng + (int)blockIdx.y * MTY;
     for (int q = tid; q < MRX * MRY; q += MTX * MSY) {
         const int ri = q % MRX, rj = q / MRX;
-        const int i = i0 - NG + ri, j = j0 - NG + rj;
-        const bool ok = i >= -2 * NG && i < g.n[0] + 2 * NG && j >= -2 * NG && j < g.n[1] + 2 * NG;
+        const int i = i0 - g.ng + ri, j = j0 - g.ng + rj;
+        const bool ok = i >= -2 * g.ng && i < g.n[0] + 2 * g.ng && j >= -2 * g.ng && j < g.n[1] + 2 * g.ng;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             xs[c][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, c, i, j, 0, true) : 0.0;
@@ -237,8 +238,8 @@ __global__ void __launch_bounds__(MTX * MSY) k_metrics2d_stages(GridDev g, const
     const int i = i0 + (int)threadIdx.x;
     const int row = (int)threadIdx.y % MTY, st = (int)threadIdx.y / MTY;
     const int j = j0 + row;
-    if (i >= g.n[0] + NG || j >= g.n[1] + NG) return;
-    const int ri = threadIdx.x + NG, rj = row + NG;
+    if (i >= g.n[0] + g.ng || j >= g.n[1] + g.ng) return;
+    const int ri = threadIdx.x + g.ng, rj = row + g.ng;
     const double cdt = (st == 0 ? 0.0 : (st == 1 ? 1.0 : 0.5)) * dt_dev[0];
     const long long t = pidx(g, i, j, 0);
     const double vx = vs[0][rj][ri], vy = vs[1][rj][ri];
@@ -247,7 +248,8 @@ __global__ void __launch_bounds__(MTX * MSY) k_metrics2d_stages(GridDev g, const
     for (int c = 0; c < 2; ++c) {
         double s = 0.0, r = 0.0;
 #pragma unroll
-        for (int n = 1; n <= 3; ++n) {
+        for (int n = 1; n <= NG_MAX; ++n) {
+            if (n > g.p) break;
             const double a = 0.5 * alpha_pn(g.p, n);
             s += a * ((xs[c][rj][ri + n] + cdt * vs[c][rj][ri + n]) - (xs[c][rj][ri - n] + cdt * vs[c][rj][ri - n]));
             r += a * ((xs[c][rj + n][ri] + cdt * vs[c][rj + n][ri]) - (xs[c][rj - n][ri] + cdt * vs[c][rj - n][ri]));
@@ -275,14 +277,14 @@ __global__ void __launch_bounds__(MTX * MSY) k_metrics2d_stages(GridDev g, const
 // 3 layers of the interior (the metric differences never read it elsewhere).
 __global__ void k_cmm_products(GridDev g, const double* __restrict__ xe, double* __restrict__ pi) {
     int i, j, k;
-    if (!box_ijk_xcd(-2 * NG, -2 * NG, -2 * NG, g.E[0], g.E[1], i, j, k)) return;
+    if (!box_ijk_xcd(-2 * g.ng, -2 * g.ng, -2 * g.ng, g.E[0], g.E[1], i, j, k)) return;
     const long long e = eidx(g, i, j, k);
     const long long EN = g.enodes;
     const int c[3] = {i, j, k};
     const long long st[3] = {1, (long long)g.E[0], (long long)g.E[0] * g.E[1]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const bool valid = c[a] >= -NG && c[a] < g.n[a] + NG;
+        const bool valid = c[a] >= -g.ng && c[a] < g.n[a] + g.ng;
 #pragma unroll
         for (int jj = 0; jj < 3; ++jj) {
             const int j1 = (jj + 1) % 3, j2 = (jj + 2) % 3;
@@ -291,7 +293,8 @@ __global__ void k_cmm_products(GridDev g, const double* __restrict__ xe, double*
                 const double* xc = xe + j1 * EN + e;
                 double d = 0.0;
 #pragma unroll
-                for (int n = 1; n <= 3; ++n) d += 0.5 * alpha_pn(g.p, n) * (xc[n * st[a]] - xc[-n * st[a]]);
+                for (int n = 1; n <= NG_MAX; ++n)
+                    if (n <= g.p) d += 0.5 * alpha_pn(g.p, n) * (xc[n * st[a]] - xc[-n * st[a]]);
                 v = d * xe[j2 * EN + e];
             }
             pi[(a * 3 + jj) * EN + e] = v;
@@ -303,7 +306,7 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
                             const double* __restrict__ pi, double* __restrict__ met,
                             double* __restrict__ J0) {
     int i, j, k;
-    if (!box_ijk_xcd(-NG, -NG, -NG, g.P[0], g.P[1], i, j, k)) return;
+    if (!box_ijk_xcd(-g.ng, -g.ng, -g.ng, g.P[0], g.P[1], i, j, k)) return;
     const long long t = pidx(g, i, j, k);
     const long long e = eidx(g, i, j, k);
     const long long EN = g.enodes;
@@ -319,7 +322,8 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
             const double* pb = pi + (k2 * 3 + jj) * EN + e;   // Pi_{k2, j}, differenced along k1
             double ta = 0.0, tb = 0.0;
 #pragma unroll
-            for (int n = 1; n <= 3; ++n) {
+            for (int n = 1; n <= NG_MAX; ++n) {
+                if (n > g.p) break;
                 const double a = 0.5 * alpha_pn(g.p, n);
                 ta += a * (pa[n * st[k2]] - pa[-n * st[k2]]);
                 tb += a * (pb[n * st[k1]] - pb[-n * st[k1]]);
@@ -345,7 +349,8 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
         for (int kk = 0; kk < 3; ++kk) {
             double d = 0.0;
 #pragma unroll
-            for (int n = 1; n <= 3; ++n) d += 0.5 * alpha_pn(g.p, n) * (xe[e + n * st[kk]] - xe[e - n * st[kk]]);
+            for (int n = 1; n <= NG_MAX; ++n)
+                if (n <= g.p) d += 0.5 * alpha_pn(g.p, n) * (xe[e + n * st[kk]] - xe[e - n * st[kk]]);
             Jv += m[kk][0] * d / g.dxi[kk];
         }
         J0[iidx(g, i, j, k)] = Jv;
@@ -367,11 +372,11 @@ __global__ void __launch_bounds__(256) k_metrics3d_march(GridDev g, const double
     const int nb = gx * gy * (int)gridDim.z;
     const int lb = xcd_block((int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x), nb);
     const int bx = lb % gx, by = (lb / gx) % gy, bz = lb / (gx * gy);
-    const int i = -NG + bx * BX + (int)threadIdx.x;
-    const int j = -NG + by * BY + (int)threadIdx.y;
-    if (i >= g.n[0] + NG || j >= g.n[1] + NG) return;
-    const int kb = -NG + bz * kz;
-    const int ke = min(kb + kz, g.n[2] + NG);
+    const int i = -g.ng + bx * BX + (int)threadIdx.x;
+    const int j = -g.ng + by * BY + (int)threadIdx.y;
+    if (i >= g.n[0] + g.ng || j >= g.n[1] + g.ng) return;
+    const int kb = -g.ng + bz * kz;
+    const int ke = min(kb + kz, g.n[2] + g.ng);
     const long long EN = g.enodes, P = g.pnodes;
     const long long sx = 1, sy = g.E[0], sz = (long long)g.E[0] * g.E[1];
     double a[H + 1];
@@ -456,7 +461,7 @@ __global__ void __launch_bounds__(256) k_metrics3d_march(GridDev g, const double
 // as in k_mesh_extend): stage 0 of a 3D step, whose mesh is x^n.
 __global__ void k_temporal_metrics3d(GridDev g, const double* __restrict__ xd, double* __restrict__ met) {
     int i, j, k;
-    if (!box_ijk(-NG, -NG, -NG, g.P[0], g.P[1], i, j, k)) return;
+    if (!box_ijk(-g.ng, -g.ng, -g.ng, g.P[0], g.P[1], i, j, k)) return;
     const long long t = pidx(g, i, j, k);
     const long long P = g.pnodes;
     double v[3];
@@ -474,14 +479,12 @@ __global__ void k_temporal_metrics3d(GridDev g, const double* __restrict__ xd, d
 // ---------------------------------------------------------------------------
 // residual: all direction sweeps in one launch
 // ---------------------------------------------------------------------------
-constexpr int SEG = 61;            // interior nodes per line segment
-constexpr int NLOAD = SEG + 6;     // loaded slots (3-node halo each side)
 constexpr int LINES = 4;           // line segments (wavefronts) per block
 
-template <int DIM>
+template <int DIM, int PO>
 struct ResidualLDS {
     static constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1, NF = 6 + NU + NA;
-    double sd[LINES][NF][NLOAD + 1];
+    double sd[LINES][NF][seg_loads(PO) + 1];
     // 3D: the flux differences of each lane wait here while the face dissipation
     // runs (register pressure)
     double rs[DIM == 3 ? LINES : 1][M + 1][64];
@@ -506,8 +509,9 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
                                                  const double* __restrict__ prim,
                                                  const double* __restrict__ met,
                                                  double* __restrict__ out, int blk, int nseg,
-                                                 long long nlines, ResidualLDS<DIM>& lds) {
+                                                 long long nlines, ResidualLDS<DIM, PO>& lds) {
     constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1;
+    constexpr int NGP = ghost_layers(PO), SEGP = seg_nodes(PO), NLOADP = seg_loads(PO);
     constexpr int F_RHO = 0, F_P = 1, F_BETA = 2, F_W = 3, F_LR = 4, F_LB = 5, F_U = 6,
                   F_A = 6 + NU;
     auto& sd = lds.sd;
@@ -518,8 +522,8 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
     const long long lid = (long long)(blk / nseg) * LINES + line;
     const bool active = lid < nlines;
     const int nAlong = g.n[DIR];
-    const int s0 = seg * SEG;
-    const int s_end = min(s0 + SEG, nAlong);
+    const int s0 = seg * SEGP;
+    const int s_end = min(s0 + SEGP, nAlong);
 
     // transverse coordinates of this line and strides along it
     int ci = 0, cj = 0, ck = 0;
@@ -536,14 +540,14 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
     const long long N = g.nodes;
 
     // ---- load the line segment with its halo into LDS
-    for (int q = lane; q < NLOAD; q += 64) {
-        const int s = s0 - NG + q;
+    for (int q = lane; q < NLOADP; q += 64) {
+        const int s = s0 - NGP + q;
         double rho = 1.0, p = 1.0, lr = 0.0, lb = 0.0, u[NU], a[NA];
 #pragma unroll
         for (int c = 0; c < NU; ++c) u[c] = 0.0;
 #pragma unroll
         for (int c = 0; c < NA; ++c) a[c] = c == 1 ? 1.0 : 0.0;
-        if (active && s < s_end + NG) {
+        if (active && s < s_end + NGP) {
             const long long idx = pbase + (long long)s * pstride;
             rho = prim[idx];
 #pragma unroll
@@ -583,11 +587,11 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
         return nd;
     };
 
-    // ---- two-point fluxes (s, s+n), n = 1..3, owned by the lane of node s, and
+    // ---- two-point fluxes (s, s+n), n = 1..p, owned by the lane of node s, and
     // flux differences R_s = -(1/dxi) sum_n alpha_n [F(s,s+n) - F(s-n,s)]
-    const int s_own = s0 - NG + lane;
+    const int s_own = s0 - NGP + lane;
     const bool valid = active && s_own < s_end;
-    const bool owner = active && lane >= NG && s_own < s_end;
+    const bool owner = active && lane >= NGP && s_own < s_end;
     const double idxi = 1.0 / g.dxi[DIR];
     double R[M + 1];
 #pragma unroll
@@ -613,7 +617,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
                 if (MIXED) pair_flux_rhd_mixed<NU>(G, l, r, al, ar, F, F[M]);
                 else pair_flux_rhd<NU>(G, l, r, al, ar, F, F[M]);
             }
-            // all lanes take part in the shuffle; owners (lane >= 3) read F(s-n, s)
+            // all lanes take part in the shuffle; owners (lane >= ng) read F(s-n, s)
 #pragma unroll
             for (int c = 0; c <= M; ++c) R[c] += alpha_pn(PO, n) * (F[c] - __shfl_up(F[c], n, 64));
             // one pair at a time (interleaving the three raises register pressure)
@@ -636,7 +640,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
         double d[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) d[c] = 0.0;
-        if (active && lane >= 2 && s_own < s_end) {
+        if (active && lane >= NGP - 1 && s_own < s_end) {
             // the stencil states are read from LDS where they are used
             if (MIXED) {
                 // FP32 dissipation from FP32 copies of the stencil states and metrics
@@ -703,7 +707,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                                                       const double* __restrict__ met,
                                                       double* __restrict__ Ld, SweepPlan sw) {
     constexpr int M = DIM + 2;
-    __shared__ ResidualLDS<DIM> lds;
+    __shared__ ResidualLDS<DIM, PO> lds;
     const long long slab = (long long)(M + 1) * g.nodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < sw.nblk[0]) {
@@ -866,23 +870,24 @@ __global__ void __launch_bounds__(MTX * CBY) k_cfl_partial2d_mesh(GridDev g, dou
     double gmx = 0.0;
     if (role == 1 && mon.enabled && inside)
         gmx = monitor_node<2>(g, mon.M, mon.sigma_ln, mon.sqgrad, mon.alpha, prim, mon.w, i, j, 0);
-    for (int q = tid; q < MRX * (MBY + 2 * NG); q += MTX * CBY) {
+    for (int q = tid; q < MRX * (MBY + 2 * g.ng); q += MTX * CBY) {
         const int ri = q % MRX, rj = q / MRX;
-        const int ii = i0 - NG + ri, jj = j0 - NG + rj;
-        const bool ok = ii < g.n[0] + 2 * NG && jj < g.n[1] + 2 * NG;
+        const int ii = i0 - g.ng + ri, jj = j0 - g.ng + rj;
+        const bool ok = ii < g.n[0] + 2 * g.ng && jj < g.n[1] + 2 * g.ng;
         xs[0][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, 0, ii, jj, 0, true) : 0.0;
         xs[1][rj][ri] = ok ? mesh_value(g, x, nullptr, 0.0, 1, ii, jj, 0, true) : 0.0;
     }
     __syncthreads();
     double mx[2] = {0.0, 0.0};
     if (role == 0 && inside) {
-        const int ri = threadIdx.x + NG, rj = threadIdx.y + NG;
+        const int ri = threadIdx.x + g.ng, rj = threadIdx.y + g.ng;
         double dxi[2], deta[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             double s = 0.0, r = 0.0;
 #pragma unroll
-            for (int n = 1; n <= 3; ++n) {
+            for (int n = 1; n <= NG_MAX; ++n) {
+                if (n > g.p) break;
                 const double a = 0.5 * alpha_pn(g.p, n);
                 s += a * (xs[c][rj][ri + n] - xs[c][rj][ri - n]);
                 r += a * (xs[c][rj + n][ri] - xs[c][rj - n][ri]);
@@ -1616,7 +1621,8 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
         } else {
             const dim3 gm((unsigned)((g.P[0] + BX - 1) / BX), (unsigned)((g.P[1] + BY - 1) / BY),
                           (unsigned)((g.P[2] + KZ_MARCH - 1) / KZ_MARCH));
-            k_metrics3d_march<NG><<<gm, box_block(), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
+            if (g.ng == 4) k_metrics3d_march<4><<<gm, box_block(), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
+            else k_metrics3d_march<3><<<gm, box_block(), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
         }
     }
     return hipGetLastError();
@@ -1637,8 +1643,9 @@ static void residual_all(const es_ctx* c, const double* prim, const double* met,
     const GridDev& g = c->g;
     SweepPlan sw{};
     long long nb = 0;
+    const int segn = seg_nodes(g.p);
     for (int d = 0; d < DIM; ++d) {
-        sw.nseg[d] = (g.n[d] + SEG - 1) / SEG;
+        sw.nseg[d] = (g.n[d] + segn - 1) / segn;
         long long nl = 1;
         for (int a = 0; a < DIM; ++a)
             if (a != d) nl *= g.n[a];
@@ -1649,6 +1656,7 @@ static void residual_all(const es_ctx* c, const double* prim, const double* met,
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
     const bool es_ = c->scheme.dissipation != 0, mixed = c->scheme.mixed != 0;
     if (g.p == 2) residual_launch<DIM, 2>(es_, mixed, (unsigned)nb, s, g, G, eps, prim, met, Ld, sw);
+    else if (g.p == 4) residual_launch<DIM, 4>(es_, mixed, (unsigned)nb, s, g, G, eps, prim, met, Ld, sw);
     else residual_launch<DIM, 3>(es_, mixed, (unsigned)nb, s, g, G, eps, prim, met, Ld, sw);
 }
 

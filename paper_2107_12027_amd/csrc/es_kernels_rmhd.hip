@@ -36,7 +36,7 @@ __global__ void k_prim2con_rmhd(GridDev g, double G, const double* __restrict__ 
 __global__ void k_con2prim_rmhd(GridDev g, double G, StateSrc ss, double* prim, int use_guess,
                                 unsigned long long* __restrict__ fail) {
     int i, j, k;
-    if (!box_ijk(-NG, -NG, -g.g2, g.P[0], g.P[1], i, j, k)) return;
+    if (!box_ijk(-g.ng, -g.ng, -g.g2, g.P[0], g.P[1], i, j, k)) return;
     const long long t = pidx(g, i, j, k);
     const int si = map_sol(i, g.n[0], g.bc[0]);
     const int sj = map_sol(j, g.n[1], g.bc[1]);
@@ -77,17 +77,16 @@ __global__ void k_con2prim_rmhd(GridDev g, double G, StateSrc ss, double* prim, 
 }
 
 // ---------------------------------------------------------------------------
-// residual: one wavefront per 61-node line segment (as the RHD residual)
+// residual: one wavefront per line segment of seg_nodes(p) nodes (as the RHD
+// residual)
 // ---------------------------------------------------------------------------
-constexpr int SEG = 61;
-constexpr int NLOAD = SEG + 6;
 constexpr int RLINES = 2;
 
-template <int DIM>
+template <int DIM, int PO>
 struct ResidualLDSM {
     static constexpr int NA = DIM + 1, NF = MR + 2 + NA;
-    double sd[RLINES][NF][NLOAD + 1];
-    double sp[RLINES][3][MR + 2][64];    // pair fluxes F (8), J and B~ values
+    double sd[RLINES][NF][seg_loads(PO) + 1];
+    double sp[RLINES][PO > 2 ? PO : 2][MR + 2][64];    // pair fluxes F (8), J and B~ values
 };
 
 struct SweepPlanM {
@@ -101,8 +100,9 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
                                                       const double* __restrict__ prim,
                                                       const double* __restrict__ met,
                                                       double* __restrict__ out, int blk, int nseg,
-                                                      long long nlines, ResidualLDSM<DIM>& lds) {
+                                                      long long nlines, ResidualLDSM<DIM, PO>& lds) {
     constexpr int NA = DIM + 1;
+    constexpr int NGP = ghost_layers(PO), SEGP = seg_nodes(PO), NLOADP = seg_loads(PO);
     constexpr int F_LR = MR, F_LB = MR + 1, F_A = MR + 2;
     auto& sd = lds.sd;
     auto& sp = lds.sp;
@@ -112,8 +112,8 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
     const long long lid = (long long)(blk / nseg) * RLINES + line;
     const bool active = lid < nlines;
     const int nAlong = g.n[DIR];
-    const int s0 = seg * SEG;
-    const int s_end = min(s0 + SEG, nAlong);
+    const int s0 = seg * SEGP;
+    const int s_end = min(s0 + SEGP, nAlong);
     int ci = 0, cj = 0, ck = 0;
     if (active) {
         if (DIR == 0) { cj = (int)(lid % g.n[1]); ck = (int)(lid / g.n[1]); }
@@ -126,15 +126,15 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
     const long long ibase = iidx(g, ci, cj, ck);
     const long long P = g.pnodes, N = g.nodes;
 
-    for (int q = lane; q < NLOAD; q += 64) {
-        const int s = s0 - NG + q;
+    for (int q = lane; q < NLOADP; q += 64) {
+        const int s = s0 - NGP + q;
         double v[MR + 2 + NA];
 #pragma unroll
         for (int c = 0; c < MR + 2 + NA; ++c) v[c] = 0.0;
         v[0] = 1.0;
         v[4] = 1.0;
         v[F_A + 1] = 1.0;
-        if (active && s < s_end + NG) {
+        if (active && s < s_end + NGP) {
             const long long idx = pbase + (long long)s * pstride;
 #pragma unroll
             for (int c = 0; c < MR + 2; ++c) v[c] = prim[c * P + idx];
@@ -156,7 +156,7 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
         return node_rmhd(G, Pq, sd[line][F_LR][q], sd[line][F_LB][q]);
     };
 
-    const int s_own = s0 - NG + lane;
+    const int s_own = s0 - NGP + lane;
     if (active && s_own < s_end) {
         const NodeRMHD l = node_at(lane);
         double al[NA];
@@ -179,7 +179,7 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
     }
     __syncthreads();
 
-    const bool owner = active && lane >= NG && s_own < s_end;
+    const bool owner = active && lane >= NGP && s_own < s_end;
     const double idxi = 1.0 / g.dxi[DIR];
     double R[MR + 1];
 #pragma unroll
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(128) k_residual_rmhd(GridDev g, double G, doub
                                                        const double* __restrict__ prim,
                                                        const double* __restrict__ met,
                                                        double* __restrict__ Ld, SweepPlanM sw) {
-    __shared__ ResidualLDSM<DIM> lds;
+    __shared__ ResidualLDSM<DIM, PO> lds;
     const long long slab = (long long)(MR + 1) * g.nodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < sw.nblk[0]) {
@@ -360,8 +360,9 @@ static void residual_all_rmhd(const es_ctx* c, const double* prim, const double*
     const GridDev& g = c->g;
     SweepPlanM sw{};
     long long nb = 0;
+    const int segn = seg_nodes(g.p);
     for (int d = 0; d < DIM; ++d) {
-        sw.nseg[d] = (g.n[d] + SEG - 1) / SEG;
+        sw.nseg[d] = (g.n[d] + segn - 1) / segn;
         long long nl = 1;
         for (int a = 0; a < DIM; ++a)
             if (a != d) nl *= g.n[a];
@@ -377,6 +378,13 @@ static void residual_all_rmhd(const es_ctx* c, const double* prim, const double*
         else if (es) k_residual_rmhd<DIM, true, false, 2><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
         else if (mixed) k_residual_rmhd<DIM, false, true, 2><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
         else k_residual_rmhd<DIM, false, false, 2><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+        return;
+    }
+    if (c->scheme.order_p == 4) {
+        if (es && mixed) k_residual_rmhd<DIM, true, true, 4><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+        else if (es) k_residual_rmhd<DIM, true, false, 4><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+        else if (mixed) k_residual_rmhd<DIM, false, true, 4><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
+        else k_residual_rmhd<DIM, false, false, 4><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);
         return;
     }
     if (es && mixed) k_residual_rmhd<DIM, true, true, 3><<<grid, block, 0, s>>>(g, G, eps, prim, met, Ld, sw);

@@ -281,6 +281,58 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
     return (w0 * q0 + w1 * q1 + w2 * q2) * frcp(R(6.0) * (w0 + w1 + w2));
 }
 
+// WENO7-JS value at i+1/2 from point values v_{i-3..i+3} = (a, b, c, d, e, f, h)
+// (Balsara and Shu 2000): four candidates on four-node stencils and linear weights
+// (1, 12, 18, 4)/35.  The smoothness indicator of the Jiang-Shu definition,
+// sum_{l=1..3} int over the cell of (p_k^(l))^2, is evaluated from the Taylor
+// coefficients c_1, c_2, c_3 of the candidate cubic at the cell centre as
+//   beta_k = (c_1 + c_3/4)^2 + 13/3 c_2^2 + 781/20 c_3^2,
+// a sum of squares of differences of v (the expanded quadratic form cancels
+// terms larger than beta by the square of the data over its variation).  With
+// u = 6 (c_1 + c_3/4), t2 = 2 c_2 and t3 = 6 c_3 (integer stencils):
+//   beta_k = u^2/36 + 13/12 t2^2 + 781/720 t3^2.
+// FP64: the weights d_k/(eps + b_k)^2 over a common denominator (one reciprocal)
+// as in weno5; FP32: reciprocal weights.
+template <typename R>
+__device__ __forceinline__ R weno7(R a, R b, R c, R d, R e, R f, R h, R eps) {
+    const R q0 = -R(3.0) * a + R(13.0) * b - R(23.0) * c + R(25.0) * d;    // 12 x candidate values
+    const R q1 = b - R(5.0) * c + R(13.0) * d + R(3.0) * e;
+    const R q2 = -c + R(7.0) * d + R(7.0) * e - f;
+    const R q3 = R(3.0) * d + R(13.0) * e - R(5.0) * f + h;
+    const R u0 = -R(2.0) * a + R(9.0) * b - R(18.0) * c + R(11.0) * d;
+    const R u1 = b - R(6.0) * c + R(3.0) * d + R(2.0) * e;
+    const R u2 = -R(2.0) * c - R(3.0) * d + R(6.0) * e - f;
+    const R u3 = -R(11.0) * d + R(18.0) * e - R(9.0) * f + R(2.0) * h;
+    const R s0 = -a + R(4.0) * b - R(5.0) * c + R(2.0) * d;
+    const R s1 = c - R(2.0) * d + e;          // candidates 1 and 2 share t2
+    const R s3 = R(2.0) * d - R(5.0) * e + R(4.0) * f - h;
+    const R r0 = -a + R(3.0) * b - R(3.0) * c + d;
+    const R r1 = -b + R(3.0) * c - R(3.0) * d + e;
+    const R r2 = -c + R(3.0) * d - R(3.0) * e + f;
+    const R r3 = -d + R(3.0) * e - R(3.0) * f + h;
+    const R ku = R(1.0 / 36.0), k2 = R(13.0 / 12.0), k3 = R(781.0 / 720.0);
+    const R b0 = ku * u0 * u0 + k2 * s0 * s0 + k3 * r0 * r0;
+    const R b1 = ku * u1 * u1 + k2 * s1 * s1 + k3 * r1 * r1;
+    const R b2 = ku * u2 * u2 + k2 * s1 * s1 + k3 * r2 * r2;
+    const R b3 = ku * u3 * u3 + k2 * s3 * s3 + k3 * r3 * r3;
+    const R e0 = eps + b0, e1 = eps + b1, e2 = eps + b2, e3 = eps + b3;
+    const R f0 = e0 * e0, f1 = e1 * e1, f2 = e2 * e2, f3 = e3 * e3;
+    R w0, w1, w2, w3;
+    if (RealTraits<R>::wide_range) {
+        const R f01 = f0 * f1, f23 = f2 * f3;
+        w0 = R(1.0) * (f1 * f23);
+        w1 = R(12.0) * (f0 * f23);
+        w2 = R(18.0) * (f01 * f3);
+        w3 = R(4.0) * (f01 * f2);
+    } else {
+        w0 = R(1.0) * frcp(f0);
+        w1 = R(12.0) * frcp(f1);
+        w2 = R(18.0) * frcp(f2);
+        w3 = R(4.0) * frcp(f3);
+    }
+    return (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) * frcp(R(12.0) * (w0 + w1 + w2 + w3));
+}
+
 // WENO3-JS value at i+1/2 from v_{i-1..i+1} = (a, b, c): candidates (3b - a)/2 and
 // (b + c)/2, linear weights 1/3 and 2/3, smoothness indicators (b - a)^2 and
 // (c - b)^2; in FP64 over a common denominator as weno5.
@@ -552,7 +604,7 @@ __device__ __forceinline__ R face_eigen_columns(R G, const R* V2, const R* V3, R
 //    zero (sign(0) at rounding level).
 //
 // The stencil states come from node(j), j = 0..2P-1 (nodes i-P+1..i+P; WENO of
-// order w = 2P - 1: WENO5 for P = 3, WENO3 for P = 2).  The face eigen-structure
+// order w = 2P - 1: WENO7 for P = 4, WENO5 for P = 3, WENO3 for P = 2).  The face eigen-structure
 // is formed first from nodes i and i+1 alone; the rotated entropy vectors of the
 // stencil are formed afterwards and projected onto the columns at once, so that
 // they are not held while the eigen-structure is built (register use).
@@ -637,7 +689,10 @@ __device__ __forceinline__ void face_diss_rhd_fn(R G, R eps, NodeFn&& node, cons
     for (int q = 0; q < M; ++q) {
         const R* r = Rm[q];
         R vm, vp;
-        if (P == 3) {
+        if (P == 4) {
+            vm = weno7(vt[q][0], vt[q][1], vt[q][2], vt[q][3], vt[q][4], vt[q][5], vt[q][6], eps);
+            vp = weno7(vt[q][7], vt[q][6], vt[q][5], vt[q][4], vt[q][3], vt[q][2], vt[q][1], eps);
+        } else if (P == 3) {
             vm = weno5(vt[q][0], vt[q][1], vt[q][2], vt[q][3], vt[q][4], eps);
             vp = weno5(vt[q][5], vt[q][4], vt[q][3], vt[q][2], vt[q][1], eps);
         } else {

@@ -848,7 +848,10 @@ __device__ __forceinline__ void face_diss_rmhd(double G, double eps, const doubl
             vt[j] = s;
         }
         RW jw;
-        if (P == 3)
+        if (P == 4)
+            jw = weno7(vt[7], vt[6], vt[5], vt[4], vt[3], vt[2], vt[1], (RW)eps) -
+                 weno7(vt[0], vt[1], vt[2], vt[3], vt[4], vt[5], vt[6], (RW)eps);
+        else if (P == 3)
             jw = weno5(vt[5], vt[4], vt[3], vt[2], vt[1], (RW)eps) - weno5(vt[0], vt[1], vt[2], vt[3], vt[4], (RW)eps);
         else
             jw = weno3(vt[3], vt[2], vt[1], (RW)eps) - weno3(vt[0], vt[1], vt[2], (RW)eps);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libes.so")
 
 ES_OK, ES_EINVAL, ES_EADMISSIBLE, ES_ENOCONV, ES_EMESH, ES_EHIP, ES_EUNSUPPORTED, ES_ETOOLARGE = range(8)
 SYMBOLS = ("es_create", "es_destroy", "es_nvars", "es_nprim", "es_nmet", "es_nodes",
-           "es_padded_nodes", "es_prim2con", "es_metrics", "es_con2prim", "es_residual",
+           "es_padded_nodes", "es_ghost_layers", "es_prim2con", "es_metrics", "es_con2prim", "es_residual",
            "es_cfl", "es_mesh_redistribute", "es_rk3_step", "es_rk3_step_moving", "es_set_graph",
            "es_diagnostics", "es_ctx_status", "es_status_string", "es_ckpt_doubles", "es_rk3_step_save",
            "es_rk3_step_vjp", "es_residual_vjp", "es_con2prim_vjp", "es_prim2con_vjp",
@@ -66,7 +66,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.es_create.restype = st
     lib.es_destroy.argtypes = [vp]
     lib.es_destroy.restype = st
-    for name in ("es_nvars", "es_nprim", "es_nmet", "es_nodes", "es_padded_nodes"):
+    for name in ("es_nvars", "es_nprim", "es_nmet", "es_nodes", "es_padded_nodes", "es_ghost_layers"):
         getattr(lib, name).argtypes = [vp]
         getattr(lib, name).restype = ctypes.c_size_t
     lib.es_prim2con.argtypes = [vp, vp, vp, vp, vp]
@@ -149,6 +149,7 @@ class Context:
         self.nmet = lib.es_nmet(h)
         self.nodes = lib.es_nodes(h)
         self.pnodes = lib.es_padded_nodes(h)
+        self.ng = lib.es_ghost_layers(h)
         self.dim = grid.dim
 
     def close(self):
@@ -167,7 +168,7 @@ class Context:
         return tuple(self.grid.shape)
 
     def padded_shape(self):
-        return tuple(s + 6 for s in self.grid.shape)
+        return tuple(s + 2 * self.ng for s in self.grid.shape)
 
     # sizes of the documented layouts ---------------------------------------
     def _int(self, comps=1):

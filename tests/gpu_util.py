@@ -89,7 +89,7 @@ class Case:
         Uo, Jo = self.oracle_state()
         Po, _ = st.prim_from_cons(self.grid, self.scheme, Uo, Jo)
         meto = mt.metrics(self.grid, self.x, self.xdot, self.scheme.order_p)
-        return rs.residual(self.grid, self.scheme, st.pad_solution(self.grid, Po), meto)
+        return rs.residual(self.grid, self.scheme, st.pad_solution(self.grid, Po, self.scheme.order_p), meto)
 
     def gpu_state(self):
         """J^0 by es_metrics and Ucurv by es_prim2con from the same primitive input."""

@@ -372,3 +372,46 @@ def test_weno7_jump_seventh_order_on_smooth_data():
         errs.append(np.max(np.abs(vp - vm)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates[-1] > 6.8, (errs, rates)
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_weno_indicators_as_sums_of_squares(r):
+    # beta_k evaluated as sum_m D_m (w_km . v)^2 is the definition's quadratic form
+    # exactly (rational arithmetic), each square is of differences (w_km annihilates
+    # constants), and for r = 3 the factors are the 13/12 and 1/4 of WENO5-JS
+    from fractions import Fraction as Fr
+    c, B, d = ds.weno_js_tables(r)
+    D, W = ds.weno_js_squares(r)
+    for k in range(r):
+        for a in range(r):
+            for b in range(r):
+                assert sum(D[m] * W[k][m][a] * W[k][m][b] for m in range(r - 1)) == B[k][a][b]
+        for m in range(r - 1):
+            assert sum(W[k][m]) == 0
+    if r == 3:
+        assert D == [Fr(1), Fr(13, 3)]
+    if r == 4:
+        assert D == [Fr(1), Fr(13, 3), Fr(781, 20)]
+
+
+def test_weno7_indicators_stable_on_smooth_data():
+    # on smooth data of size 1 with variations of 1e-3 (beta ~ 1e-7) the expanded
+    # quadratic form loses about eight digits of beta (1e-8 relative); the sum of
+    # squares keeps all but about three (1e-12), against 50-digit evaluation of the
+    # exact rational form
+    import mpmath
+    mpmath.mp.dps = 50
+    c, B, d = ds.weno_js_tables(4)
+    D, W = ds.weno_js_squares(4)
+    q = lambda f: mpmath.mpf(f.numerator) / f.denominator
+    x = 1.0 + 1e-3 * np.sin(np.arange(-3, 4) * 0.37 + 0.2)
+    worst_sq, worst_exp = 0.0, 0.0
+    for k in range(4):
+        S = x[k:k + 4]
+        exact = float(sum(q(D[m]) * mpmath.fsum(q(W[k][m][j]) * mpmath.mpf(S[j]) for j in range(4)) ** 2
+                          for m in range(3)))
+        sq = sum(float(D[m]) * sum(float(W[k][m][j]) * S[j] for j in range(4)) ** 2 for m in range(3))
+        ex = sum(float(B[k][a][b]) * S[a] * S[b] for a in range(4) for b in range(4))
+        worst_sq = max(worst_sq, abs(sq - exact) / exact)
+        worst_exp = max(worst_exp, abs(ex - exact) / exact)
+    assert worst_sq < 1e-11 and worst_exp > 1e-9, (worst_sq, worst_exp)
