@@ -58,7 +58,9 @@ def _create(grid, scheme, monitor):
     (lambda g, s, m: setattr(s, "cfl", 0.0), es.ES_EINVAL),
     (lambda g, s, m: setattr(s, "dissipation", 2), es.ES_EINVAL),
     (lambda g, s, m: setattr(m, "form", 7), es.ES_EINVAL),
-    (lambda g, s, m: setattr(s, "order_p", 4), es.ES_EUNSUPPORTED),
+    (lambda g, s, m: setattr(s, "order_p", 5), es.ES_EUNSUPPORTED),
+    # p = 4 needs 2 ng + 1 = 9 nodes on outflow axes (four ghost layers)
+    (lambda g, s, m: (setattr(s, "order_p", 4), setattr(g, "n", (8, 10, 1))), es.ES_EINVAL),
     (lambda g, s, m: (setattr(s, "order_p", 1), setattr(s, "phys", 1)), es.ES_EUNSUPPORTED),
     (lambda g, s, m: (setattr(m, "enabled", 1), setattr(m, "form", 2), setattr(m, "alpha2", -1.0)),
      es.ES_EINVAL),
@@ -77,5 +79,6 @@ def test_status_strings():
     if lib is None:
         _ensure_built()
         lib = es.load()
-    for code in range(7):
+    for code in range(8):
         assert lib.es_status_string(code)
+    assert lib.es_status_string(99) == b"unknown status"
