@@ -48,9 +48,14 @@ PEAK_HBM = 8.0e12                # B/s
 # fabs fmax count 1, fma counts 2.  2D RHD ES, p = 3, per node and direction: 3
 # two-point fluxes (102.3 each), 1 face dissipation (1494.7), state preparation
 # (6) and the flux-difference accumulation (66): 1873.7; two directions: 3747.5.
-# 3D RHD ES: 2771.0 per direction, 8313.0 for the three.
+# 3D RHD ES: 2771.0 per direction, 8313.0 for the three.  RMHD ES, p = 3 (the
+# numeric face eigen-structure dominates: about 35,400 per face; averaged over
+# smooth states with well-separated eigenvalues): 73914.1 per node in 2D, 111738.6
+# in 3D.
 RESIDUAL_FLOPS_PER_NODE_2D_RHD = 3747.5
 RESIDUAL_FLOPS_PER_NODE_3D_RHD = 8313.0
+RESIDUAL_FLOPS_PER_NODE_2D_RMHD = 73914.1
+RESIDUAL_FLOPS_PER_NODE_3D_RMHD = 111738.6
 
 # HBM bytes of one es_residual call, from the FETCH_SIZE and WRITE_SIZE counters
 # (rocprofv3 --pmc, one counter per run) of the residual kernel and k_sum_dirs,
@@ -330,9 +335,11 @@ def _cfl_inputs(run):
 
 
 def residual_flops(w):
-    """Algorithmic FP64 ops of one es_residual call per interior node (RHD ES, p = 3)."""
-    if w.scheme.phys != 0 or w.scheme.order_p != 3 or w.scheme.dissipation != 1:
+    """Algorithmic FP64 ops of one es_residual call per interior node (ES, p = 3)."""
+    if w.scheme.order_p != 3 or w.scheme.dissipation != 1:
         return None
+    if w.scheme.phys == 1:
+        return RESIDUAL_FLOPS_PER_NODE_2D_RMHD if w.grid.dim == 2 else RESIDUAL_FLOPS_PER_NODE_3D_RMHD
     return RESIDUAL_FLOPS_PER_NODE_2D_RHD if w.grid.dim == 2 else RESIDUAL_FLOPS_PER_NODE_3D_RHD
 
 
@@ -512,7 +519,7 @@ def c3_rotor(n=512, steps=200, warmup=2, reps=10):
     r = fp64_and_mixed(w, steps, warmup, reps)
     return {"workload": w.name, "steps": steps, "value": w.grid.nnodes * steps / (r["t_ms"] * 1e-3),
             "unit": "cell-updates/s", "ms_per_step": r["t_ms"] / steps, "es_residual_ms": r["res_ms"],
-            "mixed": r["mixed"], "config": describe(w)}
+            "roofline": r["roofline"], "mixed": r["mixed"], "config": describe(w)}
 
 
 def main():

@@ -1,12 +1,16 @@
-// Algorithmic FP64 operation count of the residual (2D/3D RHD, p = 3).
+// Algorithmic FP64 operation count of the residual (2D/3D, RHD and RMHD, p = 3).
 //
-// The device arithmetic of es_rhd.h (two-point EC flux and face dissipation)
-// is compiled for the host with an op-counting scalar in place of double and
-// executed on representative node states; each + - * /, sqrt, log, exp, fabs,
-// fmax/fmin counts one operation and fma counts two.  Per node and direction
-// the residual evaluates one state preparation, three two-point fluxes, one
-// face dissipation and the flux-difference accumulation; these are summed
-// into the per-node figure used as the algorithmic work of es_residual.
+// The device arithmetic of es_rhd.h and es_rmhd.h (two-point EC fluxes, face
+// dissipation, the Godunov-Powell source factor) is compiled for the host with
+// an op-counting scalar in place of double and executed on representative node
+// states; each + - * /, sqrt, log, exp, fabs, fmax/fmin counts one operation and
+// fma counts two.  Per node and direction the residual evaluates one state
+// preparation, p two-point fluxes, one face dissipation (and for RMHD the source
+// factor Phi'(V_i)) and the flux-difference accumulation; these are summed into
+// the per-node figure used as the algorithmic work of es_residual.  The RMHD face
+// dissipation's numeric eigen-structure (cyclic Jacobi sweeps until the off-
+// diagonal part vanishes) depends on the state: its figure is the average over
+// smooth states with well-separated eigenvalues.
 //
 // Build and run (host only):  python -m paper_2107_12027_amd.build --opcount
 #include "es_common.h"
@@ -21,6 +25,7 @@ struct Cnt {
     double v;
     static long long ops;
     constexpr Cnt(double x = 0.0) : v(x) {}
+    explicit operator float() const { return (float)v; }
 };
 long long Cnt::ops = 0;
 
@@ -32,6 +37,8 @@ inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
 inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
 inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
 inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
+inline Cnt& operator/=(Cnt& a, Cnt b) { a = a / b; return a; }
+inline bool operator!=(Cnt a, Cnt b) { return a.v != b.v; }
 inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
 inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
 inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
@@ -62,7 +69,7 @@ using cnt::fmin;
 #undef __forceinline__
 #define __forceinline__ inline
 #define double Cnt
-#include "es_rhd.h"
+#include "es_rmhd.h"
 #undef double
 
 template <int DIM>
@@ -105,9 +112,58 @@ static void count(double G, std::mt19937_64& rng, int samples) {
                 DIM, pair, face, prep, accum, per_dir, DIM, DIM * per_dir);
 }
 
+template <int DIM, int PO>
+static void count_rmhd(double G, std::mt19937_64& rng, int samples) {
+    std::uniform_real_distribution<double> U01(0.0, 1.0);
+    constexpr int NA = DIM + 1;
+    long long node_ops = 0, pair_ops = 0, face_ops = 0, src_ops = 0;
+    for (int s = 0; s < samples; ++s) {
+        // smooth stencil states, field near (0.6, 0.45, 0.35): no degenerate eigenvalues
+        Cnt Pn[2 * PO][8];
+        const double B0[3] = {0.6 + 0.2 * U01(rng), 0.45 + 0.2 * (U01(rng) - 0.5), 0.35 + 0.2 * (U01(rng) - 0.5)};
+        for (int q = 0; q < 2 * PO; ++q) {
+            Pn[q][0] = 1.0 + 0.05 * q + 0.1 * U01(rng);
+            for (int k = 0; k < 3; ++k) Pn[q][1 + k] = 0.4 * (U01(rng) - 0.5);
+            Pn[q][4] = 0.5 + 0.3 * U01(rng);
+            for (int k = 0; k < 3; ++k) Pn[q][5 + k] = B0[k] + 0.02 * (U01(rng) - 0.5);
+        }
+        Cnt al[NA], ar[NA];
+        for (int c = 0; c < NA; ++c) { al[c] = 0.1 * U01(rng) + (c == 1); ar[c] = 0.1 * U01(rng) + (c == 1); }
+        auto lr = [&](int q) { return Cnt(std::log(Pn[q][0].v)); };
+        auto lb = [&](int q) { return Cnt(std::log(Pn[q][0].v / Pn[q][4].v)); };
+        Cnt::ops = 0;
+        const es::NodeRMHDT<Cnt> l = es::node_rmhd<Cnt>(G, Pn[PO - 1], lr(PO - 1), lb(PO - 1));
+        node_ops += Cnt::ops;
+        const es::NodeRMHDT<Cnt> r = es::node_rmhd<Cnt>(G, Pn[PO], lr(PO), lb(PO));
+        Cnt F[8], Jt, Bt, d[8], Pp[8];
+        Cnt::ops = 0;
+        es::pair_flux_rmhd<DIM>(G, l, r, al, ar, F, Jt, Bt);
+        pair_ops += Cnt::ops;
+        Cnt::ops = 0;
+        es::face_diss_rmhd<DIM, false, PO>(G, 1e-6, Pn, al, ar, d);
+        face_ops += Cnt::ops;
+        Cnt::ops = 0;
+        const es::StateRMHD<Cnt> st = es::rmhd_state<Cnt>(G, Pn[PO - 1]);
+        es::rmhd_phi_prime<Cnt>(st, Pp);
+        src_ops += Cnt::ops;
+    }
+    const double node = (double)node_ops / samples, pair = (double)pair_ops / samples,
+                 face = (double)face_ops / samples, src = (double)src_ops / samples;
+    // accumulation per node and direction: per component (8 + J + B~) p (sub, mul,
+    // add) and a scale; the source 8 (mul, sub); the dissipation difference 8 (sub,
+    // two mul, add)
+    const double accum = 10.0 * (3 * PO + 1) + 8 * 2 + 8 * 4;
+    const double per_dir = node + PO * pair + face + src + accum;
+    std::printf("dim %d RMHD: node %.1f pair %.1f face %.1f source %.1f accum %.0f -> per node per direction "
+                "%.1f, per node (all %d directions) %.1f FP64 ops\n",
+                DIM, node, pair, face, src, accum, per_dir, DIM, DIM * per_dir);
+}
+
 int main() {
     std::mt19937_64 rng(12345);
     count<2>(5.0 / 3.0, rng, 2000);
     count<3>(5.0 / 3.0, rng, 2000);
+    count_rmhd<2, 3>(5.0 / 3.0, rng, 500);
+    count_rmhd<3, 3>(5.0 / 3.0, rng, 500);
     return 0;
 }
