@@ -97,6 +97,11 @@ def parse():
     ap.add_argument("--vortex-n", default=None,
                     help="mesh sizes N of the vortex study (2D: N x N, default 20,40,80,160; "
                          "3D: N x N x 5N, default 16,24,32,48,64)")
+    ap.add_argument("--vortex-sweeps", type=int, default=None,
+                    help="Jacobi sweeps mu of the MM-O5 mesh redistribution in the vortex study "
+                         "(default: the example's 10)")
+    ap.add_argument("--vortex-schemes", default="mm_o6,mm_o5",
+                    help="schemes of the vortex study, from mm_o6 and mm_o5")
     ap.add_argument("--no-fourier-gradient", action="store_true",
                     help="skip the gradient study of the adjoint configuration (object c5_adjoint)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -665,18 +670,21 @@ def paper_case(args):
     print(json.dumps(line))
 
 
-def vortex_run(dim, n, adaptive, max_wall_s=150.0):
+def vortex_run(dim, n, adaptive, max_wall_s=150.0, sweeps=None):
     """The RMHD vortex of Section 6 (2D: N x N nodes to t = 4; 3D: N x N x 5N
     nodes to t = 0.1): MM-O6 (EC scheme, prescribed mesh, dt = CFL dxi^2) or MM-O5
     (ES scheme, adaptive mesh with the gradient + Laplacian monitor, dt = CFL
     dxi^(5/3)), dxi = 1/N the computational spacing, the step count rounded up so
     that the run ends at the end time.  Returns the L1 and max errors of rho
-    against the closed form and the GPU time (HIP events)."""
+    against the closed form and the GPU time (HIP events).  sweeps: the Jacobi
+    sweep count of the adaptive redistribution instead of the example's."""
     import math
     import numpy as np
     import torch
     from paper_2107_12027_amd import workloads as wl
     w = wl.rmhd_vortex(dim, n, 0.0, dissipation=int(adaptive), adaptive=adaptive)
+    if adaptive and sweeps is not None:
+        w.monitor.sweeps = int(sweeps)
     t_end = w.t_end
     run = Run(w, 0)
     ctx = run.ctx
@@ -736,10 +744,14 @@ def vortex_study(args, dim):
     name_case = "vortex%dd" % dim
     line = {"paper_case": name_case, "t_end": 4.0 if dim == 2 else 0.1, "dtype": "f64",
             "data": "synthetic (the paper's closed-form initial data)"}
+    if args.vortex_sweeps is not None:
+        line["mm_o5_sweeps"] = args.vortex_sweeps
     for name, adaptive in (("mm_o6", False), ("mm_o5", True)):
+        if name not in args.vortex_schemes.split(","):
+            continue
         runs = []
         for n in ns:
-            r = vortex_run(dim, n, adaptive)
+            r = vortex_run(dim, n, adaptive, sweeps=args.vortex_sweeps)
             runs.append(r)
             print("%s %s N=%d: %s" % (name_case, name, n, json.dumps(r)), file=sys.stderr, flush=True)
         rates = []
