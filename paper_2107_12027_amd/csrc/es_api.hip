@@ -325,7 +325,7 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
         const double* met = c->met;
         if (batched) met = st == 0 ? c->met : (st == 1 ? c->met1 : c->met2);
         else if (st == 0 && met0_spatial) ES_TRY(es::launch_temporal_metrics3d(c, xdot, c->met, s));
-        else ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s));
+        else ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s, st == 2));
         ES_TRY(es::launch_residual_dirs(c, c->prim, met, c->L, s));
         if (st == 0) {
             ES_TRY(es::launch_combine_con2prim(c, 0, U, J, nullptr, nullptr, c->L, dt_dev, c->Us, c->Js,

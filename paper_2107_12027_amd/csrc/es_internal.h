@@ -68,9 +68,11 @@ hipError_t launch_con2prim(const es_ctx* c, const double* U, const double* J, do
                            int use_guess, hipStream_t s);
 int reduction_blocks(const GridDev& g);
 hipError_t launch_temporal_metrics3d(const es_ctx* c, const double* xdot, double* met, hipStream_t s);
+// ve_ready: the extended mesh velocity of this xdot is already in the context
+// (3D; an earlier call of the same step), so it is not formed again
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
-                          hipStream_t s);
+                          hipStream_t s, bool ve_ready = false);
 // the metrics of the three stage meshes x + c dt xdot (c = 0, 1, 1/2) in one launch
 bool metrics_stages_batched(const es_ctx* c);
 hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double* xdot,

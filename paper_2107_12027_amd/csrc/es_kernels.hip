@@ -363,17 +363,21 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
 // window of 2H + 1 planes, so each is read once per plane instead of 2H times;
 // the differences within a plane read their neighbours through L1/L2.  Columns
 // are taken in XCD-contiguous block ranges (x fastest, then y, then the run), so
-// the rows that a block's y-differences reach are read through one L2.
+// the rows that a block's y-differences reach are read through one L2.  Blocks
+// of MX x MY columns: 32 x 8 reads the y-neighbours of a block from fewer rows
+// than 64 x 4 and leaves fewer idle lanes on the 134-node padded rows of a 128^3
+// grid (221 against 244 us per call there).
+constexpr int MX = 32, MY = 8;
 template <int H>
-__global__ void __launch_bounds__(256) k_metrics3d_march(GridDev g, const double* __restrict__ ve,
-                                                         const double* __restrict__ pi,
-                                                         double* __restrict__ met, int kz) {
+__global__ void __launch_bounds__(MX * MY) k_metrics3d_march(GridDev g, const double* __restrict__ ve,
+                                                             const double* __restrict__ pi,
+                                                             double* __restrict__ met, int kz) {
     const int gx = (int)gridDim.x, gy = (int)gridDim.y;
     const int nb = gx * gy * (int)gridDim.z;
     const int lb = xcd_block((int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x), nb);
     const int bx = lb % gx, by = (lb / gx) % gy, bz = lb / (gx * gy);
-    const int i = -g.ng + bx * BX + (int)threadIdx.x;
-    const int j = -g.ng + by * BY + (int)threadIdx.y;
+    const int i = -g.ng + bx * MX + (int)threadIdx.x;
+    const int j = -g.ng + by * MY + (int)threadIdx.y;
     if (i >= g.n[0] + g.ng || j >= g.n[1] + g.ng) return;
     const int kb = -g.ng + bz * kz;
     const int ke = min(kb + kz, g.n[2] + g.ng);
@@ -1605,7 +1609,7 @@ hipError_t launch_temporal_metrics3d(const es_ctx* c, const double* xdot, double
 
 hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
-                          hipStream_t s) {
+                          hipStream_t s, bool ve_ready) {
     const GridDev& g = c->g;
     const dim3 ge = box_grid(g.E[0], g.E[1], g.E[2]);
     double* ve = xdot != nullptr ? c->ve : nullptr;
@@ -1614,15 +1618,16 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
         const dim3 gm((unsigned)((g.P[0] + MTX - 1) / MTX), (unsigned)((g.P[1] + MTY - 1) / MTY), 1);
         k_metrics2d_fused<<<gm, dim3(MTX, MBY, 1), 0, s>>>(g, x, xdot, dt_dev, coef, met, J0);
     } else {
-        k_mesh_extend<3><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve);
+        // the extended mesh velocity is left in c->ve by an earlier call with the same xdot
+        k_mesh_extend<3><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve_ready ? nullptr : ve);
         k_cmm_products<<<ge, box_block(), 0, s>>>(g, c->xe, c->pi);
         if (J0 != nullptr) {
             k_metrics3d<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, c->xe, ve, c->pi, met, J0);
         } else {
-            const dim3 gm((unsigned)((g.P[0] + BX - 1) / BX), (unsigned)((g.P[1] + BY - 1) / BY),
+            const dim3 gm((unsigned)((g.P[0] + MX - 1) / MX), (unsigned)((g.P[1] + MY - 1) / MY),
                           (unsigned)((g.P[2] + KZ_MARCH - 1) / KZ_MARCH));
-            if (g.ng == 4) k_metrics3d_march<4><<<gm, box_block(), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
-            else k_metrics3d_march<3><<<gm, box_block(), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
+            if (g.ng == 4) k_metrics3d_march<4><<<gm, dim3(MX, MY, 1), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
+            else k_metrics3d_march<3><<<gm, dim3(MX, MY, 1), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
         }
     }
     return hipGetLastError();
