@@ -21,7 +21,7 @@ import torch
 
 
 def _interior(ctx, prim):
-    g = 3
+    g = ctx.ng
     return prim[:, g:-g, g:-g] if ctx.grid.dim == 2 else prim[:, g:-g, g:-g, g:-g]
 
 

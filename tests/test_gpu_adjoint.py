@@ -44,24 +44,26 @@ def test_residual_vjp_against_oracle_differences(dim, n, bc, smooth, diss):
     met = empty(c.nmet, *c.padded_shape())
     c.metrics(dev(case.x), dev(case.xdot), met)
     rng = np.random.default_rng(5)
-    lam = rng.normal(size=(c.m,) + c.shape())
-    gU = empty(c.m, *c.shape())
-    gJ = empty(*c.shape())
-    c.residual_vjp(U, J, met, dev(lam), gU, gJ)
     Uo, Jo = host(U), host(J)
-    vU = Uo * rng.normal(size=Uo.shape)
-    vJ = Jo * rng.normal(size=Jo.shape)
-    adj = float(np.sum(host(gU) * vU) + np.sum(host(gJ) * vJ))
     meto = mt.metrics(case.grid, case.x, case.xdot)
     Y = None
     if diss:
         _, _, info = _oracle_L(case, Uo, Jo, meto, details=True)
         Y = {k: info[k]["Y"] for k in range(dim)}
     h = 1e-7
-    Lp, _ = _oracle_L(case, Uo + h * vU, Jo + h * vJ, meto, Y)
-    Lm, _ = _oracle_L(case, Uo - h * vU, Jo - h * vJ, meto, Y)
-    fd = float(np.sum(lam * (Lp - Lm))) / (2 * h)
-    assert abs(adj - fd) <= 5e-7 * abs(fd), (adj, fd)
+    # three (lambda, v) pairs: v along U and J, along U only, along J only
+    for pair in range(3):
+        lam = rng.normal(size=(c.m,) + c.shape())
+        gU = empty(c.m, *c.shape())
+        gJ = empty(*c.shape())
+        c.residual_vjp(U, J, met, dev(lam), gU, gJ)
+        vU = Uo * rng.normal(size=Uo.shape) * (pair != 2)
+        vJ = Jo * rng.normal(size=Jo.shape) * (pair != 1)
+        adj = float(np.sum(host(gU) * vU) + np.sum(host(gJ) * vJ))
+        Lp, _ = _oracle_L(case, Uo + h * vU, Jo + h * vJ, meto, Y)
+        Lm, _ = _oracle_L(case, Uo - h * vU, Jo - h * vJ, meto, Y)
+        fd = float(np.sum(lam * (Lp - Lm))) / (2 * h)
+        assert abs(adj - fd) <= 5e-7 * abs(fd), (pair, adj, fd)
 
 
 def _gpu_state(w, ctx):
@@ -163,12 +165,13 @@ def test_autograd_function_two_steps():
     assert torch.isfinite(gJ).all()
 
 
-def _fourier_forward(n, steps, coeffs, dt, ckpts=None, phys=ph.RHD):
+def _fourier_forward(n, steps, coeffs, dt, ckpts=None, phys=ph.RHD, p=3):
     """GPU forward of the Fourier-mode workload (RHD, or RMHD as in the adjoint
-    configuration) with a fixed time step; returns (ctx, U, J, prim0 interior,
-    mask weight) after `steps` steps."""
+    configuration) with a fixed time step and order parameter p; returns (ctx, U, J,
+    prim0 interior, mask weight) after `steps` steps."""
     from paper_2107_12027_amd import losses
     w = (wl.rhd_fourier if phys == ph.RHD else wl.rmhd_fourier)(n=n, coeffs=coeffs)
+    w.scheme.order_p = p
     ctx = es.Context(w.grid, w.scheme, w.monitor)
     U, J, x = _gpu_state(w, ctx)
     Pfull = ph.full_prim(w.prim["rho"], w.prim["u"], w.prim["p"], w.prim["B"])
@@ -189,32 +192,33 @@ def _fourier_forward(n, steps, coeffs, dt, ckpts=None, phys=ph.RHD):
     return ctx, U, J, P0, weight, losses
 
 
-@pytest.mark.parametrize("phys,K,tol", [(ph.RHD, 4, 1e-6), (ph.RMHD, 3, 1e-5)])
-def test_fourier_mode_gradient_against_differences(phys, K, tol):
+@pytest.mark.parametrize("phys,K,tol,p", [(ph.RHD, 4, 1e-6, 3), (ph.RMHD, 3, 1e-5, 3), (ph.RMHD, 2, 1e-5, 2)])
+def test_fourier_mode_gradient_against_differences(phys, K, tol, p):
     # the gradient of L = integral of rho^2 over [0.4,0.6]^2 after K steps with
     # respect to the 8 density-mode coefficients (the adjoint configuration's loss on
     # its RMHD workload, and on the RHD counterpart; static mesh, fixed dt): adjoint
     # chain (es_rk3_step_save / es_rk3_step_vjp, con2prim by the implicit-function
     # rule at both ends) against central differences h = 1e-6 of the GPU forward and,
     # for two coefficients, of the oracle's forward.  RMHD: the adjoint holds the face
-    # eigen-structure, whose variation multiplies the WENO jumps of this smooth flow
+    # eigen-structure, whose variation multiplies the WENO jumps of this smooth flow.
+    # p = 2 (RMHD): the same chain through the 4th-order flux and WENO3 dissipation
     n, dt, h = 32, 6.25e-3, 1e-6
     make = wl.rhd_fourier if phys == ph.RHD else wl.rmhd_fourier
     _, _, c0 = wl.fourier_modes(0)
     ck = []
-    ctx, U, J, P0, weight, losses = _fourier_forward(n, K, c0, dt, ck, phys)
+    ctx, U, J, P0, weight, losses = _fourier_forward(n, K, c0, dt, ck, phys, p)
     L, gU, gJ = losses.density_squared(ctx, U, J, weight)
     for k in reversed(range(K)):
         oU, oJ = empty(*gU.shape), empty(*gJ.shape)
         ctx.rk3_step_vjp(ck[k], gU, gJ, oU, oJ)
         gU, gJ = oU, oJ
     w0 = make(n=n, coeffs=c0)
-    J0 = dev(mt.jacobian(w0.grid, w0.x))
+    J0 = dev(mt.jacobian(w0.grid, w0.x, p))
     phi = dev(wl.fourier_basis(w0.x))
     grad = losses.density_mode_gradient(ctx, P0, J0, gU, phi, 0.05).cpu().numpy()
 
     def loss_gpu(c):
-        cx, Ux, Jx, _, wx, _ = _fourier_forward(n, K, c, dt, None, phys)
+        cx, Ux, Jx, _, wx, _ = _fourier_forward(n, K, c, dt, None, phys, p)
         return float(losses.density_squared(cx, Ux, Jx, wx)[0])
 
     fd = np.array([(loss_gpu(c0 + h * e) - loss_gpu(c0 - h * e)) / (2 * h) for e in np.eye(8)])
@@ -224,6 +228,7 @@ def test_fourier_mode_gradient_against_differences(phys, K, tol):
     # the oracle's forward (same inputs, prescribed zero mesh velocity and the same dt)
     def loss_oracle(c):
         wx = make(n=n, coeffs=c)
+        wx.scheme.order_p = p
         Px = ph.full_prim(wx.prim["rho"], wx.prim["u"], wx.prim["p"], wx.prim["B"])
         Uo, Jo = st.initial_state(wx.grid, wx.scheme, Px, wx.x)
         xo = wx.x
