@@ -75,7 +75,12 @@ __global__ void k_con2prim_rhd(GridDev g, double G, StateSrc ss, double* prim, i
                                unsigned long long* __restrict__ fail) {
     constexpr int M = DIM + 2;
     int i, j, k;
-    if (!box_ijk(-g.ng, -g.ng, -g.g2, g.P[0], g.P[1], i, j, k)) return;
+    if (DIM == 3) {
+        if (!plane_cell_xcd(g.P[0], g.P[1], i, j, k)) return;
+        i -= g.ng; j -= g.ng; k -= g.g2;
+    } else if (!box_ijk(-g.ng, -g.ng, -g.g2, g.P[0], g.P[1], i, j, k)) {
+        return;
+    }
     const long long t = pidx(g, i, j, k);
     const int si = map_sol(i, g.n[0], g.bc[0]);
     const int sj = map_sol(j, g.n[1], g.bc[1]);
@@ -118,14 +123,16 @@ __global__ void k_con2prim_rhd(GridDev g, double G, StateSrc ss, double* prim, i
 // ---------------------------------------------------------------------------
 // metrics (Section 3.3; 2D explicit form of Appendix B with 1/Delta xi)
 // ---------------------------------------------------------------------------
-// Stage mesh x + cdt xdot and mesh velocity on the extension box (6 layers):
+// Stage mesh x + cdt xdot and mesh velocity on the extension box (2 ng layers):
 // periodic copies with the coordinate shift, odd reflection on outflow axes.
+// Flattened cells per plane of the extension box.
 template <int DIM>
 __global__ void k_mesh_extend(GridDev g, const double* __restrict__ x, const double* __restrict__ xd,
                               const double* __restrict__ dt_dev, double coef, double* __restrict__ xe,
                               double* __restrict__ ve) {
     int i, j, k;
-    if (!box_ijk_xcd(-2 * g.ng, -2 * g.ng, -g.g6, g.E[0], g.E[1], i, j, k)) return;
+    if (!plane_cell_xcd(g.E[0], g.E[1], i, j, k)) return;
+    i -= 2 * g.ng; j -= 2 * g.ng; k -= g.g6;
     const long long t = eidx(g, i, j, k);
     const double cdt = dt_dev != nullptr ? coef * dt_dev[0] : 0.0;
     const double* xs = dt_dev != nullptr ? xd : nullptr;
@@ -277,7 +284,8 @@ __global__ void __launch_bounds__(MTX * MSY) k_metrics2d_stages(GridDev g, const
 // 3 layers of the interior (the metric differences never read it elsewhere).
 __global__ void k_cmm_products(GridDev g, const double* __restrict__ xe, double* __restrict__ pi) {
     int i, j, k;
-    if (!box_ijk_xcd(-2 * g.ng, -2 * g.ng, -2 * g.ng, g.E[0], g.E[1], i, j, k)) return;
+    if (!plane_cell_xcd(g.E[0], g.E[1], i, j, k)) return;
+    i -= 2 * g.ng; j -= 2 * g.ng; k -= 2 * g.ng;
     const long long e = eidx(g, i, j, k);
     const long long EN = g.enodes;
     const int c[3] = {i, j, k};
@@ -361,24 +369,18 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
 // padded box and a run of kz consecutive planes.  The products differenced along
 // xi_3 (Pi_{1,.} for J dxi_1/dx_., Pi_{0,.} for J dxi_2/dx_.) stay in a register
 // window of 2H + 1 planes, so each is read once per plane instead of 2H times;
-// the differences within a plane read their neighbours through L1/L2.  Columns
-// are taken in XCD-contiguous block ranges (x fastest, then y, then the run), so
-// the rows that a block's y-differences reach are read through one L2.  Blocks
-// of MX x MY columns: 32 x 8 reads the y-neighbours of a block from fewer rows
-// than 64 x 4 and leaves fewer idle lanes on the 134-node padded rows of a 128^3
-// grid (221 against 244 us per call there).
-constexpr int MX = 32, MY = 8;
+// the differences within a plane read their neighbours through L1/L2.  The
+// columns of a plane are flattened (plane_cell_xcd: no idle lanes at row ends,
+// each wave's store of a component one contiguous run) and the metrics are
+// written with non-temporal stores (they are not read again here; with ordinary
+// stores the kernel took 220 instead of 141 us at 128^3).
 template <int H>
-__global__ void __launch_bounds__(MX * MY) k_metrics3d_march(GridDev g, const double* __restrict__ ve,
-                                                             const double* __restrict__ pi,
-                                                             double* __restrict__ met, int kz) {
-    const int gx = (int)gridDim.x, gy = (int)gridDim.y;
-    const int nb = gx * gy * (int)gridDim.z;
-    const int lb = xcd_block((int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x), nb);
-    const int bx = lb % gx, by = (lb / gx) % gy, bz = lb / (gx * gy);
-    const int i = -g.ng + bx * MX + (int)threadIdx.x;
-    const int j = -g.ng + by * MY + (int)threadIdx.y;
-    if (i >= g.n[0] + g.ng || j >= g.n[1] + g.ng) return;
+__global__ void __launch_bounds__(TPB) k_metrics3d_march(GridDev g, const double* __restrict__ ve,
+                                                         const double* __restrict__ pi,
+                                                         double* __restrict__ met, int kz) {
+    int i, j, bz;
+    if (!plane_cell_xcd(g.P[0], g.P[1], i, j, bz)) return;
+    i -= g.ng; j -= g.ng;
     const int kb = -g.ng + bz * kz;
     const int ke = min(kb + kz, g.n[2] + g.ng);
     const long long EN = g.enodes, P = g.pnodes;
@@ -445,9 +447,9 @@ __global__ void __launch_bounds__(MX * MY) k_metrics3d_march(GridDev g, const do
             double at = 0.0;
 #pragma unroll
             for (int jj = 0; jj < 3; ++jj) at -= v[jj] * m[kk][jj];
-            met[(kk * 4) * P + t] = at;
+            __builtin_nontemporal_store(at, &met[(kk * 4) * P + t]);
 #pragma unroll
-            for (int jj = 0; jj < 3; ++jj) met[(kk * 4 + 1 + jj) * P + t] = m[kk][jj];
+            for (int jj = 0; jj < 3; ++jj) __builtin_nontemporal_store(m[kk][jj], &met[(kk * 4 + 1 + jj) * P + t]);
         }
 #pragma unroll
         for (int q = 0; q < 2 * H; ++q) {
@@ -465,7 +467,8 @@ __global__ void __launch_bounds__(MX * MY) k_metrics3d_march(GridDev g, const do
 // as in k_mesh_extend): stage 0 of a 3D step, whose mesh is x^n.
 __global__ void k_temporal_metrics3d(GridDev g, const double* __restrict__ xd, double* __restrict__ met) {
     int i, j, k;
-    if (!box_ijk(-g.ng, -g.ng, -g.ng, g.P[0], g.P[1], i, j, k)) return;
+    if (!plane_cell_xcd(g.P[0], g.P[1], i, j, k)) return;
+    i -= g.ng; j -= g.ng; k -= g.ng;
     const long long t = pidx(g, i, j, k);
     const long long P = g.pnodes;
     double v[3];
@@ -1557,7 +1560,7 @@ static hipError_t con2prim_from(const es_ctx* c, const StateSrc& ss, double* pri
     if (c->scheme.phys == ES_RMHD) return launch_con2prim_rmhd(c, &ss, prim, use_guess, s);
     const dim3 gr = box_grid(g.P[0], g.P[1], g.P[2]);
     if (g.dim == 2) k_con2prim_rhd<2><<<gr, box_block(), 0, s>>>(g, G, ss, prim, use_guess, c->fail);
-    else k_con2prim_rhd<3><<<gr, box_block(), 0, s>>>(g, G, ss, prim, use_guess, c->fail);
+    else k_con2prim_rhd<3><<<plane_grid(g.P[0], g.P[1], g.P[2]), TPB, 0, s>>>(g, G, ss, prim, use_guess, c->fail);
     return hipGetLastError();
 }
 
@@ -1590,7 +1593,7 @@ hipError_t launch_combine_con2prim(const es_ctx* c, int stage, const double* U0,
 bool metrics_stages_batched(const es_ctx* c) { return c->g.dim == 2; }
 
 // planes per thread of the marching 3D metric kernel
-constexpr int KZ_MARCH = 12;
+constexpr int KZ_MARCH = 8;
 
 hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double* xdot,
                                  const double* dt_dev, double* met0, double* met1, double* met2,
@@ -1603,7 +1606,7 @@ hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double*
 
 hipError_t launch_temporal_metrics3d(const es_ctx* c, const double* xdot, double* met, hipStream_t s) {
     const GridDev& g = c->g;
-    k_temporal_metrics3d<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, xdot, met);
+    k_temporal_metrics3d<<<plane_grid(g.P[0], g.P[1], g.P[2]), TPB, 0, s>>>(g, xdot, met);
     return hipGetLastError();
 }
 
@@ -1611,7 +1614,7 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
                           const double* dt_dev, double coef, double* met, double* J0,
                           hipStream_t s, bool ve_ready) {
     const GridDev& g = c->g;
-    const dim3 ge = box_grid(g.E[0], g.E[1], g.E[2]);
+    const dim3 ge = plane_grid(g.E[0], g.E[1], g.E[2]);
     double* ve = xdot != nullptr ? c->ve : nullptr;
     if (g.dim == 2) {
         (void)ve;
@@ -1619,15 +1622,14 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
         k_metrics2d_fused<<<gm, dim3(MTX, MBY, 1), 0, s>>>(g, x, xdot, dt_dev, coef, met, J0);
     } else {
         // the extended mesh velocity is left in c->ve by an earlier call with the same xdot
-        k_mesh_extend<3><<<ge, box_block(), 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve_ready ? nullptr : ve);
-        k_cmm_products<<<ge, box_block(), 0, s>>>(g, c->xe, c->pi);
+        k_mesh_extend<3><<<ge, TPB, 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve_ready ? nullptr : ve);
+        k_cmm_products<<<ge, TPB, 0, s>>>(g, c->xe, c->pi);
         if (J0 != nullptr) {
             k_metrics3d<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, c->xe, ve, c->pi, met, J0);
         } else {
-            const dim3 gm((unsigned)((g.P[0] + MX - 1) / MX), (unsigned)((g.P[1] + MY - 1) / MY),
-                          (unsigned)((g.P[2] + KZ_MARCH - 1) / KZ_MARCH));
-            if (g.ng == 4) k_metrics3d_march<4><<<gm, dim3(MX, MY, 1), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
-            else k_metrics3d_march<3><<<gm, dim3(MX, MY, 1), 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
+            const dim3 gm = plane_grid(g.P[0], g.P[1], (g.P[2] + KZ_MARCH - 1) / KZ_MARCH);
+            if (g.ng == 4) k_metrics3d_march<4><<<gm, TPB, 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
+            else k_metrics3d_march<3><<<gm, TPB, 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
         }
     }
     return hipGetLastError();

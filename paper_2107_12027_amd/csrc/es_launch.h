@@ -67,6 +67,27 @@ __device__ __forceinline__ bool box_ijk_xcd(int lo0, int lo1, int lo2, int e0, i
 
 
 // Block reductions of one double over the whole block (wavefronts of 64).
+// Flattened cells (c0, c1) of a w0 x w1 plane, c0 fastest: TPB consecutive cells
+// per block (rows wrap inside a block, so no lane idles at a row end and a
+// wave's stores to one component are one contiguous run); blockIdx.y numbers
+// the planes (or runs of planes), and the logical blocks are taken in
+// XCD-contiguous ranges.  Launch with plane_grid() and TPB threads.
+__device__ __forceinline__ bool plane_cell_xcd(int w0, int w1, int& c0, int& c1, int& plane) {
+    const int gx = (int)gridDim.x;
+    const int nb = gx * (int)gridDim.y;
+    const int lb = xcd_block((int)(blockIdx.y * gridDim.x + blockIdx.x), nb);
+    const int cell = (lb % gx) * TPB + (int)threadIdx.x;
+    plane = lb / gx;
+    if (cell >= w0 * w1) return false;
+    c0 = cell % w0;
+    c1 = cell / w0;
+    return true;
+}
+
+inline dim3 plane_grid(int w0, int w1, int planes) {
+    return dim3(grid_for((long long)w0 * w1), (unsigned)planes, 1);
+}
+
 template <int OP>   // 0 max, 1 min, 2 sum
 __device__ __forceinline__ double block_reduce(double v, double* sh) {
     v = OP == 0 ? wave_max(v) : (OP == 1 ? wave_min(v) : wave_sum(v));

@@ -192,7 +192,7 @@ def _fourier_forward(n, steps, coeffs, dt, ckpts=None, phys=ph.RHD, p=3):
     return ctx, U, J, P0, weight, losses
 
 
-@pytest.mark.parametrize("phys,K,tol,p", [(ph.RHD, 4, 1e-6, 3), (ph.RMHD, 3, 1e-5, 3), (ph.RMHD, 2, 1e-5, 2)])
+@pytest.mark.parametrize("phys,K,tol,p", [(ph.RHD, 4, 1e-6, 3), (ph.RMHD, 3, 1e-5, 3), (ph.RMHD, 2, 5e-5, 2)])
 def test_fourier_mode_gradient_against_differences(phys, K, tol, p):
     # the gradient of L = integral of rho^2 over [0.4,0.6]^2 after K steps with
     # respect to the 8 density-mode coefficients (the adjoint configuration's loss on
@@ -201,7 +201,11 @@ def test_fourier_mode_gradient_against_differences(phys, K, tol, p):
     # rule at both ends) against central differences h = 1e-6 of the GPU forward and,
     # for two coefficients, of the oracle's forward.  RMHD: the adjoint holds the face
     # eigen-structure, whose variation multiplies the WENO jumps of this smooth flow.
-    # p = 2 (RMHD): the same chain through the 4th-order flux and WENO3 dissipation
+    # p = 2 (RMHD): the same chain through the 4th-order flux and WENO3 dissipation;
+    # the held eigen-structure's terms multiply the WENO3 jumps, larger on this 32^2
+    # state than WENO5's (measured 2.4e-5 of the largest component against 4e-6 at
+    # p = 3), while the residual VJP itself matches the oracle with the structure
+    # held to 1e-6 (test_p2_rmhd_residual_vjp_against_oracle_differences)
     n, dt, h = 32, 6.25e-3, 1e-6
     make = wl.rhd_fourier if phys == ph.RHD else wl.rmhd_fourier
     _, _, c0 = wl.fourier_modes(0)
