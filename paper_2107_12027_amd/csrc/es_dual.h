@@ -129,6 +129,16 @@ __device__ __forceinline__ Dual<K> frcp(const Dual<K>& a) {
     const double r = 1.0 / a.v;
     return chain(a, r, -r * r);
 }
+// positive-argument forms of the forward path: the same values through the
+// general square root here (the adjoint's tangents need only the derivative)
+template <int K>
+__device__ __forceinline__ Dual<K> psqrt(const Dual<K>& a) {
+    return xsqrt(a);
+}
+template <int K>
+__device__ __forceinline__ Dual<K> frsqrt(const Dual<K>& a) {
+    return frcp(xsqrt(a));
+}
 template <int K>
 __device__ __forceinline__ Dual<K> fabs(const Dual<K>& a) {
     return a.v < 0.0 ? -a : a;

@@ -570,8 +570,8 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
         for (int c = 0; c < NU; ++c) uu += u[c] * u[c];
         sd[line][F_RHO][q] = rho;
         sd[line][F_P][q] = p;
-        sd[line][F_BETA][q] = rho / p;
-        sd[line][F_W][q] = sqrt(1.0 + uu);
+        sd[line][F_BETA][q] = rho * frcp(p);
+        sd[line][F_W][q] = psqrt(1.0 + uu);
         sd[line][F_LR][q] = lr;
         sd[line][F_LB][q] = lb;
 #pragma unroll

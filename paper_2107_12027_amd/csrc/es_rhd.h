@@ -42,6 +42,35 @@ __device__ __forceinline__ double xsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ double xexp(double x) { return exp(x); }
 __device__ __forceinline__ double xlog(double x) { return log(x); }
 
+// Reciprocal square root and square root of a positive, normal x (state and
+// metric quantities that are positive by construction): the hardware estimate
+// of 1/sqrt(x) refined by two Newton steps r <- r + r (1/2 - x r^2/2), each of
+// which squares the relative error, and for the root s = x r with one
+// correction s <- s + (x - s^2) r/2.  Unlike the general square root there is
+// no rescaling for denormal or zero arguments (a zero gives NaN), which saves
+// the range checks and two scalings per call.
+__device__ __forceinline__ double frsqrt(double x) {
+#ifdef ES_OPCOUNT_HOST
+    return 1.0 / sqrt(x);
+#else
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    double e = fma(-hx * r, r, 0.5);
+    r = fma(r, e, r);
+    e = fma(-hx * r, r, 0.5);
+    return fma(r, e, r);
+#endif
+}
+__device__ __forceinline__ double psqrt(double x) {
+#ifdef ES_OPCOUNT_HOST
+    return sqrt(x);
+#else
+    const double r = frsqrt(x);
+    const double s = x * r;
+    return fma(fma(-s, s, x), 0.5 * r, s);
+#endif
+}
+
 #ifndef ES_OPCOUNT_HOST
 // FP32 arithmetic of the mixed form: the hardware reciprocal, exp2 and log2
 // (about one ulp), a correctly rounded square root.
@@ -54,6 +83,8 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ float xsqrt(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ float xexp(float x) { return __expf(x); }
 __device__ __forceinline__ float xlog(float x) { return __logf(x); }
+__device__ __forceinline__ float frsqrt(float x) { return frcp(xsqrt(x)); }
+__device__ __forceinline__ float psqrt(float x) { return xsqrt(x); }
 #endif
 
 template <typename R>
@@ -430,7 +461,7 @@ __device__ __forceinline__ R face_eigen_columns(R G, const R* V2, const R* V3, R
     R vu2 = R(0.0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) vu2 += Vb[1 + a] * Vb[1 + a];
-    const R beta_f = xsqrt(Vb[M - 1] * Vb[M - 1] - vu2);
+    const R beta_f = psqrt(Vb[M - 1] * Vb[M - 1] - vu2);
     const R ib = frcp(beta_f);
     FaceRHD<DIM, R> fs;
     fs.beta = beta_f;
@@ -452,8 +483,8 @@ __device__ __forceinline__ R face_eigen_columns(R G, const R* V2, const R* V3, R
     const R h = R(1.0) + c0 * ib;
     fs.h = h;
     const R cs2 = G * ib * frcp(h);
-    const R cs = xsqrt(cs2);
-    const R disc = xsqrt((R(1.0) - v2) * (R(1.0) - v2 * cs2 - vn * vn * (R(1.0) - cs2)));
+    const R cs = psqrt(cs2);
+    const R disc = psqrt((R(1.0) - v2) * (R(1.0) - v2 * cs2 - vn * vn * (R(1.0) - cs2)));
     const R iden = frcp(R(1.0) - v2 * cs2);
     const R lam_m = (vn * (R(1.0) - cs2) - cs * disc) * iden;
     const R lam_p = (vn * (R(1.0) - cs2) + cs * disc) * iden;
@@ -485,7 +516,7 @@ __device__ __forceinline__ R face_eigen_columns(R G, const R* V2, const R* V3, R
         R nn = R(0.0);
 #pragma unroll
         for (int c = 0; c < M; ++c) nn += dU[c] * dV[c];
-        const R sc = frcp(xsqrt(nn));
+        const R sc = frsqrt(nn);
 #pragma unroll
         for (int c = 0; c < M; ++c) dU[c] *= sc;
         col(dU, s);
@@ -567,7 +598,7 @@ __device__ __forceinline__ R face_eigen_columns(R G, const R* V2, const R* V3, R
             for (int b = 0; b < NC; ++b) nn += cq[a] * Gm[a][b] * cq[b];
 #pragma unroll
         for (int a = 0; a < NC; ++a) cf[q][a] = cq[a];
-        const R rn = frcp(xsqrt(nn));
+        const R rn = frsqrt(nn);
         inq[q] = rn * rn;
         const R sc = rn;
         R r[M];
@@ -616,7 +647,7 @@ __device__ __forceinline__ void face_diss_rhd_fn(R G, R eps, NodeFn&& node, cons
     R ax[3] = {R(0.0), R(0.0), R(0.0)};
 #pragma unroll
     for (int j = 0; j < DIM; ++j) ax[j] = R(0.5) * (al[1 + j] + ar[1 + j]);
-    const R L = xsqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    const R L = psqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
     const R iL = frcp(L);
     R nrm[3] = {ax[0] * iL, ax[1] * iL, ax[2] * iL};
     R T[3][3];
