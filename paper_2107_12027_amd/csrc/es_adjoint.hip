@@ -139,9 +139,16 @@ __device__ __forceinline__ void weno3_grad(double a, double b, double c, double 
 }
 
 // P: the order parameter p (stencil of 2p nodes, WENO of order 2p - 1).
-template <int DIM, int P, typename NodeFn, typename Sync, typename Out>
+// gtv(j, c): the accumulator of the cotangent of the rotated entropy variable c of
+// stencil node j (a slot of the caller's LDS, the same slot that out(j, c, .)
+// later receives the primitive cotangent in); keeping these 2p x M sums out of
+// the registers is what lets the 3D kernel hold its column loop without spills.
+// gra(q, c): the cotangent of entry c of eigenvector column q, likewise an LDS
+// slot of the caller (it lives from the column loop through the eigen-structure
+// tangents, whose dual-number arithmetic needs the registers).
+template <int DIM, int P, typename NodeFn, typename Sync, typename GT, typename GRA, typename Out>
 __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, const double* al,
-                             const double* ar, const double* z, Out&& out) {
+                             const double* ar, const double* z, GT&& gtv, GRA&& gra, Out&& out) {
     constexpr int M = DIM + 2;
     constexpr int NS = 2 * P, CI = P - 1;
     const double at = 0.5 * (al[0] + ar[0]);
@@ -195,14 +202,12 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
         zr[1 + a] = s;
     }
 
-    double gR[M][M], gTV[NS][M], dd[M];
+    double dd[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
         dd[c] = 0.0;
 #pragma unroll
-        for (int q = 0; q < M; ++q) gR[q][c] = 0.0;
-#pragma unroll
-        for (int j = 0; j < NS; ++j) gTV[j][c] = 0.0;
+        for (int j = 0; j < NS; ++j) gtv(j, c) = 0.0;
     }
 #pragma unroll 1
     for (int q = 0; q < M; ++q) {
@@ -265,15 +270,13 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
                 const double gv = gjw * djw[j];
 #pragma unroll
                 for (int c = 0; c < M; ++c) {
-                    gTV[j][c] += gv * r[c];
+                    gtv(j, c) += gv * r[c];
                     gRq[c] += gv * TV[j][c];
                 }
             }
         }
 #pragma unroll
-        for (int qq = 0; qq < M; ++qq)
-#pragma unroll
-            for (int c = 0; c < M; ++c) gR[qq][c] = qq == q ? gRq[c] : gR[qq][c];
+        for (int c = 0; c < M; ++c) gra(q, c) = gRq[c];
     }
     double glhat = 0.0;
 #pragma unroll
@@ -283,6 +286,9 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
     // to out(j, c, value)
     auto to_prim = [&](int j) {
         const NodeRHD<DIM> q = node(j);
+        double gt[M];              // read all of node j's sums before out() reuses the slots
+#pragma unroll
+        for (int c = 0; c < M; ++c) gt[c] = gtv(j, c);
         const double ip = 1.0 / q.p, irho = 1.0 / q.rho;
         double su = 0.0;
 #pragma unroll
@@ -290,18 +296,21 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
             double tu = 0.0;
 #pragma unroll
             for (int b = 0; b < DIM; ++b) tu += T[a][b] * q.u[b];
-            su += gTV[j][1 + a] * tu;
+            su += gt[1 + a] * tu;
         }
         const double sbu = q.beta * su;
-        out(j, 0, gTV[j][0] * ((1.0 + c1) * irho + ip) + su * ip - gTV[j][M - 1] * q.W * ip);
-        out(j, M - 1, -gTV[j][0] * (c1 + q.beta) * ip - sbu * ip + gTV[j][M - 1] * q.beta * q.W * ip);
+        double res[M];
+        res[0] = gt[0] * ((1.0 + c1) * irho + ip) + su * ip - gt[M - 1] * q.W * ip;
+        res[M - 1] = -gt[0] * (c1 + q.beta) * ip - sbu * ip + gt[M - 1] * q.beta * q.W * ip;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
             double s = 0.0;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) s += T[a][b] * gTV[j][1 + a];
-            out(j, 1 + b, q.beta * s - gTV[j][M - 1] * q.beta * q.u[b] / q.W);
+            for (int a = 0; a < DIM; ++a) s += T[a][b] * gt[1 + a];
+            res[1 + b] = q.beta * s - gt[M - 1] * q.beta * q.u[b] / q.W;
         }
+#pragma unroll
+        for (int c = 0; c < M; ++c) out(j, c, res[c]);
     };
     // the outer stencil nodes are complete before the eigen-structure tangents
     sync();
@@ -323,14 +332,15 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
         double dir = 0.0;
         const D1 lh = face_eigen_columns<DIM>(D1(G), Vd, Vd, D1(at), D1(L), [&](const D1* r, int q) {
 #pragma unroll
-            for (int c = 0; c < M; ++c) dir += gR[q][c] * r[c].d[0];
+            for (int c = 0; c < M; ++c) dir += gra(q, c) * r[c].d[0];
         });
         dir += glhat * lh.d[0];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            const double a = c == k ? 0.5 * dir : 0.0;
-            gTV[CI][c] += a;
-            gTV[CI + 1][c] += a;
+            if (c == k) {
+                gtv(CI, c) += 0.5 * dir;
+                gtv(CI + 1, c) += 0.5 * dir;
+            }
         }
     }
     sync();
@@ -352,6 +362,7 @@ struct AdjLDS {
     double sd[ALINES][NF][ALOAD];
     double lam[ALINES][M][ALOAD];
     double buf[ALINES][6][M][64];
+    double gr[ALINES][M][M][64];     // cotangents of the face eigenvector columns
 };
 
 struct AdjPlan {
@@ -521,6 +532,8 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
             // the fence makes the later stages reread the stencil from LDS
             face_vjp_rhd<DIM, PO>(G, eps, [&](int j) { return node_at(lane + 3 - PO + j); },
                               [] { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); }, al, ar, z,
+                              [&](int j, int c) -> double& { return buf[line][j][c][lane]; },
+                              [&](int q, int c) -> double& { return lds.gr[line][q][c][lane]; },
                               [&](int j, int c, double v) { buf[line][j][c][lane] = v; });
         } else {
 #pragma unroll
