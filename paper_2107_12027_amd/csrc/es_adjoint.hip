@@ -12,8 +12,8 @@
 //   * ghost folding: cotangents of ghost nodes go to the interior nodes they copy;
 //   * con2prim by the implicit-function rule: dP/dU = (dU/dP)^{-1}, so the state
 //     cotangent solves (dU/dP)^T y = g_P at every node.
-// Local Jacobians: the two-point flux by forward-mode dual numbers (one node's
-// primitive variables at a time); the face dissipation by reverse accumulation
+// Local Jacobians: the two-point flux by a hand-written backward sweep
+// (es_pair_vjp.h, both nodes at once); the face dissipation by reverse accumulation
 // through the projections, WENO (dual numbers over the six characteristic
 // values) and the final combination, plus forward-mode tangents of the face
 // eigen-structure over the face entropy variables.  The sign switch Y, the branch
@@ -24,66 +24,11 @@
 #include "es_launch.h"
 #include "es_rhd.h"
 #include "es_dual.h"
+#include "es_pair_vjp.h"
 
 namespace es {
 
 namespace {
-
-// Node state with its derived quantities from primitive (rho, u, p).
-template <int NU, typename R>
-__device__ __forceinline__ NodeRHD<NU, R> node_from_prim(const R& rho, const R* u, const R& p) {
-    NodeRHD<NU, R> n;
-    n.rho = rho;
-    n.p = p;
-    R uu = R(0.0);
-#pragma unroll
-    for (int k = 0; k < NU; ++k) { n.u[k] = u[k]; uu += u[k] * u[k]; }
-    n.W = xsqrt(R(1.0) + uu);
-    n.beta = rho / p;
-    n.lr = xlog(rho);
-    n.lb = xlog(n.beta);
-    return n;
-}
-
-// Cotangents of the primitive states of the two nodes of a pair flux:
-// gl = (dF/dP_l)^T w, gr = (dF/dP_r)^T w  (P = (rho, u_1..u_NU, p)).
-template <int NU, int SIDE>
-__device__ __forceinline__ void pair_vjp_rhd_side(double G, const double* Pl, const double* Pr, const double* al,
-                                                  const double* ar, const double* w, double* g) {
-    constexpr int M = NU + 2;
-    using D = Dual<M>;
-    D rl = SIDE == 0 ? D::seed(Pl[0], 0) : D(Pl[0]);
-    D pl = SIDE == 0 ? D::seed(Pl[M - 1], M - 1) : D(Pl[M - 1]);
-    D rr = SIDE == 1 ? D::seed(Pr[0], 0) : D(Pr[0]);
-    D pr = SIDE == 1 ? D::seed(Pr[M - 1], M - 1) : D(Pr[M - 1]);
-    D ul[NU], ur[NU];
-#pragma unroll
-    for (int k = 0; k < NU; ++k) {
-        ul[k] = SIDE == 0 ? D::seed(Pl[1 + k], 1 + k) : D(Pl[1 + k]);
-        ur[k] = SIDE == 1 ? D::seed(Pr[1 + k], 1 + k) : D(Pr[1 + k]);
-    }
-    const NodeRHD<NU, D> l = node_from_prim<NU>(rl, ul, pl);
-    const NodeRHD<NU, D> r = node_from_prim<NU>(rr, ur, pr);
-    D F[M];
-    double Jt;
-    pair_flux_rhd<NU>(G, l, r, al, ar, F, Jt);
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < M; ++c) s += w[c] * F[c].d[i];
-        g[i] = s;
-    }
-}
-
-// (the side is a template parameter so that the unseeded node's zero tangents
-// fold away)
-template <int NU>
-__device__ void pair_vjp_rhd(double G, const double* Pl, const double* Pr, const double* al,
-                             const double* ar, const double* w, double* gl, double* gr) {
-    pair_vjp_rhd_side<NU, 0>(G, Pl, Pr, al, ar, w, gl);
-    pair_vjp_rhd_side<NU, 1>(G, Pl, Pr, al, ar, w, gr);
-}
 
 // Cotangents g[j] (j = 0..5, primitive slots) of the stencil states of one face
 // dissipation d (face_diss_rhd) for the cotangent z of d.
