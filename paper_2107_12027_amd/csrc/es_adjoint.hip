@@ -14,9 +14,9 @@
 //     cotangent solves (dU/dP)^T y = g_P at every node.
 // Local Jacobians: the two-point flux by a hand-written backward sweep
 // (es_pair_vjp.h, both nodes at once); the face dissipation by reverse accumulation
-// through the projections, WENO (dual numbers over the six characteristic
-// values) and the final combination, plus forward-mode tangents of the face
-// eigen-structure over the face entropy variables.  The sign switch Y, the branch
+// through the projections, WENO (its gradient written out) and the final
+// combination, and a backward sweep through the face eigen-structure
+// (es_eigen_vjp.h) to the face entropy variables.  The sign switch Y, the branch
 // of lambda^, the time step, the mesh and its velocity are held fixed.
 #include <math.h>
 
@@ -25,6 +25,7 @@
 #include "es_rhd.h"
 #include "es_dual.h"
 #include "es_pair_vjp.h"
+#include "es_eigen_vjp.h"
 
 namespace es {
 
@@ -263,30 +264,17 @@ __device__ void face_vjp_rhd(double G, double eps, NodeFn&& node, Sync&& sync, c
     for (int j = 0; j < NS; ++j)
         if (j != CI && j != CI + 1) to_prim(j);
 
-    // face eigen-structure: tangents along each face entropy variable (they
-    // reach nodes i and i+1 through the face mean of the entropy variables)
-    using D1 = Dual<1>;
-    double Vb[M];
+    // face eigen-structure: one backward sweep from the column and lambda^
+    // cotangents to the face entropy variables, which reach nodes i and i+1
+    // through the face mean
+    double Vb[M], gVb[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) Vb[c] = 0.5 * (TV[CI][c] + TV[CI + 1][c]);
-#pragma unroll 1
-    for (int k = 0; k < M; ++k) {
-        D1 Vd[M];
+    face_eigen_vjp<DIM>(G, Vb, at, L, gra, glhat, gVb);
 #pragma unroll
-        for (int c = 0; c < M; ++c) Vd[c] = c == k ? D1::seed(Vb[c], 0) : D1(Vb[c]);
-        double dir = 0.0;
-        const D1 lh = face_eigen_columns<DIM>(D1(G), Vd, Vd, D1(at), D1(L), [&](const D1* r, int q) {
-#pragma unroll
-            for (int c = 0; c < M; ++c) dir += gra(q, c) * r[c].d[0];
-        });
-        dir += glhat * lh.d[0];
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-            if (c == k) {
-                gtv(CI, c) += 0.5 * dir;
-                gtv(CI + 1, c) += 0.5 * dir;
-            }
-        }
+    for (int c = 0; c < M; ++c) {
+        gtv(CI, c) += 0.5 * gVb[c];
+        gtv(CI + 1, c) += 0.5 * gVb[c];
     }
     sync();
     to_prim(CI);
