@@ -64,7 +64,7 @@ RESIDUAL_FLOPS_PER_NODE_3D_RMHD = 111738.6
 # with their commands are the es_residual_hbm_counters_* files under profiles/.
 RESIDUAL_TRAFFIC_BYTES = {
     "rhd2d_quadrant_riemann_400_seed2": 57.74e6,
-    "rhd3d_blast_128": 1328.8e6,
+    "rhd3d_blast_128": 1322.1e6,
 }
 
 

@@ -32,7 +32,8 @@ struct es_ctx {
     double* wb;     // interior (monitor pong)
     double* xe;     // stage mesh on the extension box (d comps)
     double* ve;     // mesh velocity on the extension box (d comps)
-    double* pi;     // 3D: conservative-metric products on the extension box (9 comps)
+    double* pi;     // 3D: conservative-metric products on the extension box (9 comps; the
+                    // metrics with J^0)
     double* red;    // reduction partials
     double* scal;   // device scalars: [0] dt, [1] gmax, [2] dtau, [3..] spare
     unsigned long long* fail;   // [0] count inadmissible, [1] count no-convergence, [2] first index

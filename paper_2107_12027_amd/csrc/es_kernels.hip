@@ -365,101 +365,235 @@ __global__ void k_metrics3d(GridDev g, const double* __restrict__ xe, const doub
     }
 }
 
-// The same metrics marching along xi_3: each thread owns one (i, j) column of the
-// padded box and a run of kz consecutive planes.  The products differenced along
-// xi_3 (Pi_{1,.} for J dxi_1/dx_., Pi_{0,.} for J dxi_2/dx_.) stay in a register
-// window of 2H + 1 planes, so each is read once per plane instead of 2H times;
-// the differences within a plane read their neighbours through L1/L2.  The
-// columns of a plane are flattened (plane_cell_xcd: no idle lanes at row ends,
-// each wave's store of a component one contiguous run) and the metrics are
-// written with non-temporal stores (they are not read again here; with ordinary
-// stores the kernel took 220 instead of 141 us at 128^3).
+// The 3D metric differences in one pass after the stage mesh is extended: from the
+// extended stage mesh (and mesh velocity) straight to the 12 padded metric
+// components, the CMM products (eq. SCLCoeff) formed on the fly instead of in HBM.
+// A block owns a 16 x 16 tile of padded (i, j) columns and marches through kz
+// planes, with three threads per column, one per mesh component c (and, for the
+// products Pi_{a,jj}, one per jj = c).  Each thread keeps its component of the stage
+// mesh at planes k - H .. k + H for its own column and for one position of the
+// H-wide cross-shaped halo, and the products Pi_{0,jj}, Pi_{1,jj} of its own column
+// at the same planes (they are differenced along xi_3), in registers.  Per plane
+// the block stages in LDS the mesh at the leading plane k + H (tile and cross), the
+// mesh at the centre plane k (whole square: the corners are read directly) and its
+// xi_3 differences (tile and cross), and the products Pi_{2,.} (tile and cross),
+// Pi_{0,.} (tile and xi_2 strips) and Pi_{1,.} (tile and xi_1 strips) at the centre
+// plane; the temporal part J dxi_k/dt = -sum_jj xdot_jj (J dxi_k/dx_jj) is summed
+// from the row of spatial metrics left in LDS, at the start of the next plane.  The
+// sums (in n order), the products and the temporal sum (in jj order) are those of
+// k_cmm_products + k_metrics3d; the metric differences are scaled by the reciprocal
+// of dxi_{k+1} dxi_{k+2}.  Every global load of a plane is issued one plane ahead,
+// from clamped (always valid) addresses and outside any branch, so that its wait
+// falls in the next plane.  The kernel is bound by LDS traffic (about 1.5 KB per
+// node and plane); the three-kernel form it replaces (products in HBM, then a
+// marching difference kernel reading them through L1/L2) took about twice as long.
+constexpr int MT = 16;
+constexpr int MT_THREADS = 3 * MT * MT;
+
 template <int H>
-__global__ void __launch_bounds__(TPB) k_metrics3d_march(GridDev g, const double* __restrict__ ve,
-                                                         const double* __restrict__ pi,
-                                                         double* __restrict__ met, int kz) {
-    int i, j, bz;
-    if (!plane_cell_xcd(g.P[0], g.P[1], i, j, bz)) return;
-    i -= g.ng; j -= g.ng;
-    const int kb = -g.ng + bz * kz;
-    const int ke = min(kb + kz, g.n[2] + g.ng);
-    const long long EN = g.enodes, P = g.pnodes;
-    const long long sx = 1, sy = g.E[0], sz = (long long)g.E[0] * g.E[1];
+struct MetTile {
+    double xl[3][MT + 2 * H][MT + 2 * H];   // mesh at the leading plane (tile and cross)
+    double xc[3][MT + 2 * H][MT + 2 * H];   // mesh at the centre plane (whole square)
+    double dz[3][MT + 2 * H][MT + 2 * H];   // delta_3 of the mesh, centre plane (tile and cross)
+    double p2[3][MT + 2 * H][MT + 2 * H];   // Pi_{2,.}, centre plane (tile and cross)
+    double p0[3][MT + 2 * H][MT];           // Pi_{0,.}, centre plane (tile and xi_2 strips)
+    double p1[3][MT][MT + 2 * H];           // Pi_{1,.}, centre plane (tile and xi_1 strips)
+    double m[3][3][MT * MT];                // J dxi_kk/dx_jj of the centre plane, [kk][jj][column]
+};
+
+// offset of extension-box node (i, j, 0), each index clamped into the box
+__device__ __forceinline__ long long eidx_clamped(const GridDev& g, int i, int j) {
+    const int e = 2 * g.ng;
+    return eidx(g, min(max(i, -e), g.n[0] + e - 1), min(max(j, -e), g.n[1] + e - 1), 0);
+}
+
+template <int H>
+__global__ void __launch_bounds__(MT_THREADS) k_metrics3d_tile(GridDev g, const double* __restrict__ xe,
+                                                               const double* __restrict__ ve,
+                                                               double* __restrict__ met, int kz, int tiles0,
+                                                               int tiles1) {
+    constexpr int NCROSS = 4 * H * MT;
+    constexpr int NCORNER = 4 * H * H;
+    static_assert(NCROSS <= MT * MT && NCORNER <= MT * MT, "one halo position of each kind per thread");
+    __shared__ MetTile<H> sm;
+    const int c = (int)threadIdx.x / (MT * MT);   // mesh component (and jj) of this thread
+    const int u = (int)threadIdx.x % (MT * MT);   // column of the tile
+    const int j1 = (c + 1) % 3, j2 = (c + 2) % 3;
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int bx = lb % tiles0, by = (lb / tiles0) % tiles1, bz = lb / (tiles0 * tiles1);
+    const int i0 = -g.ng + bx * MT, j0 = -g.ng + by * MT;
+    const int kb = -g.ng + bz * kz, ke = min(kb + kz, g.n[2] + g.ng);
+    // own column: square position (H + tx, H + ty)
+    const int tx = u % MT, ty = u / MT;
+    const int oi = i0 + tx, oj = j0 + ty;
+    const bool store = oi < g.n[0] + g.ng && oj < g.n[1] + g.ng;
+    // cross position: the xi_2 strips (rows 0..H-1 and MT+H..MT+2H-1 of the square)
+    // first, then the xi_1 strips
+    const bool has_c = u < NCROSS;
+    const bool ystrip = u < 2 * H * MT;
+    int cx = H, cy = H;
+    if (ystrip) {
+        const int r = u / MT;
+        cx = H + u % MT;
+        cy = r < H ? r : MT + r;
+    } else if (has_c) {
+        const int v = u - 2 * H * MT, r = v % (2 * H);
+        cy = H + v / (2 * H);
+        cx = r < H ? r : MT + r;
+    }
+    // corner position
+    const bool has_k = u < NCORNER;
+    int kx = 0, ky = 0;
+    if (has_k) {
+        const int r = u / (2 * H), q = u % (2 * H);
+        ky = r < H ? r : MT + r;
+        kx = q < H ? q : MT + q;
+    }
     double a[H + 1];
 #pragma unroll
     for (int n = 1; n <= H; ++n) a[n] = 0.5 * alpha_pn(g.p, n);
     const double c01 = 1.0 / (g.dxi[1] * g.dxi[2]), c20 = 1.0 / (g.dxi[2] * g.dxi[0]),
                  c12 = 1.0 / (g.dxi[0] * g.dxi[1]);
-    const double* p0 = pi;              // Pi_{0, jj} at comps 0..2
-    const double* p1 = pi + 3 * EN;     // Pi_{1, jj} at comps 3..5
-    const double* p2 = pi + 6 * EN;     // Pi_{2, jj} at comps 6..8
-    // window of the xi_3-differenced products at planes k - H .. k + H
-    double w0[2 * H + 1][3], w1[2 * H + 1][3];
-    long long e = eidx(g, i, j, kb);
+    const long long P = g.pnodes, EN = g.enodes;
+    const long long tz = (long long)g.P[0] * g.P[1], sz = (long long)g.E[0] * g.E[1];
+    // plane-0 offsets of the positions in the extension box (clamped: the positions
+    // outside it belong to the ragged edge of the last tiles and are never used)
+    const long long eo = eidx_clamped(g, oi, oj);
+    const long long ec = eidx_clamped(g, i0 - H + cx, j0 - H + cy);
+    const long long ek = eidx_clamped(g, i0 - H + kx, j0 - H + ky);
+    const double* vsrc = ve != nullptr ? ve : xe;
+    const double* xec = xe + c * EN;
+    const int zlo = -2 * g.ng, zhi = g.n[2] + 2 * g.ng - 1;
+    // windows (planes L - 2H .. L of the leading plane L): component c of the mesh at
+    // the own column and at the cross position; Pi_{0,c}, Pi_{1,c} of the own column
+    double wo[2 * H + 1], wc[2 * H + 1], w0[2 * H + 1], w1[2 * H + 1];
 #pragma unroll
-    for (int q = 0; q < 2 * H; ++q) {
-        const long long eq = e + (long long)(q - H) * sz;
+    for (int q = 0; q <= 2 * H; ++q) wo[q] = wc[q] = w0[q] = w1[q] = 0.0;
+    // loads of leading plane L: component c of the mesh at the own column and the
+    // cross position, of the corner's mesh at the centre plane L - H, and the three
+    // components of the mesh velocity at the own column on the centre plane
+    double no, nc, nk, nv[3];
+    auto prefetch = [&](int L) {
+        const long long zl = (long long)min(max(L, zlo), zhi) * sz;
+        const long long zk = (long long)min(max(L - H, zlo), zhi) * sz;
+        no = xec[eo + zl];
+        nc = xec[ec + zl];
+        nk = xec[ek + zk];
 #pragma unroll
-        for (int jj = 0; jj < 3; ++jj) {
-            w0[q][jj] = p0[jj * EN + eq];
-            w1[q][jj] = p1[jj * EN + eq];
-        }
-    }
-    long long t = pidx(g, i, j, kb);
-    const long long tz = (long long)g.P[0] * g.P[1];
-    for (int k = kb; k < ke; ++k, e += sz, t += tz) {
-        const long long en = e + (long long)H * sz;
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj) {
-            w0[2 * H][jj] = p0[jj * EN + en];
-            w1[2 * H][jj] = p1[jj * EN + en];
-        }
-        double m[3][3];
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj) {
-            double ta0 = 0.0, tb0 = 0.0, ta1 = 0.0, tb1 = 0.0, ta2 = 0.0, tb2 = 0.0;
-            const double* q0 = p0 + jj * EN + e;
-            const double* q1 = p1 + jj * EN + e;
-            const double* q2 = p2 + jj * EN + e;
-#pragma unroll
-            for (int n = 1; n <= H; ++n) {
-                // row 0 (k1 = 1, k2 = 2): Pi_{1,jj} along xi_3 minus Pi_{2,jj} along xi_2
-                ta0 += a[n] * (w1[H + n][jj] - w1[H - n][jj]);
-                tb0 += a[n] * (q2[n * sy] - q2[-n * sy]);
-                // row 1 (k1 = 2, k2 = 0): Pi_{2,jj} along xi_1 minus Pi_{0,jj} along xi_3
-                ta1 += a[n] * (q2[n * sx] - q2[-n * sx]);
-                tb1 += a[n] * (w0[H + n][jj] - w0[H - n][jj]);
-                // row 2 (k1 = 0, k2 = 1): Pi_{0,jj} along xi_2 minus Pi_{1,jj} along xi_1
-                ta2 += a[n] * (q0[n * sy] - q0[-n * sy]);
-                tb2 += a[n] * (q1[n * sx] - q1[-n * sx]);
-            }
-            m[0][jj] = (ta0 - tb0) * c01;
-            m[1][jj] = (ta1 - tb1) * c20;
-            m[2][jj] = (ta2 - tb2) * c12;
-        }
-        double v[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < 3; ++q) nv[q] = vsrc[q * EN + eo + zk];
+    };
+    // temporal metric kk = c of the plane whose spatial metrics are in sm.m
+    auto temporal = [&](const double* v, long long t) {
+        double at = 0.0;
         if (ve != nullptr) {
 #pragma unroll
-            for (int jj = 0; jj < 3; ++jj) v[jj] = ve[jj * EN + e];
+            for (int jj = 0; jj < 3; ++jj) at -= v[jj] * sm.m[c][jj][u];
         }
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-            double at = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < 3; ++jj) at -= v[jj] * m[kk][jj];
-            __builtin_nontemporal_store(at, &met[(kk * 4) * P + t]);
-#pragma unroll
-            for (int jj = 0; jj < 3; ++jj) __builtin_nontemporal_store(m[kk][jj], &met[(kk * 4 + 1 + jj) * P + t]);
-        }
+        __builtin_nontemporal_store(at, &met[(c * 4) * P + t]);
+    };
+    prefetch(kb - H);
+    long long tout = pidx(g, oi, oj, kb);
+    double vp[3] = {0.0, 0.0, 0.0};   // mesh velocity of the previous centre plane
+    for (int L = kb - H; L < ke + H; ++L) {
+        const int k = L - H;
+        const bool centre = k >= kb;
+        // the previous centre plane's temporal metric (its row of sm.m is complete)
+        if (k - 1 >= kb && store) temporal(vp, tout - tz);
 #pragma unroll
         for (int q = 0; q < 2 * H; ++q) {
+            wo[q] = wo[q + 1];
+            wc[q] = wc[q + 1];
+            w0[q] = w0[q + 1];
+            w1[q] = w1[q + 1];
+        }
+        wo[2 * H] = no;
+        wc[2 * H] = nc;
+        const double kv = nk;
+        double vv[3];
 #pragma unroll
-            for (int jj = 0; jj < 3; ++jj) {
-                w0[q][jj] = w0[q + 1][jj];
-                w1[q][jj] = w1[q + 1][jj];
+        for (int q = 0; q < 3; ++q) vv[q] = nv[q];
+        prefetch(L + 1);
+        // leading plane (tile and cross) and, from the first centre plane on, the
+        // centre mesh and its xi_3 differences
+        sm.xl[c][H + ty][H + tx] = wo[2 * H];
+        if (has_c) sm.xl[c][cy][cx] = wc[2 * H];
+        if (centre) {
+            sm.xc[c][H + ty][H + tx] = wo[H];
+            if (has_c) sm.xc[c][cy][cx] = wc[H];
+            if (has_k) sm.xc[c][ky][kx] = kv;
+            double d = 0.0, e = 0.0;
+#pragma unroll
+            for (int n = 1; n <= H; ++n) {
+                d += a[n] * (wo[H + n] - wo[H - n]);
+                e += a[n] * (wc[H + n] - wc[H - n]);
+            }
+            sm.dz[c][H + ty][H + tx] = d;
+            if (has_c) sm.dz[c][cy][cx] = e;
+        }
+        __syncthreads();
+        // Pi_{0,c} and Pi_{1,c} of the own column at the leading plane
+        {
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int n = 1; n <= H; ++n) {
+                d0 += a[n] * (sm.xl[j1][H + ty][H + tx + n] - sm.xl[j1][H + ty][H + tx - n]);
+                d1 += a[n] * (sm.xl[j1][H + ty + n][H + tx] - sm.xl[j1][H + ty - n][H + tx]);
+            }
+            const double x2 = sm.xl[j2][H + ty][H + tx];
+            w0[2 * H] = d0 * x2;
+            w1[2 * H] = d1 * x2;
+        }
+        if (centre) {
+            // centre-plane Pi_{2,c} = delta_3[x_{c+1}] x_{c+2} (tile and cross), Pi_{0,c}
+            // (tile from the window, xi_2 strips) and Pi_{1,c} (tile, xi_1 strips)
+            sm.p2[c][H + ty][H + tx] = sm.dz[j1][H + ty][H + tx] * sm.xc[j2][H + ty][H + tx];
+            sm.p0[c][H + ty][tx] = w0[H];
+            sm.p1[c][ty][H + tx] = w1[H];
+            if (has_c) {
+                sm.p2[c][cy][cx] = sm.dz[j1][cy][cx] * sm.xc[j2][cy][cx];
+                double d = 0.0;
+                if (ystrip) {
+#pragma unroll
+                    for (int n = 1; n <= H; ++n) d += a[n] * (sm.xc[j1][cy][cx + n] - sm.xc[j1][cy][cx - n]);
+                    sm.p0[c][cy][cx - H] = d * sm.xc[j2][cy][cx];
+                } else {
+#pragma unroll
+                    for (int n = 1; n <= H; ++n) d += a[n] * (sm.xc[j1][cy + n][cx] - sm.xc[j1][cy - n][cx]);
+                    sm.p1[c][cy - H][cx] = d * sm.xc[j2][cy][cx];
+                }
             }
         }
+        __syncthreads();
+        if (centre && store) {
+            double ta0 = 0.0, tb0 = 0.0, ta1 = 0.0, tb1 = 0.0, ta2 = 0.0, tb2 = 0.0;
+#pragma unroll
+            for (int n = 1; n <= H; ++n) {
+                // row 0: Pi_{1,c} along xi_3 minus Pi_{2,c} along xi_2
+                ta0 += a[n] * (w1[H + n] - w1[H - n]);
+                tb0 += a[n] * (sm.p2[c][H + ty + n][H + tx] - sm.p2[c][H + ty - n][H + tx]);
+                // row 1: Pi_{2,c} along xi_1 minus Pi_{0,c} along xi_3
+                ta1 += a[n] * (sm.p2[c][H + ty][H + tx + n] - sm.p2[c][H + ty][H + tx - n]);
+                tb1 += a[n] * (w0[H + n] - w0[H - n]);
+                // row 2: Pi_{0,c} along xi_2 minus Pi_{1,c} along xi_1
+                ta2 += a[n] * (sm.p0[c][H + ty + n][tx] - sm.p0[c][H + ty - n][tx]);
+                tb2 += a[n] * (sm.p1[c][ty][H + tx + n] - sm.p1[c][ty][H + tx - n]);
+            }
+            const double m0 = (ta0 - tb0) * c01, m1 = (ta1 - tb1) * c20, m2 = (ta2 - tb2) * c12;
+            sm.m[0][c][u] = m0;
+            sm.m[1][c][u] = m1;
+            sm.m[2][c][u] = m2;
+            __builtin_nontemporal_store(m0, &met[(0 * 4 + 1 + c) * P + tout]);
+            __builtin_nontemporal_store(m1, &met[(1 * 4 + 1 + c) * P + tout]);
+            __builtin_nontemporal_store(m2, &met[(2 * 4 + 1 + c) * P + tout]);
+        }
+        if (centre) {
+            tout += tz;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) vp[q] = vv[q];
+        }
+        __syncthreads();
     }
+    if (store) temporal(vp, tout - tz);
 }
 
 // Temporal metrics J dxi_k/dt = -sum_j xdot_j (J dxi_k/dx_j) of a mesh whose
@@ -1592,8 +1726,15 @@ hipError_t launch_combine_con2prim(const es_ctx* c, int stage, const double* U0,
 
 bool metrics_stages_batched(const es_ctx* c) { return c->g.dim == 2; }
 
-// planes per thread of the marching 3D metric kernel
-constexpr int KZ_MARCH = 8;
+// planes per block of the 3D metric tile kernel: one block per compute unit at a
+// time (its LDS), so the runs of planes are cut to fill the 256 compute units once
+// (128^3: 9 x 9 tiles x 3 runs of 45 planes), and are at least 2H + 1 planes long
+static int metric_tile_planes(const GridDev& g) {
+    const int tiles = ((g.P[0] + MT - 1) / MT) * ((g.P[1] + MT - 1) / MT);
+    const int runs = tiles >= 256 ? 1 : 256 / tiles;
+    const int kz = (g.P[2] + runs - 1) / runs;
+    return kz < 2 * NG_MAX + 1 ? 2 * NG_MAX + 1 : kz;
+}
 
 hipError_t launch_metrics_stages(const es_ctx* c, const double* x, const double* xdot,
                                  const double* dt_dev, double* met0, double* met1, double* met2,
@@ -1621,15 +1762,19 @@ hipError_t launch_metrics(const es_ctx* c, const double* x, const double* xdot,
         const dim3 gm((unsigned)((g.P[0] + MTX - 1) / MTX), (unsigned)((g.P[1] + MTY - 1) / MTY), 1);
         k_metrics2d_fused<<<gm, dim3(MTX, MBY, 1), 0, s>>>(g, x, xdot, dt_dev, coef, met, J0);
     } else {
-        // the extended mesh velocity is left in c->ve by an earlier call with the same xdot
-        k_mesh_extend<3><<<ge, TPB, 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve_ready ? nullptr : ve);
-        k_cmm_products<<<ge, TPB, 0, s>>>(g, c->xe, c->pi);
         if (J0 != nullptr) {
+            // with the Jacobian J^0 (set-up, not a stage): extended mesh and products in HBM
+            k_mesh_extend<3><<<ge, TPB, 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve);
+            k_cmm_products<<<ge, TPB, 0, s>>>(g, c->xe, c->pi);
             k_metrics3d<<<box_grid(g.P[0], g.P[1], g.P[2]), box_block(), 0, s>>>(g, c->xe, ve, c->pi, met, J0);
         } else {
-            const dim3 gm = plane_grid(g.P[0], g.P[1], (g.P[2] + KZ_MARCH - 1) / KZ_MARCH);
-            if (g.ng == 4) k_metrics3d_march<4><<<gm, TPB, 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
-            else k_metrics3d_march<3><<<gm, TPB, 0, s>>>(g, ve, c->pi, met, KZ_MARCH);
+            // the extended mesh velocity is left in c->ve by an earlier call with the same xdot
+            k_mesh_extend<3><<<ge, TPB, 0, s>>>(g, x, xdot, dt_dev, coef, c->xe, ve_ready ? nullptr : ve);
+            const int t0 = (g.P[0] + MT - 1) / MT, t1 = (g.P[1] + MT - 1) / MT;
+            const int kz = metric_tile_planes(g);
+            const unsigned nb = (unsigned)(t0 * t1 * ((g.P[2] + kz - 1) / kz));
+            if (g.ng == 4) k_metrics3d_tile<4><<<nb, MT_THREADS, 0, s>>>(g, c->xe, ve, met, kz, t0, t1);
+            else k_metrics3d_tile<3><<<nb, MT_THREADS, 0, s>>>(g, c->xe, ve, met, kz, t0, t1);
         }
     }
     return hipGetLastError();
