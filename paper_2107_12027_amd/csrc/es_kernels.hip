@@ -136,6 +136,25 @@ __global__ void k_mesh_extend(GridDev g, const double* __restrict__ x, const dou
     const long long t = eidx(g, i, j, k);
     const double cdt = dt_dev != nullptr ? coef * dt_dev[0] : 0.0;
     const double* xs = dt_dev != nullptr ? xd : nullptr;
+    if (i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] && (DIM == 2 || (k >= 0 && k < g.n[2]))) {
+        // interior node: every load issued before the first use (mesh_value's value
+        // for an interior node, the velocity loaded once for both outputs)
+        const long long nd = iidx(g, i, j, DIM == 2 ? 0 : k);
+        double xv[DIM], dv[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            xv[c] = x[c * g.nodes + nd];
+            dv[c] = xd != nullptr ? xd[c * g.nodes + nd] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            double v = xv[c];
+            if (xs != nullptr) v += cdt * dv[c];
+            xe[c * g.enodes + t] = v;
+            if (ve != nullptr) ve[c * g.enodes + t] = dv[c];
+        }
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         xe[c * g.enodes + t] = mesh_value(g, x, xs, cdt, c, i, j, k, true);
@@ -605,14 +624,25 @@ __global__ void k_temporal_metrics3d(GridDev g, const double* __restrict__ xd, d
     i -= g.ng; j -= g.ng; k -= g.ng;
     const long long t = pidx(g, i, j, k);
     const long long P = g.pnodes;
-    double v[3];
+    // the spatial metrics, then the mesh velocity (loaded together at interior nodes)
+    double m[3][3], v[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[c] = mesh_value(g, xd, nullptr, 0.0, c, i, j, k, false);
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) m[kk][jj] = met[(kk * 4 + 1 + jj) * P + t];
+    if (i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] && k >= 0 && k < g.n[2]) {
+        const long long nd = iidx(g, i, j, k);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = xd[c * g.nodes + nd];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = mesh_value(g, xd, nullptr, 0.0, c, i, j, k, false);
+    }
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
         double at = 0.0;
 #pragma unroll
-        for (int jj = 0; jj < 3; ++jj) at -= v[jj] * met[(kk * 4 + 1 + jj) * P + t];
+        for (int jj = 0; jj < 3; ++jj) at -= v[jj] * m[kk][jj];
         met[(kk * 4) * P + t] = at;
     }
 }
@@ -1068,19 +1098,24 @@ __device__ __forceinline__ void finalize_dt(const DtFinal& f, double* sh) {
         if (flat_tid() == 0) f.dt_out[0] = f.fixed_dt[0];
         return;
     }
-    double tot = 0.0;
+    // the slabs' partials are read in one unrolled loop, several loads in flight
     const int tid = flat_tid(), nt = (int)(blockDim.x * blockDim.y * blockDim.z);
-    for (int kd = 0; kd < f.dim; ++kd) {
-        double m = 0.0;
-        for (int b = tid; b < f.nb; b += nt) m = fmax(m, f.partial[kd * f.nb + b]);
-        m = block_reduce<0>(m, sh);
-        tot += m / f.dx[kd];
+    double m[3] = {0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int b = tid; b < f.nb; b += nt) {
+#pragma unroll
+        for (int kd = 0; kd < 3; ++kd)
+            if (kd < f.dim) m[kd] = fmax(m[kd], f.partial[kd * f.nb + b]);
     }
+    double tot = 0.0;
+    for (int kd = 0; kd < f.dim; ++kd) tot += block_reduce<0>(m[kd], sh) / f.dx[kd];
     if (tid == 0) f.dt_out[0] = f.fixed_dt != nullptr ? f.fixed_dt[0] : f.cfl / tot;
 }
 
-__global__ void __launch_bounds__(256) k_cfl_final(DtFinal f) {
-    __shared__ double sh[8];
+constexpr int FINAL_TPB = 1024;   // threads of the one-block final reductions
+
+__global__ void __launch_bounds__(FINAL_TPB) k_cfl_final(DtFinal f) {
+    __shared__ double sh[FINAL_TPB / 64];
     finalize_dt(f, sh);
 }
 
@@ -1159,10 +1194,11 @@ __global__ void k_monitor_apply_gradlap(long long n, double alpha, double alpha2
 }
 
 // one-block reduction of partial maxima (op 0) or minima capped at 1 (op 1)
-__global__ void __launch_bounds__(256) k_reduce_final(int op, int nb, const double* __restrict__ partial,
-                                                      double* __restrict__ out) {
-    __shared__ double sh[8];
+__global__ void __launch_bounds__(FINAL_TPB) k_reduce_final(int op, int nb, const double* __restrict__ partial,
+                                                            double* __restrict__ out) {
+    __shared__ double sh[FINAL_TPB / 64];
     double v = op == 0 ? 0.0 : 1.0;
+#pragma unroll 4
     for (int b = threadIdx.x; b < nb; b += blockDim.x) v = op == 0 ? fmax(v, partial[b]) : fmin(v, partial[b]);
     v = op == 0 ? block_reduce<0>(v, sh) : block_reduce<1>(v, sh);
     if (threadIdx.x == 0) out[0] = v;
@@ -1859,7 +1895,7 @@ hipError_t launch_cfl_mesh(const es_ctx* c, const double* prim, const double* x,
     if (c->scheme.phys == ES_RMHD || g.dim != 2) {
         if (fixed_dt_dev != nullptr) {
             // a prescribed dt: no speeds needed (finalised here or by the mesh launches)
-            if (!defer_final) k_cfl_final<<<1, 256, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
+            if (!defer_final) k_cfl_final<<<1, FINAL_TPB, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
             return hipGetLastError();
         }
         const hipError_t e = launch_metrics(c, x, nullptr, nullptr, 0.0, c->met, nullptr, s);
@@ -1879,7 +1915,7 @@ hipError_t launch_cfl_mesh(const es_ctx* c, const double* prim, const double* x,
     }
     k_cfl_partial2d_mesh<<<interior_grid(g), dim3(MTX, CBY, 1), 0, s>>>(g, c->scheme.gamma, prim, x, J, red_cfl(c),
                                                                          mon);
-    if (!defer_final) k_cfl_final<<<1, 256, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
+    if (!defer_final) k_cfl_final<<<1, FINAL_TPB, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
     if (monitor_done != nullptr) *monitor_done = mon.enabled != 0;
     return hipGetLastError();
 }
@@ -1897,7 +1933,7 @@ hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, co
     } else {
         k_cfl_partial<3><<<interior_grid(g), box_block(), 0, s>>>(g, G, prim, met, J, red_cfl(c));
     }
-    if (!defer_final) k_cfl_final<<<1, 256, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
+    if (!defer_final) k_cfl_final<<<1, FINAL_TPB, 0, s>>>(cfl_final_args(c, fixed_dt_dev, dt_dev));
     return hipGetLastError();
 }
 
@@ -1931,7 +1967,7 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
     // 2D: the first filter launch finalises a pending dt (block 0); 3D: a launch of its own
     // (dt_dev is written only when dt is pending: the step's own buffer)
     DtFinal dt_fin = cfl_final_args(c, fixed_dt_dev, dt_pending ? const_cast<double*>(dt_dev) : nullptr);
-    if (dt_pending && g.dim != 2) k_cfl_final<<<1, 256, 0, s>>>(dt_fin);
+    if (dt_pending && g.dim != 2) k_cfl_final<<<1, FINAL_TPB, 0, s>>>(dt_fin);
     if (grad_done) {
         // omega (or |grad sigma|) in c->wa and its block maxima came with the CFL launch
     } else if (gradlap) {
@@ -1940,8 +1976,8 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
             k_monitor_gradlap<2><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, prim, w, w2, gpart, red_laplacian(c));
         else
             k_monitor_gradlap<3><<<gr, box_block(), 0, s>>>(g, c->m, sig_ln, prim, w, w2, gpart, red_laplacian(c));
-        k_reduce_final<<<1, 256, 0, s>>>(0, nb, gpart, c->scal + SCAL_GMAX);
-        k_reduce_final<<<1, 256, 0, s>>>(0, nb, red_laplacian(c), c->scal + SCAL_LMAX);
+        k_reduce_final<<<1, FINAL_TPB, 0, s>>>(0, nb, gpart, c->scal + SCAL_GMAX);
+        k_reduce_final<<<1, FINAL_TPB, 0, s>>>(0, nb, red_laplacian(c), c->scal + SCAL_LMAX);
         k_monitor_apply_gradlap<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, mo.alpha2, c->scal + SCAL_GMAX,
                                                                    c->scal + SCAL_LMAX, w, w2);
     } else if (g.dim == 2) {
@@ -1963,7 +1999,7 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
         } while (left > 0);
     } else {
         if (!sq && !gradlap) {
-            k_reduce_final<<<1, 256, 0, s>>>(0, nb, gpart, c->scal + SCAL_GMAX);
+            k_reduce_final<<<1, FINAL_TPB, 0, s>>>(0, nb, gpart, c->scal + SCAL_GMAX);
             k_monitor_apply<<<grid_for(g.nodes), TPB, 0, s>>>(g.nodes, mo.alpha, c->scal + SCAL_GMAX, w);
         }
         for (int f = 0; f < mo.filter_passes; ++f) {
@@ -1997,7 +2033,7 @@ hipError_t launch_mesh(const es_ctx* c, const double* prim, const double* x, con
         }
         if (g.dim == 2) k_dtau_partial<2><<<gr, box_block(), 0, s>>>(g, x, xin, red_dtau(c));
         else k_dtau_partial<3><<<gr, box_block(), 0, s>>>(g, x, xin, red_dtau(c));
-        k_reduce_final<<<1, 256, 0, s>>>(1, nb, red_dtau(c), dtau);
+        k_reduce_final<<<1, FINAL_TPB, 0, s>>>(1, nb, red_dtau(c), dtau);
     }
     k_mesh_update<<<grid_for(n), TPB, 0, s>>>(n, x, xin, dtau, red_dtau(c), nbt, dt_dev, x_new, xdot);
     return hipGetLastError();
