@@ -670,11 +670,20 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wavefront per line segment along DIR: loads the segment with its halo into
-// LDS, evaluates the three two-point fluxes owned by each node, the face
+// One wavefront per segment of the lines along DIR: loads the segment with its
+// halo into LDS, evaluates the two-point fluxes owned by each node, the face
 // dissipation and the flux differences, and writes this direction's part of the
 // residual (m components and J) to out.  The fluxes F(s-n, s) and the
 // dissipation of face s-1/2 come from the lanes that own them (lane shuffles).
+//
+// Segments are cut from the lines' padded node sequences laid end to end (each
+// line n + 2 ng nodes, its ghost layers included): wavefront w holds positions
+// w SEG - ng + lane of that sequence and owns the interior nodes among its lanes
+// ng..63, so a segment may run across the end of one line into the next.  Every
+// stencil an owned node uses stays within its own line's padded nodes; the pair
+// fluxes and faces that straddle two lines are computed and never used.  Cut per
+// line instead, a line of n = 128 nodes would take three wavefronts, the third
+// with 6 owned nodes but the full instruction stream.
 template <int DIM, int DIR, bool ES, bool MIXED, int PO>
 __device__ __forceinline__ void residual_segment(const GridDev& g, double G, double eps,
                                                  const double* __restrict__ prim,
@@ -689,37 +698,44 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 
     const int lane = threadIdx.x & 63;
     const int line = threadIdx.x >> 6;
-    const int seg = blk % nseg;
-    const long long lid = (long long)(blk / nseg) * LINES + line;
-    const bool active = lid < nlines;
+    // wavefront w of the sweep (nseg of them); blk numbers this sweep's blocks
+    const long long w = (long long)blk * LINES + line;
+    if (w >= nseg) return;
     const int nAlong = g.n[DIR];
-    const int s0 = seg * SEGP;
-    const int s_end = min(s0 + SEGP, nAlong);
-
-    // transverse coordinates of this line and strides along it
-    int ci = 0, cj = 0, ck = 0;
-    if (active) {
-        if (DIR == 0) { cj = (int)(lid % g.n[1]); ck = (int)(lid / g.n[1]); }
-        else if (DIR == 1) { ci = (int)(lid % g.n[0]); ck = (int)(lid / g.n[0]); }
-        else { ci = (int)(lid % g.n[0]); cj = (int)(lid / g.n[0]); }
-    }
+    const int PL = nAlong + 2 * NGP;                    // padded nodes of a line
+    const long long f0 = w * SEGP;                      // sequence position of lane 0
     const long long pstride = DIR == 0 ? 1 : (DIR == 1 ? (long long)g.P[0] : (long long)g.P[0] * g.P[1]);
     const long long istride = DIR == 0 ? 1 : (DIR == 1 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1]);
-    const long long pbase = pidx(g, ci, cj, ck);        // padded index of along-coordinate 0
-    const long long ibase = iidx(g, ci, cj, ck);
     const long long P = g.pnodes;
     const long long N = g.nodes;
+    // line and along-coordinate s (-ng .. n + ng - 1) of sequence position f, and
+    // the padded / interior index of the line's node 0
+    auto locate = [&](long long f, long long& lid, int& s, long long& pbase, long long& ibase) {
+        lid = f / PL;
+        s = (int)(f - lid * PL) - NGP;
+        int ci = 0, cj = 0, ck = 0;
+        if (lid < nlines) {
+            if (DIR == 0) { cj = (int)(lid % g.n[1]); ck = (int)(lid / g.n[1]); }
+            else if (DIR == 1) { ci = (int)(lid % g.n[0]); ck = (int)(lid / g.n[0]); }
+            else { ci = (int)(lid % g.n[0]); cj = (int)(lid / g.n[0]); }
+        }
+        pbase = pidx(g, ci, cj, ck);
+        ibase = iidx(g, ci, cj, ck);
+    };
 
-    // ---- load the line segment with its halo into LDS
+    // ---- load the segment with its halo into LDS
     for (int q = lane; q < NLOADP; q += 64) {
-        const int s = s0 - NGP + q;
+        long long qlid, pb, ib;
+        int s;
+        locate(f0 + q, qlid, s, pb, ib);
+        (void)ib;
         double rho = 1.0, p = 1.0, lr = 0.0, lb = 0.0, u[NU], a[NA];
 #pragma unroll
         for (int c = 0; c < NU; ++c) u[c] = 0.0;
 #pragma unroll
         for (int c = 0; c < NA; ++c) a[c] = c == 1 ? 1.0 : 0.0;
-        if (active && s < s_end + NGP) {
-            const long long idx = pbase + (long long)s * pstride;
+        if (qlid < nlines) {
+            const long long idx = pb + (long long)s * pstride;
             rho = prim[idx];
 #pragma unroll
             for (int c = 0; c < NU; ++c) u[c] = prim[(1 + c) * P + idx];
@@ -760,9 +776,13 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 
     // ---- two-point fluxes (s, s+n), n = 1..p, owned by the lane of node s, and
     // flux differences R_s = -(1/dxi) sum_n alpha_n [F(s,s+n) - F(s-n,s)]
-    const int s_own = s0 - NGP + lane;
-    const bool valid = active && s_own < s_end;
-    const bool owner = active && lane >= NGP && s_own < s_end;
+    long long lid_own, pbase_own, ibase_own;
+    int s_own;
+    locate(f0 + lane, lid_own, s_own, pbase_own, ibase_own);
+    (void)pbase_own;
+    const bool active = lid_own < nlines;
+    const bool valid = active;
+    const bool owner = active && lane >= NGP && s_own >= 0 && s_own < nAlong;
     const double idxi = 1.0 / g.dxi[DIR];
     double R[M + 1];
 #pragma unroll
@@ -807,11 +827,11 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
         // the fence makes the dissipation reload its stencil from LDS instead of
         // keeping the flux phase's node values live (register pressure)
         wave_lds_sync();
-        // ---- face dissipation at s+1/2 for faces s in [s0-1, s_end)
+        // ---- face dissipation at s+1/2 for faces s in [-1, n) of the lane's line
         double d[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) d[c] = 0.0;
-        if (active && lane >= NGP - 1 && s_own < s_end) {
+        if (active && lane >= NGP - 1 && s_own >= -1 && s_own < nAlong) {
             // the stencil states are read from LDS where they are used
             if (MIXED) {
                 // FP32 dissipation from FP32 copies of the stencil states and metrics
@@ -858,7 +878,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
     }
 
     if (owner) {
-        const long long o = ibase + (long long)s_own * istride;
+        const long long o = ibase_own + (long long)s_own * istride;
 #pragma unroll
         for (int c = 0; c <= M; ++c) out[c * N + o] = R[c];
     }
@@ -867,7 +887,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 // Residual of all directions: logical blocks [0, nb0) sweep x, [nb0, nb0 + nb1)
 // sweep y, the rest z; direction k writes slab k of Ld (m + 1 components each).
 struct SweepPlan {
-    int nseg[3];          // line segments per line
+    int nseg[3];          // segments (wavefronts) of the sweep
     int nblk[3];          // blocks of the sweep
     long long nlines[3];  // lines of the sweep
 };
@@ -1833,12 +1853,15 @@ static void residual_all(const es_ctx* c, const double* prim, const double* met,
     long long nb = 0;
     const int segn = seg_nodes(g.p);
     for (int d = 0; d < DIM; ++d) {
-        sw.nseg[d] = (g.n[d] + segn - 1) / segn;
         long long nl = 1;
         for (int a = 0; a < DIM; ++a)
             if (a != d) nl *= g.n[a];
+        // wavefronts until the one owning the last line's last interior node (the
+        // lines' padded node sequences laid end to end)
+        const long long pl = g.n[d] + 2 * g.ng;
+        sw.nseg[d] = (int)(((nl - 1) * pl + g.n[d] - 1) / segn + 1);
         sw.nlines[d] = nl;
-        sw.nblk[d] = (int)(((nl + LINES - 1) / LINES) * sw.nseg[d]);
+        sw.nblk[d] = (sw.nseg[d] + LINES - 1) / LINES;
         nb += sw.nblk[d];
     }
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;
