@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libes.so")
 ARCH = "gfx950"
 
 SOURCES = ["es_api.hip", "es_kernels.hip", "es_kernels_rmhd.hip", "es_adjoint.hip", "es_adjoint_rmhd.hip"]
-HEADERS = ["es_common.h", "es_internal.h", "es_launch.h", "es_rhd.h", "es_rmhd.h", "es_dual.h", "es_pair_vjp.h", "es_eigen_vjp.h"]
+HEADERS = ["es_common.h", "es_internal.h", "es_launch.h", "es_seq.h", "es_rhd.h", "es_rmhd.h", "es_dual.h", "es_pair_vjp.h", "es_eigen_vjp.h"]
 
 
 def hipcc() -> str:

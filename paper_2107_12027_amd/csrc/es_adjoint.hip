@@ -299,6 +299,8 @@ struct AdjLDS {
 };
 
 struct AdjPlan {
+    int flat[3];          // flat (1) or aligned (0) segment layout
+    int nsl[3];           // segments per line of the aligned layout
     int nseg[3];
     int nblk[3];
     long long nlines[3];
@@ -310,7 +312,7 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
                                                      const double* __restrict__ met,
                                                      const double* __restrict__ lam,
                                                      double* __restrict__ gout, int blk, int nseg,
-                                                     long long nlines, AdjLDS<DIM>& lds) {
+                                                     long long nlines, bool flat, int nsl, AdjLDS<DIM>& lds) {
     constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1;
     constexpr int F_RHO = 0, F_P = 1, F_BETA = 2, F_W = 3, F_LR = 4, F_LB = 5, F_U = 6, F_A = 6 + NU;
     auto& sd = lds.sd;
@@ -318,34 +320,46 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
     auto& buf = lds.buf;
     const int lane = threadIdx.x & 63;
     const int line = threadIdx.x >> 6;
-    const int seg = blk % nseg;
-    const long long lid = (long long)(blk / nseg) * ALINES + line;
-    const bool active = lid < nlines;
+    // segment w of sequence `line` (the lines dealt to ALINES sequences, es_seq.h)
+    // outputs ASEG consecutive positions.  Flat layout: the padded node sequences
+    // (n + 2 NG nodes per line) laid end to end, a pair or face across two lines
+    // joining ghost nodes of both, whose residual cotangents are zero, so that it
+    // contributes nothing; aligned: ceil((n + 2 NG) / ASEG) segments per line.  A
+    // segment past the sweep's last one runs with no active lane (the block
+    // synchronises).
+    const long long w = blk;
     const int n = g.n[DIR];
-    const int s0 = -NG + seg * ASEG;                 // first output (padded coordinate)
-    const int s_end = min(s0 + ASEG, n + NG);
-    int ci = 0, cj = 0, ck = 0;
-    if (active) {
-        if (DIR == 0) { cj = (int)(lid % g.n[1]); ck = (int)(lid / g.n[1]); }
-        else if (DIR == 1) { ci = (int)(lid % g.n[0]); ck = (int)(lid / g.n[0]); }
-        else { ci = (int)(lid % g.n[0]); cj = (int)(lid / g.n[0]); }
-    }
+    const int PL = n + 2 * NG;
     const long long pstride = DIR == 0 ? 1 : (DIR == 1 ? (long long)g.P[0] : (long long)g.P[0] * g.P[1]);
     const long long istride = DIR == 0 ? 1 : (DIR == 1 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1]);
-    const long long pbase = pidx(g, ci, cj, ck);
-    const long long ibase = iidx(g, ci, cj, ck);
     const long long P = g.pnodes, N = g.nodes;
     const double idxi = 1.0 / g.dxi[DIR];
+    // line (nlines if none) and padded coordinate s of sequence position
+    // w ASEG - AHALO + q, and the padded / interior index of the line's node 0
+    const int nf = DIR == 0 ? g.n[1] : g.n[0];
+    const SeqBase sb = flat ? seq_base(w * ASEG - AHALO, PL, NG, nf, ALINES, line)
+                            : seq_base_aligned(w, nsl, ASEG, AHALO, NG, nf, ALINES, line);
+    auto locate = [&](int q, long long& lid, int& s, long long& pbase, long long& ibase) {
+        int fa, fb;
+        seq_at(sb, q, flat, PL, NG, nf, ALINES, line, lid, s, fa, fb);
+        if (w >= nseg || lid < 0 || s < -NG || s >= n + NG) lid = nlines;
+        const int ci = DIR == 0 ? 0 : fa, cj = DIR == 0 ? fa : (DIR == 1 ? 0 : fb), ck = DIR == 2 ? 0 : fb;
+        pbase = pidx(g, ci, cj, ck);
+        ibase = iidx(g, ci, cj, ck);
+    };
+    const bool active = w < nseg;
 
-    // ---- states (positions s0 - 5 .. s0 + 58) and residual cotangents
+    // ---- states (positions w ASEG - 5 .. w ASEG + 58) and residual cotangents
     {
-        const int s = s0 - AHALO + lane;
+        long long lid, pbase, ibase;
+        int s;
+        locate(lane, lid, s, pbase, ibase);
         double rho = 1.0, p = 1.0, lr = 0.0, lb = 0.0, u[NU], a[NA];
 #pragma unroll
         for (int c = 0; c < NU; ++c) u[c] = 0.0;
 #pragma unroll
         for (int c = 0; c < NA; ++c) a[c] = c == 1 ? 1.0 : 0.0;
-        if (active && s >= -NG && s < n + NG) {
+        if (lid < nlines) {
             const long long idx = pbase + (long long)s * pstride;
             rho = prim[idx];
 #pragma unroll
@@ -369,7 +383,7 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
         for (int c = 0; c < NU; ++c) sd[line][F_U + c][lane] = u[c];
 #pragma unroll
         for (int c = 0; c < NA; ++c) sd[line][F_A + c][lane] = a[c];
-        const bool in = active && s >= 0 && s < n;
+        const bool in = lid < nlines && s >= 0 && s < n;
 #pragma unroll
         for (int c = 0; c < M; ++c) sl[line][c][lane] = in ? lam[c * N + ibase + (long long)s * istride] : 0.0;
     }
@@ -394,8 +408,8 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
         return nd;
     };
 
-    // ---- pairs (s', s'+n), s' = s0 - 3 + lane, slot of s' = lane + 2
-    const int o = lane;                            // output lane: position s0 + o
+    // ---- pairs (s', s'+n), s' = w ASEG - 3 + lane, slot of s' = lane + 2
+    const int o = lane;                            // output lane: position w ASEG + o
     double acc[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) acc[c] = 0.0;
@@ -447,7 +461,7 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
 
     if (ES) {
         __syncthreads();
-        // ---- faces f = s0 - 3 + lane (stencil slots lane + 3 - PO .. lane + 2 + PO); the
+        // ---- faces f = w ASEG - 3 + lane (stencil slots lane + 3 - PO .. lane + 2 + PO); the
         // cotangents of the 2 PO stencil states go to buf[j][.][lane]
         bool any = false;
         double z[M];
@@ -483,9 +497,12 @@ __device__ __forceinline__ void residual_vjp_segment(const GridDev& g, double G,
         }
     }
 
-    const int s = s0 + o;
-    if (active && o < ASEG && s < s_end) {
-        const long long idx = pbase + (long long)s * pstride;
+    long long lid_out, pbase_out, ibase_out;
+    int s_out;
+    locate(AHALO + o, lid_out, s_out, pbase_out, ibase_out);
+    (void)ibase_out;
+    if (o < ASEG && lid_out < nlines) {
+        const long long idx = pbase_out + (long long)s_out * pstride;
 #pragma unroll
         for (int c = 0; c < M; ++c) gout[c * P + idx] = acc[c];
     }
@@ -505,17 +522,17 @@ __global__ void __launch_bounds__(128) k_residual_vjp(GridDev g, double G, doubl
     const long long slab = (long long)M * g.pnodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < pl.nblk[0]) {
-        residual_vjp_segment<DIM, 0, ES, PO>(g, G, eps, prim, met, lam, gdir, b, pl.nseg[0], pl.nlines[0], lds);
+        residual_vjp_segment<DIM, 0, ES, PO>(g, G, eps, prim, met, lam, gdir, b, pl.nseg[0], pl.nlines[0], pl.flat[0], pl.nsl[0], lds);
         return;
     }
     b -= pl.nblk[0];
     if (DIM == 2 || b < pl.nblk[1]) {
-        residual_vjp_segment<DIM, 1, ES, PO>(g, G, eps, prim, met, lam, gdir + slab, b, pl.nseg[1], pl.nlines[1], lds);
+        residual_vjp_segment<DIM, 1, ES, PO>(g, G, eps, prim, met, lam, gdir + slab, b, pl.nseg[1], pl.nlines[1], pl.flat[1], pl.nsl[1], lds);
         return;
     }
     b -= pl.nblk[1];
     if (DIM == 3)
-        residual_vjp_segment<DIM, 2, ES, PO>(g, G, eps, prim, met, lam, gdir + 2 * slab, b, pl.nseg[2], pl.nlines[2], lds);
+        residual_vjp_segment<DIM, 2, ES, PO>(g, G, eps, prim, met, lam, gdir + 2 * slab, b, pl.nseg[2], pl.nlines[2], pl.flat[2], pl.nsl[2], lds);
 }
 
 // Solve A^T y = b for a small dense A (n x n, row-major) by Gaussian elimination
@@ -740,12 +757,19 @@ static void residual_vjp_all(const es_ctx* c, const double* prim, const double* 
     AdjPlan pl{};
     long long nb = 0;
     for (int d = 0; d < DIM; ++d) {
-        pl.nseg[d] = (g.n[d] + 2 * NG + ASEG - 1) / ASEG;
         long long nl = 1;
         for (int a = 0; a < DIM; ++a)
             if (a != d) nl *= g.n[a];
+        // every padded position of every line is an output; segments per sequence of
+        // the longest sequence (flat where it saves an eighth of the wavefronts), one
+        // block per segment offset
+        const long long ml = (nl + ALINES - 1) / ALINES;
+        const int plen = g.n[d] + 2 * NG;
+        pl.flat[d] = seq_flat(plen, plen, ASEG, 0.875) ? 1 : 0;
+        pl.nsl[d] = (plen + ASEG - 1) / ASEG;
+        pl.nseg[d] = pl.flat[d] ? (int)((ml * plen + ASEG - 1) / ASEG) : (int)(ml * pl.nsl[d]);
         pl.nlines[d] = nl;
-        pl.nblk[d] = (int)(((nl + ALINES - 1) / ALINES) * pl.nseg[d]);
+        pl.nblk[d] = pl.nseg[d];
         nb += pl.nblk[d];
     }
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;

@@ -676,20 +676,23 @@ __device__ __forceinline__ void wave_lds_sync() {
 // residual (m components and J) to out.  The fluxes F(s-n, s) and the
 // dissipation of face s-1/2 come from the lanes that own them (lane shuffles).
 //
-// Segments are cut from the lines' padded node sequences laid end to end (each
-// line n + 2 ng nodes, its ghost layers included): wavefront w holds positions
-// w SEG - ng + lane of that sequence and owns the interior nodes among its lanes
-// ng..63, so a segment may run across the end of one line into the next.  Every
-// stencil an owned node uses stays within its own line's padded nodes; the pair
-// fluxes and faces that straddle two lines are computed and never used.  Cut per
-// line instead, a line of n = 128 nodes would take three wavefronts, the third
-// with 6 owned nodes but the full instruction stream.
+// The lines are dealt to LINES sequences so that the wavefronts of a block work on
+// adjacent lines (es_seq.h); segment w of a sequence holds 64 consecutive positions
+// and owns the interior nodes among its lanes ng..63.  Flat layout: the positions
+// of the lines' padded node sequences (n + 2 ng nodes each) laid end to end, so a
+// segment may run across the end of one line into the next; every stencil an owned
+// node uses stays within its own line's padded nodes, and the pair fluxes and faces
+// that straddle two lines are computed and never used.  Aligned layout: ceil(n / SEG)
+// segments per line.  Flat is taken where it saves at least an eighth of the
+// wavefronts: aligned, a line of n = 128 nodes would take three, the third with 6
+// owned nodes but the full instruction stream.
 template <int DIM, int DIR, bool ES, bool MIXED, int PO>
 __device__ __forceinline__ void residual_segment(const GridDev& g, double G, double eps,
                                                  const double* __restrict__ prim,
                                                  const double* __restrict__ met,
                                                  double* __restrict__ out, int blk, int nseg,
-                                                 long long nlines, ResidualLDS<DIM, PO>& lds) {
+                                                 long long nlines, bool flat, int nsl,
+                                                 ResidualLDS<DIM, PO>& lds) {
     constexpr int NU = DIM, M = DIM + 2, NA = DIM + 1;
     constexpr int NGP = ghost_layers(PO), SEGP = seg_nodes(PO), NLOADP = seg_loads(PO);
     constexpr int F_RHO = 0, F_P = 1, F_BETA = 2, F_W = 3, F_LR = 4, F_LB = 5, F_U = 6,
@@ -698,8 +701,9 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 
     const int lane = threadIdx.x & 63;
     const int line = threadIdx.x >> 6;
-    // wavefront w of the sweep (nseg of them); blk numbers this sweep's blocks
-    const long long w = (long long)blk * LINES + line;
+    // segment w (nseg of them per sequence) of sequence `line`; blk numbers this
+    // sweep's blocks
+    const long long w = blk;
     if (w >= nseg) return;
     const int nAlong = g.n[DIR];
     const int PL = nAlong + 2 * NGP;                    // padded nodes of a line
@@ -708,17 +712,16 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
     const long long istride = DIR == 0 ? 1 : (DIR == 1 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1]);
     const long long P = g.pnodes;
     const long long N = g.nodes;
-    // line and along-coordinate s (-ng .. n + ng - 1) of sequence position f, and
-    // the padded / interior index of the line's node 0
-    auto locate = [&](long long f, long long& lid, int& s, long long& pbase, long long& ibase) {
-        lid = f / PL;
-        s = (int)(f - lid * PL) - NGP;
-        int ci = 0, cj = 0, ck = 0;
-        if (lid < nlines) {
-            if (DIR == 0) { cj = (int)(lid % g.n[1]); ck = (int)(lid / g.n[1]); }
-            else if (DIR == 1) { ci = (int)(lid % g.n[0]); ck = (int)(lid / g.n[0]); }
-            else { ci = (int)(lid % g.n[0]); cj = (int)(lid / g.n[0]); }
-        }
+    // line and along-coordinate s (-ng .. n + ng - 1) of sequence position f0 + q,
+    // and the padded / interior index of the line's node 0
+    const int nf = DIR == 0 ? g.n[1] : g.n[0];
+    const SeqBase sb = flat ? seq_base(f0, PL, NGP, nf, LINES, line)
+                            : seq_base_aligned(w, nsl, SEGP, 0, NGP, nf, LINES, line);
+    auto locate = [&](int q, long long& lid, int& s, long long& pbase, long long& ibase) {
+        int fa, fb;
+        seq_at(sb, q, flat, PL, NGP, nf, LINES, line, lid, s, fa, fb);
+        if (s >= nAlong + NGP) lid = nlines;   // past the line's padded end (aligned)
+        const int ci = DIR == 0 ? 0 : fa, cj = DIR == 0 ? fa : (DIR == 1 ? 0 : fb), ck = DIR == 2 ? 0 : fb;
         pbase = pidx(g, ci, cj, ck);
         ibase = iidx(g, ci, cj, ck);
     };
@@ -727,7 +730,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
     for (int q = lane; q < NLOADP; q += 64) {
         long long qlid, pb, ib;
         int s;
-        locate(f0 + q, qlid, s, pb, ib);
+        locate(q, qlid, s, pb, ib);
         (void)ib;
         double rho = 1.0, p = 1.0, lr = 0.0, lb = 0.0, u[NU], a[NA];
 #pragma unroll
@@ -776,13 +779,18 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 
     // ---- two-point fluxes (s, s+n), n = 1..p, owned by the lane of node s, and
     // flux differences R_s = -(1/dxi) sum_n alpha_n [F(s,s+n) - F(s-n,s)]
-    long long lid_own, pbase_own, ibase_own;
-    int s_own;
-    locate(f0 + lane, lid_own, s_own, pbase_own, ibase_own);
-    (void)pbase_own;
-    const bool active = lid_own < nlines;
+    // this lane's node: only flags stay live (the output index is formed again at
+    // the store)
+    bool active, owner, face;
+    {
+        long long lid_own, pb, ib;
+        int s_own;
+        locate(lane, lid_own, s_own, pb, ib);
+        active = lid_own < nlines;
+        owner = active && lane >= NGP && s_own >= 0 && s_own < nAlong;
+        face = active && lane >= NGP - 1 && s_own >= -1 && s_own < nAlong;
+    }
     const bool valid = active;
-    const bool owner = active && lane >= NGP && s_own >= 0 && s_own < nAlong;
     const double idxi = 1.0 / g.dxi[DIR];
     double R[M + 1];
 #pragma unroll
@@ -831,7 +839,7 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
         double d[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) d[c] = 0.0;
-        if (active && lane >= NGP - 1 && s_own >= -1 && s_own < nAlong) {
+        if (face) {
             // the stencil states are read from LDS where they are used
             if (MIXED) {
                 // FP32 dissipation from FP32 copies of the stencil states and metrics
@@ -878,7 +886,10 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
     }
 
     if (owner) {
-        const long long o = ibase_own + (long long)s_own * istride;
+        long long lid_own, pb, ib;
+        int s_own;
+        locate(lane, lid_own, s_own, pb, ib);
+        const long long o = ib + (long long)s_own * istride;
 #pragma unroll
         for (int c = 0; c <= M; ++c) out[c * N + o] = R[c];
     }
@@ -887,9 +898,11 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 // Residual of all directions: logical blocks [0, nb0) sweep x, [nb0, nb0 + nb1)
 // sweep y, the rest z; direction k writes slab k of Ld (m + 1 components each).
 struct SweepPlan {
-    int nseg[3];          // segments (wavefronts) of the sweep
+    int nseg[3];          // segments per sequence (blocks of the sweep)
     int nblk[3];          // blocks of the sweep
     long long nlines[3];  // lines of the sweep
+    int flat[3];          // flat (1) or aligned (0) layout of the segments
+    int nsl[3];           // segments per line of the aligned layout
 };
 
 template <int DIM, bool ES, bool MIXED, int PO>
@@ -902,17 +915,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const long long slab = (long long)(M + 1) * g.nodes;
     int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
     if (b < sw.nblk[0]) {
-        residual_segment<DIM, 0, ES, MIXED, PO>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], lds);
+        residual_segment<DIM, 0, ES, MIXED, PO>(g, G, eps, prim, met, Ld, b, sw.nseg[0], sw.nlines[0], sw.flat[0], sw.nsl[0], lds);
         return;
     }
     b -= sw.nblk[0];
     if (DIM == 2 || b < sw.nblk[1]) {
-        residual_segment<DIM, 1, ES, MIXED, PO>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], lds);
+        residual_segment<DIM, 1, ES, MIXED, PO>(g, G, eps, prim, met, Ld + slab, b, sw.nseg[1], sw.nlines[1], sw.flat[1], sw.nsl[1], lds);
         return;
     }
     b -= sw.nblk[1];
     if (DIM == 3)
-        residual_segment<DIM, 2, ES, MIXED, PO>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], lds);
+        residual_segment<DIM, 2, ES, MIXED, PO>(g, G, eps, prim, met, Ld + 2 * slab, b, sw.nseg[2], sw.nlines[2], sw.flat[2], sw.nsl[2], lds);
 }
 
 // dU = sum_k Ld_k (components 0..m-1), dJ = sum_k Ld_k (component m), summed in
@@ -1856,12 +1869,15 @@ static void residual_all(const es_ctx* c, const double* prim, const double* met,
         long long nl = 1;
         for (int a = 0; a < DIM; ++a)
             if (a != d) nl *= g.n[a];
-        // wavefronts until the one owning the last line's last interior node (the
-        // lines' padded node sequences laid end to end)
-        const long long pl = g.n[d] + 2 * g.ng;
-        sw.nseg[d] = (int)(((nl - 1) * pl + g.n[d] - 1) / segn + 1);
+        // segments per sequence (the lines dealt to LINES sequences): flat, until the
+        // one owning the longest sequence's last interior node; aligned, ceil(n / SEG)
+        // per line.  One block per segment offset, one wavefront per sequence.
+        const long long pl = g.n[d] + 2 * g.ng, ml = (nl + LINES - 1) / LINES;
+        sw.flat[d] = seq_flat(g.n[d], (int)pl, segn, 0.875) ? 1 : 0;
+        sw.nsl[d] = (g.n[d] + segn - 1) / segn;
+        sw.nseg[d] = sw.flat[d] ? (int)(((ml - 1) * pl + g.n[d] - 1) / segn + 1) : (int)(ml * sw.nsl[d]);
         sw.nlines[d] = nl;
-        sw.nblk[d] = (sw.nseg[d] + LINES - 1) / LINES;
+        sw.nblk[d] = sw.nseg[d];
         nb += sw.nblk[d];
     }
     const double G = c->scheme.gamma, eps = c->scheme.weno_eps;

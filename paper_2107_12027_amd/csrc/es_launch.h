@@ -3,6 +3,7 @@
 #pragma once
 
 #include "es_common.h"
+#include "es_seq.h"
 
 namespace es {
 namespace {
