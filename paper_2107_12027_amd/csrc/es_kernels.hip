@@ -1962,7 +1962,6 @@ hipError_t launch_cfl_mesh(const es_ctx* c, const double* prim, const double* x,
 hipError_t launch_cfl(const es_ctx* c, const double* prim, const double* met, const double* J,
                       double* dt_dev, const double* fixed_dt_dev, hipStream_t s, bool defer_final) {
     const GridDev& g = c->g;
-    const int nb = interior_blocks(g);
     const double G = c->scheme.gamma;
     if (c->scheme.phys == ES_RMHD) {
         const hipError_t e = launch_cfl_partial_rmhd(c, prim, met, J, s);
