@@ -36,6 +36,29 @@ def test_metrics_and_jacobian(dim, n, bc):
     assert np.max(np.abs(host(J0) - Jw)) <= 1e-13 * np.max(np.abs(Jw))
 
 
+# es_metrics without J0 in 3D runs the tile kernel of the stage meshes (16 x 16 column
+# tiles marching along xi_3 in runs of planes): sizes with several tiles and runs,
+# ragged tile edges, each boundary rule and p = 2, 3, 4
+@pytest.mark.parametrize("n,bc,p", [((70, 9, 8), (0, 0, 0), 3), ((10, 66, 9), (1, 1, 1), 3),
+                                    ((40, 37, 45), (0, 1, 0), 3), ((40, 37, 45), (1, 0, 1), 2),
+                                    ((33, 20, 19), (0, 0, 1), 4)])
+def test_metrics3d_tile_kernel(n, bc, p):
+    case = Case(3, n, bc, seed=4, p=p)
+    c = case.ctx
+    met = empty(c.nmet, *c.padded_shape())
+    c.metrics(dev(case.x), dev(case.xdot), met)
+    want = mt.metrics(case.grid, case.x, case.xdot, p)
+    got = host(met)
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(got - want)) <= 1e-13 * scale
+    # the static mesh: the temporal components are zero
+    c.metrics(dev(case.x), None, met)
+    got = host(met)
+    assert np.max(np.abs(got[0::4])) == 0.0
+    want0 = mt.metrics(case.grid, case.x, None, p)
+    assert np.max(np.abs(got - want0)) <= 1e-13 * scale
+
+
 @pytest.mark.parametrize("dim,n,bc", GRIDS)
 def test_prim2con_and_con2prim(dim, n, bc):
     case = Case(dim, n, bc, seed=2, vmax=0.99, rho_rng=(0.01, 1.0), p_rng=(0.01, 1.0))
