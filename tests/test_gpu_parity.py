@@ -117,6 +117,39 @@ def test_residual(dim, n, bc, diss):
     assert rel_inf(host(dJ)[None], dJo[None])[0] <= TOL
 
 
+# the two segment layouts of the residual: lines of 61 and 110 nodes take the aligned
+# one (ceil(n / 61) segments per line), the others the flat one (lines laid end to
+# end), mixed within one launch; FP64 and FP32-mixed ES
+@pytest.mark.parametrize("dim,n,bc", [(2, (110, 61, 1), (0, 1, 0)), (3, (61, 10, 9), (1, 0, 1)),
+                                      (3, (12, 110, 9), (0, 0, 0))])
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_residual_segment_layouts(dim, n, bc, mixed):
+    case = Case(dim, n, bc, seed=12, mixed=mixed)
+    c = case.ctx
+    U, J = case.gpu_state()
+    prim = empty(c.nprim, *c.padded_shape())
+    met = empty(c.nmet, *c.padded_shape())
+    c.con2prim(U, J, prim)
+    c.metrics(dev(case.x), dev(case.xdot), met)
+    dU = empty(c.m, *c.shape())
+    dJ = empty(*c.shape())
+    c.residual(prim, met, dU, dJ)
+    Uo, Jo = case.oracle_state()
+    Po, _ = st.prim_from_cons(case.grid, case.scheme, Uo, Jo)
+    meto = mt.metrics(case.grid, case.x, case.xdot)
+    dUo, dJo = rs.residual(case.grid, wl.Scheme(), st.pad_solution(case.grid, Po), meto)
+    got = host(dU)
+    if mixed:
+        # FP32 dissipation: relative L1 per component, the bar of the mixed-form tests
+        a, b = got.reshape(c.m, -1), dUo.reshape(c.m, -1)
+        l1 = np.abs(a - b).sum(axis=1) / np.abs(b).sum(axis=1)
+        assert np.all(l1 <= 2e-4), l1
+    else:
+        r = rel_inf(got, dUo)
+        assert np.all(r <= TOL), r
+    assert rel_inf(host(dJ)[None], dJo[None])[0] <= TOL
+
+
 @pytest.mark.parametrize("dim,n,bc", GRIDS[:3] + GRIDS[4:7])
 def test_cfl_time_step(dim, n, bc):
     case = Case(dim, n, bc, seed=6, vmax=0.99)
