@@ -24,9 +24,12 @@ from gpu_util import Case, dev, host, empty  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
+# lines of 100 nodes take the VJP's aligned segment layout (two segments per line),
+# the others the flat one (lines laid end to end)
 CASES = [(2, (40, 36, 1), (0, 0, 0), True), (2, (40, 36, 1), (0, 0, 0), False),
          (2, (70, 66, 1), (1, 0, 0), True), (2, (30, 33, 1), (1, 1, 0), False),
-         (3, (12, 10, 9), (0, 0, 0), True), (3, (12, 10, 9), (1, 1, 1), False)]
+         (3, (12, 10, 9), (0, 0, 0), True), (3, (12, 10, 9), (1, 1, 1), False),
+         (2, (100, 36, 1), (0, 1, 0), True)]
 
 
 def _oracle_L(case, U, J, met, Y=None, details=False):
