@@ -63,8 +63,8 @@ RESIDUAL_FLOPS_PER_NODE_3D_RMHD = 111738.6
 # WRITE x 1.000).  Valid for the kernels as they were measured; the summaries
 # with their commands are the es_residual_hbm_counters_* files under profiles/.
 RESIDUAL_TRAFFIC_BYTES = {
-    "rhd2d_quadrant_riemann_400_seed2": 57.77e6,
-    "rhd3d_blast_128": 1343.1e6,
+    "rhd2d_quadrant_riemann_400_seed2": 57.85e6,
+    "rhd3d_blast_128": 1329.3e6,
 }
 
 

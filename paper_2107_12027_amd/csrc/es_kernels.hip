@@ -726,41 +726,70 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
         ibase = iidx(g, ci, cj, ck);
     };
 
-    // ---- load the segment with its halo into LDS
-    for (int q = lane; q < NLOADP; q += 64) {
-        long long qlid, pb, ib;
-        int s;
+    // ---- load the segment with its halo into LDS.  Lane q holds position q and,
+    // for q < NLOADP - 64, position 64 + q as well; the loads of both positions are
+    // issued before the first of them is used, from addresses that are always valid
+    // and outside any branch (a position off the lines reads node 0 and then takes
+    // the far-field values instead), so the wavefront waits on memory once.
+    static_assert(NLOADP > 64 && NLOADP <= 128, "two positions per lane");
+    constexpr int NV = M + 2 + NA;   // rho, u, p, ln rho, ln beta, then the metrics
+    auto index = [&](int q, bool use, long long& qlid, int& s, bool& ok) {
+        long long pb, ib;
         locate(q, qlid, s, pb, ib);
         (void)ib;
-        double rho = 1.0, p = 1.0, lr = 0.0, lb = 0.0, u[NU], a[NA];
+        ok = use && qlid < nlines;
+        return ok ? pb + (long long)s * pstride : 0;
+    };
+    auto fetch = [&](long long idx, double* v) {
 #pragma unroll
-        for (int c = 0; c < NU; ++c) u[c] = 0.0;
+        for (int c = 0; c < M + 2; ++c) v[c] = prim[c * P + idx];
 #pragma unroll
-        for (int c = 0; c < NA; ++c) a[c] = c == 1 ? 1.0 : 0.0;
-        if (qlid < nlines) {
-            const long long idx = pb + (long long)s * pstride;
-            rho = prim[idx];
+        for (int c = 0; c < NA; ++c) v[M + 2 + c] = met[(DIR * NA + c) * P + idx];
+    };
+    auto stash = [&](int q, bool ok, const double* v) {
+        const double rho = ok ? v[0] : 1.0, p = ok ? v[M - 1] : 1.0;
+        double u[NU], uu = 0.0;
 #pragma unroll
-            for (int c = 0; c < NU; ++c) u[c] = prim[(1 + c) * P + idx];
-            p = prim[(M - 1) * P + idx];
-            lr = prim[M * P + idx];
-            lb = prim[(M + 1) * P + idx];
-#pragma unroll
-            for (int c = 0; c < NA; ++c) a[c] = met[(DIR * NA + c) * P + idx];
+        for (int c = 0; c < NU; ++c) {
+            u[c] = ok ? v[1 + c] : 0.0;
+            uu += u[c] * u[c];
         }
-        double uu = 0.0;
-#pragma unroll
-        for (int c = 0; c < NU; ++c) uu += u[c] * u[c];
         sd[line][F_RHO][q] = rho;
         sd[line][F_P][q] = p;
         sd[line][F_BETA][q] = rho * frcp(p);
         sd[line][F_W][q] = psqrt(1.0 + uu);
-        sd[line][F_LR][q] = lr;
-        sd[line][F_LB][q] = lb;
+        sd[line][F_LR][q] = ok ? v[M] : 0.0;
+        sd[line][F_LB][q] = ok ? v[M + 1] : 0.0;
 #pragma unroll
         for (int c = 0; c < NU; ++c) sd[line][F_U + c][q] = u[c];
 #pragma unroll
-        for (int c = 0; c < NA; ++c) sd[line][F_A + c][q] = a[c];
+        for (int c = 0; c < NA; ++c) sd[line][F_A + c][q] = ok ? v[M + 2 + c] : (c == 1 ? 1.0 : 0.0);
+    };
+    // this lane's own node (position lane): only flags stay live (the output index
+    // is formed again at the store)
+    bool active, owner, face;
+    {
+        constexpr int NSEC = NLOADP - 64;
+        const bool sec = lane < NSEC;
+        double v0[NV], v1[NV];
+        long long lid_own, lid1;
+        int s_own, s1;
+        bool ok0, ok1;
+        const long long i0 = index(lane, true, lid_own, s_own, ok0);
+        const long long i1 = index(64 + (sec ? lane : 0), sec, lid1, s1, ok1);
+        fetch(i0, v0);
+        fetch(i1, v1);
+        // every load issued before any of them is used
+        __builtin_amdgcn_sched_barrier(0);
+        active = lid_own < nlines;
+        owner = active && lane >= NGP && s_own >= 0 && s_own < nAlong;
+        face = active && lane >= NGP - 1 && s_own >= -1 && s_own < nAlong;
+        stash(lane, ok0, v0);
+        // the lanes without a second position store their own again (the same
+        // values): no branch, so the second loads are not sunk after the first wait
+#pragma unroll
+        for (int c = 0; c < NV; ++c) v1[c] = sec ? v1[c] : v0[c];
+        stash(sec ? 64 + lane : lane, sec ? ok1 : ok0, v1);
     }
     wave_lds_sync();
 
@@ -779,17 +808,6 @@ __device__ __forceinline__ void residual_segment(const GridDev& g, double G, dou
 
     // ---- two-point fluxes (s, s+n), n = 1..p, owned by the lane of node s, and
     // flux differences R_s = -(1/dxi) sum_n alpha_n [F(s,s+n) - F(s-n,s)]
-    // this lane's node: only flags stay live (the output index is formed again at
-    // the store)
-    bool active, owner, face;
-    {
-        long long lid_own, pb, ib;
-        int s_own;
-        locate(lane, lid_own, s_own, pb, ib);
-        active = lid_own < nlines;
-        owner = active && lane >= NGP && s_own >= 0 && s_own < nAlong;
-        face = active && lane >= NGP - 1 && s_own >= -1 && s_own < nAlong;
-    }
     const bool valid = active;
     const double idxi = 1.0 / g.dxi[DIR];
     double R[M + 1];

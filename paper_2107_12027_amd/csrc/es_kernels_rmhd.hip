@@ -126,23 +126,45 @@ __device__ __forceinline__ void residual_segment_rmhd(const GridDev& g, double G
     const long long ibase = iidx(g, ci, cj, ck);
     const long long P = g.pnodes, N = g.nodes;
 
-    for (int q = lane; q < NLOADP; q += 64) {
-        const int s = s0 - NGP + q;
-        double v[MR + 2 + NA];
+    // Lane q holds position q and, for q < NLOADP - 64, position 64 + q as well: the
+    // loads of both are issued before either is used, from addresses that are always
+    // valid and outside any branch (a position off the line reads node 0 and then
+    // takes the far-field values instead), so the wavefront waits on memory once.
+    static_assert(NLOADP > 64 && NLOADP <= 128, "two positions per lane");
+    {
+        constexpr int NV = MR + 2 + NA;
+        const bool sec = lane < NLOADP - 64;
+        const int sa = s0 - NGP + lane, sb = s0 - NGP + 64 + (sec ? lane : 0);
+        const bool oka = active && sa < s_end + NGP, okb = sec && active && sb < s_end + NGP;
+        const long long ia = oka ? pbase + (long long)sa * pstride : 0;
+        const long long ib = okb ? pbase + (long long)sb * pstride : 0;
+        double va[NV], vb[NV];
 #pragma unroll
-        for (int c = 0; c < MR + 2 + NA; ++c) v[c] = 0.0;
-        v[0] = 1.0;
-        v[4] = 1.0;
-        v[F_A + 1] = 1.0;
-        if (active && s < s_end + NGP) {
-            const long long idx = pbase + (long long)s * pstride;
-#pragma unroll
-            for (int c = 0; c < MR + 2; ++c) v[c] = prim[c * P + idx];
-#pragma unroll
-            for (int c = 0; c < NA; ++c) v[F_A + c] = met[(DIR * NA + c) * P + idx];
+        for (int c = 0; c < MR + 2; ++c) {
+            va[c] = prim[c * P + ia];
+            vb[c] = prim[c * P + ib];
         }
 #pragma unroll
-        for (int c = 0; c < MR + 2 + NA; ++c) sd[line][c][q] = v[c];
+        for (int c = 0; c < NA; ++c) {
+            va[F_A + c] = met[(DIR * NA + c) * P + ia];
+            vb[F_A + c] = met[(DIR * NA + c) * P + ib];
+        }
+        // every load issued before any of them is used
+        __builtin_amdgcn_sched_barrier(0);
+        // far field: rho = p = 1, the metric (0, 1, 0, ...), the rest 0
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            const double far = (c == 0 || c == 4 || c == F_A + 1) ? 1.0 : 0.0;
+            va[c] = oka ? va[c] : far;
+            vb[c] = okb ? vb[c] : far;
+        }
+        // the lanes without a second position store their own again (the same
+        // values): no branch, so the second loads are not sunk after the first wait
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            sd[line][c][lane] = va[c];
+            sd[line][c][sec ? 64 + lane : lane] = sec ? vb[c] : va[c];
+        }
     }
     __syncthreads();
 
