@@ -1266,7 +1266,7 @@ __global__ void k_monitor_apply(long long n, double alpha, const double* __restr
 template <int DIM>
 __global__ void k_filter(GridDev g, const double* __restrict__ win, double* __restrict__ wout) {
     int i, j, k;
-    if (!box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) return;
+    if (!box_ijk_xcd(0, 0, 0, g.n[0], g.n[1], i, j, k)) return;
     double s = 0.0;
     if (DIM == 2) {
         for (int o0 = -1; o0 <= 1; ++o0) {
@@ -1278,17 +1278,39 @@ __global__ void k_filter(GridDev g, const double* __restrict__ win, double* __re
             }
         }
     } else {
-        for (int o0 = -1; o0 <= 1; ++o0) {
-            const int ii = map_sol(i + o0, g.n[0], g.bc[0]);
-            for (int o1 = -1; o1 <= 1; ++o1) {
-                const int jj = map_sol(j + o1, g.n[1], g.bc[1]);
-                for (int o2 = -1; o2 <= 1; ++o2) {
-                    const int kk = map_sol(k + o2, g.n[2], g.bc[2]);
-                    const int e = abs(o0) + abs(o1) + abs(o2) + 3;
-                    s += ldexp(1.0, -e) * win[iidx(g, ii, jj, kk)];
-                }
-            }
+        // the 27 neighbour indices (map_sol of an interior index +- 1, without its
+        // branches), then all loads before the first use, then the sum in the order
+        // o0, o1, o2
+        const int* n = g.n;
+        auto nb = [&](int v, int a) {
+            const bool per = g.bc[a] == ES_BC_PERIODIC;
+            return v < 0 ? (per ? n[a] - 1 : 0) : (v >= n[a] ? (per ? 0 : n[a] - 1) : v);
+        };
+        int ia[3], ja[3], ka[3];
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            ia[o] = nb(i + o - 1, 0);
+            ja[o] = nb(j + o - 1, 1);
+            ka[o] = nb(k + o - 1, 2);
         }
+        double v[27];
+#pragma unroll
+        for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+            for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+                for (int o2 = 0; o2 < 3; ++o2) v[(o0 * 3 + o1) * 3 + o2] = win[iidx(g, ia[o0], ja[o1], ka[o2])];
+        // every load issued before any of them is used
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+            for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+                for (int o2 = 0; o2 < 3; ++o2) {
+                    const int e = (o0 != 1) + (o1 != 1) + (o2 != 1) + 3;
+                    s += ldexp(1.0, -e) * v[(o0 * 3 + o1) * 3 + o2];
+                }
     }
     wout[iidx(g, i, j, k)] = s;
 }
@@ -1382,41 +1404,65 @@ __device__ __forceinline__ double mesh_nb(const GridDev& g, const double* __rest
 }
 
 // One Jacobi sweep of the mesh equations over the axes along which a node is free.
+// The neighbours c +- e_a are wrapped across the box (the periodic copies, with the
+// coordinate shift of component a); along an outflow axis only the nodes off its
+// edges are free, and their neighbours never wrap (a fixed node's wrapped
+// neighbours are loaded and not used).  Every load is issued before the first is
+// used, with no branch around them, so that a sweep waits on memory once.
 template <int DIM>
 __global__ void k_jacobi(GridDev g, const double* __restrict__ w, const double* __restrict__ xin,
                          double* __restrict__ xout) {
     int i, j, k;
-    if (!box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) return;
+    if (!box_ijk_xcd(0, 0, 0, g.n[0], g.n[1], i, j, k)) return;
     const int c[3] = {i, j, k};
     const long long t = iidx(g, i, j, k);
+    const long long N = g.nodes;
+    const long long stride[3] = {1, (long long)g.n[0], (long long)g.n[0] * g.n[1]};
     bool fr[3];
+    long long tp[3], tm[3];
+    double sp[3], sm[3];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) fr[a] = g.bc[a] == ES_BC_PERIODIC || (c[a] > 0 && c[a] < g.n[a] - 1);
+    for (int a = 0; a < DIM; ++a) {
+        fr[a] = g.bc[a] == ES_BC_PERIODIC || (c[a] > 0 && c[a] < g.n[a] - 1);
+        const bool wrap_p = c[a] + 1 >= g.n[a], wrap_m = c[a] < 1;
+        tp[a] = t + (wrap_p ? (long long)(1 - g.n[a]) : 1LL) * stride[a];
+        tm[a] = t + (wrap_m ? (long long)(g.n[a] - 1) : -1LL) * stride[a];
+        sp[a] = wrap_p ? g.period[a] : 0.0;
+        sm[a] = wrap_m ? -g.period[a] : 0.0;
+    }
     const double wc = w[t];
+    double wp[3], wm[3], xp[3][3], xm[3][3], xc[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        wp[a] = w[tp[a]];
+        wm[a] = w[tm[a]];
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+            xp[a][q] = xin[q * N + tp[a]];
+            xm[a][q] = xin[q * N + tm[a]];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) xc[q] = xin[q * N + t];
+    // every load issued before any of them is used
+    __builtin_amdgcn_sched_barrier(0);
     double den = 0.0, num[DIM];
 #pragma unroll
     for (int q = 0; q < DIM; ++q) num[q] = 0.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        if (!fr[a]) continue;
-        int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
-        cp[a] = map_sol(c[a] + 1, g.n[a], g.bc[a]);
-        cm[a] = map_sol(c[a] - 1, g.n[a], g.bc[a]);
-        const double wp = w[iidx(g, cp[0], cp[1], cp[2])];
-        const double wm = w[iidx(g, cm[0], cm[1], cm[2])];
-        den += 2.0 * wc + wp + wm;
+        const double dn = den + (2.0 * wc + wp[a] + wm[a]);
+        den = fr[a] ? dn : den;
 #pragma unroll
         for (int q = 0; q < DIM; ++q) {
-            const double xp = mesh_nb<DIM>(g, xin, q, c, a, +1);
-            const double xm = mesh_nb<DIM>(g, xin, q, c, a, -1);
-            num[q] += (wc + wp) * xp + (wc + wm) * xm;
+            const double xpv = xp[a][q] + (q == a ? sp[a] : 0.0);
+            const double xmv = xm[a][q] + (q == a ? sm[a] : 0.0);
+            const double nq = num[q] + ((wc + wp[a]) * xpv + (wc + wm[a]) * xmv);
+            num[q] = fr[a] ? nq : num[q];
         }
     }
 #pragma unroll
-    for (int q = 0; q < DIM; ++q) {
-        const long long o = (long long)q * g.nodes + t;
-        xout[o] = (fr[q] && den > 0.0) ? num[q] / den : xin[o];
-    }
+    for (int q = 0; q < DIM; ++q) xout[q * N + t] = (fr[q] && den > 0.0) ? num[q] / den : xc[q];
 }
 
 // Largest admissible pseudo-time fraction at interior node c (index t) for the
@@ -1586,7 +1632,7 @@ __global__ void __launch_bounds__(256) k_dtau_partial(GridDev g, const double* _
     __shared__ double sh[8];
     double best = 1.0;
     int i, j, k;
-    if (box_ijk(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
+    if (box_ijk_xcd(0, 0, 0, g.n[0], g.n[1], i, j, k)) {
         const int c[3] = {i, j, k};
         const long long t = iidx(g, i, j, k);
         double xv[DIM];
