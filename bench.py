@@ -65,6 +65,7 @@ RESIDUAL_FLOPS_PER_NODE_3D_RMHD = 111738.6
 RESIDUAL_TRAFFIC_BYTES = {
     "rhd2d_quadrant_riemann_400_seed2": 57.85e6,
     "rhd3d_blast_128": 1329.3e6,
+    "rmhd2d_rotor_512": 1483.2e6,
 }
 
 
