@@ -34,6 +34,16 @@ __device__ __forceinline__ double frcp(double x) {
 #endif
 }
 
+// a / b as a times the reciprocal of b (frcp; the same conditions on b).  The op
+// count takes it as the one division it stands for.
+__device__ __forceinline__ double fdiv(double a, double b) {
+#ifdef ES_OPCOUNT_HOST
+    return a / b;
+#else
+    return a * frcp(b);
+#endif
+}
+
 // Logarithmic mean [a]/[ln a] (cited in Section 3.1 to Ismail & Roe) from the
 // values and their precomputed logarithms.  With f = (al - ar)/(al + ar) and
 // u = f^2: for u < 1e-2 the ratio ln(al/ar)/(2f) is replaced by its series

@@ -424,9 +424,9 @@ __device__ __forceinline__ void jacobi_eigen_sym8(const double Q[8][8], double l
                 }
                 // (|th| <= 5e17 here, so th^2 + 1 stays finite; the reciprocals and
                 // roots are of positive normal numbers)
-                const double th = (aqq - app) * frcp(2.0 * apq);
-                const double t = (th >= 0.0 ? 1.0 : -1.0) * frcp(fabs(th) + psqrt(th * th + 1.0));
-                const double c = frsqrt(t * t + 1.0), sn = t * c, tau = sn * frcp(1.0 + c);
+                const double th = fdiv(aqq - app, 2.0 * apq);
+                const double t = fdiv(th >= 0.0 ? 1.0 : -1.0, fabs(th) + psqrt(th * th + 1.0));
+                const double c = frsqrt(t * t + 1.0), sn = t * c, tau = fdiv(sn, 1.0 + c);
                 a[tri8(p, p)] = app - t * apq;
                 a[tri8(q, q)] = aqq + t * apq;
                 a[tri8(q, p)] = 0.0;
