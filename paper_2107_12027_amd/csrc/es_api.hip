@@ -157,7 +157,7 @@ es_status es_create(const es_grid* grid, const es_scheme* scheme, const es_monit
     if (e == hipSuccess) e = alloc(&c->prim, P * c->nprim);
     if (e == hipSuccess) e = alloc(&c->met, P * c->nmet);
     if (e == hipSuccess && grid->dim == 2) e = alloc(&c->met1, P * c->nmet);
-    if (e == hipSuccess && grid->dim == 2) e = alloc(&c->met2, P * c->nmet);
+    if (e == hipSuccess) e = alloc(&c->met2, P * c->nmet);
     if (e == hipSuccess) e = alloc(&c->L, N * (c->m + 1) * d);
     if (e == hipSuccess) e = alloc(&c->Us, N * c->m);
     if (e == hipSuccess) e = alloc(&c->Js, N);
@@ -321,11 +321,20 @@ static es_status enqueue_step(es_ctx* c, double* U, double* J, double* x, double
     // 3D: the CFL launch left the spatial metrics of x^n in c->met (unless dt was
     // prescribed), so stage 0, on the same mesh, adds only its temporal part
     const bool met0_spatial = !batched && fixed_dt_dev == nullptr;
+    // 3D: the stage-2 metrics (into met2) right after the stage-1 ones, while the
+    // extended mesh velocity that both read is still in cache
     for (int st = 0; st < 3; ++st) {
         const double* met = c->met;
-        if (batched) met = st == 0 ? c->met : (st == 1 ? c->met1 : c->met2);
-        else if (st == 0 && met0_spatial) ES_TRY(es::launch_temporal_metrics3d(c, xdot, c->met, s));
-        else ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s, st == 2));
+        if (batched) {
+            met = st == 0 ? c->met : (st == 1 ? c->met1 : c->met2);
+        } else if (st == 0 && met0_spatial) {
+            ES_TRY(es::launch_temporal_metrics3d(c, xdot, c->met, s));
+        } else if (st == 2) {
+            met = c->met2;
+        } else {
+            ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[st], c->met, nullptr, s, false));
+            if (st == 1) ES_TRY(es::launch_metrics(c, x, xdot, dt_dev, coef[2], c->met2, nullptr, s, true));
+        }
         ES_TRY(es::launch_residual_dirs(c, c->prim, met, c->L, s));
         if (st == 0) {
             ES_TRY(es::launch_combine_con2prim(c, 0, U, J, nullptr, nullptr, c->L, dt_dev, c->Us, c->Js,

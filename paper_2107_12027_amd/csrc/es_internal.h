@@ -19,7 +19,7 @@ struct es_ctx {
     double* prim;   // padded, nprim comps
     double* met;    // padded, nmet comps
     double* met1;   // padded, nmet comps (stage-1 metrics, 2D)
-    double* met2;   // padded, nmet comps (stage-2 metrics, 2D)
+    double* met2;   // padded, nmet comps (stage-2 metrics)
     double* L;      // interior, d slabs of m + 1 comps (stage residual by direction, J last)
     double* Us;     // interior, m comps (stage-1 state)
     double* Js;     // interior
