@@ -1149,14 +1149,22 @@ __device__ __forceinline__ void finalize_dt(const DtFinal& f, double* sh) {
         if (flat_tid() == 0) f.dt_out[0] = f.fixed_dt[0];
         return;
     }
-    // the slabs' partials are read in one unrolled loop, several loads in flight
+    // RU partials per slab and thread are loaded before any is used; an index past
+    // the last partial reads the last one again, which leaves a maximum unchanged
+    // (the three slabs are allocated in 2D too; the third is not used there)
     const int tid = flat_tid(), nt = (int)(blockDim.x * blockDim.y * blockDim.z);
+    constexpr int RU = 8;
     double m[3] = {0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int b = tid; b < f.nb; b += nt) {
+    for (int b0 = tid; b0 < f.nb; b0 += RU * nt) {
+        double q[3][RU];
 #pragma unroll
         for (int kd = 0; kd < 3; ++kd)
-            if (kd < f.dim) m[kd] = fmax(m[kd], f.partial[kd * f.nb + b]);
+#pragma unroll
+            for (int u = 0; u < RU; ++u) q[kd][u] = f.partial[kd * f.nb + min(b0 + u * nt, f.nb - 1)];
+#pragma unroll
+        for (int kd = 0; kd < 3; ++kd)
+#pragma unroll
+            for (int u = 0; u < RU; ++u) m[kd] = fmax(m[kd], q[kd][u]);
     }
     double tot = 0.0;
     for (int kd = 0; kd < f.dim; ++kd) tot += block_reduce<0>(m[kd], sh) / f.dx[kd];
@@ -1249,8 +1257,17 @@ __global__ void __launch_bounds__(FINAL_TPB) k_reduce_final(int op, int nb, cons
                                                             double* __restrict__ out) {
     __shared__ double sh[FINAL_TPB / 64];
     double v = op == 0 ? 0.0 : 1.0;
-#pragma unroll 4
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) v = op == 0 ? fmax(v, partial[b]) : fmin(v, partial[b]);
+    // RU partials per thread loaded before any is used; an index past the last
+    // partial reads the last one again (maximum and minimum are unchanged by it)
+    constexpr int RU = 8;
+    const int nt = (int)blockDim.x;
+    for (int b0 = threadIdx.x; b0 < nb; b0 += RU * nt) {
+        double q[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) q[u] = partial[min(b0 + u * nt, nb - 1)];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) v = op == 0 ? fmax(v, q[u]) : fmin(v, q[u]);
+    }
     v = op == 0 ? block_reduce<0>(v, sh) : block_reduce<1>(v, sh);
     if (threadIdx.x == 0) out[0] = v;
 }
