@@ -1143,17 +1143,18 @@ struct DtFinal {
     double* dt_out;
 };
 
+template <int RU>
 __device__ __forceinline__ void finalize_dt(const DtFinal& f, double* sh) {
     // a prescribed dt needs no reduction (the same branch for the whole block)
     if (f.fixed_dt != nullptr) {
         if (flat_tid() == 0) f.dt_out[0] = f.fixed_dt[0];
         return;
     }
-    // RU partials per slab and thread are loaded before any is used; an index past
-    // the last partial reads the last one again, which leaves a maximum unchanged
-    // (the three slabs are allocated in 2D too; the third is not used there)
+    // RU partials per slab and thread are loaded before any is used (RU sized so
+    // that one pass covers the caller's typical count); an index past the last
+    // partial reads the last one again, which leaves a maximum unchanged (the three
+    // slabs are allocated in 2D too; the third is not used there)
     const int tid = flat_tid(), nt = (int)(blockDim.x * blockDim.y * blockDim.z);
-    constexpr int RU = 8;
     double m[3] = {0.0, 0.0, 0.0};
     for (int b0 = tid; b0 < f.nb; b0 += RU * nt) {
         double q[3][RU];
@@ -1175,7 +1176,7 @@ constexpr int FINAL_TPB = 1024;   // threads of the one-block final reductions
 
 __global__ void __launch_bounds__(FINAL_TPB) k_cfl_final(DtFinal f) {
     __shared__ double sh[FINAL_TPB / 64];
-    finalize_dt(f, sh);
+    finalize_dt<8>(f, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1354,7 +1355,7 @@ __global__ void __launch_bounds__(FTX * FBY) k_monitor_filter2d(GridDev g, int a
     const int tid = threadIdx.y * FTX + threadIdx.x;
     const int i0 = (int)blockIdx.x * FTX - FH, j0 = (int)blockIdx.y * FTY - FH;
     const int n0 = g.n[0], n1 = g.n[1];
-    if (dt_fin.dt_out != nullptr && blockIdx.x == 0 && blockIdx.y == 0) finalize_dt(dt_fin, sh);
+    if (dt_fin.dt_out != nullptr && blockIdx.x == 0 && blockIdx.y == 0) finalize_dt<2>(dt_fin, sh);
     double m = 0.0;
     if (apply) {
         for (int b = tid; b < nb; b += FTX * FBY) m = fmax(m, gpart[b]);
